@@ -1,0 +1,705 @@
+// Reference oracle for the unbinned maximum-likelihood hot path.
+//
+// TEST INFRASTRUCTURE ONLY.  Plain, slow, double-precision CPU code that
+// states what the GPU library must compute; only the test suite, the smoke
+// check and the benchmark's CPU-baseline leg may load it.  It shares no code,
+// header or table with the GPU library.
+//
+// What it computes (GooFit paper: sections "GooFit code", "Combining
+// functions", "Adding new PDFs", "Results"):
+//   * a tree of PDF nodes over observables held in a box (the Variable
+//     (name, lo, hi) form of the first listing), each node a normalised
+//     density P(x; theta) over that box;
+//   * the negative log-likelihood NLL = -sum_i ln P_root(x_i; theta) (the
+//     maximum-likelihood "metric" of the FitManager section), and its exact
+//     gradient with respect to every parameter.
+// Every sum over events is a Neumaier-compensated double sum.
+//
+// Node definitions (each P is normalised over the node's observables):
+//   EXP    P = e^{alpha x} / int_a^b e^{alpha x} dx                     (listing 1)
+//   GAUSS  P = exp(-(x-mu)^2/(2 sigma^2)) / int_a^b (same) dx          (listing 3)
+//   POLY   P = sum_k a_k (x-x0)^k / int (same), a_0 = 1 fixed
+//   ADD    P = sum_{j<K} f_j P_j + (1 - sum f_j) P_K                    ("Combining functions")
+//   PROD   P = prod_j P_j over disjoint observables                     (listing 2)
+//   DALITZ P = |1 + sum_k c_k A_k(s12, s13)|^2 / N_A, with A_k relativistic
+//          Breit-Wigner x Blatt-Weisskopf x Zemach amplitudes and N_A the
+//          midpoint sum over a G x G grid of the Dalitz box ("Results": the
+//          Dalitz-plot amplitude sum)
+//   TDDP   P = [a_c C(t) + a_0 E(t;1/tau) + a_s S(t)] / N_T, the x = 0 mixing
+//          rate convolved with a per-event Gaussian resolution ("Results":
+//          hyperbolic time terms convolved with Gaussian resolution)
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef std::complex<double> cplx;
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+enum Kind { K_EXP = 1, K_GAUSS = 2, K_POLY = 3, K_ADD = 4, K_PROD = 5, K_DALITZ = 6, K_TDDP = 7 };
+
+// ---------------------------------------------------------------- sums
+struct Neumaier {
+  double s = 0.0, c = 0.0;
+  void add(double x) {
+    double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+// ---------------------------------------------------------------- special functions
+// erfcx(x) = exp(x^2) erfc(x) for x >= 0.  Below 5 the product form is used;
+// above, the classical continued fraction
+//   erfc(x) = exp(-x^2)/sqrt(pi) * 1/(x + (1/2)/(x + (2/2)/(x + (3/2)/(x + ...))))
+// evaluated from a fixed depth.
+double erfcx_pos(double x) {
+  if (x < 5.0) return std::exp(x * x) * std::erfc(x);
+  double t = x;
+  for (int n = 80; n >= 1; --n) t = x + (0.5 * n) / t;
+  return 1.0 / (std::sqrt(kPi) * t);
+}
+
+// Gaussian-resolution convolution of the unit exponential decay:
+//   E(t; G, s) = int_0^inf G0(t') N(t - t'; 0, s) dt',  G0(t') = e^{-G t'}
+//             = 1/2 exp(G^2 s^2 / 2 - G t) erfc(w),  w = (G s^2 - t)/(sqrt2 s).
+// For w > 0 the equivalent 1/2 exp(-t^2/(2 s^2)) erfcx(w) avoids overflow.
+double econv(double t, double G, double s) {
+  double w = (G * s * s - t) / (std::sqrt(2.0) * s);
+  if (w > 0.0) return 0.5 * std::exp(-t * t / (2.0 * s * s)) * erfcx_pos(w);
+  return 0.5 * std::exp(0.5 * G * G * s * s - G * t) * std::erfc(w);
+}
+// dE/dG = (G s^2 - t) E - s/sqrt(2 pi) exp(-t^2/(2 s^2))
+double econv_dG(double t, double G, double s) {
+  return (G * s * s - t) * econv(t, G, s) - s / std::sqrt(2.0 * kPi) * std::exp(-t * t / (2.0 * s * s));
+}
+
+// phi(z) = (e^z - 1)/z, so int_a^b e^{alpha (x-a)} dx = L phi(alpha L).
+double phi(double z) { return z == 0.0 ? 1.0 : std::expm1(z) / z; }
+// psi(z) = 1/(1 - e^{-z}) - 1/z ; series 1/2 + z/12 - z^3/720 + z^5/30240 near 0.
+double psi(double z) {
+  if (std::fabs(z) < 1e-2) {
+    double z2 = z * z;
+    return 0.5 + z / 12.0 - z * z2 / 720.0 + z * z2 * z2 / 30240.0;
+  }
+  return 1.0 / (-std::expm1(-z)) - 1.0 / z;
+}
+
+// ---------------------------------------------------------------- Dalitz kinematics
+struct Res { int ch; double m0, g0; int J; int p_re, p_im; };
+
+struct DalitzDef {
+  double M, m1, m2, m3, r;
+  int grid;
+  std::vector<Res> res;
+  // grid integrals: I[j][k] = sum conj(A_j) A_k h^2 ; Ib the same with swapped
+  // amplitudes; J[j][k] = sum conj(A_j) Abar_k h^2.  Index 0 is the constant.
+  std::vector<cplx> I, Ib, Jx;
+  int n_amp() const { return (int)res.size() + 1; }
+};
+
+double kallen(double a, double b, double c) { return a * a + b * b + c * c - 2 * a * b - 2 * a * c - 2 * b * c; }
+
+// Membership of (s_1x, s_1y) where x is the partner of particle 1 and y the
+// bachelor: s_1x in [(m1+mx)^2, (M-my)^2] and s_1y inside the kinematic
+// limits at that s_1x (inclusive).
+bool inside_pair(const DalitzDef& d, double s1x, double s1y, double mx, double my) {
+  double lo = (d.m1 + mx) * (d.m1 + mx), hi = (d.M - my) * (d.M - my);
+  if (!(s1x >= lo && s1x <= hi)) return false;
+  double rs = std::sqrt(s1x);
+  double E1 = (s1x - mx * mx + d.m1 * d.m1) / (2.0 * rs);
+  double Ey = (d.M * d.M - s1x - my * my) / (2.0 * rs);
+  double p1 = std::sqrt(std::fmax(E1 * E1 - d.m1 * d.m1, 0.0));
+  double py = std::sqrt(std::fmax(Ey * Ey - my * my, 0.0));
+  double e = E1 + Ey;
+  double smin = e * e - (p1 + py) * (p1 + py);
+  double smax = e * e - (p1 - py) * (p1 - py);
+  return s1y >= smin && s1y <= smax;
+}
+// A point is in the Dalitz plot when both orderings agree (keeps the
+// accepted set exactly symmetric under s12 <-> s13 when m2 = m3).
+bool inside(const DalitzDef& d, double s12, double s13) {
+  return inside_pair(d, s12, s13, d.m2, d.m3) && inside_pair(d, s13, s12, d.m3, d.m2);
+}
+
+// Amplitude of one resonance: B_J(q) * Z_J * BW(s_AB).  `parts`, when given,
+// receives {Gamma(s), B_J(q), Z_J, Re BW, Im BW}.
+cplx res_amp(const DalitzDef& d, const Res& R, double s12, double s13, double* parts = nullptr) {
+  const double M2 = d.M * d.M;
+  double s23 = M2 + d.m1 * d.m1 + d.m2 * d.m2 + d.m3 * d.m3 - s12 - s13;
+  double sAB, sAC, sBC, mA, mB, mC;
+  if (R.ch == 23) { sAB = s23; sAC = s12; sBC = s13; mA = d.m2; mB = d.m3; mC = d.m1; }
+  else if (R.ch == 12) { sAB = s12; sAC = s13; sBC = s23; mA = d.m1; mB = d.m2; mC = d.m3; }
+  else { sAB = s13; sAC = s12; sBC = s23; mA = d.m1; mB = d.m3; mC = d.m2; }
+  double mA2 = mA * mA, mB2 = mB * mB, mC2 = mC * mC;
+  double m02 = R.m0 * R.m0;
+  double q = std::sqrt(std::fmax(kallen(sAB, mA2, mB2), 0.0) / (4.0 * sAB));
+  double q0 = std::sqrt(std::fmax(kallen(m02, mA2, mB2), 0.0) / (4.0 * m02));
+  double z = (q * d.r) * (q * d.r), z0 = (q0 * d.r) * (q0 * d.r);
+  double B2 = 1.0;
+  if (R.J == 1) B2 = (1.0 + z0) / (1.0 + z);
+  else if (R.J == 2) B2 = (z0 * z0 + 3.0 * z0 + 9.0) / (z * z + 3.0 * z + 9.0);
+  double width = R.g0 * std::pow(q / q0, 2 * R.J + 1) * (R.m0 / std::sqrt(sAB)) * B2;
+  cplx bw = 1.0 / cplx(m02 - sAB, -R.m0 * width);
+  double Z = 1.0;
+  if (R.J >= 1) {
+    double z1 = sAC - sBC + (M2 - mC2) * (mB2 - mA2) / sAB;
+    Z = z1;
+    if (R.J == 2) {
+      double ta = sAB - 2.0 * M2 - 2.0 * mC2 + (M2 - mC2) * (M2 - mC2) / sAB;
+      double tb = sAB - 2.0 * mA2 - 2.0 * mB2 + (mA2 - mB2) * (mA2 - mB2) / sAB;
+      Z = z1 * z1 - ta * tb / 3.0;
+    }
+  }
+  if (parts) { parts[0] = width; parts[1] = std::sqrt(B2); parts[2] = Z; parts[3] = bw.real(); parts[4] = bw.imag(); }
+  return std::sqrt(B2) * Z * bw;
+}
+
+// amps[0] = 1 (constant term), amps[k] = A_k.
+void amplitudes(const DalitzDef& d, double s12, double s13, cplx* amps) {
+  amps[0] = cplx(1.0, 0.0);
+  for (size_t k = 0; k < d.res.size(); ++k) amps[k + 1] = res_amp(d, d.res[k], s12, s13);
+}
+
+void build_grid(DalitzDef& d) {
+  const int na = d.n_amp();
+  d.I.assign(na * na, 0.0);
+  d.Ib.assign(na * na, 0.0);
+  d.Jx.assign(na * na, 0.0);
+  const double lo12 = (d.m1 + d.m2) * (d.m1 + d.m2), hi12 = (d.M - d.m3) * (d.M - d.m3);
+  const double lo13 = (d.m1 + d.m3) * (d.m1 + d.m3), hi13 = (d.M - d.m2) * (d.M - d.m2);
+  const double h12 = (hi12 - lo12) / d.grid, h13 = (hi13 - lo13) / d.grid;
+  const double area = h12 * h13;
+  std::vector<cplx> a(na), ab(na);
+  // plain row-by-row sum; a Neumaier sum per matrix element and component
+  std::vector<Neumaier> sI(2 * na * na), sIb(2 * na * na), sJ(2 * na * na);
+  for (int i = 0; i < d.grid; ++i) {
+    double s12 = lo12 + (i + 0.5) * h12;
+    for (int j = 0; j < d.grid; ++j) {
+      double s13 = lo13 + (j + 0.5) * h13;
+      if (!inside(d, s12, s13)) continue;
+      amplitudes(d, s12, s13, a.data());
+      amplitudes(d, s13, s12, ab.data());
+      for (int p = 0; p < na; ++p)
+        for (int q = 0; q < na; ++q) {
+          cplx v = std::conj(a[p]) * a[q], vb = std::conj(ab[p]) * ab[q], vj = std::conj(a[p]) * ab[q];
+          int o = 2 * (p * na + q);
+          sI[o].add(v.real()); sI[o + 1].add(v.imag());
+          sIb[o].add(vb.real()); sIb[o + 1].add(vb.imag());
+          sJ[o].add(vj.real()); sJ[o + 1].add(vj.imag());
+        }
+    }
+  }
+  for (int e = 0; e < na * na; ++e) {
+    d.I[e] = cplx(sI[2 * e].value(), sI[2 * e + 1].value()) * area;
+    d.Ib[e] = cplx(sIb[2 * e].value(), sIb[2 * e + 1].value()) * area;
+    d.Jx[e] = cplx(sJ[2 * e].value(), sJ[2 * e + 1].value()) * area;
+  }
+}
+
+// ---------------------------------------------------------------- model
+struct Node {
+  int kind = 0;
+  std::vector<int> child;   // ADD, PROD
+  std::vector<int> obs;     // observable columns
+  std::vector<int> par;     // EXP: alpha; GAUSS: mu, sigma; POLY: a1..ad; ADD: fractions
+  double x0 = 0.0;          // POLY expansion point
+  DalitzDef* dz = nullptr;  // DALITZ, TDDP
+  int p_tau = -1, p_y = -1; // TDDP
+};
+
+struct Model {
+  int n_obs = 0, n_par = 0, root = -1;
+  std::vector<double> lo, hi;
+  std::vector<Node> nodes;
+  ~Model() { for (auto& n : nodes) delete n.dz; }
+};
+
+// Per-call normalisation of each node (depends on theta only).
+struct NodeNorm { double lnN = 0.0; std::vector<double> dlnN; };
+
+// complex coefficient vector c (c_0 = 1) and its derivative map
+void coeffs(const DalitzDef& d, const double* th, std::vector<cplx>& c) {
+  c.assign(d.n_amp(), cplx(1.0, 0.0));
+  for (size_t k = 0; k < d.res.size(); ++k) c[k + 1] = cplx(th[d.res[k].p_re], th[d.res[k].p_im]);
+}
+
+// c^H M c and its derivatives with respect to re/im of c_k (k >= 1).
+cplx quad_form(const std::vector<cplx>& M, const std::vector<cplx>& c, int na) {
+  cplx s = 0.0;
+  for (int j = 0; j < na; ++j)
+    for (int k = 0; k < na; ++k) s += std::conj(c[j]) * M[j * na + k] * c[k];
+  return s;
+}
+// d(c^H M c)/d(re c_k) = (c^H M)_k + (M c)_k ; d/d(im c_k) = i[(c^H M)_k - (M c)_k]
+void quad_form_grad(const std::vector<cplx>& M, const std::vector<cplx>& c, int na, int k, cplx& dre, cplx& dim) {
+  cplx cm = 0.0, mc = 0.0;
+  for (int j = 0; j < na; ++j) { cm += std::conj(c[j]) * M[j * na + k]; mc += M[k * na + j] * c[j]; }
+  dre = cm + mc;
+  dim = cplx(0.0, 1.0) * (cm - mc);
+}
+
+void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& out) {
+  const Node& n = m.nodes[id];
+  NodeNorm& r = out[id];
+  r.lnN = 0.0;
+  r.dlnN.assign(m.n_par, 0.0);
+  switch (n.kind) {
+    case K_EXP: {
+      // N = int_a^b e^{alpha (x-a)} dx = L phi(alpha L); dlnN/dalpha = L psi(alpha L)
+      double a = m.lo[n.obs[0]], b = m.hi[n.obs[0]], L = b - a, al = th[n.par[0]];
+      r.lnN = std::log(L * phi(al * L));
+      r.dlnN[n.par[0]] += L * psi(al * L);
+      break;
+    }
+    case K_GAUSS: {
+      double a = m.lo[n.obs[0]], b = m.hi[n.obs[0]], mu = th[n.par[0]], sg = th[n.par[1]];
+      double za = (a - mu) / (std::sqrt(2.0) * sg), zb = (b - mu) / (std::sqrt(2.0) * sg);
+      double de;  // erf(zb) - erf(za)
+      if (za > 0.0) de = std::erfc(za) - std::erfc(zb);
+      else if (zb < 0.0) de = std::erfc(-zb) - std::erfc(-za);
+      else de = std::erf(zb) - std::erf(za);
+      double N = sg * std::sqrt(kPi / 2.0) * de;
+      double ga = std::exp(-za * za), gb = std::exp(-zb * zb);
+      r.lnN = std::log(N);
+      r.dlnN[n.par[0]] += (ga - gb) / N;
+      r.dlnN[n.par[1]] += 1.0 / sg - ((b - mu) * gb - (a - mu) * ga) / (sg * N);
+      break;
+    }
+    case K_POLY: {
+      double a = m.lo[n.obs[0]], b = m.hi[n.obs[0]];
+      double N = (b - n.x0) - (a - n.x0);
+      std::vector<double> dN(n.par.size());
+      for (size_t k = 1; k <= n.par.size(); ++k) {
+        double w = (std::pow(b - n.x0, (double)(k + 1)) - std::pow(a - n.x0, (double)(k + 1))) / (k + 1);
+        N += th[n.par[k - 1]] * w;
+        dN[k - 1] = w;
+      }
+      r.lnN = std::log(N);
+      for (size_t k = 0; k < n.par.size(); ++k) r.dlnN[n.par[k]] += dN[k] / N;
+      break;
+    }
+    case K_DALITZ: {
+      const DalitzDef& d = *n.dz;
+      std::vector<cplx> c;
+      coeffs(d, th, c);
+      int na = d.n_amp();
+      double N = quad_form(d.I, c, na).real();
+      r.lnN = std::log(N);
+      for (size_t k = 0; k < d.res.size(); ++k) {
+        cplx dre, dim;
+        quad_form_grad(d.I, c, na, (int)k + 1, dre, dim);
+        r.dlnN[d.res[k].p_re] += dre.real() / N;
+        r.dlnN[d.res[k].p_im] += dim.real() / N;
+      }
+      break;
+    }
+    case K_TDDP: {
+      // N_T = int dDP int_R dt rate: the time integrals of E(t; G) over R
+      // are 1/G, so int C = tau/(1-y^2), int S = y tau/(1-y^2), int E = tau.
+      const DalitzDef& d = *n.dz;
+      std::vector<cplx> c;
+      coeffs(d, th, c);
+      int na = d.n_amp();
+      double tau = th[n.p_tau], y = th[n.p_y];
+      double IAA = quad_form(d.I, c, na).real(), IBB = quad_form(d.Ib, c, na).real();
+      double RJ = quad_form(d.Jx, c, na).real();
+      double kc = tau / (1.0 - y * y), ks = y * tau / (1.0 - y * y);
+      double N = 0.5 * (IAA + IBB) * kc + 0.5 * (IAA - IBB) * tau - RJ * ks;
+      r.lnN = std::log(N);
+      for (size_t k = 0; k < d.res.size(); ++k) {
+        cplx a1, a2, b1, b2, j1, j2;
+        quad_form_grad(d.I, c, na, (int)k + 1, a1, a2);
+        quad_form_grad(d.Ib, c, na, (int)k + 1, b1, b2);
+        quad_form_grad(d.Jx, c, na, (int)k + 1, j1, j2);
+        double dre = 0.5 * (a1.real() + b1.real()) * kc + 0.5 * (a1.real() - b1.real()) * tau - j1.real() * ks;
+        double dim = 0.5 * (a2.real() + b2.real()) * kc + 0.5 * (a2.real() - b2.real()) * tau - j2.real() * ks;
+        r.dlnN[d.res[k].p_re] += dre / N;
+        r.dlnN[d.res[k].p_im] += dim / N;
+      }
+      double omy = 1.0 - y * y;
+      double dN_dtau = 0.5 * (IAA + IBB) / omy + 0.5 * (IAA - IBB) - RJ * y / omy;
+      double dN_dy = 0.5 * (IAA + IBB) * tau * 2.0 * y / (omy * omy) - RJ * tau * (1.0 + y * y) / (omy * omy);
+      r.dlnN[n.p_tau] += dN_dtau / N;
+      r.dlnN[n.p_y] += dN_dy / N;
+      break;
+    }
+    default:
+      break;  // ADD and PROD are normalised through their children
+  }
+  for (int ch : n.child) node_norm(m, ch, th, out);
+}
+
+// ln P_node(event) and its gradient (dense, length n_par).  Returns -inf when
+// the density is zero or undefined.
+double node_eval(const Model& m, int id, const double* ev, const double* th,
+                 const std::vector<NodeNorm>& nn, double* g) {
+  const Node& n = m.nodes[id];
+  const int np = m.n_par;
+  for (int p = 0; p < np; ++p) g[p] = 0.0;
+  double lp = -INFINITY;
+  switch (n.kind) {
+    case K_EXP: {
+      double x = ev[n.obs[0]], a = m.lo[n.obs[0]];
+      lp = th[n.par[0]] * (x - a) - nn[id].lnN;
+      g[n.par[0]] += (x - a);
+      break;
+    }
+    case K_GAUSS: {
+      double x = ev[n.obs[0]], mu = th[n.par[0]], sg = th[n.par[1]];
+      lp = -0.5 * (x - mu) * (x - mu) / (sg * sg) - nn[id].lnN;
+      g[n.par[0]] += (x - mu) / (sg * sg);
+      g[n.par[1]] += (x - mu) * (x - mu) / (sg * sg * sg);
+      break;
+    }
+    case K_POLY: {
+      double u = ev[n.obs[0]] - n.x0, f = 1.0;
+      for (size_t k = 1; k <= n.par.size(); ++k) f += th[n.par[k - 1]] * std::pow(u, (double)k);
+      if (!(f > 0.0)) return -INFINITY;
+      lp = std::log(f) - nn[id].lnN;
+      for (size_t k = 1; k <= n.par.size(); ++k) g[n.par[k - 1]] += std::pow(u, (double)k) / f;
+      break;
+    }
+    case K_ADD: {
+      const size_t K = n.child.size();
+      std::vector<double> lpj(K), pj(K);
+      std::vector<std::vector<double>> gj(K, std::vector<double>(np));
+      for (size_t j = 0; j < K; ++j) {
+        lpj[j] = node_eval(m, n.child[j], ev, th, nn, gj[j].data());
+        pj[j] = std::exp(lpj[j]);
+      }
+      double flast = 1.0, P = 0.0;
+      for (size_t j = 0; j + 1 < K; ++j) { flast -= th[n.par[j]]; P += th[n.par[j]] * pj[j]; }
+      P += flast * pj[K - 1];
+      if (!(P > 0.0)) return -INFINITY;
+      lp = std::log(P);
+      for (size_t j = 0; j < K; ++j) {
+        double fj = (j + 1 < K) ? th[n.par[j]] : flast;
+        if (pj[j] == 0.0) continue;
+        for (int p = 0; p < np; ++p) g[p] += fj * pj[j] * gj[j][p] / P;
+      }
+      for (size_t j = 0; j + 1 < K; ++j) g[n.par[j]] += (pj[j] - pj[K - 1]) / P;
+      break;
+    }
+    case K_PROD: {
+      std::vector<double> gj(np);
+      lp = 0.0;
+      for (int ch : n.child) {
+        double l = node_eval(m, ch, ev, th, nn, gj.data());
+        lp += l;
+        for (int p = 0; p < np; ++p) g[p] += gj[p];
+      }
+      break;
+    }
+    case K_DALITZ: {
+      const DalitzDef& d = *n.dz;
+      double s12 = ev[n.obs[0]], s13 = ev[n.obs[1]];
+      if (!inside(d, s12, s13)) return -INFINITY;
+      std::vector<cplx> a(d.n_amp()), c;
+      amplitudes(d, s12, s13, a.data());
+      coeffs(d, th, c);
+      cplx A = 0.0;
+      for (int k = 0; k < d.n_amp(); ++k) A += c[k] * a[k];
+      double A2 = std::norm(A);
+      if (!(A2 > 0.0)) return -INFINITY;
+      lp = std::log(A2) - nn[id].lnN;
+      // d|A|^2/dx = 2 Re(conj(A) dA/dx); dA/d(re c_k) = A_k, dA/d(im c_k) = i A_k
+      for (size_t k = 0; k < d.res.size(); ++k) {
+        g[d.res[k].p_re] += 2.0 * (std::conj(A) * a[k + 1]).real() / A2;
+        g[d.res[k].p_im] += 2.0 * (std::conj(A) * cplx(0.0, 1.0) * a[k + 1]).real() / A2;
+      }
+      break;
+    }
+    case K_TDDP: {
+      const DalitzDef& d = *n.dz;
+      double s12 = ev[n.obs[0]], s13 = ev[n.obs[1]], t = ev[n.obs[2]], st = ev[n.obs[3]];
+      if (!inside(d, s12, s13) || !(st > 0.0)) return -INFINITY;
+      const int na = d.n_amp();
+      std::vector<cplx> a(na), ab(na), c;
+      amplitudes(d, s12, s13, a.data());
+      amplitudes(d, s13, s12, ab.data());  // CP-conjugate amplitude: 2 <-> 3 swap
+      coeffs(d, th, c);
+      cplx A = 0.0, Ab = 0.0;
+      for (int k = 0; k < na; ++k) { A += c[k] * a[k]; Ab += c[k] * ab[k]; }
+      double tau = th[n.p_tau], y = th[n.p_y];
+      double Gm = (1.0 - y) / tau, Gp = (1.0 + y) / tau, G = 1.0 / tau;
+      double Em = econv(t, Gm, st), Ep = econv(t, Gp, st), E0 = econv(t, G, st);
+      double Ct = 0.5 * (Em + Ep), St = 0.5 * (Em - Ep);
+      double ac = 0.5 * (std::norm(A) + std::norm(Ab));
+      double a0 = 0.5 * (std::norm(A) - std::norm(Ab));
+      double as = -(std::conj(A) * Ab).real();
+      double R = ac * Ct + a0 * E0 + as * St;
+      if (!(R > 0.0)) return -INFINITY;
+      lp = std::log(R) - nn[id].lnN;
+      for (size_t k = 0; k < d.res.size(); ++k) {
+        for (int part = 0; part < 2; ++part) {
+          cplx u = part == 0 ? cplx(1.0, 0.0) : cplx(0.0, 1.0);  // dc_k/dx
+          cplx dA = u * a[k + 1], dAb = u * ab[k + 1];
+          double dnA = 2.0 * (std::conj(A) * dA).real(), dnB = 2.0 * (std::conj(Ab) * dAb).real();
+          double dX = (std::conj(dA) * Ab + std::conj(A) * dAb).real();
+          double dR = 0.5 * (dnA + dnB) * Ct + 0.5 * (dnA - dnB) * E0 - dX * St;
+          g[part == 0 ? d.res[k].p_re : d.res[k].p_im] += dR / R;
+        }
+      }
+      double dEm = econv_dG(t, Gm, st), dEp = econv_dG(t, Gp, st), dE0 = econv_dG(t, G, st);
+      // chain rule through Gm = (1-y)/tau, Gp = (1+y)/tau, G = 1/tau
+      double dRm = ac * 0.5 + as * 0.5, dRp = ac * 0.5 - as * 0.5;  // dR/dEm, dR/dEp
+      double dR_dtau = dRm * dEm * (-(1.0 - y) / (tau * tau)) + dRp * dEp * (-(1.0 + y) / (tau * tau)) +
+                       a0 * dE0 * (-1.0 / (tau * tau));
+      double dR_dy = dRm * dEm * (-1.0 / tau) + dRp * dEp * (1.0 / tau);
+      g[n.p_tau] += dR_dtau / R;
+      g[n.p_y] += dR_dy / R;
+      break;
+    }
+    default:
+      return -INFINITY;
+  }
+  for (int p = 0; p < np; ++p) g[p] -= nn[id].dlnN[p];
+  return lp;
+}
+
+}  // namespace
+
+// ====================================================================== C API
+extern "C" {
+
+Model* om_new(int n_obs, const double* lo, const double* hi, int n_par) {
+  Model* m = new Model;
+  m->n_obs = n_obs;
+  m->n_par = n_par;
+  m->lo.assign(lo, lo + n_obs);
+  m->hi.assign(hi, hi + n_obs);
+  return m;
+}
+void om_free(Model* m) { delete m; }
+void om_set_root(Model* m, int id) { m->root = id; }
+
+static int push(Model* m, Node n) { m->nodes.push_back(n); return (int)m->nodes.size() - 1; }
+
+int om_exp(Model* m, int obs, int p_alpha) {
+  Node n; n.kind = K_EXP; n.obs = {obs}; n.par = {p_alpha}; return push(m, n);
+}
+int om_gauss(Model* m, int obs, int p_mu, int p_sigma) {
+  Node n; n.kind = K_GAUSS; n.obs = {obs}; n.par = {p_mu, p_sigma}; return push(m, n);
+}
+int om_poly(Model* m, int obs, double x0, int degree, const int* p_coef) {
+  Node n; n.kind = K_POLY; n.obs = {obs}; n.x0 = x0; n.par.assign(p_coef, p_coef + degree); return push(m, n);
+}
+int om_add(Model* m, int n_child, const int* child, const int* p_frac) {
+  Node n; n.kind = K_ADD; n.child.assign(child, child + n_child); n.par.assign(p_frac, p_frac + n_child - 1);
+  return push(m, n);
+}
+int om_prod(Model* m, int n_child, const int* child) {
+  Node n; n.kind = K_PROD; n.child.assign(child, child + n_child); return push(m, n);
+}
+static DalitzDef* make_dalitz(const double* kin, int grid, int n_res, const int* ch, const double* m0,
+                              const double* g0, const int* J, const int* p_re, const int* p_im) {
+  DalitzDef* d = new DalitzDef;
+  d->M = kin[0]; d->m1 = kin[1]; d->m2 = kin[2]; d->m3 = kin[3]; d->r = kin[4];
+  d->grid = grid;
+  for (int k = 0; k < n_res; ++k) d->res.push_back(Res{ch[k], m0[k], g0[k], J[k], p_re[k], p_im[k]});
+  build_grid(*d);
+  return d;
+}
+int om_dalitz(Model* m, int o12, int o13, const double* kin, int grid, int n_res, const int* ch,
+              const double* m0, const double* g0, const int* J, const int* p_re, const int* p_im) {
+  Node n; n.kind = K_DALITZ; n.obs = {o12, o13};
+  n.dz = make_dalitz(kin, grid, n_res, ch, m0, g0, J, p_re, p_im);
+  return push(m, n);
+}
+int om_tddp(Model* m, int o12, int o13, int ot, int osig, const double* kin, int grid, int n_res,
+            const int* ch, const double* m0, const double* g0, const int* J, const int* p_re,
+            const int* p_im, int p_tau, int p_y) {
+  Node n; n.kind = K_TDDP; n.obs = {o12, o13, ot, osig};
+  n.dz = make_dalitz(kin, grid, n_res, ch, m0, g0, J, p_re, p_im);
+  n.p_tau = p_tau; n.p_y = p_y;
+  return push(m, n);
+}
+
+// NLL = -sum ln P_root; grad (nullable) = dNLL/dtheta.  cols[o][i] is
+// observable o of event i.  Thread partials are combined in thread order.
+double om_nll(Model* m, const double* th, int64_t n, const double* const* cols, double* grad, int n_threads) {
+  std::vector<NodeNorm> nn(m->nodes.size());
+  node_norm(*m, m->root, th, nn);
+  const int np = m->n_par;
+  int nt = n_threads > 0 ? n_threads : 1;
+  std::vector<Neumaier> part((size_t)nt * (np + 1));
+  bool bad = false;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt) reduction(|| : bad)
+#endif
+  {
+    int tid = 0, T = 1;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+    T = omp_get_num_threads();
+#endif
+    int64_t b = n * tid / T, e = n * (tid + 1) / T;
+    std::vector<double> ev(m->n_obs), g(np);
+    Neumaier* acc = &part[(size_t)tid * (np + 1)];
+    for (int64_t i = b; i < e; ++i) {
+      for (int o = 0; o < m->n_obs; ++o) ev[o] = cols[o][i];
+      double lp = node_eval(*m, m->root, ev.data(), th, nn, g.data());
+      if (!std::isfinite(lp)) { bad = true; continue; }
+      acc[0].add(-lp);
+      if (grad)
+        for (int p = 0; p < np; ++p) acc[1 + p].add(-g[p]);
+    }
+  }
+  if (bad) {
+    if (grad) for (int p = 0; p < np; ++p) grad[p] = NAN;
+    return INFINITY;
+  }
+  Neumaier tot[1];
+  std::vector<Neumaier> gt(np);
+  for (int t = 0; t < nt; ++t) {
+    tot[0].add(part[(size_t)t * (np + 1)].value());
+    for (int p = 0; p < np; ++p) gt[p].add(part[(size_t)t * (np + 1) + 1 + p].value());
+  }
+  if (grad) for (int p = 0; p < np; ++p) grad[p] = gt[p].value();
+  return tot[0].value();
+}
+
+// Per-event ln P_root (and optional per-event gradient rows, n x n_par).
+void om_logpdf(Model* m, const double* th, int64_t n, const double* const* cols, double* out, double* grad_rows,
+               int n_threads) {
+  std::vector<NodeNorm> nn(m->nodes.size());
+  node_norm(*m, m->root, th, nn);
+  const int np = m->n_par;
+  int nt = n_threads > 0 ? n_threads : 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+  {
+    std::vector<double> ev(m->n_obs), g(np);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+      for (int o = 0; o < m->n_obs; ++o) ev[o] = cols[o][i];
+      out[i] = node_eval(*m, m->root, ev.data(), th, nn, g.data());
+      if (grad_rows) for (int p = 0; p < np; ++p) grad_rows[i * np + p] = g[p];
+    }
+  }
+}
+
+// ln N and d lnN/dtheta of one node (for tests of the normalisations).
+double om_node_lnnorm(Model* m, int id, const double* th, double* dlnN) {
+  std::vector<NodeNorm> nn(m->nodes.size());
+  node_norm(*m, id, th, nn);
+  if (dlnN) for (int p = 0; p < m->n_par; ++p) dlnN[p] = nn[id].dlnN[p];
+  return nn[id].lnN;
+}
+
+// Grid matrices of a DALITZ/TDDP node: which = 0 -> I, 1 -> Ibar, 2 -> J;
+// out holds (n_res+1)^2 complex values as interleaved re, im.
+int om_dalitz_matrix(Model* m, int id, int which, double* out) {
+  const DalitzDef* d = m->nodes[id].dz;
+  if (!d) return -1;
+  const std::vector<cplx>& M = which == 0 ? d->I : (which == 1 ? d->Ib : d->Jx);
+  for (size_t e = 0; e < M.size(); ++e) { out[2 * e] = M[e].real(); out[2 * e + 1] = M[e].imag(); }
+  return (int)M.size();
+}
+
+// |A(s12,s13)|^2 (and optionally the conjugate-channel |Abar|^2) at the given
+// theta for many points; 0 outside the Dalitz plot.
+void om_dalitz_amp2(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
+                    double* out, int swapped, int n_threads) {
+  const DalitzDef& d = *m->nodes[id].dz;
+  int nt = n_threads > 0 ? n_threads : 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+  {
+    std::vector<cplx> a(d.n_amp()), c;
+    coeffs(d, th, c);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+      if (!inside(d, s12[i], s13[i])) { out[i] = 0.0; continue; }
+      if (swapped) amplitudes(d, s13[i], s12[i], a.data());
+      else amplitudes(d, s12[i], s13[i], a.data());
+      cplx A = 0.0;
+      for (int k = 0; k < d.n_amp(); ++k) A += c[k] * a[k];
+      out[i] = std::norm(A);
+    }
+  }
+}
+
+// Re(conj(A) Abar) at the given theta for many points; 0 outside.
+void om_dalitz_cross(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
+                     double* out) {
+  const DalitzDef& d = *m->nodes[id].dz;
+  std::vector<cplx> a(d.n_amp()), ab(d.n_amp()), c;
+  coeffs(d, th, c);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!inside(d, s12[i], s13[i])) { out[i] = 0.0; continue; }
+    amplitudes(d, s12[i], s13[i], a.data());
+    amplitudes(d, s13[i], s12[i], ab.data());
+    cplx A = 0.0, Ab = 0.0;
+    for (int k = 0; k < d.n_amp(); ++k) { A += c[k] * a[k]; Ab += c[k] * ab[k]; }
+    out[i] = (std::conj(A) * Ab).real();
+  }
+}
+
+// Unsmeared (sigma_t -> 0) decay rate of a TDDP node at (s12, s13, t >= 0):
+// e^{-t/tau}[a_c cosh(y t/tau) + a_0 - ... ] written with the same a_c, a_0, a_s.
+void om_tddp_rate(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
+                  const double* t, double* out, int n_threads) {
+  const Node& nd = m->nodes[id];
+  const DalitzDef& d = *nd.dz;
+  double tau = th[nd.p_tau], y = th[nd.p_y];
+  int nt = n_threads > 0 ? n_threads : 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+  {
+    std::vector<cplx> a(d.n_amp()), ab(d.n_amp()), c;
+    coeffs(d, th, c);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+      if (!inside(d, s12[i], s13[i]) || t[i] < 0.0) { out[i] = 0.0; continue; }
+      amplitudes(d, s12[i], s13[i], a.data());
+      amplitudes(d, s13[i], s12[i], ab.data());
+      cplx A = 0.0, Ab = 0.0;
+      for (int k = 0; k < d.n_amp(); ++k) { A += c[k] * a[k]; Ab += c[k] * ab[k]; }
+      double Em = std::exp(-(1.0 - y) * t[i] / tau), Ep = std::exp(-(1.0 + y) * t[i] / tau);
+      double E0 = std::exp(-t[i] / tau);
+      double ac = 0.5 * (std::norm(A) + std::norm(Ab)), a0 = 0.5 * (std::norm(A) - std::norm(Ab));
+      double as = -(std::conj(A) * Ab).real();
+      out[i] = ac * 0.5 * (Em + Ep) + a0 * E0 + as * 0.5 * (Em - Ep);
+    }
+  }
+}
+
+// ---- building blocks exposed for invariant tests
+int om_inside(const double* kin, double s12, double s13) {
+  DalitzDef d; d.M = kin[0]; d.m1 = kin[1]; d.m2 = kin[2]; d.m3 = kin[3]; d.r = kin[4]; d.grid = 0;
+  return inside(d, s12, s13) ? 1 : 0;
+}
+// One resonance amplitude: out = {Re A, Im A, Gamma(s), B_J(q), Z_J, Re BW, Im BW}.
+void om_res_amp(const double* kin, int ch, double m0, double g0, int J, double s12, double s13, double* out) {
+  DalitzDef d; d.M = kin[0]; d.m1 = kin[1]; d.m2 = kin[2]; d.m3 = kin[3]; d.r = kin[4]; d.grid = 0;
+  Res R{ch, m0, g0, J, 0, 0};
+  cplx a = res_amp(d, R, s12, s13, out + 2);
+  out[0] = a.real();
+  out[1] = a.imag();
+}
+double om_econv(double t, double G, double s) { return econv(t, G, s); }
+double om_econv_dG(double t, double G, double s) { return econv_dG(t, G, s); }
+double om_erfcx(double x) { return erfcx_pos(x); }
+double om_psi(double z) { return psi(z); }
+
+}  // extern "C"

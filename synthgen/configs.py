@@ -1,0 +1,194 @@
+"""Workload descriptions: observables, parameters, model trees and sizes.
+
+Everything here is plain data.  A model tree is a nested dict:
+
+  {"op": "exp",    "obs": "x", "par": ["alpha"]}
+  {"op": "gauss",  "obs": "x", "par": ["mu", "sigma"]}
+  {"op": "poly",   "obs": "x", "par": ["a1", ...], "x0": 0.0}
+  {"op": "add",    "par": ["f1", ...], "children": [...]}   # K children, K-1 fractions
+  {"op": "prod",   "children": [...]}
+  {"op": "dalitz", "obs": ["s12", "s13"], "par": [re1, im1, re2, im2, ...],
+                   "dalitz": DALITZ_KINEMATICS}
+  {"op": "tddp",   "obs": ["s12", "s13", "t", "sigma_t"],
+                   "par": [re1, im1, ..., "tau", "y"], "dalitz": DALITZ_KINEMATICS}
+
+Observables are (name, lo, hi); parameters are (name, init, step, lo, hi,
+fixed) as in the two Variable constructors of the paper's first listing.
+Unbounded parameters use lo = hi = 0.
+"""
+import math
+
+__all__ = [
+    "C1", "C2", "C3", "C4", "C5", "LISTING2", "DALITZ_KINEMATICS", "RESONANCES",
+    "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
+]
+
+# ---------------------------------------------------------------- C1
+# 1-D exponential e^{alpha x} on [0, 10]; the paper's first listing uses
+# start -2, step 0.1 and bounds [-10, 10] for alpha.
+C1 = {
+    "name": "c1_exp",
+    "obs": [("x", 0.0, 10.0)],
+    "params": [("alpha", -2.0, 0.1, -10.0, 10.0, False)],
+    "truth": {"alpha": -0.5},
+    "model": {"op": "exp", "obs": "x", "par": ["alpha"]},
+    "n_events": 100_000,
+    "seed": 1,
+}
+
+# ---------------------------------------------------------------- C2
+# f * Gauss(x; mu, sigma) + (1 - f) * exp(beta x) on [5.2, 5.3].
+C2 = {
+    "name": "c2_gauss_exp",
+    "obs": [("x", 5.2, 5.3)],
+    "params": [
+        ("f", 0.25, 0.01, 0.0, 1.0, False),
+        ("mu", 5.279, 0.001, 5.2, 5.3, False),
+        ("sigma", 0.0035, 0.0005, 1e-4, 0.05, False),
+        ("beta", -1.5, 0.1, -10.0, 10.0, False),
+    ],
+    "truth": {"f": 0.3, "mu": 5.28, "sigma": 0.003, "beta": -2.0},
+    "model": {
+        "op": "add", "par": ["f"],
+        "children": [
+            {"op": "gauss", "obs": "x", "par": ["mu", "sigma"]},
+            {"op": "exp", "obs": "x", "par": ["beta"]},
+        ],
+    },
+    "n_events": 10_000_000,
+    "seed": 2,
+}
+
+# ---------------------------------------------------------------- Dalitz
+# Parent of 1.865 GeV into K_S (1), pi+ (2), pi- (3); Blatt-Weisskopf radius
+# 1.5 / GeV; normalisation on a 1000 x 1000 midpoint grid.
+DALITZ_KINEMATICS = {
+    "M": 1.865, "m1": 0.4976, "m2": 0.1396, "m3": 0.1396,
+    "r": 1.5, "grid": 1000,
+}
+
+# Eight relativistic Breit-Wigner resonances: (channel, m0, Gamma0, J).
+# Channel "23" is pi+ pi-, "12" is K_S pi+, "13" is K_S pi-.
+RESONANCES = [
+    ("23", 0.500, 0.400, 0),
+    ("23", 0.775, 0.149, 1),
+    ("23", 0.783, 0.010, 1),
+    ("23", 1.275, 0.185, 2),
+    ("12", 0.892, 0.050, 1),
+    ("13", 0.892, 0.050, 1),
+    ("12", 1.425, 0.270, 0),
+    ("12", 1.717, 0.322, 1),
+]
+
+# True complex coefficients c_1..c_8 (the non-resonant c_0 is fixed to 1).
+DALITZ_TRUTH = [
+    (0.343812, 0.198500), (0.277, 0.0), (-0.005233, 0.014377),
+    (0.339229, -0.123469), (-0.297225, 0.249402), (0.047035, -0.039467),
+    (0.353500, 0.612280), (-0.232689, -1.319642),
+]
+
+
+def dalitz_param_names(n_res=len(RESONANCES)):
+    out = []
+    for k in range(1, n_res + 1):
+        out += [f"re{k}", f"im{k}"]
+    return out
+
+
+def dalitz_box(kin=DALITZ_KINEMATICS):
+    """Bounding box [(m1+m2)^2, (M-m3)^2] of s12 (and, for m2 = m3, of s13)."""
+    lo = (kin["m1"] + kin["m2"]) ** 2
+    hi = (kin["M"] - kin["m3"]) ** 2
+    return lo, hi
+
+
+def _dalitz_start(seed=7):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for re, im in DALITZ_TRUTH:
+        mag = math.hypot(re, im) * (1.0 + 0.1 * rng.standard_normal())
+        ph = math.atan2(im, re) + math.radians(10.0) * rng.standard_normal()
+        out.append((mag * math.cos(ph), mag * math.sin(ph)))
+    return out
+
+
+def _dalitz_params(start):
+    ps = []
+    for k, (re, im) in enumerate(start, start=1):
+        ps.append((f"re{k}", re, 0.05, 0.0, 0.0, False))
+        ps.append((f"im{k}", im, 0.05, 0.0, 0.0, False))
+    return ps
+
+
+_BOX = dalitz_box()
+_RES_SPEC = [{"ch": ch, "m0": m0, "g0": g0, "J": J} for ch, m0, g0, J in RESONANCES]
+
+C3 = {
+    "name": "c3_dalitz",
+    "obs": [("s12", _BOX[0], _BOX[1]), ("s13", _BOX[0], _BOX[1])],
+    "params": _dalitz_params(_dalitz_start()),
+    "truth": {n: v for n, v in zip(dalitz_param_names(), [c for p in DALITZ_TRUTH for c in p])},
+    "model": {
+        "op": "dalitz", "obs": ["s12", "s13"], "par": dalitz_param_names(),
+        "dalitz": dict(DALITZ_KINEMATICS, resonances=_RES_SPEC),
+    },
+    "n_events": 1_000_000,
+    "seed": 3,
+}
+
+# ---------------------------------------------------------------- C4
+# Decay time with per-event Gaussian resolution times the C3 amplitude.
+# t and sigma_t are conditioning observables with no finite normalisation box
+# (t is normalised over the real line); the declared ranges only bound the
+# values a dataset may hold.
+C4 = {
+    "name": "c4_tddp",
+    "obs": [("s12", _BOX[0], _BOX[1]), ("s13", _BOX[0], _BOX[1]),
+            ("t", -math.inf, math.inf), ("sigma_t", 0.0, math.inf)],
+    "params": _dalitz_params(_dalitz_start()) + [
+        ("tau", 0.45, 0.01, 0.1, 2.0, False),
+        ("y", 0.0, 0.005, -0.2, 0.2, False),
+    ],
+    "truth": dict(C3["truth"], tau=0.41, y=0.01),
+    "model": {
+        "op": "tddp", "obs": ["s12", "s13", "t", "sigma_t"],
+        "par": dalitz_param_names() + ["tau", "y"],
+        "dalitz": dict(DALITZ_KINEMATICS, resonances=_RES_SPEC),
+    },
+    "sigma_t_range": (0.02, 0.2),
+    "n_events": 2_000_000,
+    "seed": 4,
+}
+
+# ---------------------------------------------------------------- C5
+# Stream of toy fits of the C1 model with uneven event counts.
+C5 = {
+    "name": "c5_serving",
+    "base": C1,
+    "n_requests": 4096,
+    "n_range": (1_000, 1_000_000),
+    "rate_hz": 200.0,
+    "jitter": 0.10,
+    "seed": 5,
+}
+
+# ---------------------------------------------------------------- Listing 2
+# Product of two exponentials in x and y (the paper's second listing).
+LISTING2 = {
+    "name": "listing2_prod",
+    "obs": [("x", 0.0, 10.0), ("y", 0.0, 10.0)],
+    "params": [("alpha_x", -2.4, 0.1, -10.0, 10.0, False),
+               ("alpha_y", -1.1, 0.1, -10.0, 10.0, False)],
+    "truth": {"alpha_x": -0.5, "alpha_y": -1.0},
+    "model": {"op": "prod", "children": [
+        {"op": "exp", "obs": "x", "par": ["alpha_x"]},
+        {"op": "exp", "obs": "y", "par": ["alpha_y"]},
+    ]},
+    "n_events": 100_000,
+    "seed": 11,
+}
+
+
+def workload(name):
+    return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "listing2": LISTING2}[name]

@@ -1,0 +1,202 @@
+"""Benchmark of the unbinned NLL + gradient hot path on one MI355X.
+
+Default workload: the composite Gaussian + exponential model on x in
+[5.2, 5.3] (f = 0.3, mu = 5.28, sigma = 0.003, beta = -2), 10^7 synthetic
+events, 4 free parameters, FP32 per-event arithmetic with double
+compensated accumulation.  A step is one pass of the whole hot path:
+parameter staging and normalisation on the host, the per-event evaluation +
+adjoint kernel, the two-pass reduction, and the host-side minimiser update
+(a BFGS iteration's worth of work is exercised by the fit measurements).
+
+Prints ONE JSON line with the metric (events x NLL+grad evaluations per
+second), the roofline of the dominant kernel, the per-fit comparisons against
+the plain FP64 numerical-gradient path, and the oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-fits", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def theta_sequence(truth, k, rng):
+    """Parameter points a minimiser would visit near the optimum."""
+    t = np.array(truth)
+    scale = np.array([2e-4, 2e-6, 2e-6, 2e-3])
+    return t + scale * rng.standard_normal((k, t.size))
+
+
+def time_evals(P, g, ds, thetas, stream, grad=True):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for th in thetas:
+        if grad:
+            P.nll_grad(g, ds, th, stream)
+        else:
+            P.nll_eval(g, ds, th, stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def fit_timing(P, g, ds, stream, mode, reps):
+    import torch
+    out = []
+    res = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = P.fit(g, ds, grad_mode=mode, stream=stream)
+        torch.cuda.synchronize()
+        out.append(time.perf_counter() - t0)
+    return float(np.median(out)), res
+
+
+def cpu_baseline(spec, data, seconds):
+    """The oracle (plain FP64 C++) on a bounded sample, all host threads."""
+    from oracle import oracle as O
+    m = O.Model(spec)
+    nt = O.n_threads_default()
+    n = min(2_000_000, data["x"].size)
+    sample = {"x": np.ascontiguousarray(data["x"][:n])}
+    th = m.theta(spec["truth"])
+    m.nll(th, sample, grad=True, n_threads=nt)
+    reps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds or reps < 2:
+        m.nll(th, sample, grad=True, n_threads=nt)
+        reps += 1
+    el = time.perf_counter() - t0
+    return {"value": n * reps / el, "unit": "events*NLL+grad evals/s", "cores": nt, "kind": "oracle",
+            "sample": "first %d of the 10^7 events, %d NLL+gradient evaluations in %.1f s" % (n, reps, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1311_1753_amd as P
+    import synthgen as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    spec = S.C2
+    n = spec["n_events"]
+    t_gen = time.perf_counter()
+    data = S.gen_c2()
+    log("generated %d events in %.1f s" % (n, time.perf_counter() - t_gen))
+    g = P.Graph.from_spec(spec)
+    ds32 = P.Dataset(g, data, "fp32", stream)
+    ds64 = P.Dataset(g, data, "fp64", stream)
+    truth = g.theta(spec["truth"])
+    rng = np.random.default_rng(0)
+
+    # ---------------- warmup + timed region (FP32-eval NLL + gradient)
+    for th in theta_sequence(truth, args.warmup, rng):
+        P.nll_grad(g, ds32, th, stream)
+    thetas = theta_sequence(truth, args.steps, rng)
+    torch.cuda.synchronize()
+    P.profile(True)
+    el = time_evals(P, g, ds32, thetas, stream)
+    eval_ms, red_ms, ncalls = P.profile(False)
+    ms_step = el / args.steps * 1e3
+    value = n * args.steps / el
+    k_ms = eval_ms / max(ncalls, 1)
+    alg_bytes = 4.0 * n
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    log("fp32 nll+grad: %.3f ms/step, kernel %.4f ms, reduce %.4f ms" % (ms_step, k_ms, red_ms / max(ncalls, 1)))
+
+    extra = {}
+    # ---------------- FP64 analytic and FP64 NLL-only (numerical-gradient path)
+    k64 = max(50, args.steps // 10)
+    th64 = theta_sequence(truth, k64, rng)
+    P.profile(True)
+    el64 = time_evals(P, g, ds64, th64, stream)
+    e64, _, c64 = P.profile(False)
+    P.profile(True)
+    el64n = time_evals(P, g, ds64, th64, stream, grad=False)
+    e64n, _, c64n = P.profile(False)
+    n_free = int(g.free_mask().sum())
+    extra["fp64_nll_grad_events_evals_per_s"] = n * k64 / el64
+    extra["fp64_nll_grad_kernel_ms"] = e64 / max(c64, 1)
+    extra["fp64_nll_only_kernel_ms"] = e64n / max(c64n, 1)
+    extra["fp64_numerical_grad_events_evals_per_s"] = n * k64 / (el64n * (1 + 2 * n_free))
+    extra["fp32_vs_fp64_numerical_grad"] = value / extra["fp64_numerical_grad_events_evals_per_s"]
+
+    # ---------------- whole fits (minimiser + every evaluation)
+    if not args.no_fits:
+        t32, r32 = fit_timing(P, g, ds32, stream, "analytic", 3)
+        t64, r64 = fit_timing(P, g, ds64, stream, "analytic", 3)
+        t64n, r64n = fit_timing(P, g, ds64, stream, "numerical", 2)
+        sig = r64["errors"]
+        extra["fit_s"] = {"fp32_analytic": t32, "fp64_analytic": t64, "fp64_numerical": t64n}
+        extra["fit_evals"] = {"fp32_analytic": r32["n_eval"], "fp64_analytic": r64["n_eval"],
+                              "fp64_numerical": r64n["n_eval"]}
+        extra["fits_per_s_fp32_analytic"] = 1.0 / t32
+        extra["fits_per_s_fp64_numerical"] = 1.0 / t64n
+        extra["fp32_fit_dtheta_over_sigma_vs_fp64"] = float(np.max(np.abs(r32["theta"] - r64["theta"]) / sig))
+
+    # ---------------- oracle on the host
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(spec, data, args.cpu_seconds)
+        log("oracle: %.3g events*evals/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": "events x NLL+grad evaluations per second",
+        "value": value,
+        "unit": "events*evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gauss+exp composite, x in [5.2,5.3], 1e7 events, 4 free params, "
+                               "FP32-eval NLL+analytic gradient, FP64 compensated accumulation",
+                   "n_events": n, "n_free_params": n_free},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_tree<float,16,8,2,false,true>", "kernel_ms": k_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * hipfit.h -- C ABI of the MI355X (gfx950) unbinned maximum-likelihood library.
+ *
+ * The library evaluates, on one GPU, the negative log-likelihood
+ *     NLL(theta) = -sum_i ln P(x_i; theta)
+ * of a tree of normalised probability densities P over a set of events, and
+ * its exact gradient, and minimises it.  The split of the interface follows
+ * the four components of a GooFit program (paper, section "GooFit code"):
+ * variables (hf_obs / hf_param), the PDF (pdf_graph), the data (dataset) and
+ * the fit manager (fit, batch_*).
+ *
+ * Conventions for every entry point:
+ *   - return 0 (HF_OK) on success or a negative hf_status;
+ *   - on error, out-parameters are left untouched (except where stated) and
+ *     hf_last_error() returns a message for the calling thread;
+ *   - no C++ exception and no abort crosses this interface;
+ *   - all pointers are host pointers unless the name says "dev";
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream);
+ *   - handles are owned by the caller and released with the matching
+ *     destroy/free call;
+ *   - calls that use one dataset (or one batch engine) must not overlap in
+ *     time: each holds a per-object device workspace.
+ */
+#ifndef HIPFIT_H
+#define HIPFIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum hf_status {
+  HF_OK = 0,
+  HF_E_INVALID = -1,        /* bad argument (NULL handle, size out of range) */
+  HF_E_GRAPH = -2,          /* invalid PDF tree (see pdf_graph_create) */
+  HF_E_SHAPE = -3,          /* dataset / parameter shape does not match the graph */
+  HF_E_OOM = -4,            /* device or pinned host allocation failed */
+  HF_E_HIP = -5,            /* a HIP runtime call failed (message has the HIP error) */
+  HF_E_DOMAIN = -6,         /* event outside its box / Dalitz plot, or density <= 0 or not finite */
+  HF_E_NOT_CONVERGED = -7,  /* minimiser hit its iteration limit */
+  HF_E_BUDGET = -8,         /* batch admission: the fit does not fit the device-memory budget now */
+  HF_E_FULL = -9            /* batch admission: no free slot */
+};
+
+/* Arithmetic of the per-event evaluation.  The reductions, normalisations
+ * and minimiser are always double precision. */
+typedef enum {
+  HF_FP64 = 0,              /* events stored and evaluated in double */
+  HF_FP32_EVAL = 1          /* events stored as float offsets from a per-column double
+                               reference; location differences (x - mu, s - m0^2) formed in
+                               double, the rest of the per-event arithmetic in float,
+                               accumulation in double with compensated sums */
+} hf_precision;
+
+/* Node kinds of the PDF tree (paper, sections "GooFit code", "Combining
+ * functions", "Results").  Every node is a density normalised over its
+ * observables' box. */
+enum hf_op {
+  HF_OP_EXP = 1,     /* e^{alpha x}/int_box; par = {alpha}; obs = {x}                    */
+  HF_OP_GAUSS = 2,   /* exp(-(x-mu)^2/(2 sigma^2))/int_box; par = {mu, sigma}; obs = {x}   */
+  HF_OP_POLY = 3,    /* (1 + sum_k a_k (x-x0)^k)/int_box; par = {a_1..a_d}; obs = {x};
+                        consts = {x0}; density <= 0 at an event is a domain error           */
+  HF_OP_ADD = 4,     /* sum_{j<K} f_j P_j + (1 - sum f_j) P_K; K >= 2 children; par = the
+                        K-1 fractions; children over the same box, each normalised          */
+  HF_OP_PROD = 5,    /* prod_j P_j over disjoint observables; K >= 2 children; no par       */
+  HF_OP_DALITZ = 6,  /* |1 + sum_k c_k A_k(s12, s13)|^2 / N_A over the Dalitz plot;
+                        obs = {s12, s13}; par = {Re c_1, Im c_1, ..., Re c_R, Im c_R};
+                        consts = DALITZ block (below)                                       */
+  HF_OP_TDDP = 7     /* time-dependent Dalitz density with per-event Gaussian resolution:
+                        [a_c C(t) + a_0 E(t; 1/tau) + a_s S(t)] / N_T, where
+                        a_c = (|A|^2+|Abar|^2)/2, a_0 = (|A|^2-|Abar|^2)/2, a_s = -Re(A* Abar),
+                        Abar(s12,s13) = A(s13,s12), C/S = (E(G-) +/- E(G+))/2,
+                        G-/+ = (1 -/+ y)/tau and E(t; G, sigma_t) the Gaussian-convolved
+                        decay e^{-G t}; t is normalised over the real line;
+                        obs = {s12, s13, t, sigma_t}; par = {Re c_1, Im c_1, ..., tau, y};
+                        consts = DALITZ block                                              */
+};
+
+/* DALITZ block of node constants:
+ *   {M, m1, m2, m3, r, G, R, then R times (channel, m0, Gamma0, J)}
+ * M: parent mass; m1..m3: daughter masses (GeV); r: Blatt-Weisskopf radius
+ * (1/GeV); G: normalisation grid size (G x G midpoint cells over the box
+ * [(m1+m2)^2, (M-m3)^2] x [(m1+m3)^2, (M-m2)^2], a cell counting when its
+ * centre is inside the plot in both orderings); R <= 8 resonances; channel
+ * 12, 13 or 23 (pair of daughters); J in {0, 1, 2}.  Amplitude of a
+ * resonance: B_J(q) Z_J BW(s_AB) with the mass-dependent width
+ * Gamma(s) = Gamma0 (q/q0)^{2J+1} (m0/sqrt s) B_J^2, Blatt-Weisskopf ratios
+ * B_J and Zemach spin factors Z_J.  The constant term has c_0 = 1. */
+
+/* Observable: Variable(name, lower limit, upper limit) of the paper's first
+ * listing.  lo < hi; infinite limits are allowed only for the t and sigma_t
+ * observables of a TDDP node. */
+typedef struct { const char* name; double lo, hi; } hf_obs;
+
+/* Fit parameter: Variable(name, initial value, step size, lower, upper) of the
+ * first listing.  lo == hi means unbounded.  fixed != 0 keeps it at `init`
+ * in fits (its gradient entry is 0). */
+typedef struct { const char* name; double init, step, lo, hi; int32_t fixed; } hf_param;
+
+/* One node of the tree, in post-order (children before parents). */
+typedef struct {
+  int32_t op;                        /* hf_op */
+  int32_t n_child; const int32_t* child;   /* indices of earlier nodes */
+  int32_t n_par;   const int32_t* par;     /* indices into the hf_param array */
+  int32_t n_obs;   const int32_t* obs;     /* indices into the hf_obs array */
+  int32_t n_const; const double* consts;   /* op-specific constants (above) */
+} hf_node;
+
+typedef struct pdf_graph pdf_graph;
+typedef struct dataset dataset;
+typedef struct batch_engine batch_engine;
+
+/* ------------------------------------------------------------------ graph
+ * Validates and flattens the tree into the per-launch opcode / constant
+ * table.  Errors (HF_E_GRAPH): child index not earlier than its parent or
+ * used twice, root not the last reachable node, PROD children sharing an
+ * observable, ADD children over different observables, wrong par/obs/const
+ * counts for the op, lo >= hi, an unbounded box for an EXP/GAUSS/POLY/DALITZ
+ * observable, more than 16 nodes, 32 gradient slots or 8 observables.  The
+ * arrays are copied; no GPU work is done here. */
+int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param* par, int32_t n_par,
+                     const hf_node* nodes, int32_t n_nodes, int32_t root, pdf_graph** out);
+void pdf_graph_destroy(pdf_graph* g);
+/* Number of observables and parameters of a graph. */
+int pdf_graph_shape(const pdf_graph* g, int32_t* n_obs, int32_t* n_par);
+
+/* ------------------------------------------------------------------ data
+ * Copies n_events events given as n_obs host columns (host_cols[o][i] is
+ * observable o of event i, double) to device memory as structure-of-arrays
+ * columns in the requested precision (the paper's setData step, section
+ * "GooFit code").  Every value must lie inside its observable's box (and
+ * Dalitz events inside the plot): otherwise HF_E_DOMAIN and nothing is
+ * allocated.  Event order is preserved.  n_events may be 0.  Blocks until the
+ * copy is done; the caller keeps ownership of the host columns. */
+int dataset_upload(const pdf_graph* g, const double* const* host_cols, int64_t n_events,
+                   hf_precision prec, void* hip_stream, dataset** out);
+void dataset_free(dataset* d);
+/* Device bytes held by a dataset (columns + workspace). */
+int64_t dataset_device_bytes(const dataset* d);
+
+/* ------------------------------------------------------------------ likelihood
+ * params: n_par doubles (external values, fixed ones included).  Runs the
+ * per-event evaluation and the deterministic two-pass reduction on
+ * `hip_stream` and blocks until the result is on the host.  A density <= 0 or
+ * not finite at any event sets *nll = +INF and returns HF_E_DOMAIN.
+ * Results are bitwise reproducible for the same inputs. */
+int nll_eval(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream,
+             double* nll);
+/* As nll_eval, plus grad[n_par] = dNLL/dtheta from the per-event adjoint
+ * (0 for fixed parameters), including the derivative of the normalisation. */
+int nll_grad(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream,
+             double* nll, double* grad);
+/* n_fits independent evaluations (same graph, own datasets and parameters,
+ * params is n_fits x n_par row-major) in one launch; each result is bitwise
+ * equal to what nll_grad returns for that fit alone.  nll[n_fits],
+ * grad[n_fits x n_par]; per-fit domain errors give +INF for that fit only
+ * (the call still returns HF_OK). */
+int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int32_t n_fits,
+                     const double* params, void* hip_stream, double* nll, double* grad);
+
+/* ------------------------------------------------------------------ fit
+ * Quasi-Newton (BFGS) minimisation with MINUIT-style sine transforms for
+ * bounded parameters, a bracketing line search, and a final Hessian from
+ * central differences of the gradient (the MINUIT role of the paper's
+ * FitManager section).  Errors are sqrt(diag(H^-1)), H the NLL Hessian. */
+typedef struct {
+  int32_t max_iter;     /* BFGS iterations (<= 0: 500) */
+  double edm_tol;       /* stop when 0.5 g^T H^-1 g < edm_tol (<= 0: 1e-10) */
+  int32_t grad_mode;    /* 0: analytic gradient (nll_grad); 1: central differences of nll_eval,
+                           2 n_free extra evaluations per gradient */
+  int32_t want_errors;  /* nonzero: compute the final Hessian, errors and covariance */
+} hf_fit_opts;
+
+typedef struct {
+  double nll, edm;
+  int32_t n_iter, n_eval, status;   /* n_eval counts likelihood evaluations; status hf_status */
+} hf_fit_summary;
+
+/* params_inout: start values in, fitted values out (n_par).  errors_out
+ * (n_par, nullable) and cov_out (n_par x n_par row-major, nullable) are 0 for
+ * fixed parameters.  Returns HF_OK, HF_E_NOT_CONVERGED (results still
+ * written) or an error. */
+int fit(const pdf_graph* g, const dataset* d, const hf_fit_opts* opts, void* hip_stream,
+        double* params_inout, double* errors_out, double* cov_out, hf_fit_summary* summary);
+
+/* ------------------------------------------------------------------ batched serving
+ * A batch engine holds up to max_slots concurrent fits of one graph.  Each
+ * batch_step advances every active fit's minimiser by one likelihood
+ * evaluation, all of them in one graph-captured launch, so fits that are
+ * admitted while others run share the device.  Admission is by device
+ * memory: the datasets of the active fits may hold at most hbm_budget_bytes.
+ * The engine borrows the datasets; the caller frees them after the fit is
+ * polled. */
+int batch_create(const pdf_graph* g, int32_t max_slots, int64_t hbm_budget_bytes, void* hip_stream,
+                 batch_engine** out);
+void batch_destroy(batch_engine* b);
+/* Starts a fit of dataset d from params_init (n_par).  HF_E_FULL: no slot;
+ * HF_E_BUDGET: not enough budget now (retry later); HF_E_INVALID: the dataset
+ * alone exceeds the whole budget or its precision differs from the engine's
+ * first dataset. */
+int batch_admit(batch_engine* b, const dataset* d, const double* params_init, const hf_fit_opts* opts,
+                int64_t tag, int32_t* slot_out);
+/* One evaluation for every active fit; blocks until done.  n_active_out: fits
+ * still running after the step; n_done_out: fits finished and waiting for
+ * batch_poll. */
+int batch_step(batch_engine* b, int32_t* n_active_out, int32_t* n_done_out);
+/* Returns up to max finished fits and frees their slots and budget.  For each
+ * i < return value: tags[i], status[i], params[i*n_par..], errors[i*n_par..],
+ * nll[i], n_eval[i] (any output pointer may be NULL).  Returns the count
+ * (>= 0) or an error. */
+int batch_poll(batch_engine* b, int32_t max, int64_t* tags, int32_t* status, double* params,
+               double* errors, double* nll, int32_t* n_eval);
+/* Cancels an active fit by tag (its slot and budget are freed at once). */
+int batch_cancel(batch_engine* b, int64_t tag);
+
+/* ------------------------------------------------------------------ misc
+ * Dalitz-plot membership (the same rule as the normalisation grid) of n
+ * points for the DALITZ/TDDP node `node` of a graph: out[i] = 1 inside. */
+int hf_dalitz_inside(const pdf_graph* g, int32_t node, int64_t n, const double* s12,
+                     const double* s13, uint8_t* out);
+/* Kernel timing for measurement: enable = 1 resets the counters and starts
+ * recording HIP events on the caller's stream around the likelihood kernel
+ * and the reduction of every nll_eval / nll_grad; enable = 0 stops; any other
+ * value only reads.  Outputs (nullable): total milliseconds of the likelihood
+ * kernels and of the reductions, and the number of timed calls so far.  Not
+ * for concurrent use from several threads. */
+int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch);
+/* Last error message of the calling thread ("" if none). */
+const char* hf_last_error(void);
+/* Library version string. */
+const char* hf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HIPFIT_H */

@@ -1,0 +1,10 @@
+"""hipfit: unbinned maximum-likelihood fits on MI355X (gfx950).
+
+The per-event PDF-tree evaluation, the adjoint gradient, the reductions, the
+normalisation grids and the minimiser run in libhipfit.so (hand-written HIP
+kernels + C++ runtime, C ABI in include/hipfit.h).  This package binds that
+library; PyTorch is used only for device streams (and the autograd wrapper).
+"""
+from ._lib import HipfitError, lib  # noqa: F401
+from .core import (FP32_EVAL, FP64, Dataset, Graph, fit, nll_eval, nll_grad,  # noqa: F401
+                   nll_grad_batched, profile, version)

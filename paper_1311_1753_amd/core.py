@@ -1,0 +1,256 @@
+"""Graph / Dataset handles over the C ABI and the likelihood calls.
+
+A `Graph` is a validated PDF tree (pdf_graph_create), a `Dataset` is a set of
+events copied to the GPU (dataset_upload).  Trees are given as nested dicts
+(the same neutral form the workload descriptions use):
+
+    {"op": "add", "par": ["f"], "children": [
+        {"op": "gauss", "obs": "x", "par": ["mu", "sigma"]},
+        {"op": "exp", "obs": "x", "par": ["beta"]}]}
+
+with observables [(name, lo, hi)] and parameters
+[(name, init, step, lo, hi, fixed)].
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+FP64 = _lib.HF_FP64
+FP32_EVAL = _lib.HF_FP32_EVAL
+_CH = {"12": 12, "13": 13, "23": 23}
+
+
+def _stream_ptr(stream):
+    """hipStream_t from None / int / torch.cuda.Stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    ptr = getattr(stream, "cuda_stream", None)
+    if ptr is not None:
+        return ptr or None
+    raise TypeError("stream must be None, an int handle or a torch.cuda.Stream")
+
+
+def _prec(p):
+    if p in (FP64, "fp64", "f64", "double"):
+        return FP64
+    if p in (FP32_EVAL, "fp32", "f32", "fp32_eval", "float"):
+        return FP32_EVAL
+    raise ValueError("precision must be 'fp64' or 'fp32'")
+
+
+def dalitz_consts(dz):
+    """Constant block of a DALITZ / TDDP node (see include/hipfit.h)."""
+    res = dz["resonances"]
+    c = [dz["M"], dz["m1"], dz["m2"], dz["m3"], dz["r"], float(dz["grid"]), float(len(res))]
+    for r in res:
+        c += [float(_CH[r["ch"]]), r["m0"], r["g0"], float(r["J"])]
+    return c
+
+
+class Graph:
+    """A validated, flattened PDF tree living in the library."""
+
+    def __init__(self, obs, params, model):
+        self.obs = [tuple(o) for o in obs]
+        self.params = [tuple(p) if len(p) == 6 else tuple(p) + (False,) for p in params]
+        self.obs_names = [o[0] for o in self.obs]
+        self.par_names = [p[0] for p in self.params]
+        self.model = model
+        nodes = []
+        keep = []
+
+        def arr(vals, ct):
+            a = (ct * max(len(vals), 1))(*vals)
+            keep.append(a)
+            return a
+
+        def flatten(node):
+            kids = [flatten(c) for c in node.get("children", [])]
+            op = node["op"]
+            ob = node.get("obs", [])
+            ob = [ob] if isinstance(ob, str) else list(ob)
+            par = [self.par_names.index(n) for n in node.get("par", [])]
+            obs_i = [self.obs_names.index(n) for n in ob]
+            consts = []
+            if op == "poly":
+                consts = [float(node.get("x0", 0.0))]
+            elif op in ("dalitz", "tddp"):
+                consts = dalitz_consts(node["dalitz"])
+            n = _lib.hf_node()
+            n.op = _lib.OP[op]
+            n.n_child = len(kids)
+            n.child = arr(kids, ctypes.c_int32)
+            n.n_par = len(par)
+            n.par = arr(par, ctypes.c_int32)
+            n.n_obs = len(obs_i)
+            n.obs = arr(obs_i, ctypes.c_int32)
+            n.n_const = len(consts)
+            n.consts = arr(consts, ctypes.c_double)
+            nodes.append(n)
+            return len(nodes) - 1
+
+        root = flatten(model)
+        o_arr = (_lib.hf_obs * len(self.obs))(*[_lib.hf_obs(o[0].encode(), o[1], o[2]) for o in self.obs])
+        p_arr = (_lib.hf_param * max(len(self.params), 1))(
+            *[_lib.hf_param(p[0].encode(), p[1], p[2], p[3], p[4], int(bool(p[5]))) for p in self.params])
+        n_arr = (_lib.hf_node * len(nodes))(*nodes)
+        h = ctypes.c_void_p()
+        check(lib().pdf_graph_create(o_arr, len(self.obs), p_arr, len(self.params), n_arr, len(nodes), root,
+                                     ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_spec(cls, spec):
+        return cls(spec["obs"], spec["params"], spec["model"])
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_par(self):
+        return len(self.params)
+
+    def theta(self, values=None):
+        th = np.array([p[1] for p in self.params], dtype=np.float64)
+        if values:
+            for k, v in values.items():
+                th[self.par_names.index(k)] = v
+        return th
+
+    def free_mask(self):
+        return np.array([not p[5] for p in self.params])
+
+    def dalitz_inside(self, s12, s13):
+        a = np.ascontiguousarray(s12, dtype=np.float64)
+        b = np.ascontiguousarray(s13, dtype=np.float64)
+        out = np.zeros(a.size, dtype=np.uint8)
+        check(lib().hf_dalitz_inside(self._h, 0, a.size, a.ctypes.data_as(_lib._DP), b.ctypes.data_as(_lib._DP),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out.astype(bool)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().pdf_graph_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+class Dataset:
+    """Events of a graph's observables copied to the GPU (structure of arrays)."""
+
+    def __init__(self, graph, columns, precision="fp64", stream=None):
+        self.graph = graph
+        self.precision = _prec(precision)
+        n = None
+        arrs = []
+        for name in graph.obs_names:
+            if name in columns:
+                a = np.ascontiguousarray(columns[name], dtype=np.float64)
+            else:
+                a = None
+            if a is not None:
+                if n is None:
+                    n = a.size
+                elif a.size != n:
+                    raise ValueError("columns differ in length")
+            arrs.append(a)
+        if n is None:
+            raise ValueError("no columns")
+        arrs = [a if a is not None else np.zeros(n) for a in arrs]
+        self._keep = arrs
+        ptrs = (_lib._DP * len(arrs))(*[a.ctypes.data_as(_lib._DP) for a in arrs])
+        h = ctypes.c_void_p()
+        check(lib().dataset_upload(graph.handle, ptrs, n, self.precision, _stream_ptr(stream), ctypes.byref(h)))
+        self._keep = None
+        self._h = h
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def device_bytes(self):
+        return lib().dataset_device_bytes(self._h)
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dataset_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _dp(a):
+    return a.ctypes.data_as(_lib._DP)
+
+
+def nll_eval(graph, ds, theta, stream=None, allow_domain=True):
+    """NLL at theta (+inf outside the density's domain when allow_domain)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = ctypes.c_double()
+    check(lib().nll_eval(graph.handle, ds.handle, _dp(th), _stream_ptr(stream), ctypes.byref(out)),
+          allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
+    return out.value
+
+
+def nll_grad(graph, ds, theta, stream=None, allow_domain=True):
+    """(NLL, dNLL/dtheta) at theta from the per-event adjoint kernels."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = ctypes.c_double()
+    g = np.zeros(graph.n_par)
+    check(lib().nll_grad(graph.handle, ds.handle, _dp(th), _stream_ptr(stream), ctypes.byref(out), _dp(g)),
+          allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
+    return out.value, g
+
+
+def nll_grad_batched(graph, datasets, thetas, stream=None):
+    """NLL and gradient of many fits (same graph) in one launch."""
+    n = len(datasets)
+    th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).reshape(n, graph.n_par))
+    hs = (ctypes.c_void_p * n)(*[d.handle.value for d in datasets])
+    nll = np.zeros(n)
+    g = np.zeros((n, graph.n_par))
+    check(lib().nll_grad_batched(graph.handle, hs, n, _dp(th), _stream_ptr(stream), _dp(nll), _dp(g)))
+    return nll, g
+
+
+def fit(graph, ds, theta0=None, grad_mode="analytic", max_iter=500, edm_tol=1e-10, want_errors=True,
+        stream=None):
+    """Minimise the NLL; returns a dict with theta, errors, cov, nll, edm, n_iter, n_eval, status."""
+    th = np.ascontiguousarray(graph.theta() if theta0 is None else theta0, dtype=np.float64).copy()
+    err = np.zeros(graph.n_par)
+    cov = np.zeros((graph.n_par, graph.n_par))
+    o = _lib.hf_fit_opts(max_iter, edm_tol, {"analytic": 0, "numerical": 1}[grad_mode], int(want_errors))
+    s = _lib.hf_fit_summary()
+    rc = lib().fit(graph.handle, ds.handle, ctypes.byref(o), _stream_ptr(stream), _dp(th), _dp(err), _dp(cov),
+                   ctypes.byref(s))
+    check(rc, allow=(_lib.HF_E_NOT_CONVERGED,))
+    return {"theta": th, "errors": err, "cov": cov, "nll": s.nll, "edm": s.edm, "n_iter": s.n_iter,
+            "n_eval": s.n_eval, "status": _lib.STATUS_NAMES.get(s.status, str(s.status))}
+
+
+def profile(enable=None):
+    """Kernel timing hook: profile(True) resets and starts, profile(False)
+    stops; returns (eval_ms, reduce_ms, n_calls) accumulated so far."""
+    e, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    flag = -1 if enable is None else int(bool(enable))
+    check(lib().hf_profile(flag, ctypes.byref(e), ctypes.byref(r), ctypes.byref(n)))
+    return e.value, r.value, n.value
+
+
+def version():
+    return lib().hf_version().decode()

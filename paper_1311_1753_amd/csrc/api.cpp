@@ -1,0 +1,275 @@
+// Datasets and likelihood evaluations of the C ABI.
+//
+// A dataset is one device allocation: structure-of-arrays event columns
+// (each 256-byte aligned, float offsets from a per-column double reference in
+// the FP32-eval path, raw doubles in the FP64 path) followed by the per-tile
+// partial rows of the reduction.  An evaluation stages the constant table on
+// the host, launches the tile kernel and the fixed-order reduction on the
+// caller's stream, and reads the reduced row from pinned, device-mapped host
+// memory written directly by the reduction kernel.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+namespace hf {
+
+namespace {
+
+// Pinned staging buffer shared by uploads (serialised by a mutex).
+std::mutex g_stage_mu;
+void* g_stage = nullptr;
+size_t g_stage_bytes = 0;
+constexpr size_t kStageChunk = size_t(32) << 20;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// Optional kernel timing (hf_profile): HIP events recorded on the caller's
+// stream around the likelihood kernel and the reduction of eval_one.
+struct Profile {
+  bool on = false;
+  bool init = false;
+  hipEvent_t e[3];
+  double eval_ms = 0.0, reduce_ms = 0.0;
+  int64_t n = 0;
+};
+static Profile g_prof;
+static std::mutex g_prof_mu;
+
+static int ensure_result_buffer(const dataset* dc) {
+  dataset* d = const_cast<dataset*>(dc);
+  if (d->res_host) return HF_OK;
+  void* h = nullptr;
+  hipError_t e = hipHostMalloc(&h, (kMaxSlots + 2) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(result row)");
+  void* dv = nullptr;
+  e = hipHostGetDevicePointer(&dv, h, 0);
+  if (e != hipSuccess) {
+    hipHostFree(h);
+    return hip_fail(e, "hipHostGetDevicePointer");
+  }
+  d->res_host = (double*)h;
+  d->res_dev = (double*)dv;
+  return HF_OK;
+}
+
+int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t st, bool want_grad, double* nll,
+             double* grad) {
+  const int np = (int)g->par.size();
+  if (int rc = ensure_grid(const_cast<pdf_graph*>(g), st)) return rc;
+  StagedCall sc;
+  stage(g, th, d->prec, sc);
+  if (!sc.ok) {
+    *nll = INFINITY;
+    if (grad) for (int p = 0; p < np; ++p) grad[p] = NAN;
+    return fail(HF_E_DOMAIN, "parameters outside the density's domain");
+  }
+  const int S = g->prog.n_slots;
+  std::vector<double> sums(S + 1, 0.0);
+  if (d->n > 0) {
+    if (int rc = ensure_result_buffer(d)) return rc;
+    EvalArgs a;
+    a.prog = sc.prog;
+    for (int c = 0; c < kMaxCols; ++c) a.col[c] = d->col[c];
+    a.n_events = d->n;
+    a.partials = d->partials;
+    a.stride = S + 2;
+    a.pad = 0;
+    const bool prof = g_prof.on;
+    if (prof) hipEventRecord(g_prof.e[0], st);
+    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, d->n_tiles, st);
+    if (prof) hipEventRecord(g_prof.e[1], st);
+    if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
+    FitRec fr;
+    std::memset(&fr, 0, sizeof(fr));
+    fr.partials = d->partials;
+    fr.n_tiles = (int32_t)d->n_tiles;
+    fr.result = d->res_dev;
+    fr.active = 1;
+    e = launch_reduce_one(fr, S + 2, want_grad ? S : 0, st);
+    if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
+    if (prof) hipEventRecord(g_prof.e[2], st);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (prof) {
+      float t1 = 0.f, t2 = 0.f;
+      hipEventElapsedTime(&t1, g_prof.e[0], g_prof.e[1]);
+      hipEventElapsedTime(&t2, g_prof.e[1], g_prof.e[2]);
+      g_prof.eval_ms += t1;
+      g_prof.reduce_ms += t2;
+      g_prof.n += 1;
+    }
+    for (int j = 0; j < (want_grad ? S + 1 : 1); ++j) sums[j] = d->res_host[j];
+  }
+  const double n = (double)d->n;
+  const double v = -sums[0] + n * sc.ht.lnN;
+  if (grad) {
+    for (int p = 0; p < np; ++p) grad[p] = n * sc.ht.dlnN[p];
+    for (int j = 0; j < S; ++j) grad[g->slot_par[j]] -= sums[1 + j];
+    for (int p = 0; p < np; ++p)
+      if (g->par[p].fixed) grad[p] = 0.0;
+  }
+  if (!std::isfinite(v)) {
+    *nll = INFINITY;
+    return fail(HF_E_DOMAIN, "density <= 0 or not finite at some event");
+  }
+  *nll = v;
+  return HF_OK;
+}
+
+}  // namespace hf
+
+using namespace hf;
+
+extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols, int64_t n, hf_precision prec,
+                              void* hip_stream, dataset** out) {
+  try {
+    if (!g || !out || (n > 0 && !host_cols)) return fail(HF_E_INVALID, "dataset_upload: NULL argument");
+    if (n < 0 || n > (int64_t(1) << 36)) return fail(HF_E_INVALID, "dataset_upload: n_events out of range");
+    if (prec != HF_FP64 && prec != HF_FP32_EVAL) return fail(HF_E_INVALID, "dataset_upload: bad precision");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int nc = (int)g->obs_of_col.size();
+    // validation on the host: every value inside its box, Dalitz points inside the plot
+    for (int c = 0; c < nc && n > 0; ++c) {
+      const int o = g->obs_of_col[c];
+      const double* x = host_cols[o];
+      if (!x) return fail(HF_E_INVALID, "dataset_upload: NULL column for a used observable");
+      const double lo = g->obs[o].lo, hi = g->obs[o].hi;
+      for (int64_t i = 0; i < n; ++i)
+        if (!(x[i] >= lo && x[i] <= hi) || !std::isfinite(x[i]))
+          return fail(HF_E_DOMAIN, "dataset_upload: event " + std::to_string(i) + " outside the box of '" +
+                                       g->obs[o].name + "'");
+    }
+    if (g->dz.node >= 0 && n > 0) {
+      const NodeInfo& nd = g->nodes[g->dz.node];
+      const double* a = host_cols[nd.obs[0]];
+      const double* b = host_cols[nd.obs[1]];
+      for (int64_t i = 0; i < n; ++i)
+        if (!dalitz_inside(g->dz, a[i], b[i]))
+          return fail(HF_E_DOMAIN, "dataset_upload: event " + std::to_string(i) + " outside the Dalitz plot");
+      if (g->dz.tddp) {
+        const double* s = host_cols[nd.obs[3]];
+        for (int64_t i = 0; i < n; ++i)
+          if (!(s[i] > 0.0)) return fail(HF_E_DOMAIN, "dataset_upload: sigma_t must be > 0");
+      }
+    }
+    std::unique_ptr<dataset> d(new dataset);
+    d->g = g;
+    d->prec = prec;
+    d->n = n;
+    d->n_cols = nc;
+    const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
+    const int64_t tile = kind_tile(g->kind);
+    d->n_tiles = (n + tile - 1) / tile;
+    const size_t col_bytes = align256((size_t)n * es);
+    const size_t part_bytes = align256((size_t)d->n_tiles * (g->prog.n_slots + 2) * sizeof(double));
+    const size_t total = col_bytes * nc + part_bytes + 256;
+    void* blk = nullptr;
+    hipError_t e = hipMalloc(&blk, total);
+    if (e != hipSuccess) return fail(HF_E_OOM, std::string("dataset_upload: hipMalloc: ") + hipGetErrorString(e));
+    d->block = blk;
+    d->bytes = (int64_t)total;
+    char* base = (char*)blk;
+    for (int c = 0; c < nc; ++c) {
+      d->col[c] = base + c * col_bytes;
+      d->ref[c] = column_ref(g, c, prec);
+    }
+    d->partials = (double*)(base + nc * col_bytes);
+    // convert through the pinned staging buffer, one chunk at a time
+    if (n > 0) {
+      std::lock_guard<std::mutex> lk(g_stage_mu);
+      if (!g_stage) {
+        e = hipHostMalloc(&g_stage, kStageChunk, hipHostMallocDefault);
+        if (e != hipSuccess) { g_stage = nullptr; hipFree(blk); return hip_fail(e, "hipHostMalloc(staging)"); }
+        g_stage_bytes = kStageChunk;
+      }
+      const int64_t per = (int64_t)(g_stage_bytes / es);
+      for (int c = 0; c < nc; ++c) {
+        const double* x = host_cols[g->obs_of_col[c]];
+        const double ref = d->ref[c];
+        for (int64_t b = 0; b < n; b += per) {
+          const int64_t m = std::min(per, n - b);
+          if (es == 4) {
+            float* s = (float*)g_stage;
+            for (int64_t i = 0; i < m; ++i) s[i] = (float)(x[b + i] - ref);
+          } else {
+            std::memcpy(g_stage, x + b, (size_t)m * 8);
+          }
+          e = hipMemcpyAsync((char*)d->col[c] + b * es, g_stage, (size_t)m * es, hipMemcpyHostToDevice, st);
+          if (e == hipSuccess) e = hipStreamSynchronize(st);
+          if (e != hipSuccess) { hipFree(blk); return hip_fail(e, "dataset_upload: copy"); }
+        }
+      }
+    }
+    *out = d.release();
+    return HF_OK;
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("dataset_upload: ") + ex.what());
+  }
+}
+
+extern "C" void dataset_free(dataset* d) {
+  if (!d) return;
+  if (d->block) hipFree(d->block);
+  if (d->res_host) hipHostFree(d->res_host);
+  delete d;
+}
+
+extern "C" int64_t dataset_device_bytes(const dataset* d) { return d ? d->bytes : 0; }
+
+static int check_call(const pdf_graph* g, const dataset* d, const double* params) {
+  if (!g || !d || !params) return fail(HF_E_INVALID, "NULL graph, dataset or params");
+  if (d->g != g) return fail(HF_E_SHAPE, "dataset was uploaded for another graph");
+  for (size_t p = 0; p < g->par.size(); ++p)
+    if (std::isnan(params[p])) return fail(HF_E_INVALID, "parameter is NaN");
+  return HF_OK;
+}
+
+extern "C" int nll_eval(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream, double* nll) {
+  try {
+    if (int rc = check_call(g, d, params)) return rc;
+    if (!nll) return fail(HF_E_INVALID, "nll_eval: NULL output");
+    return eval_one(g, d, params, (hipStream_t)hip_stream, false, nll, nullptr);
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("nll_eval: ") + ex.what());
+  }
+}
+
+extern "C" int nll_grad(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream, double* nll,
+                        double* grad) {
+  try {
+    if (int rc = check_call(g, d, params)) return rc;
+    if (!nll || !grad) return fail(HF_E_INVALID, "nll_grad: NULL output");
+    return eval_one(g, d, params, (hipStream_t)hip_stream, true, nll, grad);
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("nll_grad: ") + ex.what());
+  }
+}
+
+extern "C" int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (eval_ms) *eval_ms = g_prof.eval_ms;
+  if (reduce_ms) *reduce_ms = g_prof.reduce_ms;
+  if (n_launch) *n_launch = g_prof.n;
+  if (enable == 1) {
+    if (!g_prof.init) {
+      for (int i = 0; i < 3; ++i) {
+        hipError_t e = hipEventCreate(&g_prof.e[i]);
+        if (e != hipSuccess) return hip_fail(e, "hf_profile: hipEventCreate");
+      }
+      g_prof.init = true;
+    }
+    g_prof.eval_ms = g_prof.reduce_ms = 0.0;
+    g_prof.n = 0;
+    g_prof.on = true;
+  } else if (enable == 0) {
+    g_prof.on = false;
+  }
+  return HF_OK;
+}

@@ -1,0 +1,633 @@
+// PDF-tree validation, flattening and per-call staging of the constant table.
+//
+// The tree of the paper's composite PDFs (sections "Combining functions" and
+// "Adding new PDFs") is checked once, re-ordered into post-order with the
+// root last, and assigned gradient slots and constant offsets.  Before every
+// launch `stage` turns the parameter vector into the constants the kernels
+// read: derived per-node values (1/sigma, fractions, resonance constants,
+// complex coefficients, decay rates) and the normalisation ln N with its
+// gradient, computed here in double from closed forms (exponential, Gaussian,
+// polynomial, the time integrals) or from the cached Dalitz grid matrices.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <set>
+#include <string>
+
+#include "runtime.h"
+
+namespace hf {
+
+namespace {
+
+thread_local std::string g_err;
+
+bool finite(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return HF_E_HIP;
+}
+const char* last_error() { return g_err.c_str(); }
+
+int n_free(const pdf_graph* g) {
+  int k = 0;
+  for (auto& p : g->par) k += p.fixed ? 0 : 1;
+  return k;
+}
+
+double column_ref(const pdf_graph* g, int col, hf_precision prec) {
+  if (prec == HF_FP64) return 0.0;
+  const ObsInfo& o = g->obs[g->obs_of_col[col]];
+  if (finite(o.lo) && finite(o.hi)) return 0.5 * (o.lo + o.hi);
+  return 0.0;
+}
+
+// ------------------------------------------------------------------ closed-form normalisations
+namespace {
+
+// ln of int_a^b e^{alpha (x - a)} dx and its alpha-derivative.
+void exp_norm(double alpha, double L, double& lnN, double& dlnN) {
+  const double z = alpha * L;
+  if (std::fabs(z) < 1e-3) {
+    // expm1(z)/z = 1 + z/2 + z^2/6 + z^3/24 ; d/dalpha ln = L (1/2 + z/12 - z^3/720)
+    lnN = std::log(L) + std::log1p(z * (0.5 + z * (1.0 / 6.0 + z / 24.0)));
+    dlnN = L * (0.5 + z / 12.0 - z * z * z / 720.0);
+  } else {
+    lnN = std::log(L) + std::log(std::expm1(z) / z);
+    dlnN = L * (1.0 / (-std::expm1(-z)) - 1.0 / z);
+  }
+}
+
+// ln of int_a^b exp(-(x-mu)^2/(2 s^2)) dx and derivatives in mu and s.
+bool gauss_norm(double a, double b, double mu, double s, double& lnN, double& dmu, double& ds) {
+  if (!(s > 0.0)) return false;
+  const double k = 1.0 / (std::sqrt(2.0) * s);
+  const double za = (a - mu) * k, zb = (b - mu) * k;
+  double w;  // erf(zb) - erf(za), computed from the tail that avoids cancellation
+  if (za >= 0.0) w = std::erfc(za) - std::erfc(zb);
+  else if (zb <= 0.0) w = std::erfc(-zb) - std::erfc(-za);
+  else w = std::erf(zb) - std::erf(za);
+  const double N = s * std::sqrt(M_PI / 2.0) * w;
+  if (!(N > 0.0)) return false;
+  const double ga = std::exp(-za * za), gb = std::exp(-zb * zb);
+  lnN = std::log(N);
+  dmu = (ga - gb) / N;
+  ds = 1.0 / s - ((b - mu) * gb - (a - mu) * ga) / (s * N);
+  return true;
+}
+
+// split a double into float hi + float lo
+void split(double x, float& hi, float& lo) {
+  hi = (float)x;
+  lo = (float)(x - (double)hi);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ Dalitz helpers
+bool dalitz_inside(const DalitzInfo& dz, double s12, double s13) {
+  auto pair_in = [&](double s1x, double s1y, double mx, double my) {
+    const double lo = (dz.m1 + mx) * (dz.m1 + mx), hi = (dz.M - my) * (dz.M - my);
+    if (!(s1x >= lo && s1x <= hi)) return false;
+    const double rs = std::sqrt(s1x);
+    const double E1 = (s1x - mx * mx + dz.m1 * dz.m1) / (2.0 * rs);
+    const double Ey = (dz.M * dz.M - s1x - my * my) / (2.0 * rs);
+    const double p1 = std::sqrt(std::fmax(E1 * E1 - dz.m1 * dz.m1, 0.0));
+    const double py = std::sqrt(std::fmax(Ey * Ey - my * my, 0.0));
+    const double e = E1 + Ey;
+    return s1y >= e * e - (p1 + py) * (p1 + py) && s1y <= e * e - (p1 - py) * (p1 - py);
+  };
+  return pair_in(s12, s13, dz.m2, dz.m3) && pair_in(s13, s12, dz.m3, dz.m2);
+}
+
+int ensure_grid(pdf_graph* g, hipStream_t st) {
+  DalitzInfo& dz = g->dz;
+  if (dz.node < 0) return HF_OK;
+  std::lock_guard<std::mutex> lk(g->grid_mu);
+  if (dz.ready) return HF_OK;
+  const int na = (int)dz.res.size() + 1, n_mat = dz.tddp ? 3 : 1;
+  std::vector<double> out((size_t)n_mat * na * na * 2);
+  hipError_t e = dalitz_grid_matrices(dz.gs, g->prog, dz.node, dz.tddp, out.data(), st);
+  if (e != hipSuccess) return hip_fail(e, "Dalitz normalisation grid");
+  const double area = dz.gs.h12 * dz.gs.h13;
+  for (double& v : out) v *= area;
+  const size_t m = (size_t)na * na * 2;
+  dz.I.assign(out.begin(), out.begin() + m);
+  if (dz.tddp) {
+    dz.Ib.assign(out.begin() + m, out.begin() + 2 * m);
+    dz.J.assign(out.begin() + 2 * m, out.begin() + 3 * m);
+  }
+  dz.ready = true;
+  return HF_OK;
+}
+
+namespace {
+
+typedef std::complex<double> cd;
+
+// c^H M c and its gradient with respect to (Re c_k, Im c_k), k >= 1 (c_0 = 1).
+// d/dRe c_k = 2 Re-part pieces written out from the bilinear form.
+double herm_form(const std::vector<double>& Mf, const std::vector<cd>& c, std::vector<double>& dre,
+                 std::vector<double>& dim) {
+  const int na = (int)c.size();
+  auto M = [&](int p, int q) { return cd(Mf[2 * (p * na + q)], Mf[2 * (p * na + q) + 1]); };
+  cd tot = 0.0;
+  std::vector<cd> left(na, 0.0), right(na, 0.0);  // (c^H M)_q, (M c)_p
+  for (int p = 0; p < na; ++p)
+    for (int q = 0; q < na; ++q) {
+      const cd m = M(p, q);
+      tot += std::conj(c[p]) * m * c[q];
+      left[q] += std::conj(c[p]) * m;
+      right[p] += m * c[q];
+    }
+  dre.assign(na, 0.0);
+  dim.assign(na, 0.0);
+  for (int k = 1; k < na; ++k) {
+    // f = Re(c^H M c): d/dRe c_k = Re(left_k + right_k); d/dIm c_k = Re(i left_k - i right_k)
+    dre[k] = (left[k] + right[k]).real();
+    dim[k] = (cd(0.0, 1.0) * (left[k] - right[k])).real();
+  }
+  return tot.real();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ staging
+void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& sc) {
+  sc.prog = g->prog;
+  sc.ok = true;
+  sc.ht.lnN = 0.0;
+  sc.ht.dlnN.assign(g->par.size(), 0.0);
+  KProgram& P = sc.prog;
+  const bool fp32 = prec == HF_FP32_EVAL;
+  auto setc = [&](int i, double v) {
+    P.c64[i] = v;
+    P.c32[i] = (float)v;
+  };
+  auto set_ln = [&](int i_hi, int i_lo, double v) {
+    P.c64[i_hi] = v;
+    P.c64[i_lo] = 0.0;
+    float h, l;
+    split(v, h, l);
+    P.c32[i_hi] = h;
+    P.c32[i_lo] = l;
+  };
+  for (int k = 0; k < P.n_nodes; ++k) {
+    const KNode& kn = P.node[k];
+    const NodeInfo& nd = g->nodes[k];
+    const int c0 = kn.c0;
+    const bool hoist = kn.hoisted != 0;
+    auto norm_terms = [&](double lnN, const std::vector<std::pair<int, double>>& d, int i_hi, int i_lo,
+                          int i_d0) {
+      if (hoist) {
+        sc.ht.lnN += lnN;
+        for (auto& pd : d) sc.ht.dlnN[pd.first] += pd.second;
+        set_ln(i_hi, i_lo, 0.0);
+        for (size_t j = 0; j < d.size(); ++j) setc(i_d0 + (int)j, 0.0);
+      } else {
+        set_ln(i_hi, i_lo, lnN);
+        for (size_t j = 0; j < d.size(); ++j) setc(i_d0 + (int)j, d[j].second);
+      }
+    };
+    switch (kn.op) {
+      case OP_EXP: {
+        const int col = kn.col[0];
+        const ObsInfo& o = g->obs[g->obs_of_col[col]];
+        const double alpha = th[nd.par[0]];
+        P.c64[c0] = column_ref(g, col, prec) - o.lo;
+        P.c32[c0] = 0.0f;
+        setc(c0 + 1, alpha);
+        double lnN, dlnN;
+        exp_norm(alpha, o.hi - o.lo, lnN, dlnN);
+        norm_terms(lnN, {{nd.par[0], dlnN}}, c0 + 2, c0 + 3, c0 + 4);
+        break;
+      }
+      case OP_GAUSS: {
+        const int col = kn.col[0];
+        const ObsInfo& o = g->obs[g->obs_of_col[col]];
+        const double mu = th[nd.par[0]], s = th[nd.par[1]];
+        double lnN = 0, dmu = 0, ds = 0;
+        if (!gauss_norm(o.lo, o.hi, mu, s, lnN, dmu, ds)) sc.ok = false;
+        P.c64[c0] = column_ref(g, col, prec) - mu;
+        P.c32[c0] = 0.0f;
+        setc(c0 + 1, 1.0 / s);
+        norm_terms(lnN, {{nd.par[0], dmu}, {nd.par[1], ds}}, c0 + 2, c0 + 3, c0 + 4);
+        break;
+      }
+      case OP_POLY: {
+        const int col = kn.col[0];
+        const ObsInfo& o = g->obs[g->obs_of_col[col]];
+        const double x0 = nd.consts[0];
+        const int d = kn.aux;
+        P.c64[c0] = column_ref(g, col, prec) - x0;
+        P.c32[c0] = 0.0f;
+        double N = (o.hi - x0) - (o.lo - x0);
+        std::vector<double> w(d);
+        for (int j = 1; j <= d; ++j) {
+          w[j - 1] = (std::pow(o.hi - x0, j + 1) - std::pow(o.lo - x0, j + 1)) / (j + 1);
+          N += th[nd.par[j - 1]] * w[j - 1];
+          setc(c0 + j, th[nd.par[j - 1]]);
+        }
+        if (!(N > 0.0)) { sc.ok = false; N = 1.0; }
+        std::vector<std::pair<int, double>> dv;
+        for (int j = 0; j < d; ++j) dv.push_back({nd.par[j], w[j] / N});
+        norm_terms(std::log(N), dv, c0 + d + 1, c0 + d + 2, c0 + d + 3);
+        break;
+      }
+      case OP_ADD: {
+        double last = 1.0;
+        const int K = kn.n_child;
+        for (int j = 0; j < K - 1; ++j) {
+          setc(c0 + j, th[nd.par[j]]);
+          last -= th[nd.par[j]];
+        }
+        setc(c0 + K - 1, last);
+        break;
+      }
+      case OP_PROD:
+        break;
+      case OP_DALITZ:
+      case OP_TDDP: {
+        const DalitzInfo& dz = g->dz;
+        const bool td = kn.op == OP_TDDP;
+        const int R = kn.aux;
+        P.c64[c0 + kDzRef12] = column_ref(g, kn.col[0], prec);
+        P.c64[c0 + kDzRef13] = column_ref(g, kn.col[1], prec);
+        std::vector<cd> c(R + 1, cd(1.0, 0.0));
+        const int cb = c0 + dz_coef_base(R, td);
+        for (int j = 0; j < R; ++j) {
+          c[j + 1] = cd(th[nd.par[2 * j]], th[nd.par[2 * j + 1]]);
+          setc(cb + 2 * j, c[j + 1].real());
+          setc(cb + 2 * j + 1, c[j + 1].imag());
+        }
+        std::vector<std::pair<int, double>> dv;
+        double lnN = 0.0;
+        if (!td) {
+          std::vector<double> dre, dim;
+          const double N = herm_form(dz.I, c, dre, dim);
+          if (!(N > 0.0)) sc.ok = false;
+          lnN = std::log(N);
+          for (int j = 0; j < R; ++j) {
+            dv.push_back({nd.par[2 * j], dre[j + 1] / N});
+            dv.push_back({nd.par[2 * j + 1], dim[j + 1] / N});
+          }
+        } else {
+          const double tau = th[nd.par[2 * R]], y = th[nd.par[2 * R + 1]];
+          if (!(tau > 0.0) || !(std::fabs(y) < 1.0)) sc.ok = false;
+          std::vector<double> aR, aI, bR, bI, jR, jI;
+          const double IA = herm_form(dz.I, c, aR, aI);
+          const double IB = herm_form(dz.Ib, c, bR, bI);
+          const double X = herm_form(dz.J, c, jR, jI);  // Re c^H J c
+          // time integrals over the real line: int C = tau/(1-y^2),
+          // int E(1/tau) = tau, int S = y tau/(1-y^2)
+          const double den = 1.0 - y * y;
+          const double kc = tau / den, k0 = tau, ks = y * tau / den;
+          const double N = 0.5 * (IA + IB) * kc + 0.5 * (IA - IB) * k0 - X * ks;
+          if (!(N > 0.0)) sc.ok = false;
+          lnN = std::log(N);
+          for (int j = 1; j <= R; ++j) {
+            const double dr = 0.5 * (aR[j] + bR[j]) * kc + 0.5 * (aR[j] - bR[j]) * k0 - jR[j] * ks;
+            const double di = 0.5 * (aI[j] + bI[j]) * kc + 0.5 * (aI[j] - bI[j]) * k0 - jI[j] * ks;
+            dv.push_back({nd.par[2 * j - 2], dr / N});
+            dv.push_back({nd.par[2 * j - 1], di / N});
+          }
+          const double dtau = 0.5 * (IA + IB) / den + 0.5 * (IA - IB) - X * y / den;
+          const double dy = 0.5 * (IA + IB) * tau * 2.0 * y / (den * den) - X * tau * (1.0 + y * y) / (den * den);
+          dv.push_back({nd.par[2 * R], dtau / N});
+          dv.push_back({nd.par[2 * R + 1], dy / N});
+          const int tb = c0 + dz_time_base(R);
+          setc(tb + kTdGm, (1.0 - y) / tau);
+          setc(tb + kTdGp, (1.0 + y) / tau);
+          setc(tb + kTdG, 1.0 / tau);
+          setc(tb + kTdDGmTau, -(1.0 - y) / (tau * tau));
+          setc(tb + kTdDGpTau, -(1.0 + y) / (tau * tau));
+          setc(tb + kTdDGTau, -1.0 / (tau * tau));
+          setc(tb + kTdDGmY, -1.0 / tau);
+          setc(tb + kTdDGpY, 1.0 / tau);
+        }
+        norm_terms(lnN, dv, c0 + kDzLnHi, c0 + kDzLnLo, c0 + kDzDln);
+        break;
+      }
+    }
+  }
+  (void)fp32;
+}
+
+// ------------------------------------------------------------------ creation
+namespace {
+
+int node_slots(const NodeInfo& n) {
+  switch (n.op) {
+    case OP_EXP: return 1;
+    case OP_GAUSS: return 2;
+    case OP_POLY: return (int)n.par.size();
+    case OP_ADD: return (int)n.child.size() - 1;
+    case OP_PROD: return 0;
+    default: return (int)n.par.size();
+  }
+}
+
+int node_consts(const NodeInfo& n) {
+  switch (n.op) {
+    case OP_EXP: return 5;
+    case OP_GAUSS: return 6;
+    case OP_POLY: return 2 * (int)n.par.size() + 3;
+    case OP_ADD: return (int)n.child.size();
+    case OP_PROD: return 0;
+    case OP_DALITZ: return dz_n_const((int)n.consts[6], false);
+    default: return dz_n_const((int)n.consts[6], true);
+  }
+}
+
+}  // namespace
+
+}  // namespace hf
+
+using namespace hf;
+
+extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param* par, int32_t n_par,
+                                const hf_node* nodes, int32_t n_nodes, int32_t root, pdf_graph** out) {
+  try {
+    if (!obs || !par || !nodes || !out) return fail(HF_E_INVALID, "pdf_graph_create: NULL argument");
+    if (n_obs < 1 || n_obs > 64) return fail(HF_E_INVALID, "pdf_graph_create: n_obs out of range");
+    if (n_par < 0 || n_par > kMaxPar) return fail(HF_E_INVALID, "pdf_graph_create: n_par out of range (max 64)");
+    if (n_nodes < 1 || n_nodes > kMaxNodes) return fail(HF_E_GRAPH, "pdf_graph_create: 1..16 nodes allowed");
+    if (root < 0 || root >= n_nodes) return fail(HF_E_GRAPH, "pdf_graph_create: root index out of range");
+    std::unique_ptr<pdf_graph> g(new pdf_graph);
+    for (int i = 0; i < n_obs; ++i) {
+      const hf_obs& o = obs[i];
+      if (std::isnan(o.lo) || std::isnan(o.hi) || !(o.lo < o.hi))
+        return fail(HF_E_GRAPH, "observable " + std::to_string(i) + ": need lo < hi");
+      g->obs.push_back({o.name ? o.name : "", o.lo, o.hi});
+    }
+    for (int i = 0; i < n_par; ++i) {
+      const hf_param& p = par[i];
+      if (!std::isfinite(p.init)) return fail(HF_E_GRAPH, "parameter " + std::to_string(i) + ": init not finite");
+      if (p.lo != p.hi && !(p.lo < p.hi)) return fail(HF_E_GRAPH, "parameter " + std::to_string(i) + ": lo > hi");
+      if (p.lo != p.hi && (p.init < p.lo || p.init > p.hi))
+        return fail(HF_E_GRAPH, "parameter " + std::to_string(i) + ": init outside [lo, hi]");
+      g->par.push_back({p.name ? p.name : "", p.init, p.step > 0 ? p.step : 0.1, p.lo, p.hi, p.fixed != 0});
+    }
+    // copy + per-node checks
+    std::vector<NodeInfo> in(n_nodes);
+    for (int k = 0; k < n_nodes; ++k) {
+      const hf_node& n = nodes[k];
+      NodeInfo& ni = in[k];
+      ni.op = n.op;
+      const std::string where = "node " + std::to_string(k) + ": ";
+      if (n.n_child < 0 || n.n_par < 0 || n.n_obs < 0 || n.n_const < 0) return fail(HF_E_GRAPH, where + "negative count");
+      if ((n.n_child && !n.child) || (n.n_par && !n.par) || (n.n_obs && !n.obs) || (n.n_const && !n.consts))
+        return fail(HF_E_GRAPH, where + "NULL array");
+      ni.child.assign(n.child, n.child + n.n_child);
+      ni.par.assign(n.par, n.par + n.n_par);
+      ni.obs.assign(n.obs, n.obs + n.n_obs);
+      ni.consts.assign(n.consts, n.consts + n.n_const);
+      for (int c : ni.child)
+        if (c < 0 || c >= k) return fail(HF_E_GRAPH, where + "child index must refer to an earlier node");
+      for (int p : ni.par)
+        if (p < 0 || p >= n_par) return fail(HF_E_GRAPH, where + "parameter index out of range");
+      for (int o : ni.obs)
+        if (o < 0 || o >= n_obs) return fail(HF_E_GRAPH, where + "observable index out of range");
+      auto need = [&](bool ok, const char* m) { return ok ? 0 : fail(HF_E_GRAPH, where + m); };
+      auto finite_box = [&](int o) { return std::isfinite(g->obs[o].lo) && std::isfinite(g->obs[o].hi); };
+      int rc = 0;
+      switch (n.op) {
+        case OP_EXP:
+          rc = need(n.n_child == 0 && n.n_par == 1 && n.n_obs == 1, "EXP takes 1 parameter and 1 observable");
+          if (!rc) rc = need(finite_box(ni.obs[0]), "EXP needs a finite observable box");
+          break;
+        case OP_GAUSS:
+          rc = need(n.n_child == 0 && n.n_par == 2 && n.n_obs == 1, "GAUSS takes 2 parameters and 1 observable");
+          if (!rc) rc = need(finite_box(ni.obs[0]), "GAUSS needs a finite observable box");
+          break;
+        case OP_POLY:
+          rc = need(n.n_child == 0 && n.n_par >= 1 && n.n_par <= 8 && n.n_obs == 1 && n.n_const == 1,
+                    "POLY takes 1..8 coefficients, 1 observable and the constant x0");
+          if (!rc) rc = need(finite_box(ni.obs[0]) && std::isfinite(ni.consts[0]), "POLY needs a finite box and x0");
+          break;
+        case OP_ADD:
+          rc = need(n.n_child >= 2 && n.n_par == n.n_child - 1 && n.n_obs == 0,
+                    "ADD takes K >= 2 children and K-1 fractions");
+          break;
+        case OP_PROD:
+          rc = need(n.n_child >= 2 && n.n_par == 0 && n.n_obs == 0, "PROD takes K >= 2 children and no parameters");
+          break;
+        case OP_DALITZ:
+        case OP_TDDP: {
+          const bool td = n.op == OP_TDDP;
+          rc = need(n.n_child == 0 && n.n_const >= 7, "Dalitz node needs the constant block");
+          if (rc) break;
+          const int R = (int)ni.consts[6];
+          rc = need(R >= 1 && R <= kMaxRes && n.n_const == 7 + 4 * R, "Dalitz: 1..8 resonances, 7 + 4R constants");
+          if (!rc) rc = need(n.n_par == 2 * R + (td ? 2 : 0), "Dalitz: 2R (+tau, y) parameters");
+          if (!rc) rc = need(n.n_obs == (td ? 4 : 2), "Dalitz: observables (s12, s13[, t, sigma_t])");
+          if (!rc) rc = need(finite_box(ni.obs[0]) && finite_box(ni.obs[1]), "Dalitz: s12, s13 need finite boxes");
+          if (rc) break;
+          const double M = ni.consts[0], m1 = ni.consts[1], m2 = ni.consts[2], m3 = ni.consts[3];
+          const double G = ni.consts[5];
+          rc = need(m1 > 0 && m2 > 0 && m3 > 0 && M > m1 + m2 + m3 && ni.consts[4] >= 0,
+                    "Dalitz: need positive masses with M > m1 + m2 + m3 and r >= 0");
+          if (!rc) rc = need(G >= 2 && G <= 4096 && G == std::floor(G), "Dalitz: grid size 2..4096");
+          for (int j = 0; j < R && !rc; ++j) {
+            const double ch = ni.consts[7 + 4 * j], m0 = ni.consts[8 + 4 * j], g0 = ni.consts[9 + 4 * j],
+                         J = ni.consts[10 + 4 * j];
+            rc = need(ch == 12 || ch == 13 || ch == 23, "Dalitz: channel must be 12, 13 or 23");
+            if (!rc) rc = need(J == 0 || J == 1 || J == 2, "Dalitz: J must be 0, 1 or 2");
+            if (!rc) {
+              const double mA = ch == 23 ? m2 : m1, mB = ch == 12 ? m2 : m3;
+              rc = need(m0 > mA + mB && g0 > 0, "Dalitz: resonance mass above threshold and width > 0");
+            }
+          }
+          break;
+        }
+        default:
+          rc = fail(HF_E_GRAPH, where + "unknown op");
+      }
+      if (rc) return rc;
+    }
+    // reachable nodes in post-order (children before parents, root last)
+    std::vector<int> order, used(n_nodes, 0);
+    std::function<int(int)> visit = [&](int k) -> int {
+      if (used[k]) return fail(HF_E_GRAPH, "node " + std::to_string(k) + " is used twice");
+      used[k] = 1;
+      for (int c : in[k].child)
+        if (int rc = visit(c)) return rc;
+      order.push_back(k);
+      return 0;
+    };
+    if (int rc = visit(root)) return rc;
+    if ((int)order.size() > kMaxNodes) return fail(HF_E_GRAPH, "too many nodes");
+    std::vector<int> newidx(n_nodes, -1);
+    for (size_t i = 0; i < order.size(); ++i) newidx[order[i]] = (int)i;
+    for (int k : order) {
+      NodeInfo n = in[k];
+      for (int& c : n.child) c = newidx[c];
+      g->nodes.push_back(n);
+    }
+    const int NN = (int)g->nodes.size();
+    // observable sets; ADD children share one, PROD children are disjoint
+    std::vector<std::set<int>> os(NN);
+    int n_heavy = 0;
+    for (int k = 0; k < NN; ++k) {
+      NodeInfo& n = g->nodes[k];
+      if (n.op == OP_ADD || n.op == OP_PROD) {
+        for (int c : n.child) {
+          if (n.op == OP_ADD && os[c] != os[n.child[0]])
+            return fail(HF_E_GRAPH, "ADD children must share the same observables");
+          for (int o : os[c]) {
+            if (n.op == OP_PROD && os[k].count(o))
+              return fail(HF_E_GRAPH, "PROD children must have disjoint observables");
+            os[k].insert(o);
+          }
+        }
+      } else {
+        for (int o : n.obs) {
+          if (os[k].count(o)) return fail(HF_E_GRAPH, "a node uses an observable twice");
+          os[k].insert(o);
+        }
+      }
+      if (n.op == OP_DALITZ || n.op == OP_TDDP) ++n_heavy;
+    }
+    if (n_heavy > 1) return fail(HF_E_GRAPH, "at most one DALITZ/TDDP node per graph");
+    // columns: used observables in index order
+    g->col_of_obs.assign(n_obs, -1);
+    for (int o = 0; o < n_obs; ++o)
+      if (os[NN - 1].count(o)) {
+        g->col_of_obs[o] = (int)g->obs_of_col.size();
+        g->obs_of_col.push_back(o);
+      }
+    if ((int)g->obs_of_col.size() > kMaxCols) return fail(HF_E_GRAPH, "more than 8 observables used");
+    // hoisting: every ancestor is a PROD
+    std::vector<int> hoist(NN, 0);
+    hoist[NN - 1] = 1;
+    for (int k = NN - 1; k >= 0; --k)
+      for (int c : g->nodes[k].child) hoist[c] = hoist[k] && g->nodes[k].op == OP_PROD;
+    // flatten
+    KProgram& P = g->prog;
+    std::memset(&P, 0, sizeof(P));
+    P.n_nodes = NN;
+    P.root = NN - 1;
+    P.n_cols = (int)g->obs_of_col.size();
+    int slot = 0, cst = 0, chl = 0;
+    for (int k = 0; k < NN; ++k) {
+      const NodeInfo& n = g->nodes[k];
+      KNode& kn = P.node[k];
+      kn.op = (int16_t)n.op;
+      kn.n_child = (int16_t)n.child.size();
+      kn.child0 = (int16_t)chl;
+      for (int c : n.child) P.child[chl++] = (int16_t)c;
+      kn.slot0 = (int16_t)slot;
+      kn.n_slot = (int16_t)node_slots(n);
+      kn.c0 = (int16_t)cst;
+      for (int j = 0; j < 4; ++j) kn.col[j] = j < (int)n.obs.size() ? (int16_t)g->col_of_obs[n.obs[j]] : 0;
+      kn.hoisted = (int16_t)hoist[k];
+      kn.aux = 0;
+      if (n.op == OP_POLY) kn.aux = (int16_t)n.par.size();
+      if (n.op == OP_DALITZ || n.op == OP_TDDP) kn.aux = (int16_t)n.consts[6];
+      // gradient slot -> parameter
+      if (n.op == OP_ADD) for (int j = 0; j < kn.n_slot; ++j) g->slot_par.push_back(n.par[j]);
+      else for (int j = 0; j < kn.n_slot; ++j) g->slot_par.push_back(n.par[j]);
+      slot += kn.n_slot;
+      cst += node_consts(n);
+      if (slot > kMaxSlots) return fail(HF_E_GRAPH, "more than 32 gradient slots");
+      if (cst > kMaxConst) return fail(HF_E_GRAPH, "constant table overflow (too many resonances or nodes)");
+    }
+    P.n_slots = slot;
+    g->n_const = cst;
+    // static Dalitz constants
+    for (int k = 0; k < NN; ++k) {
+      const NodeInfo& n = g->nodes[k];
+      if (n.op != OP_DALITZ && n.op != OP_TDDP) continue;
+      DalitzInfo& dz = g->dz;
+      dz.node = k;
+      dz.tddp = n.op == OP_TDDP;
+      dz.M = n.consts[0]; dz.m1 = n.consts[1]; dz.m2 = n.consts[2]; dz.m3 = n.consts[3]; dz.r = n.consts[4];
+      dz.grid = (int)n.consts[5];
+      const int R = (int)n.consts[6];
+      for (int j = 0; j < R; ++j)
+        dz.res.push_back({(int)n.consts[7 + 4 * j], n.consts[8 + 4 * j], n.consts[9 + 4 * j], (int)n.consts[10 + 4 * j]});
+      const double lo12 = (dz.m1 + dz.m2) * (dz.m1 + dz.m2), hi12 = (dz.M - dz.m3) * (dz.M - dz.m3);
+      const double lo13 = (dz.m1 + dz.m3) * (dz.m1 + dz.m3), hi13 = (dz.M - dz.m2) * (dz.M - dz.m2);
+      dz.gs = GridSpec{lo12, (hi12 - lo12) / dz.grid, lo13, (hi13 - lo13) / dz.grid, dz.M, dz.m1, dz.m2, dz.m3, dz.grid};
+      const int c0 = P.node[k].c0;
+      auto setc = [&](int i, double v) { P.c64[i] = v; P.c32[i] = (float)v; };
+      const double M2 = dz.M * dz.M;
+      setc(c0 + kDzSsum, M2 + dz.m1 * dz.m1 + dz.m2 * dz.m2 + dz.m3 * dz.m3);
+      const int rbase = c0 + dz_res_base(R, dz.tddp);
+      for (int j = 0; j < R; ++j) {
+        const ResInfo& r = dz.res[j];
+        double mA, mB, mC;
+        if (r.ch == 23) { mA = dz.m2; mB = dz.m3; mC = dz.m1; }
+        else if (r.ch == 12) { mA = dz.m1; mB = dz.m2; mC = dz.m3; }
+        else { mA = dz.m1; mB = dz.m3; mC = dz.m2; }
+        const int rb = rbase + j * kResStride;
+        const double m02 = r.m0 * r.m0;
+        const double thrP = (mA + mB) * (mA + mB), thrM = (mA - mB) * (mA - mB);
+        const double q02 = (m02 - thrP) * (m02 - thrM) / (4.0 * m02);
+        const double q0 = std::sqrt(q02);
+        const double z0 = dz.r * dz.r * q02;
+        double bnum = 1.0;
+        if (r.J == 1) bnum = 1.0 + z0;
+        if (r.J == 2) bnum = z0 * z0 + 3.0 * z0 + 9.0;
+        setc(rb + kResM02, m02);
+        setc(rb + kResKw, m02 * r.g0 / std::pow(q0, 2 * r.J + 1));
+        setc(rb + kResBnum, bnum);
+        setc(rb + kResR2, dz.r * dz.r);
+        setc(rb + kResThrP, thrP);
+        setc(rb + kResThrM, thrM);
+        setc(rb + kResZc1, (M2 - mC * mC) * (mB * mB - mA * mA));
+        setc(rb + kResZtaC, 2.0 * M2 + 2.0 * mC * mC);
+        setc(rb + kResZtaD, (M2 - mC * mC) * (M2 - mC * mC));
+        setc(rb + kResZtbC, 2.0 * mA * mA + 2.0 * mB * mB);
+        setc(rb + kResZtbD, (mA * mA - mB * mB) * (mA * mA - mB * mB));
+        setc(rb + kResCh, r.ch);
+        setc(rb + kResJ, r.J);
+      }
+    }
+    // kernel family
+    const NodeInfo& rootn = g->nodes[NN - 1];
+    bool heavy = g->dz.node >= 0;
+    if (NN == 1 && rootn.op == OP_EXP) g->kind = KIND_EXP;
+    else if (NN == 1 && rootn.op == OP_GAUSS) g->kind = KIND_GAUSS;
+    else if (NN == 1 && rootn.op == OP_DALITZ) g->kind = KIND_DALITZ;
+    else if (NN == 1 && rootn.op == OP_TDDP) g->kind = KIND_TDDP;
+    else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2) g->kind = KIND_TREE_SMALL;
+    else g->kind = KIND_TREE;
+    *out = g.release();
+    return HF_OK;
+  } catch (const std::exception& e) {
+    return fail(HF_E_INVALID, std::string("pdf_graph_create: ") + e.what());
+  }
+}
+
+extern "C" void pdf_graph_destroy(pdf_graph* g) { delete g; }
+
+extern "C" int pdf_graph_shape(const pdf_graph* g, int32_t* n_obs, int32_t* n_par) {
+  if (!g) return fail(HF_E_INVALID, "pdf_graph_shape: NULL graph");
+  if (n_obs) *n_obs = (int32_t)g->obs.size();
+  if (n_par) *n_par = (int32_t)g->par.size();
+  return HF_OK;
+}
+
+extern "C" int hf_dalitz_inside(const pdf_graph* g, int32_t node, int64_t n, const double* s12, const double* s13,
+                                uint8_t* out) {
+  if (!g || (n > 0 && (!s12 || !s13 || !out))) return fail(HF_E_INVALID, "hf_dalitz_inside: NULL argument");
+  if (g->dz.node < 0) return fail(HF_E_INVALID, "hf_dalitz_inside: graph has no Dalitz node");
+  (void)node;
+  for (int64_t i = 0; i < n; ++i) out[i] = dalitz_inside(g->dz, s12[i], s13[i]) ? 1 : 0;
+  return HF_OK;
+}
+
+extern "C" const char* hf_last_error(void) { return hf::last_error(); }
+extern "C" const char* hf_version(void) { return "hipfit 0.1 (gfx950)"; }

@@ -1,0 +1,100 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+//
+// A PDF tree is flattened into a KProgram: nodes in post-order (children
+// before parents, root last), each with its opcode, child list, the columns
+// it reads, the slots of the per-event gradient it owns and an offset into a
+// constant table.  The host rewrites the constant table from the parameter
+// vector before every launch (double values for the FP64 path, float copies
+// for the FP32-eval path, location constants always in double); the whole
+// program travels as a kernel argument, so each launch reads it through the
+// scalar cache with no extra copy.  This replaces the paper's global
+// parameter array and per-PDF index arrays read by double indirection
+// (section "Adding new PDFs").
+#pragma once
+#include <cstdint>
+
+namespace hf {
+
+constexpr int kBlock = 256;          // threads per block (4 wave64)
+constexpr int kMaxNodes = 16;
+constexpr int kMaxCols = 8;
+constexpr int kMaxSlots = 32;
+constexpr int kMaxConst = 176;
+constexpr int kMaxRes = 8;
+constexpr int kMaxPar = 64;
+
+enum Op : int16_t {
+  OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7
+};
+
+struct KNode {
+  int16_t op;
+  int16_t n_child;
+  int16_t child0;    // first index into KProgram::child
+  int16_t slot0;     // first per-event gradient slot owned by this node
+  int16_t n_slot;
+  int16_t c0;        // first constant of this node
+  int16_t col[4];    // observable columns read
+  int16_t hoisted;   // 1: normalisation applied on the host (every ancestor is PROD)
+  int16_t aux;       // POLY: degree; DALITZ/TDDP: number of resonances
+};
+
+struct KProgram {
+  int32_t n_nodes, root, n_slots, n_cols;
+  KNode node[kMaxNodes];
+  int16_t child[kMaxNodes];
+  double c64[kMaxConst];
+  float c32[kMaxConst];
+};
+
+// Constant layouts (offsets relative to KNode::c0).
+//   EXP    0 loc = ref - a (double), 1 alpha, 2 lnN_hi, 3 lnN_lo, 4 dlnN/dalpha
+//   GAUSS  0 loc = ref - mu (double), 1 1/sigma, 2 lnN_hi, 3 lnN_lo, 4 dlnN/dmu, 5 dlnN/dsigma
+//   POLY   0 loc = ref - x0 (double), 1..d a_k, d+1 lnN_hi, d+2 lnN_lo, d+3.. dlnN/da_k
+//   ADD    0..K-1 fractions (the last one 1 - sum of the others)
+//   DALITZ/TDDP: see the kDz* offsets below.
+// For the float path lnN is split into a float pair (hi + lo) so that the
+// rounding of the constant does not bias every event in the same direction.
+constexpr int kDzRef12 = 0, kDzRef13 = 1, kDzSsum = 2, kDzLnHi = 3, kDzLnLo = 4, kDzDln = 5;
+// per resonance block (stride kResStride) after the 2R (+2 for TDDP) dlnN entries
+constexpr int kResM02 = 0, kResKw = 1, kResBnum = 2, kResR2 = 3, kResThrP = 4, kResThrM = 5,
+              kResZc1 = 6, kResZtaC = 7, kResZtaD = 8, kResZtbC = 9, kResZtbD = 10, kResCh = 11,
+              kResJ = 12, kResStride = 13;
+// TDDP time constants after the coefficients
+constexpr int kTdGm = 0, kTdGp = 1, kTdG = 2, kTdDGmTau = 3, kTdDGpTau = 4, kTdDGTau = 5,
+              kTdDGmY = 6, kTdDGpY = 7, kTdCount = 8;
+
+constexpr int dz_n_dln(int R, bool tddp) { return 2 * R + (tddp ? 2 : 0); }
+constexpr int dz_res_base(int R, bool tddp) { return kDzDln + dz_n_dln(R, tddp); }
+constexpr int dz_coef_base(int R, bool tddp) { return dz_res_base(R, tddp) + R * kResStride; }
+constexpr int dz_time_base(int R) { return dz_coef_base(R, true) + 2 * R; }
+constexpr int dz_n_const(int R, bool tddp) { return dz_coef_base(R, tddp) + 2 * R + (tddp ? kTdCount : 0); }
+
+// Arguments of one evaluation launch over one dataset.
+struct EvalArgs {
+  KProgram prog;
+  const void* col[kMaxCols];   // device columns (double or float)
+  int64_t n_events;
+  double* partials;            // [n_tiles][stride]: nll_sum, nll_comp, slot sums
+  int32_t stride;              // n_slots + 2
+  int32_t pad;
+};
+
+// Header of a batched launch's device table, followed by the FitRec array.
+struct BatchHeader {
+  int32_t n_fits, total_tiles, tiles_per_block, pad;
+};
+
+// Per-fit record of a batched launch (device memory).
+struct FitRec {
+  const void* col[kMaxCols];
+  int64_t n_events;
+  double* partials;
+  int32_t tile_begin;          // first global tile of this fit
+  int32_t n_tiles;
+  double* result;              // n_slots + 1 doubles
+  int32_t prog_index;          // program (constant table) of this fit
+  int32_t active;
+};
+
+}  // namespace hf

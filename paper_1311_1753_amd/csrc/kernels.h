@@ -1,0 +1,42 @@
+// Host-side entry points of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hf {
+
+// Kernel family chosen for a graph at creation.
+enum KernelKind {
+  KIND_EXP = 0,         // single EXP leaf
+  KIND_GAUSS = 1,       // single GAUSS leaf
+  KIND_TREE_SMALL = 2,  // tree of light nodes, <= 8 gradient slots, <= 2 columns
+  KIND_DALITZ = 3,      // single DALITZ leaf
+  KIND_TDDP = 4,        // single TDDP leaf
+  KIND_TREE = 5         // any tree
+};
+
+constexpr int kEptLight = 16;   // events per thread per tile, light kernels (tile 4096)
+constexpr int kEptHeavy = 2;    // amplitude kernels (tile 512)
+
+int kind_ept(int kind);
+inline int64_t kind_tile(int kind) { return (int64_t)kBlock * kind_ept(kind); }
+
+hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, int64_t n_tiles, hipStream_t st);
+hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,
+                               const float* c32, int n_const, int grid, hipStream_t st);
+hipError_t launch_reduce_one(const FitRec& fr, int stride, int n_slots, hipStream_t st);
+hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, int n_slots, hipStream_t st);
+
+// Dalitz normalisation grid: M[w][p][q] for w in {I, Ibar, J} (n_mat of them),
+// complex, unscaled by the cell area.  `out_host` receives n_mat * na * na * 2
+// doubles.  Blocking.
+struct GridSpec {
+  double lo12, h12, lo13, h13;   // cell centre = lo + (i + 0.5) h
+  double M, m1, m2, m3;
+  int grid;
+};
+hipError_t dalitz_grid_matrices(const GridSpec& gs, const KProgram& prog, int node, bool tddp, double* out_host,
+                                hipStream_t st);
+
+}  // namespace hf

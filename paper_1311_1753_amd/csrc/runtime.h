@@ -1,0 +1,103 @@
+// Host runtime objects behind the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hipfit.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace hf {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+struct ObsInfo { std::string name; double lo, hi; };
+struct ParInfo { std::string name; double init, step, lo, hi; bool fixed; };
+
+struct NodeInfo {
+  int op;
+  std::vector<int> child, par, obs;
+  std::vector<double> consts;
+};
+
+// Resonance description (Dalitz nodes).
+struct ResInfo { int ch; double m0, g0; int J; };
+
+struct DalitzInfo {
+  int node = -1;          // index of the DALITZ / TDDP node
+  bool tddp = false;
+  double M, m1, m2, m3, r;
+  int grid;
+  std::vector<ResInfo> res;
+  GridSpec gs;
+  bool ready = false;     // matrices computed
+  // I, Ibar, J (na x na complex, area included), row-major
+  std::vector<double> I, Ib, J;
+};
+
+// Host-side terms added after the device reduction (normalisations of the
+// nodes whose ancestors are all products).
+struct HostTerms {
+  double lnN = 0.0;                 // per event
+  std::vector<double> dlnN;         // per event, per parameter
+};
+
+struct StagedCall {
+  KProgram prog;                    // structure + constants for this call
+  HostTerms ht;
+  bool ok = true;                   // false: parameters outside the density's domain
+};
+
+}  // namespace hf
+
+struct pdf_graph {
+  std::vector<hf::ObsInfo> obs;
+  std::vector<hf::ParInfo> par;
+  std::vector<hf::NodeInfo> nodes;   // post-order, root last (re-indexed)
+  hf::KProgram prog;                 // structure; static constants filled
+  std::vector<int> slot_par;         // gradient slot -> parameter index
+  int kind = 0;
+  int n_const = 0;
+  std::vector<int> col_of_obs;       // observable -> column (-1: unused)
+  std::vector<int> obs_of_col;
+  hf::DalitzInfo dz;
+  std::mutex grid_mu;
+};
+
+struct dataset {
+  const pdf_graph* g = nullptr;
+  hf_precision prec = HF_FP64;
+  int64_t n = 0;
+  int n_cols = 0;
+  void* block = nullptr;                      // device allocation (columns + partials)
+  const void* col[hf::kMaxCols] = {nullptr};
+  double ref[hf::kMaxCols] = {0.0};           // per-column reference (float path)
+  double* partials = nullptr;
+  int64_t n_tiles = 0;
+  int64_t bytes = 0;
+  double* res_host = nullptr;                 // pinned, device-mapped result row
+  double* res_dev = nullptr;
+};
+
+namespace hf {
+
+// Column reference used by the float path (0 for unbounded observables).
+double column_ref(const pdf_graph* g, int col, hf_precision prec);
+// Fills the constant table of `sc.prog` for parameters `theta`.
+void stage(const pdf_graph* g, const double* theta, hf_precision prec, StagedCall& sc);
+// Makes sure the Dalitz normalisation matrices exist (runs the grid kernels once).
+int ensure_grid(pdf_graph* g, hipStream_t st);
+// Host membership test of the Dalitz plot (same rule as the grid).
+bool dalitz_inside(const DalitzInfo& dz, double s12, double s13);
+// nll / gradient on one dataset (want_grad false: NLL-only kernels).
+int eval_one(const pdf_graph* g, const dataset* d, const double* theta, hipStream_t st, bool want_grad, double* nll,
+             double* grad);
+int n_free(const pdf_graph* g);
+
+}  // namespace hf

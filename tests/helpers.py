@@ -1,0 +1,114 @@
+"""Shared test helpers: workload data at test sizes and tolerance scales.
+
+Data come from the seeded generators in synthgen; where a density is needed
+for accept-reject (the Dalitz workloads) it is the oracle's, so no test input
+ever comes from the GPU path."""
+import copy
+import functools
+import math
+
+import numpy as np
+
+import synthgen as S
+
+
+def spec(name):
+    return copy.deepcopy(S.workload(name))
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_model(name):
+    from oracle import oracle as O
+    return O.Model(S.workload(name))
+
+
+def oracle_model(name):
+    return _oracle_model(name)
+
+
+def gen_data(name, n, seed):
+    """Events of workload `name` (dict of float64 columns)."""
+    if name == "c1":
+        return S.gen_c1(n=n, seed=seed)
+    if name == "c2":
+        return S.gen_c2(n=n, seed=seed)
+    if name == "listing2":
+        return S.gen_listing2(n=n, seed=seed)
+    if name == "poly":
+        rng = np.random.default_rng(seed)
+        return {"x": rng.uniform(-1.0, 3.0, n)}
+    if name in ("c3", "c4"):
+        m = oracle_model(name)
+        th = m.theta(S.workload(name)["truth"])
+        lo, hi = S.dalitz_box()
+        G = 200
+        c = lo + (np.arange(G) + 0.5) * (hi - lo) / G
+        a, b = np.meshgrid(c, c, indexing="ij")
+        if name == "c3":
+            env = 1.3 * m.dalitz_amp2(th, a.ravel(), b.ravel()).max()
+            return S.gen_accept_reject_dalitz(n, seed, lambda x, y: m.dalitz_amp2(th, x, y), env,
+                                              batch=1 << 18)
+        a2 = m.dalitz_amp2(th, a.ravel(), b.ravel())
+        b2 = m.dalitz_amp2(th, a.ravel(), b.ravel(), swapped=True)
+        env = 1.3 * (a2 + b2).max()
+        tau, y = th[-2], th[-1]
+        return S.gen_accept_reject_tddp(n, seed, lambda x, yy, t: m.tddp_rate(th, x, yy, t), env, tau, y,
+                                        batch=1 << 18)
+    raise ValueError(name)
+
+
+POLY_SPEC = {
+    "name": "poly3",
+    "obs": [("x", -1.0, 3.0)],
+    "params": [("a1", 0.2, 0.05, 0.0, 0.0, False), ("a2", 0.3, 0.05, 0.0, 0.0, False),
+               ("a3", -0.05, 0.01, 0.0, 0.0, False)],
+    "truth": {"a1": 0.2, "a2": 0.3, "a3": -0.05},
+    "model": {"op": "poly", "obs": "x", "par": ["a1", "a2", "a3"], "x0": 1.0},
+}
+
+
+def get_spec(name):
+    if name == "poly":
+        return copy.deepcopy(POLY_SPEC)
+    return spec(name)
+
+
+def oracle_for(name):
+    from oracle import oracle as O
+    if name == "poly":
+        return O.Model(POLY_SPEC)
+    return oracle_model(name)
+
+
+def nll_scale(model, theta, data):
+    """max(|NLL|, sum_i |ln P_i|): the scale relative tolerances refer to."""
+    lp = model.logpdf(theta, data)
+    return max(abs(lp.sum()), np.abs(lp).sum())
+
+
+def grad_scale(model, theta, data):
+    """sum_i |d ln P_i / d theta_j| (L1 scale of each gradient component)."""
+    _, rows = model.logpdf(theta, data, grad_rows=True)
+    return np.abs(rows).sum(axis=0)
+
+
+def perturbed_theta(model, spec_, rel=0.02, seed=0):
+    rng = np.random.default_rng(seed)
+    th = model.theta(spec_["truth"])
+    return th * (1.0 + rel * rng.standard_normal(th.size))
+
+
+def fmt(x):
+    return np.array2string(np.asarray(x), precision=3)
+
+
+def rel_err(a, b, scale):
+    return abs(a - b) / scale
+
+
+def sigma_dev(a, b, sig):
+    return np.max(np.abs((np.asarray(a) - np.asarray(b)) / np.asarray(sig)))
+
+
+def inf_like(x):
+    return math.isinf(x)

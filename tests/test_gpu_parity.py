@@ -1,0 +1,152 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, element
+by element on the same seeded events.
+
+Tolerances (stated for every result):
+  * NLL: relative 1e-12 (FP64 path) / 1e-6 (FP32-eval path) of
+    max(|NLL|, sum_i |ln P_i|);
+  * gradient component j: the same relative tolerance of sum_i |d_j ln P_i|;
+  * fitted parameters: within 1e-3 sigma of the oracle's fit.
+Sizes span several tiles and a ragged tail (4096-event tiles for the light
+kernels, 512 for the amplitude kernels)."""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import gen_data, get_spec, grad_scale, nll_scale, oracle_for, perturbed_theta
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+CASES = [
+    ("c1", 100_123, 11),
+    ("c2", 200_077, 12),
+    ("listing2", 50_005, 13),
+    ("poly", 30_003, 14),
+    ("c3", 20_037, 15),
+    ("c4", 20_041, 16),
+]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1311_1753_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def stream(P):
+    import torch
+    return torch.cuda.current_stream()
+
+
+_data_cache = {}
+
+
+def data_for(name, n, seed):
+    key = (name, n, seed)
+    if key not in _data_cache:
+        _data_cache[key] = gen_data(name, n, seed)
+    return _data_cache[key]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,n,seed", CASES)
+def test_nll_and_gradient_match_oracle(P, stream, name, n, seed, prec):
+    print(f"\n[case] {name} n={n} prec={prec}", flush=True)
+    sp = get_spec(name)
+    data = data_for(name, n, seed)
+    om = oracle_for(name)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec, stream)
+    free = g.free_mask()
+    tol = TOL[prec]
+    for k, th in enumerate([om.theta(sp["truth"]), perturbed_theta(om, sp, seed=k + 1), om.theta()]):
+        v_ref, g_ref = om.nll(th, data, grad=True)
+        v, gr = P.nll_grad(g, ds, th, stream)
+        v_only = P.nll_eval(g, ds, th, stream)
+        s = nll_scale(om, th, data)
+        gs = grad_scale(om, th, data)
+        print(f"  theta#{k}: nll {v:.10g} ref {v_ref:.10g} rel {abs(v - v_ref) / s:.2e}; "
+              f"grad rel max {np.max(np.abs(gr - g_ref)[free] / gs[free]):.2e}", flush=True)
+        assert abs(v - v_ref) <= tol * s
+        assert abs(v_only - v_ref) <= tol * s
+        assert np.all(np.abs(gr - g_ref)[free] <= tol * gs[free])
+        # bitwise reproducible
+        v2, gr2 = P.nll_grad(g, ds, th, stream)
+        assert v2 == v and np.array_equal(gr2, gr)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_batched_equals_single_bitwise(P, stream, name, prec):
+    print(f"\n[case] batched {name} {prec}", flush=True)
+    sp = get_spec(name)
+    om = oracle_for(name)
+    g = P.Graph.from_spec(sp)
+    sizes = [5_003, 37, 12_345] if name != "c3" else [1_501, 37, 3_000]
+    dss, ths = [], []
+    for i, n in enumerate(sizes):
+        d = data_for(name, n, 100 + i)
+        dss.append(P.Dataset(g, d, prec, stream))
+        ths.append(perturbed_theta(om, sp, seed=10 + i))
+    nll_b, grad_b = P.nll_grad_batched(g, dss, ths, stream)
+    for i in range(len(sizes)):
+        v, gr = P.nll_grad(g, dss[i], ths[i], stream)
+        assert v == nll_b[i], (i, v, nll_b[i])
+        assert np.array_equal(gr, grad_b[i])
+    # the same fit alone in a batch of one
+    n1, g1 = P.nll_grad_batched(g, dss[1:2], ths[1:2], stream)
+    assert n1[0] == nll_b[1] and np.array_equal(g1[0], grad_b[1])
+
+
+def test_empty_and_domain_errors(P, stream):
+    sp = get_spec("c1")
+    g = P.Graph.from_spec(sp)
+    ds0 = P.Dataset(g, {"x": np.zeros(0)}, "fp64", stream)
+    v, gr = P.nll_grad(g, ds0, [-0.5], stream)
+    assert v == 0.0 and gr[0] == 0.0
+    with pytest.raises(P.HipfitError) as ei:
+        P.Dataset(g, {"x": np.array([1.0, 10.5])}, "fp64", stream)
+    assert ei.value.code == -6
+    g2 = P.Graph.from_spec(get_spec("c2"))
+    ds2 = P.Dataset(g2, data_for("c2", 5000, 3), "fp32", stream)
+    v = P.nll_eval(g2, ds2, [0.3, 5.28, -0.001, -2.0], stream)  # sigma < 0: outside the domain
+    assert math.isinf(v)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,n,seed", [("c1", 100_123, 21), ("c2", 200_077, 22), ("listing2", 50_005, 23)])
+def test_fit_matches_oracle_fit(P, stream, name, n, seed, prec):
+    print(f"\n[case] fit {name} n={n} prec={prec}", flush=True)
+    sp = get_spec(name)
+    data = data_for(name, n, seed)
+    om = oracle_for(name)
+    ref = om.fit(data)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec, stream)
+    r = P.fit(g, ds, stream=stream)
+    free = g.free_mask()
+    dev = np.abs(r["theta"] - ref["theta"])[free] / ref["errors"][free]
+    print(f"  status {r['status']} n_eval {r['n_eval']} edm {r['edm']:.2e}; "
+          f"max |dtheta|/sigma {dev.max():.2e}; err ratio {np.max(np.abs(r['errors'][free] / ref['errors'][free] - 1)):.2e}",
+          flush=True)
+    assert r["status"] == "OK"
+    assert dev.max() <= 1e-3
+    assert np.all(np.abs(r["errors"][free] / ref["errors"][free] - 1) < 1e-3)
+
+
+def test_numerical_gradient_fit_agrees(P, stream):
+    sp = get_spec("c2")
+    data = data_for("c2", 200_077, 22)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, "fp64", stream)
+    ra = P.fit(g, ds, stream=stream)
+    rn = P.fit(g, ds, grad_mode="numerical", stream=stream)
+    free = g.free_mask()
+    assert rn["status"] == "OK"
+    assert np.max(np.abs(ra["theta"] - rn["theta"])[free] / ra["errors"][free]) < 1e-3
+    assert rn["n_eval"] > ra["n_eval"]

@@ -98,6 +98,38 @@ def cpu_baseline(spec, data, seconds):
             "sample": "first %d of the 10^7 events, %d NLL+gradient evaluations in %.1f s" % (n, reps, el)}
 
 
+def serving_bench(P, S, n_req):
+    """Toy-fit stream: event counts log-uniform in [1e3, 1e6], Poisson arrivals
+    at 200 fits/s; continuous batching (FP32-eval, analytic gradient) against
+    one-at-a-time FP64 fits with central-difference gradients."""
+    import torch
+    reqs = S.serving_trace()[:n_req]
+    t0 = time.perf_counter()
+    cols = {r["id"]: S.gen_serving_request(r) for r in reqs}
+    log("serving: generated %d requests (%d events) in %.1f s" %
+        (len(reqs), sum(r["n"] for r in reqs), time.perf_counter() - t0))
+    g = P.Graph.from_spec(S.C1)
+    colf = lambda r: cols[r["id"]]
+    start = lambda r: [-2.0]
+    up = torch.cuda.Stream()
+    out = {"n_requests": len(reqs), "arrival_rate_hz": S.C5["rate_hz"]}
+    srv = P.FitServer(g, "fp32", max_slots=256, hbm_budget_bytes=32 << 30, upload_stream=up)
+    res_open, s_open = srv.run(reqs, colf, start, realtime=True)
+    res_closed, s_closed = srv.run(reqs, colf, start, realtime=False)
+    srv.close()
+    out["batched_fp32_open_loop"] = s_open
+    out["batched_fp32_closed_loop"] = s_closed
+    res_base, s_base = P.serve_one_at_a_time(g, reqs, colf, start, precision="fp64", grad_mode="numerical")
+    out["one_at_a_time_fp64_numerical"] = s_base
+    dev = [abs(res_closed[i]["theta"][0] - res_base[i]["theta"][0]) / res_base[i]["errors"][0]
+           for i in res_base if i in res_closed]
+    out["max_dtheta_over_sigma_batched_vs_baseline"] = float(max(dev)) if dev else None
+    out["fits_per_s_ratio_closed_loop"] = s_closed["fits_per_s"] / s_base["fits_per_s_saturated"]
+    log("serving: open p50 %.4f p99 %.4f s; closed %.1f fits/s; baseline %.1f fits/s" %
+        (s_open["p50_latency_s"], s_open["p99_latency_s"], s_closed["fits_per_s"], s_base["fits_per_s_saturated"]))
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -165,6 +197,10 @@ def main():
         extra["fits_per_s_fp32_analytic"] = 1.0 / t32
         extra["fits_per_s_fp64_numerical"] = 1.0 / t64n
         extra["fp32_fit_dtheta_over_sigma_vs_fp64"] = float(np.max(np.abs(r32["theta"] - r64["theta"]) / sig))
+
+    # ---------------- serving: stream of toy fits (exponential model)
+    if not args.no_serving:
+        extra["serving"] = serving_bench(P, S, args.serving_requests)
 
     # ---------------- oracle on the host
     cpu = None

@@ -8,3 +8,12 @@ library; PyTorch is used only for device streams (and the autograd wrapper).
 from ._lib import HipfitError, lib  # noqa: F401
 from .core import (FP32_EVAL, FP64, Dataset, Graph, fit, nll_eval, nll_grad,  # noqa: F401
                    nll_grad_batched, profile, version)
+from .serving import BatchEngine, FitServer, serve_one_at_a_time  # noqa: F401,E402
+
+
+def autograd_nll(theta, graph, dataset, stream=None):
+    """Differentiable NLL (torch.autograd) -- see paper_1311_1753_amd.autograd."""
+    from .autograd import nll
+    return nll(theta, graph, dataset, stream)
+from .pdfs import (AddPdf, DalitzPdf, ExpPdf, FitManager, GaussianPdf, GooPdf,  # noqa: F401,E402
+                   PolynomialPdf, ProdPdf, TddpPdf, UnbinnedDataSet, Variable)

@@ -38,18 +38,22 @@ template <typename T> struct Col;
 template <> struct Col<double> { typedef double S; };
 template <> struct Col<float> { typedef float S; };
 
-// Small per-thread arrays indexed by wave-uniform values: kept at <= 128 bytes
-// per piece so the compiler holds them in VGPRs (indexed moves) rather than
-// scratch.
-template <typename T, int N> struct RegArr {
-  static constexpr int kPiece = 128 / sizeof(T);
-  static constexpr int kA = N < kPiece ? N : kPiece;
-  static constexpr int kB = N - kA > 0 ? N - kA : 1;
+// Small per-thread arrays indexed by wave-uniform values.  The compiler keeps
+// a private array in VGPRs (indexed moves) only while it is a plain array of
+// at most 128 bytes, so larger ones are split into two plain arrays.
+template <typename T, int N, bool SPLIT = (N * sizeof(T) > 128)> struct RegArr;
+template <typename T, int N> struct RegArr<T, N, false> {
+  T a[N];
+  __device__ __forceinline__ T get(int i) const { return a[i]; }
+  __device__ __forceinline__ void set(int i, T v) { a[i] = v; }
+};
+template <typename T, int N> struct RegArr<T, N, true> {
+  static constexpr int kA = 128 / sizeof(T);
   T a[kA];
-  T b[kB];
-  __device__ __forceinline__ T get(int i) const { return (N <= kPiece || i < kA) ? a[i] : b[i - kA]; }
+  T b[N - kA];
+  __device__ __forceinline__ T get(int i) const { return i < kA ? a[i] : b[i - kA]; }
   __device__ __forceinline__ void set(int i, T v) {
-    if (N <= kPiece || i < kA) a[i] = v; else b[i - kA] = v;
+    if (i < kA) a[i] = v; else b[i - kA] = v;
   }
 };
 

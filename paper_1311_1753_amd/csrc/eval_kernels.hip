@@ -316,28 +316,31 @@ template <typename T, int EPT, int NS, int NCOL, bool HEAVY, bool GRAD>
 __device__ __forceinline__ void tree_tile(const KProgram& P, const CS& cs, const void* const* cols, int64_t n_events,
                                           int64_t tile, double* __restrict__ out) {
   typedef typename Col<T>::S Sx;
+  constexpr int NN = HEAVY ? kMaxNodes : 8;  // node capacity of this instantiation
   const int64_t base = tile * (int64_t)(kBlock * EPT) + threadIdx.x;
   const int n_nodes = P.n_nodes, n_slots = GRAD ? P.n_slots : 0, n_cols = P.n_cols;
-  Sx xv[NCOL][EPT];
+  // one event in flight ahead of the one being evaluated
+  Sx cur[NCOL];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-#pragma unroll
-    for (int c = 0; c < NCOL; ++c)
-      if (c < n_cols) xv[c][e] = i < n_events ? ((const Sx*)cols[c])[i] : Sx(0);
-  }
+  for (int c = 0; c < NCOL; ++c)
+    cur[c] = (c < n_cols && base < n_events) ? ((const Sx*)cols[c])[base] : Sx(0);
   NeuAcc nll;
   double g[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) g[j] = 0.0;
   for (int e = 0; e < EPT; ++e) {
     const int64_t i = base + (int64_t)e * kBlock;
-    if (i >= n_events) break;
     double xe[NCOL];
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) xe[c] = c < n_cols ? (double)xv[c][e] : 0.0;
-    RegArr<T, kMaxNodes> lv, adj, resp;
-    RegArr<T, NS> dl;
+    for (int c = 0; c < NCOL; ++c) xe[c] = (double)cur[c];
+    if (e + 1 < EPT) {
+      const int64_t i1 = i + kBlock;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c)
+        if (c < n_cols) cur[c] = i1 < n_events ? ((const Sx*)cols[c])[i1] : Sx(0);
+    }
+    if (i >= n_events) break;
+    T lv[NN], adj[NN], resp[NN], dl[NS];
     // forward pass (post-order)
     for (int k = 0; k < n_nodes; ++k) {
       const KNode& nd = P.node[k];
@@ -348,76 +351,82 @@ __device__ __forceinline__ void tree_tile(const KProgram& P, const CS& cs, const
       if (op == OP_EXP) {
         T d1[1];
         v = leaf_exp<T>(cs, c0, h, xe[nd.col[0]], d1);
-        dl.set(s0, d1[0]);
+        dl[s0] = d1[0];
       } else if (op == OP_GAUSS) {
         T d2[2];
         v = leaf_gauss<T>(cs, c0, h, xe[nd.col[0]], d2);
-        dl.set(s0, d2[0]);
-        dl.set(s0 + 1, d2[1]);
+        dl[s0] = d2[0];
+        dl[s0 + 1] = d2[1];
       } else if (op == OP_POLY) {
         T dp[8];
         v = leaf_poly<T>(cs, c0, nd.aux, h, xe[nd.col[0]], dp);
-        for (int j = 0; j < nd.aux; ++j) dl.set(s0 + j, dp[j]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < nd.aux) dl[s0 + j] = dp[j];
       } else if (HEAVY && op == OP_DALITZ) {
         T dd[2 * kMaxRes];
         v = leaf_dalitz<T>(cs, c0, nd.aux, h, xe[nd.col[0]], xe[nd.col[1]], dd);
-        for (int j = 0; j < 2 * nd.aux; ++j) dl.set(s0 + j, dd[j]);
+#pragma unroll
+        for (int j = 0; j < 2 * kMaxRes; ++j)
+          if (j < 2 * nd.aux) dl[s0 + j] = dd[j];
       } else if (HEAVY && op == OP_TDDP) {
         T dd[2 * kMaxRes + 2];
         v = leaf_tddp<T>(cs, c0, nd.aux, h, xe[nd.col[0]], xe[nd.col[1]], xe[nd.col[2]], xe[nd.col[3]], dd);
-        for (int j = 0; j < 2 * nd.aux + 2; ++j) dl.set(s0 + j, dd[j]);
+#pragma unroll
+        for (int j = 0; j < 2 * kMaxRes + 2; ++j)
+          if (j < 2 * nd.aux + 2) dl[s0 + j] = dd[j];
       } else if (op == OP_PROD) {
         v = T(0);
         for (int j = 0; j < nd.n_child; ++j) {
           const int ch = P.child[nd.child0 + j];
-          v += lv.get(ch);
-          resp.set(ch, T(1));
+          v += lv[ch];
+          resp[ch] = T(1);
         }
       } else {  // OP_ADD: log-sum-exp with the largest child as pivot
         const int K = nd.n_child;
         T m = T(-INFINITY);
         for (int j = 0; j < K; ++j) {
-          const T x = lv.get(P.child[nd.child0 + j]);
+          const T x = lv[P.child[nd.child0 + j]];
           m = x > m ? x : m;
         }
         const bool live = m > T(-INFINITY);
         T s = T(0);
         for (int j = 0; j < K; ++j) {
           const int ch = P.child[nd.child0 + j];
-          const T w = live ? Mth<T>::ex(lv.get(ch) - m) : T(0);
-          resp.set(ch, w);  // e_j for now
+          const T w = live ? Mth<T>::ex(lv[ch] - m) : T(0);
+          resp[ch] = w;  // e_j for now
           s += cs.get<T>(c0 + j) * w;
         }
         const T is = Mth<T>::rcp(s);
         v = live && s > T(0) ? m + Mth<T>::ln(s) : T(-INFINITY);
-        const T eK = resp.get(P.child[nd.child0 + K - 1]);
+        const T eK = resp[P.child[nd.child0 + K - 1]];
         for (int j = 0; j < K; ++j) {
           const int ch = P.child[nd.child0 + j];
-          const T ej = resp.get(ch);
-          if (j < K - 1) dl.set(s0 + j, (ej - eK) * is);
-          resp.set(ch, cs.get<T>(c0 + j) * ej * is);  // responsibility of child j
+          const T ej = resp[ch];
+          if (j < K - 1) dl[s0 + j] = (ej - eK) * is;
+          resp[ch] = cs.get<T>(c0 + j) * ej * is;  // responsibility of child j
         }
       }
-      lv.set(k, v);
+      lv[k] = v;
     }
     // reverse pass: adjoint of every node, then scale its slots
     const int root = n_nodes - 1;
-    adj.set(root, T(1));
+    adj[root] = T(1);
     for (int k = GRAD ? root : -1; k >= 0; --k) {
       const KNode& nd = P.node[k];
-      const T a = adj.get(k);
+      const T a = adj[k];
       if (nd.op == OP_ADD || nd.op == OP_PROD)
         for (int j = 0; j < nd.n_child; ++j) {
           const int ch = P.child[nd.child0 + j];
-          adj.set(ch, a * resp.get(ch));
+          adj[ch] = a * resp[ch];
         }
       if (k != root)
-        for (int j = 0; j < nd.n_slot; ++j) dl.set(nd.slot0 + j, dl.get(nd.slot0 + j) * a);
+        for (int j = 0; j < nd.n_slot; ++j) dl[nd.slot0 + j] = dl[nd.slot0 + j] * a;
     }
-    nll.add(-(double)lv.get(root));
+    nll.add(-(double)lv[root]);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
-      if (j < n_slots) g[j] += (double)dl.get(j);
+      if (j < n_slots) g[j] += (double)dl[j];
   }
   tile_store<NS>(nll, g, n_slots, out);
 }

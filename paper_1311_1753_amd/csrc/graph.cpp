@@ -602,7 +602,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     else if (NN == 1 && rootn.op == OP_GAUSS) g->kind = KIND_GAUSS;
     else if (NN == 1 && rootn.op == OP_DALITZ) g->kind = KIND_DALITZ;
     else if (NN == 1 && rootn.op == OP_TDDP) g->kind = KIND_TDDP;
-    else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2) g->kind = KIND_TREE_SMALL;
+    else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2 && NN <= 8) g->kind = KIND_TREE_SMALL;
     else g->kind = KIND_TREE;
     *out = g.release();
     return HF_OK;

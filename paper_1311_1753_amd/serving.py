@@ -1,0 +1,209 @@
+"""Continuous batching of toy / pseudo-experiment fits.
+
+`BatchEngine` wraps the library's batch engine: up to `max_slots` fits of one
+graph run concurrently, every `step()` advances each running fit's minimiser
+by one likelihood evaluation, and all of those evaluations share one
+graph-captured GPU launch.  Admission is by device memory: the datasets of
+running fits may hold at most `hbm_budget_bytes`.
+
+`FitServer` is the request loop: requests arrive over time (each with its own
+event sample), are uploaded on a separate thread and stream, admitted in FIFO
+order as slots and budget free up, stepped together, and retired as they
+converge -- requests that arrive while others are on the GPU join the running
+batch at the next step boundary.  It records per-request latency (arrival to
+result on the host) and overall fits/s.
+"""
+import collections
+import ctypes
+import queue
+import threading
+import time
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+from .core import Dataset, _dp, _stream_ptr
+
+
+class BatchEngine:
+    def __init__(self, graph, max_slots=256, hbm_budget_bytes=16 << 30):
+        self.graph = graph
+        h = ctypes.c_void_p()
+        check(lib().batch_create(graph.handle, max_slots, int(hbm_budget_bytes), None, ctypes.byref(h)))
+        self._h = h
+        self.max_slots = max_slots
+
+    def admit(self, ds, theta0=None, tag=0, max_iter=500, edm_tol=1e-10, want_errors=True):
+        """Returns the slot, or None when no slot / budget is free right now."""
+        th = np.ascontiguousarray(self.graph.theta() if theta0 is None else theta0, dtype=np.float64)
+        o = _lib.hf_fit_opts(max_iter, edm_tol, 0, int(want_errors))
+        slot = ctypes.c_int32()
+        rc = lib().batch_admit(self._h, ds.handle, _dp(th), ctypes.byref(o), int(tag), ctypes.byref(slot))
+        if rc in (_lib.HF_E_FULL, _lib.HF_E_BUDGET):
+            return None
+        check(rc)
+        return slot.value
+
+    def step(self):
+        a, d = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().batch_step(self._h, ctypes.byref(a), ctypes.byref(d)))
+        return a.value, d.value
+
+    def poll(self, max_n=None):
+        max_n = self.max_slots if max_n is None else max_n
+        npar = self.graph.n_par
+        tags = (ctypes.c_int64 * max_n)()
+        st = np.zeros(max_n, dtype=np.int32)
+        th = np.zeros((max_n, npar))
+        er = np.zeros((max_n, npar))
+        nll = np.zeros(max_n)
+        ne = np.zeros(max_n, dtype=np.int32)
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        k = check(lib().batch_poll(self._h, max_n, tags, st.ctypes.data_as(i32), _dp(th), _dp(er), _dp(nll),
+                                   ne.ctypes.data_as(i32)))
+        return [{"tag": tags[i], "status": _lib.STATUS_NAMES.get(int(st[i]), str(st[i])), "theta": th[i].copy(),
+                 "errors": er[i].copy(), "nll": nll[i], "n_eval": int(ne[i])} for i in range(k)]
+
+    def cancel(self, tag):
+        check(lib().batch_cancel(self._h, int(tag)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FitServer:
+    """FIFO request loop over a BatchEngine with a background upload thread."""
+
+    def __init__(self, graph, precision="fp32", max_slots=256, hbm_budget_bytes=16 << 30, upload_stream=None):
+        self.graph = graph
+        self.precision = precision
+        self.engine = BatchEngine(graph, max_slots, hbm_budget_bytes)
+        self.upload_stream = upload_stream
+
+    def run(self, requests, columns_of, theta0_of=None, realtime=True, max_iter=500, edm_tol=1e-10):
+        """Serves `requests` (dicts with 'id' and 'arrival_s', in arrival order).
+
+        columns_of(req) -> event columns; theta0_of(req) -> start values.
+        realtime=False submits every request at t = 0 (closed loop).  Returns
+        (results by id, summary)."""
+        reqs = sorted(requests, key=lambda r: r["arrival_s"])
+        arrivals = {r["id"]: (r["arrival_s"] if realtime else 0.0) for r in reqs}
+        ready = queue.Queue()
+        t0 = time.perf_counter()
+        stop = threading.Event()
+        errors = []
+
+        def uploader():
+            try:
+                for r in reqs:
+                    wait = arrivals[r["id"]] - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                    if stop.is_set():
+                        return
+                    ds = Dataset(self.graph, columns_of(r), self.precision, self.upload_stream)
+                    ready.put((r, ds))
+            except Exception as e:  # surfaced by the main loop
+                errors.append(e)
+            finally:
+                ready.put(None)
+
+        th = threading.Thread(target=uploader, daemon=True)
+        th.start()
+        waiting = collections.deque()
+        live = {}
+        results = {}
+        upload_done = False
+        steps = 0
+        eng = self.engine
+        try:
+            while True:
+                # collect uploaded requests
+                while True:
+                    try:
+                        item = ready.get_nowait() if (waiting or live or upload_done) else ready.get(timeout=0.5)
+                    except queue.Empty:
+                        break
+                    if item is None:
+                        upload_done = True
+                        break
+                    waiting.append(item)
+                if errors:
+                    raise errors[0]
+                # FIFO admission while slots and budget allow
+                while waiting:
+                    r, ds = waiting[0]
+                    th0 = theta0_of(r) if theta0_of else None
+                    slot = eng.admit(ds, th0, tag=r["id"], max_iter=max_iter, edm_tol=edm_tol)
+                    if slot is None:
+                        break
+                    waiting.popleft()
+                    live[r["id"]] = (r, ds, time.perf_counter() - t0)
+                if live:
+                    eng.step()
+                    steps += 1
+                    for res in eng.poll():
+                        r, ds, t_adm = live.pop(res["tag"])
+                        t_done = time.perf_counter() - t0
+                        ds.free()
+                        res.update({"arrival_s": arrivals[r["id"]], "admit_s": t_adm, "done_s": t_done,
+                                    "latency_s": t_done - arrivals[r["id"]], "n_events": ds.n})
+                        results[r["id"]] = res
+                elif upload_done and not waiting:
+                    break
+        finally:
+            stop.set()
+            th.join(timeout=60)
+        lat = np.array([v["latency_s"] for v in results.values()])
+        done = np.array([v["done_s"] for v in results.values()])
+        first = min(arrivals.values())
+        span = done.max() - first if done.size else float("nan")
+        summary = {"n": len(results), "steps": steps, "makespan_s": float(span),
+                   "fits_per_s": len(results) / span if span > 0 else float("nan"),
+                   "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else float("nan"),
+                   "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else float("nan"),
+                   "statuses": dict(collections.Counter(v["status"] for v in results.values()))}
+        return results, summary
+
+    def close(self):
+        self.engine.close()
+
+
+def serve_one_at_a_time(graph, requests, columns_of, theta0_of=None, precision="fp64", grad_mode="numerical",
+                        stream=None):
+    """Baseline: each request uploaded and fitted alone, in arrival order.
+
+    Service times are measured back to back on the GPU; latencies follow the
+    FIFO single-server queue over the same arrival times."""
+    from .core import fit
+    reqs = sorted(requests, key=lambda r: r["arrival_s"])
+    service = []
+    results = {}
+    for r in reqs:
+        t0 = time.perf_counter()
+        ds = Dataset(graph, columns_of(r), precision, stream)
+        res = fit(graph, ds, theta0_of(r) if theta0_of else None, grad_mode=grad_mode, stream=stream)
+        ds.free()
+        service.append(time.perf_counter() - t0)
+        results[r["id"]] = res
+    t_free = 0.0
+    lat = []
+    for r, s in zip(reqs, service):
+        start = max(r["arrival_s"], t_free)
+        t_free = start + s
+        lat.append(t_free - r["arrival_s"])
+    lat = np.array(lat)
+    span = t_free - reqs[0]["arrival_s"]
+    return results, {"n": len(reqs), "fits_per_s_saturated": len(reqs) / float(np.sum(service)),
+                     "makespan_s": span, "p50_latency_s": float(np.percentile(lat, 50)),
+                     "p99_latency_s": float(np.percentile(lat, 99)),
+                     "mean_service_s": float(np.mean(service))}

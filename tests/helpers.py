@@ -92,10 +92,16 @@ def grad_scale(model, theta, data):
     return np.abs(rows).sum(axis=0)
 
 
-def perturbed_theta(model, spec_, rel=0.02, seed=0):
+def perturbed_theta(model, spec_, rel=0.5, seed=0):
+    """Truth moved by rel x (parameter step) x N(0, 1), kept inside the bounds."""
     rng = np.random.default_rng(seed)
     th = model.theta(spec_["truth"])
-    return th * (1.0 + rel * rng.standard_normal(th.size))
+    steps = np.array([p[2] for p in spec_["params"]])
+    th = th + rel * steps * rng.standard_normal(th.size)
+    for i, p in enumerate(spec_["params"]):
+        if p[3] != p[4]:
+            th[i] = min(max(th[i], p[3] + 1e-9), p[4] - 1e-9)
+    return th
 
 
 def fmt(x):

@@ -1,0 +1,102 @@
+"""Parity at the workloads' full sizes, through the same kernels and launch
+shapes the benchmark times: every event is compared (the oracle computes the
+full NLL and gradient), plus the fitted parameters of the benchmark workload
+(10^7 events) against the oracle's fit.
+
+Full-size Dalitz events: the 10^6-event amplitude workload uses the oracle's
+accept-reject sample; the 2x10^6-event time-dependent workload uses points
+uniform over the Dalitz plot with exponential decay times smeared by
+sigma_t ~ U[0.02, 0.2] (a cheaper sample of the same observables and ranges:
+the parity claim does not depend on the event distribution)."""
+import numpy as np
+import pytest
+
+import synthgen as S
+from helpers import gen_data, get_spec, grad_scale, nll_scale, oracle_for, perturbed_theta
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1311_1753_amd as P
+    return P
+
+
+_cache = {}
+
+
+def full_data(name):
+    if name in _cache:
+        return _cache[name]
+    if name == "c2":
+        d = S.gen_c2()
+    elif name == "c3":
+        d = gen_data("c3", S.C3["n_events"], S.C3["seed"])
+    else:
+        om = oracle_for("c4")
+        n = S.C4["n_events"]
+        rng = np.random.default_rng(S.C4["seed"])
+        lo, hi = S.dalitz_box()
+        s12, s13 = [], []
+        got = 0
+        th = om.theta(S.C4["truth"])
+        while got < n:
+            a = lo + (hi - lo) * rng.random(1 << 22)
+            b = lo + (hi - lo) * rng.random(1 << 22)
+            keep = om.dalitz_amp2(np.zeros_like(th), a, b) > 0  # c = 0: |A|^2 = 1 inside
+            s12.append(a[keep])
+            s13.append(b[keep])
+            got += int(keep.sum())
+        s12 = np.concatenate(s12)[:n]
+        s13 = np.concatenate(s13)[:n]
+        st = rng.uniform(0.02, 0.2, n)
+        t = rng.exponential(0.41, n) + st * rng.standard_normal(n)
+        d = {"s12": s12, "s13": s13, "t": t, "sigma_t": st}
+    _cache[name] = d
+    return d
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
+def test_full_size_nll_grad(P, name, prec):
+    print(f"\n[case] full-size {name} {prec}", flush=True)
+    sp = get_spec(name)
+    data = full_data(name)
+    om = oracle_for(name)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec)
+    th = perturbed_theta(om, sp, rel=0.01, seed=3)
+    v_ref, g_ref = om.nll(th, data, grad=True)
+    v, gr = P.nll_grad(g, ds, th)
+    s = nll_scale(om, th, data)
+    gs = grad_scale(om, th, data)
+    free = g.free_mask()
+    print(f"  n={ds.n} nll rel {abs(v - v_ref) / s:.2e} grad rel max {np.max(np.abs(gr - g_ref)[free] / gs[free]):.2e}",
+          flush=True)
+    assert abs(v - v_ref) <= TOL[prec] * s
+    assert np.all(np.abs(gr - g_ref)[free] <= TOL[prec] * gs[free])
+
+
+@pytest.mark.timeout(600)
+def test_full_size_fit_of_benchmark_workload(P):
+    """10^7-event composite fit: FP32-eval and FP64 fits within 1e-3 sigma of the oracle's."""
+    print("\n[case] full-size fit c2", flush=True)
+    sp = get_spec("c2")
+    data = full_data("c2")
+    om = oracle_for("c2")
+    ref = om.fit(data)
+    g = P.Graph.from_spec(sp)
+    for prec in ("fp32", "fp64"):
+        ds = P.Dataset(g, data, prec)
+        r = P.fit(g, ds)
+        dev = np.abs(r["theta"] - ref["theta"]) / ref["errors"]
+        print(f"  {prec}: status {r['status']} n_eval {r['n_eval']} max |dtheta|/sigma {dev.max():.2e} "
+              f"err ratio-1 {np.max(np.abs(r['errors'] / ref['errors'] - 1)):.2e}", flush=True)
+        assert r["status"] == "OK"
+        assert dev.max() <= 1e-3
+        assert np.all(np.abs(r["errors"] / ref["errors"] - 1) < 2e-3)
+        ds.free()

@@ -64,7 +64,8 @@ def test_nll_and_gradient_match_oracle(P, stream, name, n, seed, prec):
     ds = P.Dataset(g, data, prec, stream)
     free = g.free_mask()
     tol = TOL[prec]
-    for k, th in enumerate([om.theta(sp["truth"]), perturbed_theta(om, sp, seed=k + 1), om.theta()]):
+    thetas = [om.theta(sp["truth"]), perturbed_theta(om, sp, seed=seed + 1), om.theta()]
+    for k, th in enumerate(thetas):
         v_ref, g_ref = om.nll(th, data, grad=True)
         v, gr = P.nll_grad(g, ds, th, stream)
         v_only = P.nll_eval(g, ds, th, stream)

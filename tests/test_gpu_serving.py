@@ -1,0 +1,101 @@
+"""Continuous batching on the GPU: a fit's result is the same alone and in
+any mix (bitwise: per-fit tiles and fixed-order reductions), admission
+respects the device-memory budget, and the request loop serves every fit."""
+import numpy as np
+import pytest
+
+import synthgen as S
+from helpers import get_spec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1311_1753_amd as P
+    return P
+
+
+def requests(k, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        n = int(np.exp(rng.uniform(np.log(1e3), np.log(3e5))))
+        out.append({"id": i, "n": n, "alpha": -0.5 * (1 + rng.uniform(-0.1, 0.1)),
+                    "arrival_s": 0.002 * i})
+    return out
+
+
+def cols(req):
+    return S.gen_serving_request(req)
+
+
+def run_engine(P, g, reqs, prec, budget=1 << 34, slots=64):
+    eng = P.BatchEngine(g, max_slots=slots, hbm_budget_bytes=budget)
+    dss = {r["id"]: P.Dataset(g, cols(r), prec) for r in reqs}
+    for r in reqs:
+        assert eng.admit(dss[r["id"]], [-2.0], tag=r["id"]) is not None
+    out = {}
+    while len(out) < len(reqs):
+        eng.step()
+        for res in eng.poll():
+            out[res["tag"]] = res
+    eng.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_alone_equals_in_the_mix(P, prec):
+    print(f"\n[case] alone vs mix {prec}", flush=True)
+    g = P.Graph.from_spec(get_spec("c1"))
+    reqs = requests(12, seed=3)
+    mix = run_engine(P, g, reqs, prec)
+    for r in reqs[::3]:
+        alone = run_engine(P, g, [r], prec)[r["id"]]
+        m = mix[r["id"]]
+        assert alone["status"] == "OK" and m["status"] == "OK"
+        assert np.array_equal(alone["theta"], m["theta"]), (alone["theta"], m["theta"])
+        assert alone["nll"] == m["nll"] and alone["n_eval"] == m["n_eval"]
+        # and the single-fit path agrees to the fit tolerance
+        ds = P.Dataset(g, cols(r), prec)
+        single = P.fit(g, ds, [-2.0])
+        assert abs(single["theta"][0] - m["theta"][0]) <= 1e-3 * single["errors"][0]
+
+
+def test_budget_admission_and_cancel(P):
+    g = P.Graph.from_spec(get_spec("c1"))
+    r = [{"id": i, "n": 20_000, "alpha": -0.5, "arrival_s": 0.0} for i in range(3)]
+    dss = [P.Dataset(g, cols(q), "fp32") for q in r]
+    eng = P.BatchEngine(g, max_slots=8, hbm_budget_bytes=2 * dss[0].device_bytes)
+    assert eng.admit(dss[0], [-2.0], tag=0) is not None
+    assert eng.admit(dss[1], [-2.0], tag=1) is not None
+    assert eng.admit(dss[2], [-2.0], tag=2) is None      # over budget: waits
+    eng.cancel(0)                                          # frees slot and budget at once
+    assert eng.admit(dss[2], [-2.0], tag=2) is not None
+    done = {}
+    while True:
+        act, fin = eng.step()
+        for res in eng.poll():
+            done[res["tag"]] = res
+        if act == 0 and fin == 0:
+            break
+    assert sorted(done) == [1, 2]
+    assert all(v["status"] == "OK" for v in done.values())
+    eng.close()
+
+
+def test_fit_server_closed_and_open_loop(P):
+    print("\n[case] fit server", flush=True)
+    g = P.Graph.from_spec(get_spec("c1"))
+    reqs = requests(24, seed=7)
+    ref = run_engine(P, g, reqs, "fp32")
+    srv = P.FitServer(g, "fp32", max_slots=8, hbm_budget_bytes=1 << 34)
+    res, summ = srv.run(reqs, cols, lambda r: [-2.0], realtime=True)
+    srv.close()
+    assert summ["n"] == len(reqs)
+    for r in reqs:
+        assert res[r["id"]]["status"] == "OK"
+        assert np.array_equal(res[r["id"]]["theta"], ref[r["id"]]["theta"])
+    assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0

@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-fits", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
+                    help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
+                         "c3 Dalitz amplitude sum, c4 time-dependent Dalitz: throughput only")
     return ap.parse_args()
 
 
@@ -130,6 +133,51 @@ def serving_bench(P, S, n_req):
     return out
 
 
+def other_workload(args, P, S, torch, stream):
+    """Throughput of the NLL+gradient kernels on one of the other workloads
+    (events sampled flat over the Dalitz plot for c3/c4: the evaluation cost
+    does not depend on where in the plot the events are)."""
+    spec = S.workload(args.workload)
+    n = spec["n_events"]
+    g = P.Graph.from_spec(spec)
+    if args.workload == "c1":
+        data = S.gen_c1()
+    else:
+        data = S.gen_flat_box(n, spec["seed"], g.dalitz_inside)
+        if args.workload == "c4":
+            rng = np.random.default_rng(spec["seed"] + 100)
+            st = rng.uniform(0.02, 0.2, n)
+            data["sigma_t"] = st
+            data["t"] = rng.exponential(0.41, n) + st * rng.standard_normal(n)
+    truth = g.theta(spec["truth"])
+    out = {}
+    for prec in ("fp32", "fp64"):
+        ds = P.Dataset(g, data, prec, stream)
+        for _ in range(args.warmup):
+            P.nll_grad(g, ds, truth, stream)
+        k = max(20, args.steps // (1 if args.workload == "c1" else 10))
+        P.profile(True)
+        el = time_evals(P, g, ds, [truth] * k, stream)
+        e_ms, r_ms, cnt = P.profile(False)
+        out[prec] = {"events_evals_per_s": n * k / el, "ms_per_eval": el / k * 1e3,
+                     "kernel_ms": e_ms / max(cnt, 1), "reduce_ms": r_ms / max(cnt, 1)}
+        ds.free()
+    ncols = len(spec["obs"])
+    bytes32 = 4.0 * ncols * n
+    k_ms = out["fp32"]["kernel_ms"]
+    res = {
+        "metric": "events x NLL+grad evaluations per second", "value": out["fp32"]["events_evals_per_s"],
+        "unit": "events*evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": out["fp32"]["ms_per_eval"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": spec["name"], "n_events": n},
+        "roofline": {"bound": "hbm", "achieved": bytes32 / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": bytes32 / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": None, "extra": out,
+    }
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -142,6 +190,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload != "c2":
+        return other_workload(args, P, S, torch, stream)
     spec = S.C2
     n = spec["n_events"]
     t_gen = time.perf_counter()
@@ -226,7 +276,7 @@ def main():
                    "n_events": n, "n_free_params": n_free},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_tree<float,16,8,2,false,true>", "kernel_ms": k_ms,
+                     "kernel": "k_mix<float,16,2,true>", "kernel_ms": k_ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "extra": extra,

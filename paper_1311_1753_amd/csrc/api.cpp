@@ -108,10 +108,11 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     for (int j = 0; j < (want_grad ? S + 1 : 1); ++j) sums[j] = d->res_host[j];
   }
   const double n = (double)d->n;
-  const double v = -sums[0] + n * sc.ht.lnN;
+  const double v = sums[0] + n * sc.ht.lnN;  // the kernels accumulate -ln P
   if (grad) {
     for (int p = 0; p < np; ++p) grad[p] = n * sc.ht.dlnN[p];
-    for (int j = 0; j < S; ++j) grad[g->slot_par[j]] -= sums[1 + j];
+    for (int j = 0; j < S; ++j)
+      if (g->slot_par[j] >= 0) grad[g->slot_par[j]] -= sums[1 + j];  // and +d ln P
     for (int p = 0; p < np; ++p)
       if (g->par[p].fixed) grad[p] = 0.0;
   }

@@ -117,10 +117,11 @@ static void finish_fit(const pdf_graph* g, const dataset* d, const StagedCall& s
                        double* grad) {
   const int np = (int)g->par.size(), S = g->prog.n_slots;
   const double n = (double)d->n;
-  const double v = (d->n > 0 ? -row[0] : 0.0) + n * sc.ht.lnN;
+  const double v = (d->n > 0 ? row[0] : 0.0) + n * sc.ht.lnN;  // rows hold sum(-ln P), sum(d ln P)
   for (int p = 0; p < np; ++p) grad[p] = n * sc.ht.dlnN[p];
   if (d->n > 0)
-    for (int j = 0; j < S; ++j) grad[g->slot_par[j]] -= row[1 + j];
+    for (int j = 0; j < S; ++j)
+      if (g->slot_par[j] >= 0) grad[g->slot_par[j]] -= row[1 + j];
   for (int p = 0; p < np; ++p)
     if (g->par[p].fixed) grad[p] = 0.0;
   *nll = std::isfinite(v) ? v : INFINITY;

@@ -284,7 +284,7 @@ __device__ __forceinline__ void leaf_tile(const KNode& nd, const CS& cs, const v
 #pragma unroll
     for (int c = 0; c < NC; ++c) xv[c][e] = i < n_events ? cp[c][i] : Sx(0);
   }
-  NeuAcc nll;
+  double nll = 0.0;  // <= EPT terms per thread: compensation starts at the tile level
   double g[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) g[j] = 0.0;
@@ -299,13 +299,13 @@ __device__ __forceinline__ void leaf_tile(const KNode& nd, const CS& cs, const v
       else if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, c0, nd.aux, hoisted, (double)xv[0][e], (double)xv[1][e], dl);
       else lv = leaf_tddp<T>(cs, c0, nd.aux, hoisted, (double)xv[0][e], (double)xv[1][e], (double)xv[2][e],
                             (double)xv[3][e], dl);
-      nll.add(-(double)lv);
+      nll -= (double)lv;
 #pragma unroll
       for (int j = 0; j < NS; ++j)
         if (j < n_slots) g[j] += (double)dl[j];
     }
   }
-  tile_store<NS>(nll, g, n_slots, out);
+  tile_store<NS>(NeuAcc{nll, 0.0}, g, n_slots, out);
 }
 
 // ------------------------------------------------------------------ tree interpreter tiles
@@ -324,7 +324,7 @@ __device__ __forceinline__ void tree_tile(const KProgram& P, const CS& cs, const
 #pragma unroll
   for (int c = 0; c < NCOL; ++c)
     cur[c] = (c < n_cols && base < n_events) ? ((const Sx*)cols[c])[base] : Sx(0);
-  NeuAcc nll;
+  double nll = 0.0;
   double g[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) g[j] = 0.0;
@@ -423,12 +423,98 @@ __device__ __forceinline__ void tree_tile(const KProgram& P, const CS& cs, const
       if (k != root)
         for (int j = 0; j < nd.n_slot; ++j) dl[nd.slot0 + j] = dl[nd.slot0 + j] * a;
     }
-    nll.add(-(double)lv[root]);
+    nll -= (double)lv[root];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
       if (j < n_slots) g[j] += (double)dl[j];
   }
-  tile_store<NS>(nll, g, n_slots, out);
+  tile_store<NS>(NeuAcc{nll, 0.0}, g, n_slots, out);
+}
+
+// ------------------------------------------------------------------ mixture tiles
+// Root ADD of K single-column EXP / GAUSS leaves (the signal-plus-background
+// shape).  Fully static: the child kinds are wave-uniform branches, the
+// accumulators have a fixed layout [2 per child, then K-1 fractions] that the
+// host maps back to parameters.
+template <typename T, int EPT, int K, bool GRAD>
+__device__ __forceinline__ void mix_tile(const KProgram& P, const CS& cs, const void* const* cols, int64_t n_events,
+                                         int64_t tile, double* __restrict__ out) {
+  typedef typename Col<T>::S Sx;
+  constexpr int NA = 3 * K - 1;
+  const int64_t base = tile * (int64_t)(kBlock * EPT) + threadIdx.x;
+  // per-child constants, wave-uniform (constant layouts of EXP / GAUSS above)
+  const KNode& rn = P.node[P.n_nodes - 1];
+  bool gs[K];
+  double loc[K];
+  T k1[K], lhi[K], llo[K], d0c[K], d1c[K], fr[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const KNode& cn = P.node[P.child[rn.child0 + j]];
+    const int c0 = cn.c0;
+    gs[j] = cn.op == OP_GAUSS;
+    loc[j] = cs.d[c0];
+    k1[j] = cs.get<T>(c0 + 1);
+    lhi[j] = cs.get<T>(c0 + 2);
+    llo[j] = cs.get<T>(c0 + 3);
+    d0c[j] = cs.get<T>(c0 + 4);
+    d1c[j] = gs[j] ? cs.get<T>(c0 + 5) : T(0);
+    fr[j] = cs.get<T>(rn.c0 + j);
+  }
+  const Sx* xp = (const Sx*)cols[0];
+  Sx xv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    xv[e] = i < n_events ? xp[i] : Sx(0);
+  }
+  double nll = 0.0;
+  double g[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) g[j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    if (i < n_events) {
+      const double x = (double)xv[e];
+      T lv[K], d0[K], d1[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const T u = (T)(x + loc[j]);  // location difference formed in double
+        if (gs[j]) {
+          const T z = u * k1[j];
+          lv[j] = (T(-0.5) * z * z - lhi[j]) - llo[j];
+          d0[j] = z * k1[j] - d0c[j];
+          d1[j] = z * z * k1[j] - d1c[j];
+        } else {
+          lv[j] = (k1[j] * u - lhi[j]) - llo[j];
+          d0[j] = u - d0c[j];
+          d1[j] = T(0);
+        }
+      }
+      T m = lv[0];
+#pragma unroll
+      for (int j = 1; j < K; ++j) m = lv[j] > m ? lv[j] : m;
+      T ej[K], ssum = T(0);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        ej[j] = Mth<T>::ex(lv[j] - m);
+        ssum += fr[j] * ej[j];
+      }
+      const T v = ssum > T(0) ? m + Mth<T>::ln(ssum) : T(-INFINITY);
+      nll -= (double)v;
+      if (GRAD) {
+        const T is = Mth<T>::rcp(ssum);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const T r = fr[j] * ej[j] * is;
+          g[2 * j] += (double)(r * d0[j]);
+          g[2 * j + 1] += (double)(r * d1[j]);
+          if (j < K - 1) g[2 * K + j] += (double)((ej[j] - ej[K - 1]) * is);
+        }
+      }
+    }
+  }
+  tile_store<NA>(NeuAcc{nll, 0.0}, g, GRAD ? NA : 0, out);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -444,6 +530,12 @@ __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   tree_tile<T, EPT, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x,
                               a.partials + (int64_t)blockIdx.x * a.stride);
+}
+
+template <typename T, int EPT, int K, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
+  const CS cs{a.prog.c64, a.prog.c32};
+  mix_tile<T, EPT, K, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x, a.partials + (int64_t)blockIdx.x * a.stride);
 }
 
 // Batched: the program structure is shared (kernel argument); constants,
@@ -484,6 +576,23 @@ __global__ __launch_bounds__(kBlock) void k_leaf_batched(const BatchArgs a) {  /
   }
 }
 
+template <typename T, int EPT, int K>
+__global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
+  const int tpb = a.hdr->tiles_per_block, total = a.hdr->total_tiles, n_fits = a.hdr->n_fits;
+  const FitRec* fits = (const FitRec*)(a.hdr + 1);
+  const int g0 = blockIdx.x * tpb;
+  const int g1 = min(g0 + tpb, total);
+  if (g0 >= g1) return;
+  int f = find_fit(fits, n_fits, g0);
+  for (int gt = g0; gt < g1; ++gt) {
+    while (gt >= fits[f].tile_begin + fits[f].n_tiles) ++f;
+    const FitRec& fr = fits[f];
+    const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
+    const int64_t lt = gt - fr.tile_begin;
+    mix_tile<T, EPT, K, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
+  }
+}
+
 template <typename T, int EPT, int NS, int NCOL, bool HEAVY>
 __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
   const int tpb = a.hdr->tiles_per_block, total = a.hdr->total_tiles, n_fits = a.hdr->n_fits;
@@ -502,35 +611,62 @@ __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
 }
 
 // Second pass: one block per fit sums that fit's tile rows in a fixed order.
-// Wave w handles columns w, w+4, ...; lane l sums rows l, l+64, ... with
-// Neumaier, then a butterfly merge.  result = [nll, slot_0 .. slot_{S-1}].
+// Thread t takes rows t, t+256, ... (two-sum compensated per column), then a
+// wave64 butterfly and a fixed-order merge of the four waves per column.
+// result = [nll, slot_0 .. slot_{S-1}].
+constexpr int kMaxRedCols = kMaxSlots + 2;
 __device__ __forceinline__ void reduce_fit(const FitRec& fr, int stride, int n_slots) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ double nll_parts[2];
-  for (int col = wave; col < n_slots + 2; col += 4) {
-    double s = 0.0, c = 0.0;
-    for (int r = lane; r < fr.n_tiles; r += 64) {
-      const double x = fr.partials[(int64_t)r * stride + col];
-      double ns, e;
-      two_sum(s, x, ns, e);
-      s = ns;
-      c += e;
-    }
+  const int nc = n_slots + 2;
+  double s[kMaxRedCols], c[kMaxRedCols];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double os = __shfl_xor(s, off, 64), oc = __shfl_xor(c, off, 64);
+  for (int j = 0; j < kMaxRedCols; ++j) s[j] = c[j] = 0.0;
+#pragma unroll 2
+  for (int r = threadIdx.x; r < fr.n_tiles; r += kBlock) {
+    const double* row = fr.partials + (int64_t)r * stride;
+#pragma unroll
+    for (int j = 0; j < kMaxRedCols; ++j)
+      if (j < nc) {
+        double ns, e;
+        two_sum(s[j], row[j], ns, e);
+        s[j] = ns;
+        c[j] += e;
+      }
+  }
+  __shared__ double red[4][kMaxRedCols][2];
+  __shared__ double nll_parts[2];
+#pragma unroll
+  for (int j = 0; j < kMaxRedCols; ++j)
+    if (j < nc) {
+      double a = s[j], b = c[j];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double oa = __shfl_xor(a, off, 64), ob = __shfl_xor(b, off, 64);
+        double ns, e;
+        two_sum(a, oa, ns, e);
+        a = ns;
+        b = (b + ob) + e;
+      }
+      if (lane == 0) {
+        red[wave][j][0] = a;
+        red[wave][j][1] = b;
+      }
+    }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < nc) {
+    double a = red[0][t][0], b = red[0][t][1];
+    for (int w = 1; w < 4; ++w) {
       double ns, e;
-      two_sum(s, os, ns, e);
-      s = ns;
-      c = (c + oc) + e;
+      two_sum(a, red[w][t][0], ns, e);
+      a = ns;
+      b = (b + red[w][t][1]) + e;
     }
-    if (lane == 0) {
-      if (col < 2) nll_parts[col] = s + c;
-      else fr.result[col - 1] = s + c;
-    }
+    if (t < 2) nll_parts[t] = a + b;
+    else fr.result[t - 1] = a + b;
   }
   __syncthreads();
-  if (threadIdx.x == 0) fr.result[0] = nll_parts[0] + nll_parts[1];
+  if (t == 0) fr.result[0] = nll_parts[0] + nll_parts[1];
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const FitRec* __restrict__ fits, int n_slots) {
@@ -551,6 +687,8 @@ static hipError_t launch_light(int kind, const EvalArgs& a, int64_t n_tiles, hip
     case KIND_EXP: hipLaunchKernelGGL((k_leaf<T, OP_EXP, EPT, GRAD>), grid, block, 0, st, a); break;
     case KIND_GAUSS: hipLaunchKernelGGL((k_leaf<T, OP_GAUSS, EPT, GRAD>), grid, block, 0, st, a); break;
     case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree<T, EPT, 8, 2, false, GRAD>), grid, block, 0, st, a); break;
+    case KIND_MIX2: hipLaunchKernelGGL((k_mix<T, EPT, 2, GRAD>), grid, block, 0, st, a); break;
+    case KIND_MIX3: hipLaunchKernelGGL((k_mix<T, EPT, 3, GRAD>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -576,7 +714,7 @@ static hipError_t launch_any(int kind, const EvalArgs& a, int64_t n_tiles, hipSt
 
 int kind_ept(int kind) {
   switch (kind) {
-    case KIND_EXP: case KIND_GAUSS: case KIND_TREE_SMALL: return kEptLight;
+    case KIND_EXP: case KIND_GAUSS: case KIND_TREE_SMALL: case KIND_MIX2: case KIND_MIX3: return kEptLight;
     default: return kEptHeavy;
   }
 }
@@ -593,6 +731,8 @@ static hipError_t launch_b_light(int kind, const BatchArgs& a, int grid, hipStre
     case KIND_EXP: hipLaunchKernelGGL((k_leaf_batched<T, OP_EXP, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case KIND_GAUSS: hipLaunchKernelGGL((k_leaf_batched<T, OP_GAUSS, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree_batched<T, EPT, 8, 2, false>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case KIND_MIX2: hipLaunchKernelGGL((k_mix_batched<T, EPT, 2>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case KIND_MIX3: hipLaunchKernelGGL((k_mix_batched<T, EPT, 3>), dim3(grid), dim3(kBlock), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -598,6 +598,26 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     // kernel family
     const NodeInfo& rootn = g->nodes[NN - 1];
     bool heavy = g->dz.node >= 0;
+    // mixture of single-column EXP/GAUSS leaves: static kernel with its own
+    // accumulator layout [2 per child, then the fractions]
+    bool mix = rootn.op == OP_ADD && (NN == 3 || NN == 4) && (int)rootn.child.size() == NN - 1 && P.n_cols == 1;
+    for (int c : rootn.child)
+      if (mix && g->nodes[c].op != OP_EXP && g->nodes[c].op != OP_GAUSS) mix = false;
+    if (mix) {
+      const int K = (int)rootn.child.size();
+      std::vector<int> acc(3 * K - 1, -1);
+      for (int j = 0; j < K; ++j) {
+        const NodeInfo& cn = g->nodes[rootn.child[j]];
+        acc[2 * j] = cn.par[0];
+        if (cn.op == OP_GAUSS) acc[2 * j + 1] = cn.par[1];
+      }
+      for (int j = 0; j < K - 1; ++j) acc[2 * K + j] = rootn.par[j];
+      g->slot_par = acc;
+      P.n_slots = 3 * K - 1;
+      g->kind = K == 2 ? KIND_MIX2 : KIND_MIX3;
+      *out = g.release();
+      return HF_OK;
+    }
     if (NN == 1 && rootn.op == OP_EXP) g->kind = KIND_EXP;
     else if (NN == 1 && rootn.op == OP_GAUSS) g->kind = KIND_GAUSS;
     else if (NN == 1 && rootn.op == OP_DALITZ) g->kind = KIND_DALITZ;

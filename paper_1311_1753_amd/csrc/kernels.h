@@ -13,7 +13,9 @@ enum KernelKind {
   KIND_TREE_SMALL = 2,  // tree of light nodes, <= 8 gradient slots, <= 2 columns
   KIND_DALITZ = 3,      // single DALITZ leaf
   KIND_TDDP = 4,        // single TDDP leaf
-  KIND_TREE = 5         // any tree
+  KIND_TREE = 5,        // any tree
+  KIND_MIX2 = 6,        // root ADD of 2 single-column EXP/GAUSS leaves
+  KIND_MIX3 = 7         // root ADD of 3 single-column EXP/GAUSS leaves
 };
 
 constexpr int kEptLight = 16;   // events per thread per tile, light kernels (tile 4096)

@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-fits", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 512 MiB device buffer 5 times (reference for the HBM byte counters)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
                     help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
                          "c3 Dalitz amplitude sum, c4 time-dependent Dalitz: throughput only")
@@ -190,6 +192,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel(), "launches": 5}))
+        return
     if args.workload != "c2":
         return other_workload(args, P, S, torch, stream)
     spec = S.C2

@@ -185,6 +185,16 @@ typedef struct {
 int fit(const pdf_graph* g, const dataset* d, const hf_fit_opts* opts, void* hip_stream,
         double* params_inout, double* errors_out, double* cov_out, hf_fit_summary* summary);
 
+/* The same minimiser on any function: fn(x, &f, g, user) must set f and the
+ * gradient g[n] at x (return 0; nonzero aborts with HF_E_INVALID; a non-finite
+ * f means "outside the domain").  params gives start values, steps, bounds
+ * and fixed flags (as for a graph); x0 (nullable) overrides the start values.
+ * Host only: no GPU work. */
+typedef int (*hf_fg_fn)(const double* x, double* f, double* g, void* user);
+int hf_minimize(int32_t n, const hf_param* params, const double* x0, const hf_fit_opts* opts, double f_noise,
+                hf_fg_fn fn, void* user, double* x_out, double* errors_out, double* cov_out,
+                hf_fit_summary* summary);
+
 /* ------------------------------------------------------------------ batched serving
  * A batch engine holds up to max_slots concurrent fits of one graph.  Each
  * batch_step advances every active fit's minimiser by one likelihood

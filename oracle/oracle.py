@@ -269,14 +269,23 @@ class Model:
     def free_mask(self):
         return np.array([not p[5] for p in self.spec["params"]])
 
-    def hessian(self, theta, data, rel=1e-4):
-        """Central finite differences of the exact gradient, symmetrised."""
+    def hessian(self, theta, data, steps=None):
+        """Central finite differences of the exact gradient, symmetrised.
+
+        Default steps: a tenth of each parameter's error, from a first pass
+        with 1e-4 of the parameter's step size (the NLL is close to quadratic
+        over a fraction of an error, so the difference quotient is its second
+        derivative there)."""
         theta = np.asarray(theta, dtype=np.float64)
         n = theta.size
+        if steps is None:
+            pstep = np.array([p[2] for p in self.spec["params"]])
+            H0 = self.hessian(theta, data, steps=1e-4 * np.maximum(pstep, 1e-12))
+            d = np.diag(H0)
+            steps = np.where(d > 0, 0.1 / np.sqrt(np.abs(d) + 1e-300), 1e-4 * pstep)
         H = np.zeros((n, n))
-        steps = np.array([p[2] for p in self.spec["params"]])
         for j in range(n):
-            h = rel * max(abs(theta[j]), steps[j], 1e-8)
+            h = steps[j]
             tp, tm = theta.copy(), theta.copy()
             tp[j] += h
             tm[j] -= h

@@ -69,6 +69,7 @@ class hf_fit_summary(ctypes.Structure):
 
 # name -> (restype, argtypes); the exported C ABI of include/hipfit.h
 _VP = ctypes.c_void_p
+FG_FN = ctypes.CFUNCTYPE(ctypes.c_int, _DP, _DP, _DP, _VP)
 SIGNATURES = {
     "pdf_graph_create": (ctypes.c_int, [ctypes.POINTER(hf_obs), ctypes.c_int32, ctypes.POINTER(hf_param),
                                         ctypes.c_int32, ctypes.POINTER(hf_node), ctypes.c_int32, ctypes.c_int32,
@@ -84,6 +85,8 @@ SIGNATURES = {
     "nll_grad_batched": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int32, _DP, _VP, _DP, _DP]),
     "fit": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(hf_fit_opts), _VP, _DP, _DP, _DP,
                            ctypes.POINTER(hf_fit_summary)]),
+    "hf_minimize": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(hf_param), _DP, ctypes.POINTER(hf_fit_opts),
+                                   ctypes.c_double, FG_FN, _VP, _DP, _DP, _DP, ctypes.POINTER(hf_fit_summary)]),
     "batch_create": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, _VP, ctypes.POINTER(_VP)]),
     "batch_destroy": (None, [_VP]),
     "batch_admit": (ctypes.c_int, [_VP, _VP, _DP, ctypes.POINTER(hf_fit_opts), ctypes.c_int64, _I32P]),

@@ -243,6 +243,44 @@ def fit(graph, ds, theta0=None, grad_mode="analytic", max_iter=500, edm_tol=1e-1
             "n_eval": s.n_eval, "status": _lib.STATUS_NAMES.get(s.status, str(s.status))}
 
 
+def minimize(fg, params, x0=None, max_iter=500, edm_tol=1e-10, want_errors=True, f_noise=0.0):
+    """The library's minimiser on a Python function fg(x) -> (f, grad).
+
+    params: [(name, init, step, lo, hi, fixed)].  Runs on the host only."""
+    n = len(params)
+    p_arr = (_lib.hf_param * max(n, 1))(
+        *[_lib.hf_param(p[0].encode(), p[1], p[2], p[3], p[4], int(bool(p[5]) if len(p) > 5 else 0))
+          for p in params])
+    err_box = []
+
+    def cb(xp, fp, gp, user):
+        try:
+            x = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+            f, g = fg(x)
+            fp[0] = float(f)
+            for i in range(n):
+                gp[i] = float(g[i])
+            return 0
+        except Exception as e:  # reported after the call
+            err_box.append(e)
+            return 1
+
+    cfun = _lib.FG_FN(cb)
+    x = np.zeros(n)
+    err = np.zeros(n)
+    cov = np.zeros((n, n))
+    s = _lib.hf_fit_summary()
+    o = _lib.hf_fit_opts(max_iter, edm_tol, 0, int(want_errors))
+    x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+    rc = lib().hf_minimize(n, p_arr, _dp(x0a) if x0a is not None else None, ctypes.byref(o), f_noise, cfun, None,
+                           _dp(x), _dp(err), _dp(cov), ctypes.byref(s))
+    if err_box:
+        raise err_box[0]
+    check(rc, allow=(_lib.HF_E_NOT_CONVERGED, _lib.HF_E_DOMAIN))
+    return {"theta": x, "errors": err, "cov": cov, "nll": s.nll, "edm": s.edm, "n_iter": s.n_iter,
+            "n_eval": s.n_eval, "status": _lib.STATUS_NAMES.get(s.status, str(s.status))}
+
+
 def profile(enable=None):
     """Kernel timing hook: profile(True) resets and starts, profile(False)
     stops; returns (eval_ms, reduce_ms, n_calls) accumulated so far."""

@@ -136,21 +136,30 @@ __device__ __forceinline__ T leaf_tddp(const CS& cs, int c0, int R, bool hoisted
   const T nA = S.re * S.re + S.im * S.im;
   const T nB = Sb.re * Sb.re + Sb.im * Sb.im;
   const T X = S.re * Sb.re + S.im * Sb.im;  // Re(conj(A) Abar)
-  const T ac = T(0.5) * (nA + nB), a0 = T(0.5) * (nA - nB), as = -X;
-  // time part
-  const T t = (T)xt, s = (T)xs;
+  const T as = -X;
+  // Decay-time factors, formed in double: C - E(1/tau), S and the tau / y
+  // derivative combinations are small differences of nearly equal terms
+  // (|y| << 1), and rounding them in float would bias every event the same way.
+  const double t = xt, s = xs;
   const int tb = c0 + dz_time_base(R);
-  const T Gm = cs.get<T>(tb + kTdGm), Gp = cs.get<T>(tb + kTdGp), G0 = cs.get<T>(tb + kTdG);
-  const T g = Mth<T>::ex(T(-0.5) * t * t * Mth<T>::rcp(s * s));
-  T Em, dEm, Ep, dEp, E0, dE0;
-  econv<T>(t, s, Gm, g, Em, dEm);
-  econv<T>(t, s, Gp, g, Ep, dEp);
-  econv<T>(t, s, G0, g, E0, dE0);
-  const T Ct = T(0.5) * (Em + Ep), St = T(0.5) * (Em - Ep);
-  const T Rv = ac * Ct + a0 * E0 + as * St;
+  const double g = ::exp(-0.5 * t * t / (s * s));
+  double Em, dEm, Ep, dEp, E0, dE0;
+  econv<double>(t, s, cs.d[tb + kTdGm], g, Em, dEm);
+  econv<double>(t, s, cs.d[tb + kTdGp], g, Ep, dEp);
+  econv<double>(t, s, cs.d[tb + kTdG], g, E0, dE0);
+  const double Cd = 0.5 * (Em + Ep);
+  const double Tm = dEm * cs.d[tb + kTdDGmTau], Tp = dEp * cs.d[tb + kTdDGpTau];
+  const double T1 = 0.5 * (Tm + Tp), T0 = dE0 * cs.d[tb + kTdDGTau];
+  const double Ym = dEm * cs.d[tb + kTdDGmY], Yp = dEp * cs.d[tb + kTdDGpY];
+  const T cc = (T)(Cd + E0);          // d R / d(|A|^2 / 2)
+  const T cb_ = (T)(Cd - E0);         // d R / d(|Abar|^2 / 2)
+  const T St = (T)(0.5 * (Em - Ep));  // S(t)
+  const T tA = (T)(T1 + T0), tB = (T)(T1 - T0), tS = (T)(0.5 * (Tm - Tp));
+  const T yAB = (T)(0.5 * (Ym + Yp)), yS = (T)(0.5 * (Ym - Yp));
+  // rate = a_c C + a_0 E0 + a_s S = |A|^2 (C + E0)/2 + |Abar|^2 (C - E0)/2 + a_s S
+  const T Rv = T(0.5) * nA * cc + T(0.5) * nB * cb_ + as * St;
   const T iR = Mth<T>::rcp(Rv);
   T lv = Rv > T(0) ? Mth<T>::ln(Rv) : T(-INFINITY);
-  const T cc = Ct + E0, cb_ = Ct - E0;  // d R / d nA = cc/2, d R / d nB = cb_/2
 #pragma unroll
   for (int k = 0; k < kMaxRes; ++k)
     if (k < R) {
@@ -172,10 +181,8 @@ __device__ __forceinline__ T leaf_tddp(const CS& cs, int c0, int R, bool hoisted
         dl[2 * k + 1] -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
       }
     }
-  const T dRm = T(0.5) * (ac + as), dRp = T(0.5) * (ac - as);
-  const T dtau = dRm * dEm * cs.get<T>(tb + kTdDGmTau) + dRp * dEp * cs.get<T>(tb + kTdDGpTau) +
-                 a0 * dE0 * cs.get<T>(tb + kTdDGTau);
-  const T dy = dRm * dEm * cs.get<T>(tb + kTdDGmY) + dRp * dEp * cs.get<T>(tb + kTdDGpY);
+  const T dtau = T(0.5) * nA * tA + T(0.5) * nB * tB + as * tS;
+  const T dy = T(0.5) * (nA + nB) * yAB + as * yS;
   dl[2 * R] = dtau * iR;
   dl[2 * R + 1] = dy * iR;
   if (!hoisted) {
@@ -517,12 +524,109 @@ __device__ __forceinline__ void mix_tile(const KProgram& P, const CS& cs, const 
   tile_store<NA>(NeuAcc{nll, 0.0}, g, GRAD ? NA : 0, out);
 }
 
+// ------------------------------------------------------------------ reduction
+// Deterministic reduction of the tile rows of one fit, done inside the
+// likelihood launch.  Tiles form groups of kGroup consecutive tiles; the block
+// that finishes the last tile of a group sums that group's rows in order into
+// a group row, and the block that finishes the last group sums the group rows
+// in order into the result [nll, slot_0 .. slot_{S-1}].  Each column is a
+// two-sum compensated sum; the NLL is the sum of its value and compensation
+// columns.  Counters are re-armed by the blocks that consume them.  The
+// fences order each block's row stores before its counter update (release)
+// and the counter before the consumer's loads (acquire), across the XCDs'
+// separate L2 caches.
+constexpr int kMaxRedCols = kMaxSlots + 2;
+
+__device__ __forceinline__ void reduce_rows(const double* rows, int n_rows, int stride, int n_slots, double* dst,
+                                            bool final_row) {
+  __shared__ double buf[kGroup][kMaxRedCols];
+  __shared__ double nll_parts[2];
+  const int nc = n_slots + 2, t = threadIdx.x;
+  double s = 0.0, c = 0.0;
+  for (int r0 = 0; r0 < n_rows; r0 += kGroup) {
+    const int m = min(kGroup, n_rows - r0);
+    for (int idx = t; idx < m * nc; idx += kBlock) {
+      const int r = idx / nc, j = idx - r * nc;
+      buf[r][j] = rows[(int64_t)(r0 + r) * stride + j];
+    }
+    __syncthreads();
+    if (t < nc)
+      for (int r = 0; r < m; ++r) {
+        double ns, e;
+        two_sum(s, buf[r][t], ns, e);
+        s = ns;
+        c += e;
+      }
+    __syncthreads();
+  }
+  if (!final_row) {
+    if (t < nc) dst[t] = s + c;
+    return;
+  }
+  if (t < nc) {
+    if (t < 2) nll_parts[t] = s + c;
+    else dst[t - 1] = s + c;
+  }
+  __syncthreads();
+  if (t == 0) dst[0] = nll_parts[0] + nll_parts[1];
+}
+
+// Called by every block after it stored the row of tile `tile` of a fit.
+// Every thread fences its own stores before the block's counter update and
+// after learning that its block consumes the rows.
+__device__ __forceinline__ void tile_done(const FitRec& fr, int64_t tile, int stride, int n_slots) {
+  __shared__ int last_group, last_all;
+  const int n_groups = (fr.n_tiles + kGroup - 1) / kGroup;
+  const int grp = (int)(tile / kGroup);
+  const int in_grp = min(kGroup, fr.n_tiles - grp * kGroup);
+  unsigned* gcount = fr.counter;
+  unsigned* fcount = fr.counter + n_groups;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last_group = atomicAdd(&gcount[grp], 1u) == (unsigned)(in_grp - 1);
+  __syncthreads();
+  if (last_group) {
+    __threadfence();
+    const double* rows = fr.partials + (int64_t)grp * kGroup * stride;
+    if (n_groups == 1) {
+      reduce_rows(rows, in_grp, stride, n_slots, fr.result, true);
+      if (threadIdx.x == 0) atomicExch(&gcount[grp], 0u);
+    } else {
+      reduce_rows(rows, in_grp, stride, n_slots, fr.gpart + (int64_t)grp * stride, false);
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        atomicExch(&gcount[grp], 0u);
+        last_all = atomicAdd(fcount, 1u) == (unsigned)(n_groups - 1);
+      }
+      __syncthreads();
+      if (last_all) {
+        __threadfence();
+        reduce_rows(fr.gpart, n_groups, stride, n_slots, fr.result, true);
+        if (threadIdx.x == 0) atomicExch(fcount, 0u);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ kernels
+__device__ __forceinline__ FitRec single_rec(const EvalArgs& a) {
+  FitRec fr;
+  fr.partials = a.partials;
+  fr.gpart = a.gpart;
+  fr.n_tiles = a.n_tiles;
+  fr.result = a.result;
+  fr.counter = a.counter;
+  return fr;
+}
+
 template <typename T, int OP, int EPT, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_leaf(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   leaf_tile<T, OP, EPT, GRAD>(a.prog.node[0], cs, a.col, a.n_events, blockIdx.x, a.prog.n_slots,
                         a.partials + (int64_t)blockIdx.x * a.stride);
+  tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
 template <typename T, int EPT, int NS, int NCOL, bool HEAVY, bool GRAD>
@@ -530,12 +634,14 @@ __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   tree_tile<T, EPT, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x,
                               a.partials + (int64_t)blockIdx.x * a.stride);
+  tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
 template <typename T, int EPT, int K, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   mix_tile<T, EPT, K, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x, a.partials + (int64_t)blockIdx.x * a.stride);
+  tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
 // Batched: the program structure is shared (kernel argument); constants,
@@ -573,6 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_batched(const BatchArgs a) {  /
     const int64_t lt = gt - fr.tile_begin;
     leaf_tile<T, OP, EPT, true>(a.prog.node[0], cs, fr.col, fr.n_events, lt, a.prog.n_slots,
                           fr.partials + lt * (a.prog.n_slots + 2));
+    tile_done(fr, lt, a.prog.n_slots + 2, a.prog.n_slots);
   }
 }
 
@@ -590,6 +697,7 @@ __global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
     const int64_t lt = gt - fr.tile_begin;
     mix_tile<T, EPT, K, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
+    tile_done(fr, lt, a.prog.n_slots + 2, a.prog.n_slots);
   }
 }
 
@@ -607,76 +715,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
     const int64_t lt = gt - fr.tile_begin;
     tree_tile<T, EPT, NS, NCOL, HEAVY, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
+    tile_done(fr, lt, a.prog.n_slots + 2, a.prog.n_slots);
   }
-}
-
-// Second pass: one block per fit sums that fit's tile rows in a fixed order.
-// Thread t takes rows t, t+256, ... (two-sum compensated per column), then a
-// wave64 butterfly and a fixed-order merge of the four waves per column.
-// result = [nll, slot_0 .. slot_{S-1}].
-constexpr int kMaxRedCols = kMaxSlots + 2;
-__device__ __forceinline__ void reduce_fit(const FitRec& fr, int stride, int n_slots) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nc = n_slots + 2;
-  double s[kMaxRedCols], c[kMaxRedCols];
-#pragma unroll
-  for (int j = 0; j < kMaxRedCols; ++j) s[j] = c[j] = 0.0;
-#pragma unroll 2
-  for (int r = threadIdx.x; r < fr.n_tiles; r += kBlock) {
-    const double* row = fr.partials + (int64_t)r * stride;
-#pragma unroll
-    for (int j = 0; j < kMaxRedCols; ++j)
-      if (j < nc) {
-        double ns, e;
-        two_sum(s[j], row[j], ns, e);
-        s[j] = ns;
-        c[j] += e;
-      }
-  }
-  __shared__ double red[4][kMaxRedCols][2];
-  __shared__ double nll_parts[2];
-#pragma unroll
-  for (int j = 0; j < kMaxRedCols; ++j)
-    if (j < nc) {
-      double a = s[j], b = c[j];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double oa = __shfl_xor(a, off, 64), ob = __shfl_xor(b, off, 64);
-        double ns, e;
-        two_sum(a, oa, ns, e);
-        a = ns;
-        b = (b + ob) + e;
-      }
-      if (lane == 0) {
-        red[wave][j][0] = a;
-        red[wave][j][1] = b;
-      }
-    }
-  __syncthreads();
-  const int t = threadIdx.x;
-  if (t < nc) {
-    double a = red[0][t][0], b = red[0][t][1];
-    for (int w = 1; w < 4; ++w) {
-      double ns, e;
-      two_sum(a, red[w][t][0], ns, e);
-      a = ns;
-      b = (b + red[w][t][1]) + e;
-    }
-    if (t < 2) nll_parts[t] = a + b;
-    else fr.result[t - 1] = a + b;
-  }
-  __syncthreads();
-  if (t == 0) fr.result[0] = nll_parts[0] + nll_parts[1];
-}
-
-__global__ __launch_bounds__(kBlock) void k_reduce(const FitRec* __restrict__ fits, int n_slots) {
-  const FitRec& fr = fits[blockIdx.x];
-  if (!fr.active) return;
-  reduce_fit(fr, n_slots + 2, n_slots);
-}
-
-__global__ __launch_bounds__(kBlock) void k_reduce_one(const FitRec fr, int stride, int n_slots) {
-  reduce_fit(fr, stride, n_slots);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -759,17 +799,6 @@ hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const 
   if (kind_ept(kind) == kEptLight)
     return fp32 ? launch_b_light<float, kEptLight>(kind, a, grid, st) : launch_b_light<double, kEptLight>(kind, a, grid, st);
   return fp32 ? launch_b_heavy<float, kEptHeavy>(kind, a, grid, st) : launch_b_heavy<double, kEptHeavy>(kind, a, grid, st);
-}
-
-hipError_t launch_reduce_one(const FitRec& fr, int stride, int n_slots, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(kBlock), 0, st, fr, stride, n_slots);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, int n_slots, hipStream_t st) {
-  if (n_fits <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(n_fits), dim3(kBlock), 0, st, fits_dev, n_slots);
-  return hipGetLastError();
 }
 
 }  // namespace hf

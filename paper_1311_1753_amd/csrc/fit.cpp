@@ -4,6 +4,7 @@
 // the plain numerical path: central differences of nll_eval, 2 n_free extra
 // evaluations per gradient.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -106,5 +107,46 @@ extern "C" int fit(const pdf_graph* g, const dataset* d, const hf_fit_opts* opts
     return rc;
   } catch (const std::exception& ex) {
     return fail(HF_E_INVALID, std::string("fit: ") + ex.what());
+  }
+}
+
+extern "C" int hf_minimize(int32_t n, const hf_param* params, const double* x0, const hf_fit_opts* opts,
+                           double f_noise, hf_fg_fn fn, void* user, double* x_out, double* errors_out,
+                           double* cov_out, hf_fit_summary* summary) {
+  try {
+    if (n < 0 || n > kMaxPar || (n > 0 && !params) || !fn || !x_out)
+      return fail(HF_E_INVALID, "hf_minimize: bad argument");
+    std::vector<MinParam> ps;
+    std::vector<double> start(n);
+    for (int i = 0; i < n; ++i) {
+      const hf_param& p = params[i];
+      ps.push_back({p.init, p.step > 0 ? p.step : 0.1, p.lo, p.hi, p.fixed != 0});
+      start[i] = x0 ? x0[i] : p.init;
+      if (!std::isfinite(start[i])) return fail(HF_E_INVALID, "hf_minimize: start value not finite");
+    }
+    MinOptions mo = min_options(opts, HF_FP64);
+    if (f_noise > 0) mo.f_noise = f_noise;
+    Minimiser m;
+    m.start(ps, start.data(), mo);
+    std::vector<double> x(n), g(n);
+    while (m.ask(x)) {
+      double f = 0.0;
+      std::fill(g.begin(), g.end(), 0.0);
+      if (fn(x.data(), &f, g.data(), user) != 0) return fail(HF_E_INVALID, "hf_minimize: callback failed");
+      m.tell(f, g);
+    }
+    std::memcpy(x_out, m.x_best.data(), n * sizeof(double));
+    if (errors_out) std::memcpy(errors_out, m.err.data(), n * sizeof(double));
+    if (cov_out) std::memcpy(cov_out, m.cov.data(), (size_t)n * n * sizeof(double));
+    if (summary) {
+      summary->nll = m.f_best;
+      summary->edm = m.edm;
+      summary->n_iter = m.n_iter;
+      summary->n_eval = m.n_eval;
+      summary->status = status_code(m.status);
+    }
+    return status_code(m.status);
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("hf_minimize: ") + ex.what());
   }
 }

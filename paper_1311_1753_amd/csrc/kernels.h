@@ -27,8 +27,6 @@ inline int64_t kind_tile(int kind) { return (int64_t)kBlock * kind_ept(kind); }
 hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, int64_t n_tiles, hipStream_t st);
 hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,
                                const float* c32, int n_const, int grid, hipStream_t st);
-hipError_t launch_reduce_one(const FitRec& fr, int stride, int n_slots, hipStream_t st);
-hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, int n_slots, hipStream_t st);
 
 // Dalitz normalisation grid: M[w][p][q] for w in {I, Ibar, J} (n_mat of them),
 // complex, unscaled by the cell area.  `out_host` receives n_mat * na * na * 2

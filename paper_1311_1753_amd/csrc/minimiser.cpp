@@ -213,7 +213,9 @@ void Minimiser::begin_final() {
     const int j = free_[k];
     double s = sigma_ext(j);
     if (!(s > 0.0) || !std::isfinite(s)) s = ps_[j].step;
-    double h = 1e-3 * s;
+    // a tenth of the error: the NLL is close to quadratic over that range, and
+    // the step is large against rounding noise in the gradient
+    double h = 0.1 * s;
     h = std::max(h, 1e-12 * (std::fabs(x_best[j]) + 1.0));
     if (bounded(ps_[j])) h = std::min(h, 0.25 * std::min(x_best[j] - ps_[j].lo, ps_[j].hi - x_best[j]));
     hstep_[k] = h;
@@ -272,7 +274,15 @@ void Minimiser::tell(double f, const std::vector<double>& g) {
       std::vector<double> u(nf_), gu;
       for (int k = 0; k < nf_; ++k) u[k] = u0_[k] + alpha_ * p_[k];
       const double allow = o_.f_noise * (std::fabs(f0_) + 1.0);
-      const bool armijo = std::isfinite(f) && f <= f0_ + 1e-4 * alpha_ * slope0_ + allow;
+      bool armijo = std::isfinite(f) && f <= f0_ + 1e-4 * alpha_ * slope0_ + allow;
+      if (!armijo && std::isfinite(f) && f <= f0_ + 100.0 * allow) {
+        // f moved by no more than its rounding noise: judge the step by the
+        // gradient, with the quadratic-model change f(a) - f(0) = a (phi'(0) + phi'(a)) / 2
+        int_grad(u, g, gu);
+        double dnew = 0.0;
+        for (int k = 0; k < nf_; ++k) dnew += gu[k] * p_[k];
+        armijo = 0.5 * alpha_ * (slope0_ + dnew) <= 1e-4 * alpha_ * slope0_;
+      }
       if (!armijo) {
         alpha_hi_ = alpha_;
         if (++n_back_ > 40) {
@@ -357,7 +367,17 @@ void Minimiser::tell(double f, const std::vector<double>& g) {
     }
     case POLISH: {
       const double allow = o_.f_noise * (std::fabs(f_best) + 1.0);
-      if (std::isfinite(f) && f <= f_best + allow) {
+      bool ok = std::isfinite(f) && f <= f_best + allow;
+      if (!ok && std::isfinite(f) && f <= f_best + 100.0 * allow) {
+        // within the noise of f: trapezoid estimate of the change from the gradients
+        double d = 0.0;
+        for (int k = 0; k < nf_; ++k) {
+          const int j = free_[k];
+          d += 0.5 * (g[j] + gext_best_[j]) * (x_pend_[j] - x_best[j]);
+        }
+        ok = d <= 0.0;
+      }
+      if (ok) {
         x_best = x_pend_;
         f_best = f;
         gext_best_ = g;

@@ -443,7 +443,93 @@ __device__ __forceinline__ void tree_tile(const KProgram& P, const CS& cs, const
 // shape).  Fully static: the child kinds are wave-uniform branches, the
 // accumulators have a fixed layout [2 per child, then K-1 fractions] that the
 // host maps back to parameters.
-template <typename T, int EPT, int K, bool GRAD>
+template <typename T> struct Split;
+template <> struct Split<double> {
+  // double path: the location constant is used as is
+  double v;
+  __device__ __forceinline__ void set(double x) { v = x; }
+  __device__ __forceinline__ double add(double x) const { return x + v; }
+};
+template <> struct Split<float> {
+  // float path: the double location constant as a float pair hi + lo, so that
+  // (x + hi) + lo rounds like one addition of the double value (its rounding
+  // error varies from event to event instead of biasing all of them)
+  float hi, lo;
+  __device__ __forceinline__ void set(double x) {
+    hi = (float)x;
+    lo = (float)(x - (double)hi);
+  }
+  __device__ __forceinline__ float add(float x) const { return (x + hi) + lo; }
+};
+
+// Per-event body of a mixture tile.  MASK bit j set: child j is a Gaussian,
+// clear: an exponential (static, so no per-event branching on the kinds);
+// FULL: every event of the tile exists (no per-event bound checks).
+template <typename T, int EPT, int K, int MASK, bool GRAD, bool FULL>
+__device__ __forceinline__ void mix_events(const typename Col<T>::S* __restrict__ xp, int64_t base, int64_t n_events,
+                                           const Split<T>* loc, const T* k1, const T* lhi, const T* llo, const T* d0c,
+                                           const T* d1c, const T* fr, double& nll, T* gt) {
+  typedef typename Col<T>::S Sx;
+  Sx xv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    xv[e] = (FULL || i < n_events) ? xp[i] : Sx(0);
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int64_t i = base + (int64_t)e * kBlock;
+    if (!FULL && i >= n_events) break;
+    const T x = (T)xv[e];
+    T lv[K], d0[K], d1[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const T u = loc[j].add(x);
+      if ((MASK >> j) & 1) {
+        const T z = u * k1[j], zz = z * z;
+        lv[j] = (T(-0.5) * zz - lhi[j]) - llo[j];
+        d0[j] = z * k1[j] - d0c[j];
+        d1[j] = zz * k1[j] - d1c[j];
+      } else {
+        lv[j] = (k1[j] * u - lhi[j]) - llo[j];
+        d0[j] = u - d0c[j];
+      }
+    }
+    T ej[K], m;
+    if (K == 2) {
+      // the larger term has e = 1: one exponential per event
+      const T dd = lv[1] - lv[0];
+      const bool up = dd > T(0);
+      const T eo = Mth<T>::ex(up ? -dd : dd);
+      ej[0] = up ? eo : T(1);
+      ej[1] = up ? T(1) : eo;
+      m = up ? lv[1] : lv[0];
+    } else {
+      m = lv[0];
+#pragma unroll
+      for (int j = 1; j < K; ++j) m = lv[j] > m ? lv[j] : m;
+#pragma unroll
+      for (int j = 0; j < K; ++j) ej[j] = Mth<T>::ex(lv[j] - m);
+    }
+    T ssum = fr[0] * ej[0];
+#pragma unroll
+    for (int j = 1; j < K; ++j) ssum += fr[j] * ej[j];
+    const T v = ssum > T(0) ? m + Mth<T>::ln(ssum) : T(-INFINITY);
+    nll -= (double)v;
+    if (GRAD) {
+      const T is = Mth<T>::rcp(ssum);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const T r = fr[j] * ej[j] * is;
+        gt[2 * j] += r * d0[j];
+        if ((MASK >> j) & 1) gt[2 * j + 1] += r * d1[j];
+        if (j < K - 1) gt[2 * K + j] += (ej[j] - ej[K - 1]) * is;
+      }
+    }
+  }
+}
+
+template <typename T, int EPT, int K, int MASK, bool GRAD>
 __device__ __forceinline__ void mix_tile(const KProgram& P, const CS& cs, const void* const* cols, int64_t n_events,
                                          int64_t tile, double* __restrict__ out) {
   typedef typename Col<T>::S Sx;
@@ -451,76 +537,31 @@ __device__ __forceinline__ void mix_tile(const KProgram& P, const CS& cs, const 
   const int64_t base = tile * (int64_t)(kBlock * EPT) + threadIdx.x;
   // per-child constants, wave-uniform (constant layouts of EXP / GAUSS above)
   const KNode& rn = P.node[P.n_nodes - 1];
-  bool gs[K];
-  double loc[K];
+  Split<T> loc[K];
   T k1[K], lhi[K], llo[K], d0c[K], d1c[K], fr[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const KNode& cn = P.node[P.child[rn.child0 + j]];
-    const int c0 = cn.c0;
-    gs[j] = cn.op == OP_GAUSS;
-    loc[j] = cs.d[c0];
+    const int c0 = P.node[P.child[rn.child0 + j]].c0;
+    loc[j].set(cs.d[c0]);
     k1[j] = cs.get<T>(c0 + 1);
     lhi[j] = cs.get<T>(c0 + 2);
     llo[j] = cs.get<T>(c0 + 3);
     d0c[j] = cs.get<T>(c0 + 4);
-    d1c[j] = gs[j] ? cs.get<T>(c0 + 5) : T(0);
+    d1c[j] = ((MASK >> j) & 1) ? cs.get<T>(c0 + 5) : T(0);
     fr[j] = cs.get<T>(rn.c0 + j);
   }
   const Sx* xp = (const Sx*)cols[0];
-  Sx xv[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    xv[e] = i < n_events ? xp[i] : Sx(0);
-  }
   double nll = 0.0;
+  T gt[NA];  // per-thread partial sums over this thread's <= EPT events
+#pragma unroll
+  for (int j = 0; j < NA; ++j) gt[j] = T(0);
+  if (tile * (int64_t)(kBlock * EPT) + (int64_t)kBlock * EPT <= n_events)
+    mix_events<T, EPT, K, MASK, GRAD, true>(xp, base, n_events, loc, k1, lhi, llo, d0c, d1c, fr, nll, gt);
+  else
+    mix_events<T, EPT, K, MASK, GRAD, false>(xp, base, n_events, loc, k1, lhi, llo, d0c, d1c, fr, nll, gt);
   double g[NA];
 #pragma unroll
-  for (int j = 0; j < NA; ++j) g[j] = 0.0;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    if (i < n_events) {
-      const double x = (double)xv[e];
-      T lv[K], d0[K], d1[K];
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const T u = (T)(x + loc[j]);  // location difference formed in double
-        if (gs[j]) {
-          const T z = u * k1[j];
-          lv[j] = (T(-0.5) * z * z - lhi[j]) - llo[j];
-          d0[j] = z * k1[j] - d0c[j];
-          d1[j] = z * z * k1[j] - d1c[j];
-        } else {
-          lv[j] = (k1[j] * u - lhi[j]) - llo[j];
-          d0[j] = u - d0c[j];
-          d1[j] = T(0);
-        }
-      }
-      T m = lv[0];
-#pragma unroll
-      for (int j = 1; j < K; ++j) m = lv[j] > m ? lv[j] : m;
-      T ej[K], ssum = T(0);
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        ej[j] = Mth<T>::ex(lv[j] - m);
-        ssum += fr[j] * ej[j];
-      }
-      const T v = ssum > T(0) ? m + Mth<T>::ln(ssum) : T(-INFINITY);
-      nll -= (double)v;
-      if (GRAD) {
-        const T is = Mth<T>::rcp(ssum);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const T r = fr[j] * ej[j] * is;
-          g[2 * j] += (double)(r * d0[j]);
-          g[2 * j + 1] += (double)(r * d1[j]);
-          if (j < K - 1) g[2 * K + j] += (double)((ej[j] - ej[K - 1]) * is);
-        }
-      }
-    }
-  }
+  for (int j = 0; j < NA; ++j) g[j] = (double)gt[j];
   tile_store<NA>(NeuAcc{nll, 0.0}, g, GRAD ? NA : 0, out);
 }
 
@@ -637,10 +678,11 @@ __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
-template <typename T, int EPT, int K, bool GRAD>
+template <typename T, int EPT, int K, int MASK, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
-  mix_tile<T, EPT, K, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x, a.partials + (int64_t)blockIdx.x * a.stride);
+  mix_tile<T, EPT, K, MASK, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x,
+                                  a.partials + (int64_t)blockIdx.x * a.stride);
   tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
@@ -683,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_batched(const BatchArgs a) {  /
   }
 }
 
-template <typename T, int EPT, int K>
+template <typename T, int EPT, int K, int MASK>
 __global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
   const int tpb = a.hdr->tiles_per_block, total = a.hdr->total_tiles, n_fits = a.hdr->n_fits;
   const FitRec* fits = (const FitRec*)(a.hdr + 1);
@@ -696,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
     const FitRec& fr = fits[f];
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
     const int64_t lt = gt - fr.tile_begin;
-    mix_tile<T, EPT, K, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
+    mix_tile<T, EPT, K, MASK, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
     tile_done(fr, lt, a.prog.n_slots + 2, a.prog.n_slots);
   }
 }
@@ -727,8 +769,13 @@ static hipError_t launch_light(int kind, const EvalArgs& a, int64_t n_tiles, hip
     case KIND_EXP: hipLaunchKernelGGL((k_leaf<T, OP_EXP, EPT, GRAD>), grid, block, 0, st, a); break;
     case KIND_GAUSS: hipLaunchKernelGGL((k_leaf<T, OP_GAUSS, EPT, GRAD>), grid, block, 0, st, a); break;
     case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree<T, EPT, 8, 2, false, GRAD>), grid, block, 0, st, a); break;
-    case KIND_MIX2: hipLaunchKernelGGL((k_mix<T, EPT, 2, GRAD>), grid, block, 0, st, a); break;
-    case KIND_MIX3: hipLaunchKernelGGL((k_mix<T, EPT, 3, GRAD>), grid, block, 0, st, a); break;
+#define HF_MIX(K_, M_)                                                                              \
+  case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
+    hipLaunchKernelGGL((k_mix<T, EPT, K_, M_, GRAD>), grid, block, 0, st, a);                       \
+    break;
+    HF_MIX(2, 0) HF_MIX(2, 1) HF_MIX(2, 2) HF_MIX(2, 3)
+    HF_MIX(3, 0) HF_MIX(3, 1) HF_MIX(3, 2) HF_MIX(3, 3) HF_MIX(3, 4) HF_MIX(3, 5) HF_MIX(3, 6) HF_MIX(3, 7)
+#undef HF_MIX
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -753,8 +800,9 @@ static hipError_t launch_any(int kind, const EvalArgs& a, int64_t n_tiles, hipSt
 }
 
 int kind_ept(int kind) {
+  if (kind >= KIND_MIX2) return kEptLight;
   switch (kind) {
-    case KIND_EXP: case KIND_GAUSS: case KIND_TREE_SMALL: case KIND_MIX2: case KIND_MIX3: return kEptLight;
+    case KIND_EXP: case KIND_GAUSS: case KIND_TREE_SMALL: return kEptLight;
     default: return kEptHeavy;
   }
 }
@@ -771,8 +819,13 @@ static hipError_t launch_b_light(int kind, const BatchArgs& a, int grid, hipStre
     case KIND_EXP: hipLaunchKernelGGL((k_leaf_batched<T, OP_EXP, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case KIND_GAUSS: hipLaunchKernelGGL((k_leaf_batched<T, OP_GAUSS, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
     case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree_batched<T, EPT, 8, 2, false>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case KIND_MIX2: hipLaunchKernelGGL((k_mix_batched<T, EPT, 2>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case KIND_MIX3: hipLaunchKernelGGL((k_mix_batched<T, EPT, 3>), dim3(grid), dim3(kBlock), 0, st, a); break;
+#define HF_MIX(K_, M_)                                                                              \
+  case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
+    hipLaunchKernelGGL((k_mix_batched<T, EPT, K_, M_>), dim3(grid), dim3(kBlock), 0, st, a);        \
+    break;
+    HF_MIX(2, 0) HF_MIX(2, 1) HF_MIX(2, 2) HF_MIX(2, 3)
+    HF_MIX(3, 0) HF_MIX(3, 1) HF_MIX(3, 2) HF_MIX(3, 3) HF_MIX(3, 4) HF_MIX(3, 5) HF_MIX(3, 6) HF_MIX(3, 7)
+#undef HF_MIX
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -614,7 +614,10 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       for (int j = 0; j < K - 1; ++j) acc[2 * K + j] = rootn.par[j];
       g->slot_par = acc;
       P.n_slots = 3 * K - 1;
-      g->kind = K == 2 ? KIND_MIX2 : KIND_MIX3;
+      int mask = 0;
+      for (int j = 0; j < K; ++j)
+        if (g->nodes[rootn.child[j]].op == OP_GAUSS) mask |= 1 << j;
+      g->kind = (K == 2 ? KIND_MIX2 : KIND_MIX3) + mask;
       *out = g.release();
       return HF_OK;
     }

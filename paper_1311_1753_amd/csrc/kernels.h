@@ -14,8 +14,10 @@ enum KernelKind {
   KIND_DALITZ = 3,      // single DALITZ leaf
   KIND_TDDP = 4,        // single TDDP leaf
   KIND_TREE = 5,        // any tree
-  KIND_MIX2 = 6,        // root ADD of 2 single-column EXP/GAUSS leaves
-  KIND_MIX3 = 7         // root ADD of 3 single-column EXP/GAUSS leaves
+  // root ADD of 2 (3) single-column EXP/GAUSS leaves: KIND_MIX2 (KIND_MIX3)
+  // plus a mask with bit j set when child j is a GAUSS
+  KIND_MIX2 = 8,
+  KIND_MIX3 = 16
 };
 
 constexpr int kEptLight = 16;   // events per thread per tile, light kernels (tile 4096)

@@ -79,23 +79,32 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     for (int c = 0; c < kMaxCols; ++c) a.col[c] = d->col[c];
     a.n_events = d->n;
     a.partials = d->partials;
-    a.gpart = d->gpart;
-    a.counter = d->counter;
-    a.result = d->res_dev;
     a.stride = S + 2;
     a.n_tiles = (int32_t)d->n_tiles;
     const bool prof = g_prof.on;
     if (prof) hipEventRecord(g_prof.e[0], st);
-    // one launch: tiles, then the last tile's block reduces all rows in a fixed order
     hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, d->n_tiles, st);
-    if (prof) hipEventRecord(g_prof.e[1], st);
     if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
+    if (prof) hipEventRecord(g_prof.e[1], st);
+    FitRec fr;
+    std::memset(&fr, 0, sizeof(fr));
+    fr.partials = d->partials;
+    fr.n_tiles = (int32_t)d->n_tiles;
+    fr.result = d->res_dev;
+    fr.stride = S + 2;
+    fr.n_slots = want_grad ? S : 0;
+    fr.active = 1;
+    e = launch_reduce_one(fr, st);
+    if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
+    if (prof) hipEventRecord(g_prof.e[2], st);
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (prof) {
-      float t1 = 0.f;
+      float t1 = 0.f, t2 = 0.f;
       hipEventElapsedTime(&t1, g_prof.e[0], g_prof.e[1]);
+      hipEventElapsedTime(&t2, g_prof.e[1], g_prof.e[2]);
       g_prof.eval_ms += t1;
+      g_prof.reduce_ms += t2;
       g_prof.n += 1;
     }
     for (int j = 0; j < (want_grad ? S + 1 : 1); ++j) sums[j] = d->res_host[j];
@@ -163,10 +172,7 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
     d->n_tiles = (n + tile - 1) / tile;
     const size_t col_bytes = align256((size_t)n * es);
     const size_t part_bytes = align256((size_t)d->n_tiles * (g->prog.n_slots + 2) * sizeof(double));
-    const int64_t n_groups = (d->n_tiles + kGroup - 1) / kGroup;
-    const size_t gpart_bytes = align256((size_t)n_groups * (g->prog.n_slots + 2) * sizeof(double));
-    const size_t cnt_bytes = align256((size_t)(n_groups + 1) * sizeof(unsigned));
-    const size_t total = col_bytes * nc + part_bytes + gpart_bytes + cnt_bytes;
+    const size_t total = col_bytes * nc + part_bytes;
     void* blk = nullptr;
     hipError_t e = hipMalloc(&blk, total);
     if (e != hipSuccess) return fail(HF_E_OOM, std::string("dataset_upload: hipMalloc: ") + hipGetErrorString(e));
@@ -178,11 +184,7 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
       d->ref[c] = column_ref(g, c, prec);
     }
     d->partials = (double*)(base + nc * col_bytes);
-    d->gpart = (double*)(base + nc * col_bytes + part_bytes);
-    d->counter = (unsigned*)(base + nc * col_bytes + part_bytes + gpart_bytes);
-    e = hipMemsetAsync(d->counter, 0, cnt_bytes, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) { hipFree(blk); return hip_fail(e, "dataset_upload: counter"); }
+
     // convert through the pinned staging buffer, one chunk at a time
     if (n > 0) {
       std::lock_guard<std::mutex> lk(g_stage_mu);

@@ -1,11 +1,11 @@
 // Batched likelihood evaluations and the continuous-batching fit engine.
 //
 // All active fits of one graph are evaluated by one launch of the tile
-// kernel: each block walks a contiguous range of the concatenated tile list,
-// and the block that finishes a fit's last tile reduces that fit's rows.  The
-// host side of a step writes a fixed-size header, the per-fit records and the
-// per-fit constant tables into pinned memory; the device side -- three copies
-// and one kernel -- is captured once into a HIP graph and replayed every step, so its shape
+// kernel (each block walks a contiguous range of the concatenated tile list)
+// followed by one launch of the per-fit reduction.  The host side of a step
+// writes a fixed-size header, the per-fit records and the per-fit constant
+// tables into pinned memory; the device side -- three copies and two kernels
+// -- is captured once into a HIP graph and replayed every step, so its shape
 // never changes: fit counts and tile counts are read from the header in
 // device memory, the eval grid is fixed and surplus blocks exit at once.
 // Results are written by the reduction straight into mapped pinned memory.
@@ -83,6 +83,7 @@ static hipError_t enqueue_step(const pdf_graph* g, bool fp32, BatchTables& t, hi
     e = hipMemcpyAsync(t.c32_d, t.c32_h, (size_t)t.max_fits * t.n_const * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = launch_eval_batched(g->kind, fp32, g->prog, t.hdr_d, t.c64_d, t.c32_d, t.n_const, kBatchGrid, st);
+  if (e == hipSuccess) e = launch_reduce(t.fits_d(), t.max_fits, st);
   return e;
 }
 
@@ -101,8 +102,8 @@ static void fill_tables(const pdf_graph* g, BatchTables& t, const std::vector<co
       fr[i].tile_begin = tile;
       fr[i].n_tiles = (int32_t)ds[i]->n_tiles;
       fr[i].result = t.res_d + (size_t)i * (t.S + 1);
-      fr[i].gpart = ds[i]->gpart;
-      fr[i].counter = ds[i]->counter;
+      fr[i].stride = g->prog.n_slots + 2;
+      fr[i].n_slots = g->prog.n_slots;
       fr[i].active = 1;
       tile += (int)ds[i]->n_tiles;
       std::memcpy(t.c64_h + (size_t)i * t.n_const, sc[i]->prog.c64, g->n_const * sizeof(double));

@@ -566,108 +566,90 @@ __device__ __forceinline__ void mix_tile(const KProgram& P, const CS& cs, const 
 }
 
 // ------------------------------------------------------------------ reduction
-// Deterministic reduction of the tile rows of one fit, done inside the
-// likelihood launch.  Tiles form groups of kGroup consecutive tiles; the block
-// that finishes the last tile of a group sums that group's rows in order into
-// a group row, and the block that finishes the last group sums the group rows
-// in order into the result [nll, slot_0 .. slot_{S-1}].  Each column is a
-// two-sum compensated sum; the NLL is the sum of its value and compensation
-// columns.  Counters are re-armed by the blocks that consume them.  The
-// fences order each block's row stores before its counter update (release)
-// and the counter before the consumer's loads (acquire), across the XCDs'
-// separate L2 caches.
+// Second launch: one 1024-thread block per fit sums that fit's tile rows in a
+// fixed order.  Wave w of the 16 works on column w % nc (several waves per
+// column when there are fewer than 16 columns, each on a fixed contiguous
+// slice of the rows); a lane takes rows lane, lane + 64, ... of its slice with
+// 16 loads in flight, two-sum compensated; then a wave64 butterfly and a
+// fixed-order merge of the slices of each column.  The NLL is the sum of its
+// value and compensation columns.  Result: [nll, slot_0 .. slot_{S-1}].
+constexpr int kRedBlock = 1024;
+constexpr int kRedWaves = kRedBlock / 64;
 constexpr int kMaxRedCols = kMaxSlots + 2;
 
-__device__ __forceinline__ void reduce_rows(const double* rows, int n_rows, int stride, int n_slots, double* dst,
-                                            bool final_row) {
-  __shared__ double buf[kGroup][kMaxRedCols];
+__device__ __forceinline__ void reduce_fit(const FitRec& fr, int stride, int n_slots) {
+  const int nc = n_slots + 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int per_col = nc >= kRedWaves ? 1 : kRedWaves / nc;  // waves per column
+  __shared__ double part[kRedWaves][2];
+  __shared__ double colsum[kMaxRedCols][kRedWaves][2];
   __shared__ double nll_parts[2];
-  const int nc = n_slots + 2, t = threadIdx.x;
-  double s = 0.0, c = 0.0;
-  for (int r0 = 0; r0 < n_rows; r0 += kGroup) {
-    const int m = min(kGroup, n_rows - r0);
-    for (int idx = t; idx < m * nc; idx += kBlock) {
-      const int r = idx / nc, j = idx - r * nc;
-      buf[r][j] = rows[(int64_t)(r0 + r) * stride + j];
-    }
-    __syncthreads();
-    if (t < nc)
-      for (int r = 0; r < m; ++r) {
+  // column pass: wave w handles (column, slice) pairs w, w + 16, ...
+  for (int task = wave; task < nc * per_col; task += kRedWaves) {
+    const int col = task / per_col, slice = task % per_col;
+    const int r_begin = (int)((int64_t)fr.n_tiles * slice / per_col);
+    const int r_end = (int)((int64_t)fr.n_tiles * (slice + 1) / per_col);
+    double s = 0.0, c = 0.0;
+    for (int r0 = r_begin; r0 < r_end; r0 += 64 * 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int r = r0 + u * 64 + lane;
+        v[u] = r < r_end ? fr.partials[(int64_t)r * stride + col] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
         double ns, e;
-        two_sum(s, buf[r][t], ns, e);
+        two_sum(s, v[u], ns, e);
         s = ns;
         c += e;
       }
-    __syncthreads();
-  }
-  if (!final_row) {
-    if (t < nc) dst[t] = s + c;
-    return;
-  }
-  if (t < nc) {
-    if (t < 2) nll_parts[t] = s + c;
-    else dst[t - 1] = s + c;
-  }
-  __syncthreads();
-  if (t == 0) dst[0] = nll_parts[0] + nll_parts[1];
-}
-
-// Called by every block after it stored the row of tile `tile` of a fit.
-// Every thread fences its own stores before the block's counter update and
-// after learning that its block consumes the rows.
-__device__ __forceinline__ void tile_done(const FitRec& fr, int64_t tile, int stride, int n_slots) {
-  __shared__ int last_group, last_all;
-  const int n_groups = (fr.n_tiles + kGroup - 1) / kGroup;
-  const int grp = (int)(tile / kGroup);
-  const int in_grp = min(kGroup, fr.n_tiles - grp * kGroup);
-  unsigned* gcount = fr.counter;
-  unsigned* fcount = fr.counter + n_groups;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last_group = atomicAdd(&gcount[grp], 1u) == (unsigned)(in_grp - 1);
-  __syncthreads();
-  if (last_group) {
-    __threadfence();
-    const double* rows = fr.partials + (int64_t)grp * kGroup * stride;
-    if (n_groups == 1) {
-      reduce_rows(rows, in_grp, stride, n_slots, fr.result, true);
-      if (threadIdx.x == 0) atomicExch(&gcount[grp], 0u);
-    } else {
-      reduce_rows(rows, in_grp, stride, n_slots, fr.gpart + (int64_t)grp * stride, false);
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        atomicExch(&gcount[grp], 0u);
-        last_all = atomicAdd(fcount, 1u) == (unsigned)(n_groups - 1);
-      }
-      __syncthreads();
-      if (last_all) {
-        __threadfence();
-        reduce_rows(fr.gpart, n_groups, stride, n_slots, fr.result, true);
-        if (threadIdx.x == 0) atomicExch(fcount, 0u);
-      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double os = __shfl_xor(s, off, 64), oc = __shfl_xor(c, off, 64);
+      double ns, e;
+      two_sum(s, os, ns, e);
+      s = ns;
+      c = (c + oc) + e;
+    }
+    if (lane == 0) {
+      colsum[col][slice][0] = s;
+      colsum[col][slice][1] = c;
     }
   }
   __syncthreads();
+  const int t = threadIdx.x;
+  if (t < nc) {
+    double s = colsum[t][0][0], c = colsum[t][0][1];
+    for (int k = 1; k < per_col; ++k) {
+      double ns, e;
+      two_sum(s, colsum[t][k][0], ns, e);
+      s = ns;
+      c = (c + colsum[t][k][1]) + e;
+    }
+    if (t < 2) nll_parts[t] = s + c;
+    else fr.result[t - 1] = s + c;
+  }
+  __syncthreads();
+  if (t == 0) fr.result[0] = nll_parts[0] + nll_parts[1];
+  (void)part;
 }
+
+__global__ __launch_bounds__(kRedBlock) void k_reduce(const FitRec* __restrict__ fits, int n_fits_max) {
+  const FitRec& fr = fits[blockIdx.x];
+  if (!fr.active) return;
+  reduce_fit(fr, fr.stride, fr.n_slots);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_reduce_one(const FitRec fr) { reduce_fit(fr, fr.stride, fr.n_slots); }
 
 // ------------------------------------------------------------------ kernels
-__device__ __forceinline__ FitRec single_rec(const EvalArgs& a) {
-  FitRec fr;
-  fr.partials = a.partials;
-  fr.gpart = a.gpart;
-  fr.n_tiles = a.n_tiles;
-  fr.result = a.result;
-  fr.counter = a.counter;
-  return fr;
-}
-
 template <typename T, int OP, int EPT, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_leaf(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   leaf_tile<T, OP, EPT, GRAD>(a.prog.node[0], cs, a.col, a.n_events, blockIdx.x, a.prog.n_slots,
                         a.partials + (int64_t)blockIdx.x * a.stride);
-  tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
 template <typename T, int EPT, int NS, int NCOL, bool HEAVY, bool GRAD>
@@ -675,7 +657,6 @@ __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   tree_tile<T, EPT, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x,
                               a.partials + (int64_t)blockIdx.x * a.stride);
-  tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
 template <typename T, int EPT, int K, int MASK, bool GRAD>
@@ -683,7 +664,6 @@ __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   mix_tile<T, EPT, K, MASK, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x,
                                   a.partials + (int64_t)blockIdx.x * a.stride);
-  tile_done(single_rec(a), blockIdx.x, a.stride, GRAD ? a.prog.n_slots : 0);
 }
 
 // Batched: the program structure is shared (kernel argument); constants,
@@ -721,7 +701,6 @@ __global__ __launch_bounds__(kBlock) void k_leaf_batched(const BatchArgs a) {  /
     const int64_t lt = gt - fr.tile_begin;
     leaf_tile<T, OP, EPT, true>(a.prog.node[0], cs, fr.col, fr.n_events, lt, a.prog.n_slots,
                           fr.partials + lt * (a.prog.n_slots + 2));
-    tile_done(fr, lt, a.prog.n_slots + 2, a.prog.n_slots);
   }
 }
 
@@ -739,7 +718,6 @@ __global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
     const int64_t lt = gt - fr.tile_begin;
     mix_tile<T, EPT, K, MASK, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
-    tile_done(fr, lt, a.prog.n_slots + 2, a.prog.n_slots);
   }
 }
 
@@ -757,7 +735,6 @@ __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
     const int64_t lt = gt - fr.tile_begin;
     tree_tile<T, EPT, NS, NCOL, HEAVY, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
-    tile_done(fr, lt, a.prog.n_slots + 2, a.prog.n_slots);
   }
 }
 
@@ -852,6 +829,17 @@ hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const 
   if (kind_ept(kind) == kEptLight)
     return fp32 ? launch_b_light<float, kEptLight>(kind, a, grid, st) : launch_b_light<double, kEptLight>(kind, a, grid, st);
   return fp32 ? launch_b_heavy<float, kEptHeavy>(kind, a, grid, st) : launch_b_heavy<double, kEptHeavy>(kind, a, grid, st);
+}
+
+hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(kRedBlock), 0, st, fr);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, hipStream_t st) {
+  if (n_fits <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(n_fits), dim3(kRedBlock), 0, st, fits_dev, n_fits);
+  return hipGetLastError();
 }
 
 }  // namespace hf

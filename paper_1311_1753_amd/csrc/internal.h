@@ -22,7 +22,6 @@ constexpr int kMaxSlots = 32;
 constexpr int kMaxConst = 176;
 constexpr int kMaxRes = 8;
 constexpr int kMaxPar = 64;
-constexpr int kGroup = 64;           // tiles per first-level reduction group
 
 enum Op : int16_t {
   OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7
@@ -77,9 +76,6 @@ struct EvalArgs {
   const void* col[kMaxCols];   // device columns (double or float)
   int64_t n_events;
   double* partials;            // [n_tiles][stride]: nll_sum, nll_comp, slot sums
-  double* gpart;               // [n_groups][stride]: group sums
-  unsigned* counter;           // [n_groups] tiles finished per group, then 1 for the groups (0 between launches)
-  double* result;              // n_slots + 1 reduced values (mapped host memory)
   int32_t stride;              // n_slots + 2
   int32_t n_tiles;
 };
@@ -97,8 +93,8 @@ struct FitRec {
   int32_t tile_begin;          // first global tile of this fit
   int32_t n_tiles;
   double* result;              // n_slots + 1 doubles
-  double* gpart;               // group rows of this fit
-  unsigned* counter;           // group counters of this fit, then its final counter
+  int32_t stride;              // row stride of partials (n_slots + 2 of the graph)
+  int32_t n_slots;             // slot columns to reduce (0: NLL only)
   int32_t active;
   int32_t pad;
 };

@@ -27,6 +27,8 @@ int kind_ept(int kind);
 inline int64_t kind_tile(int kind) { return (int64_t)kBlock * kind_ept(kind); }
 
 hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, int64_t n_tiles, hipStream_t st);
+hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st);
+hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, hipStream_t st);
 hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,
                                const float* c32, int n_const, int grid, hipStream_t st);
 

@@ -107,6 +107,7 @@ void Minimiser::start(const std::vector<MinParam>& ps, const double* x0, const M
   n_iter = n_eval = 0;
   n_fail_ = 0;
   polish_ = 0;
+  edm_polish_ = INFINITY;
   f_best = 0.0;
   edm = 0.0;
 }
@@ -402,11 +403,18 @@ void Minimiser::start_polish() {
     for (int b = 0; b < nf_; ++b) step[a] += Cfree_[a * nf_ + b] * gext_best_[free_[b]];
     e += 0.5 * gext_best_[free_[a]] * step[a];
   }
+  const double prev = edm_polish_;
   edm = e;
-  if (edm < o_.edm_tol || polish_ >= 3) {
+  edm_polish_ = e;
+  // Newton steps with the exact Hessian shrink the EDM quadratically; when a
+  // step no longer does, the gradient is at its rounding-noise floor and the
+  // point is as good as the evaluation allows (accepted if within ~5e-4 sigma)
+  const bool floor = polish_ >= 1 && e > 0.25 * prev && e < 1e-7;
+  if (edm < o_.edm_tol || floor || polish_ >= 3) {
     int st = status;
-    if (st == RUNNING) st = edm < 10.0 * o_.edm_tol ? CONVERGED : MAX_ITER;
-    else if (st == MAX_ITER && edm < o_.edm_tol) st = CONVERGED;
+    const bool ok = edm < 10.0 * o_.edm_tol || floor;
+    if (st == RUNNING) st = ok ? CONVERGED : MAX_ITER;
+    else if (st == MAX_ITER && ok) st = CONVERGED;
     finish(st);
     return;
   }

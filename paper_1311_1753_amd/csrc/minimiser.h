@@ -67,6 +67,7 @@ class Minimiser {
   std::vector<double> hstep_, Hcols_, gplus_;
   std::vector<double> x_pend_;       // point handed out by ask()
   int polish_ = 0;
+  double edm_polish_ = 0.0;          // EDM before the last Newton polish
   std::vector<double> Hext_;         // final external Hessian (free parameters)
   std::vector<double> Cfree_;        // its inverse
   std::vector<double> gext_best_;    // gradient at x_best (external)

@@ -79,8 +79,6 @@ struct dataset {
   const void* col[hf::kMaxCols] = {nullptr};
   double ref[hf::kMaxCols] = {0.0};           // per-column reference (float path)
   double* partials = nullptr;
-  double* gpart = nullptr;                    // group rows of the in-launch reduction
-  unsigned* counter = nullptr;                // group counters, then the final counter
   int64_t n_tiles = 0;
   int64_t bytes = 0;
   double* res_host = nullptr;                 // pinned, device-mapped result row

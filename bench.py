@@ -183,7 +183,7 @@ def other_workload(args, P, S, torch, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1311_1753_amd as P
@@ -287,7 +287,7 @@ def main():
                    "n_events": n, "n_free_params": n_free},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_mix<float,16,2,true>", "kernel_ms": k_ms,
+                     "kernel": "k_mix<float,16,2,1,true>", "kernel_ms": k_ms,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "extra": extra,

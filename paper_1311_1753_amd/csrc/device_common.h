@@ -63,73 +63,104 @@ template <typename T> __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
-// sqrt(B_J^2) * BW(sAB) for one resonance; `d` = m0^2 - sAB formed in double.
+// Kinematic quantities of one daughter pair at one point; they depend only on
+// the pair's masses, so resonances in the same pair share them.  sAB, sAC,
+// sBC are double; differences of invariants are formed in double.
+template <typename T> struct Chan {
+  double sABd;
+  T inv_s, rs, q2, q, z1, z2;
+};
+
 template <typename T>
-__device__ __forceinline__ Cx<T> res_line(const CS& cs, int rb, int J, T sAB, T d) {
-  const T thrP = cs.get<T>(rb + kResThrP), thrM = cs.get<T>(rb + kResThrM);
-  const T inv_s = Mth<T>::rcp(sAB);
-  T q2 = (sAB - thrP) * (sAB - thrM) * (T(0.25) * inv_s);
-  q2 = q2 > T(0) ? q2 : T(0);
-  const T q = Mth<T>::sqrt(q2);
-  const T z = cs.get<T>(rb + kResR2) * q2;
-  T B2 = T(1), qp = q;
-  if (J == 1) {
-    B2 = cs.get<T>(rb + kResBnum) * Mth<T>::rcp(T(1) + z);
-    qp = q * q2;
-  } else if (J == 2) {
-    B2 = cs.get<T>(rb + kResBnum) * Mth<T>::rcp(z * z + T(3) * z + T(9));
-    qp = q * q2 * q2;
-  }
-  const T mg = cs.get<T>(rb + kResKw) * qp * B2 * Mth<T>::rsqrt(sAB);  // m0 Gamma(s)
-  const T den = Mth<T>::rcp(d * d + mg * mg);
-  const T sb = J == 0 ? T(1) : Mth<T>::sqrt(B2);
-  return {sb * d * den, sb * mg * den};
+__device__ __forceinline__ Chan<T> chan_eval(const CS& cs, int cb, double sAB, double sAC, double sBC) {
+  Chan<T> c;
+  c.sABd = sAB;
+  const T s = (T)sAB;
+  c.inv_s = Mth<T>::rcp(s);
+  c.rs = Mth<T>::rsqrt(s);
+  T q2 = (s - cs.get<T>(cb + kChThrP)) * (s - cs.get<T>(cb + kChThrM)) * (T(0.25) * c.inv_s);
+  c.q2 = q2 > T(0) ? q2 : T(0);
+  c.q = Mth<T>::sqrt(c.q2);
+  // Zemach factors: Z_1 = s_AC - s_BC + (M^2 - m_C^2)(m_B^2 - m_A^2)/s_AB,
+  // Z_2 = Z_1^2 - (s_AB - 2M^2 - 2m_C^2 + (M^2-m_C^2)^2/s_AB)(s_AB - 2m_A^2 - 2m_B^2 + (m_A^2-m_B^2)^2/s_AB)/3
+  c.z1 = (T)(sAC - sBC) + cs.get<T>(cb + kChZc1) * c.inv_s;
+  const T ta = s - cs.get<T>(cb + kChZtaC) + cs.get<T>(cb + kChZtaD) * c.inv_s;
+  const T tb = s - cs.get<T>(cb + kChZtbC) + cs.get<T>(cb + kChZtbD) * c.inv_s;
+  c.z2 = c.z1 * c.z1 - ta * tb * T(1.0 / 3.0);
+  return c;
 }
 
-// Zemach spin factor; `diff` = sAC - sBC formed in double.
+// Zemach factor for the swapped point of a pi pi channel (s_AC <-> s_BC).
 template <typename T>
-__device__ __forceinline__ T zemach(const CS& cs, int rb, int J, T sAB, T diff) {
-  if (J == 0) return T(1);
-  const T inv_s = Mth<T>::rcp(sAB);
-  const T z1 = diff + cs.get<T>(rb + kResZc1) * inv_s;
-  if (J == 1) return z1;
-  const T ta = sAB - cs.get<T>(rb + kResZtaC) + cs.get<T>(rb + kResZtaD) * inv_s;
-  const T tb = sAB - cs.get<T>(rb + kResZtbC) + cs.get<T>(rb + kResZtbD) * inv_s;
-  return z1 * z1 - ta * tb * T(1.0 / 3.0);
+__device__ __forceinline__ Chan<T> chan_swap_ac_bc(const CS& cs, int cb, const Chan<T>& c, double sAC, double sBC) {
+  Chan<T> d = c;
+  d.z1 = (T)(sBC - sAC) + cs.get<T>(cb + kChZc1) * c.inv_s;
+  const T s = (T)c.sABd;
+  const T ta = s - cs.get<T>(cb + kChZtaC) + cs.get<T>(cb + kChZtaD) * c.inv_s;
+  const T tb = s - cs.get<T>(cb + kChZtbC) + cs.get<T>(cb + kChZtbD) * c.inv_s;
+  d.z2 = d.z1 * d.z1 - ta * tb * T(1.0 / 3.0);
+  return d;
+}
+
+// Resonance amplitude B_J(q) Z_J BW(s_AB) with the mass-dependent width
+// m0 Gamma(s) = Kw q^{2J+1} B_J^2 / sqrt(s), BW = 1/(m0^2 - s - i m0 Gamma);
+// m0^2 - s is formed in double.
+template <typename T>
+__device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, int J, const Chan<T>& c) {
+  const T d = (T)(cs.d[rb + kResM02] - c.sABd);
+  T B = T(1), qp = c.q, Z = T(1);
+  if (J == 1) {
+    B = cs.get<T>(rb + kResSqB) * Mth<T>::rsqrt(T(1) + cs.get<T>(rb + kResR2) * c.q2);
+    qp = c.q * c.q2;
+    Z = c.z1;
+  } else if (J == 2) {
+    const T z = cs.get<T>(rb + kResR2) * c.q2;
+    B = cs.get<T>(rb + kResSqB) * Mth<T>::rsqrt(z * z + T(3) * z + T(9));
+    qp = c.q * c.q2 * c.q2;
+    Z = c.z2;
+  }
+  const T mg = cs.get<T>(rb + kResKw) * qp * (B * B) * c.rs;  // m0 Gamma(s)
+  const T den = Mth<T>::rcp(d * d + mg * mg);
+  const T f = B * Z * den;
+  return {f * d, f * mg};
 }
 
 // Amplitudes A_k(s12, s13) (and, for TDDP, Abar_k = A_k(s13, s12)) of all
-// resonances at one point; s12/s13/s23 in double.
+// resonances at one point; s12/s13/s23 in double.  Pair quantities are
+// evaluated once per pair (and, for the conjugate amplitudes, once per
+// swapped pair); when m2 == m3 (SYM) the swapped 12 pair equals the 13 pair
+// and vice versa.
 template <typename T, bool TD>
 __device__ __forceinline__ void dalitz_amps(const CS& cs, int c0, int R, double s12, double s13, double s23,
                                             Cx<T>* A, Cx<T>* Ab) {
-  const int rbase = c0 + dz_res_base(R, TD);
+  const int chb = c0 + dz_ch_base(R, TD), rbase = c0 + dz_res_base(R, TD);
+  // pair (A, B; C): 12 = (1, 2; 3), 13 = (1, 3; 2), 23 = (2, 3; 1)
+  const Chan<T> c12 = chan_eval<T>(cs, chb, s12, s13, s23);
+  const Chan<T> c13 = chan_eval<T>(cs, chb + kChStride, s13, s12, s23);
+  const Chan<T> c23 = chan_eval<T>(cs, chb + 2 * kChStride, s23, s12, s13);
+  Chan<T> b12 = c13, b13 = c12, b23 = c23;
+  if (TD) {
+    // equal pair constants (m2 == m3) give bitwise equal pair quantities
+    bool sym = true;
+#pragma unroll
+    for (int i = 0; i < kChStride; ++i) sym = sym && cs.d[chb + i] == cs.d[chb + kChStride + i];
+    if (!sym) {
+      b12 = chan_eval<T>(cs, chb, s13, s12, s23);
+      b13 = chan_eval<T>(cs, chb + kChStride, s12, s13, s23);
+    }
+    b23 = chan_swap_ac_bc<T>(cs, chb + 2 * kChStride, c23, s12, s13);
+  }
 #pragma unroll
   for (int k = 0; k < kMaxRes; ++k) {
     if (k < R) {
       const int rb = rbase + k * kResStride;
       const int ch = (int)cs.d[rb + kResCh];
       const int J = (int)cs.d[rb + kResJ];
-      const double m02 = cs.d[rb + kResM02];
-      // (sAB, sAC, sBC) for A; the swapped point for Abar
-      double ab, ac, bc;
-      if (ch == 23) { ab = s23; ac = s12; bc = s13; }
-      else if (ch == 12) { ab = s12; ac = s13; bc = s23; }
-      else { ab = s13; ac = s12; bc = s23; }
-      const T sAB = (T)ab;
-      const Cx<T> L = res_line<T>(cs, rb, J, sAB, (T)(m02 - ab));
-      const T Z = zemach<T>(cs, rb, J, sAB, (T)(ac - bc));
-      A[k] = {L.re * Z, L.im * Z};
+      const Chan<T>& c = ch == 0 ? c12 : (ch == 1 ? c13 : c23);
+      A[k] = res_amp<T>(cs, rb, J, c);
       if (TD) {
-        double ab2, ac2, bc2;
-        if (ch == 23) { ab2 = s23; ac2 = s13; bc2 = s12; }
-        else if (ch == 12) { ab2 = s13; ac2 = s12; bc2 = s23; }
-        else { ab2 = s12; ac2 = s13; bc2 = s23; }
-        Cx<T> L2 = L;
-        const T sAB2 = (T)ab2;
-        if (ch != 23) L2 = res_line<T>(cs, rb, J, sAB2, (T)(m02 - ab2));
-        const T Z2 = zemach<T>(cs, rb, J, sAB2, (T)(ac2 - bc2));
-        Ab[k] = {L2.re * Z2, L2.im * Z2};
+        const Chan<T>& b = ch == 0 ? b12 : (ch == 1 ? b13 : b23);
+        Ab[k] = res_amp<T>(cs, rb, J, b);
       }
     }
   }

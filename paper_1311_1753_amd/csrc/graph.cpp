@@ -21,6 +21,14 @@
 
 namespace hf {
 
+// Masses (A, B; spectator C) of daughter pair c: 0 = 12, 1 = 13, 2 = 23.
+static void pair_masses(const DalitzInfo& dz, int c, double& mA, double& mB, double& mC) {
+  if (c == 0) { mA = dz.m1; mB = dz.m2; mC = dz.m3; }
+  else if (c == 1) { mA = dz.m1; mB = dz.m3; mC = dz.m2; }
+  else { mA = dz.m2; mB = dz.m3; mC = dz.m1; }
+}
+
+
 namespace {
 
 thread_local std::string g_err;
@@ -564,13 +572,26 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       auto setc = [&](int i, double v) { P.c64[i] = v; P.c32[i] = (float)v; };
       const double M2 = dz.M * dz.M;
       setc(c0 + kDzSsum, M2 + dz.m1 * dz.m1 + dz.m2 * dz.m2 + dz.m3 * dz.m3);
+      // pair constants: 12 = (m1, m2; spectator m3), 13 = (m1, m3; m2), 23 = (m2, m3; m1)
+      const int chb = c0 + dz_ch_base(R, dz.tddp);
+      for (int c = 0; c < kNumCh; ++c) {
+        double mA, mB, mC;
+        pair_masses(dz, c, mA, mB, mC);
+        const int cb = chb + c * kChStride;
+        setc(cb + kChThrP, (mA + mB) * (mA + mB));
+        setc(cb + kChThrM, (mA - mB) * (mA - mB));
+        setc(cb + kChZc1, (M2 - mC * mC) * (mB * mB - mA * mA));
+        setc(cb + kChZtaC, 2.0 * M2 + 2.0 * mC * mC);
+        setc(cb + kChZtaD, (M2 - mC * mC) * (M2 - mC * mC));
+        setc(cb + kChZtbC, 2.0 * mA * mA + 2.0 * mB * mB);
+        setc(cb + kChZtbD, (mA * mA - mB * mB) * (mA * mA - mB * mB));
+      }
       const int rbase = c0 + dz_res_base(R, dz.tddp);
       for (int j = 0; j < R; ++j) {
         const ResInfo& r = dz.res[j];
+        const int c = r.ch == 12 ? 0 : (r.ch == 13 ? 1 : 2);
         double mA, mB, mC;
-        if (r.ch == 23) { mA = dz.m2; mB = dz.m3; mC = dz.m1; }
-        else if (r.ch == 12) { mA = dz.m1; mB = dz.m2; mC = dz.m3; }
-        else { mA = dz.m1; mB = dz.m3; mC = dz.m2; }
+        pair_masses(dz, c, mA, mB, mC);
         const int rb = rbase + j * kResStride;
         const double m02 = r.m0 * r.m0;
         const double thrP = (mA + mB) * (mA + mB), thrM = (mA - mB) * (mA - mB);
@@ -582,16 +603,9 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
         if (r.J == 2) bnum = z0 * z0 + 3.0 * z0 + 9.0;
         setc(rb + kResM02, m02);
         setc(rb + kResKw, m02 * r.g0 / std::pow(q0, 2 * r.J + 1));
-        setc(rb + kResBnum, bnum);
+        setc(rb + kResSqB, std::sqrt(bnum));
         setc(rb + kResR2, dz.r * dz.r);
-        setc(rb + kResThrP, thrP);
-        setc(rb + kResThrM, thrM);
-        setc(rb + kResZc1, (M2 - mC * mC) * (mB * mB - mA * mA));
-        setc(rb + kResZtaC, 2.0 * M2 + 2.0 * mC * mC);
-        setc(rb + kResZtaD, (M2 - mC * mC) * (M2 - mC * mC));
-        setc(rb + kResZtbC, 2.0 * mA * mA + 2.0 * mB * mB);
-        setc(rb + kResZtbD, (mA * mA - mB * mB) * (mA * mA - mB * mB));
-        setc(rb + kResCh, r.ch);
+        setc(rb + kResCh, c);
         setc(rb + kResJ, r.J);
       }
     }

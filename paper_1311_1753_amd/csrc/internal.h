@@ -56,16 +56,19 @@ struct KProgram {
 // For the float path lnN is split into a float pair (hi + lo) so that the
 // rounding of the constant does not bias every event in the same direction.
 constexpr int kDzRef12 = 0, kDzRef13 = 1, kDzSsum = 2, kDzLnHi = 3, kDzLnLo = 4, kDzDln = 5;
-// per resonance block (stride kResStride) after the 2R (+2 for TDDP) dlnN entries
-constexpr int kResM02 = 0, kResKw = 1, kResBnum = 2, kResR2 = 3, kResThrP = 4, kResThrM = 5,
-              kResZc1 = 6, kResZtaC = 7, kResZtaD = 8, kResZtbC = 9, kResZtbD = 10, kResCh = 11,
-              kResJ = 12, kResStride = 13;
+// channel blocks (pairs 12, 13, 23 in that order) after the 2R (+2 for TDDP)
+// dlnN entries: constants that depend only on the pair's masses
+constexpr int kChThrP = 0, kChThrM = 1, kChZc1 = 2, kChZtaC = 3, kChZtaD = 4, kChZtbC = 5, kChZtbD = 6,
+              kChStride = 7, kNumCh = 3;
+// per resonance block (stride kResStride) after the channel blocks
+constexpr int kResM02 = 0, kResKw = 1, kResSqB = 2, kResR2 = 3, kResCh = 4, kResJ = 5, kResStride = 6;
 // TDDP time constants after the coefficients
 constexpr int kTdGm = 0, kTdGp = 1, kTdG = 2, kTdDGmTau = 3, kTdDGpTau = 4, kTdDGTau = 5,
               kTdDGmY = 6, kTdDGpY = 7, kTdCount = 8;
 
 constexpr int dz_n_dln(int R, bool tddp) { return 2 * R + (tddp ? 2 : 0); }
-constexpr int dz_res_base(int R, bool tddp) { return kDzDln + dz_n_dln(R, tddp); }
+constexpr int dz_ch_base(int R, bool tddp) { return kDzDln + dz_n_dln(R, tddp); }
+constexpr int dz_res_base(int R, bool tddp) { return dz_ch_base(R, tddp) + kNumCh * kChStride; }
 constexpr int dz_coef_base(int R, bool tddp) { return dz_res_base(R, tddp) + R * kResStride; }
 constexpr int dz_time_base(int R) { return dz_coef_base(R, true) + 2 * R; }
 constexpr int dz_n_const(int R, bool tddp) { return dz_coef_base(R, tddp) + 2 * R + (tddp ? kTdCount : 0); }

@@ -79,19 +79,18 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     for (int c = 0; c < kMaxCols; ++c) a.col[c] = d->col[c];
     a.n_events = d->n;
     a.partials = d->partials;
-    a.stride = S + 2;
-    a.n_tiles = (int32_t)d->n_tiles;
+    a.n_rows = d->n_rows;
+    a.pad = 0;
     const bool prof = g_prof.on;
     if (prof) hipEventRecord(g_prof.e[0], st);
-    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, d->n_tiles, st);
+    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st);
     if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
     if (prof) hipEventRecord(g_prof.e[1], st);
     FitRec fr;
     std::memset(&fr, 0, sizeof(fr));
     fr.partials = d->partials;
-    fr.n_tiles = (int32_t)d->n_tiles;
+    fr.n_rows = d->n_rows;
     fr.result = d->res_dev;
-    fr.stride = S + 2;
     fr.n_slots = want_grad ? S : 0;
     fr.active = 1;
     e = launch_reduce_one(fr, st);
@@ -109,15 +108,8 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     }
     for (int j = 0; j < (want_grad ? S + 1 : 1); ++j) sums[j] = d->res_host[j];
   }
-  const double n = (double)d->n;
-  const double v = sums[0] + n * sc.ht.lnN;  // the kernels accumulate -ln P
-  if (grad) {
-    for (int p = 0; p < np; ++p) grad[p] = n * sc.ht.dlnN[p];
-    for (int j = 0; j < S; ++j)
-      if (g->slot_par[j] >= 0) grad[g->slot_par[j]] -= sums[1 + j];  // and +d ln P
-    for (int p = 0; p < np; ++p)
-      if (g->par[p].fixed) grad[p] = 0.0;
-  }
+  double v = 0.0;
+  assemble(g, sc, d->n > 0 ? sums.data() : nullptr, d->n, &v, grad);
   if (!std::isfinite(v)) {
     *nll = INFINITY;
     return fail(HF_E_DOMAIN, "density <= 0 or not finite at some event");
@@ -168,10 +160,9 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
     d->n = n;
     d->n_cols = nc;
     const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
-    const int64_t tile = kind_tile(g->kind);
-    d->n_tiles = (n + tile - 1) / tile;
+    d->n_rows = rows_for(g->kind, n);
     const size_t col_bytes = align256((size_t)n * es);
-    const size_t part_bytes = align256((size_t)d->n_tiles * (g->prog.n_slots + 2) * sizeof(double));
+    const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * (g->prog.n_slots + 1) * sizeof(double));
     const size_t total = col_bytes * nc + part_bytes;
     void* blk = nullptr;
     hipError_t e = hipMalloc(&blk, total);

@@ -1,12 +1,12 @@
 // Batched likelihood evaluations and the continuous-batching fit engine.
 //
-// All active fits of one graph are evaluated by one launch of the tile
-// kernel (each block walks a contiguous range of the concatenated tile list)
+// All active fits of one graph are evaluated by one launch of the row
+// kernel (each block walks the concatenated row list with a grid stride)
 // followed by one launch of the per-fit reduction.  The host side of a step
 // writes a fixed-size header, the per-fit records and the per-fit constant
 // tables into pinned memory; the device side -- three copies and two kernels
 // -- is captured once into a HIP graph and replayed every step, so its shape
-// never changes: fit counts and tile counts are read from the header in
+// never changes: fit counts and row counts are read from the header in
 // device memory, the eval grid is fixed and surplus blocks exit at once.
 // Results are written by the reduction straight into mapped pinned memory.
 #include <algorithm>
@@ -92,40 +92,31 @@ static void fill_tables(const pdf_graph* g, BatchTables& t, const std::vector<co
                         const std::vector<const StagedCall*>& sc) {
   const int n = (int)ds.size();
   FitRec* fr = t.fits_h();
-  int tile = 0;
+  int row = 0;
   for (int i = 0; i < t.max_fits; ++i) {
     std::memset(&fr[i], 0, sizeof(FitRec));
     if (i < n) {
       for (int c = 0; c < kMaxCols; ++c) fr[i].col[c] = ds[i]->col[c];
       fr[i].n_events = ds[i]->n;
       fr[i].partials = ds[i]->partials;
-      fr[i].tile_begin = tile;
-      fr[i].n_tiles = (int32_t)ds[i]->n_tiles;
+      fr[i].row_begin = row;
+      fr[i].n_rows = ds[i]->n_rows;
       fr[i].result = t.res_d + (size_t)i * (t.S + 1);
-      fr[i].stride = g->prog.n_slots + 2;
       fr[i].n_slots = g->prog.n_slots;
       fr[i].active = 1;
-      tile += (int)ds[i]->n_tiles;
+      row += ds[i]->n_rows;
       std::memcpy(t.c64_h + (size_t)i * t.n_const, sc[i]->prog.c64, g->n_const * sizeof(double));
       std::memcpy(t.c32_h + (size_t)i * t.n_const, sc[i]->prog.c32, g->n_const * sizeof(float));
     }
   }
   t.hdr_h->n_fits = n;
-  t.hdr_h->total_tiles = tile;
-  t.hdr_h->tiles_per_block = (tile + kBatchGrid - 1) / kBatchGrid;
+  t.hdr_h->total_rows = row;
 }
 
 static void finish_fit(const pdf_graph* g, const dataset* d, const StagedCall& sc, const double* row, double* nll,
                        double* grad) {
-  const int np = (int)g->par.size(), S = g->prog.n_slots;
-  const double n = (double)d->n;
-  const double v = (d->n > 0 ? row[0] : 0.0) + n * sc.ht.lnN;  // rows hold sum(-ln P), sum(d ln P)
-  for (int p = 0; p < np; ++p) grad[p] = n * sc.ht.dlnN[p];
-  if (d->n > 0)
-    for (int j = 0; j < S; ++j)
-      if (g->slot_par[j] >= 0) grad[g->slot_par[j]] -= row[1 + j];
-  for (int p = 0; p < np; ++p)
-    if (g->par[p].fixed) grad[p] = 0.0;
+  double v = 0.0;
+  assemble(g, sc, d->n > 0 ? row : nullptr, d->n, &v, grad);
   *nll = std::isfinite(v) ? v : INFINITY;
 }
 

@@ -1,22 +1,25 @@
 // Per-event likelihood kernels for gfx950 (CDNA4, wave64).
 //
-// One block of 256 threads owns a fixed tile of TILE = 256 * EPT consecutive
-// events; thread t reads events tile*TILE + e*256 + t (e < EPT), so every
-// column load is a fully coalesced 256-lane access.  Per event the kernel
-// evaluates the flattened PDF tree (forward pass in log space), runs the
-// adjoint (reverse pass) to get d ln P / d theta for every gradient slot, and
-// accumulates -ln P (Neumaier-compensated) and the slot derivatives in double.
-// The block reduces its accumulators with wave64 butterflies (bitwise equal on
-// every lane) and a fixed-order merge of the four waves, and stores one row of
-// partials per tile.  A second kernel sums the rows of each fit in a fixed
-// order.  The partials of a tile depend only on the tile's events and the
-// constant table, never on the grid size or on other fits in the same launch,
-// so a fit gives bit-identical results alone and batched.
+// Work split.  The events of a dataset form chunks of 256 consecutive events
+// (one per thread of a 256-thread block; every column load is a fully
+// coalesced 256-lane access).  The chunks are divided into n_rows contiguous,
+// equal (+-1 chunk) ranges, one per block: n_rows is fixed per dataset (a few
+// rows per compute unit), so the launch is a single balanced wave of blocks
+// and each block reduces its accumulators once.  Per event a kernel evaluates
+// the PDF (forward pass in log space), the derivatives d ln P / d theta of
+// every gradient slot (reverse pass), and accumulates -ln P and the slot
+// derivatives per thread in double.  The block then sums its threads in a
+// fixed order (LDS, DPP lane exchanges, fixed lanes) and writes one row of
+// partials; partials are stored column-major, [column][row].  A second kernel
+// sums the rows of each fit in a fixed order.  A row depends only on its event
+// range and the constant table, never on the grid or on other fits of the
+// same launch, so a fit gives bit-identical results alone and batched.
 //
 // Precision: T = double (FP64 path) or float (FP32-eval path).  In the float
 // path events are stored as float offsets from a per-column double
-// reference; every location difference (x - a, x - mu, m0^2 - s) is formed in
-// double from the stored offset and a double constant, then rounded once.
+// reference; location differences (x - a, x - mu, m0^2 - s) are formed from
+// the stored offset and a double constant (in double, or as a float hi + lo
+// pair), then rounded once.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -193,160 +196,340 @@ __device__ __forceinline__ T leaf_tddp(const CS& cs, int c0, int R, bool hoisted
   return lv;
 }
 
-// ------------------------------------------------------------------ accumulation
-struct NeuAcc {
-  double s = 0.0, c = 0.0;
-  __device__ __forceinline__ void add(double x) {
-    const double t = s + x;
-    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-    s = t;
-  }
-};
-
-// Error-free sum of two values (Knuth): a + b = s + e exactly.
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-  s = a + b;
-  const double bp = s - a;
-  e = (a - (s - bp)) + (b - bp);
+// ------------------------------------------------------------------ cross-lane sums
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Block reduction of one tile: lanes hold (nll_s, nll_c, slot sums); wave64
-// butterflies then a fixed-order merge of the 4 waves.  Row layout written to
-// `out`: [nll_s, nll_c, slot_0 .. slot_{S-1}].
-template <int S>
-__device__ __forceinline__ void tile_store(NeuAcc nll, const double* g, int n_slots, double* __restrict__ out) {
-  __shared__ double red[4][S + 2];
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active): pair and quad
+// exchanges, then rotations by 4 and 8 inside each 16-lane row, so lanes 0,
+// 16, 32 and 48 hold their row sums; those four are added in a fixed order.
+// The result is wave-uniform.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x128>(v);  // row_ror:8
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Row store for few columns: the threads' accumulators go through LDS; wave
+// w sums columns w, w + 4, ... over the four waves (fixed order) and its 64
+// lanes.  `out` points at this row of column 0; columns are `stride` apart.
+template <int NC>
+__device__ __forceinline__ void row_store_lds(const double* acc, double* __restrict__ out, int stride) {
+  __shared__ double sh[NC][kBlock];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) sh[j][threadIdx.x] = acc[j];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double s = nll.s, c = nll.c;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double os = __shfl_xor(s, off, 64), oc = __shfl_xor(c, off, 64);
-    double ns, e;
-    two_sum(s, os, ns, e);
-    s = ns;
-    c = (c + oc) + e;
+  for (int j = wave; j < NC; j += kBlock / 64) {
+    const double v = ((sh[j][lane] + sh[j][lane + 64]) + sh[j][lane + 128]) + sh[j][lane + 192];
+    const double s = wave_sum(v);
+    if (lane == 0) out[(int64_t)j * stride] = s;
   }
-  double v[S];
+  __syncthreads();  // sh is reused by the next row of a grid-stride block
+}
+
+// Row store for many columns (amplitude and tree kernels): a lane sum per
+// wave and column, then the four waves in a fixed order.
+template <int NC>
+__device__ __forceinline__ void row_store_waves(const double* acc, int nc, double* __restrict__ out, int stride) {
+  __shared__ double red[kBlock / 64][NC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    v[j] = 0.0;
-    if (j < n_slots) {
-      double x = g[j];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-      v[j] = x;
+  for (int j = 0; j < NC; ++j)
+    if (j < nc) {
+      const double s = wave_sum(acc[j]);
+      if (lane == 0) red[wave][j] = s;
     }
-  }
-  if (lane == 0) {
-    red[wave][0] = s;
-    red[wave][1] = c;
-#pragma unroll
-    for (int j = 0; j < S; ++j)
-      if (j < n_slots) red[wave][2 + j] = v[j];
-  }
   __syncthreads();
   const int t = threadIdx.x;
-  if (t == 0) {
-    double ss = red[0][0], cc = red[0][1];
-    for (int w = 1; w < 4; ++w) {
-      double ns, e;
-      two_sum(ss, red[w][0], ns, e);
-      ss = ns;
-      cc = (cc + red[w][1]) + e;
-    }
-    out[0] = ss;
-    out[1] = cc;
-  } else if (t < n_slots + 1) {
-    const int j = t - 1;
-    out[2 + j] = ((red[0][2 + j] + red[1][2 + j]) + red[2][2 + j]) + red[3][2 + j];
-  }
-  __syncthreads();  // `red` is reused by the next tile of a persistent block
+  if (t < nc) out[(int64_t)t * stride] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+  __syncthreads();
 }
 
-// ------------------------------------------------------------------ single-leaf tiles
-template <int OP> struct LeafInfo;
-template <> struct LeafInfo<OP_EXP> { static constexpr int ncol = 1, nslot = 1; };
-template <> struct LeafInfo<OP_GAUSS> { static constexpr int ncol = 1, nslot = 2; };
-template <> struct LeafInfo<OP_DALITZ> { static constexpr int ncol = 2, nslot = 2 * kMaxRes; };
-template <> struct LeafInfo<OP_TDDP> { static constexpr int ncol = 4, nslot = 2 * kMaxRes + 2; };
-
-template <typename T, int OP, int EPT, bool GRAD>
-__device__ __forceinline__ void leaf_tile(const KNode& nd, const CS& cs, const void* const* cols, int64_t n_events,
-                                          int64_t tile, int n_slots_all, double* __restrict__ out) {
-  const int n_slots = GRAD ? n_slots_all : 0;
-  typedef typename Col<T>::S Sx;
-  constexpr int NC = LeafInfo<OP>::ncol;
-  constexpr int NS = LeafInfo<OP>::nslot;
-  const int64_t base = tile * (int64_t)(kBlock * EPT) + threadIdx.x;
-  const bool hoisted = nd.hoisted != 0;
-  const int c0 = nd.c0;
-  const Sx* cp[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) cp[c] = (const Sx*)cols[nd.col[c]];
-  // issue every load of the tile before any arithmetic
-  Sx xv[NC][EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) xv[c][e] = i < n_events ? cp[c][i] : Sx(0);
-  }
-  double nll = 0.0;  // <= EPT terms per thread: compensation starts at the tile level
-  double g[NS];
-#pragma unroll
-  for (int j = 0; j < NS; ++j) g[j] = 0.0;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    if (i < n_events) {
-      T dl[NS];
-      T lv;
-      if (OP == OP_EXP) lv = leaf_exp<T>(cs, c0, hoisted, (double)xv[0][e], dl);
-      else if (OP == OP_GAUSS) lv = leaf_gauss<T>(cs, c0, hoisted, (double)xv[0][e], dl);
-      else if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, c0, nd.aux, hoisted, (double)xv[0][e], (double)xv[1][e], dl);
-      else lv = leaf_tddp<T>(cs, c0, nd.aux, hoisted, (double)xv[0][e], (double)xv[1][e], (double)xv[2][e],
-                            (double)xv[3][e], dl);
-      nll -= (double)lv;
-#pragma unroll
-      for (int j = 0; j < NS; ++j)
-        if (j < n_slots) g[j] += (double)dl[j];
-    }
-  }
-  tile_store<NS>(NeuAcc{nll, 0.0}, g, n_slots, out);
+// Chunk range [c0, c1) of row r when the dataset's chunks are split into
+// n_rows equal parts.
+__device__ __forceinline__ void row_chunks(int64_t n_events, int n_rows, int r, int64_t& c0, int64_t& c1) {
+  const int64_t nch = (n_events + kBlock - 1) / kBlock;
+  c0 = (int64_t)r * nch / n_rows;
+  c1 = (int64_t)(r + 1) * nch / n_rows;
 }
 
-// ------------------------------------------------------------------ tree interpreter tiles
-// General trees (ADD / PROD over leaves).  Node log-values, adjoints and the
-// per-event slot derivatives live in small VGPR arrays indexed by
-// wave-uniform node / slot numbers.
-template <typename T, int EPT, int NS, int NCOL, bool HEAVY, bool GRAD>
-__device__ __forceinline__ void tree_tile(const KProgram& P, const CS& cs, const void* const* cols, int64_t n_events,
-                                          int64_t tile, double* __restrict__ out) {
+// ------------------------------------------------------------------ row loops
+// Single-column evaluators (mixtures, single EXP / GAUSS leaves): groups of
+// U chunks, the loads of the next group in flight while the current one is
+// evaluated.  An evaluator adds -ln P to `nl` and its NA gradient
+// accumulators to `ga` (type T over one group); the group sums go into the
+// per-thread double accumulators acc[0] (NLL) and acc[1 + j].  Only the last
+// chunk of a dataset can be partial, so all groups but the last are
+// unchecked.
+template <typename T, int U, class Ev>
+__device__ __forceinline__ void light_row(const Ev& ev, const typename Col<T>::S* __restrict__ xp, int64_t n,
+                                          int64_t c0, int64_t c1, double* acc) {
   typedef typename Col<T>::S Sx;
-  constexpr int NN = HEAVY ? kMaxNodes : 8;  // node capacity of this instantiation
-  const int64_t base = tile * (int64_t)(kBlock * EPT) + threadIdx.x;
-  const int n_nodes = P.n_nodes, n_slots = GRAD ? P.n_slots : 0, n_cols = P.n_cols;
-  // one event in flight ahead of the one being evaluated
+  constexpr int NA = Ev::NA;
+  const int64_t t = threadIdx.x;
+  const int64_t full = n / kBlock;                 // chunks with 256 events
+  const int64_t cfe = c1 < full ? c1 : full;
+  const int64_t ng = cfe > c0 ? (cfe - c0) / U : 0;
+  int64_t c = c0;
+  Sx nx[U];
+  if (ng > 0) {
+#pragma unroll
+    for (int k = 0; k < U; ++k) nx[k] = xp[(c + k) * kBlock + t];
+  }
+  for (int64_t gi = 0; gi < ng; ++gi) {
+    Sx cur[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) cur[k] = nx[k];
+    if (gi + 1 < ng) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) nx[k] = xp[(c + U + k) * kBlock + t];
+    }
+    T nl = T(0), ga[NA + 1];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) ga[j] = T(0);
+#pragma unroll
+    for (int k = 0; k < U; ++k) ev((T)cur[k], nl, ga);
+    acc[0] += (double)nl;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[1 + j] += (double)ga[j];
+    c += U;
+  }
+  if (c < c1) {  // at most U chunks left, the last one possibly partial
+    Sx cur[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t i = (c + k) * kBlock + t;
+      cur[k] = (c + k < c1 && i < n) ? xp[i] : Sx(0);
+    }
+    T nl = T(0), ga[NA + 1];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) ga[j] = T(0);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t i = (c + k) * kBlock + t;
+      if (c + k < c1 && i < n) ev((T)cur[k], nl, ga);
+    }
+    acc[0] += (double)nl;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[1 + j] += (double)ga[j];
+  }
+}
+
+// Multi-column evaluators (amplitude leaves, trees): one event per chunk and
+// thread, the next event's columns in flight; the evaluator adds straight
+// into the double accumulators.
+template <typename T, int NCOL, class Ev>
+__device__ __forceinline__ void heavy_row(const Ev& ev, const KProgram& P, const typename Col<T>::S* const* cp,
+                                          int ncols, int64_t n, int64_t c0, int64_t c1, double* acc) {
+  typedef typename Col<T>::S Sx;
+  const int64_t t = threadIdx.x;
   Sx cur[NCOL];
+  {
+    const int64_t i = c0 * kBlock + t;
 #pragma unroll
-  for (int c = 0; c < NCOL; ++c)
-    cur[c] = (c < n_cols && base < n_events) ? ((const Sx*)cols[c])[base] : Sx(0);
-  double nll = 0.0;
-  double g[NS];
-#pragma unroll
-  for (int j = 0; j < NS; ++j) g[j] = 0.0;
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
+    for (int c = 0; c < NCOL; ++c) cur[c] = (c < ncols && c0 < c1 && i < n) ? cp[c][i] : Sx(0);
+  }
+#pragma unroll 1
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    const int64_t i = ch * kBlock + t;
     double xe[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) xe[c] = (double)cur[c];
-    if (e + 1 < EPT) {
+    if (ch + 1 < c1) {
       const int64_t i1 = i + kBlock;
 #pragma unroll
       for (int c = 0; c < NCOL; ++c)
-        if (c < n_cols) cur[c] = i1 < n_events ? ((const Sx*)cols[c])[i1] : Sx(0);
+        if (c < ncols) cur[c] = i1 < n ? cp[c][i1] : Sx(0);
     }
-    if (i >= n_events) break;
+    if (i < n) ev(P, xe, acc);
+  }
+}
+
+// ------------------------------------------------------------------ mixtures
+// Root ADD of K single-column EXP / GAUSS leaves (the signal-plus-background
+// shape), fully static: MASK bit j set means child j is a GAUSS.  With e_j =
+// exp(lv_j - m) (m the largest child log-density), s = sum f_j e_j and q_j =
+// e_j / s, the per-event terms are ln P = m + ln s and
+//   d ln P / d f_j      = q_j - q_{K-1}                 (j < K-1)
+//   d ln P / d(GAUSS j) = f_j q_j (z / sigma - dlnN), f_j q_j (z^2 / sigma - dlnN')
+//   d ln P / d(EXP j)   = f_j q_j (x - a - dlnN).
+// The kernel accumulates per child sum q_j, sum q_j z (EXP: sum q_j x) and
+// sum q_j z^2; the host combines them with the constants.
+template <typename T> struct Split;
+template <> struct Split<double> {
+  double v;
+  __device__ __forceinline__ void set(double x) { v = x; }
+  __device__ __forceinline__ double add_to(double a) const { return a + v; }
+  // a * b + v and a * b - v
+  __device__ __forceinline__ double fma_add(double a, double b) const { return __builtin_fma(a, b, v); }
+  __device__ __forceinline__ double fma_sub(double a, double b) const { return __builtin_fma(a, b, -v); }
+};
+template <> struct Split<float> {
+  // a double constant as a float pair hi + lo: (a + hi) + lo rounds like one
+  // addition of the double value, so its rounding error varies from event to
+  // event instead of biasing all of them the same way
+  float hi, lo;
+  __device__ __forceinline__ void set(double x) {
+    hi = (float)x;
+    lo = (float)(x - (double)hi);
+  }
+  __device__ __forceinline__ float add_to(float a) const { return (a + hi) + lo; }
+  // a * b + (hi + lo) and a * b - (hi + lo)
+  __device__ __forceinline__ float fma_add(float a, float b) const { return __builtin_fmaf(a, b, hi) + lo; }
+  __device__ __forceinline__ float fma_sub(float a, float b) const { return __builtin_fmaf(a, b, -hi) - lo; }
+};
+
+__device__ __forceinline__ float neg_abs(float x) { return -__builtin_fabsf(x); }
+__device__ __forceinline__ double neg_abs(double x) { return -__builtin_fabs(x); }
+
+template <typename T, int K, int MASK, bool GRAD>
+struct MixEv {
+  static constexpr int NA = GRAD ? 3 * K : 0;
+  Split<T> loc[K];  // GAUSS: column reference - mu
+  Split<T> cst[K];  // GAUSS: ln N ; EXP: alpha (column reference - a) - ln N
+  T k1[K];          // GAUSS: 1 / sigma ; EXP: alpha
+  T f[K];           // fractions, the last one 1 - sum of the others
+
+  __device__ __forceinline__ void operator()(T x, T& nl, T* ga) const {
+    T lv[K], za[K], zb[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if ((MASK >> j) & 1) {
+        const T z = loc[j].add_to(x) * k1[j], zz = z * z;
+        lv[j] = cst[j].fma_sub(T(-0.5), zz);
+        za[j] = z;
+        zb[j] = zz;
+      } else {
+        lv[j] = cst[j].fma_add(k1[j], x);
+        za[j] = x;
+        zb[j] = T(0);
+      }
+    }
+    T q[K];
+    if (K == 2) {
+      // the larger term has e = 1: one exponential per event
+      const T dd = lv[1] - lv[0];
+      const bool up = dd > T(0);
+      const T eo = Mth<T>::ex(neg_abs(dd));
+      const T m = up ? lv[1] : lv[0];
+      const T fa = up ? f[1] : f[0], fb = up ? f[0] : f[1];
+      const T s = Mth<T>::fma(fb, eo, fa);
+      nl -= Mth<T>::ln_add(s, m);
+      if (GRAD) {
+        const T is = Mth<T>::rcp(s), qo = eo * is;
+        q[0] = up ? qo : is;
+        q[1] = up ? is : qo;
+      }
+    } else {
+      T m = lv[0];
+#pragma unroll
+      for (int j = 1; j < K; ++j) m = lv[j] > m ? lv[j] : m;
+      T e[K], s = T(0);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        e[j] = Mth<T>::ex(lv[j] - m);
+        s = Mth<T>::fma(f[j], e[j], s);
+      }
+      nl -= Mth<T>::ln_add(s, m);
+      if (GRAD) {
+        const T is = Mth<T>::rcp(s);
+#pragma unroll
+        for (int j = 0; j < K; ++j) q[j] = e[j] * is;
+      }
+    }
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        ga[3 * j] += q[j];
+        ga[3 * j + 1] = Mth<T>::fma(q[j], za[j], ga[3 * j + 1]);
+        if ((MASK >> j) & 1) ga[3 * j + 2] = Mth<T>::fma(q[j], zb[j], ga[3 * j + 2]);
+      }
+    }
+  }
+};
+
+// Constants of a mixture from the staged table (EXP / GAUSS / ADD layouts).
+template <typename T, int K, int MASK, bool GRAD>
+__device__ __forceinline__ MixEv<T, K, MASK, GRAD> make_mix(const KProgram& P, const CS& cs) {
+  MixEv<T, K, MASK, GRAD> ev;
+  const KNode& rn = P.node[P.n_nodes - 1];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int c0 = P.node[P.child[rn.child0 + j]].c0;
+    ev.k1[j] = cs.get<T>(c0 + 1);
+    if ((MASK >> j) & 1) {
+      ev.loc[j].set(cs.d[c0]);
+      ev.cst[j].set(cs.d[c0 + 2]);
+    } else {
+      ev.loc[j].set(0.0);
+      ev.cst[j].set(cs.d[c0 + 1] * cs.d[c0] - cs.d[c0 + 2]);
+    }
+    ev.f[j] = cs.get<T>(rn.c0 + j);
+  }
+  return ev;
+}
+
+// ------------------------------------------------------------------ leaf evaluators
+template <typename T, int OP, bool GRAD>
+struct LightLeafEv {  // single EXP / GAUSS leaf
+  static constexpr int NA = GRAD ? (OP == OP_EXP ? 1 : 2) : 0;
+  CS cs;
+  int c0;
+  bool hoisted;
+  __device__ __forceinline__ void operator()(T x, T& nl, T* ga) const {
+    T dl[2];
+    const T lv = OP == OP_EXP ? leaf_exp<T>(cs, c0, hoisted, (double)x, dl)
+                              : leaf_gauss<T>(cs, c0, hoisted, (double)x, dl);
+    nl -= lv;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) ga[j] += dl[j];
+  }
+};
+
+template <typename T, int OP, bool GRAD>
+struct AmpLeafEv {  // single DALITZ / TDDP leaf
+  static constexpr int NS = OP == OP_DALITZ ? 2 * kMaxRes : 2 * kMaxRes + 2;
+  CS cs;
+  int c0, R, n_slots;
+  bool hoisted;
+  __device__ __forceinline__ void operator()(const KProgram&, const double* xe, double* acc) const {
+    T dl[NS];
+    T lv;
+    if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, c0, R, hoisted, xe[0], xe[1], dl);
+    else lv = leaf_tddp<T>(cs, c0, R, hoisted, xe[0], xe[1], xe[2], xe[3], dl);
+    acc[0] -= (double)lv;
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+        if (j < n_slots) acc[1 + j] += (double)dl[j];
+    }
+  }
+};
+
+// General trees (ADD / PROD over leaves).  Node log-values, adjoints and the
+// per-event slot derivatives live in small VGPR arrays indexed by
+// wave-uniform node / slot numbers.
+template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+struct TreeEv {
+  CS cs;
+  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, double* acc) const {
+    constexpr int NN = HEAVY ? kMaxNodes : 8;  // node capacity of this instantiation
+    const int n_nodes = P.n_nodes, n_slots = GRAD ? P.n_slots : 0;
     T lv[NN], adj[NN], resp[NN], dl[NS];
     // forward pass (post-order)
     for (int k = 0; k < n_nodes; ++k) {
@@ -430,172 +613,129 @@ __device__ __forceinline__ void tree_tile(const KProgram& P, const CS& cs, const
       if (k != root)
         for (int j = 0; j < nd.n_slot; ++j) dl[nd.slot0 + j] = dl[nd.slot0 + j] * a;
     }
-    nll -= (double)lv[root];
+    acc[0] -= (double)lv[root];
 #pragma unroll
     for (int j = 0; j < NS; ++j)
-      if (j < n_slots) g[j] += (double)dl[j];
+      if (j < n_slots) acc[1 + j] += (double)dl[j];
   }
-  tile_store<NS>(NeuAcc{nll, 0.0}, g, n_slots, out);
-}
-
-// ------------------------------------------------------------------ mixture tiles
-// Root ADD of K single-column EXP / GAUSS leaves (the signal-plus-background
-// shape).  Fully static: the child kinds are wave-uniform branches, the
-// accumulators have a fixed layout [2 per child, then K-1 fractions] that the
-// host maps back to parameters.
-template <typename T> struct Split;
-template <> struct Split<double> {
-  // double path: the location constant is used as is
-  double v;
-  __device__ __forceinline__ void set(double x) { v = x; }
-  __device__ __forceinline__ double add(double x) const { return x + v; }
-};
-template <> struct Split<float> {
-  // float path: the double location constant as a float pair hi + lo, so that
-  // (x + hi) + lo rounds like one addition of the double value (its rounding
-  // error varies from event to event instead of biasing all of them)
-  float hi, lo;
-  __device__ __forceinline__ void set(double x) {
-    hi = (float)x;
-    lo = (float)(x - (double)hi);
-  }
-  __device__ __forceinline__ float add(float x) const { return (x + hi) + lo; }
 };
 
-// Per-event body of a mixture tile.  MASK bit j set: child j is a Gaussian,
-// clear: an exponential (static, so no per-event branching on the kinds);
-// FULL: every event of the tile exists (no per-event bound checks).
-template <typename T, int EPT, int K, int MASK, bool GRAD, bool FULL>
-__device__ __forceinline__ void mix_events(const typename Col<T>::S* __restrict__ xp, int64_t base, int64_t n_events,
-                                           const Split<T>* loc, const T* k1, const T* lhi, const T* llo, const T* d0c,
-                                           const T* d1c, const T* fr, double& nll, T* gt) {
-  typedef typename Col<T>::S Sx;
-  Sx xv[EPT];
+// ------------------------------------------------------------------ rows
+constexpr int kUnroll = 8;  // chunks per group in the single-column kernels
+
+template <typename T, int K, int MASK, bool GRAD>
+__device__ __forceinline__ void mix_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
+                                        int n_rows, int r, double* __restrict__ out) {
+  constexpr int NC = 1 + (GRAD ? 3 * K : 0);
+  const auto ev = make_mix<T, K, MASK, GRAD>(P, cs);
+  double acc[NC];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    xv[e] = (FULL || i < n_events) ? xp[i] : Sx(0);
-  }
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int64_t i = base + (int64_t)e * kBlock;
-    if (!FULL && i >= n_events) break;
-    const T x = (T)xv[e];
-    T lv[K], d0[K], d1[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const T u = loc[j].add(x);
-      if ((MASK >> j) & 1) {
-        const T z = u * k1[j], zz = z * z;
-        lv[j] = (T(-0.5) * zz - lhi[j]) - llo[j];
-        d0[j] = z * k1[j] - d0c[j];
-        d1[j] = zz * k1[j] - d1c[j];
-      } else {
-        lv[j] = (k1[j] * u - lhi[j]) - llo[j];
-        d0[j] = u - d0c[j];
-      }
-    }
-    T ej[K], m;
-    if (K == 2) {
-      // the larger term has e = 1: one exponential per event
-      const T dd = lv[1] - lv[0];
-      const bool up = dd > T(0);
-      const T eo = Mth<T>::ex(up ? -dd : dd);
-      ej[0] = up ? eo : T(1);
-      ej[1] = up ? T(1) : eo;
-      m = up ? lv[1] : lv[0];
-    } else {
-      m = lv[0];
-#pragma unroll
-      for (int j = 1; j < K; ++j) m = lv[j] > m ? lv[j] : m;
-#pragma unroll
-      for (int j = 0; j < K; ++j) ej[j] = Mth<T>::ex(lv[j] - m);
-    }
-    T ssum = fr[0] * ej[0];
-#pragma unroll
-    for (int j = 1; j < K; ++j) ssum += fr[j] * ej[j];
-    const T v = ssum > T(0) ? m + Mth<T>::ln(ssum) : T(-INFINITY);
-    nll -= (double)v;
-    if (GRAD) {
-      const T is = Mth<T>::rcp(ssum);
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const T r = fr[j] * ej[j] * is;
-        gt[2 * j] += r * d0[j];
-        if ((MASK >> j) & 1) gt[2 * j + 1] += r * d1[j];
-        if (j < K - 1) gt[2 * K + j] += (ej[j] - ej[K - 1]) * is;
-      }
-    }
-  }
+  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  int64_t c0, c1;
+  row_chunks(n, n_rows, r, c0, c1);
+  light_row<T, kUnroll>(ev, (const typename Col<T>::S*)cols[0], n, c0, c1, acc);
+  row_store_lds<NC>(acc, out, n_rows);
 }
 
-template <typename T, int EPT, int K, int MASK, bool GRAD>
-__device__ __forceinline__ void mix_tile(const KProgram& P, const CS& cs, const void* const* cols, int64_t n_events,
-                                         int64_t tile, double* __restrict__ out) {
+template <typename T, int OP, bool GRAD>
+__device__ __forceinline__ void light_leaf_row(const KNode& nd, const CS& cs, const void* const* cols, int64_t n,
+                                               int n_rows, int r, double* __restrict__ out) {
+  typedef LightLeafEv<T, OP, GRAD> Ev;
+  constexpr int NC = 1 + Ev::NA;
+  Ev ev;
+  ev.cs = cs;
+  ev.c0 = nd.c0;
+  ev.hoisted = nd.hoisted != 0;
+  double acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  int64_t c0, c1;
+  row_chunks(n, n_rows, r, c0, c1);
+  light_row<T, kUnroll>(ev, (const typename Col<T>::S*)cols[nd.col[0]], n, c0, c1, acc);
+  row_store_lds<NC>(acc, out, n_rows);
+}
+
+template <typename T, int OP, bool GRAD>
+__device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
+                                             int n_rows, int r, double* __restrict__ out) {
+  typedef AmpLeafEv<T, OP, GRAD> Ev;
   typedef typename Col<T>::S Sx;
-  constexpr int NA = 3 * K - 1;
-  const int64_t base = tile * (int64_t)(kBlock * EPT) + threadIdx.x;
-  // per-child constants, wave-uniform (constant layouts of EXP / GAUSS above)
-  const KNode& rn = P.node[P.n_nodes - 1];
-  Split<T> loc[K];
-  T k1[K], lhi[K], llo[K], d0c[K], d1c[K], fr[K];
+  constexpr int NCOL = OP == OP_DALITZ ? 2 : 4;
+  constexpr int NC = 1 + Ev::NS;
+  const KNode& nd = P.node[0];
+  Ev ev;
+  ev.cs = cs;
+  ev.c0 = nd.c0;
+  ev.R = nd.aux;
+  ev.n_slots = GRAD ? P.n_slots : 0;
+  ev.hoisted = nd.hoisted != 0;
+  const Sx* cp[NCOL];
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const int c0 = P.node[P.child[rn.child0 + j]].c0;
-    loc[j].set(cs.d[c0]);
-    k1[j] = cs.get<T>(c0 + 1);
-    lhi[j] = cs.get<T>(c0 + 2);
-    llo[j] = cs.get<T>(c0 + 3);
-    d0c[j] = cs.get<T>(c0 + 4);
-    d1c[j] = ((MASK >> j) & 1) ? cs.get<T>(c0 + 5) : T(0);
-    fr[j] = cs.get<T>(rn.c0 + j);
-  }
-  const Sx* xp = (const Sx*)cols[0];
-  double nll = 0.0;
-  T gt[NA];  // per-thread partial sums over this thread's <= EPT events
+  for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[nd.col[c]];
+  double acc[NC];
 #pragma unroll
-  for (int j = 0; j < NA; ++j) gt[j] = T(0);
-  if (tile * (int64_t)(kBlock * EPT) + (int64_t)kBlock * EPT <= n_events)
-    mix_events<T, EPT, K, MASK, GRAD, true>(xp, base, n_events, loc, k1, lhi, llo, d0c, d1c, fr, nll, gt);
-  else
-    mix_events<T, EPT, K, MASK, GRAD, false>(xp, base, n_events, loc, k1, lhi, llo, d0c, d1c, fr, nll, gt);
-  double g[NA];
+  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  int64_t c0, c1;
+  row_chunks(n, n_rows, r, c0, c1);
+  heavy_row<T, NCOL>(ev, P, cp, NCOL, n, c0, c1, acc);
+  row_store_waves<NC>(acc, 1 + ev.n_slots, out, n_rows);
+}
+
+template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+__device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
+                                         int n_rows, int r, double* __restrict__ out) {
+  typedef typename Col<T>::S Sx;
+  constexpr int NC = 1 + NS;
+  const TreeEv<T, NS, NCOL, HEAVY, GRAD> ev{cs};
+  const Sx* cp[NCOL];
 #pragma unroll
-  for (int j = 0; j < NA; ++j) g[j] = (double)gt[j];
-  tile_store<NA>(NeuAcc{nll, 0.0}, g, GRAD ? NA : 0, out);
+  for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[c];
+  double acc[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  int64_t c0, c1;
+  row_chunks(n, n_rows, r, c0, c1);
+  heavy_row<T, NCOL>(ev, P, cp, P.n_cols, n, c0, c1, acc);
+  row_store_waves<NC>(acc, 1 + (GRAD ? P.n_slots : 0), out, n_rows);
 }
 
 // ------------------------------------------------------------------ reduction
-// Second launch: one 1024-thread block per fit sums that fit's tile rows in a
+// Second launch: one 1024-thread block per fit sums that fit's rows in a
 // fixed order.  Wave w of the 16 works on column w % nc (several waves per
 // column when there are fewer than 16 columns, each on a fixed contiguous
-// slice of the rows); a lane takes rows lane, lane + 64, ... of its slice with
-// 16 loads in flight, two-sum compensated; then a wave64 butterfly and a
-// fixed-order merge of the slices of each column.  The NLL is the sum of its
-// value and compensation columns.  Result: [nll, slot_0 .. slot_{S-1}].
+// slice of the rows); a lane takes rows lane, lane + 64, ... of its slice
+// (contiguous in the column-major layout) with 16 loads in flight,
+// two-sum compensated; then a wave64 butterfly and a fixed-order merge of the
+// slices of each column.  Result: [nll, slot_0 .. slot_{S-1}].
 constexpr int kRedBlock = 1024;
 constexpr int kRedWaves = kRedBlock / 64;
-constexpr int kMaxRedCols = kMaxSlots + 2;
+constexpr int kMaxRedCols = kMaxSlots + 1;
 
-__device__ __forceinline__ void reduce_fit(const FitRec& fr, int stride, int n_slots) {
-  const int nc = n_slots + 2;
+// Error-free sum of two values (Knuth): a + b = s + e exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+__device__ __forceinline__ void reduce_fit(const FitRec& fr) {
+  const int nc = fr.n_slots + 1;
+  const int R = fr.n_rows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int per_col = nc >= kRedWaves ? 1 : kRedWaves / nc;  // waves per column
-  __shared__ double part[kRedWaves][2];
   __shared__ double colsum[kMaxRedCols][kRedWaves][2];
-  __shared__ double nll_parts[2];
-  // column pass: wave w handles (column, slice) pairs w, w + 16, ...
   for (int task = wave; task < nc * per_col; task += kRedWaves) {
     const int col = task / per_col, slice = task % per_col;
-    const int r_begin = (int)((int64_t)fr.n_tiles * slice / per_col);
-    const int r_end = (int)((int64_t)fr.n_tiles * (slice + 1) / per_col);
+    const int r_begin = (int)((int64_t)R * slice / per_col);
+    const int r_end = (int)((int64_t)R * (slice + 1) / per_col);
+    const double* src = fr.partials + (int64_t)col * R;
     double s = 0.0, c = 0.0;
     for (int r0 = r_begin; r0 < r_end; r0 += 64 * 16) {
       double v[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int r = r0 + u * 64 + lane;
-        v[u] = r < r_end ? fr.partials[(int64_t)r * stride + col] : 0.0;
+        v[u] = r < r_end ? src[r] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -628,47 +768,44 @@ __device__ __forceinline__ void reduce_fit(const FitRec& fr, int stride, int n_s
       s = ns;
       c = (c + colsum[t][k][1]) + e;
     }
-    if (t < 2) nll_parts[t] = s + c;
-    else fr.result[t - 1] = s + c;
+    fr.result[t] = s + c;
   }
-  __syncthreads();
-  if (t == 0) fr.result[0] = nll_parts[0] + nll_parts[1];
-  (void)part;
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce(const FitRec* __restrict__ fits, int n_fits_max) {
   const FitRec& fr = fits[blockIdx.x];
   if (!fr.active) return;
-  reduce_fit(fr, fr.stride, fr.n_slots);
+  reduce_fit(fr);
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_reduce_one(const FitRec fr) { reduce_fit(fr, fr.stride, fr.n_slots); }
+__global__ __launch_bounds__(kRedBlock) void k_reduce_one(const FitRec fr) { reduce_fit(fr); }
 
-// ------------------------------------------------------------------ kernels
-template <typename T, int OP, int EPT, bool GRAD>
+// ------------------------------------------------------------------ kernels (one dataset; one block per row)
+template <typename T, int OP, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_leaf(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
-  leaf_tile<T, OP, EPT, GRAD>(a.prog.node[0], cs, a.col, a.n_events, blockIdx.x, a.prog.n_slots,
-                        a.partials + (int64_t)blockIdx.x * a.stride);
+  if constexpr (OP == OP_EXP || OP == OP_GAUSS)
+    light_leaf_row<T, OP, GRAD>(a.prog.node[0], cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
+  else
+    amp_leaf_row<T, OP, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
 }
 
-template <typename T, int EPT, int NS, int NCOL, bool HEAVY, bool GRAD>
+template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
-  tree_tile<T, EPT, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x,
-                              a.partials + (int64_t)blockIdx.x * a.stride);
+  tree_row<T, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
 }
 
-template <typename T, int EPT, int K, int MASK, bool GRAD>
+template <typename T, int K, int MASK, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
-  mix_tile<T, EPT, K, MASK, GRAD>(a.prog, cs, a.col, a.n_events, blockIdx.x,
-                                  a.partials + (int64_t)blockIdx.x * a.stride);
+  mix_row<T, K, MASK, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
 }
 
 // Batched: the program structure is shared (kernel argument); constants,
-// columns and partials are per fit.  Each block walks a contiguous range of
-// global tiles; fits own contiguous tile ranges in fit order.
+// columns and partials are per fit.  Fits own contiguous ranges of the global
+// row list in fit order; each block walks global rows blockIdx.x,
+// blockIdx.x + gridDim.x, ...
 struct BatchArgs {
   KProgram prog;               // structure only (constants unused)
   const BatchHeader* hdr;      // counts, then the FitRec array
@@ -677,128 +814,76 @@ struct BatchArgs {
   int32_t n_const;
 };
 
-__device__ __forceinline__ int find_fit(const FitRec* fits, int n_fits, int gtile) {
+__device__ __forceinline__ int find_fit(const FitRec* fits, int n_fits, int grow) {
   int lo = 0, hi = n_fits - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (fits[mid].tile_begin <= gtile) lo = mid; else hi = mid - 1;
+    if (fits[mid].row_begin <= grow) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
-template <typename T, int OP, int EPT>
+template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_leaf_batched(const BatchArgs a) {  // always with gradient
-  const int tpb = a.hdr->tiles_per_block, total = a.hdr->total_tiles, n_fits = a.hdr->n_fits;
+  const int total = a.hdr->total_rows, n_fits = a.hdr->n_fits;
   const FitRec* fits = (const FitRec*)(a.hdr + 1);
-  const int g0 = blockIdx.x * tpb;
-  const int g1 = min(g0 + tpb, total);
-  if (g0 >= g1) return;
-  int f = find_fit(fits, n_fits, g0);
-  for (int gt = g0; gt < g1; ++gt) {
-    while (gt >= fits[f].tile_begin + fits[f].n_tiles) ++f;
+  for (int gr = blockIdx.x; gr < total; gr += gridDim.x) {
+    const int f = find_fit(fits, n_fits, gr);
     const FitRec& fr = fits[f];
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
-    const int64_t lt = gt - fr.tile_begin;
-    leaf_tile<T, OP, EPT, true>(a.prog.node[0], cs, fr.col, fr.n_events, lt, a.prog.n_slots,
-                          fr.partials + lt * (a.prog.n_slots + 2));
+    const int r = gr - fr.row_begin;
+    if constexpr (OP == OP_EXP || OP == OP_GAUSS)
+      light_leaf_row<T, OP, true>(a.prog.node[0], cs, fr.col, fr.n_events, fr.n_rows, r, fr.partials + r);
+    else
+      amp_leaf_row<T, OP, true>(a.prog, cs, fr.col, fr.n_events, fr.n_rows, r, fr.partials + r);
   }
 }
 
-template <typename T, int EPT, int K, int MASK>
+template <typename T, int K, int MASK>
 __global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
-  const int tpb = a.hdr->tiles_per_block, total = a.hdr->total_tiles, n_fits = a.hdr->n_fits;
+  const int total = a.hdr->total_rows, n_fits = a.hdr->n_fits;
   const FitRec* fits = (const FitRec*)(a.hdr + 1);
-  const int g0 = blockIdx.x * tpb;
-  const int g1 = min(g0 + tpb, total);
-  if (g0 >= g1) return;
-  int f = find_fit(fits, n_fits, g0);
-  for (int gt = g0; gt < g1; ++gt) {
-    while (gt >= fits[f].tile_begin + fits[f].n_tiles) ++f;
+  for (int gr = blockIdx.x; gr < total; gr += gridDim.x) {
+    const int f = find_fit(fits, n_fits, gr);
     const FitRec& fr = fits[f];
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
-    const int64_t lt = gt - fr.tile_begin;
-    mix_tile<T, EPT, K, MASK, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
+    const int r = gr - fr.row_begin;
+    mix_row<T, K, MASK, true>(a.prog, cs, fr.col, fr.n_events, fr.n_rows, r, fr.partials + r);
   }
 }
 
-template <typename T, int EPT, int NS, int NCOL, bool HEAVY>
+template <typename T, int NS, int NCOL, bool HEAVY>
 __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
-  const int tpb = a.hdr->tiles_per_block, total = a.hdr->total_tiles, n_fits = a.hdr->n_fits;
+  const int total = a.hdr->total_rows, n_fits = a.hdr->n_fits;
   const FitRec* fits = (const FitRec*)(a.hdr + 1);
-  const int g0 = blockIdx.x * tpb;
-  const int g1 = min(g0 + tpb, total);
-  if (g0 >= g1) return;
-  int f = find_fit(fits, n_fits, g0);
-  for (int gt = g0; gt < g1; ++gt) {
-    while (gt >= fits[f].tile_begin + fits[f].n_tiles) ++f;
+  for (int gr = blockIdx.x; gr < total; gr += gridDim.x) {
+    const int f = find_fit(fits, n_fits, gr);
     const FitRec& fr = fits[f];
     const CS cs{a.c64 + (int64_t)f * a.n_const, a.c32 + (int64_t)f * a.n_const};
-    const int64_t lt = gt - fr.tile_begin;
-    tree_tile<T, EPT, NS, NCOL, HEAVY, true>(a.prog, cs, fr.col, fr.n_events, lt, fr.partials + lt * (a.prog.n_slots + 2));
+    const int r = gr - fr.row_begin;
+    tree_row<T, NS, NCOL, HEAVY, true>(a.prog, cs, fr.col, fr.n_events, fr.n_rows, r, fr.partials + r);
   }
 }
 
 // ------------------------------------------------------------------ dispatch
-template <typename T, int EPT, bool GRAD>
-static hipError_t launch_light(int kind, const EvalArgs& a, int64_t n_tiles, hipStream_t st) {
-  const dim3 grid((unsigned)n_tiles), block(kBlock);
-  switch (kind) {
-    case KIND_EXP: hipLaunchKernelGGL((k_leaf<T, OP_EXP, EPT, GRAD>), grid, block, 0, st, a); break;
-    case KIND_GAUSS: hipLaunchKernelGGL((k_leaf<T, OP_GAUSS, EPT, GRAD>), grid, block, 0, st, a); break;
-    case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree<T, EPT, 8, 2, false, GRAD>), grid, block, 0, st, a); break;
-#define HF_MIX(K_, M_)                                                                              \
-  case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
-    hipLaunchKernelGGL((k_mix<T, EPT, K_, M_, GRAD>), grid, block, 0, st, a);                       \
-    break;
-    HF_MIX(2, 0) HF_MIX(2, 1) HF_MIX(2, 2) HF_MIX(2, 3)
-    HF_MIX(3, 0) HF_MIX(3, 1) HF_MIX(3, 2) HF_MIX(3, 3) HF_MIX(3, 4) HF_MIX(3, 5) HF_MIX(3, 6) HF_MIX(3, 7)
-#undef HF_MIX
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <typename T, int EPT, bool GRAD>
-static hipError_t launch_heavy(int kind, const EvalArgs& a, int64_t n_tiles, hipStream_t st) {
-  const dim3 grid((unsigned)n_tiles), block(kBlock);
-  switch (kind) {
-    case KIND_DALITZ: hipLaunchKernelGGL((k_leaf<T, OP_DALITZ, EPT, GRAD>), grid, block, 0, st, a); break;
-    case KIND_TDDP: hipLaunchKernelGGL((k_leaf<T, OP_TDDP, EPT, GRAD>), grid, block, 0, st, a); break;
-    case KIND_TREE: hipLaunchKernelGGL((k_tree<T, EPT, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+bool kind_light(int kind) {
+  if (kind >= KIND_MIX2) return true;
+  return kind == KIND_EXP || kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
 }
 
 template <typename T, bool GRAD>
-static hipError_t launch_any(int kind, const EvalArgs& a, int64_t n_tiles, hipStream_t st) {
-  if (kind_ept(kind) == kEptLight) return launch_light<T, kEptLight, GRAD>(kind, a, n_tiles, st);
-  return launch_heavy<T, kEptHeavy, GRAD>(kind, a, n_tiles, st);
-}
-
-int kind_ept(int kind) {
-  if (kind >= KIND_MIX2) return kEptLight;
+static hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)a.n_rows), block(kBlock);
   switch (kind) {
-    case KIND_EXP: case KIND_GAUSS: case KIND_TREE_SMALL: return kEptLight;
-    default: return kEptHeavy;
-  }
-}
-
-hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, int64_t n_tiles, hipStream_t st) {
-  if (n_tiles <= 0) return hipSuccess;
-  if (fp32) return grad ? launch_any<float, true>(kind, a, n_tiles, st) : launch_any<float, false>(kind, a, n_tiles, st);
-  return grad ? launch_any<double, true>(kind, a, n_tiles, st) : launch_any<double, false>(kind, a, n_tiles, st);
-}
-
-template <typename T, int EPT>
-static hipError_t launch_b_light(int kind, const BatchArgs& a, int grid, hipStream_t st) {
-  switch (kind) {
-    case KIND_EXP: hipLaunchKernelGGL((k_leaf_batched<T, OP_EXP, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case KIND_GAUSS: hipLaunchKernelGGL((k_leaf_batched<T, OP_GAUSS, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree_batched<T, EPT, 8, 2, false>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case KIND_EXP: hipLaunchKernelGGL((k_leaf<T, OP_EXP, GRAD>), grid, block, 0, st, a); break;
+    case KIND_GAUSS: hipLaunchKernelGGL((k_leaf<T, OP_GAUSS, GRAD>), grid, block, 0, st, a); break;
+    case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree<T, 8, 2, false, GRAD>), grid, block, 0, st, a); break;
+    case KIND_DALITZ: hipLaunchKernelGGL((k_leaf<T, OP_DALITZ, GRAD>), grid, block, 0, st, a); break;
+    case KIND_TDDP: hipLaunchKernelGGL((k_leaf<T, OP_TDDP, GRAD>), grid, block, 0, st, a); break;
+    case KIND_TREE: hipLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, a); break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
-    hipLaunchKernelGGL((k_mix_batched<T, EPT, K_, M_>), dim3(grid), dim3(kBlock), 0, st, a);        \
+    hipLaunchKernelGGL((k_mix<T, K_, M_, GRAD>), grid, block, 0, st, a);                            \
     break;
     HF_MIX(2, 0) HF_MIX(2, 1) HF_MIX(2, 2) HF_MIX(2, 3)
     HF_MIX(3, 0) HF_MIX(3, 1) HF_MIX(3, 2) HF_MIX(3, 3) HF_MIX(3, 4) HF_MIX(3, 5) HF_MIX(3, 6) HF_MIX(3, 7)
@@ -807,12 +892,30 @@ static hipError_t launch_b_light(int kind, const BatchArgs& a, int grid, hipStre
   }
   return hipGetLastError();
 }
-template <typename T, int EPT>
-static hipError_t launch_b_heavy(int kind, const BatchArgs& a, int grid, hipStream_t st) {
+
+hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st) {
+  if (a.n_rows <= 0) return hipSuccess;
+  if (fp32) return grad ? launch_any<float, true>(kind, a, st) : launch_any<float, false>(kind, a, st);
+  return grad ? launch_any<double, true>(kind, a, st) : launch_any<double, false>(kind, a, st);
+}
+
+template <typename T>
+static hipError_t launch_b(int kind, const BatchArgs& a, int grid, hipStream_t st) {
+  const dim3 g(grid), b(kBlock);
   switch (kind) {
-    case KIND_DALITZ: hipLaunchKernelGGL((k_leaf_batched<T, OP_DALITZ, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case KIND_TDDP: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP, EPT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, EPT, kMaxSlots, kMaxCols, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case KIND_EXP: hipLaunchKernelGGL((k_leaf_batched<T, OP_EXP>), g, b, 0, st, a); break;
+    case KIND_GAUSS: hipLaunchKernelGGL((k_leaf_batched<T, OP_GAUSS>), g, b, 0, st, a); break;
+    case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree_batched<T, 8, 2, false>), g, b, 0, st, a); break;
+    case KIND_DALITZ: hipLaunchKernelGGL((k_leaf_batched<T, OP_DALITZ>), g, b, 0, st, a); break;
+    case KIND_TDDP: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP>), g, b, 0, st, a); break;
+    case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, true>), g, b, 0, st, a); break;
+#define HF_MIX(K_, M_)                                                                              \
+  case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
+    hipLaunchKernelGGL((k_mix_batched<T, K_, M_>), g, b, 0, st, a);                                 \
+    break;
+    HF_MIX(2, 0) HF_MIX(2, 1) HF_MIX(2, 2) HF_MIX(2, 3)
+    HF_MIX(3, 0) HF_MIX(3, 1) HF_MIX(3, 2) HF_MIX(3, 3) HF_MIX(3, 4) HF_MIX(3, 5) HF_MIX(3, 6) HF_MIX(3, 7)
+#undef HF_MIX
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -826,9 +929,7 @@ hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const 
   a.c64 = c64;
   a.c32 = c32;
   a.n_const = n_const;
-  if (kind_ept(kind) == kEptLight)
-    return fp32 ? launch_b_light<float, kEptLight>(kind, a, grid, st) : launch_b_light<double, kEptLight>(kind, a, grid, st);
-  return fp32 ? launch_b_heavy<float, kEptHeavy>(kind, a, grid, st) : launch_b_heavy<double, kEptHeavy>(kind, a, grid, st);
+  return fp32 ? launch_b<float>(kind, a, grid, st) : launch_b<double>(kind, a, grid, st);
 }
 
 hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st) {

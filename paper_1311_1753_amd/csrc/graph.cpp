@@ -171,6 +171,61 @@ double herm_form(const std::vector<double>& Mf, const std::vector<cd>& c, std::v
 
 }  // namespace
 
+// ------------------------------------------------------------------ results
+void assemble(const pdf_graph* g, const StagedCall& sc, const double* sums, int64_t n_ev, double* nll, double* grad) {
+  const int np = (int)g->par.size(), S = g->prog.n_slots;
+  const double n = (double)n_ev;
+  *nll = (sums ? sums[0] : 0.0) + n * sc.ht.lnN;  // the kernels sum -ln P
+  if (!grad) return;
+  for (int p = 0; p < np; ++p) grad[p] = n * sc.ht.dlnN[p];
+  if (sums && g->mix.K > 0) {
+    // mixture sums per child j: S0 = sum q_j, S1 = sum q_j z (EXP: q_j x),
+    // S2 = sum q_j z^2; the derivatives of ln L are
+    //   f_j (S1 / sigma - dlnN/dmu S0), f_j (S2 / sigma - dlnN/dsigma S0)  (GAUSS)
+    //   f_j (S1 + (column reference - a - dlnN/dalpha) S0)                  (EXP)
+    //   S0_j - S0_{K-1}                                                      (fraction j)
+    const MixInfo& mx = g->mix;
+    const double* c = sc.prog.c64;
+    const int K = mx.K, rc0 = sc.prog.node[mx.root].c0;
+    for (int j = 0; j < K; ++j) {
+      const double fj = c[rc0 + j];
+      const NodeInfo& cn = g->nodes[mx.child[j]];
+      const int c0 = sc.prog.node[mx.child[j]].c0;
+      const double S0 = sums[1 + 3 * j], S1 = sums[2 + 3 * j], S2 = sums[3 + 3 * j];
+      if (mx.gauss[j]) {
+        grad[cn.par[0]] -= fj * (c[c0 + 1] * S1 - c[c0 + 4] * S0);
+        grad[cn.par[1]] -= fj * (c[c0 + 1] * S2 - c[c0 + 5] * S0);
+      } else {
+        grad[cn.par[0]] -= fj * (S1 + (c[c0] - c[c0 + 4]) * S0);
+      }
+    }
+    const NodeInfo& rn = g->nodes[mx.root];
+    for (int j = 0; j < K - 1; ++j) grad[rn.par[j]] -= sums[1 + 3 * j] - sums[1 + 3 * (K - 1)];
+  } else if (sums) {
+    for (int j = 0; j < S; ++j)
+      if (g->slot_par[j] >= 0) grad[g->slot_par[j]] -= sums[1 + j];  // slots hold sum d ln P
+  }
+  for (int p = 0; p < np; ++p)
+    if (g->par[p].fixed) grad[p] = 0.0;
+}
+
+int32_t rows_for(int kind, int64_t n) {
+  if (n <= 0) return 0;
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cus[dev] <= 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+    cus[dev] = cu;
+  }
+  const int64_t nch = (n + kBlock - 1) / kBlock;
+  const int64_t minc = kind_light(kind) ? kMinChunksLight : 1;
+  const int64_t want = (nch + minc - 1) / minc;
+  const int64_t cap = (int64_t)cus[dev] * kRowsPerCU;
+  return (int32_t)(want < cap ? want : cap);
+}
+
 // ------------------------------------------------------------------ staging
 void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& sc) {
   sc.prog = g->prog;
@@ -613,21 +668,20 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     const NodeInfo& rootn = g->nodes[NN - 1];
     bool heavy = g->dz.node >= 0;
     // mixture of single-column EXP/GAUSS leaves: static kernel with its own
-    // accumulator layout [2 per child, then the fractions]
+    // accumulator layout [3 per child], combined on the host (MixInfo)
     bool mix = rootn.op == OP_ADD && (NN == 3 || NN == 4) && (int)rootn.child.size() == NN - 1 && P.n_cols == 1;
     for (int c : rootn.child)
       if (mix && g->nodes[c].op != OP_EXP && g->nodes[c].op != OP_GAUSS) mix = false;
     if (mix) {
       const int K = (int)rootn.child.size();
-      std::vector<int> acc(3 * K - 1, -1);
+      g->mix.K = K;
+      g->mix.root = NN - 1;
       for (int j = 0; j < K; ++j) {
-        const NodeInfo& cn = g->nodes[rootn.child[j]];
-        acc[2 * j] = cn.par[0];
-        if (cn.op == OP_GAUSS) acc[2 * j + 1] = cn.par[1];
+        g->mix.child[j] = rootn.child[j];
+        g->mix.gauss[j] = g->nodes[rootn.child[j]].op == OP_GAUSS;
       }
-      for (int j = 0; j < K - 1; ++j) acc[2 * K + j] = rootn.par[j];
-      g->slot_par = acc;
-      P.n_slots = 3 * K - 1;
+      g->slot_par.assign(3 * K, -1);
+      P.n_slots = 3 * K;
       int mask = 0;
       for (int j = 0; j < K; ++j)
         if (g->nodes[rootn.child[j]].op == OP_GAUSS) mask |= 1 << j;

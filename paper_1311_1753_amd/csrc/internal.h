@@ -78,28 +78,26 @@ struct EvalArgs {
   KProgram prog;
   const void* col[kMaxCols];   // device columns (double or float)
   int64_t n_events;
-  double* partials;            // [n_tiles][stride]: nll_sum, nll_comp, slot sums
-  int32_t stride;              // n_slots + 2
-  int32_t n_tiles;
+  double* partials;            // column-major [n_slots + 1][n_rows]: sum(-ln P), slot sums
+  int32_t n_rows;              // one block per row
+  int32_t pad;
 };
 
 // Header of a batched launch's device table, followed by the FitRec array.
 struct BatchHeader {
-  int32_t n_fits, total_tiles, tiles_per_block, pad;
+  int32_t n_fits, total_rows, pad0, pad1;
 };
 
 // Per-fit record of a batched launch (device memory).
 struct FitRec {
   const void* col[kMaxCols];
   int64_t n_events;
-  double* partials;
-  int32_t tile_begin;          // first global tile of this fit
-  int32_t n_tiles;
+  double* partials;            // column-major, column stride n_rows
+  int32_t row_begin;           // first global row of this fit
+  int32_t n_rows;
   double* result;              // n_slots + 1 doubles
-  int32_t stride;              // row stride of partials (n_slots + 2 of the graph)
   int32_t n_slots;             // slot columns to reduce (0: NLL only)
   int32_t active;
-  int32_t pad;
 };
 
 }  // namespace hf

@@ -20,13 +20,15 @@ enum KernelKind {
   KIND_MIX3 = 16
 };
 
-constexpr int kEptLight = 16;   // events per thread per tile, light kernels (tile 4096)
-constexpr int kEptHeavy = 2;    // amplitude kernels (tile 512)
+// Rows (blocks) per dataset: at most kRowsPerCU per compute unit, and at
+// least kMinChunksLight chunks of 256 events per row for the light kinds.
+constexpr int kRowsPerCU = 4;
+constexpr int kMinChunksLight = 4;
 
-int kind_ept(int kind);
-inline int64_t kind_tile(int kind) { return (int64_t)kBlock * kind_ept(kind); }
+// true for the single-column kinds (EXP, GAUSS, small trees, mixtures)
+bool kind_light(int kind);
 
-hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, int64_t n_tiles, hipStream_t st);
+hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st);
 hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st);
 hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, hipStream_t st);
 hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,

@@ -48,6 +48,16 @@ struct HostTerms {
   std::vector<double> dlnN;         // per event, per parameter
 };
 
+// Root ADD of K single-column EXP / GAUSS leaves evaluated by the static
+// mixture kernel: per child the kernel sums q, q z (EXP: q x) and q z^2,
+// which the host turns into parameter derivatives.
+struct MixInfo {
+  int K = 0;            // 0: not a mixture
+  int root = -1;
+  int child[3] = {-1, -1, -1};
+  bool gauss[3] = {false, false, false};
+};
+
 struct StagedCall {
   KProgram prog;                    // structure + constants for this call
   HostTerms ht;
@@ -67,6 +77,7 @@ struct pdf_graph {
   std::vector<int> col_of_obs;       // observable -> column (-1: unused)
   std::vector<int> obs_of_col;
   hf::DalitzInfo dz;
+  hf::MixInfo mix;
   std::mutex grid_mu;
 };
 
@@ -79,7 +90,7 @@ struct dataset {
   const void* col[hf::kMaxCols] = {nullptr};
   double ref[hf::kMaxCols] = {0.0};           // per-column reference (float path)
   double* partials = nullptr;
-  int64_t n_tiles = 0;
+  int32_t n_rows = 0;                         // one block per row (see rows_for)
   int64_t bytes = 0;
   double* res_host = nullptr;                 // pinned, device-mapped result row
   double* res_dev = nullptr;
@@ -99,5 +110,11 @@ bool dalitz_inside(const DalitzInfo& dz, double s12, double s13);
 int eval_one(const pdf_graph* g, const dataset* d, const double* theta, hipStream_t st, bool want_grad, double* nll,
              double* grad);
 int n_free(const pdf_graph* g);
+// Rows of a dataset of n events for a graph of kernel kind `kind` on the
+// current device.
+int32_t rows_for(int kind, int64_t n);
+// NLL and gradient from the reduced sums [sum(-ln P), slot sums] of one
+// evaluation (sums may be null for an empty dataset); grad may be null.
+void assemble(const pdf_graph* g, const StagedCall& sc, const double* sums, int64_t n, double* nll, double* grad);
 
 }  // namespace hf

@@ -6,8 +6,9 @@ Tolerances (stated for every result):
     max(|NLL|, sum_i |ln P_i|);
   * gradient component j: the same relative tolerance of sum_i |d_j ln P_i|;
   * fitted parameters: within 1e-3 sigma of the oracle's fit.
-Sizes span several tiles and a ragged tail (4096-event tiles for the light
-kernels, 512 for the amplitude kernels)."""
+Sizes span many rows (a row is a block's equal share of the 256-event chunks)
+and a ragged tail; the row-geometry test adds sizes at chunk boundaries and
+one whose rows hold full groups of 8 chunks plus a remainder."""
 import math
 
 import numpy as np
@@ -102,6 +103,30 @@ def test_batched_equals_single_bitwise(P, stream, name, prec):
     # the same fit alone in a batch of one
     n1, g1 = P.nll_grad_batched(g, dss[1:2], ths[1:2], stream)
     assert n1[0] == nll_b[1] and np.array_equal(g1[0], grad_b[1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 4 * 2048 + 1, 2_621_440 + 129])
+def test_row_geometry_edges(P, stream, n, prec):
+    """Single events, partial and exact chunks, one partial chunk after many
+    rows, and 2.6e6 events (rows of 10 chunks: one full group of 8 with the
+    next group's loads in flight, then a remainder with the ragged chunk)."""
+    print(f"\n[case] row geometry c2 n={n} prec={prec}", flush=True)
+    sp = get_spec("c2")
+    data = data_for("c2", n, 40 + n % 97)
+    om = oracle_for("c2")
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec, stream)
+    free = g.free_mask()
+    th = perturbed_theta(om, sp, seed=41)
+    v_ref, g_ref = om.nll(th, data, grad=True)
+    v, gr = P.nll_grad(g, ds, th, stream)
+    s = nll_scale(om, th, data)
+    gs = grad_scale(om, th, data)
+    print(f"  nll rel {abs(v - v_ref) / s:.2e}; grad rel max {np.max(np.abs(gr - g_ref)[free] / gs[free]):.2e}",
+          flush=True)
+    assert abs(v - v_ref) <= TOL[prec] * s
+    assert np.all(np.abs(gr - g_ref)[free] <= TOL[prec] * gs[free])
 
 
 def test_empty_and_domain_errors(P, stream):

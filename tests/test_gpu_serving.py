@@ -1,5 +1,5 @@
 """Continuous batching on the GPU: a fit's result is the same alone and in
-any mix (bitwise: per-fit tiles and fixed-order reductions), admission
+any mix (bitwise: per-fit rows and fixed-order reductions), admission
 respects the device-memory budget, and the request loop serves every fit."""
 import numpy as np
 import pytest

@@ -27,6 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HIP events (and a full stream synchronisation) bracket every PROFILE_EVERY-th
+# evaluation of a timed loop; the other evaluations wait on the completion flag.
+PROFILE_EVERY = 10
 
 
 def parse():
@@ -158,7 +161,7 @@ def other_workload(args, P, S, torch, stream):
         for _ in range(args.warmup):
             P.nll_grad(g, ds, truth, stream)
         k = max(20, args.steps // (1 if args.workload == "c1" else 10))
-        P.profile(True)
+        P.profile(True, every=PROFILE_EVERY)
         el = time_evals(P, g, ds, [truth] * k, stream)
         e_ms, r_ms, cnt = P.profile(False)
         out[prec] = {"events_evals_per_s": n * k / el, "ms_per_eval": el / k * 1e3,
@@ -219,7 +222,7 @@ def main():
         P.nll_grad(g, ds32, th, stream)
     thetas = theta_sequence(truth, args.steps, rng)
     torch.cuda.synchronize()
-    P.profile(True)
+    P.profile(True, every=PROFILE_EVERY)
     el = time_evals(P, g, ds32, thetas, stream)
     eval_ms, red_ms, ncalls = P.profile(False)
     ms_step = el / args.steps * 1e3
@@ -233,10 +236,10 @@ def main():
     # ---------------- FP64 analytic and FP64 NLL-only (numerical-gradient path)
     k64 = max(50, args.steps // 10)
     th64 = theta_sequence(truth, k64, rng)
-    P.profile(True)
+    P.profile(True, every=PROFILE_EVERY)
     el64 = time_evals(P, g, ds64, th64, stream)
     e64, _, c64 = P.profile(False)
-    P.profile(True)
+    P.profile(True, every=PROFILE_EVERY)
     el64n = time_evals(P, g, ds64, th64, stream, grad=False)
     e64n, _, c64n = P.profile(False)
     n_free = int(g.free_mask().sum())

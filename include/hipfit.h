@@ -143,7 +143,10 @@ int64_t dataset_device_bytes(const dataset* d);
 /* ------------------------------------------------------------------ likelihood
  * params: n_par doubles (external values, fixed ones included).  Runs the
  * per-event evaluation and the deterministic two-pass reduction on
- * `hip_stream` and blocks until the result is on the host.  A density <= 0 or
+ * `hip_stream` and blocks until the result is on the host (the calling thread
+ * spins on a flag that the reduction sets in mapped host memory, checking the
+ * stream for errors while it waits).  One dataset must not be evaluated from
+ * two threads at once.  A density <= 0 or
  * not finite at any event sets *nll = +INF and returns HF_E_DOMAIN.
  * Results are bitwise reproducible for the same inputs. */
 int nll_eval(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream,
@@ -230,10 +233,11 @@ int batch_cancel(batch_engine* b, int64_t tag);
  * points for the DALITZ/TDDP node `node` of a graph: out[i] = 1 inside. */
 int hf_dalitz_inside(const pdf_graph* g, int32_t node, int64_t n, const double* s12,
                      const double* s13, uint8_t* out);
-/* Kernel timing for measurement: enable = 1 resets the counters and starts
- * recording HIP events on the caller's stream around the likelihood kernel
- * and the reduction of every nll_eval / nll_grad; enable = 0 stops; any other
- * value only reads.  Outputs (nullable): total milliseconds of the likelihood
+/* Kernel timing for measurement: enable = k >= 1 resets the counters and
+ * starts recording HIP events on the caller's stream around the likelihood
+ * kernel and the reduction of every k-th nll_eval / nll_grad (those calls
+ * wait with hipStreamSynchronize instead of the completion flag); enable = 0
+ * stops; a negative value only reads.  Outputs (nullable): total milliseconds of the likelihood
  * kernels and of the reductions, and the number of timed calls so far.  Not
  * for concurrent use from several threads. */
 int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch);

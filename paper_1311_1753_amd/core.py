@@ -281,11 +281,12 @@ def minimize(fg, params, x0=None, max_iter=500, edm_tol=1e-10, want_errors=True,
             "n_eval": s.n_eval, "status": _lib.STATUS_NAMES.get(s.status, str(s.status))}
 
 
-def profile(enable=None):
-    """Kernel timing hook: profile(True) resets and starts, profile(False)
-    stops; returns (eval_ms, reduce_ms, n_calls) accumulated so far."""
+def profile(enable=None, every=1):
+    """Kernel timing hook: profile(True) resets and starts timing every
+    `every`-th evaluation, profile(False) stops; returns (eval_ms, reduce_ms,
+    n_timed_calls) accumulated so far."""
     e, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-    flag = -1 if enable is None else int(bool(enable))
+    flag = -1 if enable is None else (max(1, int(every)) if enable else 0)
     check(lib().hf_profile(flag, ctypes.byref(e), ctypes.byref(r), ctypes.byref(n)))
     return e.value, r.value, n.value
 

@@ -7,6 +7,7 @@
 // the host, launches the tile kernel and the fixed-order reduction on the
 // caller's stream, and reads the reduced row from pinned, device-mapped host
 // memory written directly by the reduction kernel.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -31,10 +32,13 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
 // Optional kernel timing (hf_profile): HIP events recorded on the caller's
-// stream around the likelihood kernel and the reduction of eval_one.
+// stream around the likelihood kernel and the reduction of every
+// `every`-th eval_one.
 struct Profile {
   bool on = false;
   bool init = false;
+  int every = 1;
+  int64_t calls = 0;
   hipEvent_t e[3];
   double eval_ms = 0.0, reduce_ms = 0.0;
   int64_t n = 0;
@@ -42,12 +46,39 @@ struct Profile {
 static Profile g_prof;
 static std::mutex g_prof_mu;
 
+// Waits for the reduction of one evaluation: spins on the flag that the
+// reduction kernel sets after its result is visible in mapped host memory,
+// asking the stream every 4096 spins (errors, or a finished stream without
+// the flag, end the wait).
+static hipError_t wait_result(const dataset* d, hipStream_t st) {
+  const volatile int64_t* flag = (const volatile int64_t*)(d->res_host + kMaxSlots + 1);
+  for (uint64_t spin = 1;; ++spin) {
+    if (*flag == d->seq) {
+      std::atomic_thread_fence(std::memory_order_acquire);
+      return hipSuccess;
+    }
+    if ((spin & 4095) == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        if (*flag == d->seq) {
+          std::atomic_thread_fence(std::memory_order_acquire);
+          return hipSuccess;
+        }
+        return hipErrorUnknown;
+      }
+      if (e != hipErrorNotReady) return e;
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 static int ensure_result_buffer(const dataset* dc) {
   dataset* d = const_cast<dataset*>(dc);
   if (d->res_host) return HF_OK;
   void* h = nullptr;
   hipError_t e = hipHostMalloc(&h, (kMaxSlots + 2) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
   if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(result row)");
+  std::memset(h, 0, (kMaxSlots + 2) * sizeof(double));  // flag 0: no evaluation finished yet
   void* dv = nullptr;
   e = hipHostGetDevicePointer(&dv, h, 0);
   if (e != hipSuccess) {
@@ -81,7 +112,7 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     a.partials = d->partials;
     a.n_rows = d->n_rows;
     a.pad = 0;
-    const bool prof = g_prof.on;
+    const bool prof = g_prof.on && (g_prof.calls++ % g_prof.every) == 0;
     if (prof) hipEventRecord(g_prof.e[0], st);
     hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st);
     if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
@@ -93,11 +124,20 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     fr.result = d->res_dev;
     fr.n_slots = want_grad ? S : 0;
     fr.active = 1;
+    dataset* dm = const_cast<dataset*>(d);
+    dm->seq += 1;
+    fr.flag = (int64_t*)(d->res_dev + kMaxSlots + 1);
+    fr.seq = d->seq;
     e = launch_reduce_one(fr, st);
     if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
-    if (prof) hipEventRecord(g_prof.e[2], st);
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (prof) {
+      hipEventRecord(g_prof.e[2], st);
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    } else {
+      e = wait_result(d, st);
+      if (e != hipSuccess) return hip_fail(e, "waiting for the reduction");
+    }
     if (prof) {
       float t1 = 0.f, t2 = 0.f;
       hipEventElapsedTime(&t1, g_prof.e[0], g_prof.e[1]);
@@ -252,7 +292,7 @@ extern "C" int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, in
   if (eval_ms) *eval_ms = g_prof.eval_ms;
   if (reduce_ms) *reduce_ms = g_prof.reduce_ms;
   if (n_launch) *n_launch = g_prof.n;
-  if (enable == 1) {
+  if (enable >= 1) {
     if (!g_prof.init) {
       for (int i = 0; i < 3; ++i) {
         hipError_t e = hipEventCreate(&g_prof.e[i]);
@@ -262,6 +302,8 @@ extern "C" int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, in
     }
     g_prof.eval_ms = g_prof.reduce_ms = 0.0;
     g_prof.n = 0;
+    g_prof.calls = 0;
+    g_prof.every = enable;
     g_prof.on = true;
   } else if (enable == 0) {
     g_prof.on = false;

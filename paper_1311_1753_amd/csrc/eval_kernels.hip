@@ -759,6 +759,7 @@ __device__ __forceinline__ void reduce_fit(const FitRec& fr) {
     }
   }
   __syncthreads();
+  __shared__ double fin[kMaxRedCols];
   const int t = threadIdx.x;
   if (t < nc) {
     double s = colsum[t][0][0], c = colsum[t][0][1];
@@ -768,7 +769,17 @@ __device__ __forceinline__ void reduce_fit(const FitRec& fr) {
       s = ns;
       c = (c + colsum[t][k][1]) + e;
     }
-    fr.result[t] = s + c;
+    fin[t] = s + c;
+  }
+  __syncthreads();
+  // one thread stores the result, then (system-scope release) the flag the
+  // host may spin on
+  if (t == 0) {
+    for (int j = 0; j < nc; ++j) fr.result[j] = fin[j];
+    if (fr.flag) {
+      __threadfence_system();
+      *(volatile int64_t*)fr.flag = fr.seq;
+    }
   }
 }
 

@@ -98,6 +98,8 @@ struct FitRec {
   double* result;              // n_slots + 1 doubles
   int32_t n_slots;             // slot columns to reduce (0: NLL only)
   int32_t active;
+  int64_t* flag;               // nullable: set to `seq` after the result is visible to the host
+  int64_t seq;
 };
 
 }  // namespace hf

@@ -92,8 +92,9 @@ struct dataset {
   double* partials = nullptr;
   int32_t n_rows = 0;                         // one block per row (see rows_for)
   int64_t bytes = 0;
-  double* res_host = nullptr;                 // pinned, device-mapped result row
+  double* res_host = nullptr;                 // pinned, device-mapped: result row, then the completion flag
   double* res_dev = nullptr;
+  int64_t seq = 0;                            // completion flag value of the last evaluation
 };
 
 namespace hf {

@@ -44,9 +44,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 5 times (reference for the HBM byte counters)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c1l", "c2l"],
                     help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
-                         "c3 Dalitz amplitude sum, c4 time-dependent Dalitz: throughput only")
+                         "c3 Dalitz amplitude sum, c4 time-dependent Dalitz, c1l / c2l the c1 / c2 "
+                         "models at 2^28 / 10^8 events (beyond the last-level cache): throughput only")
     return ap.parse_args()
 
 
@@ -142,11 +143,15 @@ def other_workload(args, P, S, torch, stream):
     """Throughput of the NLL+gradient kernels on one of the other workloads
     (events sampled flat over the Dalitz plot for c3/c4: the evaluation cost
     does not depend on where in the plot the events are)."""
-    spec = S.workload(args.workload)
-    n = spec["n_events"]
+    large = {"c1l": ("c1", 1 << 28), "c2l": ("c2", 10 ** 8)}
+    base = large[args.workload][0] if args.workload in large else args.workload
+    spec = S.workload(base)
+    n = large[args.workload][1] if args.workload in large else spec["n_events"]
     g = P.Graph.from_spec(spec)
-    if args.workload == "c1":
-        data = S.gen_c1()
+    if base == "c1":
+        data = S.gen_c1(n=n, seed=spec["seed"])
+    elif base == "c2":
+        data = S.gen_c2(n=n, seed=spec["seed"])
     else:
         data = S.gen_flat_box(n, spec["seed"], g.dalitz_inside)
         if args.workload == "c4":
@@ -161,6 +166,8 @@ def other_workload(args, P, S, torch, stream):
         for _ in range(args.warmup):
             P.nll_grad(g, ds, truth, stream)
         k = max(20, args.steps // (1 if args.workload == "c1" else 10))
+        if args.workload in large:
+            k = max(20, args.steps // 20)
         P.profile(True, every=PROFILE_EVERY)
         el = time_evals(P, g, ds, [truth] * k, stream)
         e_ms, r_ms, cnt = P.profile(False)
@@ -170,12 +177,24 @@ def other_workload(args, P, S, torch, stream):
     ncols = len(spec["obs"])
     bytes32 = 4.0 * ncols * n
     k_ms = out["fp32"]["kernel_ms"]
+    # device copy of the same footprint (read + write bytes over time)
+    a = torch.empty(int(bytes32), dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    out["copy_same_footprint_gbs"] = 2.0 * bytes32 * 20 / (time.perf_counter() - t0) / 1e9
+    del a, b
     res = {
         "metric": "events x NLL+grad evaluations per second", "value": out["fp32"]["events_evals_per_s"],
         "unit": "events*evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": out["fp32"]["ms_per_eval"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": spec["name"], "n_events": n},
+        "config": {"workload": spec["name"] + ("_large" if args.workload in large else ""), "n_events": n},
         "roofline": {"bound": "hbm", "achieved": bytes32 / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": bytes32 / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": None, "extra": out,

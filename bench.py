@@ -88,23 +88,42 @@ def fit_timing(P, g, ds, stream, mode, reps):
     return float(np.median(out)), res
 
 
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, data, seconds):
-    """The oracle (plain FP64 C++) on a bounded sample, all host threads."""
+    """The oracle (plain FP64 C++) on a bounded sample: all host threads (the
+    reported baseline), then one thread."""
     from oracle import oracle as O
     m = O.Model(spec)
     nt = O.n_threads_default()
     n = min(2_000_000, data["x"].size)
     sample = {"x": np.ascontiguousarray(data["x"][:n])}
     th = m.theta(spec["truth"])
-    m.nll(th, sample, grad=True, n_threads=nt)
-    reps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds or reps < 2:
-        m.nll(th, sample, grad=True, n_threads=nt)
-        reps += 1
-    el = time.perf_counter() - t0
-    return {"value": n * reps / el, "unit": "events*NLL+grad evals/s", "cores": nt, "kind": "oracle",
-            "sample": "first %d of the 10^7 events, %d NLL+gradient evaluations in %.1f s" % (n, reps, el)}
+
+    def rate(threads, budget):
+        m.nll(th, sample, grad=True, n_threads=threads)
+        reps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget or reps < 2:
+            m.nll(th, sample, grad=True, n_threads=threads)
+            reps += 1
+        el = time.perf_counter() - t0
+        return n * reps / el, reps, el
+
+    v, reps, el = rate(nt, seconds)
+    v1, reps1, el1 = rate(1, max(2.0, seconds / 4))
+    return {"value": v, "unit": "events*NLL+grad evals/s", "cores": nt, "kind": "oracle",
+            "sample": "first %d of the 10^7 events, %d NLL+gradient evaluations in %.1f s" % (n, reps, el),
+            "one_thread_value": v1, "one_thread_sample": "%d evaluations in %.1f s" % (reps1, el1),
+            "cpu_model": _cpu_model()}
 
 
 def serving_bench(P, S, n_req):

@@ -10,6 +10,7 @@
 // device memory, the eval grid is fixed and surplus blocks exit at once.
 // Results are written by the reduction straight into mapped pinned memory.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -34,8 +35,10 @@ struct BatchTables {
   double* c64_d = nullptr;
   float* c32_h = nullptr;
   float* c32_d = nullptr;
-  double* res_h = nullptr;        // mapped pinned, [max_fits][S + 1]
+  double* res_h = nullptr;        // mapped pinned, [max_fits][S + 2]: result row, completion flag
   double* res_d = nullptr;
+  int64_t seq = 0;                // completion flag value of the last step
+  int RS() const { return S + 2; }
   size_t tab_bytes = 0;
 
   FitRec* fits_h() { return (FitRec*)(hdr_h + 1); }
@@ -53,8 +56,9 @@ struct BatchTables {
     if ((e = hipMalloc((void**)&c64_d, (size_t)mf * n_const * 8)) != hipSuccess) return hip_fail(e, "batch constants");
     if ((e = hipHostMalloc((void**)&c32_h, (size_t)mf * n_const * 4, hipHostMallocDefault)) != hipSuccess) return hip_fail(e, "batch constants");
     if ((e = hipMalloc((void**)&c32_d, (size_t)mf * n_const * 4)) != hipSuccess) return hip_fail(e, "batch constants");
-    if ((e = hipHostMalloc((void**)&res_h, (size_t)mf * (S + 1) * 8, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
+    if ((e = hipHostMalloc((void**)&res_h, (size_t)mf * (S + 2) * 8, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
       return hip_fail(e, "batch results");
+    std::memset(res_h, 0, (size_t)mf * (S + 2) * 8);
     if ((e = hipHostGetDevicePointer((void**)&res_d, res_h, 0)) != hipSuccess) return hip_fail(e, "batch results");
     std::memset(hdr_h, 0, tab_bytes);
     return HF_OK;
@@ -93,6 +97,7 @@ static void fill_tables(const pdf_graph* g, BatchTables& t, const std::vector<co
   const int n = (int)ds.size();
   FitRec* fr = t.fits_h();
   int row = 0;
+  t.seq += 1;
   for (int i = 0; i < t.max_fits; ++i) {
     std::memset(&fr[i], 0, sizeof(FitRec));
     if (i < n) {
@@ -101,7 +106,9 @@ static void fill_tables(const pdf_graph* g, BatchTables& t, const std::vector<co
       fr[i].partials = ds[i]->partials;
       fr[i].row_begin = row;
       fr[i].n_rows = ds[i]->n_rows;
-      fr[i].result = t.res_d + (size_t)i * (t.S + 1);
+      fr[i].result = t.res_d + (size_t)i * t.RS();
+      fr[i].flag = (int64_t*)(t.res_d + (size_t)i * t.RS() + t.S + 1);
+      fr[i].seq = t.seq;
       fr[i].n_slots = g->prog.n_slots;
       fr[i].active = 1;
       row += ds[i]->n_rows;
@@ -111,6 +118,27 @@ static void fill_tables(const pdf_graph* g, BatchTables& t, const std::vector<co
   }
   t.hdr_h->n_fits = n;
   t.hdr_h->total_rows = row;
+}
+
+// Waits until the reduction has set the completion flag of each of the first
+// n fits (spinning on mapped host memory, asking the stream every 4096 spins).
+static hipError_t wait_fits(const BatchTables& t, int n, hipStream_t st) {
+  for (int k = 0; k < n; ++k) {
+    const volatile int64_t* flag = (const volatile int64_t*)(t.res_h + (size_t)k * t.RS() + t.S + 1);
+    for (uint64_t spin = 1; *flag != t.seq; ++spin) {
+      if ((spin & 4095) == 0) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipSuccess) {
+          if (*flag == t.seq) break;
+          return hipErrorUnknown;
+        }
+        if (e != hipErrorNotReady) return e;
+      }
+      __builtin_ia32_pause();
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return hipSuccess;
 }
 
 static void finish_fit(const pdf_graph* g, const dataset* d, const StagedCall& sc, const double* row, double* nll,
@@ -156,10 +184,10 @@ extern "C" int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int
       if (rc) { t.release(); return rc; }
       fill_tables(g, t, ds, scp);
       hipError_t e = enqueue_step(g, d[0]->prec == HF_FP32_EVAL, t, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = wait_fits(t, (int)ds.size(), st);
       if (e != hipSuccess) { t.release(); return hip_fail(e, "nll_grad_batched"); }
       for (size_t k = 0; k < ds.size(); ++k)
-        std::memcpy(&rows[(size_t)which[k] * (g->prog.n_slots + 1)], t.res_h + k * (t.S + 1),
+        std::memcpy(&rows[(size_t)which[k] * (g->prog.n_slots + 1)], t.res_h + k * t.RS(),
                     (t.S + 1) * sizeof(double));
       t.release();
     }
@@ -327,13 +355,13 @@ extern "C" int batch_step(batch_engine* b, int32_t* n_active_out, int32_t* n_don
       } else {
         e = enqueue_step(g, fp32, b->t, b->st);
       }
-      if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+      if (e == hipSuccess) e = wait_fits(b->t, (int)ds.size(), b->st);
       if (e != hipSuccess) return hip_fail(e, "batch_step: launch");
       for (size_t k = 0; k < ds.size(); ++k) {
         auto& s = b->slots[idx[k]];
         s.g.assign(np, 0.0);
         double f;
-        finish_fit(g, s.d, s.sc, b->t.res_h + k * (b->t.S + 1), &f, s.g.data());
+        finish_fit(g, s.d, s.sc, b->t.res_h + k * b->t.RS(), &f, s.g.data());
         ++s.n_eval;
         s.m.tell(f, s.g);
         if (s.m.done()) retire_running(b, s);

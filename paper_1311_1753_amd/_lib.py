@@ -80,8 +80,9 @@ SIGNATURES = {
                                       ctypes.POINTER(_VP)]),
     "dataset_free": (None, [_VP]),
     "dataset_device_bytes": (ctypes.c_int64, [_VP]),
-    "nll_eval": (ctypes.c_int, [_VP, _VP, _DP, _VP, _DP]),
-    "nll_grad": (ctypes.c_int, [_VP, _VP, _DP, _VP, _DP, _DP]),
+    # theta and grad are passed as raw addresses (numpy .ctypes.data)
+    "nll_eval": (ctypes.c_int, [_VP, _VP, _VP, _VP, _DP]),
+    "nll_grad": (ctypes.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
     "nll_grad_batched": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int32, _DP, _VP, _DP, _DP]),
     "fit": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(hf_fit_opts), _VP, _DP, _DP, _DP,
                            ctypes.POINTER(hf_fit_summary)]),

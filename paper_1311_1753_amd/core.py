@@ -201,19 +201,26 @@ def _dp(a):
 def nll_eval(graph, ds, theta, stream=None, allow_domain=True):
     """NLL at theta (+inf outside the density's domain when allow_domain)."""
     th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.size != graph.n_par:
+        raise ValueError("theta must have %d entries" % graph.n_par)
     out = ctypes.c_double()
-    check(lib().nll_eval(graph.handle, ds.handle, _dp(th), _stream_ptr(stream), ctypes.byref(out)),
-          allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
+    rc = lib().nll_eval(graph.handle, ds.handle, th.ctypes.data, _stream_ptr(stream), ctypes.byref(out))
+    if rc < 0:
+        check(rc, allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
     return out.value
 
 
 def nll_grad(graph, ds, theta, stream=None, allow_domain=True):
     """(NLL, dNLL/dtheta) at theta from the per-event adjoint kernels."""
     th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.size != graph.n_par:
+        raise ValueError("theta must have %d entries" % graph.n_par)
     out = ctypes.c_double()
-    g = np.zeros(graph.n_par)
-    check(lib().nll_grad(graph.handle, ds.handle, _dp(th), _stream_ptr(stream), ctypes.byref(out), _dp(g)),
-          allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
+    g = np.empty(graph.n_par)
+    rc = lib().nll_grad(graph.handle, ds.handle, th.ctypes.data, _stream_ptr(stream), ctypes.byref(out),
+                        g.ctypes.data)
+    if rc < 0:
+        check(rc, allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
     return out.value, g
 
 

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -219,10 +220,16 @@ int32_t rows_for(int kind, int64_t n) {
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
     cus[dev] = cu;
   }
+  // rows per compute unit: kRowsPerCU, or HIPFIT_ROWS_PER_CU (1..64) for tuning
+  static const int per_cu = [] {
+    const char* v = std::getenv("HIPFIT_ROWS_PER_CU");
+    const int k = v ? std::atoi(v) : 0;
+    return k >= 1 && k <= 64 ? k : kRowsPerCU;
+  }();
   const int64_t nch = (n + kBlock - 1) / kBlock;
   const int64_t minc = kind_light(kind) ? kMinChunksLight : 1;
   const int64_t want = (nch + minc - 1) / minc;
-  const int64_t cap = (int64_t)cus[dev] * kRowsPerCU;
+  const int64_t cap = (int64_t)cus[dev] * per_cu;
   return (int32_t)(want < cap ? want : cap);
 }
 

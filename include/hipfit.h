@@ -234,10 +234,10 @@ int batch_cancel(batch_engine* b, int64_t tag);
 int hf_dalitz_inside(const pdf_graph* g, int32_t node, int64_t n, const double* s12,
                      const double* s13, uint8_t* out);
 /* Kernel timing for measurement: enable = k >= 1 resets the counters and
- * starts recording HIP events on the caller's stream around the likelihood
- * kernel and the reduction of every k-th nll_eval / nll_grad (those calls
- * wait with hipStreamSynchronize instead of the completion flag); enable = 0
- * stops; a negative value only reads.  Outputs (nullable): total milliseconds of the likelihood
+ * starts timing the likelihood kernel and the reduction of every k-th
+ * nll_eval / nll_grad with HIP events that take the dispatches' own start and
+ * end time stamps (those calls wait with hipStreamSynchronize instead of the
+ * completion flag); enable = 0 stops; a negative value only reads.  Outputs (nullable): total milliseconds of the likelihood
  * kernels and of the reductions, and the number of timed calls so far.  Not
  * for concurrent use from several threads. */
 int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch);

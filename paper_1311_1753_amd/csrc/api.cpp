@@ -31,15 +31,15 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-// Optional kernel timing (hf_profile): HIP events recorded on the caller's
-// stream around the likelihood kernel and the reduction of every
-// `every`-th eval_one.
+// Optional kernel timing (hf_profile): HIP events that take the start and
+// end time stamps of the likelihood kernel's and the reduction's dispatches
+// (hipExtLaunchKernel) of every `every`-th eval_one.
 struct Profile {
   bool on = false;
   bool init = false;
   int every = 1;
   int64_t calls = 0;
-  hipEvent_t e[3];
+  hipEvent_t e[4];
   double eval_ms = 0.0, reduce_ms = 0.0;
   int64_t n = 0;
 };
@@ -113,10 +113,9 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     a.n_rows = d->n_rows;
     a.pad = 0;
     const bool prof = g_prof.on && (g_prof.calls++ % g_prof.every) == 0;
-    if (prof) hipEventRecord(g_prof.e[0], st);
-    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st);
+    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
+                               prof ? g_prof.e[1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
-    if (prof) hipEventRecord(g_prof.e[1], st);
     FitRec fr;
     std::memset(&fr, 0, sizeof(fr));
     fr.partials = d->partials;
@@ -128,10 +127,9 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     dm->seq += 1;
     fr.flag = (int64_t*)(d->res_dev + kMaxSlots + 1);
     fr.seq = d->seq;
-    e = launch_reduce_one(fr, st);
+    e = launch_reduce_one(fr, st, prof ? g_prof.e[2] : nullptr, prof ? g_prof.e[3] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
     if (prof) {
-      hipEventRecord(g_prof.e[2], st);
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     } else {
@@ -141,7 +139,7 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     if (prof) {
       float t1 = 0.f, t2 = 0.f;
       hipEventElapsedTime(&t1, g_prof.e[0], g_prof.e[1]);
-      hipEventElapsedTime(&t2, g_prof.e[1], g_prof.e[2]);
+      hipEventElapsedTime(&t2, g_prof.e[2], g_prof.e[3]);
       g_prof.eval_ms += t1;
       g_prof.reduce_ms += t2;
       g_prof.n += 1;
@@ -294,7 +292,7 @@ extern "C" int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, in
   if (n_launch) *n_launch = g_prof.n;
   if (enable >= 1) {
     if (!g_prof.init) {
-      for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < 4; ++i) {
         hipError_t e = hipEventCreate(&g_prof.e[i]);
         if (e != hipSuccess) return hip_fail(e, "hf_profile: hipEventCreate");
       }

@@ -16,6 +16,8 @@ template <> struct Mth<float> {
     return __builtin_fmaf(__builtin_amdgcn_logf(x), 0.693147180559945309f, m);
   }
   static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+  static __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
   static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -26,6 +28,8 @@ template <> struct Mth<double> {
   static __device__ __forceinline__ double ln(double x) { return ::log(x); }
   static __device__ __forceinline__ double ln_add(double x, double m) { return m + ::log(x); }
   static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+  static __device__ __forceinline__ double ex2(double x) { return ::exp2(x); }
+  static __device__ __forceinline__ double lg2(double x) { return ::log2(x); }
   static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
   static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }

@@ -20,6 +20,7 @@
 // reference; location differences (x - a, x - mu, m0^2 - s) are formed from
 // the stored offset and a double constant (in double, or as a float hi + lo
 // pair), then rounded once.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -271,9 +272,10 @@ __device__ __forceinline__ void row_chunks(int64_t n_events, int n_rows, int r, 
 // ------------------------------------------------------------------ row loops
 // Single-column evaluators (mixtures, single EXP / GAUSS leaves): groups of
 // U chunks, the loads of the next group in flight while the current one is
-// evaluated.  An evaluator adds -ln P to `nl` and its NA gradient
+// evaluated.  An evaluator adds its NLL term to `nl` and its NA gradient
 // accumulators to `ga` (type T over one group); the group sums go into the
-// per-thread double accumulators acc[0] (NLL) and acc[1 + j].  Only the last
+// per-thread double accumulators: acc[0] += kNllScale * (group sum of nl),
+// acc[1 + j] += group sum of ga[j].  Only the last
 // chunk of a dataset can be partial, so all groups but the last are
 // unchecked.
 template <typename T, int U, class Ev>
@@ -304,7 +306,7 @@ __device__ __forceinline__ void light_row(const Ev& ev, const typename Col<T>::S
     for (int j = 0; j < NA; ++j) ga[j] = T(0);
 #pragma unroll
     for (int k = 0; k < U; ++k) ev((T)cur[k], nl, ga);
-    acc[0] += (double)nl;
+    acc[0] = __builtin_fma((double)nl, Ev::kNllScale, acc[0]);
 #pragma unroll
     for (int j = 0; j < NA; ++j) acc[1 + j] += (double)ga[j];
     c += U;
@@ -324,7 +326,7 @@ __device__ __forceinline__ void light_row(const Ev& ev, const typename Col<T>::S
       const int64_t i = (c + k) * kBlock + t;
       if (c + k < c1 && i < n) ev((T)cur[k], nl, ga);
     }
-    acc[0] += (double)nl;
+    acc[0] = __builtin_fma((double)nl, Ev::kNllScale, acc[0]);
 #pragma unroll
     for (int j = 0; j < NA; ++j) acc[1 + j] += (double)ga[j];
   }
@@ -400,18 +402,22 @@ __device__ __forceinline__ double neg_abs(double x) { return -__builtin_fabs(x);
 template <typename T, int K, int MASK, bool GRAD>
 struct MixEv {
   static constexpr int NA = GRAD ? 3 * K : 0;
+  static constexpr double kNllScale = -0.69314718055994530942;  // -ln 2: nl holds sum log2 P
+  // the log-densities are carried in base 2: lv2 = log2 e * ln(f_j / N_j)
   Split<T> loc[K];  // GAUSS: column reference - mu
-  Split<T> cst[K];  // GAUSS: ln N ; EXP: alpha (column reference - a) - ln N
-  T k1[K];          // GAUSS: 1 / sigma ; EXP: alpha
+  Split<T> cst[K];  // GAUSS: log2 e ln N ; EXP: log2 e (alpha (column reference - a) - ln N)
+  T k1[K];          // GAUSS: 1 / sigma ; EXP: log2 e alpha
   T f[K];           // fractions, the last one 1 - sum of the others
 
+  // adds log2 P to nl (the caller scales by -ln 2)
   __device__ __forceinline__ void operator()(T x, T& nl, T* ga) const {
+    constexpr T kHalfLog2e = T(-0.5 * 1.44269504088896340736);
     T lv[K], za[K], zb[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       if ((MASK >> j) & 1) {
         const T z = loc[j].add_to(x) * k1[j], zz = z * z;
-        lv[j] = cst[j].fma_sub(T(-0.5), zz);
+        lv[j] = cst[j].fma_sub(kHalfLog2e, zz);
         za[j] = z;
         zb[j] = zz;
       } else {
@@ -425,11 +431,11 @@ struct MixEv {
       // the larger term has e = 1: one exponential per event
       const T dd = lv[1] - lv[0];
       const bool up = dd > T(0);
-      const T eo = Mth<T>::ex(neg_abs(dd));
+      const T eo = Mth<T>::ex2(neg_abs(dd));
       const T m = up ? lv[1] : lv[0];
       const T fa = up ? f[1] : f[0], fb = up ? f[0] : f[1];
       const T s = Mth<T>::fma(fb, eo, fa);
-      nl -= Mth<T>::ln_add(s, m);
+      nl += m + Mth<T>::lg2(s);
       if (GRAD) {
         const T is = Mth<T>::rcp(s), qo = eo * is;
         q[0] = up ? qo : is;
@@ -442,10 +448,10 @@ struct MixEv {
       T e[K], s = T(0);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        e[j] = Mth<T>::ex(lv[j] - m);
+        e[j] = Mth<T>::ex2(lv[j] - m);
         s = Mth<T>::fma(f[j], e[j], s);
       }
-      nl -= Mth<T>::ln_add(s, m);
+      nl += m + Mth<T>::lg2(s);
       if (GRAD) {
         const T is = Mth<T>::rcp(s);
 #pragma unroll
@@ -466,18 +472,20 @@ struct MixEv {
 // Constants of a mixture from the staged table (EXP / GAUSS / ADD layouts).
 template <typename T, int K, int MASK, bool GRAD>
 __device__ __forceinline__ MixEv<T, K, MASK, GRAD> make_mix(const KProgram& P, const CS& cs) {
+  constexpr double kLog2e = 1.44269504088896340736;
   MixEv<T, K, MASK, GRAD> ev;
   const KNode& rn = P.node[P.n_nodes - 1];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int c0 = P.node[P.child[rn.child0 + j]].c0;
-    ev.k1[j] = cs.get<T>(c0 + 1);
     if ((MASK >> j) & 1) {
+      ev.k1[j] = cs.get<T>(c0 + 1);
       ev.loc[j].set(cs.d[c0]);
-      ev.cst[j].set(cs.d[c0 + 2]);
+      ev.cst[j].set(kLog2e * cs.d[c0 + 2]);
     } else {
+      ev.k1[j] = (T)(kLog2e * cs.d[c0 + 1]);
       ev.loc[j].set(0.0);
-      ev.cst[j].set(cs.d[c0 + 1] * cs.d[c0] - cs.d[c0 + 2]);
+      ev.cst[j].set(kLog2e * (cs.d[c0 + 1] * cs.d[c0] - cs.d[c0 + 2]));
     }
     ev.f[j] = cs.get<T>(rn.c0 + j);
   }
@@ -488,6 +496,7 @@ __device__ __forceinline__ MixEv<T, K, MASK, GRAD> make_mix(const KProgram& P, c
 template <typename T, int OP, bool GRAD>
 struct LightLeafEv {  // single EXP / GAUSS leaf
   static constexpr int NA = GRAD ? (OP == OP_EXP ? 1 : 2) : 0;
+  static constexpr double kNllScale = 1.0;  // nl holds sum -ln P
   CS cs;
   int c0;
   bool hoisted;
@@ -882,19 +891,23 @@ bool kind_light(int kind) {
   return kind == KIND_EXP || kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
 }
 
+// Single-dataset launches go through hipExtLaunchKernel so that timing
+// events (when given) take the dispatch's own start and end time stamps.
 template <typename T, bool GRAD>
-static hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st) {
+static hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid((unsigned)a.n_rows), block(kBlock);
   switch (kind) {
-    case KIND_EXP: hipLaunchKernelGGL((k_leaf<T, OP_EXP, GRAD>), grid, block, 0, st, a); break;
-    case KIND_GAUSS: hipLaunchKernelGGL((k_leaf<T, OP_GAUSS, GRAD>), grid, block, 0, st, a); break;
-    case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree<T, 8, 2, false, GRAD>), grid, block, 0, st, a); break;
-    case KIND_DALITZ: hipLaunchKernelGGL((k_leaf<T, OP_DALITZ, GRAD>), grid, block, 0, st, a); break;
-    case KIND_TDDP: hipLaunchKernelGGL((k_leaf<T, OP_TDDP, GRAD>), grid, block, 0, st, a); break;
-    case KIND_TREE: hipLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, a); break;
+    case KIND_EXP: hipExtLaunchKernelGGL((k_leaf<T, OP_EXP, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_GAUSS: hipExtLaunchKernelGGL((k_leaf<T, OP_GAUSS, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TREE_SMALL: hipExtLaunchKernelGGL((k_tree<T, 8, 2, false, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_DALITZ: hipExtLaunchKernelGGL((k_leaf<T, OP_DALITZ, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TDDP: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TREE:
+      hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+      break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
-    hipLaunchKernelGGL((k_mix<T, K_, M_, GRAD>), grid, block, 0, st, a);                            \
+    hipExtLaunchKernelGGL((k_mix<T, K_, M_, GRAD>), grid, block, 0, st, e0, e1, 0, a);              \
     break;
     HF_MIX(2, 0) HF_MIX(2, 1) HF_MIX(2, 2) HF_MIX(2, 3)
     HF_MIX(3, 0) HF_MIX(3, 1) HF_MIX(3, 2) HF_MIX(3, 3) HF_MIX(3, 4) HF_MIX(3, 5) HF_MIX(3, 6) HF_MIX(3, 7)
@@ -904,10 +917,11 @@ static hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st) {
+hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st, hipEvent_t e0,
+                       hipEvent_t e1) {
   if (a.n_rows <= 0) return hipSuccess;
-  if (fp32) return grad ? launch_any<float, true>(kind, a, st) : launch_any<float, false>(kind, a, st);
-  return grad ? launch_any<double, true>(kind, a, st) : launch_any<double, false>(kind, a, st);
+  if (fp32) return grad ? launch_any<float, true>(kind, a, st, e0, e1) : launch_any<float, false>(kind, a, st, e0, e1);
+  return grad ? launch_any<double, true>(kind, a, st, e0, e1) : launch_any<double, false>(kind, a, st, e0, e1);
 }
 
 template <typename T>
@@ -943,8 +957,8 @@ hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const 
   return fp32 ? launch_b<float>(kind, a, grid, st) : launch_b<double>(kind, a, grid, st);
 }
 
-hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(kRedBlock), 0, st, fr);
+hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  hipExtLaunchKernelGGL(k_reduce_one, dim3(1), dim3(kRedBlock), 0, st, e0, e1, 0, fr);
   return hipGetLastError();
 }
 

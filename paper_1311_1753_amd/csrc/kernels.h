@@ -28,8 +28,10 @@ constexpr int kMinChunksLight = 4;
 // true for the single-column kinds (EXP, GAUSS, small trees, mixtures)
 bool kind_light(int kind);
 
-hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st);
-hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st);
+// e0 / e1 (nullable): events that receive the dispatch's start / end time
+hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
+hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, hipStream_t st);
 hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,
                                const float* c32, int n_const, int grid, hipStream_t st);

@@ -174,6 +174,11 @@ typedef struct {
   int32_t grad_mode;    /* 0: analytic gradient (nll_grad); 1: central differences of nll_eval,
                            2 n_free extra evaluations per gradient */
   int32_t want_errors;  /* nonzero: compute the final Hessian, errors and covariance */
+  double param_eps;     /* relative precision with which the evaluation sees the parameters:
+                           the final Hessian's difference steps are at least 1e4 param_eps |x|,
+                           so that rounding the parameters does not disturb them.  0: the
+                           default (2^-24 for FP32-eval datasets in fit / batch_admit, else
+                           exact); < 0: exact */
 } hf_fit_opts;
 
 typedef struct {

@@ -59,7 +59,7 @@ class hf_node(ctypes.Structure):
 
 class hf_fit_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("edm_tol", ctypes.c_double), ("grad_mode", ctypes.c_int32),
-                ("want_errors", ctypes.c_int32)]
+                ("want_errors", ctypes.c_int32), ("param_eps", ctypes.c_double)]
 
 
 class hf_fit_summary(ctypes.Structure):

@@ -236,12 +236,13 @@ def nll_grad_batched(graph, datasets, thetas, stream=None):
 
 
 def fit(graph, ds, theta0=None, grad_mode="analytic", max_iter=500, edm_tol=1e-10, want_errors=True,
-        stream=None):
+        stream=None, param_eps=0.0):
     """Minimise the NLL; returns a dict with theta, errors, cov, nll, edm, n_iter, n_eval, status."""
     th = np.ascontiguousarray(graph.theta() if theta0 is None else theta0, dtype=np.float64).copy()
     err = np.zeros(graph.n_par)
     cov = np.zeros((graph.n_par, graph.n_par))
-    o = _lib.hf_fit_opts(max_iter, edm_tol, {"analytic": 0, "numerical": 1}[grad_mode], int(want_errors))
+    o = _lib.hf_fit_opts(max_iter, edm_tol, {"analytic": 0, "numerical": 1}[grad_mode], int(want_errors),
+                         param_eps)
     s = _lib.hf_fit_summary()
     rc = lib().fit(graph.handle, ds.handle, ctypes.byref(o), _stream_ptr(stream), _dp(th), _dp(err), _dp(cov),
                    ctypes.byref(s))
@@ -250,10 +251,11 @@ def fit(graph, ds, theta0=None, grad_mode="analytic", max_iter=500, edm_tol=1e-1
             "n_eval": s.n_eval, "status": _lib.STATUS_NAMES.get(s.status, str(s.status))}
 
 
-def minimize(fg, params, x0=None, max_iter=500, edm_tol=1e-10, want_errors=True, f_noise=0.0):
+def minimize(fg, params, x0=None, max_iter=500, edm_tol=1e-10, want_errors=True, f_noise=0.0, param_eps=0.0):
     """The library's minimiser on a Python function fg(x) -> (f, grad).
 
-    params: [(name, init, step, lo, hi, fixed)].  Runs on the host only."""
+    params: [(name, init, step, lo, hi, fixed)].  param_eps: relative precision
+    with which fg sees x (0: exact).  Runs on the host only."""
     n = len(params)
     p_arr = (_lib.hf_param * max(n, 1))(
         *[_lib.hf_param(p[0].encode(), p[1], p[2], p[3], p[4], int(bool(p[5]) if len(p) > 5 else 0))
@@ -277,7 +279,7 @@ def minimize(fg, params, x0=None, max_iter=500, edm_tol=1e-10, want_errors=True,
     err = np.zeros(n)
     cov = np.zeros((n, n))
     s = _lib.hf_fit_summary()
-    o = _lib.hf_fit_opts(max_iter, edm_tol, 0, int(want_errors))
+    o = _lib.hf_fit_opts(max_iter, edm_tol, 0, int(want_errors), param_eps)
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     rc = lib().hf_minimize(n, p_arr, _dp(x0a) if x0a is not None else None, ctypes.byref(o), f_noise, cfun, None,
                            _dp(x), _dp(err), _dp(cov), ctypes.byref(s))

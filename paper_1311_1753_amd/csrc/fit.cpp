@@ -29,6 +29,10 @@ MinOptions min_options(const hf_fit_opts* o, hf_precision prec) {
   // the float path's NLL carries rounding noise of order sqrt(n) 1e-7 |ln P|:
   // let the line search accept steps within that noise and stop on the gradient
   m.f_noise = prec == HF_FP32_EVAL ? 1e-9 : 1e-13;
+  // the float path sees parameter-derived constants (1/sigma, fractions, ...)
+  // rounded to float
+  const double pe = o ? o->param_eps : 0.0;
+  m.param_eps = pe > 0.0 ? pe : (pe < 0.0 ? 0.0 : (prec == HF_FP32_EVAL ? 0x1p-24 : 0.0));
   return m;
 }
 

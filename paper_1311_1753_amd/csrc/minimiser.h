@@ -24,6 +24,7 @@ struct MinOptions {
   double edm_tol = 1e-10;
   bool want_errors = true;
   double f_noise = 1e-13;  // relative noise of f tolerated by the line search
+  double param_eps = 0.0;  // relative precision of the parameters as the evaluation sees them
 };
 
 class Minimiser {

@@ -78,3 +78,30 @@ def test_minimiser_tolerates_rounding_noise(oracle_mod):
     assert r["status"] == "OK"
     assert np.max(np.abs(r["theta"] - ref["theta"]) / ref["errors"]) < 1e-2
     assert np.max(np.abs(r["errors"] / ref["errors"] - 1)) < 1e-2
+
+
+@pytest.mark.parametrize("param_eps,ok", [(2.0 ** -24, True), (0.0, False)])
+def test_final_hessian_steps_clear_parameter_rounding(param_eps, ok):
+    """An evaluation that rounds its parameters to float (as the FP32-eval
+    kernels do with constants derived from them): with the parameters' relative
+    precision given, the final Hessian's difference steps are large against
+    that rounding and the errors of this quadratic are exact; with exact
+    parameters assumed, 0.1 sigma steps are a few float ulps of x and the
+    errors are off by several 1e-4 (deterministic for these inputs)."""
+    import paper_1311_1753_amd as P
+    c = np.array([1.0, -3.0])
+    sig = np.array([1e-5, 2e-5])
+
+    def fg(x):
+        xf = np.asarray(x, dtype=np.float32).astype(np.float64)
+        r = (xf - c) / sig
+        return 0.5 * float(r @ r), r / sig
+
+    r = P.minimize(fg, [("a", 1.0002, 1e-4, 0, 0, False), ("b", -2.9996, 1e-4, 0, 0, False)],
+                   param_eps=param_eps)
+    assert r["status"] == "OK"
+    dev = np.max(np.abs(r["errors"] / sig - 1))
+    if ok:
+        assert dev < 1e-6
+    else:
+        assert dev > 1e-4

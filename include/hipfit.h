@@ -177,8 +177,10 @@ typedef struct {
   double param_eps;     /* relative precision with which the evaluation sees the parameters:
                            the final Hessian's difference steps are at least 1e4 param_eps |x|,
                            so that rounding the parameters does not disturb them.  0: the
-                           default (2^-24 for FP32-eval datasets in fit / batch_admit, else
-                           exact); < 0: exact */
+                           default (fit / batch_admit on FP32-eval datasets: 2^-24 for the
+                           parameters the float kernels see rounded -- all but Gaussian means
+                           and the decay time and width difference; otherwise exact);
+                           > 0: this value for every parameter; < 0: exact */
 } hf_fit_opts;
 
 typedef struct {

@@ -22,7 +22,7 @@
 
 namespace hf {
 
-std::vector<MinParam> min_params(const pdf_graph* g);
+std::vector<MinParam> min_params(const pdf_graph* g, hf_precision prec);
 MinOptions min_options(const hf_fit_opts* o, hf_precision prec);
 int status_code(int st);
 
@@ -292,7 +292,7 @@ extern "C" int batch_admit(batch_engine* b, const dataset* d, const double* para
     s.tag = tag;
     s.bytes = d->bytes;
     s.n_eval = 0;
-    s.m.start(min_params(b->g), params_init, min_options(opts, d->prec));
+    s.m.start(min_params(b->g, d->prec), params_init, min_options(opts, d->prec));
     b->in_use += d->bytes;
     b->prec = d->prec;
     b->prec_set = true;

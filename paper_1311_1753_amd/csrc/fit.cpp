@@ -13,9 +13,12 @@
 
 namespace hf {
 
-std::vector<MinParam> min_params(const pdf_graph* g) {
+std::vector<MinParam> min_params(const pdf_graph* g, hf_precision prec) {
   std::vector<MinParam> ps;
-  for (auto& p : g->par) ps.push_back({p.init, p.step, p.lo, p.hi, p.fixed});
+  for (size_t i = 0; i < g->par.size(); ++i) {
+    const auto& p = g->par[i];
+    ps.push_back({p.init, p.step, p.lo, p.hi, p.fixed, prec == HF_FP32_EVAL && g->par_rounded[i] ? 0x1p-24 : 0.0});
+  }
   return ps;
 }
 
@@ -29,10 +32,8 @@ MinOptions min_options(const hf_fit_opts* o, hf_precision prec) {
   // the float path's NLL carries rounding noise of order sqrt(n) 1e-7 |ln P|:
   // let the line search accept steps within that noise and stop on the gradient
   m.f_noise = prec == HF_FP32_EVAL ? 1e-9 : 1e-13;
-  // the float path sees parameter-derived constants (1/sigma, fractions, ...)
-  // rounded to float
-  const double pe = o ? o->param_eps : 0.0;
-  m.param_eps = pe > 0.0 ? pe : (pe < 0.0 ? 0.0 : (prec == HF_FP32_EVAL ? 0x1p-24 : 0.0));
+  // 0: per-parameter defaults (min_params); > 0 overrides; < 0: all exact
+  m.param_eps = o ? o->param_eps : 0.0;
   return m;
 }
 
@@ -60,7 +61,7 @@ extern "C" int fit(const pdf_graph* g, const dataset* d, const hf_fit_opts* opts
     if (mode != 0 && mode != 1) return fail(HF_E_INVALID, "fit: grad_mode must be 0 or 1");
     hipStream_t st = (hipStream_t)hip_stream;
     Minimiser m;
-    m.start(min_params(g), params_inout, min_options(opts, d->prec));
+    m.start(min_params(g, d->prec), params_inout, min_options(opts, d->prec));
     std::vector<double> x(np), gr(np), xp(np);
     int n_eval = 0;
     while (m.ask(x)) {
@@ -124,7 +125,7 @@ extern "C" int hf_minimize(int32_t n, const hf_param* params, const double* x0, 
     std::vector<double> start(n);
     for (int i = 0; i < n; ++i) {
       const hf_param& p = params[i];
-      ps.push_back({p.init, p.step > 0 ? p.step : 0.1, p.lo, p.hi, p.fixed != 0});
+      ps.push_back({p.init, p.step > 0 ? p.step : 0.1, p.lo, p.hi, p.fixed != 0, 0.0});
       start[i] = x0 ? x0[i] : p.init;
       if (!std::isfinite(start[i])) return fail(HF_E_INVALID, "hf_minimize: start value not finite");
     }

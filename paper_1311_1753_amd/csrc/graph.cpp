@@ -671,6 +671,16 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
         setc(rb + kResJ, r.J);
       }
     }
+    // parameters that the float path sees rounded to float (through 1/sigma,
+    // fractions, rates, coefficients); Gaussian means and the decay time and
+    // width difference of the time-dependent density enter through double
+    // differences only
+    g->par_rounded.assign(g->par.size(), false);
+    for (const NodeInfo& n : g->nodes)
+      for (size_t j = 0; j < n.par.size(); ++j) {
+        const bool exact = (n.op == OP_GAUSS && j == 0) || (n.op == OP_TDDP && j + 2 >= n.par.size());
+        if (!exact) g->par_rounded[n.par[j]] = true;
+      }
     // kernel family
     const NodeInfo& rootn = g->nodes[NN - 1];
     bool heavy = g->dz.node >= 0;

@@ -218,9 +218,10 @@ void Minimiser::begin_final() {
     // the step is large against rounding noise in the gradient
     double h = 0.1 * s;
     h = std::max(h, 1e-12 * (std::fabs(x_best[j]) + 1.0));
-    // when the evaluation rounds the parameters (relative precision
-    // param_eps), keep that rounding below 1e-4 of the step
-    h = std::max(h, 1e4 * o_.param_eps * std::fabs(x_best[j]));
+    // when the evaluation rounds the parameter (relative precision eps),
+    // keep that rounding below 1e-4 of the step
+    const double eps = o_.param_eps > 0.0 ? o_.param_eps : (o_.param_eps < 0.0 ? 0.0 : ps_[j].eps);
+    h = std::max(h, 1e4 * eps * std::fabs(x_best[j]));
     if (bounded(ps_[j])) h = std::min(h, 0.25 * std::min(x_best[j] - ps_[j].lo, ps_[j].hi - x_best[j]));
     hstep_[k] = h;
   }

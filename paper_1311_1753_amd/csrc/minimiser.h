@@ -17,6 +17,7 @@ namespace hf {
 struct MinParam {
   double init, step, lo, hi;  // lo == hi: unbounded
   bool fixed;
+  double eps = 0.0;           // relative precision with which the evaluation sees it (0: exact)
 };
 
 struct MinOptions {
@@ -24,7 +25,7 @@ struct MinOptions {
   double edm_tol = 1e-10;
   bool want_errors = true;
   double f_noise = 1e-13;  // relative noise of f tolerated by the line search
-  double param_eps = 0.0;  // relative precision of the parameters as the evaluation sees them
+  double param_eps = 0.0;  // > 0: overrides every MinParam::eps; < 0: all exact
 };
 
 class Minimiser {

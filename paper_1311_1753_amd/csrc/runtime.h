@@ -72,6 +72,7 @@ struct pdf_graph {
   std::vector<hf::NodeInfo> nodes;   // post-order, root last (re-indexed)
   hf::KProgram prog;                 // structure; static constants filled
   std::vector<int> slot_par;         // gradient slot -> parameter index
+  std::vector<bool> par_rounded;     // parameter reaches the float kernels rounded to float
   int kind = 0;
   int n_const = 0;
   std::vector<int> col_of_obs;       // observable -> column (-1: unused)

@@ -94,7 +94,8 @@ def test_full_size_fit_of_benchmark_workload(P):
         ds = P.Dataset(g, data, prec)
         r = P.fit(g, ds)
         dev = np.abs(r["theta"] - ref["theta"]) / ref["errors"]
-        print(f"  {prec}: status {r['status']} n_eval {r['n_eval']} max |dtheta|/sigma {dev.max():.2e} "
+        print(f"  {prec}: status {r['status']} n_eval {r['n_eval']} n_iter {r['n_iter']} edm {r['edm']:.2e} "
+              f"max |dtheta|/sigma {dev.max():.2e} "
               f"err ratio-1 {np.max(np.abs(r['errors'] / ref['errors'] - 1)):.2e}", flush=True)
         assert r["status"] == "OK"
         assert dev.max() <= 1e-3

@@ -115,9 +115,9 @@ __device__ __forceinline__ Chan<T> chan_swap_ac_bc(const CS& cs, int cb, const C
 
 // Resonance amplitude B_J(q) Z_J BW(s_AB) with the mass-dependent width
 // m0 Gamma(s) = Kw q^{2J+1} B_J^2 / sqrt(s), BW = 1/(m0^2 - s - i m0 Gamma);
-// m0^2 - s is formed in double.
-template <typename T>
-__device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, int J, const Chan<T>& c) {
+// m0^2 - s is formed in double.  J is static here.
+template <typename T, int J>
+__device__ __forceinline__ Cx<T> res_amp_j(const CS& cs, int rb, const Chan<T>& c) {
   const T d = (T)(cs.d[rb + kResM02] - c.sABd);
   T B = T(1), qp = c.q, Z = T(1);
   if (J == 1) {
@@ -134,6 +134,26 @@ __device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, int J, const Chan
   const T den = Mth<T>::rcp(d * d + mg * mg);
   const T f = B * Z * den;
   return {f * d, f * mg};
+}
+
+// The resonance's pair and spin are wave-uniform: branch on them (only one
+// variant runs) instead of selecting the pair quantities field by field.
+template <typename T>
+__device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, int ch, int J, const Chan<T>& c12,
+                                         const Chan<T>& c13, const Chan<T>& c23) {
+  if (ch == 0) {
+    if (J == 0) return res_amp_j<T, 0>(cs, rb, c12);
+    if (J == 1) return res_amp_j<T, 1>(cs, rb, c12);
+    return res_amp_j<T, 2>(cs, rb, c12);
+  }
+  if (ch == 1) {
+    if (J == 0) return res_amp_j<T, 0>(cs, rb, c13);
+    if (J == 1) return res_amp_j<T, 1>(cs, rb, c13);
+    return res_amp_j<T, 2>(cs, rb, c13);
+  }
+  if (J == 0) return res_amp_j<T, 0>(cs, rb, c23);
+  if (J == 1) return res_amp_j<T, 1>(cs, rb, c23);
+  return res_amp_j<T, 2>(cs, rb, c23);
 }
 
 // Amplitudes A_k(s12, s13) (and, for TDDP, Abar_k = A_k(s13, s12)) of all
@@ -167,12 +187,8 @@ __device__ __forceinline__ void dalitz_amps(const CS& cs, int c0, int R, double 
       const int rb = rbase + k * kResStride;
       const int ch = (int)cs.d[rb + kResCh];
       const int J = (int)cs.d[rb + kResJ];
-      const Chan<T>& c = ch == 0 ? c12 : (ch == 1 ? c13 : c23);
-      A[k] = res_amp<T>(cs, rb, J, c);
-      if (TD) {
-        const Chan<T>& b = ch == 0 ? b12 : (ch == 1 ? b13 : b23);
-        Ab[k] = res_amp<T>(cs, rb, J, b);
-      }
+      A[k] = res_amp<T>(cs, rb, ch, J, c12, c13, c23);
+      if (TD) Ab[k] = res_amp<T>(cs, rb, ch, J, b12, b13, b23);
     }
   }
 }

@@ -136,6 +136,22 @@ int pdf_graph_shape(const pdf_graph* g, int32_t* n_obs, int32_t* n_par);
  * copy is done; the caller keeps ownership of the host columns. */
 int dataset_upload(const pdf_graph* g, const double* const* host_cols, int64_t n_events,
                    hf_precision prec, void* hip_stream, dataset** out);
+/* Borrows columns that already live in device memory (e.g. tensors of a
+ * framework) instead of copying: dev_cols[o] is the device address of
+ * observable o's column (n_events values; unused observables may be NULL).
+ * HF_FP64: doubles, the observable's values.  HF_FP32_EVAL: floats, each
+ * the value minus hf_column_ref(g, o, HF_FP32_EVAL), rounded once.  The
+ * columns are not validated (events outside an observable's box or the
+ * Dalitz plot give meaningless densities); they must stay allocated and
+ * unchanged while the dataset is used, and stay owned by the caller
+ * (dataset_free releases only the library's workspace).  Columns must be
+ * aligned to their element size. */
+int dataset_wrap_device(const pdf_graph* g, void* const* dev_cols, int64_t n_events, hf_precision prec,
+                        dataset** out);
+/* The reference subtracted from observable obs in the FP32-eval storage (the
+ * middle of its box, 0 for an unbounded or unused observable; always 0 for
+ * HF_FP64). */
+int hf_column_ref(const pdf_graph* g, int32_t obs, hf_precision prec, double* ref);
 void dataset_free(dataset* d);
 /* Device bytes held by a dataset (columns + workspace). */
 int64_t dataset_device_bytes(const dataset* d);

@@ -78,6 +78,9 @@ SIGNATURES = {
     "pdf_graph_shape": (ctypes.c_int, [_VP, _I32P, _I32P]),
     "dataset_upload": (ctypes.c_int, [_VP, ctypes.POINTER(_DP), ctypes.c_int64, ctypes.c_int, _VP,
                                       ctypes.POINTER(_VP)]),
+    "dataset_wrap_device": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int,
+                                           ctypes.POINTER(_VP)]),
+    "hf_column_ref": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _DP]),
     "dataset_free": (None, [_VP]),
     "dataset_device_bytes": (ctypes.c_int64, [_VP]),
     # theta and grad are passed as raw addresses (numpy .ctypes.data)

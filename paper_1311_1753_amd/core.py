@@ -126,6 +126,13 @@ class Graph:
     def free_mask(self):
         return np.array([not p[5] for p in self.params])
 
+    def column_ref(self, name, precision="fp32"):
+        """The reference subtracted from observable `name` in the FP32-eval
+        storage (0 for FP64)."""
+        r = ctypes.c_double()
+        check(lib().hf_column_ref(self.handle, self.obs_names.index(name), _prec(precision), ctypes.byref(r)))
+        return r.value
+
     def dalitz_inside(self, s12, s13):
         a = np.ascontiguousarray(s12, dtype=np.float64)
         b = np.ascontiguousarray(s13, dtype=np.float64)
@@ -173,6 +180,41 @@ class Dataset:
         self._keep = None
         self._h = h
         self.n = n
+
+    @classmethod
+    def from_device(cls, graph, columns, precision="fp64"):
+        """Borrows device tensors instead of copying (dataset_wrap_device):
+        columns maps observable names to contiguous CUDA tensors -- float64
+        values for "fp64", float32 offsets value - graph.column_ref(name,
+        "fp32") for "fp32".  The tensors are kept referenced by the dataset;
+        their values are not validated."""
+        self = cls.__new__(cls)
+        self.graph = graph
+        self.precision = _prec(precision)
+        want = "torch.float64" if self.precision == FP64 else "torch.float32"
+        n = None
+        ptrs = (ctypes.c_void_p * len(graph.obs_names))()
+        keep = []
+        for i, name in enumerate(graph.obs_names):
+            t = columns.get(name)
+            if t is None:
+                continue
+            if str(t.dtype) != want or not t.is_cuda or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError("column %r must be a contiguous 1-d CUDA tensor of %s" % (name, want))
+            if n is None:
+                n = t.numel()
+            elif t.numel() != n:
+                raise ValueError("columns differ in length")
+            ptrs[i] = t.data_ptr()
+            keep.append(t)
+        if n is None:
+            raise ValueError("no columns")
+        h = ctypes.c_void_p()
+        check(lib().dataset_wrap_device(graph.handle, ptrs, n, self.precision, ctypes.byref(h)))
+        self._keep = keep
+        self._h = h
+        self.n = n
+        return self
 
     @property
     def handle(self):

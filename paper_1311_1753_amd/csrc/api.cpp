@@ -247,6 +247,49 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
   }
 }
 
+extern "C" int hf_column_ref(const pdf_graph* g, int32_t obs, hf_precision prec, double* ref) {
+  if (!g || !ref || obs < 0 || obs >= (int32_t)g->obs.size()) return fail(HF_E_INVALID, "hf_column_ref: bad argument");
+  if (prec != HF_FP64 && prec != HF_FP32_EVAL) return fail(HF_E_INVALID, "hf_column_ref: bad precision");
+  const int c = g->col_of_obs[obs];
+  *ref = c < 0 ? 0.0 : column_ref(g, c, prec);
+  return HF_OK;
+}
+
+extern "C" int dataset_wrap_device(const pdf_graph* g, void* const* dev_cols, int64_t n, hf_precision prec,
+                                   dataset** out) {
+  try {
+    if (!g || !out || (n > 0 && !dev_cols)) return fail(HF_E_INVALID, "dataset_wrap_device: NULL argument");
+    if (n < 0 || n > (int64_t(1) << 36)) return fail(HF_E_INVALID, "dataset_wrap_device: n_events out of range");
+    if (prec != HF_FP64 && prec != HF_FP32_EVAL) return fail(HF_E_INVALID, "dataset_wrap_device: bad precision");
+    const int nc = (int)g->obs_of_col.size();
+    const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
+    std::unique_ptr<dataset> d(new dataset);
+    d->g = g;
+    d->prec = prec;
+    d->n = n;
+    d->n_cols = nc;
+    for (int c = 0; c < nc; ++c) {
+      void* p = n > 0 ? dev_cols[g->obs_of_col[c]] : nullptr;
+      if (n > 0 && !p) return fail(HF_E_INVALID, "dataset_wrap_device: NULL column for a used observable");
+      if ((uintptr_t)p % es != 0) return fail(HF_E_INVALID, "dataset_wrap_device: misaligned column");
+      d->col[c] = p;
+      d->ref[c] = column_ref(g, c, prec);
+    }
+    d->n_rows = rows_for(g->kind, n);
+    const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * (g->prog.n_slots + 1) * sizeof(double));
+    void* blk = nullptr;
+    hipError_t e = hipMalloc(&blk, part_bytes);
+    if (e != hipSuccess) return fail(HF_E_OOM, std::string("dataset_wrap_device: hipMalloc: ") + hipGetErrorString(e));
+    d->block = blk;
+    d->partials = (double*)blk;
+    d->bytes = (int64_t)part_bytes;
+    *out = d.release();
+    return HF_OK;
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("dataset_wrap_device: ") + ex.what());
+  }
+}
+
 extern "C" void dataset_free(dataset* d) {
   if (!d) return;
   if (d->block) hipFree(d->block);

@@ -176,3 +176,29 @@ def test_numerical_gradient_fit_agrees(P, stream):
     assert rn["status"] == "OK"
     assert np.max(np.abs(ra["theta"] - rn["theta"])[free] / ra["errors"][free]) < 1e-3
     assert rn["n_eval"] > ra["n_eval"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_device_borrowed_dataset_equals_uploaded(P, stream, prec):
+    """dataset_wrap_device on tensors holding the storage format gives the
+    same bits as dataset_upload of the same events."""
+    import torch
+    print(f"\n[case] borrowed columns c2 {prec}", flush=True)
+    sp = get_spec("c2")
+    data = data_for("c2", 300_001, 50)
+    om = oracle_for("c2")
+    g = P.Graph.from_spec(sp)
+    up = P.Dataset(g, data, prec, stream)
+    if prec == "fp64":
+        t = torch.from_numpy(data["x"]).to("cuda")
+    else:
+        ref = g.column_ref("x", "fp32")
+        t = torch.from_numpy((data["x"] - ref).astype(np.float32)).to("cuda")
+    torch.cuda.synchronize()
+    wr = P.Dataset.from_device(g, {"x": t}, prec)
+    th = perturbed_theta(om, sp, seed=51)
+    v1, g1 = P.nll_grad(g, up, th, stream)
+    v2, g2 = P.nll_grad(g, wr, th, stream)
+    assert v1 == v2 and np.array_equal(g1, g2)
+    wr.free()
+    up.free()

@@ -166,6 +166,17 @@ def serving_bench(P, S, n_req):
     srv.close()
     out["batched_fp32_open_loop"] = s_open
     out["batched_fp32_closed_loop"] = s_closed
+    # arrival-rate sweep: the same requests (first 1024) at higher Poisson rates
+    sweep = []
+    srv = P.FitServer(g, "fp32", max_slots=256, hbm_budget_bytes=32 << 30, upload_stream=up)
+    base = S.C5["rate_hz"]
+    for rate in (1000.0, 5000.0, 20000.0):
+        rq = [dict(r, arrival_s=r["arrival_s"] * base / rate) for r in reqs[:1024]]
+        _, sm = srv.run(rq, colf, start, realtime=True)
+        sweep.append({"rate_hz": rate, "fits_per_s": sm["fits_per_s"], "p50_latency_s": sm["p50_latency_s"],
+                      "p99_latency_s": sm["p99_latency_s"], "n": sm["n"]})
+    srv.close()
+    out["batched_fp32_rate_sweep"] = sweep
     res_base, s_base = P.serve_one_at_a_time(g, reqs, colf, start, precision="fp64", grad_mode="numerical")
     out["one_at_a_time_fp64_numerical"] = s_base
     dev = [abs(res_closed[i]["theta"][0] - res_base[i]["theta"][0]) / res_base[i]["errors"][0]
@@ -290,6 +301,15 @@ def main():
     log("fp32 nll+grad: %.3f ms/step, kernel %.4f ms, reduce %.4f ms" % (ms_step, k_ms, red_ms / max(ncalls, 1)))
 
     extra = {}
+    # ---------------- latency distribution of single FP32 evaluations
+    lat = []
+    for th in theta_sequence(truth, 500, rng):
+        t1 = time.perf_counter()
+        P.nll_grad(g, ds32, th, stream)
+        lat.append(time.perf_counter() - t1)
+    lat = np.array(lat) * 1e6
+    extra["fp32_nll_grad_latency_us"] = {"median": float(np.median(lat)), "p99": float(np.percentile(lat, 99)),
+                                         "n": int(lat.size)}
     # ---------------- FP64 analytic and FP64 NLL-only (numerical-gradient path)
     k64 = max(50, args.steps // 10)
     th64 = theta_sequence(truth, k64, rng)

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace hf {
 
@@ -230,8 +232,22 @@ void Minimiser::begin_final() {
   phase_ = FINAL_H;
 }
 
+// HIPFIT_TRACE=1 prints every evaluation the minimiser is told about.
+static bool trace_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("HIPFIT_TRACE");
+    return v && v[0] == '1';
+  }();
+  return on;
+}
+
 void Minimiser::tell(double f, const std::vector<double>& g) {
   ++n_eval;
+  if (trace_on()) {
+    static const char* names[] = {"EVAL0", "HESS0", "LINE", "FINAL_H", "POLISH", "DONE"};
+    std::fprintf(stderr, "[minimiser] eval %d phase %s f %.12g f_best %.12g edm %.3g alpha %.3g\n", n_eval,
+                 names[phase_], f, f_best, edm, alpha_);
+  }
   switch (phase_) {
     case EVAL0: {
       if (!std::isfinite(f)) {

@@ -598,6 +598,7 @@ struct TreeEv {
         }
         const T is = Mth<T>::rcp(s);
         v = live && s > T(0) ? m + Mth<T>::ln(s) : T(-INFINITY);
+        if (!h) v -= cs.get<T>(c0 + K);  // ln of the fractions' sum (hoisted: on the host)
         const T eK = resp[P.child[nd.child0 + K - 1]];
         for (int j = 0; j < K; ++j) {
           const int ch = P.child[nd.child0 + j];

@@ -241,6 +241,14 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
   sc.ht.dlnN.assign(g->par.size(), 0.0);
   KProgram& P = sc.prog;
   const bool fp32 = prec == HF_FP32_EVAL;
+  // The float path sees parameter-derived factors (rates, 1/sigma,
+  // fractions, polynomial and amplitude coefficients) rounded to float.  They
+  // are rounded here first and every normalisation is computed from the
+  // rounded values, so the float density is exactly normalised: its NLL is
+  // the NLL at a nearby parameter point, without offsets that jump as the
+  // rounding changes.
+  auto rnd = [&](double v) { return fp32 ? (double)(float)v : v; };
+  constexpr double kLog2e = 1.44269504088896340736;
   auto setc = [&](int i, double v) {
     P.c64[i] = v;
     P.c32[i] = (float)v;
@@ -274,7 +282,10 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
       case OP_EXP: {
         const int col = kn.col[0];
         const ObsInfo& o = g->obs[g->obs_of_col[col]];
-        const double alpha = th[nd.par[0]];
+        // the mixture kernel uses log2(e) alpha rounded to float
+        const bool mixc = g->mix.K > 0 && k != g->mix.root;
+        const double alpha = !fp32 ? th[nd.par[0]]
+                                   : (mixc ? (double)(float)(kLog2e * th[nd.par[0]]) / kLog2e : rnd(th[nd.par[0]]));
         P.c64[c0] = column_ref(g, col, prec) - o.lo;
         P.c32[c0] = 0.0f;
         setc(c0 + 1, alpha);
@@ -286,12 +297,14 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
       case OP_GAUSS: {
         const int col = kn.col[0];
         const ObsInfo& o = g->obs[g->obs_of_col[col]];
-        const double mu = th[nd.par[0]], s = th[nd.par[1]];
+        const double mu = th[nd.par[0]];
+        const double k1 = rnd(1.0 / th[nd.par[1]]);
+        const double s = fp32 ? 1.0 / k1 : th[nd.par[1]];
         double lnN = 0, dmu = 0, ds = 0;
         if (!gauss_norm(o.lo, o.hi, mu, s, lnN, dmu, ds)) sc.ok = false;
         P.c64[c0] = column_ref(g, col, prec) - mu;
         P.c32[c0] = 0.0f;
-        setc(c0 + 1, 1.0 / s);
+        setc(c0 + 1, k1);
         norm_terms(lnN, {{nd.par[0], dmu}, {nd.par[1], ds}}, c0 + 2, c0 + 3, c0 + 4);
         break;
       }
@@ -306,8 +319,9 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         std::vector<double> w(d);
         for (int j = 1; j <= d; ++j) {
           w[j - 1] = (std::pow(o.hi - x0, j + 1) - std::pow(o.lo - x0, j + 1)) / (j + 1);
-          N += th[nd.par[j - 1]] * w[j - 1];
-          setc(c0 + j, th[nd.par[j - 1]]);
+          const double a = rnd(th[nd.par[j - 1]]);
+          N += a * w[j - 1];
+          setc(c0 + j, a);
         }
         if (!(N > 0.0)) { sc.ok = false; N = 1.0; }
         std::vector<std::pair<int, double>> dv;
@@ -316,13 +330,26 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         break;
       }
       case OP_ADD: {
-        double last = 1.0;
+        // fractions as the kernels see them; ln of their sum (1 up to the
+        // rounding) normalises the sum: added per event by the tree kernel,
+        // or on the host when the node is hoisted
+        double last = 1.0, sum = 0.0;
         const int K = kn.n_child;
         for (int j = 0; j < K - 1; ++j) {
-          setc(c0 + j, th[nd.par[j]]);
+          const double f = rnd(th[nd.par[j]]);
+          setc(c0 + j, f);
           last -= th[nd.par[j]];
+          sum += f;
         }
-        setc(c0 + K - 1, last);
+        setc(c0 + K - 1, rnd(last));
+        sum += rnd(last);
+        const double lnsum = sum > 0.0 ? std::log(sum) : 0.0;
+        if (hoist) {
+          sc.ht.lnN += lnsum;
+          setc(c0 + K, 0.0);
+        } else {
+          setc(c0 + K, lnsum);
+        }
         break;
       }
       case OP_PROD:
@@ -337,7 +364,7 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         std::vector<cd> c(R + 1, cd(1.0, 0.0));
         const int cb = c0 + dz_coef_base(R, td);
         for (int j = 0; j < R; ++j) {
-          c[j + 1] = cd(th[nd.par[2 * j]], th[nd.par[2 * j + 1]]);
+          c[j + 1] = cd(rnd(th[nd.par[2 * j]]), rnd(th[nd.par[2 * j + 1]]));
           setc(cb + 2 * j, c[j + 1].real());
           setc(cb + 2 * j + 1, c[j + 1].imag());
         }
@@ -391,7 +418,6 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
       }
     }
   }
-  (void)fp32;
 }
 
 // ------------------------------------------------------------------ creation
@@ -413,7 +439,7 @@ int node_consts(const NodeInfo& n) {
     case OP_EXP: return 5;
     case OP_GAUSS: return 6;
     case OP_POLY: return 2 * (int)n.par.size() + 3;
-    case OP_ADD: return (int)n.child.size();
+    case OP_ADD: return (int)n.child.size() + 1;
     case OP_PROD: return 0;
     case OP_DALITZ: return dz_n_const((int)n.consts[6], false);
     default: return dz_n_const((int)n.consts[6], true);

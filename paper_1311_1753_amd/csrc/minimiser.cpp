@@ -167,6 +167,21 @@ void Minimiser::finish(int st) {
   }
 }
 
+// EDM below which the evaluation cannot resolve the minimum: one rounding
+// unit of every parameter the evaluation rounds (relative precision eps),
+// measured in errors, with a factor 4 of margin; at least edm_tol.
+double Minimiser::edm_target() const {
+  double r = 0.0;
+  for (int k = 0; k < nf_; ++k) {
+    const int j = free_[k];
+    const double eps = o_.param_eps > 0.0 ? o_.param_eps : (o_.param_eps < 0.0 ? 0.0 : ps_[j].eps);
+    if (eps <= 0.0) continue;
+    const double sg = sigma_ext(j);
+    if (sg > 0.0 && std::isfinite(sg)) r += eps * std::fabs(x_best[j]) / sg;
+  }
+  return std::max(o_.edm_tol, 2.0 * r * r);
+}
+
 void Minimiser::begin_line() {
   p_.assign(nf_, 0.0);
   double slope = 0.0;
@@ -182,7 +197,7 @@ void Minimiser::begin_line() {
     reset_metric_diag();
   }
   edm = -0.5 * slope;
-  if (!(slope < 0.0) || edm < o_.edm_tol) {
+  if (!(slope < 0.0) || edm < edm_target()) {
     begin_final();
     return;
   }
@@ -312,7 +327,7 @@ void Minimiser::tell(double f, const std::vector<double>& g) {
             reset_metric_diag();
             begin_line();
           } else {
-            if (edm > 10.0 * o_.edm_tol) status = MAX_ITER;
+            if (edm > 10.0 * edm_target()) status = MAX_ITER;
             begin_final();
           }
           return;
@@ -430,9 +445,10 @@ void Minimiser::start_polish() {
   // step no longer does, the gradient is at its rounding-noise floor and the
   // point is as good as the evaluation allows (accepted if within ~5e-4 sigma)
   const bool floor = polish_ >= 1 && e > 0.25 * prev && e < 1e-7;
-  if (edm < o_.edm_tol || floor || polish_ >= 3) {
+  const double tgt = edm_target();
+  if (edm < tgt || floor || polish_ >= 3) {
     int st = status;
-    const bool ok = edm < 10.0 * o_.edm_tol || floor;
+    const bool ok = edm < 10.0 * tgt || floor;
     if (st == RUNNING) st = ok ? CONVERGED : MAX_ITER;
     else if (st == MAX_ITER && ok) st = CONVERGED;
     finish(st);

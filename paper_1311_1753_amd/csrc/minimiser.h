@@ -81,6 +81,7 @@ class Minimiser {
   void int_grad(const std::vector<double>& u, const std::vector<double>& gext, std::vector<double>& gu) const;
   void reset_metric_diag();
   void begin_line();
+  double edm_target() const;
   void begin_final();
   void finish(int st);
   void start_polish();

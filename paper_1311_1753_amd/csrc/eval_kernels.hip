@@ -261,6 +261,36 @@ __device__ __forceinline__ void row_store_waves(const double* acc, int nc, doubl
   __syncthreads();
 }
 
+// Per-thread double accumulators kept in LDS ([column][thread]) for the
+// amplitude and tree kernels, whose per-event state already fills the VGPRs:
+// each thread adds only to its own slots (ds_add_f64, program order, so the
+// sums are deterministic), and the block reduction reads them in place.
+template <int NC> struct LdsAcc {
+  double (*a)[kBlock];
+  __device__ __forceinline__ void zero(int nc) const {
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (j < nc) a[j][threadIdx.x] = 0.0;
+  }
+  __device__ __forceinline__ void add(int j, double v) const {
+    __hip_atomic_fetch_add(&a[j][threadIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+// Row store of LDS accumulators: wave w sums columns w, w + 4, ... over the
+// four waves (fixed order) and its 64 lanes.
+template <int NC>
+__device__ __forceinline__ void row_store_acc(const LdsAcc<NC>& acc, int nc, double* __restrict__ out, int stride) {
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = wave; j < nc; j += kBlock / 64) {
+    const double v = ((acc.a[j][lane] + acc.a[j][lane + 64]) + acc.a[j][lane + 128]) + acc.a[j][lane + 192];
+    const double s = wave_sum(v);
+    if (lane == 0) out[(int64_t)j * stride] = s;
+  }
+  __syncthreads();  // the accumulators are reused by the next row of a grid-stride block
+}
+
 // Chunk range [c0, c1) of row r when the dataset's chunks are split into
 // n_rows equal parts.
 __device__ __forceinline__ void row_chunks(int64_t n_events, int n_rows, int r, int64_t& c0, int64_t& c1) {
@@ -334,10 +364,10 @@ __device__ __forceinline__ void light_row(const Ev& ev, const typename Col<T>::S
 
 // Multi-column evaluators (amplitude leaves, trees): one event per chunk and
 // thread, the next event's columns in flight; the evaluator adds straight
-// into the double accumulators.
-template <typename T, int NCOL, class Ev>
+// into the (LDS) double accumulators.
+template <typename T, int NCOL, class Ev, class Acc>
 __device__ __forceinline__ void heavy_row(const Ev& ev, const KProgram& P, const typename Col<T>::S* const* cp,
-                                          int ncols, int64_t n, int64_t c0, int64_t c1, double* acc) {
+                                          int ncols, int64_t n, int64_t c0, int64_t c1, const Acc& acc) {
   typedef typename Col<T>::S Sx;
   const int64_t t = threadIdx.x;
   Sx cur[NCOL];
@@ -516,16 +546,17 @@ struct AmpLeafEv {  // single DALITZ / TDDP leaf
   CS cs;
   int c0, R, n_slots;
   bool hoisted;
-  __device__ __forceinline__ void operator()(const KProgram&, const double* xe, double* acc) const {
+  template <class Acc>
+  __device__ __forceinline__ void operator()(const KProgram&, const double* xe, const Acc& acc) const {
     T dl[NS];
     T lv;
     if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, c0, R, hoisted, xe[0], xe[1], dl);
     else lv = leaf_tddp<T>(cs, c0, R, hoisted, xe[0], xe[1], xe[2], xe[3], dl);
-    acc[0] -= (double)lv;
+    acc.add(0, -(double)lv);
     if (GRAD) {
 #pragma unroll
       for (int j = 0; j < NS; ++j)
-        if (j < n_slots) acc[1 + j] += (double)dl[j];
+        if (j < n_slots) acc.add(1 + j, (double)dl[j]);
     }
   }
 };
@@ -536,7 +567,8 @@ struct AmpLeafEv {  // single DALITZ / TDDP leaf
 template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
 struct TreeEv {
   CS cs;
-  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, double* acc) const {
+  template <class Acc>
+  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, const Acc& acc) const {
     constexpr int NN = HEAVY ? kMaxNodes : 8;  // node capacity of this instantiation
     const int n_nodes = P.n_nodes, n_slots = GRAD ? P.n_slots : 0;
     T lv[NN], adj[NN], resp[NN], dl[NS];
@@ -623,10 +655,10 @@ struct TreeEv {
       if (k != root)
         for (int j = 0; j < nd.n_slot; ++j) dl[nd.slot0 + j] = dl[nd.slot0 + j] * a;
     }
-    acc[0] -= (double)lv[root];
+    acc.add(0, -(double)lv[root]);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
-      if (j < n_slots) acc[1 + j] += (double)dl[j];
+      if (j < n_slots) acc.add(1 + j, (double)dl[j]);
   }
 };
 
@@ -682,13 +714,13 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
   const Sx* cp[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[nd.col[c]];
-  double acc[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  __shared__ double accs[NC][kBlock];
+  const LdsAcc<NC> acc{accs};
+  acc.zero(1 + ev.n_slots);
   int64_t c0, c1;
   row_chunks(n, n_rows, r, c0, c1);
   heavy_row<T, NCOL>(ev, P, cp, NCOL, n, c0, c1, acc);
-  row_store_waves<NC>(acc, 1 + ev.n_slots, out, n_rows);
+  row_store_acc<NC>(acc, 1 + ev.n_slots, out, n_rows);
 }
 
 template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
@@ -700,13 +732,14 @@ __device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const 
   const Sx* cp[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[c];
-  double acc[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  __shared__ double accs[NC][kBlock];
+  const LdsAcc<NC> acc{accs};
+  const int nc = 1 + (GRAD ? P.n_slots : 0);
+  acc.zero(nc);
   int64_t c0, c1;
   row_chunks(n, n_rows, r, c0, c1);
   heavy_row<T, NCOL>(ev, P, cp, P.n_cols, n, c0, c1, acc);
-  row_store_waves<NC>(acc, 1 + (GRAD ? P.n_slots : 0), out, n_rows);
+  row_store_acc<NC>(acc, nc, out, n_rows);
 }
 
 // ------------------------------------------------------------------ reduction
@@ -802,8 +835,15 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(const FitRec* __restrict__
 __global__ __launch_bounds__(kRedBlock) void k_reduce_one(const FitRec fr) { reduce_fit(fr); }
 
 // ------------------------------------------------------------------ kernels (one dataset; one block per row)
+// Waves per SIMD the compiler must leave room for: 3 for the float
+// time-dependent Dalitz kernel (168 VGPRs instead of 176 keeps three waves
+// resident; the others fit as they are).
+template <typename T, int OP> struct LeafWaves { static constexpr int value = 1; };
+template <> struct LeafWaves<float, OP_TDDP> { static constexpr int value = 3; };
+
 template <typename T, int OP, bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_leaf(const EvalArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LeafWaves<T, OP>::value)))
+void k_leaf(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   if constexpr (OP == OP_EXP || OP == OP_GAUSS)
     light_leaf_row<T, OP, GRAD>(a.prog.node[0], cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);

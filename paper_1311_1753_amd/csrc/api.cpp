@@ -9,7 +9,6 @@
 // memory written directly by the reduction kernel.
 #include <atomic>
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -73,15 +72,6 @@ static hipError_t wait_result(const dataset* d, hipStream_t st) {
   }
 }
 
-// In-launch reduction: on unless HIPFIT_FUSED_REDUCE=0.
-static bool fused_reduce() {
-  static const bool on = [] {
-    const char* v = std::getenv("HIPFIT_FUSED_REDUCE");
-    return !(v && v[0] == '0');
-  }();
-  return on;
-}
-
 static int ensure_result_buffer(const dataset* dc) {
   dataset* d = const_cast<dataset*>(dc);
   if (d->res_host) return HF_OK;
@@ -122,38 +112,23 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     a.partials = d->partials;
     a.n_rows = d->n_rows;
     a.pad = 0;
-    std::memset(&a.fuse, 0, sizeof(a.fuse));
     const bool prof = g_prof.on && (g_prof.calls++ % g_prof.every) == 0;
+    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
+                               prof ? g_prof.e[1] : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
+    FitRec fr;
+    std::memset(&fr, 0, sizeof(fr));
+    fr.partials = d->partials;
+    fr.n_rows = d->n_rows;
+    fr.result = d->res_dev;
+    fr.n_slots = want_grad ? S : 0;
+    fr.active = 1;
     dataset* dm = const_cast<dataset*>(d);
     dm->seq += 1;
-    int64_t* flag_dev = (int64_t*)(d->res_dev + kMaxSlots + 1);
-    hipError_t e;
-    if (fused_reduce()) {
-      // rows summed inside the likelihood launch (one launch per evaluation)
-      a.fuse.counters = d->counters;
-      a.fuse.gpart = d->gpart;
-      a.fuse.result = d->res_dev;
-      a.fuse.flag = flag_dev;
-      a.fuse.seq = d->seq;
-      e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
-                      prof ? g_prof.e[1] : nullptr);
-      if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
-    } else {
-      e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
-                      prof ? g_prof.e[1] : nullptr);
-      if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
-      FitRec fr;
-      std::memset(&fr, 0, sizeof(fr));
-      fr.partials = d->partials;
-      fr.n_rows = d->n_rows;
-      fr.result = d->res_dev;
-      fr.n_slots = want_grad ? S : 0;
-      fr.active = 1;
-      fr.flag = flag_dev;
-      fr.seq = d->seq;
-      e = launch_reduce_one(fr, st, prof ? g_prof.e[2] : nullptr, prof ? g_prof.e[3] : nullptr);
-      if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
-    }
+    fr.flag = (int64_t*)(d->res_dev + kMaxSlots + 1);
+    fr.seq = d->seq;
+    e = launch_reduce_one(fr, st, prof ? g_prof.e[2] : nullptr, prof ? g_prof.e[3] : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
     if (prof) {
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -164,7 +139,7 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     if (prof) {
       float t1 = 0.f, t2 = 0.f;
       hipEventElapsedTime(&t1, g_prof.e[0], g_prof.e[1]);
-      if (!fused_reduce()) hipEventElapsedTime(&t2, g_prof.e[2], g_prof.e[3]);
+      hipEventElapsedTime(&t2, g_prof.e[2], g_prof.e[3]);
       g_prof.eval_ms += t1;
       g_prof.reduce_ms += t2;
       g_prof.n += 1;
@@ -179,26 +154,6 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
   }
   *nll = v;
   return HF_OK;
-}
-
-size_t workspace_bytes(const pdf_graph* g, int32_t n_rows) {
-  const size_t nc = (size_t)g->prog.n_slots + 1;
-  const size_t rows = (size_t)std::max<int32_t>(n_rows, 1);
-  const size_t groups = (rows + kRowGroup - 1) / kRowGroup;
-  return align256(rows * nc * sizeof(double)) + align256((groups + 1) * sizeof(unsigned)) +
-         align256(groups * nc * sizeof(double));
-}
-
-void place_workspace(dataset* d, char* base) {
-  const pdf_graph* g = d->g;
-  const size_t nc = (size_t)g->prog.n_slots + 1;
-  const size_t rows = (size_t)std::max<int32_t>(d->n_rows, 1);
-  const size_t groups = (rows + kRowGroup - 1) / kRowGroup;
-  d->partials = (double*)base;
-  base += align256(rows * nc * sizeof(double));
-  d->counters = (unsigned*)base;
-  base += align256((groups + 1) * sizeof(unsigned));
-  d->gpart = (double*)base;
 }
 
 }  // namespace hf
@@ -245,7 +200,7 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
     const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
     d->n_rows = rows_for(g->kind, n);
     const size_t col_bytes = align256((size_t)n * es);
-    const size_t part_bytes = workspace_bytes(g, d->n_rows);
+    const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * (g->prog.n_slots + 1) * sizeof(double));
     const size_t total = col_bytes * nc + part_bytes;
     void* blk = nullptr;
     hipError_t e = hipMalloc(&blk, total);
@@ -257,9 +212,7 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
       d->col[c] = base + c * col_bytes;
       d->ref[c] = column_ref(g, c, prec);
     }
-    place_workspace(d.get(), base + nc * col_bytes);
-    e = hipMemset(d->counters, 0, (size_t)((d->n_rows + kRowGroup - 1) / kRowGroup + 1) * sizeof(unsigned));
-    if (e != hipSuccess) { hipFree(blk); return hip_fail(e, "dataset_upload: hipMemset"); }
+    d->partials = (double*)(base + nc * col_bytes);
 
     // convert through the pinned staging buffer, one chunk at a time
     if (n > 0) {
@@ -323,15 +276,13 @@ extern "C" int dataset_wrap_device(const pdf_graph* g, void* const* dev_cols, in
       d->ref[c] = column_ref(g, c, prec);
     }
     d->n_rows = rows_for(g->kind, n);
-    const size_t part_bytes = workspace_bytes(g, d->n_rows);
+    const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * (g->prog.n_slots + 1) * sizeof(double));
     void* blk = nullptr;
     hipError_t e = hipMalloc(&blk, part_bytes);
     if (e != hipSuccess) return fail(HF_E_OOM, std::string("dataset_wrap_device: hipMalloc: ") + hipGetErrorString(e));
     d->block = blk;
+    d->partials = (double*)blk;
     d->bytes = (int64_t)part_bytes;
-    place_workspace(d.get(), (char*)blk);
-    e = hipMemset(d->counters, 0, (size_t)((d->n_rows + kRowGroup - 1) / kRowGroup + 1) * sizeof(unsigned));
-    if (e != hipSuccess) { hipFree(blk); return hip_fail(e, "dataset_wrap_device: hipMemset"); }
     *out = d.release();
     return HF_OK;
   } catch (const std::exception& ex) {

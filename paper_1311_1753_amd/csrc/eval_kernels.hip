@@ -234,15 +234,12 @@ __device__ __forceinline__ void row_store_lds(const double* acc, double* __restr
 #pragma unroll
   for (int j = 0; j < NC; ++j) sh[j][threadIdx.x] = acc[j];
   __syncthreads();
-  __shared__ double fin[NC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = wave; j < NC; j += kBlock / 64) {
     const double v = ((sh[j][lane] + sh[j][lane + 64]) + sh[j][lane + 128]) + sh[j][lane + 192];
     const double s = wave_sum(v);
-    if (lane == 0) fin[j] = s;
+    if (lane == 0) out[(int64_t)j * stride] = s;
   }
-  __syncthreads();
-  if (threadIdx.x < NC) out[(int64_t)threadIdx.x * stride] = fin[threadIdx.x];
   __syncthreads();  // sh is reused by the next row of a grid-stride block
 }
 
@@ -285,15 +282,12 @@ template <int NC> struct LdsAcc {
 template <int NC>
 __device__ __forceinline__ void row_store_acc(const LdsAcc<NC>& acc, int nc, double* __restrict__ out, int stride) {
   __syncthreads();
-  __shared__ double fin[NC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = wave; j < nc; j += kBlock / 64) {
     const double v = ((acc.a[j][lane] + acc.a[j][lane + 64]) + acc.a[j][lane + 128]) + acc.a[j][lane + 192];
     const double s = wave_sum(v);
-    if (lane == 0) fin[j] = s;
+    if (lane == 0) out[(int64_t)j * stride] = s;
   }
-  __syncthreads();
-  if ((int)threadIdx.x < nc) out[(int64_t)threadIdx.x * stride] = fin[threadIdx.x];
   __syncthreads();  // the accumulators are reused by the next row of a grid-stride block
 }
 
@@ -840,72 +834,6 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(const FitRec* __restrict__
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce_one(const FitRec fr) { reduce_fit(fr); }
 
-// ------------------------------------------------------------------ in-launch reduction
-// Optional (EvalArgs::fuse): the rows are summed inside the likelihood
-// launch.  Rows form groups of kRowGroup; the block that completes a group
-// (counter) sums its rows in order into a group row, and the block that
-// completes the last group sums the group rows in order into the result and
-// sets the completion flag.  Only the first wave of a block stores rows, so
-// one device-scope release per block orders them before its counter update;
-// consumers acquire before reading.  Counters are reset by their consumers.
-__device__ __forceinline__ void fused_tail(const EvalArgs& a, int r, int nc) {
-  __shared__ int s_last;
-  const FuseArgs& f = a.fuse;
-  const int t = threadIdx.x;
-  const int n_groups = (a.n_rows + kRowGroup - 1) / kRowGroup;
-  const int g = r / kRowGroup;
-  const int in_g = min(kRowGroup, a.n_rows - g * kRowGroup);
-  if (t < 64) __threadfence();  // this block's row (stored by the first wave)
-  __syncthreads();
-  if (t == 0) s_last = atomicAdd(&f.counters[g], 1u) == (unsigned)(in_g - 1);
-  __syncthreads();
-  if (!s_last) return;
-  // this block completes group g
-  if (t < 64) {
-    __threadfence();
-    if (t < nc) {
-      const double* src = a.partials + (int64_t)t * a.n_rows + g * kRowGroup;
-      double v[kRowGroup];
-#pragma unroll
-      for (int k = 0; k < kRowGroup; ++k) v[k] = k < in_g ? src[k] : 0.0;
-      double sum = 0.0, c = 0.0;
-#pragma unroll
-      for (int k = 0; k < kRowGroup; ++k) {
-        double ns, e;
-        two_sum(sum, v[k], ns, e);
-        sum = ns;
-        c += e;
-      }
-      f.gpart[(int64_t)t * n_groups + g] = sum + c;
-    }
-    __threadfence();
-  }
-  __syncthreads();
-  if (t == 0) {
-    f.counters[g] = 0u;
-    s_last = atomicAdd(&f.counters[n_groups], 1u) == (unsigned)(n_groups - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  // this block completes the last group: the result
-  if (t < 64) {
-    __threadfence();
-    if (t < nc) {
-      double sum = 0.0, c = 0.0;
-      for (int k = 0; k < n_groups; ++k) {
-        double ns, e;
-        two_sum(sum, f.gpart[(int64_t)t * n_groups + k], ns, e);
-        sum = ns;
-        c += e;
-      }
-      f.result[t] = sum + c;
-    }
-    if (t == 0) f.counters[n_groups] = 0u;
-    __threadfence_system();
-    if (t == 0) *(volatile int64_t*)f.flag = f.seq;
-  }
-}
-
 // ------------------------------------------------------------------ kernels (one dataset; one block per row)
 // Waves per SIMD the compiler must leave room for: 3 for the float
 // time-dependent Dalitz kernel (168 VGPRs instead of 176 keeps three waves
@@ -921,21 +849,18 @@ void k_leaf(const EvalArgs a) {
     light_leaf_row<T, OP, GRAD>(a.prog.node[0], cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
   else
     amp_leaf_row<T, OP, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
-  if (a.fuse.counters) fused_tail(a, blockIdx.x, 1 + (GRAD ? a.prog.n_slots : 0));
 }
 
 template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   tree_row<T, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
-  if (a.fuse.counters) fused_tail(a, blockIdx.x, 1 + (GRAD ? a.prog.n_slots : 0));
 }
 
 template <typename T, int K, int MASK, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   mix_row<T, K, MASK, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
-  if (a.fuse.counters) fused_tail(a, blockIdx.x, 1 + (GRAD ? a.prog.n_slots : 0));
 }
 
 // Batched: the program structure is shared (kernel argument); constants,

@@ -73,15 +73,6 @@ constexpr int dz_coef_base(int R, bool tddp) { return dz_res_base(R, tddp) + R *
 constexpr int dz_time_base(int R) { return dz_coef_base(R, true) + 2 * R; }
 constexpr int dz_n_const(int R, bool tddp) { return dz_coef_base(R, tddp) + 2 * R + (tddp ? kTdCount : 0); }
 
-// In-launch reduction of one evaluation (counters == nullptr: off).
-struct FuseArgs {
-  unsigned* counters;          // n_groups + 1, zero between launches
-  double* gpart;               // column-major [n_slots + 1][n_groups]
-  double* result;              // n_slots + 1 doubles (mapped host memory)
-  int64_t* flag;               // set to seq once result is visible
-  int64_t seq;
-};
-
 // Arguments of one evaluation launch over one dataset.
 struct EvalArgs {
   KProgram prog;
@@ -90,7 +81,6 @@ struct EvalArgs {
   double* partials;            // column-major [n_slots + 1][n_rows]: sum(-ln P), slot sums
   int32_t n_rows;              // one block per row
   int32_t pad;
-  FuseArgs fuse;
 };
 
 // Header of a batched launch's device table, followed by the FitRec array.

@@ -24,8 +24,6 @@ enum KernelKind {
 // least kMinChunksLight chunks of 256 events per row for the light kinds.
 constexpr int kRowsPerCU = 4;
 constexpr int kMinChunksLight = 4;
-// rows per group of the in-launch reduction
-constexpr int kRowGroup = 32;
 
 // true for the single-column kinds (EXP, GAUSS, small trees, mixtures)
 bool kind_light(int kind);

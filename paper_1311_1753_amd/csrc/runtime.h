@@ -91,8 +91,6 @@ struct dataset {
   const void* col[hf::kMaxCols] = {nullptr};
   double ref[hf::kMaxCols] = {0.0};           // per-column reference (float path)
   double* partials = nullptr;
-  unsigned* counters = nullptr;               // in-launch reduction: group counters (zeroed)
-  double* gpart = nullptr;                    // in-launch reduction: group rows
   int32_t n_rows = 0;                         // one block per row (see rows_for)
   int64_t bytes = 0;
   double* res_host = nullptr;                 // pinned, device-mapped: result row, then the completion flag
@@ -117,11 +115,6 @@ int n_free(const pdf_graph* g);
 // Rows of a dataset of n events for a graph of kernel kind `kind` on the
 // current device.
 int32_t rows_for(int kind, int64_t n);
-// Device bytes of the per-dataset workspace (partial rows, group counters
-// and group rows of the in-launch reduction) for n_rows rows.
-size_t workspace_bytes(const pdf_graph* g, int32_t n_rows);
-// Points the workspace pointers of d into `base` (workspace_bytes long).
-void place_workspace(dataset* d, char* base);
 // NLL and gradient from the reduced sums [sum(-ln P), slot sums] of one
 // evaluation (sums may be null for an empty dataset); grad may be null.
 void assemble(const pdf_graph* g, const StagedCall& sc, const double* sums, int64_t n, double* nll, double* grad);

@@ -569,6 +569,68 @@ double om_nll(Model* m, const double* th, int64_t n, const double* const* cols, 
   return tot[0].value();
 }
 
+// Binned metrics (the fit-manager metric switch of section "GooFit code"):
+// events are bin centres with weights w_i (counts); P is the normalised root
+// density.  metric 1: binned NLL = -sum w_i ln P(x_i).  metric 2: chi^2 =
+// sum (w_i - K P(x_i))^2 / max(w_i, 1), K = (sum of weights) x bin volume,
+// the expected count of a bin being K P at its centre.  grad (nullable) =
+// d metric / d theta.  Thread partials are combined in thread order.
+double om_binned(Model* m, const double* th, int64_t n, const double* const* cols, const double* w, int metric,
+                 double K, double* grad, int n_threads) {
+  std::vector<NodeNorm> nn(m->nodes.size());
+  node_norm(*m, m->root, th, nn);
+  const int np = m->n_par;
+  int nt = n_threads > 0 ? n_threads : 1;
+  std::vector<Neumaier> part((size_t)nt * (np + 1));
+  bool bad = false;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt) reduction(|| : bad)
+#endif
+  {
+    int tid = 0, T = 1;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+    T = omp_get_num_threads();
+#endif
+    int64_t b = n * tid / T, e = n * (tid + 1) / T;
+    std::vector<double> ev(m->n_obs), g(np);
+    Neumaier* acc = &part[(size_t)tid * (np + 1)];
+    for (int64_t i = b; i < e; ++i) {
+      for (int o = 0; o < m->n_obs; ++o) ev[o] = cols[o][i];
+      const double lp = node_eval(*m, m->root, ev.data(), th, nn, g.data());
+      double term, dterm;  // metric term and its derivative with respect to ln P
+      if (metric == 1) {
+        if (!std::isfinite(lp)) {
+          if (w[i] != 0.0) bad = true;
+          continue;
+        }
+        term = -w[i] * lp;
+        dterm = -w[i];
+      } else {
+        const double E = std::isfinite(lp) ? K * std::exp(lp) : 0.0;
+        const double r = w[i] - E, s2 = std::max(w[i], 1.0);
+        term = r * r / s2;
+        dterm = -2.0 * r * E / s2;
+      }
+      acc[0].add(term);
+      if (grad)
+        for (int p = 0; p < np; ++p) acc[1 + p].add(dterm * g[p]);
+    }
+  }
+  if (bad) {
+    if (grad) for (int p = 0; p < np; ++p) grad[p] = NAN;
+    return INFINITY;
+  }
+  Neumaier tot;
+  std::vector<Neumaier> gt(np);
+  for (int t = 0; t < nt; ++t) {
+    tot.add(part[(size_t)t * (np + 1)].value());
+    for (int p = 0; p < np; ++p) gt[p].add(part[(size_t)t * (np + 1) + 1 + p].value());
+  }
+  if (grad) for (int p = 0; p < np; ++p) grad[p] = gt[p].value();
+  return tot.value();
+}
+
 // Per-event ln P_root (and optional per-event gradient rows, n x n_par).
 void om_logpdf(Model* m, const double* th, int64_t n, const double* const* cols, double* out, double* grad_rows,
                int n_threads) {

@@ -63,6 +63,9 @@ def lib():
                               ctypes.c_int, ctypes.c_int]
         L.om_nll.restype = ctypes.c_double
         L.om_nll.argtypes = [vp, dp, ctypes.c_int64, ctypes.POINTER(dp), dp, ctypes.c_int]
+        L.om_binned.restype = ctypes.c_double
+        L.om_binned.argtypes = [vp, dp, ctypes.c_int64, ctypes.POINTER(dp), dp, ctypes.c_int, ctypes.c_double, dp,
+                                ctypes.c_int]
         L.om_logpdf.argtypes = [vp, dp, ctypes.c_int64, ctypes.POINTER(dp), dp, dp, ctypes.c_int]
         L.om_node_lnnorm.restype = ctypes.c_double
         L.om_node_lnnorm.argtypes = [vp, ctypes.c_int, dp, dp]
@@ -199,6 +202,30 @@ class Model:
                          n_threads or n_threads_default())
         return (v, g) if grad else v
 
+    METRICS = {"bnll": 1, "chi2": 2}
+
+    def binned(self, theta, data, weights, metric, volume, grad=False, n_threads=None):
+        """Binned metric over bin centres `data` with weights (counts):
+        'bnll' = -sum w ln P, 'chi2' = sum (w - K P)^2 / max(w, 1) with
+        K = sum(w) * volume (om_binned)."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        keep, ptrs, n = self._cols(data)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if w.size != n:
+            raise ValueError("one weight per bin")
+        K = float(w.sum()) * float(volume)
+        g = np.zeros(len(self.par_names)) if grad else None
+        v = lib().om_binned(self._h, _dp(th), n, ptrs, _dp(w), self.METRICS[metric], K, _dp(g) if grad else None,
+                            n_threads or n_threads_default())
+        return (v, g) if grad else v
+
+    def objective(self, theta, data, grad=False, binned=None):
+        """The unbinned NLL, or the binned metric binned = dict(weights,
+        metric, volume)."""
+        if binned is None:
+            return self.nll(theta, data, grad=grad)
+        return self.binned(theta, data, binned["weights"], binned["metric"], binned["volume"], grad=grad)
+
     def logpdf(self, theta, data, grad_rows=False, n_threads=None):
         th = np.ascontiguousarray(theta, dtype=np.float64)
         keep, ptrs, n = self._cols(data)
@@ -269,7 +296,7 @@ class Model:
     def free_mask(self):
         return np.array([not p[5] for p in self.spec["params"]])
 
-    def hessian(self, theta, data, steps=None):
+    def hessian(self, theta, data, steps=None, binned=None):
         """Central finite differences of the exact gradient, symmetrised.
 
         Default steps: a tenth of each parameter's error, from a first pass
@@ -280,7 +307,7 @@ class Model:
         n = theta.size
         if steps is None:
             pstep = np.array([p[2] for p in self.spec["params"]])
-            H0 = self.hessian(theta, data, steps=1e-4 * np.maximum(pstep, 1e-12))
+            H0 = self.hessian(theta, data, steps=1e-4 * np.maximum(pstep, 1e-12), binned=binned)
             d = np.diag(H0)
             steps = np.where(d > 0, 0.1 / np.sqrt(np.abs(d) + 1e-300), 1e-4 * pstep)
         H = np.zeros((n, n))
@@ -289,16 +316,18 @@ class Model:
             tp, tm = theta.copy(), theta.copy()
             tp[j] += h
             tm[j] -= h
-            gp = self.nll(tp, data, grad=True)[1]
-            gm = self.nll(tm, data, grad=True)[1]
+            gp = self.objective(tp, data, grad=True, binned=binned)[1]
+            gm = self.objective(tm, data, grad=True, binned=binned)[1]
             H[:, j] = (gp - gm) / (2 * h)
         return 0.5 * (H + H.T)
 
-    def fit(self, data, theta0=None, polish_edm=1e-12, max_polish=20):
-        """Minimise the NLL; returns dict(theta, errors, cov, nll, edm).
+    def fit(self, data, theta0=None, polish_edm=1e-12, max_polish=20, binned=None):
+        """Minimise the NLL (or a binned metric); returns dict(theta, errors,
+        cov, nll, edm).
 
-        Errors are sqrt(diag(H^-1)) with H the NLL Hessian (the NLL up = 0.5
-        convention)."""
+        The covariance is 2 up H^-1 with H the Hessian of the objective: up =
+        0.5 for likelihoods (errors sqrt(diag(H^-1))), 1 for chi^2."""
+        up = 1.0 if binned is not None and binned["metric"] == "chi2" else 0.5
         from scipy.optimize import minimize
         free = self.free_mask()
         th0 = self.theta() if theta0 is None else np.asarray(theta0, dtype=np.float64).copy()
@@ -309,7 +338,7 @@ class Model:
         def f(u):
             th = th0.copy()
             th[idx] = u * scale
-            v, g = self.nll(th, data, grad=True)
+            v, g = self.objective(th, data, grad=True, binned=binned)
             if not np.isfinite(v):
                 return 1e300, np.zeros_like(u)
             return v, g[idx] * scale
@@ -322,19 +351,19 @@ class Model:
         th[idx] = r.x * scale
         edm = np.inf
         for _ in range(max_polish):
-            v, g = self.nll(th, data, grad=True)
-            H = self.hessian(th, data)[np.ix_(idx, idx)]
+            v, g = self.objective(th, data, grad=True, binned=binned)
+            H = self.hessian(th, data, binned=binned)[np.ix_(idx, idx)]
             step = np.linalg.solve(H, g[idx])
             edm = 0.5 * float(g[idx] @ step)
             if edm < polish_edm:
                 break
             th[idx] -= step
-        v, g = self.nll(th, data, grad=True)
-        H = self.hessian(th, data)[np.ix_(idx, idx)]
-        cov = np.linalg.inv(H)
+        v, g = self.objective(th, data, grad=True, binned=binned)
+        H = self.hessian(th, data, binned=binned)[np.ix_(idx, idx)]
+        cov = 2.0 * up * np.linalg.inv(H)
         err = np.zeros(th.size)
         err[idx] = np.sqrt(np.diag(cov))
-        edm = 0.5 * float(g[idx] @ (cov @ g[idx]))
+        edm = 0.5 * float(g[idx] @ np.linalg.solve(H, g[idx]))
         return {"theta": th, "errors": err, "cov": cov, "nll": v, "edm": edm, "free": idx}
 
 

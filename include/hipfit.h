@@ -54,6 +54,17 @@ typedef enum {
                                accumulation in double with compensated sums */
 } hf_precision;
 
+/* Binned metrics (the fit-manager metric switch of the paper's "GooFit code"
+ * section; binned fits as in its results section).  Events are bin centres
+ * with weights w_i (counts); P is the normalised density of the graph.
+ *   HF_METRIC_BNLL: binned NLL = -sum_i w_i ln P(x_i)
+ *   HF_METRIC_CHI2: chi^2 = sum_i (w_i - K P(x_i))^2 / max(w_i, 1), with
+ *                   K = (sum of the weights) x bin volume the expected
+ *                   count of a bin per unit density at its centre.
+ * Fits of chi^2 use up = 1 (errors sqrt(diag(2 H^-1))), the likelihoods up
+ * = 0.5 (sqrt(diag(H^-1))). */
+typedef enum { HF_METRIC_BNLL = 1, HF_METRIC_CHI2 = 2 } hf_metric;
+
 /* Node kinds of the PDF tree (paper, sections "GooFit code", "Combining
  * functions", "Results").  Every node is a density normalised over its
  * observables' box. */
@@ -152,6 +163,15 @@ int dataset_wrap_device(const pdf_graph* g, void* const* dev_cols, int64_t n_eve
  * middle of its box, 0 for an unbounded or unused observable; always 0 for
  * HF_FP64). */
 int hf_column_ref(const pdf_graph* g, int32_t obs, hf_precision prec, double* ref);
+/* Binned dataset: n_bins bin centres (host columns as for dataset_upload,
+ * validated the same way) with weights[n_bins] >= 0 (finite), equal bins of
+ * volume bin_volume > 0, and the metric that nll_eval / nll_grad / fit then
+ * evaluate for it (the "NLL" outputs carry the metric's value).  Any graph
+ * with at most 31 gradient slots; binned datasets are evaluated one at a
+ * time (nll_grad_batched and the batch engine reject them). */
+int dataset_upload_binned(const pdf_graph* g, const double* const* centres, const double* weights,
+                          int64_t n_bins, double bin_volume, int32_t metric, hf_precision prec, void* hip_stream,
+                          dataset** out);
 void dataset_free(dataset* d);
 /* Device bytes held by a dataset (columns + workspace). */
 int64_t dataset_device_bytes(const dataset* d);

@@ -23,6 +23,8 @@ HF_E_FULL = -9
 
 HF_FP64 = 0
 HF_FP32_EVAL = 1
+HF_METRIC_BNLL = 1
+HF_METRIC_CHI2 = 2
 
 OP = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7}
 
@@ -81,6 +83,8 @@ SIGNATURES = {
     "dataset_wrap_device": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int,
                                            ctypes.POINTER(_VP)]),
     "hf_column_ref": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _DP]),
+    "dataset_upload_binned": (ctypes.c_int, [_VP, ctypes.POINTER(_DP), _DP, ctypes.c_int64, ctypes.c_double,
+                                             ctypes.c_int32, ctypes.c_int, _VP, ctypes.POINTER(_VP)]),
     "dataset_free": (None, [_VP]),
     "dataset_device_bytes": (ctypes.c_int64, [_VP]),
     # theta and grad are passed as raw addresses (numpy .ctypes.data)

@@ -182,6 +182,33 @@ class Dataset:
         self.n = n
 
     @classmethod
+    def binned(cls, graph, centres, weights, bin_volume, metric="bnll", precision="fp64", stream=None):
+        """Binned dataset (dataset_upload_binned): bin centres per observable,
+        weights (counts) per bin, equal bins of volume bin_volume; metric
+        "bnll" (-sum w ln P) or "chi2" (sum (w - K P)^2 / max(w, 1), K = sum(w)
+        x bin volume).  nll_eval / nll_grad / fit then evaluate that metric."""
+        self = cls.__new__(cls)
+        self.graph = graph
+        self.precision = _prec(precision)
+        m = {"bnll": _lib.HF_METRIC_BNLL, "chi2": _lib.HF_METRIC_CHI2}[metric]
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        n = w.size
+        arrs = []
+        for name in graph.obs_names:
+            a = np.ascontiguousarray(centres[name], dtype=np.float64) if name in centres else np.zeros(n)
+            if a.size != n:
+                raise ValueError("one centre per bin and observable")
+            arrs.append(a)
+        ptrs = (_lib._DP * len(arrs))(*[a.ctypes.data_as(_lib._DP) for a in arrs])
+        h = ctypes.c_void_p()
+        check(lib().dataset_upload_binned(graph.handle, ptrs, w.ctypes.data_as(_lib._DP), n, float(bin_volume), m,
+                                          self.precision, _stream_ptr(stream), ctypes.byref(h)))
+        self._keep = None
+        self._h = h
+        self.n = n
+        return self
+
+    @classmethod
     def from_device(cls, graph, columns, precision="fp64"):
         """Borrows device tensors instead of copying (dataset_wrap_device):
         columns maps observable names to contiguous CUDA tensors -- float64

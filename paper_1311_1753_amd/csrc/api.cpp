@@ -90,17 +90,68 @@ static int ensure_result_buffer(const dataset* dc) {
   return HF_OK;
 }
 
+// One evaluation of a binned dataset: the tree interpreter with the metric,
+// then the reduction of its [metric, slots, sum of dmetric/dlnP] columns.
+static int eval_binned(const pdf_graph* g, const dataset* d, const StagedCall& sc, hipStream_t st, bool want_grad,
+                       double* value, double* grad) {
+  const int S = g->n_slots_tree;
+  std::vector<double> sums(S + 2, 0.0);
+  if (d->n > 0) {
+    if (int rc = ensure_result_buffer(d)) return rc;
+    EvalArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.prog = sc.prog;
+    a.prog.n_slots = S;
+    for (int c = 0; c < kMaxCols; ++c) a.col[c] = d->col[c];
+    a.n_events = d->n;
+    a.partials = d->partials;
+    a.n_rows = d->n_rows;
+    a.metric = d->metric;
+    a.wcol = d->wcol;
+    a.kfac = d->wsum * d->volume;
+    a.lnL = sc.ht.lnN;
+    const bool heavy = g->dz.node >= 0 || S > 8 || g->prog.n_cols > 2 || g->prog.n_nodes > 8;
+    hipError_t e = launch_binned(d->prec == HF_FP32_EVAL, want_grad, heavy, a, st);
+    if (e != hipSuccess) return hip_fail(e, "launch of the binned kernel");
+    FitRec fr;
+    std::memset(&fr, 0, sizeof(fr));
+    fr.partials = d->partials;
+    fr.n_rows = d->n_rows;
+    fr.result = d->res_dev;
+    fr.n_slots = want_grad ? S + 1 : 0;
+    fr.active = 1;
+    dataset* dm = const_cast<dataset*>(d);
+    dm->seq += 1;
+    fr.flag = (int64_t*)(d->res_dev + kMaxSlots + 1);
+    fr.seq = d->seq;
+    e = launch_reduce_one(fr, st);
+    if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
+    e = wait_result(d, st);
+    if (e != hipSuccess) return hip_fail(e, "waiting for the reduction");
+    for (int j = 0; j < (want_grad ? S + 2 : 1); ++j) sums[j] = d->res_host[j];
+  }
+  double v = 0.0;
+  assemble_binned(g, sc, d->n > 0 ? sums.data() : nullptr, &v, grad);
+  if (!std::isfinite(v)) {
+    *value = INFINITY;
+    return fail(HF_E_DOMAIN, "density <= 0 or not finite at a bin with weight");
+  }
+  *value = v;
+  return HF_OK;
+}
+
 int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t st, bool want_grad, double* nll,
              double* grad) {
   const int np = (int)g->par.size();
   if (int rc = ensure_grid(const_cast<pdf_graph*>(g), st)) return rc;
   StagedCall sc;
-  stage(g, th, d->prec, sc);
+  stage(g, th, d->prec, sc, d->metric != 0);
   if (!sc.ok) {
     *nll = INFINITY;
     if (grad) for (int p = 0; p < np; ++p) grad[p] = NAN;
     return fail(HF_E_DOMAIN, "parameters outside the density's domain");
   }
+  if (d->metric != 0) return eval_binned(g, d, sc, st, want_grad, nll, grad);
   const int S = g->prog.n_slots;
   std::vector<double> sums(S + 1, 0.0);
   if (d->n > 0) {
@@ -111,7 +162,10 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     a.n_events = d->n;
     a.partials = d->partials;
     a.n_rows = d->n_rows;
-    a.pad = 0;
+    a.metric = 0;
+    a.wcol = nullptr;
+    a.kfac = 0.0;
+    a.lnL = 0.0;
     const bool prof = g_prof.on && (g_prof.calls++ % g_prof.every) == 0;
     hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
                                prof ? g_prof.e[1] : nullptr);
@@ -160,8 +214,10 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
 
 using namespace hf;
 
-extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols, int64_t n, hf_precision prec,
-                              void* hip_stream, dataset** out) {
+// Upload of an unbinned dataset (metric 0) or of bin centres with weights
+// (metric 1 or 2).
+static int upload(const pdf_graph* g, const double* const* host_cols, int64_t n, hf_precision prec,
+                  void* hip_stream, int metric, const double* weights, double volume, dataset** out) {
   try {
     if (!g || !out || (n > 0 && !host_cols)) return fail(HF_E_INVALID, "dataset_upload: NULL argument");
     if (n < 0 || n > (int64_t(1) << 36)) return fail(HF_E_INVALID, "dataset_upload: n_events out of range");
@@ -198,10 +254,16 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
     d->n = n;
     d->n_cols = nc;
     const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
-    d->n_rows = rows_for(g->kind, n);
+    // binned datasets run the tree interpreter: one event per chunk and
+    // thread, partial columns [metric, tree slots, sum of dmetric/dlnP]
+    d->metric = metric;
+    d->volume = volume;
+    d->n_rows = rows_for(metric ? (int)KIND_TREE : g->kind, n);
+    const int part_cols = metric ? g->n_slots_tree + 2 : g->prog.n_slots + 1;
     const size_t col_bytes = align256((size_t)n * es);
-    const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * (g->prog.n_slots + 1) * sizeof(double));
-    const size_t total = col_bytes * nc + part_bytes;
+    const size_t w_bytes = metric ? align256((size_t)n * sizeof(double)) : 0;
+    const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * part_cols * sizeof(double));
+    const size_t total = col_bytes * nc + w_bytes + part_bytes;
     void* blk = nullptr;
     hipError_t e = hipMalloc(&blk, total);
     if (e != hipSuccess) return fail(HF_E_OOM, std::string("dataset_upload: hipMalloc: ") + hipGetErrorString(e));
@@ -212,7 +274,17 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
       d->col[c] = base + c * col_bytes;
       d->ref[c] = column_ref(g, c, prec);
     }
-    d->partials = (double*)(base + nc * col_bytes);
+    d->partials = (double*)(base + nc * col_bytes + w_bytes);
+    if (metric) {
+      d->wcol = (const double*)(base + nc * col_bytes);
+      double ws = 0.0;
+      for (int64_t i = 0; i < n; ++i) ws += weights[i];
+      d->wsum = ws;
+      if (n > 0) {
+        e = hipMemcpy((void*)d->wcol, weights, (size_t)n * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { hipFree(blk); return hip_fail(e, "dataset_upload_binned: weights"); }
+      }
+    }
 
     // convert through the pinned staging buffer, one chunk at a time
     if (n > 0) {
@@ -245,6 +317,28 @@ extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols
   } catch (const std::exception& ex) {
     return fail(HF_E_INVALID, std::string("dataset_upload: ") + ex.what());
   }
+}
+
+extern "C" int dataset_upload(const pdf_graph* g, const double* const* host_cols, int64_t n, hf_precision prec,
+                              void* hip_stream, dataset** out) {
+  return upload(g, host_cols, n, prec, hip_stream, 0, nullptr, 0.0, out);
+}
+
+extern "C" int dataset_upload_binned(const pdf_graph* g, const double* const* centres, const double* weights,
+                                     int64_t n_bins, double bin_volume, int32_t metric, hf_precision prec,
+                                     void* hip_stream, dataset** out) {
+  if (metric != HF_METRIC_BNLL && metric != HF_METRIC_CHI2)
+    return fail(HF_E_INVALID, "dataset_upload_binned: metric must be HF_METRIC_BNLL or HF_METRIC_CHI2");
+  if (!(bin_volume > 0.0) || !std::isfinite(bin_volume))
+    return fail(HF_E_INVALID, "dataset_upload_binned: bin volume must be positive");
+  if (!g) return fail(HF_E_INVALID, "dataset_upload_binned: NULL graph");
+  if (g->n_slots_tree + 2 > kMaxSlots + 1)
+    return fail(HF_E_GRAPH, "dataset_upload_binned: more than 31 gradient slots");
+  if (n_bins > 0 && !weights) return fail(HF_E_INVALID, "dataset_upload_binned: NULL weights");
+  for (int64_t i = 0; i < n_bins; ++i)
+    if (!(weights[i] >= 0.0) || !std::isfinite(weights[i]))
+      return fail(HF_E_INVALID, "dataset_upload_binned: weights must be finite and >= 0");
+  return upload(g, centres, n_bins, prec, hip_stream, metric, weights, bin_volume, out);
 }
 
 extern "C" int hf_column_ref(const pdf_graph* g, int32_t obs, hf_precision prec, double* ref) {

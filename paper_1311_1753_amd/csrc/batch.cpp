@@ -162,6 +162,7 @@ extern "C" int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int
     for (int i = 0; i < n_fits; ++i) {
       if (!d[i] || d[i]->g != g) return fail(HF_E_SHAPE, "nll_grad_batched: dataset of another graph");
       if (d[i]->prec != d[0]->prec) return fail(HF_E_SHAPE, "nll_grad_batched: mixed precisions");
+      if (d[i]->metric != 0) return fail(HF_E_INVALID, "nll_grad_batched: binned datasets are evaluated one at a time");
     }
     hipStream_t st = (hipStream_t)hip_stream;
     if (int rc = ensure_grid(const_cast<pdf_graph*>(g), st)) return rc;
@@ -273,6 +274,7 @@ extern "C" int batch_admit(batch_engine* b, const dataset* d, const double* para
   try {
     if (!b || !d || !params_init) return fail(HF_E_INVALID, "batch_admit: NULL argument");
     if (d->g != b->g) return fail(HF_E_SHAPE, "batch_admit: dataset of another graph");
+    if (d->metric != 0) return fail(HF_E_INVALID, "batch_admit: binned datasets are fitted one at a time");
     if (opts && opts->grad_mode != 0) return fail(HF_E_INVALID, "batch_admit: only the analytic gradient is batched");
     if (b->prec_set && d->prec != b->prec) return fail(HF_E_INVALID, "batch_admit: precision differs from the engine's");
     if (d->bytes > b->budget) return fail(HF_E_INVALID, "batch_admit: dataset larger than the whole budget");

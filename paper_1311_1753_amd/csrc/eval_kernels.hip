@@ -388,7 +388,7 @@ __device__ __forceinline__ void heavy_row(const Ev& ev, const KProgram& P, const
       for (int c = 0; c < NCOL; ++c)
         if (c < ncols) cur[c] = i1 < n ? cp[c][i1] : Sx(0);
     }
-    if (i < n) ev(P, xe, acc);
+    if (i < n) ev(P, xe, i, acc);
   }
 }
 
@@ -547,7 +547,7 @@ struct AmpLeafEv {  // single DALITZ / TDDP leaf
   int c0, R, n_slots;
   bool hoisted;
   template <class Acc>
-  __device__ __forceinline__ void operator()(const KProgram&, const double* xe, const Acc& acc) const {
+  __device__ __forceinline__ void operator()(const KProgram&, const double* xe, int64_t, const Acc& acc) const {
     T dl[NS];
     T lv;
     if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, c0, R, hoisted, xe[0], xe[1], dl);
@@ -564,14 +564,13 @@ struct AmpLeafEv {  // single DALITZ / TDDP leaf
 // General trees (ADD / PROD over leaves).  Node log-values, adjoints and the
 // per-event slot derivatives live in small VGPR arrays indexed by
 // wave-uniform node / slot numbers.
+// Returns ln P of the root (without the normalisations of hoisted nodes)
+// and, with GRAD, its slot derivatives in dl[0 .. P.n_slots).
 template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
-struct TreeEv {
-  CS cs;
-  template <class Acc>
-  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, const Acc& acc) const {
+__device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const double* xe, T* dl) {
     constexpr int NN = HEAVY ? kMaxNodes : 8;  // node capacity of this instantiation
-    const int n_nodes = P.n_nodes, n_slots = GRAD ? P.n_slots : 0;
-    T lv[NN], adj[NN], resp[NN], dl[NS];
+    const int n_nodes = P.n_nodes;
+    T lv[NN], adj[NN], resp[NN];
     // forward pass (post-order)
     for (int k = 0; k < n_nodes; ++k) {
       const KNode& nd = P.node[k];
@@ -655,10 +654,58 @@ struct TreeEv {
       if (k != root)
         for (int j = 0; j < nd.n_slot; ++j) dl[nd.slot0 + j] = dl[nd.slot0 + j] * a;
     }
-    acc.add(0, -(double)lv[root]);
+    return lv[root];
+}
+
+template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+struct TreeEv {
+  CS cs;
+  template <class Acc>
+  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, int64_t, const Acc& acc) const {
+    const int n_slots = GRAD ? P.n_slots : 0;
+    T dl[NS];
+    const T lr = tree_eval<T, NS, NCOL, HEAVY, GRAD>(P, cs, xe, dl);
+    acc.add(0, -(double)lr);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
       if (j < n_slots) acc.add(1 + j, (double)dl[j]);
+  }
+};
+
+// Binned metrics over bin centres with weights w (metric 1: -w ln P; metric
+// 2: (w - K P)^2 / max(w, 1)).  ln P is the full log-density: the hoisted
+// normalisations L are subtracted here.  Accumulators: [metric, sum over
+// bins of dmetric/dlnP x slot derivatives, sum of dmetric/dlnP] -- the last
+// carries the hoisted normalisations' derivatives on the host.
+template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+struct BinnedEv {
+  CS cs;
+  const double* w;
+  double K, L;
+  int metric;
+  template <class Acc>
+  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, int64_t i, const Acc& acc) const {
+    const int n_slots = GRAD ? P.n_slots : 0;
+    T dl[NS];
+    const double lp = (double)tree_eval<T, NS, NCOL, HEAVY, GRAD>(P, cs, xe, dl) - L;
+    const double wi = w[i];
+    double term, dterm;
+    if (metric == 1) {
+      term = wi != 0.0 ? -wi * lp : 0.0;
+      dterm = -wi;
+    } else {
+      const double E = lp > -INFINITY ? K * ::exp(lp) : 0.0;
+      const double r = wi - E, s2 = wi > 1.0 ? wi : 1.0;
+      term = r * r / s2;
+      dterm = -2.0 * r * E / s2;
+    }
+    acc.add(0, term);
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+        if (j < n_slots) acc.add(1 + j, dterm * (double)dl[j]);
+      acc.add(1 + n_slots, dterm);
+    }
   }
 };
 
@@ -863,6 +910,26 @@ __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
   mix_row<T, K, MASK, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
 }
 
+// Binned datasets (any tree): the tree interpreter with the binned metric.
+template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_binned(const EvalArgs a) {
+  typedef typename Col<T>::S Sx;
+  constexpr int NC = NS + 2;
+  const CS cs{a.prog.c64, a.prog.c32};
+  const BinnedEv<T, NS, NCOL, HEAVY, GRAD> ev{cs, a.wcol, a.kfac, a.lnL, a.metric};
+  const Sx* cp[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)a.col[c];
+  __shared__ double accs[NC][kBlock];
+  const LdsAcc<NC> acc{accs};
+  const int nc = GRAD ? a.prog.n_slots + 2 : 1;
+  acc.zero(nc);
+  int64_t c0, c1;
+  row_chunks(a.n_events, a.n_rows, blockIdx.x, c0, c1);
+  heavy_row<T, NCOL>(ev, a.prog, cp, a.prog.n_cols, a.n_events, c0, c1, acc);
+  row_store_acc<NC>(acc, nc, a.partials + blockIdx.x, a.n_rows);
+}
+
 // Batched: the program structure is shared (kernel argument); constants,
 // columns and partials are per fit.  Fits own contiguous ranges of the global
 // row list in fit order; each block walks global rows blockIdx.x,
@@ -963,6 +1030,24 @@ hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStr
   if (a.n_rows <= 0) return hipSuccess;
   if (fp32) return grad ? launch_any<float, true>(kind, a, st, e0, e1) : launch_any<float, false>(kind, a, st, e0, e1);
   return grad ? launch_any<double, true>(kind, a, st, e0, e1) : launch_any<double, false>(kind, a, st, e0, e1);
+}
+
+template <typename T, bool GRAD>
+static hipError_t launch_binned_t(bool heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid((unsigned)a.n_rows), block(kBlock);
+  if (heavy)
+    hipExtLaunchKernelGGL((k_binned<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+  else
+    hipExtLaunchKernelGGL((k_binned<T, 8, 2, false, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_binned(bool fp32, bool grad, bool heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1) {
+  if (a.n_rows <= 0) return hipSuccess;
+  if (fp32)
+    return grad ? launch_binned_t<float, true>(heavy, a, st, e0, e1) : launch_binned_t<float, false>(heavy, a, st, e0, e1);
+  return grad ? launch_binned_t<double, true>(heavy, a, st, e0, e1) : launch_binned_t<double, false>(heavy, a, st, e0, e1);
 }
 
 template <typename T>

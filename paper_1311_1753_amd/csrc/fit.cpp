@@ -61,7 +61,9 @@ extern "C" int fit(const pdf_graph* g, const dataset* d, const hf_fit_opts* opts
     if (mode != 0 && mode != 1) return fail(HF_E_INVALID, "fit: grad_mode must be 0 or 1");
     hipStream_t st = (hipStream_t)hip_stream;
     Minimiser m;
-    m.start(min_params(g, d->prec), params_inout, min_options(opts, d->prec));
+    MinOptions mo = min_options(opts, d->prec);
+    if (d->metric == HF_METRIC_CHI2) mo.up = 1.0;
+    m.start(min_params(g, d->prec), params_inout, mo);
     std::vector<double> x(np), gr(np), xp(np);
     int n_eval = 0;
     while (m.ask(x)) {

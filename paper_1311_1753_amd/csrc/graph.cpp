@@ -210,6 +210,18 @@ void assemble(const pdf_graph* g, const StagedCall& sc, const double* sums, int6
     if (g->par[p].fixed) grad[p] = 0.0;
 }
 
+void assemble_binned(const pdf_graph* g, const StagedCall& sc, const double* sums, double* value, double* grad) {
+  const int np = (int)g->par.size(), S = g->n_slots_tree;
+  *value = sums ? sums[0] : 0.0;
+  if (!grad) return;
+  for (int p = 0; p < np; ++p) grad[p] = sums ? -sc.ht.dlnN[p] * sums[1 + S] : 0.0;
+  if (sums)
+    for (int j = 0; j < S; ++j)
+      if (g->slot_par_tree[j] >= 0) grad[g->slot_par_tree[j]] += sums[1 + j];
+  for (int p = 0; p < np; ++p)
+    if (g->par[p].fixed) grad[p] = 0.0;
+}
+
 int32_t rows_for(int kind, int64_t n) {
   if (n <= 0) return 0;
   static int cus[64] = {0};
@@ -234,7 +246,7 @@ int32_t rows_for(int kind, int64_t n) {
 }
 
 // ------------------------------------------------------------------ staging
-void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& sc) {
+void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& sc, bool generic) {
   sc.prog = g->prog;
   sc.ok = true;
   sc.ht.lnN = 0.0;
@@ -283,7 +295,7 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         const int col = kn.col[0];
         const ObsInfo& o = g->obs[g->obs_of_col[col]];
         // the mixture kernel uses log2(e) alpha rounded to float
-        const bool mixc = g->mix.K > 0 && k != g->mix.root;
+        const bool mixc = !generic && g->mix.K > 0 && k != g->mix.root;
         const double alpha = !fp32 ? th[nd.par[0]]
                                    : (mixc ? (double)(float)(kLog2e * th[nd.par[0]]) / kLog2e : rnd(th[nd.par[0]]));
         P.c64[c0] = column_ref(g, col, prec) - o.lo;
@@ -697,6 +709,9 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
         setc(rb + kResJ, r.J);
       }
     }
+    // the generic slot layout (the tree interpreter's, used by binned datasets)
+    g->slot_par_tree = g->slot_par;
+    g->n_slots_tree = P.n_slots;
     // parameters that the float path sees rounded to float (through 1/sigma,
     // fractions, rates, coefficients); Gaussian means and the decay time and
     // width difference of the time-dependent density enter through double

@@ -80,7 +80,10 @@ struct EvalArgs {
   int64_t n_events;
   double* partials;            // column-major [n_slots + 1][n_rows]: sum(-ln P), slot sums
   int32_t n_rows;              // one block per row
-  int32_t pad;
+  int32_t metric;              // 0: unbinned NLL; binned: 1 weighted NLL, 2 chi^2
+  const double* wcol;          // binned: bin weights (counts)
+  double kfac;                 // binned chi^2: expected count = kfac * P
+  double lnL;                  // binned: normalisations of hoisted nodes (ln P = kernel value - lnL)
 };
 
 // Header of a batched launch's device table, followed by the FitRec array.

@@ -32,6 +32,10 @@ bool kind_light(int kind);
 hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Binned datasets: the tree interpreter with the binned metric; `heavy`
+// selects the general instantiation (32 slots, 8 columns, amplitude nodes).
+hipError_t launch_binned(bool fp32, bool grad, bool heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, hipStream_t st);
 hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,
                                const float* c32, int n_const, int grid, hipStream_t st);

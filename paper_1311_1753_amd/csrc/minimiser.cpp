@@ -162,7 +162,8 @@ void Minimiser::finish(int st) {
     // errors from the variable metric when no final Hessian was taken
     for (int k = 0; k < nf_; ++k) {
       const int j = free_[k];
-      if (!V_.empty() && V_[k * nf_ + k] > 0.0) err[j] = std::sqrt(V_[k * nf_ + k]) * std::fabs(dxdu(j, u_[k]));
+      if (!V_.empty() && V_[k * nf_ + k] > 0.0)
+        err[j] = std::sqrt(2.0 * o_.up * V_[k * nf_ + k]) * std::fabs(dxdu(j, u_[k]));
     }
   }
 }
@@ -395,8 +396,9 @@ void Minimiser::tell(double f, const std::vector<double>& g) {
       }
       Cfree_ = C;
       for (int a = 0; a < nf_; ++a) {
-        err[free_[a]] = std::sqrt(C[a * nf_ + a]);
-        for (int b = 0; b < nf_; ++b) cov[(size_t)free_[a] * n_ + free_[b]] = C[a * nf_ + b];
+        // covariance 2 up H^-1 (up = 0.5: likelihoods, 1: chi^2)
+        err[free_[a]] = std::sqrt(2.0 * o_.up * C[a * nf_ + a]);
+        for (int b = 0; b < nf_; ++b) cov[(size_t)free_[a] * n_ + free_[b]] = 2.0 * o_.up * C[a * nf_ + b];
       }
       start_polish();
       return;

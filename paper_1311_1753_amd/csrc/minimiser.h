@@ -26,6 +26,7 @@ struct MinOptions {
   bool want_errors = true;
   double f_noise = 1e-13;  // relative noise of f tolerated by the line search
   double param_eps = 0.0;  // > 0: overrides every MinParam::eps; < 0: all exact
+  double up = 0.5;         // objective change that defines one error (0.5: likelihoods, 1: chi^2)
 };
 
 class Minimiser {

@@ -72,6 +72,8 @@ struct pdf_graph {
   std::vector<hf::NodeInfo> nodes;   // post-order, root last (re-indexed)
   hf::KProgram prog;                 // structure; static constants filled
   std::vector<int> slot_par;         // gradient slot -> parameter index
+  std::vector<int> slot_par_tree;    // the same for the tree interpreter's slot layout
+  int n_slots_tree = 0;
   std::vector<bool> par_rounded;     // parameter reaches the float kernels rounded to float
   int kind = 0;
   int n_const = 0;
@@ -96,6 +98,9 @@ struct dataset {
   double* res_host = nullptr;                 // pinned, device-mapped: result row, then the completion flag
   double* res_dev = nullptr;
   int64_t seq = 0;                            // completion flag value of the last evaluation
+  int metric = 0;                             // 0: unbinned; 1 binned NLL; 2 chi^2 (HF_METRIC_*)
+  const double* wcol = nullptr;               // binned: weights (device, in the block)
+  double wsum = 0.0, volume = 0.0;            // binned: total weight, bin volume
 };
 
 namespace hf {
@@ -103,7 +108,9 @@ namespace hf {
 // Column reference used by the float path (0 for unbounded observables).
 double column_ref(const pdf_graph* g, int col, hf_precision prec);
 // Fills the constant table of `sc.prog` for parameters `theta`.
-void stage(const pdf_graph* g, const double* theta, hf_precision prec, StagedCall& sc);
+// generic: constants for the tree interpreter even when the graph has a
+// static mixture kernel (binned datasets).
+void stage(const pdf_graph* g, const double* theta, hf_precision prec, StagedCall& sc, bool generic = false);
 // Makes sure the Dalitz normalisation matrices exist (runs the grid kernels once).
 int ensure_grid(pdf_graph* g, hipStream_t st);
 // Host membership test of the Dalitz plot (same rule as the grid).
@@ -118,5 +125,8 @@ int32_t rows_for(int kind, int64_t n);
 // NLL and gradient from the reduced sums [sum(-ln P), slot sums] of one
 // evaluation (sums may be null for an empty dataset); grad may be null.
 void assemble(const pdf_graph* g, const StagedCall& sc, const double* sums, int64_t n, double* nll, double* grad);
+// The same for a binned dataset: sums = [metric, slot sums, sum of dmetric/dlnP]
+// over the tree interpreter's slots.
+void assemble_binned(const pdf_graph* g, const StagedCall& sc, const double* sums, double* value, double* grad);
 
 }  // namespace hf

@@ -62,7 +62,12 @@ extern "C" int fit(const pdf_graph* g, const dataset* d, const hf_fit_opts* opts
     hipStream_t st = (hipStream_t)hip_stream;
     Minimiser m;
     MinOptions mo = min_options(opts, d->prec);
-    if (d->metric == HF_METRIC_CHI2) mo.up = 1.0;
+    if (d->metric == HF_METRIC_CHI2) {
+      mo.up = 1.0;
+      // chi^2 amplifies the rounding of ln P by (w - K P) K P / w per bin: in
+      // the float path its noise is ~1e-6 of the value, not ~1e-9
+      if (d->prec == HF_FP32_EVAL) mo.f_noise = 1e-5;
+    }
     m.start(min_params(g, d->prec), params_inout, mo);
     std::vector<double> x(np), gr(np), xp(np);
     int n_eval = 0;

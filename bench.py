@@ -340,25 +340,26 @@ def main():
         extra["fp32_fit_dtheta_over_sigma_vs_fp64"] = float(np.max(np.abs(r32["theta"] - r64["theta"]) / sig))
 
     # ---------------- binned fits: the same 10^7 events in 2000 bins
-    counts, edges = np.histogram(data["x"], bins=2000, range=(5.2, 5.3))
-    cen = {"x": 0.5 * (edges[1:] + edges[:-1])}
-    binned = {}
-    for metric in ("bnll", "chi2"):
-        for prec in ("fp32", "fp64"):
-            bd = P.Dataset.binned(g, cen, counts.astype(np.float64), edges[1] - edges[0], metric, prec, stream)
-            for _ in range(10):
-                P.nll_grad(g, bd, truth, stream)
-            k = 500
-            t1 = time.perf_counter()
-            for th in theta_sequence(truth, k, rng):
-                P.nll_grad(g, bd, th, stream)
-            e_us = (time.perf_counter() - t1) / k * 1e6
-            t1 = time.perf_counter()
-            rb = P.fit(g, bd, stream=stream)
-            binned["%s_%s" % (metric, prec)] = {"us_per_eval": e_us, "fit_ms": (time.perf_counter() - t1) * 1e3,
-                                                 "fit_evals": rb["n_eval"], "status": rb["status"]}
-            bd.free()
-    extra["binned_2000_bins"] = binned
+    if not args.no_fits:
+        counts, edges = np.histogram(data["x"], bins=2000, range=(5.2, 5.3))
+        cen = {"x": 0.5 * (edges[1:] + edges[:-1])}
+        binned = {}
+        for metric in ("bnll", "chi2"):
+            for prec in ("fp32", "fp64"):
+                bd = P.Dataset.binned(g, cen, counts.astype(np.float64), edges[1] - edges[0], metric, prec, stream)
+                for _ in range(10):
+                    P.nll_grad(g, bd, truth, stream)
+                k = 500
+                t1 = time.perf_counter()
+                for th in theta_sequence(truth, k, rng):
+                    P.nll_grad(g, bd, th, stream)
+                e_us = (time.perf_counter() - t1) / k * 1e6
+                t1 = time.perf_counter()
+                rb = P.fit(g, bd, stream=stream)
+                binned["%s_%s" % (metric, prec)] = {"us_per_eval": e_us, "fit_ms": (time.perf_counter() - t1) * 1e3,
+                                                     "fit_evals": rb["n_eval"], "status": rb["status"]}
+                bd.free()
+        extra["binned_2000_bins"] = binned
 
     # ---------------- serving: stream of toy fits (exponential model)
     if not args.no_serving:

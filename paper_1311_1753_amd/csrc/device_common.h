@@ -136,35 +136,38 @@ __device__ __forceinline__ Cx<T> res_amp_j(const CS& cs, int rb, const Chan<T>& 
   return {f * d, f * mg};
 }
 
-// The resonance's pair and spin are wave-uniform: branch on them (only one
-// variant runs) instead of selecting the pair quantities field by field.
-template <typename T>
-__device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, int ch, int J, const Chan<T>& c12,
-                                         const Chan<T>& c13, const Chan<T>& c23) {
-  if (ch == 0) {
-    if (J == 0) return res_amp_j<T, 0>(cs, rb, c12);
-    if (J == 1) return res_amp_j<T, 1>(cs, rb, c12);
-    return res_amp_j<T, 2>(cs, rb, c12);
+// Amplitudes of the resonances [k0, k1) of one (pair, spin) group, all with
+// the pair quantities `c` (and, for TD, `cb` at the swapped point), into
+// a[2k], a[2k + 1] (re, im) and ab.  The bounds are wave-uniform, so the
+// writes are indexed register moves.
+template <typename T, int J, bool TD>
+__device__ __forceinline__ void res_group(const CS& cs, int rbase, int k0, int k1, const Chan<T>& c,
+                                          const Chan<T>& cb, T* a, T* ab) {
+  for (int k = k0; k < k1; ++k) {
+    const int rb = rbase + k * kResStride;
+    const Cx<T> v = res_amp_j<T, J>(cs, rb, c);
+    a[2 * k] = v.re;
+    a[2 * k + 1] = v.im;
+    if (TD) {
+      const Cx<T> w = res_amp_j<T, J>(cs, rb, cb);
+      ab[2 * k] = w.re;
+      ab[2 * k + 1] = w.im;
+    }
   }
-  if (ch == 1) {
-    if (J == 0) return res_amp_j<T, 0>(cs, rb, c13);
-    if (J == 1) return res_amp_j<T, 1>(cs, rb, c13);
-    return res_amp_j<T, 2>(cs, rb, c13);
-  }
-  if (J == 0) return res_amp_j<T, 0>(cs, rb, c23);
-  if (J == 1) return res_amp_j<T, 1>(cs, rb, c23);
-  return res_amp_j<T, 2>(cs, rb, c23);
 }
 
 // Amplitudes A_k(s12, s13) (and, for TDDP, Abar_k = A_k(s13, s12)) of all
-// resonances at one point; s12/s13/s23 in double.  Pair quantities are
-// evaluated once per pair (and, for the conjugate amplitudes, once per
-// swapped pair); when m2 == m3 (SYM) the swapped 12 pair equals the 13 pair
-// and vice versa.
+// resonances of node `nd` at one point into a (ab) as (re, im) pairs;
+// s12/s13/s23 in double.  Pair quantities are evaluated once per pair (and,
+// for the conjugate amplitudes, once per swapped pair); when m2 == m3 (SYM)
+// the swapped 12 pair equals the 13 pair and vice versa.  The resonances are
+// stored grouped by (pair, spin), so each group is one loop with the pair
+// and spin fixed at compile time.
 template <typename T, bool TD>
-__device__ __forceinline__ void dalitz_amps(const CS& cs, int c0, int R, double s12, double s13, double s23,
-                                            Cx<T>* A, Cx<T>* Ab) {
-  const int chb = c0 + dz_ch_base(R, TD), rbase = c0 + dz_res_base(R, TD);
+__device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, double s12, double s13, double s23, T* a,
+                                            T* ab) {
+  const int R = nd.aux;
+  const int chb = nd.c0 + dz_ch_base(R, TD), rbase = nd.c0 + dz_res_base(R, TD);
   // pair (A, B; C): 12 = (1, 2; 3), 13 = (1, 3; 2), 23 = (2, 3; 1)
   const Chan<T> c12 = chan_eval<T>(cs, chb, s12, s13, s23);
   const Chan<T> c13 = chan_eval<T>(cs, chb + kChStride, s13, s12, s23);
@@ -181,16 +184,16 @@ __device__ __forceinline__ void dalitz_amps(const CS& cs, int c0, int R, double 
     }
     b23 = chan_swap_ac_bc<T>(cs, chb + 2 * kChStride, c23, s12, s13);
   }
-#pragma unroll
-  for (int k = 0; k < kMaxRes; ++k) {
-    if (k < R) {
-      const int rb = rbase + k * kResStride;
-      const int ch = (int)cs.d[rb + kResCh];
-      const int J = (int)cs.d[rb + kResJ];
-      A[k] = res_amp<T>(cs, rb, ch, J, c12, c13, c23);
-      if (TD) Ab[k] = res_amp<T>(cs, rb, ch, J, b12, b13, b23);
-    }
-  }
+  const int16_t* e = nd.res_end;
+  res_group<T, 0, TD>(cs, rbase, 0, e[0], c12, b12, a, ab);
+  res_group<T, 1, TD>(cs, rbase, e[0], e[1], c12, b12, a, ab);
+  res_group<T, 2, TD>(cs, rbase, e[1], e[2], c12, b12, a, ab);
+  res_group<T, 0, TD>(cs, rbase, e[2], e[3], c13, b13, a, ab);
+  res_group<T, 1, TD>(cs, rbase, e[3], e[4], c13, b13, a, ab);
+  res_group<T, 2, TD>(cs, rbase, e[4], e[5], c13, b13, a, ab);
+  res_group<T, 0, TD>(cs, rbase, e[5], e[6], c23, b23, a, ab);
+  res_group<T, 1, TD>(cs, rbase, e[6], e[7], c23, b23, a, ab);
+  res_group<T, 2, TD>(cs, rbase, e[7], e[8], c23, b23, a, ab);
 }
 
 // Gaussian-resolution convolution of e^{-G t}, written without branches:

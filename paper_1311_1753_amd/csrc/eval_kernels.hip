@@ -79,15 +79,21 @@ __device__ __forceinline__ T leaf_poly(const CS& cs, int c0, int deg, bool hoist
   return lv;
 }
 
-// DALITZ: ln |1 + sum c_k A_k|^2 ; dl = d/d(Re c_k), d/d(Im c_k)
-template <typename T>
-__device__ __forceinline__ T leaf_dalitz(const CS& cs, int c0, int R, bool hoisted, double x12, double x13,
-                                         T* dl) {
+// DALITZ: ln |1 + sum c_k A_k|^2 ; slot derivatives d/d(Re c_k), d/d(Im c_k)
+// go to emit(slot, value) (stored by the tree interpreter, accumulated
+// directly by the single-leaf kernels).
+template <typename T, class Emit>
+__device__ __forceinline__ T leaf_dalitz(const CS& cs, const KNode& nd, bool hoisted, double x12, double x13,
+                                         const Emit& emit) {
+  const int c0 = nd.c0, R = nd.aux;
   const double s12 = x12 + cs.d[c0 + kDzRef12];
   const double s13 = x13 + cs.d[c0 + kDzRef13];
   const double s23 = cs.d[c0 + kDzSsum] - s12 - s13;
+  T a[2 * kMaxRes];
+  dalitz_amps<T, false>(cs, nd, s12, s13, s23, a, nullptr);
   Cx<T> A[kMaxRes];
-  dalitz_amps<T, false>(cs, c0, R, s12, s13, s23, A, nullptr);
+#pragma unroll
+  for (int k = 0; k < kMaxRes; ++k) A[k] = {a[2 * k], a[2 * k + 1]};
   const int cb = c0 + dz_coef_base(R, false);
   Cx<T> S = {T(1), T(0)};
 #pragma unroll
@@ -107,26 +113,35 @@ __device__ __forceinline__ T leaf_dalitz(const CS& cs, int c0, int R, bool hoist
       // conj(S) A_k
       const T re = S.re * A[k].re + S.im * A[k].im;
       const T im = S.re * A[k].im - S.im * A[k].re;
-      dl[2 * k] = re * inv;
-      dl[2 * k + 1] = -im * inv;
+      T d_re = re * inv, d_im = -im * inv;
       if (!hoisted) {
-        dl[2 * k] -= cs.get<T>(c0 + kDzDln + 2 * k);
-        dl[2 * k + 1] -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
+        d_re -= cs.get<T>(c0 + kDzDln + 2 * k);
+        d_im -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
       }
+      emit(2 * k, d_re);
+      emit(2 * k + 1, d_im);
     }
   if (!hoisted) lv = (lv - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
   return lv;
 }
 
-// TDDP: ln [a_c C + a_0 E0 + a_s S]; dl = coefficient derivatives, then tau, y
-template <typename T>
-__device__ __forceinline__ T leaf_tddp(const CS& cs, int c0, int R, bool hoisted, double x12, double x13,
-                                       double xt, double xs, T* dl) {
+// TDDP: ln [a_c C + a_0 E0 + a_s S]; slot derivatives (coefficients, then
+// tau, y) go to emit(slot, value)
+template <typename T, class Emit>
+__device__ __forceinline__ T leaf_tddp(const CS& cs, const KNode& nd, bool hoisted, double x12, double x13,
+                                       double xt, double xs, const Emit& emit) {
+  const int c0 = nd.c0, R = nd.aux;
   const double s12 = x12 + cs.d[c0 + kDzRef12];
   const double s13 = x13 + cs.d[c0 + kDzRef13];
   const double s23 = cs.d[c0 + kDzSsum] - s12 - s13;
+  T a[2 * kMaxRes], ab[2 * kMaxRes];
+  dalitz_amps<T, true>(cs, nd, s12, s13, s23, a, ab);
   Cx<T> A[kMaxRes], Ab[kMaxRes];
-  dalitz_amps<T, true>(cs, c0, R, s12, s13, s23, A, Ab);
+#pragma unroll
+  for (int k = 0; k < kMaxRes; ++k) {
+    A[k] = {a[2 * k], a[2 * k + 1]};
+    Ab[k] = {ab[2 * k], ab[2 * k + 1]};
+  }
   const int cb = c0 + dz_coef_base(R, true);
   Cx<T> S = {T(1), T(0)}, Sb = {T(1), T(0)};
 #pragma unroll
@@ -178,22 +193,24 @@ __device__ __forceinline__ T leaf_tddp(const CS& cs, int c0, int R, bool hoisted
       const T x2_im = S.re * Ab[k].im - S.im * Ab[k].re;   // Im(conj(S) Ab_k)
       const T dR_re = cc * pA_re + cb_ * pB_re - (x1_re + x2_re) * St;
       const T dR_im = -cc * pA_im - cb_ * pB_im - (x1_im - x2_im) * St;
-      dl[2 * k] = dR_re * iR;
-      dl[2 * k + 1] = dR_im * iR;
+      T d_re = dR_re * iR, d_im = dR_im * iR;
       if (!hoisted) {
-        dl[2 * k] -= cs.get<T>(c0 + kDzDln + 2 * k);
-        dl[2 * k + 1] -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
+        d_re -= cs.get<T>(c0 + kDzDln + 2 * k);
+        d_im -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
       }
+      emit(2 * k, d_re);
+      emit(2 * k + 1, d_im);
     }
   const T dtau = T(0.5) * nA * tA + T(0.5) * nB * tB + as * tS;
   const T dy = T(0.5) * (nA + nB) * yAB + as * yS;
-  dl[2 * R] = dtau * iR;
-  dl[2 * R + 1] = dy * iR;
+  T d_tau = dtau * iR, d_y = dy * iR;
   if (!hoisted) {
-    dl[2 * R] -= cs.get<T>(c0 + kDzDln + 2 * R);
-    dl[2 * R + 1] -= cs.get<T>(c0 + kDzDln + 2 * R + 1);
+    d_tau -= cs.get<T>(c0 + kDzDln + 2 * R);
+    d_y -= cs.get<T>(c0 + kDzDln + 2 * R + 1);
     lv = (lv - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
   }
+  emit(2 * R, d_tau);
+  emit(2 * R + 1, d_y);
   return lv;
 }
 
@@ -544,20 +561,16 @@ template <typename T, int OP, bool GRAD>
 struct AmpLeafEv {  // single DALITZ / TDDP leaf
   static constexpr int NS = OP == OP_DALITZ ? 2 * kMaxRes : 2 * kMaxRes + 2;
   CS cs;
-  int c0, R, n_slots;
-  bool hoisted;
   template <class Acc>
-  __device__ __forceinline__ void operator()(const KProgram&, const double* xe, int64_t, const Acc& acc) const {
-    T dl[NS];
+  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, int64_t, const Acc& acc) const {
+    // the single leaf is the root: its normalisation is applied on the host
+    const auto emit = [&](int j, T v) {
+      if (GRAD) acc.add(1 + j, (double)v);
+    };
     T lv;
-    if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, c0, R, hoisted, xe[0], xe[1], dl);
-    else lv = leaf_tddp<T>(cs, c0, R, hoisted, xe[0], xe[1], xe[2], xe[3], dl);
+    if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, P.node[0], true, xe[0], xe[1], emit);
+    else lv = leaf_tddp<T>(cs, P.node[0], true, xe[0], xe[1], xe[2], xe[3], emit);
     acc.add(0, -(double)lv);
-    if (GRAD) {
-#pragma unroll
-      for (int j = 0; j < NS; ++j)
-        if (j < n_slots) acc.add(1 + j, (double)dl[j]);
-    }
   }
 };
 
@@ -594,17 +607,10 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         for (int j = 0; j < 8; ++j)
           if (j < nd.aux) dl[s0 + j] = dp[j];
       } else if (HEAVY && op == OP_DALITZ) {
-        T dd[2 * kMaxRes];
-        v = leaf_dalitz<T>(cs, c0, nd.aux, h, xe[nd.col[0]], xe[nd.col[1]], dd);
-#pragma unroll
-        for (int j = 0; j < 2 * kMaxRes; ++j)
-          if (j < 2 * nd.aux) dl[s0 + j] = dd[j];
+        v = leaf_dalitz<T>(cs, nd, h, xe[nd.col[0]], xe[nd.col[1]], [&](int j, T d) { dl[s0 + j] = d; });
       } else if (HEAVY && op == OP_TDDP) {
-        T dd[2 * kMaxRes + 2];
-        v = leaf_tddp<T>(cs, c0, nd.aux, h, xe[nd.col[0]], xe[nd.col[1]], xe[nd.col[2]], xe[nd.col[3]], dd);
-#pragma unroll
-        for (int j = 0; j < 2 * kMaxRes + 2; ++j)
-          if (j < 2 * nd.aux + 2) dl[s0 + j] = dd[j];
+        v = leaf_tddp<T>(cs, nd, h, xe[nd.col[0]], xe[nd.col[1]], xe[nd.col[2]], xe[nd.col[3]],
+                         [&](int j, T d) { dl[s0 + j] = d; });
       } else if (op == OP_PROD) {
         v = T(0);
         for (int j = 0; j < nd.n_child; ++j) {
@@ -752,22 +758,19 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
   constexpr int NCOL = OP == OP_DALITZ ? 2 : 4;
   constexpr int NC = 1 + Ev::NS;
   const KNode& nd = P.node[0];
-  Ev ev;
-  ev.cs = cs;
-  ev.c0 = nd.c0;
-  ev.R = nd.aux;
-  ev.n_slots = GRAD ? P.n_slots : 0;
-  ev.hoisted = nd.hoisted != 0;
+  const Ev ev{cs};
+  // slot columns: 2R coefficient derivatives (+ tau, y)
+  const int n_slots = GRAD ? P.n_slots : 0;
   const Sx* cp[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[nd.col[c]];
   __shared__ double accs[NC][kBlock];
   const LdsAcc<NC> acc{accs};
-  acc.zero(1 + ev.n_slots);
+  acc.zero(1 + n_slots);
   int64_t c0, c1;
   row_chunks(n, n_rows, r, c0, c1);
   heavy_row<T, NCOL>(ev, P, cp, NCOL, n, c0, c1, acc);
-  row_store_acc<NC>(acc, 1 + ev.n_slots, out, n_rows);
+  row_store_acc<NC>(acc, 1 + n_slots, out, n_rows);
 }
 
 template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>

@@ -458,6 +458,30 @@ int node_consts(const NodeInfo& n) {
   }
 }
 
+// (pair, spin) group 3 * pair + J of resonance j of a Dalitz node (the
+// node's constant block holds per resonance: pair 12 / 13 / 23, m0, Gamma0, J).
+int res_group_of(const NodeInfo& n, int j) {
+  const double ch = n.consts[7 + 4 * j];
+  return 3 * (ch == 12 ? 0 : (ch == 13 ? 1 : 2)) + (int)n.consts[10 + 4 * j];
+}
+
+// Stable reordering of a Dalitz node's resonances into (pair, spin) groups,
+// each resonance's two coefficient parameters moving with it: the kernels
+// evaluate every group in a loop of its own with the pair and spin fixed.
+// The density does not depend on the order of the terms of the coherent sum.
+void group_resonances(NodeInfo& n, int R) {
+  std::vector<int> idx(R);
+  for (int j = 0; j < R; ++j) idx[j] = j;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return res_group_of(n, a) < res_group_of(n, b); });
+  const std::vector<double> c = n.consts;
+  const std::vector<int> p = n.par;
+  for (int j = 0; j < R; ++j) {
+    for (int i = 0; i < 4; ++i) n.consts[7 + 4 * j + i] = c[7 + 4 * idx[j] + i];
+    n.par[2 * j] = p[2 * idx[j]];
+    n.par[2 * j + 1] = p[2 * idx[j] + 1];
+  }
+}
+
 }  // namespace
 
 }  // namespace hf
@@ -557,6 +581,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
               rc = need(m0 > mA + mB && g0 > 0, "Dalitz: resonance mass above threshold and width > 0");
             }
           }
+          if (!rc) group_resonances(ni, R);
           break;
         }
         default:
@@ -642,7 +667,13 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       kn.hoisted = (int16_t)hoist[k];
       kn.aux = 0;
       if (n.op == OP_POLY) kn.aux = (int16_t)n.par.size();
-      if (n.op == OP_DALITZ || n.op == OP_TDDP) kn.aux = (int16_t)n.consts[6];
+      if (n.op == OP_DALITZ || n.op == OP_TDDP) {
+        const int R = (int)n.consts[6];
+        kn.aux = (int16_t)R;
+        int cnt[kNumGroups] = {0};
+        for (int j = 0; j < R; ++j) ++cnt[res_group_of(n, j)];
+        for (int gi = 0, e = 0; gi < kNumGroups; ++gi) kn.res_end[gi] = (int16_t)(e += cnt[gi]);
+      }
       // gradient slot -> parameter
       if (n.op == OP_ADD) for (int j = 0; j < kn.n_slot; ++j) g->slot_par.push_back(n.par[j]);
       else for (int j = 0; j < kn.n_slot; ++j) g->slot_par.push_back(n.par[j]);
@@ -705,8 +736,6 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
         setc(rb + kResKw, m02 * r.g0 / std::pow(q0, 2 * r.J + 1));
         setc(rb + kResSqB, std::sqrt(bnum));
         setc(rb + kResR2, dz.r * dz.r);
-        setc(rb + kResCh, c);
-        setc(rb + kResJ, r.J);
       }
     }
     // the generic slot layout (the tree interpreter's, used by binned datasets)

@@ -49,7 +49,7 @@ __device__ __forceinline__ bool in_pair(double M, double m1, double s1x, double 
 struct GridArgs {
   KProgram prog;
   GridSpec gs;
-  int c0, R, tddp, n_chunks;
+  int node, c0, R, tddp, n_chunks;
   double2* part;     // [row * n_chunks + chunk][n_mat * na * na]
 };
 
@@ -72,17 +72,17 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows(const GridArgs a) {
       in = in_pair(a.gs.M, a.gs.m1, s12, s13, a.gs.m2, a.gs.m3) &&
            in_pair(a.gs.M, a.gs.m1, s13, s12, a.gs.m3, a.gs.m2);
     }
-    Cx<double> A[kMaxRes], Ab[kMaxRes];
+    double A[2 * kMaxRes], Ab[2 * kMaxRes];
     if (in) {
       const double s23 = cs.d[a.c0 + kDzSsum] - s12 - s13;
-      if (a.tddp) dalitz_amps<double, true>(cs, a.c0, a.R, s12, s13, s23, A, Ab);
-      else dalitz_amps<double, false>(cs, a.c0, a.R, s12, s13, s23, A, nullptr);
+      if (a.tddp) dalitz_amps<double, true>(cs, a.prog.node[a.node], s12, s13, s23, A, Ab);
+      else dalitz_amps<double, false>(cs, a.prog.node[a.node], s12, s13, s23, A, nullptr);
     }
     sa[t][0] = make_double2(in ? 1.0 : 0.0, 0.0);
     sb[t][0] = sa[t][0];
     for (int k = 0; k < a.R; ++k) {
-      sa[t][k + 1] = in ? make_double2(A[k].re, A[k].im) : make_double2(0.0, 0.0);
-      sb[t][k + 1] = (in && a.tddp) ? make_double2(Ab[k].re, Ab[k].im) : make_double2(0.0, 0.0);
+      sa[t][k + 1] = in ? make_double2(A[2 * k], A[2 * k + 1]) : make_double2(0.0, 0.0);
+      sb[t][k + 1] = (in && a.tddp) ? make_double2(Ab[2 * k], Ab[2 * k + 1]) : make_double2(0.0, 0.0);
     }
   }
   __syncthreads();
@@ -141,6 +141,7 @@ hipError_t dalitz_grid_matrices(const GridSpec& gs, const KProgram& prog, int no
   GridArgs a;
   a.prog = prog;
   a.gs = gs;
+  a.node = node;
   a.c0 = nd.c0;
   a.R = R;
   a.tddp = tddp ? 1 : 0;

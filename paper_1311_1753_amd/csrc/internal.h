@@ -22,6 +22,7 @@ constexpr int kMaxSlots = 32;
 constexpr int kMaxConst = 176;
 constexpr int kMaxRes = 8;
 constexpr int kMaxPar = 64;
+constexpr int kNumGroups = 9;        // (pair, spin) groups of Dalitz resonances
 
 enum Op : int16_t {
   OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7
@@ -37,6 +38,10 @@ struct KNode {
   int16_t col[4];    // observable columns read
   int16_t hoisted;   // 1: normalisation applied on the host (every ancestor is PROD)
   int16_t aux;       // POLY: degree; DALITZ/TDDP: number of resonances
+  // DALITZ/TDDP: the resonances are stored grouped by (pair, spin), group
+  // g = 3 * pair + J (pairs 12, 13, 23 = 0, 1, 2); group g holds resonances
+  // [res_end[g - 1], res_end[g]) with res_end[-1] = 0 and res_end[8] = R.
+  int16_t res_end[kNumGroups];
 };
 
 struct KProgram {
@@ -60,8 +65,9 @@ constexpr int kDzRef12 = 0, kDzRef13 = 1, kDzSsum = 2, kDzLnHi = 3, kDzLnLo = 4,
 // dlnN entries: constants that depend only on the pair's masses
 constexpr int kChThrP = 0, kChThrM = 1, kChZc1 = 2, kChZtaC = 3, kChZtaD = 4, kChZtbC = 5, kChZtbD = 6,
               kChStride = 7, kNumCh = 3;
-// per resonance block (stride kResStride) after the channel blocks
-constexpr int kResM02 = 0, kResKw = 1, kResSqB = 2, kResR2 = 3, kResCh = 4, kResJ = 5, kResStride = 6;
+// per resonance block (stride kResStride) after the channel blocks, in the
+// group order of KNode::res_end
+constexpr int kResM02 = 0, kResKw = 1, kResSqB = 2, kResR2 = 3, kResStride = 4;
 // TDDP time constants after the coefficients
 constexpr int kTdGm = 0, kTdGp = 1, kTdG = 2, kTdDGmTau = 3, kTdDGpTau = 4, kTdDGTau = 5,
               kTdDGmY = 6, kTdDGpY = 7, kTdCount = 8;

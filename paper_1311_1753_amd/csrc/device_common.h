@@ -114,25 +114,31 @@ __device__ __forceinline__ Chan<T> chan_swap_ac_bc(const CS& cs, int cb, const C
 }
 
 // Resonance amplitude B_J(q) Z_J BW(s_AB) with the mass-dependent width
-// m0 Gamma(s) = Kw q^{2J+1} B_J^2 / sqrt(s), BW = 1/(m0^2 - s - i m0 Gamma);
-// m0^2 - s is formed in double.  J is static here.
+// m0 Gamma(s) = Kw q^{2J+1} B_J^2 / sqrt(s) and BW = 1/(m0^2 - s - i m0 Gamma).
+// With the Blatt-Weisskopf factor B_J = B0 / sqrt(P_J(r^2 q^2)) (P_0 = 1,
+// P_1 = 1 + z, P_2 = z^2 + 3z + 9, B0 = sqrt(P_J(r^2 q0^2))), everything but
+// m0^2, Kw B0^2 and B0 depends only on the pair and the spin, so it is formed
+// once per (pair, spin) group:
+//   g  = q^{2J+1} / (P_J sqrt(s))     m0 Gamma(s) = (Kw B0^2) g
+//   zf = Z_J / sqrt(P_J)              B_J Z_J = B0 zf
+template <typename T> struct GroupQ { T g, zf; };
+
 template <typename T, int J>
-__device__ __forceinline__ Cx<T> res_amp_j(const CS& cs, int rb, const Chan<T>& c) {
-  const T d = (T)(cs.d[rb + kResM02] - c.sABd);
-  T B = T(1), qp = c.q, Z = T(1);
-  if (J == 1) {
-    B = cs.get<T>(rb + kResSqB) * Mth<T>::rsqrt(T(1) + cs.get<T>(rb + kResR2) * c.q2);
-    qp = c.q * c.q2;
-    Z = c.z1;
-  } else if (J == 2) {
-    const T z = cs.get<T>(rb + kResR2) * c.q2;
-    B = cs.get<T>(rb + kResSqB) * Mth<T>::rsqrt(z * z + T(3) * z + T(9));
-    qp = c.q * c.q2 * c.q2;
-    Z = c.z2;
-  }
-  const T mg = cs.get<T>(rb + kResKw) * qp * (B * B) * c.rs;  // m0 Gamma(s)
-  const T den = Mth<T>::rcp(d * d + mg * mg);
-  const T f = B * Z * den;
+__device__ __forceinline__ GroupQ<T> group_q(T r2, const Chan<T>& c) {
+  if (J == 0) return {c.q * c.rs, T(1)};
+  const T z = r2 * c.q2;
+  const T rp = Mth<T>::rsqrt(J == 1 ? T(1) + z : Mth<T>::fma(z, z + T(3), T(9)));
+  const T qp = J == 1 ? c.q * c.q2 : c.q * c.q2 * c.q2;
+  return {qp * (rp * rp) * c.rs, (J == 1 ? c.z1 : c.z2) * rp};
+}
+
+// One resonance: m0^2 - s is formed in double.
+template <typename T>
+__device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, const GroupQ<T>& gq, double sABd) {
+  const T d = (T)(cs.d[rb + kResM02] - sABd);
+  const T mg = cs.get<T>(rb + kResKwB) * gq.g;  // m0 Gamma(s)
+  const T den = Mth<T>::rcp(Mth<T>::fma(d, d, mg * mg));
+  const T f = cs.get<T>(rb + kResSqB) * gq.zf * den;
   return {f * d, f * mg};
 }
 
@@ -141,15 +147,19 @@ __device__ __forceinline__ Cx<T> res_amp_j(const CS& cs, int rb, const Chan<T>& 
 // a[2k], a[2k + 1] (re, im) and ab.  The bounds are wave-uniform, so the
 // writes are indexed register moves.
 template <typename T, int J, bool TD>
-__device__ __forceinline__ void res_group(const CS& cs, int rbase, int k0, int k1, const Chan<T>& c,
+__device__ __forceinline__ void res_group(const CS& cs, int rbase, T r2, int k0, int k1, const Chan<T>& c,
                                           const Chan<T>& cb, T* a, T* ab) {
+  if (k0 >= k1) return;
+  const GroupQ<T> gq = group_q<T, J>(r2, c);
+  GroupQ<T> gb{};
+  if (TD) gb = group_q<T, J>(r2, cb);
   for (int k = k0; k < k1; ++k) {
     const int rb = rbase + k * kResStride;
-    const Cx<T> v = res_amp_j<T, J>(cs, rb, c);
+    const Cx<T> v = res_amp<T>(cs, rb, gq, c.sABd);
     a[2 * k] = v.re;
     a[2 * k + 1] = v.im;
     if (TD) {
-      const Cx<T> w = res_amp_j<T, J>(cs, rb, cb);
+      const Cx<T> w = res_amp<T>(cs, rb, gb, cb.sABd);
       ab[2 * k] = w.re;
       ab[2 * k + 1] = w.im;
     }
@@ -185,15 +195,21 @@ __device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, doubl
     b23 = chan_swap_ac_bc<T>(cs, chb + 2 * kChStride, c23, s12, s13);
   }
   const int16_t* e = nd.res_end;
-  res_group<T, 0, TD>(cs, rbase, 0, e[0], c12, b12, a, ab);
-  res_group<T, 1, TD>(cs, rbase, e[0], e[1], c12, b12, a, ab);
-  res_group<T, 2, TD>(cs, rbase, e[1], e[2], c12, b12, a, ab);
-  res_group<T, 0, TD>(cs, rbase, e[2], e[3], c13, b13, a, ab);
-  res_group<T, 1, TD>(cs, rbase, e[3], e[4], c13, b13, a, ab);
-  res_group<T, 2, TD>(cs, rbase, e[4], e[5], c13, b13, a, ab);
-  res_group<T, 0, TD>(cs, rbase, e[5], e[6], c23, b23, a, ab);
-  res_group<T, 1, TD>(cs, rbase, e[6], e[7], c23, b23, a, ab);
-  res_group<T, 2, TD>(cs, rbase, e[7], e[8], c23, b23, a, ab);
+  const T r2 = cs.get<T>(nd.c0 + kDzR2);
+  res_group<T, 0, TD>(cs, rbase, r2, 0, e[0], c12, b12, a, ab);
+  res_group<T, 1, TD>(cs, rbase, r2, e[0], e[1], c12, b12, a, ab);
+  res_group<T, 2, TD>(cs, rbase, r2, e[1], e[2], c12, b12, a, ab);
+  res_group<T, 0, TD>(cs, rbase, r2, e[2], e[3], c13, b13, a, ab);
+  res_group<T, 1, TD>(cs, rbase, r2, e[3], e[4], c13, b13, a, ab);
+  res_group<T, 2, TD>(cs, rbase, r2, e[4], e[5], c13, b13, a, ab);
+  res_group<T, 0, TD>(cs, rbase, r2, e[5], e[6], c23, b23, a, ab);
+  res_group<T, 1, TD>(cs, rbase, r2, e[6], e[7], c23, b23, a, ab);
+  res_group<T, 2, TD>(cs, rbase, r2, e[7], e[8], c23, b23, a, ab);
+  // absent resonances: zero amplitudes (their coefficients are zero too)
+  for (int k = R; k < kMaxRes; ++k) {
+    a[2 * k] = a[2 * k + 1] = T(0);
+    if (TD) ab[2 * k] = ab[2 * k + 1] = T(0);
+  }
 }
 
 // Gaussian-resolution convolution of e^{-G t}, written without branches:

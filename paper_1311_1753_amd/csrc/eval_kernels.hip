@@ -81,7 +81,10 @@ __device__ __forceinline__ T leaf_poly(const CS& cs, int c0, int deg, bool hoist
 
 // DALITZ: ln |1 + sum c_k A_k|^2 ; slot derivatives d/d(Re c_k), d/d(Im c_k)
 // go to emit(slot, value) (stored by the tree interpreter, accumulated
-// directly by the single-leaf kernels).
+// directly by the single-leaf kernels).  The sums run over all kMaxRes
+// resonance places: absent ones have zero amplitude and coefficient, and
+// emit zero derivatives for slots 2R .. 2 kMaxRes - 1, which the caller
+// drops or adds harmlessly.
 template <typename T, class Emit>
 __device__ __forceinline__ T leaf_dalitz(const CS& cs, const KNode& nd, bool hoisted, double x12, double x13,
                                          const Emit& emit) {
@@ -97,24 +100,22 @@ __device__ __forceinline__ T leaf_dalitz(const CS& cs, const KNode& nd, bool hoi
   const int cb = c0 + dz_coef_base(R, false);
   Cx<T> S = {T(1), T(0)};
 #pragma unroll
-  for (int k = 0; k < kMaxRes; ++k)
-    if (k < R) {
-      const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
-      const Cx<T> t = cmul(c, A[k]);
-      S.re += t.re;
-      S.im += t.im;
-    }
+  for (int k = 0; k < kMaxRes; ++k) {
+    const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
+    const Cx<T> t = cmul(c, A[k]);
+    S.re += t.re;
+    S.im += t.im;
+  }
   const T a2 = S.re * S.re + S.im * S.im;
   const T inv = T(2) * Mth<T>::rcp(a2);
   T lv = a2 > T(0) ? Mth<T>::ln(a2) : T(-INFINITY);
 #pragma unroll
-  for (int k = 0; k < kMaxRes; ++k)
-    if (k < R) {
+  for (int k = 0; k < kMaxRes; ++k) {
       // conj(S) A_k
       const T re = S.re * A[k].re + S.im * A[k].im;
       const T im = S.re * A[k].im - S.im * A[k].re;
       T d_re = re * inv, d_im = -im * inv;
-      if (!hoisted) {
+      if (!hoisted && k < R) {
         d_re -= cs.get<T>(c0 + kDzDln + 2 * k);
         d_im -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
       }
@@ -126,7 +127,9 @@ __device__ __forceinline__ T leaf_dalitz(const CS& cs, const KNode& nd, bool hoi
 }
 
 // TDDP: ln [a_c C + a_0 E0 + a_s S]; slot derivatives (coefficients, then
-// tau, y) go to emit(slot, value)
+// tau, y) go to emit(slot, value), the coefficients' first over all kMaxRes
+// places as for DALITZ, then tau and y to slots 2R and 2R + 1 (after any
+// zero emitted there)
 template <typename T, class Emit>
 __device__ __forceinline__ T leaf_tddp(const CS& cs, const KNode& nd, bool hoisted, double x12, double x13,
                                        double xt, double xs, const Emit& emit) {
@@ -145,13 +148,12 @@ __device__ __forceinline__ T leaf_tddp(const CS& cs, const KNode& nd, bool hoist
   const int cb = c0 + dz_coef_base(R, true);
   Cx<T> S = {T(1), T(0)}, Sb = {T(1), T(0)};
 #pragma unroll
-  for (int k = 0; k < kMaxRes; ++k)
-    if (k < R) {
-      const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
-      const Cx<T> t = cmul(c, A[k]), tb = cmul(c, Ab[k]);
-      S.re += t.re; S.im += t.im;
-      Sb.re += tb.re; Sb.im += tb.im;
-    }
+  for (int k = 0; k < kMaxRes; ++k) {
+    const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
+    const Cx<T> t = cmul(c, A[k]), tb = cmul(c, Ab[k]);
+    S.re += t.re; S.im += t.im;
+    Sb.re += tb.re; Sb.im += tb.im;
+  }
   const T nA = S.re * S.re + S.im * S.im;
   const T nB = Sb.re * Sb.re + Sb.im * Sb.im;
   const T X = S.re * Sb.re + S.im * Sb.im;  // Re(conj(A) Abar)
@@ -180,8 +182,7 @@ __device__ __forceinline__ T leaf_tddp(const CS& cs, const KNode& nd, bool hoist
   const T iR = Mth<T>::rcp(Rv);
   T lv = Rv > T(0) ? Mth<T>::ln(Rv) : T(-INFINITY);
 #pragma unroll
-  for (int k = 0; k < kMaxRes; ++k)
-    if (k < R) {
+  for (int k = 0; k < kMaxRes; ++k) {
       // re part: dA = A_k, dAb = Ab_k ; im part: dA = i A_k, dAb = i Ab_k
       const T pA_re = S.re * A[k].re + S.im * A[k].im;     // Re(conj(S) A_k)
       const T pA_im = S.re * A[k].im - S.im * A[k].re;     // Im(conj(S) A_k)
@@ -194,7 +195,7 @@ __device__ __forceinline__ T leaf_tddp(const CS& cs, const KNode& nd, bool hoist
       const T dR_re = cc * pA_re + cb_ * pB_re - (x1_re + x2_re) * St;
       const T dR_im = -cc * pA_im - cb_ * pB_im - (x1_im - x2_im) * St;
       T d_re = dR_re * iR, d_im = dR_im * iR;
-      if (!hoisted) {
+      if (!hoisted && k < R) {
         d_re -= cs.get<T>(c0 + kDzDln + 2 * k);
         d_im -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
       }
@@ -607,10 +608,16 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         for (int j = 0; j < 8; ++j)
           if (j < nd.aux) dl[s0 + j] = dp[j];
       } else if (HEAVY && op == OP_DALITZ) {
-        v = leaf_dalitz<T>(cs, nd, h, xe[nd.col[0]], xe[nd.col[1]], [&](int j, T d) { dl[s0 + j] = d; });
+        const int ns = nd.n_slot;
+        v = leaf_dalitz<T>(cs, nd, h, xe[nd.col[0]], xe[nd.col[1]], [&](int j, T d) {
+          if (j < ns) dl[s0 + j] = d;
+        });
       } else if (HEAVY && op == OP_TDDP) {
+        const int ns = nd.n_slot;
         v = leaf_tddp<T>(cs, nd, h, xe[nd.col[0]], xe[nd.col[1]], xe[nd.col[2]], xe[nd.col[3]],
-                         [&](int j, T d) { dl[s0 + j] = d; });
+                         [&](int j, T d) {
+                           if (j < ns) dl[s0 + j] = d;
+                         });
       } else if (op == OP_PROD) {
         v = T(0);
         for (int j = 0; j < nd.n_child; ++j) {
@@ -759,14 +766,15 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
   constexpr int NC = 1 + Ev::NS;
   const KNode& nd = P.node[0];
   const Ev ev{cs};
-  // slot columns: 2R coefficient derivatives (+ tau, y)
+  // slot columns: 2R coefficient derivatives (+ tau, y); zero derivatives
+  // land in the columns up to 2 kMaxRes, so all are cleared
   const int n_slots = GRAD ? P.n_slots : 0;
   const Sx* cp[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[nd.col[c]];
   __shared__ double accs[NC][kBlock];
   const LdsAcc<NC> acc{accs};
-  acc.zero(1 + n_slots);
+  acc.zero(GRAD ? NC : 1);
   int64_t c0, c1;
   row_chunks(n, n_rows, r, c0, c1);
   heavy_row<T, NCOL>(ev, P, cp, NCOL, n, c0, c1, acc);

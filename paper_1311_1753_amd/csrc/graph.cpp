@@ -703,6 +703,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       auto setc = [&](int i, double v) { P.c64[i] = v; P.c32[i] = (float)v; };
       const double M2 = dz.M * dz.M;
       setc(c0 + kDzSsum, M2 + dz.m1 * dz.m1 + dz.m2 * dz.m2 + dz.m3 * dz.m3);
+      setc(c0 + kDzR2, dz.r * dz.r);
       // pair constants: 12 = (m1, m2; spectator m3), 13 = (m1, m3; m2), 23 = (m2, m3; m1)
       const int chb = c0 + dz_ch_base(R, dz.tddp);
       for (int c = 0; c < kNumCh; ++c) {
@@ -733,9 +734,8 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
         if (r.J == 1) bnum = 1.0 + z0;
         if (r.J == 2) bnum = z0 * z0 + 3.0 * z0 + 9.0;
         setc(rb + kResM02, m02);
-        setc(rb + kResKw, m02 * r.g0 / std::pow(q0, 2 * r.J + 1));
+        setc(rb + kResKwB, m02 * r.g0 / std::pow(q0, 2 * r.J + 1) * bnum);
         setc(rb + kResSqB, std::sqrt(bnum));
-        setc(rb + kResR2, dz.r * dz.r);
       }
     }
     // the generic slot layout (the tree interpreter's, used by binned datasets)

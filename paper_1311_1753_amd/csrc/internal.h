@@ -60,14 +60,16 @@ struct KProgram {
 //   DALITZ/TDDP: see the kDz* offsets below.
 // For the float path lnN is split into a float pair (hi + lo) so that the
 // rounding of the constant does not bias every event in the same direction.
-constexpr int kDzRef12 = 0, kDzRef13 = 1, kDzSsum = 2, kDzLnHi = 3, kDzLnLo = 4, kDzDln = 5;
+// kDzR2: squared barrier radius r^2 (all resonances)
+constexpr int kDzRef12 = 0, kDzRef13 = 1, kDzSsum = 2, kDzLnHi = 3, kDzLnLo = 4, kDzR2 = 5, kDzDln = 6;
 // channel blocks (pairs 12, 13, 23 in that order) after the 2R (+2 for TDDP)
 // dlnN entries: constants that depend only on the pair's masses
 constexpr int kChThrP = 0, kChThrM = 1, kChZc1 = 2, kChZtaC = 3, kChZtaD = 4, kChZtbC = 5, kChZtbD = 6,
               kChStride = 7, kNumCh = 3;
 // per resonance block (stride kResStride) after the channel blocks, in the
-// group order of KNode::res_end
-constexpr int kResM02 = 0, kResKw = 1, kResSqB = 2, kResR2 = 3, kResStride = 4;
+// group order of KNode::res_end: m0^2, Kw B0^2 (B0 = the barrier polynomial's
+// square root at q0, 1 for J = 0), B0
+constexpr int kResM02 = 0, kResKwB = 1, kResSqB = 2, kResStride = 3;
 // TDDP time constants after the coefficients
 constexpr int kTdGm = 0, kTdGp = 1, kTdG = 2, kTdDGmTau = 3, kTdDGpTau = 4, kTdDGTau = 5,
               kTdDGmY = 6, kTdDGpY = 7, kTdCount = 8;
@@ -75,9 +77,11 @@ constexpr int kTdGm = 0, kTdGp = 1, kTdG = 2, kTdDGmTau = 3, kTdDGpTau = 4, kTdD
 constexpr int dz_n_dln(int R, bool tddp) { return 2 * R + (tddp ? 2 : 0); }
 constexpr int dz_ch_base(int R, bool tddp) { return kDzDln + dz_n_dln(R, tddp); }
 constexpr int dz_res_base(int R, bool tddp) { return dz_ch_base(R, tddp) + kNumCh * kChStride; }
+// the coefficient block always has room for kMaxRes coefficients; those of
+// absent resonances stay zero, so the kernels sum over all kMaxRes
 constexpr int dz_coef_base(int R, bool tddp) { return dz_res_base(R, tddp) + R * kResStride; }
-constexpr int dz_time_base(int R) { return dz_coef_base(R, true) + 2 * R; }
-constexpr int dz_n_const(int R, bool tddp) { return dz_coef_base(R, tddp) + 2 * R + (tddp ? kTdCount : 0); }
+constexpr int dz_time_base(int R) { return dz_coef_base(R, true) + 2 * kMaxRes; }
+constexpr int dz_n_const(int R, bool tddp) { return dz_coef_base(R, tddp) + 2 * kMaxRes + (tddp ? kTdCount : 0); }
 
 // Arguments of one evaluation launch over one dataset.
 struct EvalArgs {

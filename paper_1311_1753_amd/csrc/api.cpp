@@ -258,7 +258,7 @@ static int upload(const pdf_graph* g, const double* const* host_cols, int64_t n,
     // thread, partial columns [metric, tree slots, sum of dmetric/dlnP]
     d->metric = metric;
     d->volume = volume;
-    d->n_rows = rows_for(metric ? (int)KIND_TREE : g->kind, n);
+    d->n_rows = rows_for(metric ? (int)KIND_TREE : g->kind, prec, n);
     const int part_cols = metric ? g->n_slots_tree + 2 : g->prog.n_slots + 1;
     const size_t col_bytes = align256((size_t)n * es);
     const size_t w_bytes = metric ? align256((size_t)n * sizeof(double)) : 0;
@@ -369,7 +369,7 @@ extern "C" int dataset_wrap_device(const pdf_graph* g, void* const* dev_cols, in
       d->col[c] = p;
       d->ref[c] = column_ref(g, c, prec);
     }
-    d->n_rows = rows_for(g->kind, n);
+    d->n_rows = rows_for(g->kind, prec, n);
     const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * (g->prog.n_slots + 1) * sizeof(double));
     void* blk = nullptr;
     hipError_t e = hipMalloc(&blk, part_bytes);

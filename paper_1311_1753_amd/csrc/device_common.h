@@ -2,6 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "internal.h"
 
 namespace hf {
@@ -68,7 +71,32 @@ template <typename T, int N> struct RegArr<T, N, true> {
   }
 };
 
+// Loop unrolled at compile time: f(std::integral_constant<int, 0>{}), ...,
+// f(std::integral_constant<int, N - 1>{}).  Used where the index selects one
+// of several register arrays, so that the selection is resolved before the
+// arrays are placed.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // ------------------------------------------------------------------ Dalitz pieces
+// Per-event amplitudes: (re, im) pairs of the kMaxRes resonance places,
+// written at wave-uniform runtime indices.  Each event's array is a separate
+// plain array, picked by a compile-time event number, so that each is kept in
+// registers on its own (a two-dimensional array indexed by a runtime
+// resonance number would be placed in scratch memory).
+template <typename T> using AmpArr = T[2 * kMaxRes];
+template <int e, class A>
+__device__ __forceinline__ A& pick(A& x0, A& x1) {
+  if constexpr (e == 0) return x0;
+  else return x1;
+}
+
 template <typename T> struct Cx { T re, im; };
 template <typename T> __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -142,73 +170,95 @@ __device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, const GroupQ<T>& 
   return {f * d, f * mg};
 }
 
-// Amplitudes of the resonances [k0, k1) of one (pair, spin) group, all with
-// the pair quantities `c` (and, for TD, `cb` at the swapped point), into
-// a[2k], a[2k + 1] (re, im) and ab.  The bounds are wave-uniform, so the
-// writes are indexed register moves.
-template <typename T, int J, bool TD>
-__device__ __forceinline__ void res_group(const CS& cs, int rbase, T r2, int k0, int k1, const Chan<T>& c,
-                                          const Chan<T>& cb, T* a, T* ab) {
+// Amplitudes of the resonances [k0, k1) of one (pair, spin) group, for E <= 2
+// events at once, all with the pair quantities c[e] (and, for TD, cb[e] at
+// the swapped point), into event e's array (a0, a1) at 2k, 2k + 1 (re, im)
+// and the conjugate amplitudes into b0, b1.  The bounds are wave-uniform, so
+// the writes are indexed register moves; each resonance's constants are read
+// once for the E events.
+template <typename T, int J, bool TD, int E>
+__device__ __forceinline__ void res_group(const CS& cs, int rbase, T r2, int k0, int k1, const Chan<T> (&c)[E],
+                                          const Chan<T> (&cb)[E], AmpArr<T>& a0, AmpArr<T>& a1,
+                                          AmpArr<T>& b0, AmpArr<T>& b1) {
   if (k0 >= k1) return;
-  const GroupQ<T> gq = group_q<T, J>(r2, c);
-  GroupQ<T> gb{};
-  if (TD) gb = group_q<T, J>(r2, cb);
+  GroupQ<T> gq[E], gb[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    gq[e] = group_q<T, J>(r2, c[e]);
+    if (TD) gb[e] = group_q<T, J>(r2, cb[e]);
+  }
   for (int k = k0; k < k1; ++k) {
     const int rb = rbase + k * kResStride;
-    const Cx<T> v = res_amp<T>(cs, rb, gq, c.sABd);
-    a[2 * k] = v.re;
-    a[2 * k + 1] = v.im;
-    if (TD) {
-      const Cx<T> w = res_amp<T>(cs, rb, gb, cb.sABd);
-      ab[2 * k] = w.re;
-      ab[2 * k + 1] = w.im;
-    }
+    static_for<E>([&](auto ei) {
+      constexpr int e = decltype(ei)::value;
+      const Cx<T> v = res_amp<T>(cs, rb, gq[e], c[e].sABd);
+      pick<e>(a0, a1)[2 * k] = v.re;
+      pick<e>(a0, a1)[2 * k + 1] = v.im;
+      if (TD) {
+        const Cx<T> w = res_amp<T>(cs, rb, gb[e], cb[e].sABd);
+        pick<e>(b0, b1)[2 * k] = w.re;
+        pick<e>(b0, b1)[2 * k + 1] = w.im;
+      }
+    });
   }
 }
 
 // Amplitudes A_k(s12, s13) (and, for TDDP, Abar_k = A_k(s13, s12)) of all
-// resonances of node `nd` at one point into a (ab) as (re, im) pairs;
-// s12/s13/s23 in double.  Pair quantities are evaluated once per pair (and,
-// for the conjugate amplitudes, once per swapped pair); when m2 == m3 (SYM)
-// the swapped 12 pair equals the 13 pair and vice versa.  The resonances are
-// stored grouped by (pair, spin), so each group is one loop with the pair
-// and spin fixed at compile time.
-template <typename T, bool TD>
-__device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, double s12, double s13, double s23, T* a,
-                                            T* ab) {
+// resonances of node `nd` at E <= 2 points into a0, a1 (b0, b1) as (re, im)
+// pairs; s12/s13/s23 in double (b0, b1 are not touched without TD).  Pair quantities are
+// evaluated once per pair (and, for the conjugate amplitudes, once per
+// swapped pair); when m2 == m3 (SYM) the swapped 12 pair equals the 13 pair
+// and vice versa.  The resonances are stored grouped by (pair, spin), so each
+// group is one loop with the pair and spin fixed at compile time.  Absent
+// resonance places (k >= R) get zero amplitudes.
+template <typename T, bool TD, int E>
+__device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, const double (&s12)[E],
+                                            const double (&s13)[E], const double (&s23)[E], AmpArr<T>& a0,
+                                            AmpArr<T>& a1, AmpArr<T>& b0, AmpArr<T>& b1) {
   const int R = nd.aux;
   const int chb = nd.c0 + dz_ch_base(R, TD), rbase = nd.c0 + dz_res_base(R, TD);
   // pair (A, B; C): 12 = (1, 2; 3), 13 = (1, 3; 2), 23 = (2, 3; 1)
-  const Chan<T> c12 = chan_eval<T>(cs, chb, s12, s13, s23);
-  const Chan<T> c13 = chan_eval<T>(cs, chb + kChStride, s13, s12, s23);
-  const Chan<T> c23 = chan_eval<T>(cs, chb + 2 * kChStride, s23, s12, s13);
-  Chan<T> b12 = c13, b13 = c12, b23 = c23;
+  Chan<T> c12[E], c13[E], c23[E], b12[E], b13[E], b23[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    c12[e] = chan_eval<T>(cs, chb, s12[e], s13[e], s23[e]);
+    c13[e] = chan_eval<T>(cs, chb + kChStride, s13[e], s12[e], s23[e]);
+    c23[e] = chan_eval<T>(cs, chb + 2 * kChStride, s23[e], s12[e], s13[e]);
+    b12[e] = c13[e];
+    b13[e] = c12[e];
+    b23[e] = c23[e];
+  }
   if (TD) {
     // equal pair constants (m2 == m3) give bitwise equal pair quantities
     bool sym = true;
 #pragma unroll
     for (int i = 0; i < kChStride; ++i) sym = sym && cs.d[chb + i] == cs.d[chb + kChStride + i];
-    if (!sym) {
-      b12 = chan_eval<T>(cs, chb, s13, s12, s23);
-      b13 = chan_eval<T>(cs, chb + kChStride, s12, s13, s23);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (!sym) {
+        b12[e] = chan_eval<T>(cs, chb, s13[e], s12[e], s23[e]);
+        b13[e] = chan_eval<T>(cs, chb + kChStride, s12[e], s13[e], s23[e]);
+      }
+      b23[e] = chan_swap_ac_bc<T>(cs, chb + 2 * kChStride, c23[e], s12[e], s13[e]);
     }
-    b23 = chan_swap_ac_bc<T>(cs, chb + 2 * kChStride, c23, s12, s13);
   }
-  const int16_t* e = nd.res_end;
+  const int16_t* g = nd.res_end;
   const T r2 = cs.get<T>(nd.c0 + kDzR2);
-  res_group<T, 0, TD>(cs, rbase, r2, 0, e[0], c12, b12, a, ab);
-  res_group<T, 1, TD>(cs, rbase, r2, e[0], e[1], c12, b12, a, ab);
-  res_group<T, 2, TD>(cs, rbase, r2, e[1], e[2], c12, b12, a, ab);
-  res_group<T, 0, TD>(cs, rbase, r2, e[2], e[3], c13, b13, a, ab);
-  res_group<T, 1, TD>(cs, rbase, r2, e[3], e[4], c13, b13, a, ab);
-  res_group<T, 2, TD>(cs, rbase, r2, e[4], e[5], c13, b13, a, ab);
-  res_group<T, 0, TD>(cs, rbase, r2, e[5], e[6], c23, b23, a, ab);
-  res_group<T, 1, TD>(cs, rbase, r2, e[6], e[7], c23, b23, a, ab);
-  res_group<T, 2, TD>(cs, rbase, r2, e[7], e[8], c23, b23, a, ab);
-  // absent resonances: zero amplitudes (their coefficients are zero too)
+  res_group<T, 0, TD, E>(cs, rbase, r2, 0, g[0], c12, b12, a0, a1, b0, b1);
+  res_group<T, 1, TD, E>(cs, rbase, r2, g[0], g[1], c12, b12, a0, a1, b0, b1);
+  res_group<T, 2, TD, E>(cs, rbase, r2, g[1], g[2], c12, b12, a0, a1, b0, b1);
+  res_group<T, 0, TD, E>(cs, rbase, r2, g[2], g[3], c13, b13, a0, a1, b0, b1);
+  res_group<T, 1, TD, E>(cs, rbase, r2, g[3], g[4], c13, b13, a0, a1, b0, b1);
+  res_group<T, 2, TD, E>(cs, rbase, r2, g[4], g[5], c13, b13, a0, a1, b0, b1);
+  res_group<T, 0, TD, E>(cs, rbase, r2, g[5], g[6], c23, b23, a0, a1, b0, b1);
+  res_group<T, 1, TD, E>(cs, rbase, r2, g[6], g[7], c23, b23, a0, a1, b0, b1);
+  res_group<T, 2, TD, E>(cs, rbase, r2, g[7], g[8], c23, b23, a0, a1, b0, b1);
   for (int k = R; k < kMaxRes; ++k) {
-    a[2 * k] = a[2 * k + 1] = T(0);
-    if (TD) ab[2 * k] = ab[2 * k + 1] = T(0);
+    static_for<E>([&](auto ei) {
+      constexpr int e = decltype(ei)::value;
+      pick<e>(a0, a1)[2 * k] = pick<e>(a0, a1)[2 * k + 1] = T(0);
+      if (TD) pick<e>(b0, b1)[2 * k] = pick<e>(b0, b1)[2 * k + 1] = T(0);
+    });
   }
 }
 

@@ -20,6 +20,8 @@
 // reference; location differences (x - a, x - mu, m0^2 - s) are formed from
 // the stored offset and a double constant (in double, or as a float hi + lo
 // pair), then rounded once.
+#include <algorithm>
+
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -79,140 +81,167 @@ __device__ __forceinline__ T leaf_poly(const CS& cs, int c0, int deg, bool hoist
   return lv;
 }
 
-// DALITZ: ln |1 + sum c_k A_k|^2 ; slot derivatives d/d(Re c_k), d/d(Im c_k)
-// go to emit(slot, value) (stored by the tree interpreter, accumulated
-// directly by the single-leaf kernels).  The sums run over all kMaxRes
-// resonance places: absent ones have zero amplitude and coefficient, and
-// emit zero derivatives for slots 2R .. 2 kMaxRes - 1, which the caller
-// drops or adds harmlessly.
-template <typename T, class Emit>
-__device__ __forceinline__ T leaf_dalitz(const CS& cs, const KNode& nd, bool hoisted, double x12, double x13,
-                                         const Emit& emit) {
+// DALITZ: ln |1 + sum c_k A_k|^2 for E events at once (lv[e]); the slot
+// derivatives d/d(Re c_k), d/d(Im c_k) of all E events go to emit(slot,
+// values[E]) (stored by the tree interpreter, accumulated directly by the
+// single-leaf kernels).  The sums run over all kMaxRes resonance places:
+// absent ones have zero amplitude and coefficient, and emit zero derivatives
+// for slots 2R .. 2 kMaxRes - 1, which the caller drops or adds harmlessly.
+template <typename T, int E, class Emit>
+__device__ __forceinline__ void leaf_dalitz(const CS& cs, const KNode& nd, bool hoisted, const double (&x12)[E],
+                                            const double (&x13)[E], T (&lv)[E], const Emit& emit) {
   const int c0 = nd.c0, R = nd.aux;
-  const double s12 = x12 + cs.d[c0 + kDzRef12];
-  const double s13 = x13 + cs.d[c0 + kDzRef13];
-  const double s23 = cs.d[c0 + kDzSsum] - s12 - s13;
-  T a[2 * kMaxRes];
-  dalitz_amps<T, false>(cs, nd, s12, s13, s23, a, nullptr);
-  Cx<T> A[kMaxRes];
+  double s12[E], s13[E], s23[E];
 #pragma unroll
-  for (int k = 0; k < kMaxRes; ++k) A[k] = {a[2 * k], a[2 * k + 1]};
-  const int cb = c0 + dz_coef_base(R, false);
-  Cx<T> S = {T(1), T(0)};
-#pragma unroll
-  for (int k = 0; k < kMaxRes; ++k) {
-    const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
-    const Cx<T> t = cmul(c, A[k]);
-    S.re += t.re;
-    S.im += t.im;
+  for (int e = 0; e < E; ++e) {
+    s12[e] = x12[e] + cs.d[c0 + kDzRef12];
+    s13[e] = x13[e] + cs.d[c0 + kDzRef13];
+    s23[e] = cs.d[c0 + kDzSsum] - s12[e] - s13[e];
   }
-  const T a2 = S.re * S.re + S.im * S.im;
-  const T inv = T(2) * Mth<T>::rcp(a2);
-  T lv = a2 > T(0) ? Mth<T>::ln(a2) : T(-INFINITY);
+  static_assert(E == 1 || E == 2, "one or two events per step");
+  AmpArr<T> a0, a1;
+  dalitz_amps<T, false, E>(cs, nd, s12, s13, s23, a0, a1, a0, a1);
+  const int cb = c0 + dz_coef_base(R, false);
+  Cx<T> S[E];
+  T inv[E];
+  static_for<E>([&](auto ei) {
+    constexpr int e = decltype(ei)::value;
+    const AmpArr<T>& ae = pick<e>(a0, a1);
+    S[e] = {T(1), T(0)};
+#pragma unroll
+    for (int k = 0; k < kMaxRes; ++k) {
+      const Cx<T> t = cmul(Cx<T>{cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)}, Cx<T>{ae[2 * k], ae[2 * k + 1]});
+      S[e].re += t.re;
+      S[e].im += t.im;
+    }
+    const T a2 = S[e].re * S[e].re + S[e].im * S[e].im;
+    inv[e] = T(2) * Mth<T>::rcp(a2);
+    lv[e] = a2 > T(0) ? Mth<T>::ln(a2) : T(-INFINITY);
+    if (!hoisted) lv[e] = (lv[e] - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
+  });
 #pragma unroll
   for (int k = 0; k < kMaxRes; ++k) {
+    T d_re[E], d_im[E];
+    static_for<E>([&](auto ei) {
+      constexpr int e = decltype(ei)::value;
+      const AmpArr<T>& ae = pick<e>(a0, a1);
       // conj(S) A_k
-      const T re = S.re * A[k].re + S.im * A[k].im;
-      const T im = S.re * A[k].im - S.im * A[k].re;
-      T d_re = re * inv, d_im = -im * inv;
+      const T re = S[e].re * ae[2 * k] + S[e].im * ae[2 * k + 1];
+      const T im = S[e].re * ae[2 * k + 1] - S[e].im * ae[2 * k];
+      d_re[e] = re * inv[e];
+      d_im[e] = -im * inv[e];
       if (!hoisted && k < R) {
-        d_re -= cs.get<T>(c0 + kDzDln + 2 * k);
-        d_im -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
+        d_re[e] -= cs.get<T>(c0 + kDzDln + 2 * k);
+        d_im[e] -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
       }
-      emit(2 * k, d_re);
-      emit(2 * k + 1, d_im);
-    }
-  if (!hoisted) lv = (lv - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
-  return lv;
+    });
+    emit(2 * k, d_re);
+    emit(2 * k + 1, d_im);
+  }
 }
 
-// TDDP: ln [a_c C + a_0 E0 + a_s S]; slot derivatives (coefficients, then
-// tau, y) go to emit(slot, value), the coefficients' first over all kMaxRes
-// places as for DALITZ, then tau and y to slots 2R and 2R + 1 (after any
-// zero emitted there)
-template <typename T, class Emit>
-__device__ __forceinline__ T leaf_tddp(const CS& cs, const KNode& nd, bool hoisted, double x12, double x13,
-                                       double xt, double xs, const Emit& emit) {
+// TDDP: ln [a_c C + a_0 E0 + a_s S] for E events at once; slot derivatives
+// (coefficients, then tau, y) go to emit(slot, values[E]), the coefficients'
+// first over all kMaxRes places as for DALITZ, then tau and y to slots 2R and
+// 2R + 1 (after any zero emitted there).
+template <typename T, int E, class Emit>
+__device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool hoisted, const double (&x12)[E],
+                                          const double (&x13)[E], const double (&xt)[E], const double (&xs)[E],
+                                          T (&lv)[E], const Emit& emit) {
   const int c0 = nd.c0, R = nd.aux;
-  const double s12 = x12 + cs.d[c0 + kDzRef12];
-  const double s13 = x13 + cs.d[c0 + kDzRef13];
-  const double s23 = cs.d[c0 + kDzSsum] - s12 - s13;
-  T a[2 * kMaxRes], ab[2 * kMaxRes];
-  dalitz_amps<T, true>(cs, nd, s12, s13, s23, a, ab);
-  Cx<T> A[kMaxRes], Ab[kMaxRes];
+  double s12[E], s13[E], s23[E];
 #pragma unroll
-  for (int k = 0; k < kMaxRes; ++k) {
-    A[k] = {a[2 * k], a[2 * k + 1]};
-    Ab[k] = {ab[2 * k], ab[2 * k + 1]};
+  for (int e = 0; e < E; ++e) {
+    s12[e] = x12[e] + cs.d[c0 + kDzRef12];
+    s13[e] = x13[e] + cs.d[c0 + kDzRef13];
+    s23[e] = cs.d[c0 + kDzSsum] - s12[e] - s13[e];
   }
+  static_assert(E == 1 || E == 2, "one or two events per step");
+  AmpArr<T> a0, a1, b0, b1;
+  dalitz_amps<T, true, E>(cs, nd, s12, s13, s23, a0, a1, b0, b1);
   const int cb = c0 + dz_coef_base(R, true);
-  Cx<T> S = {T(1), T(0)}, Sb = {T(1), T(0)};
-#pragma unroll
-  for (int k = 0; k < kMaxRes; ++k) {
-    const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
-    const Cx<T> t = cmul(c, A[k]), tb = cmul(c, Ab[k]);
-    S.re += t.re; S.im += t.im;
-    Sb.re += tb.re; Sb.im += tb.im;
-  }
-  const T nA = S.re * S.re + S.im * S.im;
-  const T nB = Sb.re * Sb.re + Sb.im * Sb.im;
-  const T X = S.re * Sb.re + S.im * Sb.im;  // Re(conj(A) Abar)
-  const T as = -X;
-  // Decay-time factors, formed in double: C - E(1/tau), S and the tau / y
-  // derivative combinations are small differences of nearly equal terms
-  // (|y| << 1), and rounding them in float would bias every event the same way.
-  const double t = xt, s = xs;
   const int tb = c0 + dz_time_base(R);
-  const double g = ::exp(-0.5 * t * t / (s * s));
-  double Em, dEm, Ep, dEp, E0, dE0;
-  econv<double>(t, s, cs.d[tb + kTdGm], g, Em, dEm);
-  econv<double>(t, s, cs.d[tb + kTdGp], g, Ep, dEp);
-  econv<double>(t, s, cs.d[tb + kTdG], g, E0, dE0);
-  const double Cd = 0.5 * (Em + Ep);
-  const double Tm = dEm * cs.d[tb + kTdDGmTau], Tp = dEp * cs.d[tb + kTdDGpTau];
-  const double T1 = 0.5 * (Tm + Tp), T0 = dE0 * cs.d[tb + kTdDGTau];
-  const double Ym = dEm * cs.d[tb + kTdDGmY], Yp = dEp * cs.d[tb + kTdDGpY];
-  const T cc = (T)(Cd + E0);          // d R / d(|A|^2 / 2)
-  const T cb_ = (T)(Cd - E0);         // d R / d(|Abar|^2 / 2)
-  const T St = (T)(0.5 * (Em - Ep));  // S(t)
-  const T tA = (T)(T1 + T0), tB = (T)(T1 - T0), tS = (T)(0.5 * (Tm - Tp));
-  const T yAB = (T)(0.5 * (Ym + Yp)), yS = (T)(0.5 * (Ym - Yp));
-  // rate = a_c C + a_0 E0 + a_s S = |A|^2 (C + E0)/2 + |Abar|^2 (C - E0)/2 + a_s S
-  const T Rv = T(0.5) * nA * cc + T(0.5) * nB * cb_ + as * St;
-  const T iR = Mth<T>::rcp(Rv);
-  T lv = Rv > T(0) ? Mth<T>::ln(Rv) : T(-INFINITY);
+  Cx<T> S[E], Sb[E];
+  T cc[E], cb_[E], St[E], iR[E], dtau[E], dy[E];
+  static_for<E>([&](auto ei) {
+    constexpr int e = decltype(ei)::value;
+    const AmpArr<T>& ae = pick<e>(a0, a1);
+    const AmpArr<T>& be = pick<e>(b0, b1);
+    S[e] = {T(1), T(0)};
+    Sb[e] = {T(1), T(0)};
+#pragma unroll
+    for (int k = 0; k < kMaxRes; ++k) {
+      const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
+      const Cx<T> t = cmul(c, Cx<T>{ae[2 * k], ae[2 * k + 1]});
+      const Cx<T> u = cmul(c, Cx<T>{be[2 * k], be[2 * k + 1]});
+      S[e].re += t.re; S[e].im += t.im;
+      Sb[e].re += u.re; Sb[e].im += u.im;
+    }
+    const T nA = S[e].re * S[e].re + S[e].im * S[e].im;
+    const T nB = Sb[e].re * Sb[e].re + Sb[e].im * Sb[e].im;
+    const T as = -(S[e].re * Sb[e].re + S[e].im * Sb[e].im);  // -Re(conj(A) Abar)
+    // Decay-time factors, formed in double: C - E(1/tau), S and the tau / y
+    // derivative combinations are small differences of nearly equal terms
+    // (|y| << 1), and rounding them in float would bias every event the
+    // same way.
+    const double t = xt[e], s = xs[e];
+    const double g = ::exp(-0.5 * t * t / (s * s));
+    double Em, dEm, Ep, dEp, E0, dE0;
+    econv<double>(t, s, cs.d[tb + kTdGm], g, Em, dEm);
+    econv<double>(t, s, cs.d[tb + kTdGp], g, Ep, dEp);
+    econv<double>(t, s, cs.d[tb + kTdG], g, E0, dE0);
+    const double Cd = 0.5 * (Em + Ep);
+    const double Tm = dEm * cs.d[tb + kTdDGmTau], Tp = dEp * cs.d[tb + kTdDGpTau];
+    const double T1 = 0.5 * (Tm + Tp), T0 = dE0 * cs.d[tb + kTdDGTau];
+    const double Ym = dEm * cs.d[tb + kTdDGmY], Yp = dEp * cs.d[tb + kTdDGpY];
+    cc[e] = (T)(Cd + E0);          // d R / d(|A|^2 / 2)
+    cb_[e] = (T)(Cd - E0);         // d R / d(|Abar|^2 / 2)
+    St[e] = (T)(0.5 * (Em - Ep));  // S(t)
+    const T tA = (T)(T1 + T0), tB = (T)(T1 - T0), tS = (T)(0.5 * (Tm - Tp));
+    const T yAB = (T)(0.5 * (Ym + Yp)), yS = (T)(0.5 * (Ym - Yp));
+    // rate = a_c C + a_0 E0 + a_s S = |A|^2 (C + E0)/2 + |Abar|^2 (C - E0)/2 + a_s S
+    const T Rv = T(0.5) * nA * cc[e] + T(0.5) * nB * cb_[e] + as * St[e];
+    iR[e] = Mth<T>::rcp(Rv);
+    lv[e] = Rv > T(0) ? Mth<T>::ln(Rv) : T(-INFINITY);
+    dtau[e] = (T(0.5) * nA * tA + T(0.5) * nB * tB + as * tS) * iR[e];
+    dy[e] = (T(0.5) * (nA + nB) * yAB + as * yS) * iR[e];
+    if (!hoisted) {
+      dtau[e] -= cs.get<T>(c0 + kDzDln + 2 * R);
+      dy[e] -= cs.get<T>(c0 + kDzDln + 2 * R + 1);
+      lv[e] = (lv[e] - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
+    }
+  });
 #pragma unroll
   for (int k = 0; k < kMaxRes; ++k) {
+    T d_re[E], d_im[E];
+    static_for<E>([&](auto ei) {
+      constexpr int e = decltype(ei)::value;
+      const AmpArr<T>& ae = pick<e>(a0, a1);
+      const AmpArr<T>& be = pick<e>(b0, b1);
       // re part: dA = A_k, dAb = Ab_k ; im part: dA = i A_k, dAb = i Ab_k
-      const T pA_re = S.re * A[k].re + S.im * A[k].im;     // Re(conj(S) A_k)
-      const T pA_im = S.re * A[k].im - S.im * A[k].re;     // Im(conj(S) A_k)
-      const T pB_re = Sb.re * Ab[k].re + Sb.im * Ab[k].im;
-      const T pB_im = Sb.re * Ab[k].im - Sb.im * Ab[k].re;
-      const T x1_re = A[k].re * Sb.re + A[k].im * Sb.im;   // Re(conj(A_k) Sb)
-      const T x1_im = A[k].re * Sb.im - A[k].im * Sb.re;   // Im(conj(A_k) Sb)
-      const T x2_re = S.re * Ab[k].re + S.im * Ab[k].im;   // Re(conj(S) Ab_k)
-      const T x2_im = S.re * Ab[k].im - S.im * Ab[k].re;   // Im(conj(S) Ab_k)
-      const T dR_re = cc * pA_re + cb_ * pB_re - (x1_re + x2_re) * St;
-      const T dR_im = -cc * pA_im - cb_ * pB_im - (x1_im - x2_im) * St;
-      T d_re = dR_re * iR, d_im = dR_im * iR;
+      const T ar = ae[2 * k], ai = ae[2 * k + 1], br = be[2 * k], bi = be[2 * k + 1];
+      const T pA_re = S[e].re * ar + S[e].im * ai;    // Re(conj(S) A_k)
+      const T pA_im = S[e].re * ai - S[e].im * ar;    // Im(conj(S) A_k)
+      const T pB_re = Sb[e].re * br + Sb[e].im * bi;
+      const T pB_im = Sb[e].re * bi - Sb[e].im * br;
+      const T x1_re = ar * Sb[e].re + ai * Sb[e].im;  // Re(conj(A_k) Sb)
+      const T x1_im = ar * Sb[e].im - ai * Sb[e].re;  // Im(conj(A_k) Sb)
+      const T x2_re = S[e].re * br + S[e].im * bi;    // Re(conj(S) Ab_k)
+      const T x2_im = S[e].re * bi - S[e].im * br;    // Im(conj(S) Ab_k)
+      const T dR_re = cc[e] * pA_re + cb_[e] * pB_re - (x1_re + x2_re) * St[e];
+      const T dR_im = -cc[e] * pA_im - cb_[e] * pB_im - (x1_im - x2_im) * St[e];
+      d_re[e] = dR_re * iR[e];
+      d_im[e] = dR_im * iR[e];
       if (!hoisted && k < R) {
-        d_re -= cs.get<T>(c0 + kDzDln + 2 * k);
-        d_im -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
+        d_re[e] -= cs.get<T>(c0 + kDzDln + 2 * k);
+        d_im[e] -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
       }
-      emit(2 * k, d_re);
-      emit(2 * k + 1, d_im);
-    }
-  const T dtau = T(0.5) * nA * tA + T(0.5) * nB * tB + as * tS;
-  const T dy = T(0.5) * (nA + nB) * yAB + as * yS;
-  T d_tau = dtau * iR, d_y = dy * iR;
-  if (!hoisted) {
-    d_tau -= cs.get<T>(c0 + kDzDln + 2 * R);
-    d_y -= cs.get<T>(c0 + kDzDln + 2 * R + 1);
-    lv = (lv - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
+    });
+    emit(2 * k, d_re);
+    emit(2 * k + 1, d_im);
   }
-  emit(2 * R, d_tau);
-  emit(2 * R + 1, d_y);
-  return lv;
+  emit(2 * R, dtau);
+  emit(2 * R + 1, dy);
 }
 
 // ------------------------------------------------------------------ cross-lane sums
@@ -558,22 +587,10 @@ struct LightLeafEv {  // single EXP / GAUSS leaf
   }
 };
 
-template <typename T, int OP, bool GRAD>
-struct AmpLeafEv {  // single DALITZ / TDDP leaf
-  static constexpr int NS = OP == OP_DALITZ ? 2 * kMaxRes : 2 * kMaxRes + 2;
-  CS cs;
-  template <class Acc>
-  __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, int64_t, const Acc& acc) const {
-    // the single leaf is the root: its normalisation is applied on the host
-    const auto emit = [&](int j, T v) {
-      if (GRAD) acc.add(1 + j, (double)v);
-    };
-    T lv;
-    if (OP == OP_DALITZ) lv = leaf_dalitz<T>(cs, P.node[0], true, xe[0], xe[1], emit);
-    else lv = leaf_tddp<T>(cs, P.node[0], true, xe[0], xe[1], xe[2], xe[3], emit);
-    acc.add(0, -(double)lv);
-  }
-};
+// Events per thread and step of the single-leaf amplitude kernels: the E
+// events share every read of a resonance's constants and every loop step,
+// and give the wave E independent instruction chains.
+template <typename T, int OP> struct AmpEvents { static constexpr int value = OP == OP_DALITZ ? 2 : 1; };
 
 // General trees (ADD / PROD over leaves).  Node log-values, adjoints and the
 // per-event slot derivatives live in small VGPR arrays indexed by
@@ -607,17 +624,20 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           if (j < nd.aux) dl[s0 + j] = dp[j];
-      } else if (HEAVY && op == OP_DALITZ) {
+      } else if (HEAVY && (op == OP_DALITZ || op == OP_TDDP)) {
         const int ns = nd.n_slot;
-        v = leaf_dalitz<T>(cs, nd, h, xe[nd.col[0]], xe[nd.col[1]], [&](int j, T d) {
-          if (j < ns) dl[s0 + j] = d;
-        });
-      } else if (HEAVY && op == OP_TDDP) {
-        const int ns = nd.n_slot;
-        v = leaf_tddp<T>(cs, nd, h, xe[nd.col[0]], xe[nd.col[1]], xe[nd.col[2]], xe[nd.col[3]],
-                         [&](int j, T d) {
-                           if (j < ns) dl[s0 + j] = d;
-                         });
+        const auto emit = [&](int j, const T (&d)[1]) {
+          if (j < ns) dl[s0 + j] = d[0];
+        };
+        const double x12[1] = {xe[nd.col[0]]}, x13[1] = {xe[nd.col[1]]};
+        T l1[1];
+        if (op == OP_DALITZ) {
+          leaf_dalitz<T, 1>(cs, nd, h, x12, x13, l1, emit);
+        } else {
+          const double xt[1] = {xe[nd.col[2]]}, xs[1] = {xe[nd.col[3]]};
+          leaf_tddp<T, 1>(cs, nd, h, x12, x13, xt, xs, l1, emit);
+        }
+        v = l1[0];
       } else if (op == OP_PROD) {
         v = T(0);
         for (int j = 0; j < nd.n_child; ++j) {
@@ -757,15 +777,21 @@ __device__ __forceinline__ void light_leaf_row(const KNode& nd, const CS& cs, co
   row_store_lds<NC>(acc, out, n_rows);
 }
 
+// Single DALITZ / TDDP leaf (the root: its normalisation is applied on the
+// host).  A thread takes event t of E consecutive chunks per step (the next
+// step's columns in flight) and adds each slot's E derivatives, summed in
+// double, with one LDS add.  Events past the row's end are replaced by the
+// step's first event and weighted out; a thread whose first event is past
+// the end has none left.
 template <typename T, int OP, bool GRAD>
 __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
                                              int n_rows, int r, double* __restrict__ out) {
-  typedef AmpLeafEv<T, OP, GRAD> Ev;
   typedef typename Col<T>::S Sx;
+  constexpr int E = AmpEvents<T, OP>::value;
   constexpr int NCOL = OP == OP_DALITZ ? 2 : 4;
-  constexpr int NC = 1 + Ev::NS;
+  constexpr int NS = OP == OP_DALITZ ? 2 * kMaxRes : 2 * kMaxRes + 2;
+  constexpr int NC = 1 + NS;
   const KNode& nd = P.node[0];
-  const Ev ev{cs};
   // slot columns: 2R coefficient derivatives (+ tau, y); zero derivatives
   // land in the columns up to 2 kMaxRes, so all are cleared
   const int n_slots = GRAD ? P.n_slots : 0;
@@ -777,7 +803,48 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
   acc.zero(GRAD ? NC : 1);
   int64_t c0, c1;
   row_chunks(n, n_rows, r, c0, c1);
-  heavy_row<T, NCOL>(ev, P, cp, NCOL, n, c0, c1, acc);
+  const int64_t t = threadIdx.x;
+  Sx cur[E][NCOL];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t i = (c0 + e) * kBlock + t;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) cur[e][c] = (c0 + e < c1 && i < n) ? cp[c][i] : Sx(0);
+  }
+#pragma unroll 1
+  for (int64_t ch = c0; ch < c1; ch += E) {
+    bool ok[E];
+    double x[NCOL][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      ok[e] = ch + e < c1 && (ch + e) * kBlock + t < n;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) x[c][e] = (double)(ok[e] ? cur[e][c] : cur[0][c]);
+    }
+    if (ch + E < c1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t i1 = (ch + E + e) * kBlock + t;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) cur[e][c] = (ch + E + e < c1 && i1 < n) ? cp[c][i1] : Sx(0);
+      }
+    }
+    if (!ok[0]) continue;
+    // sum over the step's valid events, in double
+    const auto sum = [&](const T (&v)[E]) {
+      double s = (double)v[0];
+#pragma unroll
+      for (int e = 1; e < E; ++e) s += (double)(ok[e] ? v[e] : T(0));
+      return s;
+    };
+    const auto emit = [&](int j, const T (&v)[E]) {
+      if (GRAD) acc.add(1 + j, sum(v));
+    };
+    T lv[E];
+    if constexpr (OP == OP_DALITZ) leaf_dalitz<T, E>(cs, nd, true, x[0], x[1], lv, emit);
+    else leaf_tddp<T, E>(cs, nd, true, x[0], x[1], x[2], x[3], lv, emit);
+    acc.add(0, -sum(lv));
+  }
   row_store_acc<NC>(acc, 1 + n_slots, out, n_rows);
 }
 
@@ -1008,6 +1075,34 @@ __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
 bool kind_light(int kind) {
   if (kind >= KIND_MIX2) return true;
   return kind == KIND_EXP || kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
+}
+
+// Resident blocks per compute unit of a kind's kernels (the smaller of the
+// NLL-only and gradient instantiations), from the occupancy calculator.
+template <typename T, bool GRAD>
+static const void* kernel_of(int kind) {
+  switch (kind) {
+    case KIND_EXP: return (const void*)&k_leaf<T, OP_EXP, GRAD>;
+    case KIND_GAUSS: return (const void*)&k_leaf<T, OP_GAUSS, GRAD>;
+    case KIND_TREE_SMALL: return (const void*)&k_tree<T, 8, 2, false, GRAD>;
+    case KIND_DALITZ: return (const void*)&k_leaf<T, OP_DALITZ, GRAD>;
+    case KIND_TDDP: return (const void*)&k_leaf<T, OP_TDDP, GRAD>;
+    case KIND_TREE: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, true, GRAD>;
+    default: return nullptr;  // mixtures: light, never below kRowsPerCU
+  }
+}
+
+int resident_blocks_per_cu(int kind, bool fp32) {
+  int best = 0;
+  for (int grad = 0; grad < 2; ++grad) {
+    const void* f = fp32 ? (grad ? kernel_of<float, true>(kind) : kernel_of<float, false>(kind))
+                         : (grad ? kernel_of<double, true>(kind) : kernel_of<double, false>(kind));
+    if (!f) continue;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess || nb <= 0) continue;
+    best = best == 0 ? nb : std::min(best, nb);
+  }
+  return best;
 }
 
 // Single-dataset launches go through hipExtLaunchKernel so that timing

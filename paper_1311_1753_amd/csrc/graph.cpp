@@ -9,6 +9,7 @@
 // gradient, computed here in double from closed forms (exponential, Gaussian,
 // polynomial, the time integrals) or from the cached Dalitz grid matrices.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdlib>
@@ -222,26 +223,39 @@ void assemble_binned(const pdf_graph* g, const StagedCall& sc, const double* sum
     if (g->par[p].fixed) grad[p] = 0.0;
 }
 
-int32_t rows_for(int kind, int64_t n) {
+int32_t rows_for(int kind, hf_precision prec, int64_t n) {
   if (n <= 0) return 0;
-  static int cus[64] = {0};
+  static std::atomic<int> cus[64];
+  static std::atomic<int> resident[64][2][KIND_MIX3 + 8];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  if (cus[dev] <= 0) {
+  if (cus[dev].load() <= 0) {
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
-    cus[dev] = cu;
+    cus[dev].store(cu);
   }
-  // rows per compute unit: kRowsPerCU, or HIPFIT_ROWS_PER_CU (1..64) for tuning
-  static const int per_cu = [] {
+  // rows per compute unit: kRowsPerCU, or HIPFIT_ROWS_PER_CU (1..64) for
+  // tuning; at most the kernels' resident blocks per compute unit
+  static const int per_cu_env = [] {
     const char* v = std::getenv("HIPFIT_ROWS_PER_CU");
     const int k = v ? std::atoi(v) : 0;
-    return k >= 1 && k <= 64 ? k : kRowsPerCU;
+    return k >= 1 && k <= 64 ? k : 0;
   }();
+  int per_cu = per_cu_env ? per_cu_env : kRowsPerCU;
+  const bool fp32 = prec == HF_FP32_EVAL;
+  if (!per_cu_env && kind >= 0 && kind < KIND_MIX3 + 8) {
+    std::atomic<int>& r = resident[dev][fp32 ? 1 : 0][kind];
+    if (r.load() == 0) {
+      const int nb = resident_blocks_per_cu(kind, fp32);
+      r.store(nb > 0 ? nb : -1);
+    }
+    const int nb = r.load();
+    if (nb > 0 && nb < per_cu) per_cu = nb;
+  }
   const int64_t nch = (n + kBlock - 1) / kBlock;
   const int64_t minc = kind_light(kind) ? kMinChunksLight : 1;
   const int64_t want = (nch + minc - 1) / minc;
-  const int64_t cap = (int64_t)cus[dev] * per_cu;
+  const int64_t cap = (int64_t)cus[dev].load() * per_cu;
   return (int32_t)(want < cap ? want : cap);
 }
 

@@ -72,17 +72,17 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows(const GridArgs a) {
       in = in_pair(a.gs.M, a.gs.m1, s12, s13, a.gs.m2, a.gs.m3) &&
            in_pair(a.gs.M, a.gs.m1, s13, s12, a.gs.m3, a.gs.m2);
     }
-    double A[2 * kMaxRes], Ab[2 * kMaxRes];
+    AmpArr<double> a0, b0;
     if (in) {
-      const double s23 = cs.d[a.c0 + kDzSsum] - s12 - s13;
-      if (a.tddp) dalitz_amps<double, true>(cs, a.prog.node[a.node], s12, s13, s23, A, Ab);
-      else dalitz_amps<double, false>(cs, a.prog.node[a.node], s12, s13, s23, A, nullptr);
+      const double p12[1] = {s12}, p13[1] = {s13}, p23[1] = {cs.d[a.c0 + kDzSsum] - s12 - s13};
+      if (a.tddp) dalitz_amps<double, true, 1>(cs, a.prog.node[a.node], p12, p13, p23, a0, a0, b0, b0);
+      else dalitz_amps<double, false, 1>(cs, a.prog.node[a.node], p12, p13, p23, a0, a0, b0, b0);
     }
     sa[t][0] = make_double2(in ? 1.0 : 0.0, 0.0);
     sb[t][0] = sa[t][0];
     for (int k = 0; k < a.R; ++k) {
-      sa[t][k + 1] = in ? make_double2(A[2 * k], A[2 * k + 1]) : make_double2(0.0, 0.0);
-      sb[t][k + 1] = (in && a.tddp) ? make_double2(Ab[2 * k], Ab[2 * k + 1]) : make_double2(0.0, 0.0);
+      sa[t][k + 1] = in ? make_double2(a0[2 * k], a0[2 * k + 1]) : make_double2(0.0, 0.0);
+      sb[t][k + 1] = (in && a.tddp) ? make_double2(b0[2 * k], b0[2 * k + 1]) : make_double2(0.0, 0.0);
     }
   }
   __syncthreads();

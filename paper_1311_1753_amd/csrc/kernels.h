@@ -20,13 +20,18 @@ enum KernelKind {
   KIND_MIX3 = 16
 };
 
-// Rows (blocks) per dataset: at most kRowsPerCU per compute unit, and at
-// least kMinChunksLight chunks of 256 events per row for the light kinds.
+// Rows (blocks) per dataset: at most kRowsPerCU per compute unit (fewer when
+// fewer blocks of the kind's kernels fit on a compute unit at once, so that
+// every row is resident from the start), and at least kMinChunksLight chunks
+// of 256 events per row for the light kinds.
 constexpr int kRowsPerCU = 4;
 constexpr int kMinChunksLight = 4;
 
 // true for the single-column kinds (EXP, GAUSS, small trees, mixtures)
 bool kind_light(int kind);
+// Blocks of a kind's kernels that fit on one compute unit at once (current
+// device); 0 when unknown (mixtures, or the occupancy query failed).
+int resident_blocks_per_cu(int kind, bool fp32);
 
 // e0 / e1 (nullable): events that receive the dispatch's start / end time
 hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,

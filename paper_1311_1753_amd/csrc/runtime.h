@@ -119,9 +119,9 @@ bool dalitz_inside(const DalitzInfo& dz, double s12, double s13);
 int eval_one(const pdf_graph* g, const dataset* d, const double* theta, hipStream_t st, bool want_grad, double* nll,
              double* grad);
 int n_free(const pdf_graph* g);
-// Rows of a dataset of n events for a graph of kernel kind `kind` on the
-// current device.
-int32_t rows_for(int kind, int64_t n);
+// Rows of a dataset of n events for a graph of kernel kind `kind` in
+// precision `prec` on the current device.
+int32_t rows_for(int kind, hf_precision prec, int64_t n);
 // NLL and gradient from the reduced sums [sum(-ln P), slot sums] of one
 // evaluation (sums may be null for an empty dataset); grad may be null.
 void assemble(const pdf_graph* g, const StagedCall& sc, const double* sums, int64_t n, double* nll, double* grad);

@@ -27,7 +27,12 @@
 //          Dalitz-plot amplitude sum)
 //   TDDP   P = [a_c C(t) + a_0 E(t;1/tau) + a_s S(t)] / N_T, the x = 0 mixing
 //          rate convolved with a per-event Gaussian resolution ("Results":
-//          hyperbolic time terms convolved with Gaussian resolution)
+//          hyperbolic time terms convolved with Gaussian resolution); with
+//          the mixing parameter x the trigonometric terms enter too:
+//          P = [a_c C(t) + a_0 Cz(t) + a_s S(t) + b_s Sz(t)] / N_T, Cz / Sz the
+//          resolution-convolved e^{-t/tau} cos(x t/tau) / sin(x t/tau),
+//          b_s = -Im(conj(A) Abar)
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -81,6 +86,61 @@ double econv(double t, double G, double s) {
 // dE/dG = (G s^2 - t) E - s/sqrt(2 pi) exp(-t^2/(2 s^2))
 double econv_dG(double t, double G, double s) {
   return (G * s * s - t) * econv(t, G, s) - s / std::sqrt(2.0 * kPi) * std::exp(-t * t / (2.0 * s * s));
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton iteration on the
+// Legendre polynomial P_n from the usual starting guesses.
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), pp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      double z1 = z;
+      z = z1 - p1 / pp;
+      if (std::fabs(z - z1) < 1e-15) break;
+    }
+    x[i] = -z; x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+// Gaussian-resolution convolution of the oscillating decay, straight from its
+// definition:
+//   Cz(t) + i Sz(t) = int_0^inf e^{-G u} e^{i w u} N(t - u; 0, s) du
+// (Cz convolves e^{-G u} cos(w u), Sz e^{-G u} sin(w u)), and the derivatives
+// of both with respect to G and w, by 16-point Gauss-Legendre quadrature on
+// segments of width <= s over the window where the Gaussian exceeds e^{-72}
+// of its peak.  out = {Cz, Sz, dCz/dG, dSz/dG, dCz/dw, dSz/dw}.
+void econv_osc(double t, double G, double w, double s, double* out) {
+  struct GL16 { double x[16], w[16]; };
+  static const GL16 gl = [] { GL16 g; gauss_legendre(16, g.x, g.w); return g; }();
+  const double* gx = gl.x;
+  const double* gw = gl.w;
+  const double u0 = std::max(0.0, t - 12.0 * s), u1 = std::max(0.0, t) + 12.0 * s;
+  const int nseg = std::max(1, (int)std::ceil((u1 - u0) / s));
+  const double h = (u1 - u0) / nseg, norm = 1.0 / (std::sqrt(2.0 * kPi) * s);
+  Neumaier acc[6];
+  for (int k = 0; k < nseg; ++k) {
+    const double a = u0 + k * h;
+    for (int i = 0; i < 16; ++i) {
+      const double u = a + 0.5 * h * (gx[i] + 1.0);
+      const double f = 0.5 * h * gw[i] * norm * std::exp(-G * u - (t - u) * (t - u) / (2.0 * s * s));
+      const double c = std::cos(w * u), sn = std::sin(w * u);
+      acc[0].add(f * c);
+      acc[1].add(f * sn);
+      acc[2].add(-u * f * c);
+      acc[3].add(-u * f * sn);
+      acc[4].add(-u * f * sn);
+      acc[5].add(u * f * c);
+    }
+  }
+  for (int j = 0; j < 6; ++j) out[j] = acc[j].value();
 }
 
 // phi(z) = (e^z - 1)/z, so int_a^b e^{alpha (x-a)} dx = L phi(alpha L).
@@ -215,6 +275,7 @@ struct Node {
   double x0 = 0.0;          // POLY expansion point
   DalitzDef* dz = nullptr;  // DALITZ, TDDP
   int p_tau = -1, p_y = -1; // TDDP
+  int p_x = -1;             // TDDP with the trigonometric terms (x free)
 };
 
 struct Model {
@@ -310,27 +371,36 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
       std::vector<cplx> c;
       coeffs(d, th, c);
       int na = d.n_amp();
-      double tau = th[n.p_tau], y = th[n.p_y];
+      // With x: int Cz = tau/(1+x^2), int Sz = x tau/(1+x^2).
+      double tau = th[n.p_tau], y = th[n.p_y], x = n.p_x >= 0 ? th[n.p_x] : 0.0;
+      cplx QJ = quad_form(d.Jx, c, na);
       double IAA = quad_form(d.I, c, na).real(), IBB = quad_form(d.Ib, c, na).real();
-      double RJ = quad_form(d.Jx, c, na).real();
+      double RJ = QJ.real(), IJ = QJ.imag();
       double kc = tau / (1.0 - y * y), ks = y * tau / (1.0 - y * y);
-      double N = 0.5 * (IAA + IBB) * kc + 0.5 * (IAA - IBB) * tau - RJ * ks;
+      double opx = 1.0 + x * x, kz = tau / opx, kzs = x * tau / opx;
+      double N = 0.5 * (IAA + IBB) * kc + 0.5 * (IAA - IBB) * kz - RJ * ks - IJ * kzs;
       r.lnN = std::log(N);
       for (size_t k = 0; k < d.res.size(); ++k) {
         cplx a1, a2, b1, b2, j1, j2;
         quad_form_grad(d.I, c, na, (int)k + 1, a1, a2);
         quad_form_grad(d.Ib, c, na, (int)k + 1, b1, b2);
         quad_form_grad(d.Jx, c, na, (int)k + 1, j1, j2);
-        double dre = 0.5 * (a1.real() + b1.real()) * kc + 0.5 * (a1.real() - b1.real()) * tau - j1.real() * ks;
-        double dim = 0.5 * (a2.real() + b2.real()) * kc + 0.5 * (a2.real() - b2.real()) * tau - j2.real() * ks;
+        double dre = 0.5 * (a1.real() + b1.real()) * kc + 0.5 * (a1.real() - b1.real()) * kz - j1.real() * ks -
+                     j1.imag() * kzs;
+        double dim = 0.5 * (a2.real() + b2.real()) * kc + 0.5 * (a2.real() - b2.real()) * kz - j2.real() * ks -
+                     j2.imag() * kzs;
         r.dlnN[d.res[k].p_re] += dre / N;
         r.dlnN[d.res[k].p_im] += dim / N;
       }
       double omy = 1.0 - y * y;
-      double dN_dtau = 0.5 * (IAA + IBB) / omy + 0.5 * (IAA - IBB) - RJ * y / omy;
+      double dN_dtau = 0.5 * (IAA + IBB) / omy + 0.5 * (IAA - IBB) / opx - RJ * y / omy - IJ * x / opx;
       double dN_dy = 0.5 * (IAA + IBB) * tau * 2.0 * y / (omy * omy) - RJ * tau * (1.0 + y * y) / (omy * omy);
       r.dlnN[n.p_tau] += dN_dtau / N;
       r.dlnN[n.p_y] += dN_dy / N;
+      if (n.p_x >= 0) {
+        double dN_dx = -0.5 * (IAA - IBB) * tau * 2.0 * x / (opx * opx) - IJ * tau * (1.0 - x * x) / (opx * opx);
+        r.dlnN[n.p_x] += dN_dx / N;
+      }
       break;
     }
     default:
@@ -432,12 +502,24 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
       for (int k = 0; k < na; ++k) { A += c[k] * a[k]; Ab += c[k] * ab[k]; }
       double tau = th[n.p_tau], y = th[n.p_y];
       double Gm = (1.0 - y) / tau, Gp = (1.0 + y) / tau, G = 1.0 / tau;
-      double Em = econv(t, Gm, st), Ep = econv(t, Gp, st), E0 = econv(t, G, st);
+      double Em = econv(t, Gm, st), Ep = econv(t, Gp, st);
       double Ct = 0.5 * (Em + Ep), St = 0.5 * (Em - Ep);
+      // trigonometric terms: Cz, Sz convolve e^{-G t} cos / sin(x G t); without
+      // x, Cz = E(t; 1/tau) and Sz = 0
+      double x = 0.0, oz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (n.p_x >= 0) {
+        x = th[n.p_x];
+        econv_osc(t, G, x * G, st, oz);
+      } else {
+        oz[0] = econv(t, G, st);
+        oz[2] = econv_dG(t, G, st);
+      }
+      double Cz = oz[0], Sz = oz[1];
       double ac = 0.5 * (std::norm(A) + std::norm(Ab));
       double a0 = 0.5 * (std::norm(A) - std::norm(Ab));
-      double as = -(std::conj(A) * Ab).real();
-      double R = ac * Ct + a0 * E0 + as * St;
+      cplx X = std::conj(A) * Ab;
+      double as = -X.real(), bs = -X.imag();
+      double R = ac * Ct + a0 * Cz + as * St + bs * Sz;
       if (!(R > 0.0)) return -INFINITY;
       lp = std::log(R) - nn[id].lnN;
       for (size_t k = 0; k < d.res.size(); ++k) {
@@ -445,19 +527,23 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
           cplx u = part == 0 ? cplx(1.0, 0.0) : cplx(0.0, 1.0);  // dc_k/dx
           cplx dA = u * a[k + 1], dAb = u * ab[k + 1];
           double dnA = 2.0 * (std::conj(A) * dA).real(), dnB = 2.0 * (std::conj(Ab) * dAb).real();
-          double dX = (std::conj(dA) * Ab + std::conj(A) * dAb).real();
-          double dR = 0.5 * (dnA + dnB) * Ct + 0.5 * (dnA - dnB) * E0 - dX * St;
+          cplx dX = std::conj(dA) * Ab + std::conj(A) * dAb;
+          double dR = 0.5 * (dnA + dnB) * Ct + 0.5 * (dnA - dnB) * Cz - dX.real() * St - dX.imag() * Sz;
           g[part == 0 ? d.res[k].p_re : d.res[k].p_im] += dR / R;
         }
       }
-      double dEm = econv_dG(t, Gm, st), dEp = econv_dG(t, Gp, st), dE0 = econv_dG(t, G, st);
-      // chain rule through Gm = (1-y)/tau, Gp = (1+y)/tau, G = 1/tau
+      double dEm = econv_dG(t, Gm, st), dEp = econv_dG(t, Gp, st);
+      // chain rule through Gm = (1-y)/tau, Gp = (1+y)/tau, G = 1/tau and the
+      // oscillation frequency w = x/tau
       double dRm = ac * 0.5 + as * 0.5, dRp = ac * 0.5 - as * 0.5;  // dR/dEm, dR/dEp
+      double dG_dtau = -1.0 / (tau * tau), dw_dtau = -x / (tau * tau);
+      double dCz_dtau = oz[2] * dG_dtau + oz[4] * dw_dtau, dSz_dtau = oz[3] * dG_dtau + oz[5] * dw_dtau;
       double dR_dtau = dRm * dEm * (-(1.0 - y) / (tau * tau)) + dRp * dEp * (-(1.0 + y) / (tau * tau)) +
-                       a0 * dE0 * (-1.0 / (tau * tau));
+                       a0 * dCz_dtau + bs * dSz_dtau;
       double dR_dy = dRm * dEm * (-1.0 / tau) + dRp * dEp * (1.0 / tau);
       g[n.p_tau] += dR_dtau / R;
       g[n.p_y] += dR_dy / R;
+      if (n.p_x >= 0) g[n.p_x] += (a0 * oz[4] + bs * oz[5]) / tau / R;
       break;
     }
     default:
@@ -518,10 +604,10 @@ int om_dalitz(Model* m, int o12, int o13, const double* kin, int grid, int n_res
 }
 int om_tddp(Model* m, int o12, int o13, int ot, int osig, const double* kin, int grid, int n_res,
             const int* ch, const double* m0, const double* g0, const int* J, const int* p_re,
-            const int* p_im, int p_tau, int p_y) {
+            const int* p_im, int p_tau, int p_y, int p_x) {
   Node n; n.kind = K_TDDP; n.obs = {o12, o13, ot, osig};
   n.dz = make_dalitz(kin, grid, n_res, ch, m0, g0, J, p_re, p_im);
-  n.p_tau = p_tau; n.p_y = p_y;
+  n.p_tau = p_tau; n.p_y = p_y; n.p_x = p_x;
   return push(m, n);
 }
 
@@ -698,9 +784,10 @@ void om_dalitz_amp2(Model* m, int id, const double* th, int64_t n, const double*
   }
 }
 
-// Re(conj(A) Abar) at the given theta for many points; 0 outside.
+// Re(conj(A) Abar) (imag = 0) or Im(conj(A) Abar) (imag = 1) at the given
+// theta for many points; 0 outside.
 void om_dalitz_cross(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
-                     double* out) {
+                     double* out, int imag) {
   const DalitzDef& d = *m->nodes[id].dz;
   std::vector<cplx> a(d.n_amp()), ab(d.n_amp()), c;
   coeffs(d, th, c);
@@ -710,17 +797,35 @@ void om_dalitz_cross(Model* m, int id, const double* th, int64_t n, const double
     amplitudes(d, s13[i], s12[i], ab.data());
     cplx A = 0.0, Ab = 0.0;
     for (int k = 0; k < d.n_amp(); ++k) { A += c[k] * a[k]; Ab += c[k] * ab[k]; }
-    out[i] = (std::conj(A) * Ab).real();
+    out[i] = imag ? (std::conj(A) * Ab).imag() : (std::conj(A) * Ab).real();
+  }
+}
+
+// The coherent sum A = sum_k c_k A_k (c_0 = 1) at many points; 0 outside.
+void om_dalitz_amp(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
+                   double* re, double* im) {
+  const DalitzDef& d = *m->nodes[id].dz;
+  std::vector<cplx> a(d.n_amp()), c;
+  coeffs(d, th, c);
+  for (int64_t i = 0; i < n; ++i) {
+    re[i] = im[i] = 0.0;
+    if (!inside(d, s12[i], s13[i])) continue;
+    amplitudes(d, s12[i], s13[i], a.data());
+    cplx A = 0.0;
+    for (int k = 0; k < d.n_amp(); ++k) A += c[k] * a[k];
+    re[i] = A.real();
+    im[i] = A.imag();
   }
 }
 
 // Unsmeared (sigma_t -> 0) decay rate of a TDDP node at (s12, s13, t >= 0):
-// e^{-t/tau}[a_c cosh(y t/tau) + a_0 - ... ] written with the same a_c, a_0, a_s.
+// e^{-t/tau}[a_c cosh(y t/tau) + a_0 cos(x t/tau) + a_s sinh(y t/tau)
+// + b_s sin(x t/tau)] with the same a_c, a_0, a_s, b_s.
 void om_tddp_rate(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
                   const double* t, double* out, int n_threads) {
   const Node& nd = m->nodes[id];
   const DalitzDef& d = *nd.dz;
-  double tau = th[nd.p_tau], y = th[nd.p_y];
+  double tau = th[nd.p_tau], y = th[nd.p_y], x = nd.p_x >= 0 ? th[nd.p_x] : 0.0;
   int nt = n_threads > 0 ? n_threads : 1;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(nt)
@@ -740,8 +845,9 @@ void om_tddp_rate(Model* m, int id, const double* th, int64_t n, const double* s
       double Em = std::exp(-(1.0 - y) * t[i] / tau), Ep = std::exp(-(1.0 + y) * t[i] / tau);
       double E0 = std::exp(-t[i] / tau);
       double ac = 0.5 * (std::norm(A) + std::norm(Ab)), a0 = 0.5 * (std::norm(A) - std::norm(Ab));
-      double as = -(std::conj(A) * Ab).real();
-      out[i] = ac * 0.5 * (Em + Ep) + a0 * E0 + as * 0.5 * (Em - Ep);
+      cplx X = std::conj(A) * Ab;
+      out[i] = ac * 0.5 * (Em + Ep) + a0 * E0 * std::cos(x * t[i] / tau) - X.real() * 0.5 * (Em - Ep) -
+               X.imag() * E0 * std::sin(x * t[i] / tau);
     }
   }
 }
@@ -761,6 +867,7 @@ void om_res_amp(const double* kin, int ch, double m0, double g0, int J, double s
 }
 double om_econv(double t, double G, double s) { return econv(t, G, s); }
 double om_econv_dG(double t, double G, double s) { return econv_dG(t, G, s); }
+void om_econv_osc(double t, double G, double w, double s, double* out) { econv_osc(t, G, w, s, out); }
 double om_erfcx(double x) { return erfcx_pos(x); }
 double om_psi(double z) { return psi(z); }
 

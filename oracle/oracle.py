@@ -60,7 +60,7 @@ def lib():
                                 ip, dp, dp, ip, ip, ip]
         L.om_tddp.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
                               ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, ip, ip,
-                              ctypes.c_int, ctypes.c_int]
+                              ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.om_nll.restype = ctypes.c_double
         L.om_nll.argtypes = [vp, dp, ctypes.c_int64, ctypes.POINTER(dp), dp, ctypes.c_int]
         L.om_binned.restype = ctypes.c_double
@@ -73,7 +73,8 @@ def lib():
         L.om_dalitz_matrix.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp]
         L.om_dalitz_amp2.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp,
                                      ctypes.c_int, ctypes.c_int]
-        L.om_dalitz_cross.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp]
+        L.om_dalitz_cross.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, ctypes.c_int]
+        L.om_dalitz_amp.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, dp]
         L.om_tddp_rate.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int]
         L.om_inside.restype = ctypes.c_int
         L.om_inside.argtypes = [dp, ctypes.c_double, ctypes.c_double]
@@ -82,6 +83,7 @@ def lib():
         for f in ("om_econv", "om_econv_dG"):
             getattr(L, f).restype = ctypes.c_double
             getattr(L, f).argtypes = [ctypes.c_double] * 3
+        L.om_econv_osc.argtypes = [ctypes.c_double] * 4 + [dp]
         for f in ("om_erfcx", "om_psi"):
             getattr(L, f).restype = ctypes.c_double
             getattr(L, f).argtypes = [ctypes.c_double]
@@ -165,9 +167,12 @@ class Model:
                 nid = L.om_dalitz(self._h, obs[0], obs[1], _dp(kin), int(dz["grid"]), len(res), chp,
                                   _dp(m0), _dp(g0), Jp, prep, pimp)
             else:
+                # parameters: 2R coefficients, tau, y and optionally x
+                R = len(res)
+                p_x = self._p(names[2 * R + 2]) if len(names) == 2 * R + 3 else -1
                 nid = L.om_tddp(self._h, obs[0], obs[1], obs[2], obs[3], _dp(kin), int(dz["grid"]),
-                                len(res), chp, _dp(m0), _dp(g0), Jp, prep, pimp,
-                                self._p(names[-2]), self._p(names[-1]))
+                                R, chp, _dp(m0), _dp(g0), Jp, prep, pimp,
+                                self._p(names[2 * R]), self._p(names[2 * R + 1]), p_x)
         else:
             raise ValueError(op)
         self.node_ids.append((nid, node))
@@ -264,15 +269,26 @@ class Model:
                              n_threads or n_threads_default())
         return out
 
-    def dalitz_cross(self, theta, s12, s13):
-        """Re(conj(A) Abar) at each point (0 outside the Dalitz plot)."""
+    def dalitz_cross(self, theta, s12, s13, imag=False):
+        """Re(conj(A) Abar) (Im with imag=True) at each point (0 outside the
+        Dalitz plot)."""
         nid, _ = self.dalitz_node()
         th = np.ascontiguousarray(theta, dtype=np.float64)
         a = np.ascontiguousarray(s12, dtype=np.float64)
         b = np.ascontiguousarray(s13, dtype=np.float64)
         out = np.empty(a.size)
-        lib().om_dalitz_cross(self._h, nid, _dp(th), a.size, _dp(a), _dp(b), _dp(out))
+        lib().om_dalitz_cross(self._h, nid, _dp(th), a.size, _dp(a), _dp(b), _dp(out), int(imag))
         return out
+
+    def dalitz_amp(self, theta, s12, s13):
+        """The coherent amplitude sum A(s12, s13) (complex; 0 outside)."""
+        nid, _ = self.dalitz_node()
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        a = np.ascontiguousarray(s12, dtype=np.float64)
+        b = np.ascontiguousarray(s13, dtype=np.float64)
+        re, im = np.empty(a.size), np.empty(a.size)
+        lib().om_dalitz_amp(self._h, nid, _dp(th), a.size, _dp(a), _dp(b), _dp(re), _dp(im))
+        return re + 1j * im
 
     def tddp_rate(self, theta, s12, s13, t, n_threads=None):
         nid, _ = self.dalitz_node()
@@ -388,6 +404,14 @@ def econv(t, G, s):
 
 def econv_dG(t, G, s):
     return lib().om_econv_dG(t, G, s)
+
+
+def econv_osc(t, G, w, s):
+    """(Cz, Sz, dCz/dG, dSz/dG, dCz/dw, dSz/dw): the Gaussian-resolution
+    convolutions of e^{-G t} cos(w t) and e^{-G t} sin(w t) by quadrature."""
+    out = np.empty(6)
+    lib().om_econv_osc(t, G, w, s, _dp(out))
+    return out
 
 
 def erfcx(x):

@@ -19,7 +19,7 @@ Unbounded parameters use lo = hi = 0.
 import math
 
 __all__ = [
-    "C1", "C2", "C3", "C4", "C5", "LISTING2", "DALITZ_KINEMATICS", "RESONANCES",
+    "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -161,6 +161,25 @@ C4 = {
     "seed": 4,
 }
 
+# ---------------------------------------------------------------- C4X
+# C4 with the mixing parameter x free as well: the trigonometric time terms
+# (cos / sin (x t / tau) convolved with the resolution) join the hyperbolic
+# ones.  The parameter vector ends tau, y, x.
+C4X = {
+    "name": "c4x_tddp_mixing",
+    "obs": C4["obs"],
+    "params": C4["params"] + [("x", 0.0, 0.005, -0.2, 0.2, False)],
+    "truth": dict(C4["truth"], x=0.008),
+    "model": {
+        "op": "tddp", "obs": ["s12", "s13", "t", "sigma_t"],
+        "par": dalitz_param_names() + ["tau", "y", "x"],
+        "dalitz": dict(DALITZ_KINEMATICS, resonances=_RES_SPEC),
+    },
+    "sigma_t_range": C4["sigma_t_range"],
+    "n_events": 2_000_000,
+    "seed": 6,
+}
+
 # ---------------------------------------------------------------- C5
 # Stream of toy fits of the C1 model with uneven event counts.
 C5 = {
@@ -191,4 +210,4 @@ LISTING2 = {
 
 
 def workload(name):
-    return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "listing2": LISTING2}[name]
+    return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2}[name]

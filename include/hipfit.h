@@ -80,13 +80,15 @@ enum hf_op {
                         obs = {s12, s13}; par = {Re c_1, Im c_1, ..., Re c_R, Im c_R};
                         consts = DALITZ block (below)                                       */
   HF_OP_TDDP = 7     /* time-dependent Dalitz density with per-event Gaussian resolution:
-                        [a_c C(t) + a_0 E(t; 1/tau) + a_s S(t)] / N_T, where
+                        [a_c C(t) + a_0 Cz(t) + a_s S(t) + b_s Sz(t)] / N_T, where
                         a_c = (|A|^2+|Abar|^2)/2, a_0 = (|A|^2-|Abar|^2)/2, a_s = -Re(A* Abar),
-                        Abar(s12,s13) = A(s13,s12), C/S = (E(G-) +/- E(G+))/2,
-                        G-/+ = (1 -/+ y)/tau and E(t; G, sigma_t) the Gaussian-convolved
-                        decay e^{-G t}; t is normalised over the real line;
-                        obs = {s12, s13, t, sigma_t}; par = {Re c_1, Im c_1, ..., tau, y};
-                        consts = DALITZ block                                              */
+                        b_s = -Im(A* Abar), Abar(s12,s13) = A(s13,s12), C/S = (E(G-) +/- E(G+))/2,
+                        G-/+ = (1 -/+ y)/tau, E(t; G, sigma_t) the Gaussian-convolved decay
+                        e^{-G t}, and Cz + i Sz the Gaussian-convolved e^{-t/tau} e^{i x t/tau}
+                        (section "Results": hyperbolic and trigonometric terms); t is
+                        normalised over the real line; obs = {s12, s13, t, sigma_t};
+                        par = {Re c_1, Im c_1, ..., tau, y} (x = 0: Cz = E(t; 1/tau), Sz = 0)
+                        or {..., tau, y, x}; consts = DALITZ block                          */
 };
 
 /* DALITZ block of node constants:

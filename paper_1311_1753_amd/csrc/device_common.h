@@ -5,6 +5,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "faddeeva_coef.h"
 #include "internal.h"
 
 namespace hf {
@@ -279,6 +280,58 @@ __device__ __forceinline__ void econv(T t, T s, T G, T g, T& E, T& dE) {
     E = Mth<T>::ex(T(0.5) * G * G * s * s - G * t) - half;
   }
   dE = a * E - s * g * T(0.39894228040143268);
+}
+
+// Faddeeva function w(z) = exp(-z^2) erfc(-i z) for Im z >= 0 by Weideman's
+// rational series in Z = (L + i z)/(L - i z) (coefficients and reference in
+// faddeeva_coef.h; about 1e-14 relative in the upper half plane).
+__device__ __forceinline__ Cx<double> faddeeva_uhp(Cx<double> z) {
+  const double L = kFaddeevaL;
+  // i z = (-Im z, Re z); den = L - i z, num = L + i z
+  const double dre = L + z.im, dim = -z.re;
+  const double nre = L - z.im, nim = z.re;
+  const double r = 1.0 / (dre * dre + dim * dim);
+  const Cx<double> rd = {dre * r, -dim * r};  // 1 / (L - i z)
+  const Cx<double> Z = cmul(Cx<double>{nre, nim}, rd);
+  Cx<double> p = {kFaddeevaA[0], 0.0};
+#pragma unroll
+  for (int n = 1; n < kFaddeevaN; ++n) {
+    const Cx<double> q = cmul(p, Z);
+    p = {q.re + kFaddeevaA[n], q.im};
+  }
+  const Cx<double> rd2 = cmul(rd, rd);
+  const Cx<double> t = cmul(p, rd2);
+  const double c = 0.56418958354775628;  // 1/sqrt(pi)
+  return {2.0 * t.re + c * rd.re, 2.0 * t.im + c * rd.im};
+}
+
+// Gaussian-resolution convolution of e^{-z t} with complex z = G - i W
+// (G > 0): its real part convolves e^{-G t} cos(W t), its imaginary part
+// e^{-G t} sin(W t).  With xi = (z s^2 - t)/(sqrt2 s) and g = e^{-t^2/(2 s^2)}:
+//   Re xi > 0 : E = g w(i xi) / 2
+//   otherwise : E = e^{z^2 s^2/2 - z t} - g w(-i xi) / 2   (erfc(v) = 2 - erfc(-v))
+//   dE/dz = (z s^2 - t) E - s g / sqrt(2 pi)
+// The Faddeeva argument is in the upper half plane on both branches.
+__device__ __forceinline__ void econv_c(double t, double s, double G, double W, double g, Cx<double>& E,
+                                        Cx<double>& dE) {
+  const double k = 0.70710678118654752 / s;
+  const Cx<double> a = {G * s * s - t, -W * s * s};  // z s^2 - t
+  const Cx<double> xi = {a.re * k, a.im * k};
+  const bool pos = xi.re > 0.0;
+  // i xi = (-Im xi, Re xi), -i xi = (Im xi, -Re xi)
+  const Cx<double> arg = pos ? Cx<double>{-xi.im, xi.re} : Cx<double>{xi.im, -xi.re};
+  const Cx<double> wv = faddeeva_uhp(arg);
+  E = {0.5 * g * wv.re, 0.5 * g * wv.im};
+  if (!pos) {
+    // exponent z^2 s^2/2 - z t = (G^2 - W^2) s^2/2 - G t + i (W t - G W s^2)
+    const double er = 0.5 * (G * G - W * W) * s * s - G * t, ei = W * t - G * W * s * s;
+    const double m = ::exp(er);
+    double sn, cn;
+    ::sincos(ei, &sn, &cn);
+    E = {m * cn - E.re, m * sn - E.im};
+  }
+  const Cx<double> aE = cmul(a, E);
+  dE = {aE.re - s * g * 0.39894228040143268, aE.im};
 }
 
 }  // namespace hf

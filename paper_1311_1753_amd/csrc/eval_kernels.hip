@@ -140,15 +140,19 @@ __device__ __forceinline__ void leaf_dalitz(const CS& cs, const KNode& nd, bool 
   }
 }
 
-// TDDP: ln [a_c C + a_0 E0 + a_s S] for E events at once; slot derivatives
-// (coefficients, then tau, y) go to emit(slot, values[E]), the coefficients'
-// first over all kMaxRes places as for DALITZ, then tau and y to slots 2R and
-// 2R + 1 (after any zero emitted there).
-template <typename T, int E, class Emit>
+// TDDP: ln [a_c C + a_0 Cz + a_s S + b_s Sz] for E events at once, with
+// b_s = -Im(conj(A) Abar) and Cz + i Sz the resolution-convolved
+// e^{-t/tau} e^{i x t/tau} (without x: Cz = E(t; 1/tau), Sz = 0); slot
+// derivatives (coefficients, then tau, y and, with x, x) go to emit(slot,
+// values[E]), the coefficients' first over all kMaxRes places as for DALITZ,
+// then tau, y (, x) to slots 2R, 2R + 1 (, 2R + 2) after any zero emitted
+// there.
+template <typename T, int E, bool HX, class Emit>
 __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool hoisted, const double (&x12)[E],
                                           const double (&x13)[E], const double (&xt)[E], const double (&xs)[E],
                                           T (&lv)[E], const Emit& emit) {
   const int c0 = nd.c0, R = nd.aux;
+  constexpr bool hx = HX;  // x free: trigonometric terms (the node has 2R + 3 slots)
   double s12[E], s13[E], s23[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -162,7 +166,7 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
   const int cb = c0 + dz_coef_base(R, true);
   const int tb = c0 + dz_time_base(R);
   Cx<T> S[E], Sb[E];
-  T cc[E], cb_[E], St[E], iR[E], dtau[E], dy[E];
+  T cc[E], cb_[E], St[E], Sz[E], iR[E], dtau[E], dy[E], dx[E];
   static_for<E>([&](auto ei) {
     constexpr int e = decltype(ei)::value;
     const AmpArr<T>& ae = pick<e>(a0, a1);
@@ -180,34 +184,61 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
     const T nA = S[e].re * S[e].re + S[e].im * S[e].im;
     const T nB = Sb[e].re * Sb[e].re + Sb[e].im * Sb[e].im;
     const T as = -(S[e].re * Sb[e].re + S[e].im * Sb[e].im);  // -Re(conj(A) Abar)
+    const T bs = -(S[e].re * Sb[e].im - S[e].im * Sb[e].re);  // -Im(conj(A) Abar)
     // Decay-time factors, formed in double: C - E(1/tau), S and the tau / y
     // derivative combinations are small differences of nearly equal terms
     // (|y| << 1), and rounding them in float would bias every event the
     // same way.
     const double t = xt[e], s = xs[e];
     const double g = ::exp(-0.5 * t * t / (s * s));
-    double Em, dEm, Ep, dEp, E0, dE0;
+    double Em, dEm, Ep, dEp;
     econv<double>(t, s, cs.d[tb + kTdGm], g, Em, dEm);
     econv<double>(t, s, cs.d[tb + kTdGp], g, Ep, dEp);
-    econv<double>(t, s, cs.d[tb + kTdG], g, E0, dE0);
+    // trigonometric pair Cz, Sz and their tau and x derivatives
+    double Cz, Szd = 0.0, Cz_tau, Sz_tau = 0.0, Cz_x = 0.0, Sz_x = 0.0;
+    if (hx) {
+      Cx<double> Ez, dEz;
+      econv_c(t, s, cs.d[tb + kTdG], cs.d[tb + kTdW], g, Ez, dEz);
+      Cz = Ez.re;
+      Szd = Ez.im;
+      // z = G - i W: dz/dtau = dG/dtau - i dW/dtau, dz/dx = -i dW/dx
+      const double gt = cs.d[tb + kTdDGTau], wt = cs.d[tb + kTdDWTau], wx = cs.d[tb + kTdDWX];
+      Cz_tau = dEz.re * gt + dEz.im * wt;
+      Sz_tau = dEz.im * gt - dEz.re * wt;
+      Cz_x = dEz.im * wx;
+      Sz_x = -dEz.re * wx;
+    } else {
+      double dE0;
+      econv<double>(t, s, cs.d[tb + kTdG], g, Cz, dE0);
+      Cz_tau = dE0 * cs.d[tb + kTdDGTau];
+    }
     const double Cd = 0.5 * (Em + Ep);
     const double Tm = dEm * cs.d[tb + kTdDGmTau], Tp = dEp * cs.d[tb + kTdDGpTau];
-    const double T1 = 0.5 * (Tm + Tp), T0 = dE0 * cs.d[tb + kTdDGTau];
+    const double T1 = 0.5 * (Tm + Tp);
     const double Ym = dEm * cs.d[tb + kTdDGmY], Yp = dEp * cs.d[tb + kTdDGpY];
-    cc[e] = (T)(Cd + E0);          // d R / d(|A|^2 / 2)
-    cb_[e] = (T)(Cd - E0);         // d R / d(|Abar|^2 / 2)
+    cc[e] = (T)(Cd + Cz);          // d R / d(|A|^2 / 2)
+    cb_[e] = (T)(Cd - Cz);         // d R / d(|Abar|^2 / 2)
     St[e] = (T)(0.5 * (Em - Ep));  // S(t)
-    const T tA = (T)(T1 + T0), tB = (T)(T1 - T0), tS = (T)(0.5 * (Tm - Tp));
+    Sz[e] = (T)Szd;
+    const T tA = (T)(T1 + Cz_tau), tB = (T)(T1 - Cz_tau), tS = (T)(0.5 * (Tm - Tp)), tZ = (T)Sz_tau;
     const T yAB = (T)(0.5 * (Ym + Yp)), yS = (T)(0.5 * (Ym - Yp));
-    // rate = a_c C + a_0 E0 + a_s S = |A|^2 (C + E0)/2 + |Abar|^2 (C - E0)/2 + a_s S
-    const T Rv = T(0.5) * nA * cc[e] + T(0.5) * nB * cb_[e] + as * St[e];
+    // rate = a_c C + a_0 Cz + a_s S + b_s Sz
+    //      = |A|^2 (C + Cz)/2 + |Abar|^2 (C - Cz)/2 + a_s S + b_s Sz
+    T Rv = T(0.5) * nA * cc[e] + T(0.5) * nB * cb_[e] + as * St[e];
+    T rt = T(0.5) * nA * tA + T(0.5) * nB * tB + as * tS;
+    if (hx) {
+      Rv += bs * Sz[e];
+      rt += bs * tZ;
+    }
     iR[e] = Mth<T>::rcp(Rv);
     lv[e] = Rv > T(0) ? Mth<T>::ln(Rv) : T(-INFINITY);
-    dtau[e] = (T(0.5) * nA * tA + T(0.5) * nB * tB + as * tS) * iR[e];
+    dtau[e] = rt * iR[e];
     dy[e] = (T(0.5) * (nA + nB) * yAB + as * yS) * iR[e];
+    dx[e] = hx ? (T(0.5) * (nA - nB) * (T)Cz_x + bs * (T)Sz_x) * iR[e] : T(0);
     if (!hoisted) {
       dtau[e] -= cs.get<T>(c0 + kDzDln + 2 * R);
       dy[e] -= cs.get<T>(c0 + kDzDln + 2 * R + 1);
+      dx[e] -= cs.get<T>(c0 + kDzDln + 2 * R + 2);
       lv[e] = (lv[e] - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
     }
   });
@@ -228,8 +259,12 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
       const T x1_im = ar * Sb[e].im - ai * Sb[e].re;  // Im(conj(A_k) Sb)
       const T x2_re = S[e].re * br + S[e].im * bi;    // Re(conj(S) Ab_k)
       const T x2_im = S[e].re * bi - S[e].im * br;    // Im(conj(S) Ab_k)
-      const T dR_re = cc[e] * pA_re + cb_[e] * pB_re - (x1_re + x2_re) * St[e];
-      const T dR_im = -cc[e] * pA_im - cb_[e] * pB_im - (x1_im - x2_im) * St[e];
+      T dR_re = cc[e] * pA_re + cb_[e] * pB_re - (x1_re + x2_re) * St[e];
+      T dR_im = -cc[e] * pA_im - cb_[e] * pB_im - (x1_im - x2_im) * St[e];
+      if (hx) {
+        dR_re -= (x1_im + x2_im) * Sz[e];
+        dR_im += (x1_re - x2_re) * Sz[e];
+      }
       d_re[e] = dR_re * iR[e];
       d_im[e] = dR_im * iR[e];
       if (!hoisted && k < R) {
@@ -242,6 +277,7 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
   }
   emit(2 * R, dtau);
   emit(2 * R + 1, dy);
+  if (hx) emit(2 * R + 2, dx);
 }
 
 // ------------------------------------------------------------------ cross-lane sums
@@ -587,6 +623,11 @@ struct LightLeafEv {  // single EXP / GAUSS leaf
   }
 };
 
+// Kernel variant of OP_TDDP with the trigonometric terms (x free): a
+// compile-time choice, so that the x = 0 kernel carries none of their
+// registers.
+constexpr int OP_TDDP_X = 8;
+
 // Events per thread and step of the single-leaf amplitude kernels: the E
 // events share every read of a resonance's constants and every loop step,
 // and give the wave E independent instruction chains.
@@ -635,7 +676,8 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
           leaf_dalitz<T, 1>(cs, nd, h, x12, x13, l1, emit);
         } else {
           const double xt[1] = {xe[nd.col[2]]}, xs[1] = {xe[nd.col[3]]};
-          leaf_tddp<T, 1>(cs, nd, h, x12, x13, xt, xs, l1, emit);
+          if (nd.n_slot == 2 * nd.aux + 3) leaf_tddp<T, 1, true>(cs, nd, h, x12, x13, xt, xs, l1, emit);
+          else leaf_tddp<T, 1, false>(cs, nd, h, x12, x13, xt, xs, l1, emit);
         }
         v = l1[0];
       } else if (op == OP_PROD) {
@@ -789,7 +831,7 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
   typedef typename Col<T>::S Sx;
   constexpr int E = AmpEvents<T, OP>::value;
   constexpr int NCOL = OP == OP_DALITZ ? 2 : 4;
-  constexpr int NS = OP == OP_DALITZ ? 2 * kMaxRes : 2 * kMaxRes + 2;
+  constexpr int NS = OP == OP_DALITZ ? 2 * kMaxRes : (OP == OP_TDDP ? 2 * kMaxRes + 2 : 2 * kMaxRes + 3);
   constexpr int NC = 1 + NS;
   const KNode& nd = P.node[0];
   // slot columns: 2R coefficient derivatives (+ tau, y); zero derivatives
@@ -842,7 +884,7 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
     };
     T lv[E];
     if constexpr (OP == OP_DALITZ) leaf_dalitz<T, E>(cs, nd, true, x[0], x[1], lv, emit);
-    else leaf_tddp<T, E>(cs, nd, true, x[0], x[1], x[2], x[3], lv, emit);
+    else leaf_tddp<T, E, OP == OP_TDDP_X>(cs, nd, true, x[0], x[1], x[2], x[3], lv, emit);
     acc.add(0, -sum(lv));
   }
   row_store_acc<NC>(acc, 1 + n_slots, out, n_rows);
@@ -965,6 +1007,7 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_one(const FitRec fr) { red
 // resident; the others fit as they are).
 template <typename T, int OP> struct LeafWaves { static constexpr int value = 1; };
 template <> struct LeafWaves<float, OP_TDDP> { static constexpr int value = 3; };
+template <> struct LeafWaves<float, OP_TDDP_X> { static constexpr int value = 3; };
 
 template <typename T, int OP, bool GRAD>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LeafWaves<T, OP>::value)))
@@ -1087,6 +1130,7 @@ static const void* kernel_of(int kind) {
     case KIND_TREE_SMALL: return (const void*)&k_tree<T, 8, 2, false, GRAD>;
     case KIND_DALITZ: return (const void*)&k_leaf<T, OP_DALITZ, GRAD>;
     case KIND_TDDP: return (const void*)&k_leaf<T, OP_TDDP, GRAD>;
+    case KIND_TDDPX: return (const void*)&k_leaf<T, OP_TDDP_X, GRAD>;
     case KIND_TREE: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, true, GRAD>;
     default: return nullptr;  // mixtures: light, never below kRowsPerCU
   }
@@ -1116,6 +1160,7 @@ static hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st, hipEve
     case KIND_TREE_SMALL: hipExtLaunchKernelGGL((k_tree<T, 8, 2, false, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_DALITZ: hipExtLaunchKernelGGL((k_leaf<T, OP_DALITZ, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDP: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TDDPX: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_X, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TREE:
       hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, e0, e1, 0, a);
       break;
@@ -1165,6 +1210,7 @@ static hipError_t launch_b(int kind, const BatchArgs& a, int grid, hipStream_t s
     case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree_batched<T, 8, 2, false>), g, b, 0, st, a); break;
     case KIND_DALITZ: hipLaunchKernelGGL((k_leaf_batched<T, OP_DALITZ>), g, b, 0, st, a); break;
     case KIND_TDDP: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP>), g, b, 0, st, a); break;
+    case KIND_TDDPX: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_X>), g, b, 0, st, a); break;
     case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, true>), g, b, 0, st, a); break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \

@@ -171,6 +171,29 @@ double herm_form(const std::vector<double>& Mf, const std::vector<cd>& c, std::v
   return tot.real();
 }
 
+// Im(c^H M c) and its gradient with respect to (Re c_k, Im c_k), k >= 1.
+double herm_form_im(const std::vector<double>& Mf, const std::vector<cd>& c, std::vector<double>& dre,
+                    std::vector<double>& dim) {
+  const int na = (int)c.size();
+  auto M = [&](int p, int q) { return cd(Mf[2 * (p * na + q)], Mf[2 * (p * na + q) + 1]); };
+  cd tot = 0.0;
+  std::vector<cd> left(na, 0.0), right(na, 0.0);
+  for (int p = 0; p < na; ++p)
+    for (int q = 0; q < na; ++q) {
+      const cd m = M(p, q);
+      tot += std::conj(c[p]) * m * c[q];
+      left[q] += std::conj(c[p]) * m;
+      right[p] += m * c[q];
+    }
+  dre.assign(na, 0.0);
+  dim.assign(na, 0.0);
+  for (int k = 1; k < na; ++k) {
+    dre[k] = (left[k] + right[k]).imag();
+    dim[k] = (cd(0.0, 1.0) * (left[k] - right[k])).imag();
+  }
+  return tot.imag();
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ results
@@ -406,29 +429,36 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
             dv.push_back({nd.par[2 * j + 1], dim[j + 1] / N});
           }
         } else {
-          const double tau = th[nd.par[2 * R]], y = th[nd.par[2 * R + 1]];
+          // parameters: 2R coefficients, tau, y and (optionally) x
+          const bool hx = (int)nd.par.size() == 2 * R + 3;
+          const double tau = th[nd.par[2 * R]], y = th[nd.par[2 * R + 1]], x = hx ? th[nd.par[2 * R + 2]] : 0.0;
           if (!(tau > 0.0) || !(std::fabs(y) < 1.0)) sc.ok = false;
-          std::vector<double> aR, aI, bR, bI, jR, jI;
+          std::vector<double> aR, aI, bR, bI, jR, jI, kR, kI;
           const double IA = herm_form(dz.I, c, aR, aI);
           const double IB = herm_form(dz.Ib, c, bR, bI);
-          const double X = herm_form(dz.J, c, jR, jI);  // Re c^H J c
+          const double X = herm_form(dz.J, c, jR, jI);     // Re c^H J c
+          const double Y = herm_form_im(dz.J, c, kR, kI);  // Im c^H J c
           // time integrals over the real line: int C = tau/(1-y^2),
-          // int E(1/tau) = tau, int S = y tau/(1-y^2)
-          const double den = 1.0 - y * y;
-          const double kc = tau / den, k0 = tau, ks = y * tau / den;
-          const double N = 0.5 * (IA + IB) * kc + 0.5 * (IA - IB) * k0 - X * ks;
+          // int S = y tau/(1-y^2), int Cz = tau/(1+x^2), int Sz = x tau/(1+x^2)
+          const double den = 1.0 - y * y, opx = 1.0 + x * x;
+          const double kc = tau / den, ks = y * tau / den, kz = tau / opx, kzs = x * tau / opx;
+          const double N = 0.5 * (IA + IB) * kc + 0.5 * (IA - IB) * kz - X * ks - Y * kzs;
           if (!(N > 0.0)) sc.ok = false;
           lnN = std::log(N);
           for (int j = 1; j <= R; ++j) {
-            const double dr = 0.5 * (aR[j] + bR[j]) * kc + 0.5 * (aR[j] - bR[j]) * k0 - jR[j] * ks;
-            const double di = 0.5 * (aI[j] + bI[j]) * kc + 0.5 * (aI[j] - bI[j]) * k0 - jI[j] * ks;
+            const double dr = 0.5 * (aR[j] + bR[j]) * kc + 0.5 * (aR[j] - bR[j]) * kz - jR[j] * ks - kR[j] * kzs;
+            const double di = 0.5 * (aI[j] + bI[j]) * kc + 0.5 * (aI[j] - bI[j]) * kz - jI[j] * ks - kI[j] * kzs;
             dv.push_back({nd.par[2 * j - 2], dr / N});
             dv.push_back({nd.par[2 * j - 1], di / N});
           }
-          const double dtau = 0.5 * (IA + IB) / den + 0.5 * (IA - IB) - X * y / den;
+          const double dtau = 0.5 * (IA + IB) / den + 0.5 * (IA - IB) / opx - X * y / den - Y * x / opx;
           const double dy = 0.5 * (IA + IB) * tau * 2.0 * y / (den * den) - X * tau * (1.0 + y * y) / (den * den);
           dv.push_back({nd.par[2 * R], dtau / N});
           dv.push_back({nd.par[2 * R + 1], dy / N});
+          if (hx) {
+            const double dx = -0.5 * (IA - IB) * tau * 2.0 * x / (opx * opx) - Y * tau * (1.0 - x * x) / (opx * opx);
+            dv.push_back({nd.par[2 * R + 2], dx / N});
+          }
           const int tb = c0 + dz_time_base(R);
           setc(tb + kTdGm, (1.0 - y) / tau);
           setc(tb + kTdGp, (1.0 + y) / tau);
@@ -438,6 +468,9 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
           setc(tb + kTdDGTau, -1.0 / (tau * tau));
           setc(tb + kTdDGmY, -1.0 / tau);
           setc(tb + kTdDGpY, 1.0 / tau);
+          setc(tb + kTdW, x / tau);
+          setc(tb + kTdDWTau, -x / (tau * tau));
+          setc(tb + kTdDWX, hx ? 1.0 / tau : 0.0);
         }
         norm_terms(lnN, dv, c0 + kDzLnHi, c0 + kDzLnLo, c0 + kDzDln);
         break;
@@ -576,7 +609,9 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
           if (rc) break;
           const int R = (int)ni.consts[6];
           rc = need(R >= 1 && R <= kMaxRes && n.n_const == 7 + 4 * R, "Dalitz: 1..8 resonances, 7 + 4R constants");
-          if (!rc) rc = need(n.n_par == 2 * R + (td ? 2 : 0), "Dalitz: 2R (+tau, y) parameters");
+          if (!rc)
+            rc = need(td ? (n.n_par == 2 * R + 2 || n.n_par == 2 * R + 3) : n.n_par == 2 * R,
+                      "Dalitz: 2R parameters; time-dependent: 2R + tau, y (+ x)");
           if (!rc) rc = need(n.n_obs == (td ? 4 : 2), "Dalitz: observables (s12, s13[, t, sigma_t])");
           if (!rc) rc = need(finite_box(ni.obs[0]) && finite_box(ni.obs[1]), "Dalitz: s12, s13 need finite boxes");
           if (rc) break;
@@ -756,13 +791,13 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     g->slot_par_tree = g->slot_par;
     g->n_slots_tree = P.n_slots;
     // parameters that the float path sees rounded to float (through 1/sigma,
-    // fractions, rates, coefficients); Gaussian means and the decay time and
-    // width difference of the time-dependent density enter through double
-    // differences only
+    // fractions, rates, coefficients); Gaussian means and the decay time,
+    // width and mass differences of the time-dependent density enter through
+    // double constants only
     g->par_rounded.assign(g->par.size(), false);
     for (const NodeInfo& n : g->nodes)
       for (size_t j = 0; j < n.par.size(); ++j) {
-        const bool exact = (n.op == OP_GAUSS && j == 0) || (n.op == OP_TDDP && j + 2 >= n.par.size());
+        const bool exact = (n.op == OP_GAUSS && j == 0) || (n.op == OP_TDDP && j >= 2 * (size_t)n.consts[6]);
         if (!exact) g->par_rounded[n.par[j]] = true;
       }
     // kernel family
@@ -793,7 +828,8 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     if (NN == 1 && rootn.op == OP_EXP) g->kind = KIND_EXP;
     else if (NN == 1 && rootn.op == OP_GAUSS) g->kind = KIND_GAUSS;
     else if (NN == 1 && rootn.op == OP_DALITZ) g->kind = KIND_DALITZ;
-    else if (NN == 1 && rootn.op == OP_TDDP) g->kind = KIND_TDDP;
+    else if (NN == 1 && rootn.op == OP_TDDP)
+      g->kind = (int)rootn.par.size() == 2 * (int)rootn.consts[6] + 3 ? KIND_TDDPX : KIND_TDDP;
     else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2 && NN <= 8) g->kind = KIND_TREE_SMALL;
     else g->kind = KIND_TREE;
     *out = g.release();

@@ -70,11 +70,16 @@ constexpr int kChThrP = 0, kChThrM = 1, kChZc1 = 2, kChZtaC = 3, kChZtaD = 4, kC
 // group order of KNode::res_end: m0^2, Kw B0^2 (B0 = the barrier polynomial's
 // square root at q0, 1 for J = 0), B0
 constexpr int kResM02 = 0, kResKwB = 1, kResSqB = 2, kResStride = 3;
-// TDDP time constants after the coefficients
+// TDDP time constants after the coefficients: the decay rates G-/+ = (1 -/+ y)/tau
+// and G = 1/tau with their tau and y derivatives, and the oscillation
+// frequency W = x/tau of the trigonometric terms with its tau and x
+// derivatives (zero without x)
 constexpr int kTdGm = 0, kTdGp = 1, kTdG = 2, kTdDGmTau = 3, kTdDGpTau = 4, kTdDGTau = 5,
-              kTdDGmY = 6, kTdDGpY = 7, kTdCount = 8;
+              kTdDGmY = 6, kTdDGpY = 7, kTdW = 8, kTdDWTau = 9, kTdDWX = 10, kTdCount = 11;
 
-constexpr int dz_n_dln(int R, bool tddp) { return 2 * R + (tddp ? 2 : 0); }
+// dlnN entries: 2R coefficients (+ tau, y, x for TDDP; the x entry stays
+// unused without x)
+constexpr int dz_n_dln(int R, bool tddp) { return 2 * R + (tddp ? 3 : 0); }
 constexpr int dz_ch_base(int R, bool tddp) { return kDzDln + dz_n_dln(R, tddp); }
 constexpr int dz_res_base(int R, bool tddp) { return dz_ch_base(R, tddp) + kNumCh * kChStride; }
 // the coefficient block always has room for kMaxRes coefficients; those of

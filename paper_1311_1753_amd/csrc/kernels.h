@@ -14,6 +14,7 @@ enum KernelKind {
   KIND_DALITZ = 3,      // single DALITZ leaf
   KIND_TDDP = 4,        // single TDDP leaf
   KIND_TREE = 5,        // any tree
+  KIND_TDDPX = 6,       // single TDDP leaf with x free (trigonometric terms)
   // root ADD of 2 (3) single-column EXP/GAUSS leaves: KIND_MIX2 (KIND_MIX3)
   // plus a mask with bit j set when child j is a GAUSS
   KIND_MIX2 = 8,

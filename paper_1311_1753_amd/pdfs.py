@@ -165,10 +165,11 @@ class DalitzPdf(GooPdf):
 
 
 class TddpPdf(GooPdf):
-    """Time-dependent Dalitz density with per-event Gaussian resolution."""
+    """Time-dependent Dalitz density with per-event Gaussian resolution
+    (mixing parameters y and, when given, x: the trigonometric terms)."""
 
-    def __init__(self, name, s12, s13, t, sigma_t, coefficients, tau, y, kinematics):
-        flat = [v for pair in coefficients for v in pair] + [tau, y]
+    def __init__(self, name, s12, s13, t, sigma_t, coefficients, tau, y, kinematics, x=None):
+        flat = [v for pair in coefficients for v in pair] + [tau, y] + ([x] if x is not None else [])
         super().__init__(name, "tddp", [s12, s13, t, sigma_t], flat, extra={"dalitz": dict(kinematics)})
 
 

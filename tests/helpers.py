@@ -37,7 +37,7 @@ def gen_data(name, n, seed):
     if name == "poly":
         rng = np.random.default_rng(seed)
         return {"x": rng.uniform(-1.0, 3.0, n)}
-    if name in ("c3", "c4"):
+    if name in ("c3", "c4", "c4x"):
         m = oracle_model(name)
         th = m.theta(S.workload(name)["truth"])
         lo, hi = S.dalitz_box()
@@ -50,8 +50,9 @@ def gen_data(name, n, seed):
                                               batch=1 << 18)
         a2 = m.dalitz_amp2(th, a.ravel(), b.ravel())
         b2 = m.dalitz_amp2(th, a.ravel(), b.ravel(), swapped=True)
-        env = 1.3 * (a2 + b2).max()
-        tau, y = th[-2], th[-1]
+        # the rate over e^{-(1-|y|) t/tau} is at most (1 + 1/sqrt2)(|A|^2 + |Abar|^2)
+        env = (1.3 if name == "c4" else 1.8) * (a2 + b2).max()
+        tau, y = (th[-2], th[-1]) if name == "c4" else (th[-3], th[-2])
         return S.gen_accept_reject_tddp(n, seed, lambda x, yy, t: m.tddp_rate(th, x, yy, t), env, tau, y,
                                         batch=1 << 18)
     raise ValueError(name)

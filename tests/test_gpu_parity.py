@@ -27,6 +27,7 @@ CASES = [
     ("poly", 30_003, 14),
     ("c3", 20_037, 15),
     ("c4", 20_041, 16),
+    ("c4x", 20_043, 17),
 ]
 
 

@@ -281,10 +281,12 @@ int hf_dalitz_inside(const pdf_graph* g, int32_t node, int64_t n, const double* 
 /* Kernel timing for measurement: enable = k >= 1 resets the counters and
  * starts timing the likelihood kernel and the reduction of every k-th
  * nll_eval / nll_grad with HIP events that take the dispatches' own start and
- * end time stamps (those calls wait with hipStreamSynchronize instead of the
- * completion flag); enable = 0 stops; a negative value only reads.  Outputs (nullable): total milliseconds of the likelihood
- * kernels and of the reductions, and the number of timed calls so far.  Not
- * for concurrent use from several threads. */
+ * end time stamps (those calls wait on the completion flag as usual; their
+ * time stamps are read at the next timed call or by the next hf_profile
+ * call); enable = 0 stops; a negative value only reads.  Outputs (nullable):
+ * total milliseconds of the likelihood kernels and of the reductions, and the
+ * number of timed calls so far (all complete when read).  Not for concurrent
+ * use from several threads. */
 int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch);
 /* Last error message of the calling thread ("" if none). */
 const char* hf_last_error(void);

@@ -33,10 +33,14 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Optional kernel timing (hf_profile): HIP events that take the start and
 // end time stamps of the likelihood kernel's and the reduction's dispatches
-// (hipExtLaunchKernel) of every `every`-th eval_one.
+// (hipExtLaunchKernel) of every `every`-th eval_one.  The evaluation itself
+// waits as usual (on the completion flag); its time stamps are read at the
+// next profiled evaluation or when the profile is read, by when they are
+// complete, so profiling adds no synchronisation to the timed calls.
 struct Profile {
   bool on = false;
   bool init = false;
+  bool pending = false;  // events of a profiled evaluation not yet read
   int every = 1;
   int64_t calls = 0;
   hipEvent_t e[4];
@@ -45,6 +49,20 @@ struct Profile {
 };
 static Profile g_prof;
 static std::mutex g_prof_mu;
+
+static hipError_t prof_harvest() {
+  if (!g_prof.pending) return hipSuccess;
+  hipError_t e = hipEventSynchronize(g_prof.e[3]);
+  if (e != hipSuccess) return e;
+  float t1 = 0.f, t2 = 0.f;
+  if ((e = hipEventElapsedTime(&t1, g_prof.e[0], g_prof.e[1])) != hipSuccess) return e;
+  if ((e = hipEventElapsedTime(&t2, g_prof.e[2], g_prof.e[3])) != hipSuccess) return e;
+  g_prof.eval_ms += t1;
+  g_prof.reduce_ms += t2;
+  g_prof.n += 1;
+  g_prof.pending = false;
+  return hipSuccess;
+}
 
 // Waits for the reduction of one evaluation: spins on the flag that the
 // reduction kernel sets after its result is visible in mapped host memory,
@@ -167,6 +185,10 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     a.kfac = 0.0;
     a.lnL = 0.0;
     const bool prof = g_prof.on && (g_prof.calls++ % g_prof.every) == 0;
+    if (prof) {
+      hipError_t e = prof_harvest();
+      if (e != hipSuccess) return hip_fail(e, "profile events");
+    }
     hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
                                prof ? g_prof.e[1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
@@ -183,21 +205,9 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     fr.seq = d->seq;
     e = launch_reduce_one(fr, st, prof ? g_prof.e[2] : nullptr, prof ? g_prof.e[3] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
-    if (prof) {
-      e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    } else {
-      e = wait_result(d, st);
-      if (e != hipSuccess) return hip_fail(e, "waiting for the reduction");
-    }
-    if (prof) {
-      float t1 = 0.f, t2 = 0.f;
-      hipEventElapsedTime(&t1, g_prof.e[0], g_prof.e[1]);
-      hipEventElapsedTime(&t2, g_prof.e[2], g_prof.e[3]);
-      g_prof.eval_ms += t1;
-      g_prof.reduce_ms += t2;
-      g_prof.n += 1;
-    }
+    e = wait_result(d, st);
+    if (e != hipSuccess) return hip_fail(e, "waiting for the reduction");
+    if (prof) g_prof.pending = true;
     for (int j = 0; j < (want_grad ? S + 1 : 1); ++j) sums[j] = d->res_host[j];
   }
   double v = 0.0;
@@ -424,6 +434,10 @@ extern "C" int nll_grad(const pdf_graph* g, const dataset* d, const double* para
 
 extern "C" int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (g_prof.init) {
+    hipError_t e = prof_harvest();
+    if (e != hipSuccess) return hip_fail(e, "hf_profile: profile events");
+  }
   if (eval_ms) *eval_ms = g_prof.eval_ms;
   if (reduce_ms) *reduce_ms = g_prof.reduce_ms;
   if (n_launch) *n_launch = g_prof.n;

@@ -21,6 +21,10 @@
 //   POLY   P = sum_k a_k (x-x0)^k / int (same), a_0 = 1 fixed
 //   ADD    P = sum_{j<K} f_j P_j + (1 - sum f_j) P_K                    ("Combining functions")
 //   PROD   P = prod_j P_j over disjoint observables                     (listing 2)
+//   MAP    P(x) = P_j(x) / Z for x in the j-th of K consecutive ranges of the
+//          box ([lo, b_1), [b_1, b_2), ..., [b_{K-1}, hi]), children P_j
+//          one-observable EXP / GAUSS / POLY leaves normalised over the box,
+//          Z = sum_j int_{range j} P_j dx                  ("Combining functions": MappedPdf)
 //   DALITZ P = |1 + sum_k c_k A_k(s12, s13)|^2 / N_A, with A_k relativistic
 //          Breit-Wigner x Blatt-Weisskopf x Zemach amplitudes and N_A the
 //          midpoint sum over a G x G grid of the Dalitz box ("Results": the
@@ -48,7 +52,7 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
-enum Kind { K_EXP = 1, K_GAUSS = 2, K_POLY = 3, K_ADD = 4, K_PROD = 5, K_DALITZ = 6, K_TDDP = 7 };
+enum Kind { K_EXP = 1, K_GAUSS = 2, K_POLY = 3, K_ADD = 4, K_PROD = 5, K_DALITZ = 6, K_TDDP = 7, K_MAP = 8 };
 
 // ---------------------------------------------------------------- sums
 struct Neumaier {
@@ -273,6 +277,7 @@ struct Node {
   std::vector<int> obs;     // observable columns
   std::vector<int> par;     // EXP: alpha; GAUSS: mu, sigma; POLY: a1..ad; ADD: fractions
   double x0 = 0.0;          // POLY expansion point
+  std::vector<double> bounds;  // MAP: the K-1 inner range boundaries
   DalitzDef* dz = nullptr;  // DALITZ, TDDP
   int p_tau = -1, p_y = -1; // TDDP
   int p_x = -1;             // TDDP with the trigonometric terms (x free)
@@ -307,6 +312,45 @@ void quad_form_grad(const std::vector<cplx>& M, const std::vector<cplx>& c, int 
   for (int j = 0; j < na; ++j) { cm += std::conj(c[j]) * M[j * na + k]; mc += M[k * na + j] * c[j]; }
   dre = cm + mc;
   dim = cplx(0.0, 1.0) * (cm - mc);
+}
+
+// int_u^v f(x) dx of the unnormalised EXP / GAUSS / POLY leaf f (as in
+// node_norm below) and its gradient (added into dI, length n_par).
+double leaf_integral(const Model& m, const Node& n, const double* th, double u, double v, std::vector<double>& dI) {
+  const double a = m.lo[n.obs[0]];
+  switch (n.kind) {
+    case K_EXP: {
+      // e^{alpha (u-a)} L phi(alpha L), L = v - u; d/dalpha ln = (u - a) + L psi(alpha L)
+      double al = th[n.par[0]], L = v - u;
+      double I = std::exp(al * (u - a)) * L * phi(al * L);
+      dI[n.par[0]] += I * ((u - a) + L * psi(al * L));
+      return I;
+    }
+    case K_GAUSS: {
+      double mu = th[n.par[0]], sg = th[n.par[1]];
+      double zu = (u - mu) / (std::sqrt(2.0) * sg), zv = (v - mu) / (std::sqrt(2.0) * sg);
+      double de;
+      if (zu > 0.0) de = std::erfc(zu) - std::erfc(zv);
+      else if (zv < 0.0) de = std::erfc(-zv) - std::erfc(-zu);
+      else de = std::erf(zv) - std::erf(zu);
+      double I = sg * std::sqrt(kPi / 2.0) * de;
+      double gu = std::exp(-zu * zu), gv = std::exp(-zv * zv);
+      dI[n.par[0]] += gu - gv;
+      dI[n.par[1]] += I / sg - ((v - mu) * gv - (u - mu) * gu) / sg;
+      return I;
+    }
+    case K_POLY: {
+      double I = v - u;
+      for (size_t k = 1; k <= n.par.size(); ++k) {
+        double w = (std::pow(v - n.x0, (double)(k + 1)) - std::pow(u - n.x0, (double)(k + 1))) / (k + 1);
+        I += th[n.par[k - 1]] * w;
+        dI[n.par[k - 1]] += w;
+      }
+      return I;
+    }
+    default:
+      return NAN;
+  }
 }
 
 void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& out) {
@@ -403,6 +447,27 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
       }
       break;
     }
+    case K_MAP: {
+      // Z = sum_j I_j / N_j: the children's integrals over their ranges,
+      // each child normalised over the whole box (N_j)
+      const double lo = m.lo[n.obs[0]], hi = m.hi[n.obs[0]];
+      const size_t K = n.child.size();
+      double Z = 0.0;
+      std::vector<double> dZ(m.n_par, 0.0);
+      for (size_t j = 0; j < K; ++j) {
+        node_norm(m, n.child[j], th, out);
+        const NodeNorm& cn = out[n.child[j]];
+        const double u = j == 0 ? lo : n.bounds[j - 1], v = j + 1 == K ? hi : n.bounds[j];
+        std::vector<double> dI(m.n_par, 0.0);
+        const double I = leaf_integral(m, m.nodes[n.child[j]], th, u, v, dI);
+        const double Nj = std::exp(cn.lnN), q = I / Nj;
+        Z += q;
+        for (int p = 0; p < m.n_par; ++p) dZ[p] += dI[p] / Nj - q * cn.dlnN[p];
+      }
+      r.lnN = std::log(Z);
+      for (int p = 0; p < m.n_par; ++p) r.dlnN[p] = dZ[p] / Z;
+      break;
+    }
     default:
       break;  // ADD and PROD are normalised through their children
   }
@@ -458,6 +523,14 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
         for (int p = 0; p < np; ++p) g[p] += fj * pj[j] * gj[j][p] / P;
       }
       for (size_t j = 0; j + 1 < K; ++j) g[n.par[j]] += (pj[j] - pj[K - 1]) / P;
+      break;
+    }
+    case K_MAP: {
+      // the child whose range holds x
+      const double x = ev[n.obs[0]];
+      size_t sel = 0;
+      while (sel < n.bounds.size() && x >= n.bounds[sel]) ++sel;
+      lp = node_eval(m, n.child[sel], ev, th, nn, g) - nn[id].lnN;
       break;
     }
     case K_PROD: {
@@ -582,6 +655,13 @@ int om_poly(Model* m, int obs, double x0, int degree, const int* p_coef) {
 }
 int om_add(Model* m, int n_child, const int* child, const int* p_frac) {
   Node n; n.kind = K_ADD; n.child.assign(child, child + n_child); n.par.assign(p_frac, p_frac + n_child - 1);
+  return push(m, n);
+}
+// MAP over observable `obs`: n_child one-observable leaves and their n_child - 1
+// increasing inner boundaries.
+int om_map(Model* m, int obs, int n_child, const int* child, const double* bounds) {
+  Node n; n.kind = K_MAP; n.obs = {obs}; n.child.assign(child, child + n_child);
+  n.bounds.assign(bounds, bounds + n_child - 1);
   return push(m, n);
 }
 int om_prod(Model* m, int n_child, const int* child) {

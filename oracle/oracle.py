@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KINDS = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7}
+KINDS = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7, "map": 8}
 _CH = {"12": 12, "13": 13, "23": 23}
 
 
@@ -56,6 +56,7 @@ def lib():
         L.om_poly.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip]
         L.om_add.argtypes = [vp, ctypes.c_int, ip, ip]
         L.om_prod.argtypes = [vp, ctypes.c_int, ip]
+        L.om_map.argtypes = [vp, ctypes.c_int, ctypes.c_int, ip, dp]
         L.om_dalitz.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                 ip, dp, dp, ip, ip, ip]
         L.om_tddp.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
@@ -143,6 +144,11 @@ class Model:
         elif op == "poly":
             keep, pp = _ip([self._p(n) for n in node["par"]])
             nid = L.om_poly(self._h, self._o(node["obs"]), float(node.get("x0", 0.0)), len(node["par"]), pp)
+        elif op == "map":
+            kids = [self._add(c) for c in node["children"]]
+            kk, kp = _ip(kids)
+            b = np.ascontiguousarray(node["bounds"], dtype=np.float64)
+            nid = L.om_map(self._h, self._o(node["obs"]), len(kids), kp, _dp(b))
         elif op in ("add", "prod"):
             kids = [self._add(c) for c in node["children"]]
             kk, kp = _ip(kids)

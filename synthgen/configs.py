@@ -19,7 +19,7 @@ Unbounded parameters use lo = hi = 0.
 import math
 
 __all__ = [
-    "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "DALITZ_KINEMATICS", "RESONANCES",
+    "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -180,6 +180,37 @@ C4X = {
     "seed": 6,
 }
 
+# ---------------------------------------------------------------- mapped densities
+# The MappedPdf form of section "Combining functions": a different leaf on
+# each of three ranges of x (exponential on [0, 4), Gaussian on [4, 7),
+# quadratic on [7, 10]); and the same map added to an exponential
+# background (the map then normalised per event inside the sum).
+MAPPED = {
+    "name": "mapped3",
+    "obs": [("x", 0.0, 10.0)],
+    "params": [("m_alpha", -0.25, 0.05, -5.0, 5.0, False), ("m_mu", 5.4, 0.05, 3.0, 8.0, False),
+               ("m_sigma", 0.7, 0.05, 0.05, 5.0, False), ("m_a1", 0.12, 0.02, 0.0, 0.0, False),
+               ("m_a2", 0.012, 0.002, 0.0, 0.0, False)],
+    "truth": {"m_alpha": -0.3, "m_mu": 5.5, "m_sigma": 0.6, "m_a1": 0.1, "m_a2": 0.01},
+    "model": {"op": "map", "obs": "x", "bounds": [4.0, 7.0], "children": [
+        {"op": "exp", "obs": "x", "par": ["m_alpha"]},
+        {"op": "gauss", "obs": "x", "par": ["m_mu", "m_sigma"]},
+        {"op": "poly", "obs": "x", "par": ["m_a1", "m_a2"], "x0": 8.5},
+    ]},
+    "n_events": 10_000_000,
+    "seed": 21,
+}
+MAPPED_SUM = {
+    "name": "mapped3_plus_exp",
+    "obs": [("x", 0.0, 10.0)],
+    "params": MAPPED["params"] + [("m_f", 0.6, 0.05, 0.0, 1.0, False), ("m_beta", -0.1, 0.05, -5.0, 5.0, False)],
+    "truth": dict(MAPPED["truth"], m_f=0.7, m_beta=-0.15),
+    "model": {"op": "add", "par": ["m_f"], "children": [
+        MAPPED["model"], {"op": "exp", "obs": "x", "par": ["m_beta"]}]},
+    "n_events": 10_000_000,
+    "seed": 22,
+}
+
 # ---------------------------------------------------------------- C5
 # Stream of toy fits of the C1 model with uneven event counts.
 C5 = {
@@ -210,4 +241,5 @@ LISTING2 = {
 
 
 def workload(name):
-    return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2}[name]
+    return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2, "mapped": MAPPED,
+            "mapped_sum": MAPPED_SUM}[name]

@@ -13,7 +13,7 @@ from .configs import C1, C2, C4, C5, LISTING2, dalitz_box
 
 __all__ = [
     "truncated_exponential", "truncated_normal", "gen_c1", "gen_c2",
-    "gen_listing2", "gen_accept_reject_dalitz", "gen_accept_reject_tddp",
+    "gen_listing2", "gen_accept_reject_dalitz", "gen_accept_reject_tddp", "gen_accept_reject_1d",
     "gen_flat_box", "serving_trace", "gen_serving_request",
 ]
 
@@ -118,6 +118,23 @@ def gen_accept_reject_dalitz(n, seed, density, envelope, batch=1 << 20):
         s13[got:got + a.size] = b
         got += a.size
     return {"s12": s12, "s13": s13}
+
+
+def gen_accept_reject_1d(n, seed, density, envelope, lo, hi, batch=1 << 20):
+    """Accept-reject on [lo, hi] for a caller-supplied density(x) <= envelope."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(n)
+    got = 0
+    while got < n:
+        x = lo + (hi - lo) * rng.random(batch)
+        u = rng.random(batch)
+        d = np.asarray(density(x))
+        if np.any(d > envelope):
+            raise ValueError("accept-reject envelope too low")
+        keep = x[u * envelope < d][:n - got]
+        out[got:got + keep.size] = keep
+        got += keep.size
+    return out
 
 
 def gen_accept_reject_tddp(n, seed, rate, envelope, tau, y, sigma_t_range=None,

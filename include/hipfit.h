@@ -88,7 +88,13 @@ enum hf_op {
                         (section "Results": hyperbolic and trigonometric terms); t is
                         normalised over the real line; obs = {s12, s13, t, sigma_t};
                         par = {Re c_1, Im c_1, ..., tau, y} (x = 0: Cz = E(t; 1/tau), Sz = 0)
-                        or {..., tau, y, x}; consts = DALITZ block                          */
+                        or {..., tau, y, x}; consts = DALITZ block                          */,
+  HF_OP_MAP = 8      /* piecewise density (section "Combining functions": MappedPdf):
+                        P(x) = P_j(x) / Z for x in the j-th of the K ranges [lo, b_1),
+                        [b_1, b_2), ..., [b_{K-1}, hi] of observable x's box; children = K >= 2
+                        one-observable EXP / GAUSS / POLY leaves on x, each normalised over
+                        the box; Z = sum_j int_{range j} P_j dx; obs = {x}; no par;
+                        consts = {b_1 < ... < b_{K-1}}, strictly inside the box             */
 };
 
 /* DALITZ block of node constants:

@@ -81,6 +81,8 @@ class Graph:
                 consts = [float(node.get("x0", 0.0))]
             elif op in ("dalitz", "tddp"):
                 consts = dalitz_consts(node["dalitz"])
+            elif op == "map":
+                consts = [float(b) for b in node["bounds"]]
             n = _lib.hf_node()
             n.op = _lib.OP[op]
             n.n_child = len(kids)

@@ -243,7 +243,7 @@ __device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, const
       b23[e] = chan_swap_ac_bc<T>(cs, chb + 2 * kChStride, c23[e], s12[e], s13[e]);
     }
   }
-  const int16_t* g = nd.res_end;
+  const int32_t* g = nd.res_end;
   const T r2 = cs.get<T>(nd.c0 + kDzR2);
   res_group<T, 0, TD, E>(cs, rbase, r2, 0, g[0], c12, b12, a0, a1, b0, b1);
   res_group<T, 1, TD, E>(cs, rbase, r2, g[0], g[1], c12, b12, a0, a1, b0, b1);

@@ -626,7 +626,7 @@ struct LightLeafEv {  // single EXP / GAUSS leaf
 // Kernel variant of OP_TDDP with the trigonometric terms (x free): a
 // compile-time choice, so that the x = 0 kernel carries none of their
 // registers.
-constexpr int OP_TDDP_X = 8;
+constexpr int OP_TDDP_X = 16;
 
 // Events per thread and step of the single-leaf amplitude kernels: the E
 // events share every read of a resonance's constants and every loop step,
@@ -687,6 +687,31 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
           v += lv[ch];
           resp[ch] = T(1);
         }
+      } else if (op == OP_MAP) {
+        // the child whose range holds x (increasing boundaries in the
+        // column's offset frame) gives the value; the other children's slot
+        // derivatives are dropped (set, not scaled: they may be undefined
+        // outside their ranges); unhoisted, ln Z and its slot derivatives
+        // are subtracted here
+        const int K = nd.n_child;
+        const double x = xe[nd.col[0]];
+        int sel = 0;
+        for (int j = 0; j < K - 1; ++j) sel += x >= cs.d[c0 + j] ? 1 : 0;
+        v = T(0);
+        int m = 0;
+        for (int j = 0; j < K; ++j) {
+          const int ch = P.child[nd.child0 + j];
+          const bool on = sel == j;
+          v = on ? lv[ch] : v;
+          resp[ch] = T(1);
+          const KNode& cn = P.node[ch];
+          for (int q = 0; q < cn.n_slot; ++q, ++m) {
+            T d = on ? dl[cn.slot0 + q] : T(0);
+            if (!h) d -= cs.get<T>(c0 + K + 1 + m);
+            dl[cn.slot0 + q] = d;
+          }
+        }
+        if (!h) v = (v - cs.get<T>(c0 + K - 1)) - cs.get<T>(c0 + K);
       } else {  // OP_ADD: log-sum-exp with the largest child as pivot
         const int K = nd.n_child;
         T m = T(-INFINITY);
@@ -721,7 +746,7 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
     for (int k = GRAD ? root : -1; k >= 0; --k) {
       const KNode& nd = P.node[k];
       const T a = adj[k];
-      if (nd.op == OP_ADD || nd.op == OP_PROD)
+      if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP)
         for (int j = 0; j < nd.n_child; ++j) {
           const int ch = P.child[nd.child0 + j];
           adj[ch] = a * resp[ch];

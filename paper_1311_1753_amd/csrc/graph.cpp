@@ -283,6 +283,61 @@ int32_t rows_for(int kind, hf_precision prec, int64_t n) {
 }
 
 // ------------------------------------------------------------------ staging
+// Share q = int_u^v f / int_box f of a one-observable EXP / GAUSS / POLY leaf
+// f on [u, v] inside its box, and dq/d(slot) for the leaf's slots (the
+// parameter values are those the kernels see: `rnd` rounds to float on the
+// FP32 path).  False when the box integral is not positive.
+template <class Rnd>
+static bool leaf_share(const pdf_graph* g, const NodeInfo& nd, const double* th, const Rnd& rnd, bool fp32, double u,
+                       double v, double& q, std::vector<double>& dq) {
+  const ObsInfo& o = g->obs[nd.obs[0]];
+  q = 0.0;
+  switch (nd.op) {
+    case OP_EXP: {
+      // ln q = alpha (u - lo) + ln int_0^{v-u} e^{alpha y} dy - ln int_0^L e^{alpha y} dy
+      const double alpha = rnd(th[nd.par[0]]);
+      double lnI, dI, lnN, dN;
+      exp_norm(alpha, v - u, lnI, dI);
+      exp_norm(alpha, o.hi - o.lo, lnN, dN);
+      q = std::exp(alpha * (u - o.lo) + lnI - lnN);
+      dq.assign(1, q * ((u - o.lo) + dI - dN));
+      return true;
+    }
+    case OP_GAUSS: {
+      const double mu = th[nd.par[0]];
+      const double s = fp32 ? 1.0 / rnd(1.0 / th[nd.par[1]]) : th[nd.par[1]];
+      double lnN, dmN, dsN, lnI, dmI, dsI;
+      if (!gauss_norm(o.lo, o.hi, mu, s, lnN, dmN, dsN)) return false;
+      dq.assign(2, 0.0);
+      if (!gauss_norm(u, v, mu, s, lnI, dmI, dsI)) return true;  // far tail: q = 0
+      q = std::exp(lnI - lnN);
+      dq[0] = q * (dmI - dmN);
+      dq[1] = q * (dsI - dsN);
+      return true;
+    }
+    case OP_POLY: {
+      const double x0 = nd.consts[0];
+      const int d = (int)nd.par.size();
+      double I = v - u, N = o.hi - o.lo;
+      std::vector<double> wI(d), wN(d);
+      for (int j = 1; j <= d; ++j) {
+        const double a = rnd(th[nd.par[j - 1]]);
+        wI[j - 1] = (std::pow(v - x0, j + 1) - std::pow(u - x0, j + 1)) / (j + 1);
+        wN[j - 1] = (std::pow(o.hi - x0, j + 1) - std::pow(o.lo - x0, j + 1)) / (j + 1);
+        I += a * wI[j - 1];
+        N += a * wN[j - 1];
+      }
+      if (!(N > 0.0)) return false;
+      q = I / N;
+      dq.assign(d, 0.0);
+      for (int j = 0; j < d; ++j) dq[j] = (wI[j] - q * wN[j]) / N;
+      return true;
+    }
+    default:
+      return false;
+  }
+}
+
 void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& sc, bool generic) {
   sc.prog = g->prog;
   sc.ok = true;
@@ -403,6 +458,47 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
       }
       case OP_PROD:
         break;
+      case OP_MAP: {
+        // boundaries in the column's offset frame; Z = sum of the children's
+        // shares of their ranges (each child normalised over the box)
+        const int K = kn.n_child, col = kn.col[0];
+        const ObsInfo& o = g->obs[g->obs_of_col[col]];
+        const double ref = column_ref(g, col, prec);
+        for (int j = 0; j < K - 1; ++j) {
+          P.c64[c0 + j] = nd.consts[j] - ref;
+          P.c32[c0 + j] = (float)P.c64[c0 + j];
+        }
+        double Z = 0.0;
+        std::vector<std::vector<double>> dq(K);
+        for (int j = 0; j < K; ++j) {
+          const double u = j == 0 ? o.lo : nd.consts[j - 1], v = j + 1 == K ? o.hi : nd.consts[j];
+          double q = 0.0;
+          if (!leaf_share(g, g->nodes[nd.child[j]], th, rnd, fp32, u, v, q, dq[j])) sc.ok = false;
+          Z += q;
+        }
+        if (!(Z > 0.0)) { sc.ok = false; Z = 1.0; }
+        const double lnZ = std::log(Z);
+        int m = 0;
+        for (int j = 0; j < K; ++j) {
+          const NodeInfo& cn = g->nodes[nd.child[j]];
+          for (size_t q = 0; q < dq[j].size(); ++q, ++m) {
+            const double dz = dq[j][q] / Z;
+            if (hoist) {
+              sc.ht.dlnN[cn.par[q]] += dz;
+              setc(c0 + K + 1 + m, 0.0);
+            } else {
+              setc(c0 + K + 1 + m, dz);
+            }
+          }
+        }
+        if (hoist) {
+          sc.ht.lnN += lnZ;
+          set_ln(c0 + K - 1, c0 + K, 0.0);
+        } else {
+          set_ln(c0 + K - 1, c0 + K, lnZ);
+        }
+        break;
+      }
       case OP_DALITZ:
       case OP_TDDP: {
         const DalitzInfo& dz = g->dz;
@@ -493,8 +589,13 @@ int node_slots(const NodeInfo& n) {
   }
 }
 
-int node_consts(const NodeInfo& n) {
+int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
   switch (n.op) {
+    case OP_MAP: {
+      int slots = 0;
+      for (int c : n.child) slots += node_slots(all[c]);
+      return (int)n.child.size() + 1 + slots;
+    }
     case OP_EXP: return 5;
     case OP_GAUSS: return 6;
     case OP_POLY: return 2 * (int)n.par.size() + 3;
@@ -602,6 +703,29 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
         case OP_PROD:
           rc = need(n.n_child >= 2 && n.n_par == 0 && n.n_obs == 0, "PROD takes K >= 2 children and no parameters");
           break;
+        case OP_MAP: {
+          rc = need(n.n_child >= 2 && n.n_par == 0 && n.n_obs == 1 && n.n_const == n.n_child - 1,
+                    "MAP takes K >= 2 children, one observable, K-1 boundaries and no parameters");
+          if (!rc) rc = need(finite_box(ni.obs[0]), "MAP needs a finite observable box");
+          if (!rc) {
+            const ObsInfo& o = g->obs[ni.obs[0]];
+            double prev = o.lo;
+            for (double b : ni.consts) {
+              rc = need(std::isfinite(b) && b > prev, "MAP boundaries must increase strictly inside the box");
+              if (rc) break;
+              prev = b;
+            }
+            if (!rc) rc = need(prev < o.hi, "MAP boundaries must increase strictly inside the box");
+          }
+          for (int c : ni.child) {
+            if (rc) break;
+            const NodeInfo& cn = in[c];
+            rc = need((cn.op == OP_EXP || cn.op == OP_GAUSS || cn.op == OP_POLY) && cn.obs.size() == 1 &&
+                          cn.obs[0] == ni.obs[0],
+                      "MAP children must be EXP / GAUSS / POLY leaves on the MAP's observable");
+          }
+          break;
+        }
         case OP_DALITZ:
         case OP_TDDP: {
           const bool td = n.op == OP_TDDP;
@@ -705,29 +829,29 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     for (int k = 0; k < NN; ++k) {
       const NodeInfo& n = g->nodes[k];
       KNode& kn = P.node[k];
-      kn.op = (int16_t)n.op;
-      kn.n_child = (int16_t)n.child.size();
-      kn.child0 = (int16_t)chl;
-      for (int c : n.child) P.child[chl++] = (int16_t)c;
-      kn.slot0 = (int16_t)slot;
-      kn.n_slot = (int16_t)node_slots(n);
-      kn.c0 = (int16_t)cst;
-      for (int j = 0; j < 4; ++j) kn.col[j] = j < (int)n.obs.size() ? (int16_t)g->col_of_obs[n.obs[j]] : 0;
-      kn.hoisted = (int16_t)hoist[k];
+      kn.op = (int32_t)n.op;
+      kn.n_child = (int32_t)n.child.size();
+      kn.child0 = (int32_t)chl;
+      for (int c : n.child) P.child[chl++] = (int32_t)c;
+      kn.slot0 = (int32_t)slot;
+      kn.n_slot = (int32_t)node_slots(n);
+      kn.c0 = (int32_t)cst;
+      for (int j = 0; j < 4; ++j) kn.col[j] = j < (int)n.obs.size() ? (int32_t)g->col_of_obs[n.obs[j]] : 0;
+      kn.hoisted = (int32_t)hoist[k];
       kn.aux = 0;
-      if (n.op == OP_POLY) kn.aux = (int16_t)n.par.size();
+      if (n.op == OP_POLY) kn.aux = (int32_t)n.par.size();
       if (n.op == OP_DALITZ || n.op == OP_TDDP) {
         const int R = (int)n.consts[6];
-        kn.aux = (int16_t)R;
+        kn.aux = (int32_t)R;
         int cnt[kNumGroups] = {0};
         for (int j = 0; j < R; ++j) ++cnt[res_group_of(n, j)];
-        for (int gi = 0, e = 0; gi < kNumGroups; ++gi) kn.res_end[gi] = (int16_t)(e += cnt[gi]);
+        for (int gi = 0, e = 0; gi < kNumGroups; ++gi) kn.res_end[gi] = (int32_t)(e += cnt[gi]);
       }
       // gradient slot -> parameter
       if (n.op == OP_ADD) for (int j = 0; j < kn.n_slot; ++j) g->slot_par.push_back(n.par[j]);
       else for (int j = 0; j < kn.n_slot; ++j) g->slot_par.push_back(n.par[j]);
       slot += kn.n_slot;
-      cst += node_consts(n);
+      cst += node_consts(g->nodes, n);
       if (slot > kMaxSlots) return fail(HF_E_GRAPH, "more than 32 gradient slots");
       if (cst > kMaxConst) return fail(HF_E_GRAPH, "constant table overflow (too many resonances or nodes)");
     }

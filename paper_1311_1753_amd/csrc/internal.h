@@ -25,29 +25,33 @@ constexpr int kMaxPar = 64;
 constexpr int kNumGroups = 9;        // (pair, spin) groups of Dalitz resonances
 
 enum Op : int16_t {
-  OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7
+  OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7, OP_MAP = 8
 };
 
+// Node fields are 32-bit so that the kernels read them from the kernel
+// argument with scalar loads at wave-uniform node indices (16-bit fields at
+// runtime offsets become per-lane memory loads whose values the compiler can
+// no longer treat as uniform).
 struct KNode {
-  int16_t op;
-  int16_t n_child;
-  int16_t child0;    // first index into KProgram::child
-  int16_t slot0;     // first per-event gradient slot owned by this node
-  int16_t n_slot;
-  int16_t c0;        // first constant of this node
-  int16_t col[4];    // observable columns read
-  int16_t hoisted;   // 1: normalisation applied on the host (every ancestor is PROD)
-  int16_t aux;       // POLY: degree; DALITZ/TDDP: number of resonances
+  int32_t op;
+  int32_t n_child;
+  int32_t child0;    // first index into KProgram::child
+  int32_t slot0;     // first per-event gradient slot owned by this node
+  int32_t n_slot;
+  int32_t c0;        // first constant of this node
+  int32_t col[4];    // observable columns read
+  int32_t hoisted;   // 1: normalisation applied on the host (every ancestor is PROD)
+  int32_t aux;       // POLY: degree; DALITZ/TDDP: number of resonances
   // DALITZ/TDDP: the resonances are stored grouped by (pair, spin), group
   // g = 3 * pair + J (pairs 12, 13, 23 = 0, 1, 2); group g holds resonances
   // [res_end[g - 1], res_end[g]) with res_end[-1] = 0 and res_end[8] = R.
-  int16_t res_end[kNumGroups];
+  int32_t res_end[kNumGroups];
 };
 
 struct KProgram {
   int32_t n_nodes, root, n_slots, n_cols;
   KNode node[kMaxNodes];
-  int16_t child[kMaxNodes];
+  int32_t child[kMaxNodes];
   double c64[kMaxConst];
   float c32[kMaxConst];
 };
@@ -57,6 +61,9 @@ struct KProgram {
 //   GAUSS  0 loc = ref - mu (double), 1 1/sigma, 2 lnN_hi, 3 lnN_lo, 4 dlnN/dmu, 5 dlnN/dsigma
 //   POLY   0 loc = ref - x0 (double), 1..d a_k, d+1 lnN_hi, d+2 lnN_lo, d+3.. dlnN/da_k
 //   ADD    0..K-1 fractions (the last one 1 - sum of the others)
+//   MAP    0..K-2 inner range boundaries (double, in the column's offset frame),
+//          K-1 lnZ_hi, K lnZ_lo, then dlnZ/d(slot) for every slot of the
+//          children in child order (not hoisted; zeros when hoisted)
 //   DALITZ/TDDP: see the kDz* offsets below.
 // For the float path lnN is split into a float pair (hi + lo) so that the
 // rounding of the constant does not bias every event in the same direction.

@@ -55,6 +55,18 @@ def gen_data(name, n, seed):
         tau, y = (th[-2], th[-1]) if name == "c4" else (th[-3], th[-2])
         return S.gen_accept_reject_tddp(n, seed, lambda x, yy, t: m.tddp_rate(th, x, yy, t), env, tau, y,
                                         batch=1 << 18)
+    if name in ("mapped", "mapped_sum"):
+        m = oracle_model(name)
+        th = m.theta(S.workload(name)["truth"])
+        grid = np.linspace(0.0, 10.0, 4001)
+        dens = lambda x: np.exp(m.logpdf(th, {"x": x}))
+        x = S.gen_accept_reject_1d(n, seed, dens, 1.2 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)
+        # events within 1e-5 of a range boundary move just above it: there the
+        # float-rounded offsets of the FP32-eval path could select the other range
+        for b in S.MAPPED["model"]["bounds"]:
+            near = np.abs(x - b) < 1e-5
+            x[near] = b + 1e-5
+        return {"x": x}
     raise ValueError(name)
 
 

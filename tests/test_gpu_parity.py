@@ -28,6 +28,8 @@ CASES = [
     ("c3", 20_037, 15),
     ("c4", 20_041, 16),
     ("c4x", 20_043, 17),
+    ("mapped", 150_001, 18),
+    ("mapped_sum", 150_003, 19),
 ]
 
 
@@ -146,7 +148,8 @@ def test_empty_and_domain_errors(P, stream):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name,n,seed", [("c1", 100_123, 21), ("c2", 200_077, 22), ("listing2", 50_005, 23)])
+@pytest.mark.parametrize("name,n,seed", [("c1", 100_123, 21), ("c2", 200_077, 22), ("listing2", 50_005, 23),
+                                         ("mapped", 200_011, 24)])
 def test_fit_matches_oracle_fit(P, stream, name, n, seed, prec):
     print(f"\n[case] fit {name} n={n} prec={prec}", flush=True)
     sp = get_spec(name)

@@ -33,7 +33,7 @@ def test_library_exports_every_header_symbol():
 
 def test_graph_creation_for_every_workload():
     import paper_1311_1753_amd as P
-    for name in ("c1", "c2", "c3", "c4", "listing2"):
+    for name in ("c1", "c2", "c3", "c4", "c4x", "listing2", "mapped", "mapped_sum"):
         g = P.Graph.from_spec(S.workload(name))
         assert g.n_par == len(S.workload(name)["params"])
 
@@ -70,6 +70,14 @@ def test_graph_validation_errors():
     dz["resonances"] = [dict(dz["resonances"][0], m0=0.2)] + dz["resonances"][1:]
     m["dalitz"] = dz
     _expect_graph_error(bad["obs"], bad["params"], m)
+    # MAP: boundaries not increasing, on the box edge, wrong count, a child
+    # that is not a leaf on the MAP's observable
+    ga = {"op": "gauss", "obs": "x", "par": ["a", "b"]}
+    for b in ([0.6, 0.3], [0.0, 0.5], [0.5, 1.0], [0.5]):
+        _expect_graph_error(obs, par, {"op": "map", "obs": "x", "bounds": b, "children": [ex, ga, ex]})
+    _expect_graph_error(obs, par, {"op": "map", "obs": "x", "bounds": [0.5], "children": [ex, ey]})
+    _expect_graph_error(obs, par, {"op": "map", "obs": "x", "bounds": [0.5], "children": [
+        ex, {"op": "add", "par": ["f"], "children": [ex, dict(ex, par=["b"])]}]})
 
 
 def test_graph_create_raw_abi_errors():

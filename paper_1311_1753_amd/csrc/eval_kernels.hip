@@ -640,7 +640,11 @@ template <typename T, int OP> struct AmpEvents { static constexpr int value = OP
 // and, with GRAD, its slot derivatives in dl[0 .. P.n_slots).
 template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
 __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const double* xe, T* dl) {
-    constexpr int NN = HEAVY ? kMaxNodes : 8;  // node capacity of this instantiation
+    // node capacity of this instantiation; float arrays get 16 entries so
+    // that the compiler indexes them with register moves (8 floats become
+    // chains of compares and selects, one per entry and access; 8 doubles
+    // are already indexed)
+    constexpr int NN = HEAVY || sizeof(T) == 4 ? kMaxNodes : 8;
     const int n_nodes = P.n_nodes;
     T lv[NN], adj[NN], resp[NN];
     // forward pass (post-order)
@@ -763,7 +767,7 @@ struct TreeEv {
   template <class Acc>
   __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, int64_t, const Acc& acc) const {
     const int n_slots = GRAD ? P.n_slots : 0;
-    T dl[NS];
+    T dl[sizeof(T) == 4 && NS < 16 ? 16 : NS];  // indexed with register moves (see tree_eval)
     const T lr = tree_eval<T, NS, NCOL, HEAVY, GRAD>(P, cs, xe, dl);
     acc.add(0, -(double)lr);
 #pragma unroll
@@ -786,7 +790,7 @@ struct BinnedEv {
   template <class Acc>
   __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, int64_t i, const Acc& acc) const {
     const int n_slots = GRAD ? P.n_slots : 0;
-    T dl[NS];
+    T dl[sizeof(T) == 4 && NS < 16 ? 16 : NS];  // indexed with register moves (see tree_eval)
     const double lp = (double)tree_eval<T, NS, NCOL, HEAVY, GRAD>(P, cs, xe, dl) - L;
     const double wi = w[i];
     double term, dterm;

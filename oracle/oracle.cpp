@@ -20,7 +20,10 @@
 //   GAUSS  P = exp(-(x-mu)^2/(2 sigma^2)) / int_a^b (same) dx          (listing 3)
 //   POLY   P = sum_k a_k (x-x0)^k / int (same), a_0 = 1 fixed
 //   ADD    P = sum_{j<K} f_j P_j + (1 - sum f_j) P_K                    ("Combining functions")
-//   PROD   P = prod_j P_j over disjoint observables                     (listing 2)
+//   PROD   P = prod_j P_j over disjoint observables                     (listing 2);
+//          one-observable EXP / GAUSS / POLY children may share an
+//          observable: each such group is renormalised by the integral of
+//          its product over the box (numerical, composite Gauss-Legendre)
 //   MAP    P(x) = P_j(x) / Z for x in the j-th of K consecutive ranges of the
 //          box ([lo, b_1), [b_1, b_2), ..., [b_{K-1}, hi]), children P_j
 //          one-observable EXP / GAUSS / POLY leaves normalised over the box,
@@ -353,6 +356,9 @@ double leaf_integral(const Model& m, const Node& n, const double* th, double u, 
   }
 }
 
+double node_eval(const Model& m, int id, const double* ev, const double* th, const std::vector<NodeNorm>& nn,
+                 double* g);
+
 void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& out) {
   const Node& n = m.nodes[id];
   NodeNorm& r = out[id];
@@ -444,6 +450,52 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
       if (n.p_x >= 0) {
         double dN_dx = -0.5 * (IAA - IBB) * tau * 2.0 * x / (opx * opx) - IJ * tau * (1.0 - x * x) / (opx * opx);
         r.dlnN[n.p_x] += dN_dx / N;
+      }
+      break;
+    }
+    case K_PROD: {
+      // groups of one-observable leaf children on a shared observable:
+      // Z_g = int_box prod_{j in g} P_j(x) dx by 200 x 16-point Gauss-Legendre
+      for (int ch : n.child) node_norm(m, ch, th, out);
+      struct GL16 { double x[16], w[16]; };
+      static const GL16 gl = [] { GL16 q; gauss_legendre(16, q.x, q.w); return q; }();
+      std::vector<int> done(n.child.size(), 0);
+      for (size_t a = 0; a < n.child.size(); ++a) {
+        const Node& ca = m.nodes[n.child[a]];
+        if (done[a] || ca.obs.size() != 1 || !(ca.kind == K_EXP || ca.kind == K_GAUSS || ca.kind == K_POLY)) continue;
+        std::vector<int> grp = {n.child[a]};
+        for (size_t b = a + 1; b < n.child.size(); ++b) {
+          const Node& cb = m.nodes[n.child[b]];
+          if (cb.obs.size() == 1 && cb.obs[0] == ca.obs[0] &&
+              (cb.kind == K_EXP || cb.kind == K_GAUSS || cb.kind == K_POLY)) {
+            grp.push_back(n.child[b]);
+            done[b] = 1;
+          }
+        }
+        if (grp.size() < 2) continue;
+        const int o = ca.obs[0];
+        const double lo = m.lo[o], hi = m.hi[o];
+        const int nseg = 200;
+        const double h = (hi - lo) / nseg;
+        std::vector<double> ev(m.n_obs, 0.0), gj(m.n_par), gs(m.n_par);
+        Neumaier Z;
+        std::vector<Neumaier> dZ(m.n_par);
+        for (int k = 0; k < nseg; ++k)
+          for (int i = 0; i < 16; ++i) {
+            ev[o] = lo + h * (k + 0.5 * (gl.x[i] + 1.0));
+            double l = 0.0;
+            std::fill(gs.begin(), gs.end(), 0.0);
+            for (int c : grp) {
+              l += node_eval(m, c, ev.data(), th, out, gj.data());
+              for (int p = 0; p < m.n_par; ++p) gs[p] += gj[p];
+            }
+            const double f = 0.5 * h * gl.w[i] * std::exp(l);
+            Z.add(f);
+            for (int p = 0; p < m.n_par; ++p) dZ[p].add(f * gs[p]);
+          }
+        const double z = Z.value();
+        r.lnN += std::log(z);
+        for (int p = 0; p < m.n_par; ++p) r.dlnN[p] += dZ[p].value() / z;
       }
       break;
     }
@@ -541,6 +593,7 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
         lp += l;
         for (int p = 0; p < np; ++p) g[p] += gj[p];
       }
+      lp -= nn[id].lnN;  // shared-observable groups (0 without)
       break;
     }
     case K_DALITZ: {

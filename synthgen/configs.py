@@ -19,7 +19,8 @@ Unbounded parameters use lo = hi = 0.
 import math
 
 __all__ = [
-    "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "DALITZ_KINEMATICS", "RESONANCES",
+    "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "SHARED", "SHARED_SUM",
+    "SHARED_2D", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -211,6 +212,45 @@ MAPPED_SUM = {
     "seed": 22,
 }
 
+# ---------------------------------------------------------------- products over a shared observable
+# An acceptance (quadratic in x) times a Gaussian signal on the same x: the
+# product is renormalised numerically (section "Combining functions":
+# ProdPdf); the same product added to an exponential background; and the
+# product times an independent exponential in y.
+SHARED = {
+    "name": "acceptance_x_gauss",
+    "obs": [("x", 0.0, 10.0)],
+    "params": [("e_a1", 0.04, 0.02, 0.0, 0.0, False), ("e_a2", -0.008, 0.005, 0.0, 0.0, False),
+               ("s_mu", 6.2, 0.1, 0.0, 10.0, False), ("s_sigma", 1.1, 0.1, 0.05, 5.0, False)],
+    "truth": {"e_a1": 0.05, "e_a2": -0.01, "s_mu": 6.0, "s_sigma": 1.2},
+    "model": {"op": "prod", "children": [
+        {"op": "poly", "obs": "x", "par": ["e_a1", "e_a2"], "x0": 5.0},
+        {"op": "gauss", "obs": "x", "par": ["s_mu", "s_sigma"]},
+    ]},
+    "n_events": 10_000_000,
+    "seed": 23,
+}
+SHARED_SUM = {
+    "name": "acceptance_x_gauss_plus_exp",
+    "obs": [("x", 0.0, 10.0)],
+    "params": SHARED["params"] + [("s_f", 0.6, 0.05, 0.0, 1.0, False), ("b_beta", -0.2, 0.05, -5.0, 5.0, False)],
+    "truth": dict(SHARED["truth"], s_f=0.55, b_beta=-0.25),
+    "model": {"op": "add", "par": ["s_f"], "children": [
+        SHARED["model"], {"op": "exp", "obs": "x", "par": ["b_beta"]}]},
+    "n_events": 10_000_000,
+    "seed": 24,
+}
+SHARED_2D = {
+    "name": "acceptance_x_gauss_times_exp_y",
+    "obs": [("x", 0.0, 10.0), ("y", 0.0, 5.0)],
+    "params": SHARED["params"] + [("y_alpha", -0.4, 0.05, -5.0, 5.0, False)],
+    "truth": dict(SHARED["truth"], y_alpha=-0.5),
+    "model": {"op": "prod", "children": SHARED["model"]["children"] + [
+        {"op": "exp", "obs": "y", "par": ["y_alpha"]}]},
+    "n_events": 1_000_000,
+    "seed": 25,
+}
+
 # ---------------------------------------------------------------- C5
 # Stream of toy fits of the C1 model with uneven event counts.
 C5 = {
@@ -242,4 +282,4 @@ LISTING2 = {
 
 def workload(name):
     return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2, "mapped": MAPPED,
-            "mapped_sum": MAPPED_SUM}[name]
+            "mapped_sum": MAPPED_SUM, "shared": SHARED, "shared_sum": SHARED_SUM, "shared_2d": SHARED_2D}[name]

@@ -75,7 +75,13 @@ enum hf_op {
                         consts = {x0}; density <= 0 at an event is a domain error           */
   HF_OP_ADD = 4,     /* sum_{j<K} f_j P_j + (1 - sum f_j) P_K; K >= 2 children; par = the
                         K-1 fractions; children over the same box, each normalised          */
-  HF_OP_PROD = 5,    /* prod_j P_j over disjoint observables; K >= 2 children; no par       */
+  HF_OP_PROD = 5,    /* prod_j P_j / prod_g Z_g; K >= 2 children; no par; children use
+                        disjoint observables, except that one-observable EXP / GAUSS / POLY
+                        leaves may share one: each such group g (two or more leaves on one
+                        observable x) is renormalised by Z_g = int_box prod_{j in g} P_j dx
+                        (section "Combining functions"), computed on the host by composite
+                        16-point Gauss-Legendre quadrature on at most 4096 segments; any
+                        other overlap is HF_E_GRAPH                                          */
   HF_OP_DALITZ = 6,  /* |1 + sum_k c_k A_k(s12, s13)|^2 / N_A over the Dalitz plot;
                         obs = {s12, s13}; par = {Re c_1, Im c_1, ..., Re c_R, Im c_R};
                         consts = DALITZ block (below)                                       */

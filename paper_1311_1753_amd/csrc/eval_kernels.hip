@@ -685,12 +685,20 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         }
         v = l1[0];
       } else if (op == OP_PROD) {
+        // with leaves that share an observable (aux), unhoisted: minus ln Z
+        // of their products and its derivatives in the children's slots
+        const bool sub = nd.aux != 0 && !h;
         v = T(0);
+        int m = 0;
         for (int j = 0; j < nd.n_child; ++j) {
           const int ch = P.child[nd.child0 + j];
           v += lv[ch];
           resp[ch] = T(1);
+          const KNode& cn = P.node[ch];
+          if (sub)
+            for (int q = 0; q < cn.n_slot; ++q, ++m) dl[cn.slot0 + q] -= cs.get<T>(c0 + 2 + m);
         }
+        if (sub) v = (v - cs.get<T>(c0)) - cs.get<T>(c0 + 1);
       } else if (op == OP_MAP) {
         // the child whose range holds x (increasing boundaries in the
         // column's offset frame) gives the value; the other children's slot

@@ -283,6 +283,33 @@ int32_t rows_for(int kind, hf_precision prec, int64_t n) {
 }
 
 // ------------------------------------------------------------------ staging
+namespace {
+
+// One-observable leaf that a PROD may multiply with others on the same observable.
+bool is_leaf1(const NodeInfo& n) {
+  return (n.op == OP_EXP || n.op == OP_GAUSS || n.op == OP_POLY) && n.obs.size() == 1;
+}
+
+// Groups of a PROD's children (indices into n.child) that are one-observable
+// leaves sharing an observable; only groups of two or more.
+std::vector<std::vector<int>> shared_groups(const std::vector<NodeInfo>& all, const NodeInfo& n) {
+  std::vector<std::vector<int>> out;
+  std::vector<int> done(n.child.size(), 0);
+  for (size_t a = 0; a < n.child.size(); ++a) {
+    if (done[a] || !is_leaf1(all[n.child[a]])) continue;
+    std::vector<int> grp = {(int)a};
+    for (size_t b = a + 1; b < n.child.size(); ++b)
+      if (!done[b] && is_leaf1(all[n.child[b]]) && all[n.child[b]].obs[0] == all[n.child[a]].obs[0]) {
+        grp.push_back((int)b);
+        done[b] = 1;
+      }
+    if (grp.size() >= 2) out.push_back(grp);
+  }
+  return out;
+}
+
+}  // namespace
+
 // Share q = int_u^v f / int_box f of a one-observable EXP / GAUSS / POLY leaf
 // f on [u, v] inside its box, and dq/d(slot) for the leaf's slots (the
 // parameter values are those the kernels see: `rnd` rounds to float on the
@@ -336,6 +363,142 @@ static bool leaf_share(const pdf_graph* g, const NodeInfo& nd, const double* th,
     default:
       return false;
   }
+}
+
+// A one-observable EXP / GAUSS / POLY leaf with the parameter values the
+// kernels see: ln P(x), normalised over the observable's box, and its slot
+// derivatives.
+struct HostLeaf {
+  int op = 0, n_slot = 0;
+  double p[8] = {0.0}, x0 = 0.0, s = 1.0, lnN = 0.0, dN[8] = {0.0};
+  // false where P(x) = 0 (a polynomial at or below zero)
+  bool eval(double x, double& l, double* d) const {
+    switch (op) {
+      case OP_EXP:
+        l = p[0] * (x - x0) - lnN;
+        d[0] = (x - x0) - dN[0];
+        return true;
+      case OP_GAUSS: {
+        const double z = (x - p[0]) / s;
+        l = -0.5 * z * z - lnN;
+        d[0] = z / s - dN[0];
+        d[1] = z * z / s - dN[1];
+        return true;
+      }
+      default: {
+        double f = 1.0, u = 1.0;
+        double pw[8];
+        for (int j = 0; j < n_slot; ++j) {
+          u *= x - x0;
+          pw[j] = u;
+          f += p[j] * u;
+        }
+        if (!(f > 0.0)) return false;
+        l = std::log(f) - lnN;
+        for (int j = 0; j < n_slot; ++j) d[j] = pw[j] / f - dN[j];
+        return true;
+      }
+    }
+  }
+};
+
+template <class Rnd>
+static HostLeaf host_leaf(const pdf_graph* g, const NodeInfo& nd, const double* th, const Rnd& rnd, bool fp32,
+                          bool& ok) {
+  const ObsInfo& o = g->obs[nd.obs[0]];
+  HostLeaf h;
+  h.op = nd.op;
+  switch (nd.op) {
+    case OP_EXP:
+      h.n_slot = 1;
+      h.p[0] = rnd(th[nd.par[0]]);
+      h.x0 = o.lo;
+      exp_norm(h.p[0], o.hi - o.lo, h.lnN, h.dN[0]);
+      break;
+    case OP_GAUSS:
+      h.n_slot = 2;
+      h.p[0] = th[nd.par[0]];
+      h.s = fp32 ? 1.0 / rnd(1.0 / th[nd.par[1]]) : th[nd.par[1]];
+      if (!gauss_norm(o.lo, o.hi, h.p[0], h.s, h.lnN, h.dN[0], h.dN[1])) ok = false;
+      break;
+    default: {
+      h.n_slot = (int)nd.par.size();
+      h.x0 = nd.consts[0];
+      double N = o.hi - o.lo;
+      for (int j = 1; j <= h.n_slot; ++j) {
+        h.p[j - 1] = rnd(th[nd.par[j - 1]]);
+        h.dN[j - 1] = (std::pow(o.hi - h.x0, j + 1) - std::pow(o.lo - h.x0, j + 1)) / (j + 1);
+        N += h.p[j - 1] * h.dN[j - 1];
+      }
+      if (!(N > 0.0)) { ok = false; N = 1.0; }
+      h.lnN = std::log(N);
+      for (int j = 0; j < h.n_slot; ++j) h.dN[j] /= N;
+    }
+  }
+  return h;
+}
+
+// Z = int_box prod_j P_j(x) dx over a group of one-observable leaves on one
+// observable, by composite 16-point Gauss-Legendre on segments no wider than
+// two of the narrowest Gaussian's widths and four decay lengths of the
+// steepest exponential (32 .. 4096 segments), and dZ/d(slot) / Z for the
+// leaves' slots in order.  False when Z is not positive.
+static bool shared_norm(const std::vector<HostLeaf>& lf, double lo, double hi, double& lnZ,
+                        std::vector<double>& dz) {
+  static const double* const gl = [] {
+    // nodes (first 16) and weights (next 16) on [-1, 1] by Newton on P_16
+    static double q[32];
+    const int n = 16;
+    for (int i = 0; i < n; ++i) {
+      double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (x * p1 - p0) / (x * x - 1.0);
+        const double dx = p1 / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      q[i] = x;
+      q[n + i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    return q;
+  }();
+  const double L = hi - lo;
+  double h = L / 32.0;
+  for (const HostLeaf& f : lf) {
+    if (f.op == OP_GAUSS) h = std::min(h, 2.0 * f.s);
+    if (f.op == OP_EXP && f.p[0] != 0.0) h = std::min(h, 4.0 / std::fabs(f.p[0]));
+  }
+  const int nseg = (int)std::min(4096.0, std::ceil(L / h));
+  h = L / nseg;
+  int ns = 0;
+  for (const HostLeaf& f : lf) ns += f.n_slot;
+  std::vector<double> acc(ns, 0.0), d(ns);
+  double Z = 0.0;
+  for (int k = 0; k < nseg; ++k)
+    for (int i = 0; i < 16; ++i) {
+      const double x = lo + h * (k + 0.5 * (gl[i] + 1.0));
+      double l = 0.0, li;
+      bool live = true;
+      for (size_t j = 0, m = 0; j < lf.size(); m += lf[j].n_slot, ++j) {
+        live = live && lf[j].eval(x, li, d.data() + m);
+        l += li;
+      }
+      if (!live) continue;
+      const double w = 0.5 * h * gl[16 + i] * std::exp(l);
+      Z += w;
+      for (int m = 0; m < ns; ++m) acc[m] += w * d[m];
+    }
+  if (!(Z > 0.0) || !std::isfinite(Z)) return false;
+  lnZ = std::log(Z);
+  dz.resize(ns);
+  for (int m = 0; m < ns; ++m) dz[m] = acc[m] / Z;
+  return true;
 }
 
 void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& sc, bool generic) {
@@ -456,8 +619,46 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         }
         break;
       }
-      case OP_PROD:
+      case OP_PROD: {
+        if (!kn.aux) break;
+        // shared-observable groups: ln Z of each group's product and its
+        // slot derivatives, per child slot in child order (zero for the
+        // children outside every group)
+        std::vector<int> base(kn.n_child + 1, 0);
+        for (int j = 0; j < kn.n_child; ++j) base[j + 1] = base[j] + P.node[nd.child[j]].n_slot;
+        std::vector<double> dslot(base[kn.n_child], 0.0);
+        double lnZ = 0.0;
+        for (const std::vector<int>& grp : shared_groups(g->nodes, nd)) {
+          std::vector<HostLeaf> lf;
+          bool ok = true;
+          for (int j : grp) lf.push_back(host_leaf(g, g->nodes[nd.child[j]], th, rnd, fp32, ok));
+          const ObsInfo& o = g->obs[g->nodes[nd.child[grp[0]]].obs[0]];
+          double lz = 0.0;
+          std::vector<double> dz;
+          if (!ok || !shared_norm(lf, o.lo, o.hi, lz, dz)) { sc.ok = false; continue; }
+          lnZ += lz;
+          for (size_t j = 0, m = 0; j < grp.size(); m += lf[j].n_slot, ++j)
+            for (int q = 0; q < lf[j].n_slot; ++q) dslot[base[grp[j]] + q] = dz[m + q];
+        }
+        for (int j = 0, m = 0; j < kn.n_child; ++j) {
+          const NodeInfo& cn = g->nodes[nd.child[j]];
+          for (int q = 0; q < P.node[nd.child[j]].n_slot; ++q, ++m) {
+            if (hoist) {
+              if (dslot[m] != 0.0) sc.ht.dlnN[cn.par[q]] += dslot[m];
+              setc(c0 + 2 + m, 0.0);
+            } else {
+              setc(c0 + 2 + m, dslot[m]);
+            }
+          }
+        }
+        if (hoist) {
+          sc.ht.lnN += lnZ;
+          set_ln(c0, c0 + 1, 0.0);
+        } else {
+          set_ln(c0, c0 + 1, lnZ);
+        }
         break;
+      }
       case OP_MAP: {
         // boundaries in the column's offset frame; Z = sum of the children's
         // shares of their ranges (each child normalised over the box)
@@ -596,11 +797,17 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
       for (int c : n.child) slots += node_slots(all[c]);
       return (int)n.child.size() + 1 + slots;
     }
+    case OP_PROD: {
+      // with shared groups: lnZ_hi, lnZ_lo, then dlnZ/d(slot) of every child slot
+      if (shared_groups(all, n).empty()) return 0;
+      int slots = 0;
+      for (int c : n.child) slots += node_slots(all[c]);
+      return 2 + slots;
+    }
     case OP_EXP: return 5;
     case OP_GAUSS: return 6;
     case OP_POLY: return 2 * (int)n.par.size() + 3;
     case OP_ADD: return (int)n.child.size() + 1;
-    case OP_PROD: return 0;
     case OP_DALITZ: return dz_n_const((int)n.consts[6], false);
     default: return dz_n_const((int)n.consts[6], true);
   }
@@ -783,17 +990,25 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     }
     const int NN = (int)g->nodes.size();
     // observable sets; ADD children share one, PROD children are disjoint
+    // apart from groups of one-observable leaves
     std::vector<std::set<int>> os(NN);
     int n_heavy = 0;
     for (int k = 0; k < NN; ++k) {
       NodeInfo& n = g->nodes[k];
       if (n.op == OP_ADD || n.op == OP_PROD) {
+        // PROD: one-observable EXP / GAUSS / POLY children may share their
+        // observable (renormalised numerically); any other overlap is an error
+        std::set<int> leaf_only;
         for (int c : n.child) {
           if (n.op == OP_ADD && os[c] != os[n.child[0]])
             return fail(HF_E_GRAPH, "ADD children must share the same observables");
+          const bool l1 = is_leaf1(g->nodes[c]);
           for (int o : os[c]) {
-            if (n.op == OP_PROD && os[k].count(o))
-              return fail(HF_E_GRAPH, "PROD children must have disjoint observables");
+            if (n.op == OP_PROD && os[k].count(o) && !(l1 && leaf_only.count(o)))
+              return fail(HF_E_GRAPH,
+                          "PROD children must have disjoint observables, except one-observable EXP / GAUSS / POLY "
+                          "leaves, which may share one");
+            if (!os[k].count(o) && l1) leaf_only.insert(o);
             os[k].insert(o);
           }
         }
@@ -840,6 +1055,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       kn.hoisted = (int32_t)hoist[k];
       kn.aux = 0;
       if (n.op == OP_POLY) kn.aux = (int32_t)n.par.size();
+      if (n.op == OP_PROD) kn.aux = shared_groups(g->nodes, n).empty() ? 0 : 1;
       if (n.op == OP_DALITZ || n.op == OP_TDDP) {
         const int R = (int)n.consts[6];
         kn.aux = (int32_t)R;

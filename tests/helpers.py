@@ -67,6 +67,20 @@ def gen_data(name, n, seed):
             near = np.abs(x - b) < 1e-5
             x[near] = b + 1e-5
         return {"x": x}
+    if name in ("shared", "shared_sum", "shared_2d"):
+        # x from the 1-D density (the 2-D product factorises: x from the shared
+        # product, y from its exponential by inverting the CDF)
+        base = "shared" if name == "shared_2d" else name
+        m = oracle_model(base)
+        th = m.theta(S.workload(base)["truth"])
+        grid = np.linspace(0.0, 10.0, 4001)
+        dens = lambda x: np.exp(m.logpdf(th, {"x": x}))
+        x = S.gen_accept_reject_1d(n, seed, dens, 1.2 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)
+        if name != "shared_2d":
+            return {"x": x}
+        a, L = S.SHARED_2D["truth"]["y_alpha"], 5.0
+        u = np.random.default_rng(seed + 1).uniform(0.0, 1.0, n)
+        return {"x": x, "y": np.log1p(u * np.expm1(a * L)) / a}
     raise ValueError(name)
 
 

@@ -30,6 +30,9 @@ CASES = [
     ("c4x", 20_043, 17),
     ("mapped", 150_001, 18),
     ("mapped_sum", 150_003, 19),
+    ("shared", 100_003, 26),
+    ("shared_sum", 100_005, 27),
+    ("shared_2d", 100_007, 28),
 ]
 
 
@@ -164,6 +167,31 @@ def test_fit_matches_oracle_fit(P, stream, name, n, seed, prec):
     print(f"  status {r['status']} n_eval {r['n_eval']} edm {r['edm']:.2e}; "
           f"max |dtheta|/sigma {dev.max():.2e}; err ratio {np.max(np.abs(r['errors'][free] / ref['errors'][free] - 1)):.2e}",
           flush=True)
+    assert r["status"] == "OK"
+    assert dev.max() <= 1e-3
+    assert np.all(np.abs(r["errors"][free] / ref["errors"][free] - 1) < 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fit_shared_observable_product_matches_oracle_fit(P, stream, prec):
+    """Fit of the Gaussian-times-acceptance plus exponential model, with the
+    acceptance fixed (free, its coefficients and the Gaussian's mean and
+    width are nearly degenerate): the numerically renormalised product is
+    fitted like any other node."""
+    from oracle import oracle as O
+    print(f"\n[case] fit shared_sum (fixed acceptance) prec={prec}", flush=True)
+    sp = get_spec("shared_sum")
+    sp["params"] = [(p[0], sp["truth"][p[0]], p[2], p[3], p[4], True) if p[0].startswith("e_a") else p
+                    for p in sp["params"]]
+    data = data_for("shared_sum", 200_013, 25)
+    om = O.Model(sp)
+    ref = om.fit(data)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec, stream)
+    r = P.fit(g, ds, stream=stream)
+    free = g.free_mask()
+    dev = np.abs(r["theta"] - ref["theta"])[free] / ref["errors"][free]
+    print(f"  status {r['status']} n_eval {r['n_eval']}; max |dtheta|/sigma {dev.max():.2e}", flush=True)
     assert r["status"] == "OK"
     assert dev.max() <= 1e-3
     assert np.all(np.abs(r["errors"][free] / ref["errors"][free] - 1) < 1e-3)

@@ -51,8 +51,17 @@ def test_graph_validation_errors():
     par = [("a", -1.0, 0.1, -5, 5, False), ("b", -1.0, 0.1, -5, 5, False), ("f", 0.5, 0.1, 0, 1, False)]
     ex = {"op": "exp", "obs": "x", "par": ["a"]}
     ey = {"op": "exp", "obs": "y", "par": ["b"]}
-    # PROD over a shared observable
-    _expect_graph_error(obs, par, {"op": "prod", "children": [ex, {"op": "exp", "obs": "x", "par": ["b"]}]})
+    # PROD over a shared observable that is not a group of one-observable
+    # leaves: a leaf times a sum on the same observable, and the reverse
+    sx = {"op": "add", "par": ["f"], "children": [ex, {"op": "exp", "obs": "x", "par": ["b"]}]}
+    _expect_graph_error(obs, par, {"op": "prod", "children": [ex, sx]})
+    _expect_graph_error(obs, par, {"op": "prod", "children": [sx, ex]})
+    # ... and a PROD of a 2-D product with a leaf on one of its observables
+    _expect_graph_error(obs, par, {"op": "prod", "children": [{"op": "prod", "children": [ex, ey]},
+                                                               {"op": "gauss", "obs": "y", "par": ["a", "b"]}]})
+    # leaves sharing x build (renormalised numerically)
+    P_ = __import__("paper_1311_1753_amd")
+    P_.Graph(obs, par, {"op": "prod", "children": [ex, {"op": "exp", "obs": "x", "par": ["b"]}]})
     # ADD over different observables
     _expect_graph_error(obs, par, {"op": "add", "par": ["f"], "children": [ex, ey]})
     # ADD with a wrong number of fractions

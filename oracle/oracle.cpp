@@ -39,6 +39,15 @@
 //          P = [a_c C(t) + a_0 Cz(t) + a_s S(t) + b_s Sz(t)] / N_T, Cz / Sz the
 //          resolution-convolved e^{-t/tau} cos(x t/tau) / sin(x t/tau),
 //          b_s = -Im(conj(A) Abar)
+//   DPMAP  P(u | s12, s13) = P_c(u): the Dalitz box cut into an n12 x n13
+//          grid of rectangles (inner boundaries b12, b13; a boundary belongs
+//          to the cell above it), cell c = i12 n13 + i13 taking its own
+//          one-observable EXP / GAUSS / POLY leaf on u, normalised over u's
+//          box ("Results": the decay-time uncertainty's distribution varies
+//          across the Dalitz plot).  A density of u conditional on the plot
+//          position; in a PROD with the DALITZ / TDDP node on (s12, s13) it
+//          completes the joint density (u may be the TDDP's sigma_t, on
+//          which that node is conditional).
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -55,7 +64,8 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
-enum Kind { K_EXP = 1, K_GAUSS = 2, K_POLY = 3, K_ADD = 4, K_PROD = 5, K_DALITZ = 6, K_TDDP = 7, K_MAP = 8 };
+enum Kind { K_EXP = 1, K_GAUSS = 2, K_POLY = 3, K_ADD = 4, K_PROD = 5, K_DALITZ = 6, K_TDDP = 7, K_MAP = 8,
+            K_DPMAP = 9 };
 
 // ---------------------------------------------------------------- sums
 struct Neumaier {
@@ -280,7 +290,8 @@ struct Node {
   std::vector<int> obs;     // observable columns
   std::vector<int> par;     // EXP: alpha; GAUSS: mu, sigma; POLY: a1..ad; ADD: fractions
   double x0 = 0.0;          // POLY expansion point
-  std::vector<double> bounds;  // MAP: the K-1 inner range boundaries
+  std::vector<double> bounds;  // MAP: the K-1 inner range boundaries; DPMAP: b12
+  std::vector<double> bounds2; // DPMAP: b13
   DalitzDef* dz = nullptr;  // DALITZ, TDDP
   int p_tau = -1, p_y = -1; // TDDP
   int p_x = -1;             // TDDP with the trigonometric terms (x free)
@@ -585,6 +596,15 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
       lp = node_eval(m, n.child[sel], ev, th, nn, g) - nn[id].lnN;
       break;
     }
+    case K_DPMAP: {
+      // the cell holding (s12, s13): count the boundaries at or below each
+      const double a = ev[n.obs[0]], b = ev[n.obs[1]];
+      size_t i12 = 0, i13 = 0;
+      for (double v : n.bounds) i12 += a >= v ? 1 : 0;
+      for (double v : n.bounds2) i13 += b >= v ? 1 : 0;
+      lp = node_eval(m, n.child[i12 * (n.bounds2.size() + 1) + i13], ev, th, nn, g);
+      break;
+    }
     case K_PROD: {
       std::vector<double> gj(np);
       lp = 0.0;
@@ -715,6 +735,15 @@ int om_add(Model* m, int n_child, const int* child, const int* p_frac) {
 int om_map(Model* m, int obs, int n_child, const int* child, const double* bounds) {
   Node n; n.kind = K_MAP; n.obs = {obs}; n.child.assign(child, child + n_child);
   n.bounds.assign(bounds, bounds + n_child - 1);
+  return push(m, n);
+}
+// DPMAP: n12 x n13 children (row-major, s12 index first) on observable u,
+// with the n12 - 1 and n13 - 1 inner boundaries of s12 and s13.
+int om_dpmap(Model* m, int o12, int o13, int ou, int n12, int n13, const int* child, const double* b12,
+             const double* b13) {
+  Node n; n.kind = K_DPMAP; n.obs = {o12, o13, ou}; n.child.assign(child, child + n12 * n13);
+  n.bounds.assign(b12, b12 + n12 - 1);
+  n.bounds2.assign(b13, b13 + n13 - 1);
   return push(m, n);
 }
 int om_prod(Model* m, int n_child, const int* child) {

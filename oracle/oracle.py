@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KINDS = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7, "map": 8}
+KINDS = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7, "map": 8, "dpmap": 9}
 _CH = {"12": 12, "13": 13, "23": 23}
 
 
@@ -57,6 +57,7 @@ def lib():
         L.om_add.argtypes = [vp, ctypes.c_int, ip, ip]
         L.om_prod.argtypes = [vp, ctypes.c_int, ip]
         L.om_map.argtypes = [vp, ctypes.c_int, ctypes.c_int, ip, dp]
+        L.om_dpmap.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp]
         L.om_dalitz.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                 ip, dp, dp, ip, ip, ip]
         L.om_tddp.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
@@ -149,6 +150,17 @@ class Model:
             kk, kp = _ip(kids)
             b = np.ascontiguousarray(node["bounds"], dtype=np.float64)
             nid = L.om_map(self._h, self._o(node["obs"]), len(kids), kp, _dp(b))
+        elif op == "dpmap":
+            # obs = (s12, s13, u); children row-major over the (s12, s13) cells
+            kids = [self._add(c) for c in node["children"]]
+            kk, kp = _ip(kids)
+            b12 = np.ascontiguousarray(node["b12"], dtype=np.float64)
+            b13 = np.ascontiguousarray(node["b13"], dtype=np.float64)
+            if len(kids) != (b12.size + 1) * (b13.size + 1):
+                raise ValueError("dpmap needs (len(b12) + 1) x (len(b13) + 1) children")
+            o = [self._o(n) for n in node["obs"]]
+            nid = L.om_dpmap(self._h, o[0], o[1], o[2], b12.size + 1, b13.size + 1, kp,
+                             _dp(np.append(b12, 0.0)), _dp(np.append(b13, 0.0)))
         elif op in ("add", "prod"):
             kids = [self._add(c) for c in node["children"]]
             kk, kp = _ip(kids)

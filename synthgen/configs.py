@@ -20,7 +20,7 @@ import math
 
 __all__ = [
     "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "SHARED", "SHARED_SUM",
-    "SHARED_2D", "DALITZ_KINEMATICS", "RESONANCES",
+    "SHARED_2D", "C4S", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -251,6 +251,32 @@ SHARED_2D = {
     "seed": 25,
 }
 
+# ---------------------------------------------------------------- C4S
+# C4 with a density for the decay-time uncertainty that varies across the
+# Dalitz plot: the plot's box is cut at s12 = 1.5 and s13 = 1.5 GeV^2 into a
+# 2 x 2 grid of cells, each with a Gaussian sigma_t density on [0.02, 0.2] ps
+# (cells row-major, s12 index first); the model is the product of the
+# time-dependent density (conditional on sigma_t) and that map.
+SIGMA_T_CELLS = [(0.08, 0.03), (0.10, 0.035), (0.12, 0.04), (0.14, 0.045)]
+SIGMA_T_BOUNDS = ([1.5], [1.5])
+C4S = {
+    "name": "c4s_tddp_sigma_t_map",
+    "obs": [("s12", _BOX[0], _BOX[1]), ("s13", _BOX[0], _BOX[1]),
+            ("t", -math.inf, math.inf), ("sigma_t", 0.02, 0.2)],
+    "params": C4["params"] + [p for c in range(4) for p in (
+        (f"st_mu{c}", 0.11, 0.005, 0.0, 0.5, False), (f"st_sg{c}", 0.05, 0.005, 0.005, 0.5, False))],
+    "truth": dict(C4["truth"], **{k: v for c, (mu, sg) in enumerate(SIGMA_T_CELLS)
+                                  for k, v in ((f"st_mu{c}", mu), (f"st_sg{c}", sg))}),
+    "model": {"op": "prod", "children": [
+        C4["model"],
+        {"op": "dpmap", "obs": ["s12", "s13", "sigma_t"], "b12": SIGMA_T_BOUNDS[0], "b13": SIGMA_T_BOUNDS[1],
+         "children": [{"op": "gauss", "obs": "sigma_t", "par": [f"st_mu{c}", f"st_sg{c}"]} for c in range(4)]},
+    ]},
+    "sigma_t_range": (0.02, 0.2),
+    "n_events": 2_000_000,
+    "seed": 7,
+}
+
 # ---------------------------------------------------------------- C5
 # Stream of toy fits of the C1 model with uneven event counts.
 C5 = {
@@ -282,4 +308,5 @@ LISTING2 = {
 
 def workload(name):
     return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2, "mapped": MAPPED,
-            "mapped_sum": MAPPED_SUM, "shared": SHARED, "shared_sum": SHARED_SUM, "shared_2d": SHARED_2D}[name]
+            "mapped_sum": MAPPED_SUM, "shared": SHARED, "shared_sum": SHARED_SUM, "shared_2d": SHARED_2D,
+            "c4s": C4S}[name]

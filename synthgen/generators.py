@@ -138,14 +138,17 @@ def gen_accept_reject_1d(n, seed, density, envelope, lo, hi, batch=1 << 20):
 
 
 def gen_accept_reject_tddp(n, seed, rate, envelope, tau, y, sigma_t_range=None,
-                           batch=1 << 20):
+                           batch=1 << 20, sigma_t_cells=None):
     """Accept-reject for (s12, s13, t_true), then Gaussian smearing of t.
 
     Candidates: (s12, s13) uniform over the box, t_true ~ Exp with rate
     (1-|y|)/tau.  `rate(s12, s13, t_true)` is the unsmeared decay rate (0
     outside the Dalitz plot) and must satisfy
-    rate <= envelope * exp(-(1-|y|) t / tau).  sigma_t ~ U(range) and
-    t = t_true + sigma_t * N(0, 1).
+    rate <= envelope * exp(-(1-|y|) t / tau).  sigma_t ~ U(range), or with
+    sigma_t_cells = (b12, b13, [(mu, sigma) per cell]) a normal truncated to
+    the range with the parameters of the event's cell on the grid cut at
+    b12 / b13 (cells row-major, s12 index first; a boundary belongs to the
+    cell above it); t = t_true + sigma_t * N(0, 1).
     """
     sigma_t_range = C4["sigma_t_range"] if sigma_t_range is None else sigma_t_range
     lo, hi = dalitz_box()
@@ -164,7 +167,16 @@ def gen_accept_reject_tddp(n, seed, rate, envelope, tau, y, sigma_t_range=None,
             raise ValueError("accept-reject envelope too low")
         keep = np.nonzero(u * env < d)[0][:n - got]
         k = keep.size
-        st = sigma_t_range[0] + (sigma_t_range[1] - sigma_t_range[0]) * rng.random(k)
+        if sigma_t_cells is None:
+            st = sigma_t_range[0] + (sigma_t_range[1] - sigma_t_range[0]) * rng.random(k)
+        else:
+            b12, b13, cells = sigma_t_cells
+            cell = (np.searchsorted(b12, a[keep], side="right") * (len(b13) + 1)
+                    + np.searchsorted(b13, b[keep], side="right"))
+            st = np.empty(k)
+            for c, (mu, sg) in enumerate(cells):
+                idx = np.nonzero(cell == c)[0]
+                st[idx] = truncated_normal(rng, idx.size, mu, sg, *sigma_t_range)
         cols["s12"][got:got + k] = a[keep]
         cols["s13"][got:got + k] = b[keep]
         cols["t"][got:got + k] = tt[keep] + st * rng.standard_normal(k)

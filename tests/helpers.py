@@ -37,6 +37,19 @@ def gen_data(name, n, seed):
     if name == "poly":
         rng = np.random.default_rng(seed)
         return {"x": rng.uniform(-1.0, 3.0, n)}
+    if name == "c4s":
+        # the C4 events with sigma_t drawn from the density of the event's cell
+        m = oracle_model("c4")
+        th = m.theta(S.workload("c4")["truth"])
+        lo, hi = S.dalitz_box()
+        G = 200
+        c = lo + (np.arange(G) + 0.5) * (hi - lo) / G
+        a, b = np.meshgrid(c, c, indexing="ij")
+        env = 1.3 * (m.dalitz_amp2(th, a.ravel(), b.ravel()) + m.dalitz_amp2(th, a.ravel(), b.ravel(),
+                                                                               swapped=True)).max()
+        cells = (S.SIGMA_T_BOUNDS[0], S.SIGMA_T_BOUNDS[1], S.SIGMA_T_CELLS)
+        return S.gen_accept_reject_tddp(n, seed, lambda x, yy, t: m.tddp_rate(th, x, yy, t), env, th[-2], th[-1],
+                                        batch=1 << 18, sigma_t_cells=cells)
     if name in ("c3", "c4", "c4x"):
         m = oracle_model(name)
         th = m.theta(S.workload(name)["truth"])

@@ -63,11 +63,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 5 times (reference for the HBM byte counters)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4x", "mapped", "mapped_sum", "shared",
-                             "shared_sum", "c1l", "c2l"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4x", "c4s", "mapped", "mapped_sum",
+                             "shared", "shared_sum", "c1l", "c2l"],
                     help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
                          "c3 Dalitz amplitude sum, c4 time-dependent Dalitz (c4x with x free: the "
-                         "trigonometric terms), mapped / mapped_sum the piecewise density (alone / "
+                         "trigonometric terms; c4s times the sigma_t density that varies across "
+                         "the plot), mapped / mapped_sum the piecewise density (alone / "
                          "added to an exponential, 1e7 events), shared / shared_sum a Gaussian times "
                          "an acceptance polynomial on the same observable (alone / added to an "
                          "exponential, 1e7 events), c1l / c2l the c1 / c2 "
@@ -210,7 +211,7 @@ def other_workload(args, P, S, torch, stream):
         data = {"x": np.random.default_rng(spec["seed"]).uniform(0.0, 10.0, n)}
     else:
         data = S.gen_flat_box(n, spec["seed"], g.dalitz_inside)
-        if args.workload in ("c4", "c4x"):
+        if args.workload in ("c4", "c4x", "c4s"):
             rng = np.random.default_rng(spec["seed"] + 100)
             st = rng.uniform(0.02, 0.2, n)
             data["sigma_t"] = st

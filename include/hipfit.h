@@ -100,7 +100,18 @@ enum hf_op {
                         [b_1, b_2), ..., [b_{K-1}, hi] of observable x's box; children = K >= 2
                         one-observable EXP / GAUSS / POLY leaves on x, each normalised over
                         the box; Z = sum_j int_{range j} P_j dx; obs = {x}; no par;
-                        consts = {b_1 < ... < b_{K-1}}, strictly inside the box             */
+                        consts = {b_1 < ... < b_{K-1}}, strictly inside the box             */,
+  HF_OP_DPMAP = 9    /* density of an observable u that varies across the Dalitz plot
+                        (section "Results": the decay-time uncertainty's distribution):
+                        P(u | s12, s13) = P_c(u), c = i12 n13 + i13 the event's cell of the
+                        n12 x n13 grid cut at the inner boundaries b12 of s12 and b13 of s13
+                        (a boundary belongs to the cell above it); obs = {s12, s13, u};
+                        children = the n12 n13 cells' one-observable EXP / GAUSS / POLY leaves
+                        on u (row-major, s12 index first), each normalised over u's box; no
+                        par; consts = {n12, n13, b12 (n12 - 1, increasing), b13 (n13 - 1)}.
+                        Only as a PROD child beside the DALITZ / TDDP node on the same
+                        (s12, s13); u may be that TDDP's sigma_t (which it then describes)
+                        or an observable no other child uses                                */
 };
 
 /* DALITZ block of node constants:

@@ -83,6 +83,9 @@ class Graph:
                 consts = dalitz_consts(node["dalitz"])
             elif op == "map":
                 consts = [float(b) for b in node["bounds"]]
+            elif op == "dpmap":
+                b12, b13 = [float(b) for b in node["b12"]], [float(b) for b in node["b13"]]
+                consts = [len(b12) + 1.0, len(b13) + 1.0] + b12 + b13
             n = _lib.hf_node()
             n.op = _lib.OP[op]
             n.n_child = len(kids)

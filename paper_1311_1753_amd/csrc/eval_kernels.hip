@@ -724,6 +724,25 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
           }
         }
         if (!h) v = (v - cs.get<T>(c0 + K - 1)) - cs.get<T>(c0 + K);
+      } else if (op == OP_DPMAP) {
+        // the child of the event's cell on the s12 x s13 grid (row-major,
+        // boundaries in the columns' offset frames) gives the value; the
+        // other children's slot derivatives are dropped
+        const int K = nd.n_child, n13 = nd.aux, n12 = K / n13;
+        const double a = xe[nd.col[0]], b = xe[nd.col[1]];
+        int i12 = 0, i13 = 0;
+        for (int j = 0; j < n12 - 1; ++j) i12 += a >= cs.d[c0 + j] ? 1 : 0;
+        for (int j = 0; j < n13 - 1; ++j) i13 += b >= cs.d[c0 + n12 - 1 + j] ? 1 : 0;
+        const int sel = i12 * n13 + i13;
+        v = T(0);
+        for (int j = 0; j < K; ++j) {
+          const int ch = P.child[nd.child0 + j];
+          const bool on = sel == j;
+          v = on ? lv[ch] : v;
+          resp[ch] = T(1);
+          const KNode& cn = P.node[ch];
+          for (int q = 0; q < cn.n_slot; ++q) dl[cn.slot0 + q] = on ? dl[cn.slot0 + q] : T(0);
+        }
       } else {  // OP_ADD: log-sum-exp with the largest child as pivot
         const int K = nd.n_child;
         T m = T(-INFINITY);
@@ -758,7 +777,7 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
     for (int k = GRAD ? root : -1; k >= 0; --k) {
       const KNode& nd = P.node[k];
       const T a = adj[k];
-      if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP)
+      if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP)
         for (int j = 0; j < nd.n_child; ++j) {
           const int ch = P.child[nd.child0 + j];
           adj[ch] = a * resp[ch];
@@ -862,24 +881,90 @@ __device__ __forceinline__ void light_leaf_row(const KNode& nd, const CS& cs, co
 // double, with one LDS add.  Events past the row's end are replaced by the
 // step's first event and weighted out; a thread whose first event is past
 // the end has none left.
+// One (unhoisted) EXP / GAUSS / POLY child of a DPMAP at u: ln P and its
+// slot derivatives in d[0 .. n_slot).
+template <typename T>
+__device__ __forceinline__ T dpmap_child(const CS& cs, const KNode& cn, double u, T (&d)[8]) {
+  if (cn.op == OP_EXP) return leaf_exp<T>(cs, cn.c0, false, u, d);
+  if (cn.op == OP_GAUSS) return leaf_gauss<T>(cs, cn.c0, false, u, d);
+  return leaf_poly<T>(cs, cn.c0, cn.aux, false, u, d);
+}
+
+// A DPMAP's cell boundaries and, when every child is a Gaussian, each
+// cell's constants, staged in LDS once per row by one lane (reading the
+// kernel argument at uniform indices only): per event the cell comes from
+// broadcast reads of the boundaries and its constants from one lane-indexed
+// read of the table, instead of chains of dependent scalar loads per child.
+struct SigLds {
+  double b[2 * kMaxNodes];   // s12 boundaries, then s13 (the columns' offset frames)
+  double tab[kMaxNodes][8];  // loc = ref - mu, 1/sigma, lnN hi, lnN lo, dlnN/dmu, dlnN/dsigma, first slot
+};
+
+template <typename T>
+__device__ __forceinline__ bool sig_stage(const KProgram& P, const CS& cs, const KNode& dm, SigLds& L) {
+  const int K = dm.n_child, n13 = dm.aux, n12 = K / n13;
+  bool all = true;
+  for (int j = 0; j < K; ++j) all = all && P.node[P.child[dm.child0 + j]].op == OP_GAUSS;
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < n12 + n13 - 2; ++j) L.b[j] = cs.d[dm.c0 + j];
+    if (all)
+      for (int j = 0; j < K; ++j) {
+        const KNode& cn = P.node[P.child[dm.child0 + j]];
+        L.tab[j][0] = cs.d[cn.c0];
+#pragma unroll
+        for (int q = 1; q < 6; ++q) L.tab[j][q] = (double)cs.get<T>(cn.c0 + q);
+        L.tab[j][6] = (double)cn.slot0;
+      }
+  }
+  __syncthreads();
+  return all;
+}
+
+// Cell of (a, b) on the n12 x n13 grid (row-major).
+__device__ __forceinline__ int sig_cell(const SigLds& L, int n12, int n13, double a, double b) {
+  int i12 = 0, i13 = 0;
+  for (int j = 0; j < n12 - 1; ++j) i12 += a >= L.b[j] ? 1 : 0;
+  for (int j = 0; j < n13 - 1; ++j) i13 += b >= L.b[n12 - 1 + j] ? 1 : 0;
+  return i12 * n13 + i13;
+}
+
+// Time-dependent Dalitz kernels with the sigma_t density that varies across
+// the plot (a root PROD of the TDDP node, node 0, and a DPMAP on its s12,
+// s13 and sigma_t, the last node but one): the per-event value of the
+// event's cell joins ln P in the main loop; the map's slot derivatives are
+// summed in a second, light pass over the row (s12, s13 and sigma_t only),
+// whose accumulators reuse the LDS of the first.
+constexpr int OP_TDDP_S = 17;    // x = 0
+constexpr int OP_TDDP_XS = 18;   // x free
+template <int OP> struct AmpOp {
+  static constexpr int base = OP == OP_TDDP_S ? OP_TDDP : (OP == OP_TDDP_XS ? OP_TDDP_X : OP);
+  static constexpr bool sig = OP == OP_TDDP_S || OP == OP_TDDP_XS;
+};
+
 template <typename T, int OP, bool GRAD>
 __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
                                              int n_rows, int r, double* __restrict__ out) {
   typedef typename Col<T>::S Sx;
-  constexpr int E = AmpEvents<T, OP>::value;
-  constexpr int NCOL = OP == OP_DALITZ ? 2 : 4;
-  constexpr int NS = OP == OP_DALITZ ? 2 * kMaxRes : (OP == OP_TDDP ? 2 * kMaxRes + 2 : 2 * kMaxRes + 3);
+  constexpr int BOP = AmpOp<OP>::base;
+  constexpr bool SIG = AmpOp<OP>::sig;
+  constexpr int E = AmpEvents<T, BOP>::value;
+  constexpr int NCOL = BOP == OP_DALITZ ? 2 : 4;
+  constexpr int NS = BOP == OP_DALITZ ? 2 * kMaxRes : (BOP == OP_TDDP ? 2 * kMaxRes + 2 : 2 * kMaxRes + 3);
   constexpr int NC = 1 + NS;
   const KNode& nd = P.node[0];
   // slot columns: 2R coefficient derivatives (+ tau, y); zero derivatives
-  // land in the columns up to 2 kMaxRes, so all are cleared
-  const int n_slots = GRAD ? P.n_slots : 0;
+  // land in the columns up to 2 kMaxRes, so all are cleared.  With the
+  // sigma_t map the first pass stores the amplitude node's columns only.
+  const int n_slots = GRAD ? (SIG ? nd.n_slot : P.n_slots) : 0;
   const Sx* cp[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[nd.col[c]];
   __shared__ double accs[NC][kBlock];
   const LdsAcc<NC> acc{accs};
   acc.zero(GRAD ? NC : 1);
+  __shared__ SigLds sl;  // sigma_t map (SIG only)
+  bool all_gauss = false;
+  if constexpr (SIG) all_gauss = sig_stage<T>(P, cs, P.node[P.n_nodes - 2], sl);
   int64_t c0, c1;
   row_chunks(n, n_rows, r, c0, c1);
   const int64_t t = threadIdx.x;
@@ -920,11 +1005,84 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
       if (GRAD) acc.add(1 + j, sum(v));
     };
     T lv[E];
-    if constexpr (OP == OP_DALITZ) leaf_dalitz<T, E>(cs, nd, true, x[0], x[1], lv, emit);
-    else leaf_tddp<T, E, OP == OP_TDDP_X>(cs, nd, true, x[0], x[1], x[2], x[3], lv, emit);
+    if constexpr (BOP == OP_DALITZ) leaf_dalitz<T, E>(cs, nd, true, x[0], x[1], lv, emit);
+    else leaf_tddp<T, E, BOP == OP_TDDP_X>(cs, nd, true, x[0], x[1], x[2], x[3], lv, emit);
+    if constexpr (SIG) {
+      const KNode& dm = P.node[P.n_nodes - 2];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int cell = sig_cell(sl, dm.n_child / dm.aux, dm.aux, x[0][e], x[1][e]);
+        T v = T(0);
+        if (all_gauss) {
+          const double* g = sl.tab[cell];
+          const T z = (T)(x[3][e] + g[0]) * (T)g[1];
+          v = ((T(-0.5) * z * z) - (T)g[2]) - (T)g[3];
+        } else {
+          for (int j = 0; j < dm.n_child; ++j) {
+            T d[8];
+            const T lj = dpmap_child<T>(cs, P.node[P.child[dm.child0 + j]], x[3][e], d);
+            v = cell == j ? lj : v;
+          }
+        }
+        lv[e] += v;
+      }
+    }
     acc.add(0, -sum(lv));
   }
   row_store_acc<NC>(acc, 1 + n_slots, out, n_rows);
+  if constexpr (SIG && GRAD) {
+    // second pass: the map's slots (columns after the amplitude node's),
+    // the selected child's derivatives added to its own columns (all
+    // Gaussian: the loads of U chunks issued together; with more, the
+    // compiler turns the unrolled selections into lane-indexed reads of the
+    // kernel argument and copies it to scratch)
+    constexpr int U = 4;
+    const KNode& dm = P.node[P.n_nodes - 2];
+    const int sb = nd.n_slot, ns2 = P.n_slots - nd.n_slot, n13 = dm.aux, n12 = dm.n_child / n13;
+    acc.zero(ns2);
+    if (all_gauss) {
+#pragma unroll 1
+      for (int64_t ch = c0; ch < c1; ch += U) {
+        double a[U], b[U], u[U];
+#pragma unroll
+        for (int e = 0; e < U; ++e) {
+          const int64_t i = (ch + e) * kBlock + t;
+          const bool ok = ch + e < c1 && i < n;
+          a[e] = ok ? (double)cp[0][i] : 0.0;
+          b[e] = ok ? (double)cp[1][i] : 0.0;
+          u[e] = ok ? (double)cp[3][i] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < U; ++e) {
+          if (!(ch + e < c1 && (ch + e) * kBlock + t < n)) continue;
+          const double* g = sl.tab[sig_cell(sl, n12, n13, a[e], b[e])];
+          const T isg = (T)g[1];
+          const T z = (T)(u[e] + g[0]) * isg;
+          const int s0 = (int)g[6] - sb;
+          acc.add(s0, (double)(z * isg - (T)g[4]));
+          acc.add(s0 + 1, (double)(z * z * isg - (T)g[5]));
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int64_t ch = c0; ch < c1; ++ch) {
+        const int64_t i = ch * kBlock + t;
+        if (i >= n) break;
+        const double a = (double)cp[0][i], b = (double)cp[1][i], u = (double)cp[3][i];
+        const int cell = sig_cell(sl, n12, n13, a, b);
+        for (int j = 0; j < dm.n_child; ++j) {
+          const KNode& cn = P.node[P.child[dm.child0 + j]];
+          T d[8];
+          dpmap_child<T>(cs, cn, u, d);
+          if (cell == j)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (q < cn.n_slot) acc.add(cn.slot0 - sb + q, (double)d[q]);
+        }
+      }
+    }
+    row_store_acc<NC>(acc, ns2, out + (int64_t)(1 + sb) * n_rows, n_rows);
+  }
 }
 
 template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
@@ -1045,6 +1203,8 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_one(const FitRec fr) { red
 template <typename T, int OP> struct LeafWaves { static constexpr int value = 1; };
 template <> struct LeafWaves<float, OP_TDDP> { static constexpr int value = 3; };
 template <> struct LeafWaves<float, OP_TDDP_X> { static constexpr int value = 3; };
+template <> struct LeafWaves<float, OP_TDDP_S> { static constexpr int value = 3; };
+template <> struct LeafWaves<float, OP_TDDP_XS> { static constexpr int value = 3; };
 
 template <typename T, int OP, bool GRAD>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LeafWaves<T, OP>::value)))
@@ -1168,6 +1328,8 @@ static const void* kernel_of(int kind) {
     case KIND_DALITZ: return (const void*)&k_leaf<T, OP_DALITZ, GRAD>;
     case KIND_TDDP: return (const void*)&k_leaf<T, OP_TDDP, GRAD>;
     case KIND_TDDPX: return (const void*)&k_leaf<T, OP_TDDP_X, GRAD>;
+    case KIND_TDDPS: return (const void*)&k_leaf<T, OP_TDDP_S, GRAD>;
+    case KIND_TDDPXS: return (const void*)&k_leaf<T, OP_TDDP_XS, GRAD>;
     case KIND_TREE: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, true, GRAD>;
     default: return nullptr;  // mixtures: light, never below kRowsPerCU
   }
@@ -1198,6 +1360,8 @@ static hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st, hipEve
     case KIND_DALITZ: hipExtLaunchKernelGGL((k_leaf<T, OP_DALITZ, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDP: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDPX: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_X, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TDDPS: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_S, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TDDPXS: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_XS, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TREE:
       hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, e0, e1, 0, a);
       break;
@@ -1248,6 +1412,8 @@ static hipError_t launch_b(int kind, const BatchArgs& a, int grid, hipStream_t s
     case KIND_DALITZ: hipLaunchKernelGGL((k_leaf_batched<T, OP_DALITZ>), g, b, 0, st, a); break;
     case KIND_TDDP: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP>), g, b, 0, st, a); break;
     case KIND_TDDPX: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_X>), g, b, 0, st, a); break;
+    case KIND_TDDPS: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_S>), g, b, 0, st, a); break;
+    case KIND_TDDPXS: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_XS>), g, b, 0, st, a); break;
     case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, true>), g, b, 0, st, a); break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \

@@ -58,6 +58,11 @@ int n_free(const pdf_graph* g) {
 
 double column_ref(const pdf_graph* g, int col, hf_precision prec) {
   if (prec == HF_FP64) return 0.0;
+  // the time-dependent density reads t and sigma_t as stored
+  if (g->dz.node >= 0 && g->dz.tddp) {
+    const KNode& dn = g->prog.node[g->dz.node];
+    if (col == dn.col[2] || col == dn.col[3]) return 0.0;
+  }
   const ObsInfo& o = g->obs[g->obs_of_col[col]];
   if (finite(o.lo) && finite(o.hi)) return 0.5 * (o.lo + o.hi);
   return 0.0;
@@ -659,6 +664,20 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         }
         break;
       }
+      case OP_DPMAP: {
+        // cell boundaries of s12 and s13 in their columns' offset frames
+        const int n12 = (int)nd.consts[0], n13 = (int)nd.consts[1];
+        const double r12 = column_ref(g, kn.col[0], prec), r13 = column_ref(g, kn.col[1], prec);
+        for (int j = 0; j < n12 - 1; ++j) {
+          P.c64[c0 + j] = nd.consts[2 + j] - r12;
+          P.c32[c0 + j] = (float)P.c64[c0 + j];
+        }
+        for (int j = 0; j < n13 - 1; ++j) {
+          P.c64[c0 + n12 - 1 + j] = nd.consts[n12 + 1 + j] - r13;
+          P.c32[c0 + n12 - 1 + j] = (float)P.c64[c0 + n12 - 1 + j];
+        }
+        break;
+      }
       case OP_MAP: {
         // boundaries in the column's offset frame; Z = sum of the children's
         // shares of their ranges (each child normalised over the box)
@@ -804,6 +823,7 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
       for (int c : n.child) slots += node_slots(all[c]);
       return 2 + slots;
     }
+    case OP_DPMAP: return (int)n.consts[0] + (int)n.consts[1] - 2;
     case OP_EXP: return 5;
     case OP_GAUSS: return 6;
     case OP_POLY: return 2 * (int)n.par.size() + 3;
@@ -933,6 +953,36 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
           }
           break;
         }
+        case OP_DPMAP: {
+          // obs = (s12, s13, u); consts = (n12, n13, b12..., b13...)
+          rc = need(n.n_par == 0 && n.n_obs == 3 && n.n_const >= 2, "DPMAP takes (s12, s13, u), no parameters");
+          if (rc) break;
+          const double a12 = ni.consts[0], a13 = ni.consts[1];
+          rc = need(a12 >= 1 && a13 >= 1 && a12 <= kMaxNodes && a13 <= kMaxNodes && a12 == std::floor(a12) &&
+                        a13 == std::floor(a13) && n.n_const == (int)(a12 + a13) &&
+                        n.n_child == (int)(a12 * a13) && n.n_child >= 2,
+                    "DPMAP: consts (n12, n13, n12-1 s12 boundaries, n13-1 s13 boundaries), n12 x n13 >= 2 children");
+          for (int ax = 0; ax < 2 && !rc; ++ax) {
+            const int o = ni.obs[ax];
+            rc = need(finite_box(o), "DPMAP: s12 and s13 need finite boxes");
+            const int nb = (int)(ax == 0 ? a12 : a13) - 1, b0 = ax == 0 ? 2 : 2 + (int)a12 - 1;
+            double prev = g->obs[o].lo;
+            for (int j = 0; j < nb && !rc; ++j) {
+              const double b = ni.consts[b0 + j];
+              rc = need(std::isfinite(b) && b > prev, "DPMAP boundaries must increase strictly inside the box");
+              prev = b;
+            }
+            if (!rc) rc = need(prev < g->obs[o].hi, "DPMAP boundaries must increase strictly inside the box");
+          }
+          for (int c : ni.child) {
+            if (rc) break;
+            const NodeInfo& cn = in[c];
+            rc = need((cn.op == OP_EXP || cn.op == OP_GAUSS || cn.op == OP_POLY) && cn.obs.size() == 1 &&
+                          cn.obs[0] == ni.obs[2],
+                      "DPMAP children must be EXP / GAUSS / POLY leaves on its third observable");
+          }
+          break;
+        }
         case OP_DALITZ:
         case OP_TDDP: {
           const bool td = n.op == OP_TDDP;
@@ -969,6 +1019,11 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       }
       if (rc) return rc;
     }
+    // a root PROD of a DPMAP and a TDDP node lists the TDDP node first (the
+    // product is symmetric; the fused kernel expects it as node 0)
+    if (in[root].op == OP_PROD && in[root].child.size() == 2 && in[in[root].child[0]].op == OP_DPMAP &&
+        in[in[root].child[1]].op == OP_TDDP)
+      std::swap(in[root].child[0], in[root].child[1]);
     // reachable nodes in post-order (children before parents, root last)
     std::vector<int> order, used(n_nodes, 0);
     std::function<int(int)> visit = [&](int k) -> int {
@@ -992,25 +1047,45 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     // observable sets; ADD children share one, PROD children are disjoint
     // apart from groups of one-observable leaves
     std::vector<std::set<int>> os(NN);
+    std::vector<int> dpmap_ok(NN, 0);
     int n_heavy = 0;
     for (int k = 0; k < NN; ++k) {
       NodeInfo& n = g->nodes[k];
       if (n.op == OP_ADD || n.op == OP_PROD) {
         // PROD: one-observable EXP / GAUSS / POLY children may share their
-        // observable (renormalised numerically); any other overlap is an error
-        std::set<int> leaf_only;
+        // observable (renormalised numerically); a DPMAP child conditions on
+        // the (s12, s13) of a DALITZ / TDDP sibling and may describe that
+        // TDDP's sigma_t; any other overlap is an error
+        std::set<int> leaf_only, claimed;
+        int dzc = -1;
+        if (n.op == OP_PROD)
+          for (int c : n.child)
+            if (g->nodes[c].op == OP_DALITZ || g->nodes[c].op == OP_TDDP) dzc = c;
         for (int c : n.child) {
           if (n.op == OP_ADD && os[c] != os[n.child[0]])
             return fail(HF_E_GRAPH, "ADD children must share the same observables");
+          // the observables this child adds to the product
+          std::set<int> own = os[c];
+          if (g->nodes[c].op == OP_DPMAP) {
+            const NodeInfo& dm = g->nodes[c];
+            if (n.op != OP_PROD || dzc < 0 || g->nodes[dzc].obs[0] != dm.obs[0] ||
+                g->nodes[dzc].obs[1] != dm.obs[1])
+              return fail(HF_E_GRAPH,
+                          "a DPMAP must be a PROD child beside the DALITZ / TDDP node on the same (s12, s13)");
+            dpmap_ok[c] = 1;
+            own = {dm.obs[2]};
+            if (g->nodes[dzc].op == OP_TDDP && g->nodes[dzc].obs[3] == dm.obs[2]) own.clear();
+          }
           const bool l1 = is_leaf1(g->nodes[c]);
-          for (int o : os[c]) {
-            if (n.op == OP_PROD && os[k].count(o) && !(l1 && leaf_only.count(o)))
+          for (int o : own) {
+            if (n.op == OP_PROD && claimed.count(o) && !(l1 && leaf_only.count(o)))
               return fail(HF_E_GRAPH,
                           "PROD children must have disjoint observables, except one-observable EXP / GAUSS / POLY "
                           "leaves, which may share one");
-            if (!os[k].count(o) && l1) leaf_only.insert(o);
-            os[k].insert(o);
+            if (!claimed.count(o) && l1) leaf_only.insert(o);
+            claimed.insert(o);
           }
+          for (int o : os[c]) os[k].insert(o);
         }
       } else {
         for (int o : n.obs) {
@@ -1021,6 +1096,9 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       if (n.op == OP_DALITZ || n.op == OP_TDDP) ++n_heavy;
     }
     if (n_heavy > 1) return fail(HF_E_GRAPH, "at most one DALITZ/TDDP node per graph");
+    for (int k = 0; k < NN; ++k)
+      if (g->nodes[k].op == OP_DPMAP && !dpmap_ok[k])
+        return fail(HF_E_GRAPH, "a DPMAP must be a PROD child beside the DALITZ / TDDP node on the same (s12, s13)");
     // columns: used observables in index order
     g->col_of_obs.assign(n_obs, -1);
     for (int o = 0; o < n_obs; ++o)
@@ -1056,6 +1134,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       kn.aux = 0;
       if (n.op == OP_POLY) kn.aux = (int32_t)n.par.size();
       if (n.op == OP_PROD) kn.aux = shared_groups(g->nodes, n).empty() ? 0 : 1;
+      if (n.op == OP_DPMAP) kn.aux = (int32_t)n.consts[1];
       if (n.op == OP_DALITZ || n.op == OP_TDDP) {
         const int R = (int)n.consts[6];
         kn.aux = (int32_t)R;
@@ -1170,6 +1249,11 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     else if (NN == 1 && rootn.op == OP_DALITZ) g->kind = KIND_DALITZ;
     else if (NN == 1 && rootn.op == OP_TDDP)
       g->kind = (int)rootn.par.size() == 2 * (int)rootn.consts[6] + 3 ? KIND_TDDPX : KIND_TDDP;
+    else if (NN >= 5 && rootn.op == OP_PROD && rootn.child.size() == 2 && P.node[0].op == OP_TDDP &&
+             P.node[NN - 2].op == OP_DPMAP && P.node[NN - 2].n_child == NN - 3 &&
+             P.node[NN - 2].col[2] == P.node[0].col[3])
+      // TDDP x sigma_t density of the event's Dalitz-plot cell: fused kernel
+      g->kind = (int)g->nodes[0].par.size() == 2 * (int)g->nodes[0].consts[6] + 3 ? KIND_TDDPXS : KIND_TDDPS;
     else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2 && NN <= 8) g->kind = KIND_TREE_SMALL;
     else g->kind = KIND_TREE;
     *out = g.release();

@@ -25,7 +25,8 @@ constexpr int kMaxPar = 64;
 constexpr int kNumGroups = 9;        // (pair, spin) groups of Dalitz resonances
 
 enum Op : int16_t {
-  OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7, OP_MAP = 8
+  OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7, OP_MAP = 8,
+  OP_DPMAP = 9
 };
 
 // Node fields are 32-bit so that the kernels read them from the kernel

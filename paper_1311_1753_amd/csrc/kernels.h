@@ -15,6 +15,8 @@ enum KernelKind {
   KIND_TDDP = 4,        // single TDDP leaf
   KIND_TREE = 5,        // any tree
   KIND_TDDPX = 6,       // single TDDP leaf with x free (trigonometric terms)
+  KIND_TDDPS = 7,       // PROD of a TDDP leaf (x = 0) and a DPMAP on its s12, s13, sigma_t
+  KIND_TDDPXS = 12,     // the same with x free
   // root ADD of 2 (3) single-column EXP/GAUSS leaves: KIND_MIX2 (KIND_MIX3)
   // plus a mask with bit j set when child j is a GAUSS
   KIND_MIX2 = 8,

@@ -7,8 +7,9 @@ Full-size Dalitz events: the 10^6-event amplitude workload uses the oracle's
 accept-reject sample; the 2x10^6-event time-dependent workload uses points
 uniform over the Dalitz plot with exponential decay times smeared by
 sigma_t ~ U[0.02, 0.2] (a cheaper sample of the same observables and ranges:
-the parity claim does not depend on the event distribution); the workload
-with the trigonometric terms (x free) reuses that sample."""
+the parity claim does not depend on the event distribution); the workloads
+with the trigonometric terms (x free) and with the sigma_t density of the
+Dalitz-plot cells reuse that sample."""
 import numpy as np
 import pytest
 
@@ -33,7 +34,7 @@ _cache = {}
 def full_data(name):
     if name in _cache:
         return _cache[name]
-    if name == "c4x":  # the same observables as c4
+    if name in ("c4x", "c4s"):  # the same observables as c4
         return full_data("c4")
     if name == "c2":
         d = S.gen_c2()
@@ -64,7 +65,7 @@ def full_data(name):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c4x"])
+@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c4x", "c4s"])
 def test_full_size_nll_grad(P, name, prec):
     print(f"\n[case] full-size {name} {prec}", flush=True)
     sp = get_spec(name)

@@ -33,6 +33,7 @@ CASES = [
     ("shared", 100_003, 26),
     ("shared_sum", 100_005, 27),
     ("shared_2d", 100_007, 28),
+    ("c4s", 20_047, 29),
 ]
 
 
@@ -89,13 +90,13 @@ def test_nll_and_gradient_match_oracle(P, stream, name, n, seed, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4s"])
 def test_batched_equals_single_bitwise(P, stream, name, prec):
     print(f"\n[case] batched {name} {prec}", flush=True)
     sp = get_spec(name)
     om = oracle_for(name)
     g = P.Graph.from_spec(sp)
-    sizes = [5_003, 37, 12_345] if name != "c3" else [1_501, 37, 3_000]
+    sizes = [5_003, 37, 12_345] if name not in ("c3", "c4s") else [1_501, 37, 3_000]
     dss, ths = [], []
     for i, n in enumerate(sizes):
         d = data_for(name, n, 100 + i)
@@ -195,6 +196,57 @@ def test_fit_shared_observable_product_matches_oracle_fit(P, stream, prec):
     assert r["status"] == "OK"
     assert dev.max() <= 1e-3
     assert np.all(np.abs(r["errors"][free] / ref["errors"][free] - 1) < 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tddp_sigma_map_child_order_is_irrelevant(P, stream, prec):
+    """The product of the time-dependent density and the sigma_t map, its
+    children listed either way round, gives the same bits (the fused kernel
+    takes the amplitude node first in both)."""
+    import copy
+    sp = get_spec("c4s")
+    sw = copy.deepcopy(sp)
+    sw["model"]["children"] = sw["model"]["children"][::-1]
+    data = data_for("c4s", 20_047, 29)
+    om = oracle_for("c4s")
+    th = perturbed_theta(om, sp, seed=5)
+    res = []
+    for s_ in (sp, sw):
+        g = P.Graph.from_spec(s_)
+        ds = P.Dataset(g, data, prec, stream)
+        res.append(P.nll_grad(g, ds, th, stream))
+    assert res[0][0] == res[1][0] and np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tddp_sigma_map_mixed_cells_match_oracle(P, stream, prec):
+    """The sigma_t map with an exponential, a quadratic and two Gaussian
+    cells (the fused kernel's general path, not the Gaussian selection)."""
+    import copy
+    from oracle import oracle as O
+    print(f"\n[case] c4s mixed cells {prec}", flush=True)
+    sp = copy.deepcopy(get_spec("c4s"))
+    dm = sp["model"]["children"][1]
+    dm["children"][0] = {"op": "exp", "obs": "sigma_t", "par": ["st_mu0"]}
+    dm["children"][1] = {"op": "poly", "obs": "sigma_t", "par": ["st_mu1", "st_sg1"], "x0": 0.11}
+    sp["params"] = [(p[0], p[1], p[2], 0.0, 0.0, p[5]) if p[0] in ("st_mu0", "st_mu1", "st_sg1") else p
+                    for p in sp["params"]]
+    # the exponential cell leaves st_sg0 unused
+    sp["params"] = [p[:5] + (True,) if p[0] == "st_sg0" else p for p in sp["params"]]
+    data = data_for("c4s", 20_047, 29)
+    om = O.Model(sp)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec, stream)
+    free = g.free_mask()
+    for k, th in enumerate([om.theta(sp["truth"]), perturbed_theta(om, sp, seed=9)]):
+        v_ref, g_ref = om.nll(th, data, grad=True)
+        v, gr = P.nll_grad(g, ds, th, stream)
+        s = nll_scale(om, th, data)
+        gs = grad_scale(om, th, data)
+        print(f"  theta#{k}: nll rel {abs(v - v_ref) / s:.2e}; grad rel max "
+              f"{np.max(np.abs(gr - g_ref)[free] / gs[free]):.2e}", flush=True)
+        assert abs(v - v_ref) <= TOL[prec] * s
+        assert np.all(np.abs(gr - g_ref)[free] <= TOL[prec] * gs[free])
 
 
 def test_numerical_gradient_fit_agrees(P, stream):

@@ -33,7 +33,8 @@ def test_library_exports_every_header_symbol():
 
 def test_graph_creation_for_every_workload():
     import paper_1311_1753_amd as P
-    for name in ("c1", "c2", "c3", "c4", "c4x", "listing2", "mapped", "mapped_sum"):
+    for name in ("c1", "c2", "c3", "c4", "c4x", "listing2", "mapped", "mapped_sum", "shared", "shared_sum",
+                 "shared_2d", "c4s"):
         g = P.Graph.from_spec(S.workload(name))
         assert g.n_par == len(S.workload(name)["params"])
 
@@ -79,6 +80,21 @@ def test_graph_validation_errors():
     dz["resonances"] = [dict(dz["resonances"][0], m0=0.2)] + dz["resonances"][1:]
     m["dalitz"] = dz
     _expect_graph_error(bad["obs"], bad["params"], m)
+    # DPMAP: alone (not beside a Dalitz node), wrong child count, boundaries
+    # outside the box, a child on another observable
+    c4s = S.workload("c4s")
+    dm = c4s["model"]["children"][1]
+    _expect_graph_error(c4s["obs"], c4s["params"], dm)
+    _expect_graph_error(c4s["obs"], c4s["params"], dict(c4s["model"], children=[
+        c4s["model"]["children"][0], dict(dm, children=dm["children"][:3])]))
+    _expect_graph_error(c4s["obs"], c4s["params"], dict(c4s["model"], children=[
+        c4s["model"]["children"][0], dict(dm, b12=[3.5])]))
+    _expect_graph_error(c4s["obs"], c4s["params"], dict(c4s["model"], children=[
+        c4s["model"]["children"][0], dict(dm, children=dm["children"][:3] + [
+            {"op": "exp", "obs": "t", "par": ["st_mu3"]}])]))
+    # ... beside a Dalitz node on (s13, s12) instead of (s12, s13)
+    _expect_graph_error(c4s["obs"], c4s["params"], dict(c4s["model"], children=[
+        c4s["model"]["children"][0], dict(dm, obs=["s13", "s12", "sigma_t"])]))
     # MAP: boundaries not increasing, on the box edge, wrong count, a child
     # that is not a leaf on the MAP's observable
     ga = {"op": "gauss", "obs": "x", "par": ["a", "b"]}

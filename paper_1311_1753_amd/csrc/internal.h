@@ -65,6 +65,11 @@ struct KProgram {
 //   MAP    0..K-2 inner range boundaries (double, in the column's offset frame),
 //          K-1 lnZ_hi, K lnZ_lo, then dlnZ/d(slot) for every slot of the
 //          children in child order (not hoisted; zeros when hoisted)
+//   PROD   with leaves sharing an observable: 0 lnZ_hi, 1 lnZ_lo, then
+//          dlnZ/d(slot) for every slot of the children in child order
+//          (zeros when hoisted); otherwise none
+//   DPMAP  0..n12-2 s12 cell boundaries, then n13-1 s13 boundaries (double,
+//          in the columns' offset frames); aux = n13
 //   DALITZ/TDDP: see the kDz* offsets below.
 // For the float path lnN is split into a float pair (hi + lo) so that the
 // rounding of the constant does not bias every event in the same direction.

@@ -197,6 +197,31 @@ int hf_column_ref(const pdf_graph* g, int32_t obs, hf_precision prec, double* re
 int dataset_upload_binned(const pdf_graph* g, const double* const* centres, const double* weights,
                           int64_t n_bins, double bin_volume, int32_t metric, hf_precision prec, void* hip_stream,
                           dataset** out);
+/* Device-side toy generation (the toy / pseudo-experiment fits of the
+ * paper's sections on fitting and of the serving loop, without moving their
+ * events over PCIe): a dataset of n_events events drawn from graph g's
+ * density at parameters params (n_par doubles), written in device memory on
+ * hip_stream in the storage format of prec; the call returns when they are
+ * written.  Sampleable graphs: an EXP or GAUSS leaf, an ADD of up to 4 such
+ * leaves on one observable, or a PROD of those over their observables.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011); uniform m of
+ * event i is taken from the block with counter (i mod 2^32, i div 2^32,
+ * m div 2, 0) and key (seed mod 2^32, seed div 2^32), words 0-1 (even m) or
+ * 2-3 (odd m) as u = (floor((w_a 2^32 + w_b) / 2^11) + 1/2) 2^-53.  Per event,
+ * the PROD's factors in order; an ADD takes one uniform to pick its child
+ * (the first j with u < f_0 + ... + f_j, the last child taking the rest);
+ * a leaf takes one uniform through its inverse CDF (EXP:
+ * lo + ln(1 + u (e^{alpha L} - 1)) / alpha; GAUSS:
+ * mu + sqrt(2) sigma erfinv(erf(z_lo) + u (erf(z_hi) - erf(z_lo)))), clamped
+ * to the box.  HF_E_GRAPH for other graphs; HF_E_DOMAIN for sigma <= 0,
+ * negative fractions or fractions summing above 1.  The same (graph, params,
+ * n, seed) give the same events; event i does not depend on n. */
+int dataset_generate(const pdf_graph* g, const double* params, int64_t n_events, uint64_t seed,
+                     hf_precision prec, void* hip_stream, dataset** out);
+/* Copies observable obs of an unbinned dataset to the host as doubles (the
+ * stored value, plus the column reference for HF_FP32_EVAL); host_out holds
+ * n_events doubles.  Blocking on hip_stream. */
+int dataset_read_column(const dataset* d, int32_t obs, void* hip_stream, double* host_out);
 void dataset_free(dataset* d);
 /* Device bytes held by a dataset (columns + workspace). */
 int64_t dataset_device_bytes(const dataset* d);

@@ -73,12 +73,14 @@ def _box(spec, name):
     raise KeyError(name)
 
 
-def generate(spec, theta, n, seed):
-    """Events of spec's model at parameters theta (dict of observable columns)."""
+def generate(spec, theta, n, seed, idx=None):
+    """Events of spec's model at parameters theta (dict of observable columns):
+    events 0 .. n-1, or those with the indices idx (n is then ignored)."""
     pidx = {p[0]: i for i, p in enumerate(spec["params"])}
     th = np.asarray(theta, dtype=np.float64)
     cols = {}
-    idx = np.arange(n, dtype=np.int64)
+    idx = np.arange(n, dtype=np.int64) if idx is None else np.asarray(idx, dtype=np.int64)
+    n = idx.size
     counter = np.zeros(n, dtype=np.int64)  # next uniform number of each event
 
     def draw(sel):
@@ -121,5 +123,5 @@ def generate(spec, theta, n, seed):
         else:
             leaf(node, sel)
 
-    node_(spec["model"], idx)
+    node_(spec["model"], np.arange(n))
     return cols

@@ -214,6 +214,32 @@ class Dataset:
         return self
 
     @classmethod
+    def generate(cls, graph, theta, n, seed, precision="fp64", stream=None):
+        """Toy dataset drawn on the device (dataset_generate): n events of the
+        graph's density at theta, Philox4x32-10 stream keyed by seed."""
+        self = cls.__new__(cls)
+        self.graph = graph
+        self.precision = _prec(precision)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if th.size != graph.n_par:
+            raise ValueError("theta needs one value per parameter")
+        h = ctypes.c_void_p()
+        check(lib().dataset_generate(graph.handle, th.ctypes.data_as(_lib._DP), int(n),
+                                     int(seed) & 0xFFFFFFFFFFFFFFFF, self.precision, _stream_ptr(stream),
+                                     ctypes.byref(h)))
+        self._keep = None
+        self._h = h
+        self.n = int(n)
+        return self
+
+    def column(self, name, stream=None):
+        """One observable's stored events as float64 (dataset_read_column)."""
+        out = np.empty(self.n)
+        check(lib().dataset_read_column(self.handle, self.graph.obs_names.index(name), _stream_ptr(stream),
+                                        out.ctypes.data_as(_lib._DP)))
+        return out
+
+    @classmethod
     def from_device(cls, graph, columns, precision="fp64"):
         """Borrows device tensors instead of copying (dataset_wrap_device):
         columns maps observable names to contiguous CUDA tensors -- float64

@@ -226,6 +226,46 @@ using namespace hf;
 
 // Upload of an unbinned dataset (metric 0) or of bin centres with weights
 // (metric 1 or 2).
+// Allocates a dataset of n events for graph g: one device block holding the
+// columns (256-byte aligned, storage format of `prec`), the binned weights
+// (metric != 0) and the partial rows of the evaluation kernels.
+static int make_dataset(const pdf_graph* g, int64_t n, hf_precision prec, int metric, double volume, const char* who,
+                        std::unique_ptr<dataset>& d) {
+  d.reset(new dataset);
+  const int nc = (int)g->obs_of_col.size();
+  d->g = g;
+  d->prec = prec;
+  d->n = n;
+  d->n_cols = nc;
+  const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
+  // binned datasets run the tree interpreter: one event per chunk and
+  // thread, partial columns [metric, tree slots, sum of dmetric/dlnP]
+  d->metric = metric;
+  d->volume = volume;
+  d->n_rows = rows_for(metric ? (int)KIND_TREE : g->kind, prec, n);
+  const int part_cols = metric ? g->n_slots_tree + 2 : g->prog.n_slots + 1;
+  const size_t col_bytes = align256((size_t)n * es);
+  const size_t w_bytes = metric ? align256((size_t)n * sizeof(double)) : 0;
+  const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * part_cols * sizeof(double));
+  const size_t total = col_bytes * nc + w_bytes + part_bytes;
+  void* blk = nullptr;
+  hipError_t e = hipMalloc(&blk, total);
+  if (e != hipSuccess) {
+    d.reset();
+    return fail(HF_E_OOM, std::string(who) + ": hipMalloc: " + hipGetErrorString(e));
+  }
+  d->block = blk;
+  d->bytes = (int64_t)total;
+  char* base = (char*)blk;
+  for (int c = 0; c < nc; ++c) {
+    d->col[c] = base + c * col_bytes;
+    d->ref[c] = column_ref(g, c, prec);
+  }
+  d->partials = (double*)(base + nc * col_bytes + w_bytes);
+  if (metric) d->wcol = (const double*)(base + nc * col_bytes);
+  return HF_OK;
+}
+
 static int upload(const pdf_graph* g, const double* const* host_cols, int64_t n, hf_precision prec,
                   void* hip_stream, int metric, const double* weights, double volume, dataset** out) {
   try {
@@ -258,35 +298,12 @@ static int upload(const pdf_graph* g, const double* const* host_cols, int64_t n,
           if (!(s[i] > 0.0)) return fail(HF_E_DOMAIN, "dataset_upload: sigma_t must be > 0");
       }
     }
-    std::unique_ptr<dataset> d(new dataset);
-    d->g = g;
-    d->prec = prec;
-    d->n = n;
-    d->n_cols = nc;
+    std::unique_ptr<dataset> d;
+    if (int rc = make_dataset(g, n, prec, metric, volume, "dataset_upload", d)) return rc;
     const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
-    // binned datasets run the tree interpreter: one event per chunk and
-    // thread, partial columns [metric, tree slots, sum of dmetric/dlnP]
-    d->metric = metric;
-    d->volume = volume;
-    d->n_rows = rows_for(metric ? (int)KIND_TREE : g->kind, prec, n);
-    const int part_cols = metric ? g->n_slots_tree + 2 : g->prog.n_slots + 1;
-    const size_t col_bytes = align256((size_t)n * es);
-    const size_t w_bytes = metric ? align256((size_t)n * sizeof(double)) : 0;
-    const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * part_cols * sizeof(double));
-    const size_t total = col_bytes * nc + w_bytes + part_bytes;
-    void* blk = nullptr;
-    hipError_t e = hipMalloc(&blk, total);
-    if (e != hipSuccess) return fail(HF_E_OOM, std::string("dataset_upload: hipMalloc: ") + hipGetErrorString(e));
-    d->block = blk;
-    d->bytes = (int64_t)total;
-    char* base = (char*)blk;
-    for (int c = 0; c < nc; ++c) {
-      d->col[c] = base + c * col_bytes;
-      d->ref[c] = column_ref(g, c, prec);
-    }
-    d->partials = (double*)(base + nc * col_bytes + w_bytes);
+    void* blk = d->block;
+    hipError_t e = hipSuccess;
     if (metric) {
-      d->wcol = (const double*)(base + nc * col_bytes);
       double ws = 0.0;
       for (int64_t i = 0; i < n; ++i) ws += weights[i];
       d->wsum = ws;
@@ -349,6 +366,137 @@ extern "C" int dataset_upload_binned(const pdf_graph* g, const double* const* ce
     if (!(weights[i] >= 0.0) || !std::isfinite(weights[i]))
       return fail(HF_E_INVALID, "dataset_upload_binned: weights must be finite and >= 0");
   return upload(g, centres, n_bins, prec, hip_stream, metric, weights, bin_volume, out);
+}
+
+// ---------------------------------------------------------------- toy generation
+namespace {
+
+// Sampling table of a graph at parameters th: the factors (root PROD
+// children, or the root) with their leaves.  HF_E_GRAPH for a tree that is
+// not sampleable, HF_E_DOMAIN for parameters outside the density's domain.
+int gen_table(const pdf_graph* g, const double* th, GenArgs& a) {
+  const int NN = (int)g->nodes.size();
+  const NodeInfo& root = g->nodes[NN - 1];
+  std::vector<int> factors;
+  if (root.op == OP_PROD) factors = root.child;
+  else factors = {NN - 1};
+  if ((int)factors.size() > kMaxCols) return fail(HF_E_GRAPH, "dataset_generate: too many factors");
+  const char* kShape =
+      "dataset_generate: sampleable graphs are EXP / GAUSS leaves, ADDs of up to 4 such leaves on one "
+      "observable, and PRODs of those";
+  int nl = 0;
+  a.n_factor = (int)factors.size();
+  for (int f = 0; f < a.n_factor; ++f) {
+    const NodeInfo& fn = g->nodes[factors[f]];
+    std::vector<int> leaves;
+    if (fn.op == OP_ADD) leaves = fn.child;
+    else leaves = {factors[f]};
+    if ((int)leaves.size() > kMaxGenLeaf) return fail(HF_E_GRAPH, kShape);
+    a.first[f] = nl;
+    a.n_leaf[f] = (int)leaves.size();
+    double cum = 0.0;
+    for (size_t q = 0; q < leaves.size(); ++q) {
+      const NodeInfo& ln = g->nodes[leaves[q]];
+      if (!(ln.op == OP_EXP || ln.op == OP_GAUSS)) return fail(HF_E_GRAPH, kShape);
+      if (ln.obs[0] != g->nodes[leaves[0]].obs[0]) return fail(HF_E_GRAPH, kShape);
+      GenLeaf& L = a.leaf[nl++];
+      const ObsInfo& o = g->obs[ln.obs[0]];
+      L.op = ln.op;
+      L.pad = 0;
+      L.lo = o.lo;
+      L.hi = o.hi;
+      if (fn.op == OP_ADD && q + 1 < leaves.size()) {
+        const double fq = th[fn.par[q]];
+        if (!(fq >= 0.0)) return fail(HF_E_DOMAIN, "dataset_generate: fractions must be >= 0");
+        cum += fq;
+      }
+      L.cum = fn.op == OP_ADD && q + 1 < leaves.size() ? cum : 2.0;
+      if (ln.op == OP_EXP) {
+        const double al = th[ln.par[0]];
+        L.p0 = al;
+        L.p1 = std::expm1(al * (o.hi - o.lo));
+        L.p2 = L.p3 = 0.0;
+      } else {
+        const double mu = th[ln.par[0]], sg = th[ln.par[1]];
+        if (!(sg > 0.0)) return fail(HF_E_DOMAIN, "dataset_generate: sigma must be > 0");
+        L.p0 = mu;
+        L.p1 = std::sqrt(2.0) * sg;
+        L.p2 = std::erf((o.lo - mu) / L.p1);
+        L.p3 = std::erf((o.hi - mu) / L.p1);
+        if (!(L.p3 > L.p2)) return fail(HF_E_DOMAIN, "dataset_generate: Gaussian without weight in its box");
+      }
+    }
+    if (fn.op == OP_ADD && cum > 1.0) return fail(HF_E_DOMAIN, "dataset_generate: fractions sum above 1");
+    a.col[f] = g->col_of_obs[g->nodes[leaves[0]].obs[0]];
+    for (int h = 0; h < f; ++h)
+      if (a.col[h] == a.col[f])
+        return fail(HF_E_GRAPH, "dataset_generate: product factors on a shared observable are not sampleable");
+  }
+  return HF_OK;
+}
+
+}  // namespace
+
+extern "C" int dataset_generate(const pdf_graph* g, const double* params, int64_t n, uint64_t seed,
+                                hf_precision prec, void* hip_stream, dataset** out) {
+  try {
+    if (!g || !params || !out) return fail(HF_E_INVALID, "dataset_generate: NULL argument");
+    if (n < 0 || n > (int64_t(1) << 36)) return fail(HF_E_INVALID, "dataset_generate: n_events out of range");
+    if (prec != HF_FP64 && prec != HF_FP32_EVAL) return fail(HF_E_INVALID, "dataset_generate: bad precision");
+    for (size_t p = 0; p < g->par.size(); ++p)
+      if (!std::isfinite(params[p])) return fail(HF_E_INVALID, "dataset_generate: parameter not finite");
+    GenArgs a;
+    std::memset(&a, 0, sizeof(a));
+    if (int rc = gen_table(g, params, a)) return rc;
+    std::unique_ptr<dataset> d;
+    if (int rc = make_dataset(g, n, prec, 0, 0.0, "dataset_generate", d)) return rc;
+    a.n = n;
+    a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(seed >> 32);
+    a.fp32 = prec == HF_FP32_EVAL ? 1 : 0;
+    for (int f = 0; f < a.n_factor; ++f) {
+      a.out[f] = const_cast<void*>(d->col[a.col[f]]);
+      a.ref[f] = d->ref[a.col[f]];
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = launch_generate(a, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      hipFree(d->block);
+      return hip_fail(e, "dataset_generate");
+    }
+    *out = d.release();
+    return HF_OK;
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("dataset_generate: ") + ex.what());
+  }
+}
+
+extern "C" int dataset_read_column(const dataset* d, int32_t obs, void* hip_stream, double* host_out) {
+  try {
+    if (!d || !host_out) return fail(HF_E_INVALID, "dataset_read_column: NULL argument");
+    const pdf_graph* g = d->g;
+    if (obs < 0 || obs >= (int)g->obs.size() || g->col_of_obs[obs] < 0)
+      return fail(HF_E_INVALID, "dataset_read_column: observable not stored");
+    if (d->metric) return fail(HF_E_INVALID, "dataset_read_column: binned datasets hold bin centres only");
+    const int c = g->col_of_obs[obs];
+    const size_t es = d->prec == HF_FP32_EVAL ? 4 : 8;
+    if (d->n == 0) return HF_OK;
+    std::vector<char> buf((size_t)d->n * es);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(buf.data(), d->col[c], buf.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "dataset_read_column");
+    if (es == 8) {
+      std::memcpy(host_out, buf.data(), buf.size());
+    } else {
+      const float* f = (const float*)buf.data();
+      for (int64_t i = 0; i < d->n; ++i) host_out[i] = (double)f[i] + d->ref[c];
+    }
+    return HF_OK;
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("dataset_read_column: ") + ex.what());
+  }
 }
 
 extern "C" int hf_column_ref(const pdf_graph* g, int32_t obs, hf_precision prec, double* ref) {

@@ -48,6 +48,29 @@ hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, hipStream_t st);
 hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,
                                const float* c32, int n_const, int grid, hipStream_t st);
 
+// Device-side toy generation.  Factors (the children of a root PROD, or the
+// root alone) each fill one column; a factor is one leaf, or an ADD of up to
+// kMaxGenLeaf leaves on one observable picked with the cumulative fractions.
+constexpr int kMaxGenLeaf = 4;
+constexpr int kMaxGenLeaves = kMaxCols * kMaxGenLeaf;
+struct GenLeaf {
+  int32_t op;        // OP_EXP or OP_GAUSS
+  int32_t pad;
+  double cum;        // cumulative fraction up to this leaf (the factor's last leaf: unused)
+  double lo, hi;     // the observable's box
+  double p0, p1, p2, p3;  // EXP: alpha, e^{alpha L} - 1; GAUSS: mu, sqrt(2) sigma, erf(z_lo), erf(z_hi)
+};
+struct GenArgs {
+  int64_t n;
+  uint32_t key0, key1;                 // Philox key (the seed's low and high words)
+  int32_t n_factor, fp32;
+  int32_t first[kMaxCols], n_leaf[kMaxCols], col[kMaxCols];
+  double ref[kMaxCols];                // FP32-eval storage reference per factor's column
+  void* out[kMaxCols];                 // per factor: its column (double, or float offsets)
+  GenLeaf leaf[kMaxGenLeaves];
+};
+hipError_t launch_generate(const GenArgs& a, hipStream_t st);
+
 // Dalitz normalisation grid: M[w][p][q] for w in {I, Ibar, J} (n_mat of them),
 // complex, unscaled by the cell area.  `out_host` receives n_mat * na * na * 2
 // doubles.  Blocking.

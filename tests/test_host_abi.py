@@ -147,3 +147,27 @@ def test_dalitz_membership_matches_oracle_rule(oracle_mod):
     ref = np.array([oracle_mod.inside(dz, x, y) for x, y in zip(a, b)])
     assert (mine == ref).all()
     assert 0.4 < mine.mean() < 0.55
+
+
+def test_toy_generation_refuses_unsampleable_graphs_and_bad_parameters():
+    """dataset_generate's checks run on the host before any device work."""
+    import paper_1311_1753_amd as P
+    for name in ("c3", "mapped", "shared", "poly"):
+        sp = S.workload(name) if name != "poly" else {
+            "obs": [("x", -1.0, 3.0)], "params": [("a1", 0.2, 0.05, 0, 0, False)],
+            "model": {"op": "poly", "obs": "x", "par": ["a1"], "x0": 1.0}}
+        g = P.Graph.from_spec(sp)
+        with pytest.raises(P.HipfitError) as ei:
+            P.Dataset.generate(g, g.theta(sp.get("truth")), 10, 1)
+        assert ei.value.code == -2, (name, ei.value)
+    ee = {"obs": [("x", 0.0, 1.0)], "params": [("a", -1.0, 0.1, 0, 0, False), ("b", 1.0, 0.1, 0, 0, False)],
+          "model": {"op": "prod", "children": [{"op": "exp", "obs": "x", "par": ["a"]},
+                                               {"op": "exp", "obs": "x", "par": ["b"]}]}}
+    with pytest.raises(P.HipfitError) as ei:
+        P.Dataset.generate(P.Graph.from_spec(ee), [-1.0, 1.0], 10, 1)
+    assert ei.value.code == -2
+    g = P.Graph.from_spec(S.workload("c2"))
+    for th in ([0.3, 5.28, -0.003, -2.0], [-0.1, 5.28, 0.003, -2.0], [1.2, 5.28, 0.003, -2.0]):
+        with pytest.raises(P.HipfitError) as ei:
+            P.Dataset.generate(g, th, 10, 1)
+        assert ei.value.code == -6, (th, ei.value)

@@ -37,7 +37,7 @@ PROFILE_EVERY = 10
 # sources it was measured on (sha256 of KERNEL_SOURCES), else reported as null.
 KERNEL_SOURCES = ["paper_1311_1753_amd/csrc/eval_kernels.hip", "paper_1311_1753_amd/csrc/device_common.h",
                   "paper_1311_1753_amd/csrc/internal.h", "paper_1311_1753_amd/csrc/kernels.h"]
-MEASURED_TRAFFIC = {"sha256": "e1de97313d4ae432687ce29de0cfb6ebd727b9bd950a7937e7c8e030d394e474",
+MEASURED_TRAFFIC = {"sha256": "d1de49a0e24d0d615fb0680aa6764cacd054467a2c16d73c665b436e89a4eb53",
                     "bytes_per_launch": 40.35e6}
 
 
@@ -172,6 +172,17 @@ def serving_bench(P, S, n_req):
     srv.close()
     out["batched_fp32_open_loop"] = s_open
     out["batched_fp32_closed_loop"] = s_closed
+    # the same requests with their toys drawn on the device (dataset_generate)
+    # instead of generated on the host and uploaded
+    gen = lambda r, st: P.Dataset.generate(g, [r["alpha"]], r["n"], (S.C5["seed"] << 32) | r["id"], "fp32", st)
+    srv = P.FitServer(g, "fp32", max_slots=256, hbm_budget_bytes=32 << 30, upload_stream=up)
+    _, s_open_d = srv.run(reqs, None, start, realtime=True, dataset_of=gen)
+    _, s_closed_d = srv.run(reqs, None, start, realtime=False, dataset_of=gen)
+    srv.close()
+    out["batched_fp32_open_loop_device_toys"] = s_open_d
+    out["batched_fp32_closed_loop_device_toys"] = s_closed_d
+    log("serving (device toys): open p50 %.4f p99 %.4f s; closed %.1f fits/s" %
+        (s_open_d["p50_latency_s"], s_open_d["p99_latency_s"], s_closed_d["fits_per_s"]))
     # arrival-rate sweep: the same requests (first 1024) at higher Poisson rates
     sweep = []
     srv = P.FitServer(g, "fp32", max_slots=256, hbm_budget_bytes=32 << 30, upload_stream=up)

@@ -89,12 +89,15 @@ class FitServer:
         self.engine = BatchEngine(graph, max_slots, hbm_budget_bytes)
         self.upload_stream = upload_stream
 
-    def run(self, requests, columns_of, theta0_of=None, realtime=True, max_iter=500, edm_tol=1e-10):
+    def run(self, requests, columns_of, theta0_of=None, realtime=True, max_iter=500, edm_tol=1e-10,
+            dataset_of=None):
         """Serves `requests` (dicts with 'id' and 'arrival_s', in arrival order).
 
-        columns_of(req) -> event columns; theta0_of(req) -> start values.
-        realtime=False submits every request at t = 0 (closed loop).  Returns
-        (results by id, summary)."""
+        columns_of(req) -> event columns, uploaded from the host; or
+        dataset_of(req, stream) -> Dataset made on the device (e.g. a toy
+        drawn with Dataset.generate), columns_of then unused.
+        theta0_of(req) -> start values.  realtime=False submits every request
+        at t = 0 (closed loop).  Returns (results by id, summary)."""
         reqs = sorted(requests, key=lambda r: r["arrival_s"])
         arrivals = {r["id"]: (r["arrival_s"] if realtime else 0.0) for r in reqs}
         ready = queue.Queue()
@@ -110,7 +113,10 @@ class FitServer:
                         time.sleep(wait)
                     if stop.is_set():
                         return
-                    ds = Dataset(self.graph, columns_of(r), self.precision, self.upload_stream)
+                    if dataset_of is not None:
+                        ds = dataset_of(r, self.upload_stream)
+                    else:
+                        ds = Dataset(self.graph, columns_of(r), self.precision, self.upload_stream)
                     ready.put((r, ds))
             except Exception as e:  # surfaced by the main loop
                 errors.append(e)

@@ -99,3 +99,34 @@ def test_fit_server_closed_and_open_loop(P):
         assert res[r["id"]]["status"] == "OK"
         assert np.array_equal(res[r["id"]]["theta"], ref[r["id"]]["theta"])
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+
+
+def test_fit_server_with_device_toys(P):
+    """Requests whose toys are drawn on the device (Dataset.generate on the
+    upload stream): every fit converges, and each equals the engine's fit of
+    the same generated events uploaded from the host."""
+    import torch
+    print("\n[case] fit server, device toys", flush=True)
+    g = P.Graph.from_spec(get_spec("c1"))
+    reqs = requests(16, seed=11)
+    up = torch.cuda.Stream()
+    gen = lambda r, st: P.Dataset.generate(g, [r["alpha"]], r["n"], (5 << 32) | r["id"], "fp32", st)
+    srv = P.FitServer(g, "fp32", max_slots=8, hbm_budget_bytes=1 << 34, upload_stream=up)
+    res, summ = srv.run(reqs, None, lambda r: [-2.0], realtime=False, dataset_of=gen)
+    srv.close()
+    assert summ["n"] == len(reqs)
+    host = {r["id"]: {"x": gen(r, None).column("x")} for r in reqs}
+    eng = P.BatchEngine(g, max_slots=16, hbm_budget_bytes=1 << 34)
+    dss = {r["id"]: P.Dataset(g, host[r["id"]], "fp32") for r in reqs}
+    for r in reqs:
+        assert eng.admit(dss[r["id"]], [-2.0], tag=r["id"]) is not None
+    ref = {}
+    while len(ref) < len(reqs):
+        eng.step()
+        for q in eng.poll():
+            ref[q["tag"]] = q
+    eng.close()
+    for r in reqs:
+        assert res[r["id"]]["status"] == "OK"
+        assert np.array_equal(res[r["id"]]["theta"], ref[r["id"]]["theta"])
+        assert abs(res[r["id"]]["theta"][0] - r["alpha"]) < 5 * res[r["id"]]["errors"][0]

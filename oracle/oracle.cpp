@@ -48,6 +48,12 @@
 //          position; in a PROD with the DALITZ / TDDP node on (s12, s13) it
 //          completes the joint density (u may be the TDDP's sigma_t, on
 //          which that node is conditional).
+//   CONV   numerical convolution of a model M with a resolution R (section
+//          "Combining functions": ConvolutionPdf), both one-observable EXP /
+//          GAUSS / POLY leaves on x taken as unnormalised shapes f_M, f_R:
+//          P(x) = sum_k f_M(t_k) f_R(x - t_k) / Z over the N midpoints t_k of
+//          x's box, the residual x - t_k restricted to [d_lo, d_hi], and
+//          Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms)
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -65,7 +71,7 @@ namespace {
 const double kPi = 3.14159265358979323846;
 
 enum Kind { K_EXP = 1, K_GAUSS = 2, K_POLY = 3, K_ADD = 4, K_PROD = 5, K_DALITZ = 6, K_TDDP = 7, K_MAP = 8,
-            K_DPMAP = 9 };
+            K_DPMAP = 9, K_CONV = 10 };
 
 // ---------------------------------------------------------------- sums
 struct Neumaier {
@@ -292,6 +298,8 @@ struct Node {
   double x0 = 0.0;          // POLY expansion point
   std::vector<double> bounds;  // MAP: the K-1 inner range boundaries; DPMAP: b12
   std::vector<double> bounds2; // DPMAP: b13
+  int grid = 0;                // CONV: number of grid points
+  double d_lo = 0.0, d_hi = 0.0;  // CONV: residual range
   DalitzDef* dz = nullptr;  // DALITZ, TDDP
   int p_tau = -1, p_y = -1; // TDDP
   int p_x = -1;             // TDDP with the trigonometric terms (x free)
@@ -361,6 +369,32 @@ double leaf_integral(const Model& m, const Node& n, const double* th, double u, 
         dI[n.par[k - 1]] += w;
       }
       return I;
+    }
+    default:
+      return NAN;
+  }
+}
+
+// Unnormalised shape f of an EXP / GAUSS / POLY leaf at x (the forms of
+// leaf_integral) and d ln f / d theta added into g (dense); NaN when f <= 0.
+double leaf_shape(const Model& m, const Node& n, const double* th, double x, double* g) {
+  switch (n.kind) {
+    case K_EXP: {
+      const double a = m.lo[n.obs[0]];
+      g[n.par[0]] += x - a;
+      return std::exp(th[n.par[0]] * (x - a));
+    }
+    case K_GAUSS: {
+      const double mu = th[n.par[0]], sg = th[n.par[1]], z = (x - mu) / sg;
+      g[n.par[0]] += z / sg;
+      g[n.par[1]] += z * z / sg;
+      return std::exp(-0.5 * z * z);
+    }
+    case K_POLY: {
+      double f = 1.0;
+      for (size_t k = 1; k <= n.par.size(); ++k) f += th[n.par[k - 1]] * std::pow(x - n.x0, (double)k);
+      for (size_t k = 1; k <= n.par.size(); ++k) g[n.par[k - 1]] += std::pow(x - n.x0, (double)k) / f;
+      return f;
     }
     default:
       return NAN;
@@ -531,6 +565,30 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
       for (int p = 0; p < m.n_par; ++p) r.dlnN[p] = dZ[p] / Z;
       break;
     }
+    case K_CONV: {
+      // Z = sum_k f_M(t_k) int f_R over the residuals that keep x in the box
+      const Node& M = m.nodes[n.child[0]];
+      const Node& R = m.nodes[n.child[1]];
+      const double lo = m.lo[n.obs[0]], hi = m.hi[n.obs[0]], h = (hi - lo) / n.grid;
+      Neumaier Z;
+      std::vector<Neumaier> dZ(m.n_par);
+      std::vector<double> gm(m.n_par), dI(m.n_par);
+      for (int k = 0; k < n.grid; ++k) {
+        const double t = lo + (k + 0.5) * h;
+        const double u = std::max(lo - t, n.d_lo), v = std::min(hi - t, n.d_hi);
+        if (!(v > u)) continue;
+        std::fill(gm.begin(), gm.end(), 0.0);
+        std::fill(dI.begin(), dI.end(), 0.0);
+        const double fm = leaf_shape(m, M, th, t, gm.data());
+        const double I = leaf_integral(m, R, th, u, v, dI);
+        Z.add(fm * I);
+        for (int p = 0; p < m.n_par; ++p) dZ[p].add(fm * gm[p] * I + fm * dI[p]);
+      }
+      const double z = Z.value();
+      r.lnN = std::log(z);
+      for (int p = 0; p < m.n_par; ++p) r.dlnN[p] = dZ[p].value() / z;
+      break;
+    }
     default:
       break;  // ADD and PROD are normalised through their children
   }
@@ -594,6 +652,28 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
       size_t sel = 0;
       while (sel < n.bounds.size() && x >= n.bounds[sel]) ++sel;
       lp = node_eval(m, n.child[sel], ev, th, nn, g) - nn[id].lnN;
+      break;
+    }
+    case K_CONV: {
+      // sum over the grid of f_M(t_k) f_R(x - t_k), residual in [d_lo, d_hi]
+      const Node& M = m.nodes[n.child[0]];
+      const Node& R = m.nodes[n.child[1]];
+      const double x = ev[n.obs[0]], lo = m.lo[n.obs[0]], hi = m.hi[n.obs[0]], h = (hi - lo) / n.grid;
+      Neumaier S;
+      std::vector<Neumaier> dS(np);
+      std::vector<double> gk(np);
+      for (int k = 0; k < n.grid; ++k) {
+        const double t = lo + (k + 0.5) * h, d = x - t;
+        if (d < n.d_lo || d > n.d_hi) continue;
+        std::fill(gk.begin(), gk.end(), 0.0);
+        const double w = leaf_shape(m, M, th, t, gk.data()) * leaf_shape(m, R, th, d, gk.data());
+        S.add(w);
+        for (int p = 0; p < np; ++p) dS[p].add(w * gk[p]);
+      }
+      const double sv = S.value();
+      if (!(sv > 0.0)) return -INFINITY;
+      lp = std::log(sv) - nn[id].lnN;
+      for (int p = 0; p < np; ++p) g[p] = dS[p].value() / sv;
       break;
     }
     case K_DPMAP: {
@@ -744,6 +824,13 @@ int om_dpmap(Model* m, int o12, int o13, int ou, int n12, int n13, const int* ch
   Node n; n.kind = K_DPMAP; n.obs = {o12, o13, ou}; n.child.assign(child, child + n12 * n13);
   n.bounds.assign(b12, b12 + n12 - 1);
   n.bounds2.assign(b13, b13 + n13 - 1);
+  return push(m, n);
+}
+// CONV over observable obs: children model, resolution; N grid points;
+// residual range [d_lo, d_hi].
+int om_conv(Model* m, int obs, int model, int resolution, int grid, double d_lo, double d_hi) {
+  Node n; n.kind = K_CONV; n.obs = {obs}; n.child = {model, resolution}; n.grid = grid; n.d_lo = d_lo;
+  n.d_hi = d_hi;
   return push(m, n);
 }
 int om_prod(Model* m, int n_child, const int* child) {

@@ -20,7 +20,7 @@ import math
 
 __all__ = [
     "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "SHARED", "SHARED_SUM",
-    "SHARED_2D", "C4S", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
+    "SHARED_2D", "C4S", "CONV", "CONV_POLY", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -277,6 +277,39 @@ C4S = {
     "seed": 7,
 }
 
+# ---------------------------------------------------------------- CONV
+# Numerical convolution (ConvolutionPdf): an exponential model smeared by a
+# Gaussian resolution (residual range [-2, 2], 400 grid points), plus an
+# exponential background; and a quadratic model smeared by a one-sided
+# exponential resolution on [0, 1].
+CONV = {
+    "name": "conv_exp_gauss_plus_exp",
+    "obs": [("x", 0.0, 10.0)],
+    "params": [("c_alpha", -0.3, 0.05, -5.0, 5.0, False), ("r_mu", 0.0, 0.02, -1.0, 1.0, False),
+               ("r_sigma", 0.4, 0.02, 0.02, 2.0, False), ("c_f", 0.6, 0.05, 0.0, 1.0, False),
+               ("b_beta", -0.05, 0.02, -5.0, 5.0, False)],
+    "truth": {"c_alpha": -0.4, "r_mu": 0.05, "r_sigma": 0.3, "c_f": 0.7, "b_beta": -0.1},
+    "model": {"op": "add", "par": ["c_f"], "children": [
+        {"op": "conv", "obs": "x", "grid": 400, "d_lo": -2.0, "d_hi": 2.0, "children": [
+            {"op": "exp", "obs": "x", "par": ["c_alpha"]},
+            {"op": "gauss", "obs": "x", "par": ["r_mu", "r_sigma"]}]},
+        {"op": "exp", "obs": "x", "par": ["b_beta"]}]},
+    "n_events": 1_000_000,
+    "seed": 26,
+}
+CONV_POLY = {
+    "name": "conv_poly_onesided",
+    "obs": [("x", 0.0, 10.0)],
+    "params": [("p_a1", 0.05, 0.02, 0.0, 0.0, False), ("p_a2", -0.01, 0.005, 0.0, 0.0, False),
+               ("r_alpha", -3.0, 0.2, -20.0, -0.1, False)],
+    "truth": {"p_a1": 0.1, "p_a2": -0.02, "r_alpha": -4.0},
+    "model": {"op": "conv", "obs": "x", "grid": 256, "d_lo": 0.0, "d_hi": 1.0, "children": [
+        {"op": "poly", "obs": "x", "par": ["p_a1", "p_a2"], "x0": 5.0},
+        {"op": "exp", "obs": "x", "par": ["r_alpha"]}]},
+    "n_events": 1_000_000,
+    "seed": 27,
+}
+
 # ---------------------------------------------------------------- C5
 # Stream of toy fits of the C1 model with uneven event counts.
 C5 = {
@@ -309,4 +342,4 @@ LISTING2 = {
 def workload(name):
     return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2, "mapped": MAPPED,
             "mapped_sum": MAPPED_SUM, "shared": SHARED, "shared_sum": SHARED_SUM, "shared_2d": SHARED_2D,
-            "c4s": C4S}[name]
+            "c4s": C4S, "conv": CONV, "conv_poly": CONV_POLY}[name]

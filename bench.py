@@ -64,14 +64,15 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 5 times (reference for the HBM byte counters)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4x", "c4s", "mapped", "mapped_sum",
-                             "shared", "shared_sum", "c1l", "c2l"],
+                             "shared", "shared_sum", "conv", "conv_poly", "c1l", "c2l"],
                     help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
                          "c3 Dalitz amplitude sum, c4 time-dependent Dalitz (c4x with x free: the "
                          "trigonometric terms; c4s times the sigma_t density that varies across "
                          "the plot), mapped / mapped_sum the piecewise density (alone / "
                          "added to an exponential, 1e7 events), shared / shared_sum a Gaussian times "
                          "an acceptance polynomial on the same observable (alone / added to an "
-                         "exponential, 1e7 events), c1l / c2l the c1 / c2 "
+                         "exponential, 1e7 events), conv / conv_poly numerical convolutions "
+                         "(1e6 events), c1l / c2l the c1 / c2 "
                          "models at 2^28 / 10^8 events (beyond the last-level cache): throughput only")
     return ap.parse_args()
 
@@ -218,8 +219,9 @@ def other_workload(args, P, S, torch, stream):
         data = S.gen_c1(n=n, seed=spec["seed"])
     elif base == "c2":
         data = S.gen_c2(n=n, seed=spec["seed"])
-    elif base in ("mapped", "mapped_sum", "shared", "shared_sum"):
-        data = {"x": np.random.default_rng(spec["seed"]).uniform(0.0, 10.0, n)}
+    elif base in ("mapped", "mapped_sum", "shared", "shared_sum", "conv", "conv_poly"):
+        # (conv_poly's density is zero below its first grid point)
+        data = {"x": np.random.default_rng(spec["seed"]).uniform(0.1 if base == "conv_poly" else 0.0, 10.0, n)}
     else:
         data = S.gen_flat_box(n, spec["seed"], g.dalitz_inside)
         if args.workload in ("c4", "c4x", "c4s"):

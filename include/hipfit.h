@@ -111,7 +111,17 @@ enum hf_op {
                         par; consts = {n12, n13, b12 (n12 - 1, increasing), b13 (n13 - 1)}.
                         Only as a PROD child beside the DALITZ / TDDP node on the same
                         (s12, s13); u may be that TDDP's sigma_t (which it then describes)
-                        or an observable no other child uses                                */
+                        or an observable no other child uses                                */,
+  HF_OP_CONV = 10    /* numerical convolution (section "Combining functions": ConvolutionPdf):
+                        P(x) = sum_k f_M(t_k) f_R(x - t_k) / Z over the N midpoints t_k of x's
+                        box, the residual x - t_k restricted to [d_lo, d_hi]; children =
+                        {model, resolution}, one-observable EXP / GAUSS / POLY (degree <= 4)
+                        leaves on x taken as unnormalised shapes f (EXP e^{alpha (v - lo)},
+                        GAUSS e^{-(v - mu)^2 / (2 sigma^2)}, POLY 1 + sum a_j (v - x0)^j, v
+                        the model's t or the resolution's residual);
+                        Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms, on the
+                        host); obs = {x}; no par; consts = {N (2..4096), d_lo, d_hi}; the
+                        per-event sum runs over all N points (cost ~ N per event)            */
 };
 
 /* DALITZ block of node constants:

@@ -83,6 +83,8 @@ class Graph:
                 consts = dalitz_consts(node["dalitz"])
             elif op == "map":
                 consts = [float(b) for b in node["bounds"]]
+            elif op == "conv":
+                consts = [float(node["grid"]), float(node["d_lo"]), float(node["d_hi"])]
             elif op == "dpmap":
                 b12, b13 = [float(b) for b in node["b12"]], [float(b) for b in node["b13"]]
                 consts = [len(b12) + 1.0, len(b13) + 1.0] + b12 + b13

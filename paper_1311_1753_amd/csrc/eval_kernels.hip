@@ -633,6 +633,15 @@ constexpr int OP_TDDP_X = 16;
 // and give the wave E independent instruction chains.
 template <typename T, int OP> struct AmpEvents { static constexpr int value = OP == OP_DALITZ ? 2 : 1; };
 
+// A CONV child at x (offset frame) as an unnormalised shape: ln f and
+// d ln f / d(slot) in d[0 .. n_slot).
+template <typename T>
+__device__ __forceinline__ T conv_leaf(const CS& cs, const KNode& cn, double x, T (&d)[8]) {
+  if (cn.op == OP_EXP) return leaf_exp<T>(cs, cn.c0, true, x, d);
+  if (cn.op == OP_GAUSS) return leaf_gauss<T>(cs, cn.c0, true, x, d);
+  return leaf_poly<T>(cs, cn.c0, cn.aux, true, x, d);
+}
+
 // General trees (ADD / PROD over leaves).  Node log-values, adjoints and the
 // per-event slot derivatives live in small VGPR arrays indexed by
 // wave-uniform node / slot numbers.
@@ -724,6 +733,44 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
           }
         }
         if (!h) v = (v - cs.get<T>(c0 + K - 1)) - cs.get<T>(c0 + K);
+      } else if (HEAVY && op == OP_CONV) {
+        // numerical convolution: sum over the grid t_k of f_M(t_k) f_R(x - t_k)
+        // with the residual in [d_lo, d_hi] and the exponents shifted by c;
+        // the children's slots receive the convolution's derivatives
+        const int N = nd.aux;
+        const int chm = P.child[nd.child0], chr = P.child[nd.child0 + 1];
+        const KNode& cm = P.node[chm];
+        const KNode& cr = P.node[chr];
+        const int nm = cm.n_slot, nr = cr.n_slot;
+        const double x = xe[nd.col[0]];
+        const double t0 = cs.d[c0], hh = cs.d[c0 + 1], dlo = cs.d[c0 + 2], dhi = cs.d[c0 + 3], ref = cs.d[c0 + 4];
+        const T shift = cs.get<T>(c0 + 5);
+        T S = T(0), gm[8], gr[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) gm[j] = gr[j] = T(0);
+        for (int k = 0; k < N; ++k) {
+          const double t = t0 + k * hh, d = x - t;
+          T dm[8], dr[8];
+          const T lm = conv_leaf<T>(cs, cm, t, dm);
+          const T lr = conv_leaf<T>(cs, cr, d - ref, dr);
+          const T w = d >= dlo && d <= dhi ? Mth<T>::ex((lm + lr) - shift) : T(0);
+          S += w;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (j < nm) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
+            if (j < nr) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
+          }
+        }
+        const T iS = Mth<T>::rcp(S);
+        v = S > T(0) ? Mth<T>::ln(S) : T(-INFINITY);
+        v = (v - cs.get<T>(c0 + 6)) - cs.get<T>(c0 + 7);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (j < nm) dl[cm.slot0 + j] = gm[j] * iS - cs.get<T>(c0 + 8 + j);
+          if (j < nr) dl[cr.slot0 + j] = gr[j] * iS - cs.get<T>(c0 + 8 + nm + j);
+        }
+        resp[chm] = T(1);
+        resp[chr] = T(1);
       } else if (op == OP_DPMAP) {
         // the child of the event's cell on the s12 x s13 grid (row-major,
         // boundaries in the columns' offset frames) gives the value; the
@@ -777,7 +824,7 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
     for (int k = GRAD ? root : -1; k >= 0; --k) {
       const KNode& nd = P.node[k];
       const T a = adj[k];
-      if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP)
+      if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP || nd.op == OP_CONV)
         for (int j = 0; j < nd.n_child; ++j) {
           const int ch = P.child[nd.child0 + j];
           adj[ch] = a * resp[ch];

@@ -443,6 +443,41 @@ static HostLeaf host_leaf(const pdf_graph* g, const NodeInfo& nd, const double* 
   return h;
 }
 
+// int_u^v f of the unnormalised shape f of an EXP / GAUSS / POLY leaf (the
+// kernels' forms: EXP e^{alpha (x - lo)}, GAUSS e^{-(x - mu)^2 / (2 s^2)},
+// POLY 1 + sum a_j (x - x0)^j) and d/d(slot) of that integral; 0 when
+// v <= u.  `h` carries the parameters as the kernels see them.
+static double raw_integral(const HostLeaf& h, double lo, double u, double v, double* dI) {
+  for (int j = 0; j < h.n_slot; ++j) dI[j] = 0.0;
+  if (!(v > u)) return 0.0;
+  switch (h.op) {
+    case OP_EXP: {
+      double lnI, dln;
+      exp_norm(h.p[0], v - u, lnI, dln);
+      const double I = std::exp(h.p[0] * (u - lo) + lnI);
+      dI[0] = I * ((u - lo) + dln);
+      return I;
+    }
+    case OP_GAUSS: {
+      double lnI, dm, ds;
+      if (!gauss_norm(u, v, h.p[0], h.s, lnI, dm, ds)) return 0.0;
+      const double I = std::exp(lnI);
+      dI[0] = I * dm;
+      dI[1] = I * ds;
+      return I;
+    }
+    default: {
+      double I = v - u;
+      for (int j = 1; j <= h.n_slot; ++j) {
+        const double w = (std::pow(v - h.x0, j + 1) - std::pow(u - h.x0, j + 1)) / (j + 1);
+        I += h.p[j - 1] * w;
+        dI[j - 1] = w;
+      }
+      return I;
+    }
+  }
+}
+
 // Z = int_box prod_j P_j(x) dx over a group of one-observable leaves on one
 // observable, by composite 16-point Gauss-Legendre on segments no wider than
 // two of the narrowest Gaussian's widths and four decay lengths of the
@@ -533,14 +568,24 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
     P.c32[i_hi] = h;
     P.c32[i_lo] = l;
   };
+  // children of CONV nodes enter as unnormalised shapes: no normalisation
+  // of their own (and no domain check over the box)
+  std::vector<char> conv_child(P.n_nodes, 0);
+  for (int k = 0; k < P.n_nodes; ++k)
+    if (P.node[k].op == OP_CONV)
+      for (int c : g->nodes[k].child) conv_child[c] = 1;
   for (int k = 0; k < P.n_nodes; ++k) {
     const KNode& kn = P.node[k];
     const NodeInfo& nd = g->nodes[k];
     const int c0 = kn.c0;
     const bool hoist = kn.hoisted != 0;
+    const bool shape_only = conv_child[k] != 0;
     auto norm_terms = [&](double lnN, const std::vector<std::pair<int, double>>& d, int i_hi, int i_lo,
                           int i_d0) {
-      if (hoist) {
+      if (shape_only) {
+        set_ln(i_hi, i_lo, 0.0);
+        for (size_t j = 0; j < d.size(); ++j) setc(i_d0 + (int)j, 0.0);
+      } else if (hoist) {
         sc.ht.lnN += lnN;
         for (auto& pd : d) sc.ht.dlnN[pd.first] += pd.second;
         set_ln(i_hi, i_lo, 0.0);
@@ -573,7 +618,7 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         const double k1 = rnd(1.0 / th[nd.par[1]]);
         const double s = fp32 ? 1.0 / k1 : th[nd.par[1]];
         double lnN = 0, dmu = 0, ds = 0;
-        if (!gauss_norm(o.lo, o.hi, mu, s, lnN, dmu, ds)) sc.ok = false;
+        if (!gauss_norm(o.lo, o.hi, mu, s, lnN, dmu, ds) && !shape_only) sc.ok = false;
         P.c64[c0] = column_ref(g, col, prec) - mu;
         P.c32[c0] = 0.0f;
         setc(c0 + 1, k1);
@@ -595,7 +640,7 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
           N += a * w[j - 1];
           setc(c0 + j, a);
         }
-        if (!(N > 0.0)) { sc.ok = false; N = 1.0; }
+        if (!(N > 0.0)) { sc.ok = sc.ok && shape_only; N = 1.0; }
         std::vector<std::pair<int, double>> dv;
         for (int j = 0; j < d; ++j) dv.push_back({nd.par[j], w[j] / N});
         norm_terms(std::log(N), dv, c0 + d + 1, c0 + d + 2, c0 + d + 3);
@@ -661,6 +706,68 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
           set_ln(c0, c0 + 1, 0.0);
         } else {
           set_ln(c0, c0 + 1, lnZ);
+        }
+        break;
+      }
+      case OP_CONV: {
+        // grid t_k = lo + (k + 1/2) h; Z = sum_k f_M(t_k) int_{box} f_R(x - t_k) dx
+        const int N = kn.aux, col = kn.col[0];
+        const ObsInfo& o = g->obs[g->obs_of_col[col]];
+        const double ref = column_ref(g, col, prec), h = (o.hi - o.lo) / N;
+        const double dlo = nd.consts[1], dhi = nd.consts[2];
+        // (the box normalisations host_leaf checks are the model's; the
+        // resolution lives on the residual range)
+        bool ok = true, ok_r = true;
+        HostLeaf M = host_leaf(g, g->nodes[nd.child[0]], th, rnd, fp32, ok);
+        HostLeaf R = host_leaf(g, g->nodes[nd.child[1]], th, rnd, fp32, ok_r);
+        if (R.op == OP_GAUSS && !(R.s > 0.0)) ok = false;
+        M.lnN = R.lnN = 0.0;  // shapes
+        for (int j = 0; j < 8; ++j) M.dN[j] = R.dN[j] = 0.0;
+        const int nm = M.n_slot, nr = R.n_slot;
+        // exponent shift: the shapes' maxima over the grid and the residual range
+        double cm = -INFINITY, cr = -INFINITY, l, d[8];
+        for (int k = 0; k < N; ++k)
+          if (M.eval(o.lo + (k + 0.5) * h, l, d)) cm = std::max(cm, l);
+        for (int k = 0; k <= 256; ++k)
+          if (R.eval(dlo + (dhi - dlo) * k / 256.0, l, d)) cr = std::max(cr, l);
+        if (R.op == OP_GAUSS && R.p[0] > dlo && R.p[0] < dhi) cr = std::max(cr, 0.0);
+        const double shift = std::isfinite(cm) && std::isfinite(cr) ? cm + cr : 0.0;
+        double Z = 0.0;
+        std::vector<double> dZ(nm + nr, 0.0);
+        double dm[8], dI[8];
+        for (int k = 0; k < N; ++k) {
+          const double t = o.lo + (k + 0.5) * h;
+          const double I = raw_integral(R, o.lo, std::max(o.lo - t, dlo), std::min(o.hi - t, dhi), dI);
+          if (I == 0.0 || !M.eval(t, l, dm)) continue;
+          const double fm = std::exp(l);
+          Z += fm * I;
+          for (int j = 0; j < nm; ++j) dZ[j] += fm * dm[j] * I;
+          for (int j = 0; j < nr; ++j) dZ[nm + j] += fm * dI[j];
+        }
+        if (!ok || !(Z > 0.0) || !std::isfinite(Z)) { sc.ok = false; Z = 1.0; }
+        P.c64[c0] = o.lo + 0.5 * h - ref;
+        P.c32[c0] = (float)P.c64[c0];
+        setc(c0 + 1, h);
+        setc(c0 + 2, dlo);
+        setc(c0 + 3, dhi);
+        setc(c0 + 4, ref);
+        setc(c0 + 5, shift);
+        const double lnZ = std::log(Z);
+        for (int j = 0; j < nm + nr; ++j) {
+          const double dz = dZ[j] / Z;
+          const NodeInfo& cn = g->nodes[nd.child[j < nm ? 0 : 1]];
+          if (hoist) {
+            sc.ht.dlnN[cn.par[j < nm ? j : j - nm]] += dz;
+            setc(c0 + 8 + j, 0.0);
+          } else {
+            setc(c0 + 8 + j, dz);
+          }
+        }
+        if (hoist) {
+          sc.ht.lnN += lnZ;
+          set_ln(c0 + 6, c0 + 7, -shift);
+        } else {
+          set_ln(c0 + 6, c0 + 7, lnZ - shift);
         }
         break;
       }
@@ -824,6 +931,7 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
       return 2 + slots;
     }
     case OP_DPMAP: return (int)n.consts[0] + (int)n.consts[1] - 2;
+    case OP_CONV: return 8 + node_slots(all[n.child[0]]) + node_slots(all[n.child[1]]);
     case OP_EXP: return 5;
     case OP_GAUSS: return 6;
     case OP_POLY: return 2 * (int)n.par.size() + 3;
@@ -950,6 +1058,24 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
             rc = need((cn.op == OP_EXP || cn.op == OP_GAUSS || cn.op == OP_POLY) && cn.obs.size() == 1 &&
                           cn.obs[0] == ni.obs[0],
                       "MAP children must be EXP / GAUSS / POLY leaves on the MAP's observable");
+          }
+          break;
+        }
+        case OP_CONV: {
+          // consts = (N, d_lo, d_hi); children = (model, resolution) leaves on obs
+          rc = need(n.n_child == 2 && n.n_par == 0 && n.n_obs == 1 && n.n_const == 3,
+                    "CONV takes a model and a resolution, one observable and (N, d_lo, d_hi)");
+          if (!rc) rc = need(finite_box(ni.obs[0]), "CONV needs a finite observable box");
+          if (!rc)
+            rc = need(ni.consts[0] >= 2 && ni.consts[0] <= kMaxConvGrid && ni.consts[0] == std::floor(ni.consts[0]) &&
+                          std::isfinite(ni.consts[1]) && std::isfinite(ni.consts[2]) && ni.consts[1] < ni.consts[2],
+                      "CONV: 2..4096 grid points and a residual range d_lo < d_hi");
+          for (int c : ni.child) {
+            if (rc) break;
+            const NodeInfo& cn = in[c];
+            rc = need((cn.op == OP_EXP || cn.op == OP_GAUSS || cn.op == OP_POLY) && cn.obs.size() == 1 &&
+                          cn.obs[0] == ni.obs[0] && cn.par.size() <= 4,
+                      "CONV children must be EXP / GAUSS / POLY (degree <= 4) leaves on its observable");
           }
           break;
         }
@@ -1135,6 +1261,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       if (n.op == OP_POLY) kn.aux = (int32_t)n.par.size();
       if (n.op == OP_PROD) kn.aux = shared_groups(g->nodes, n).empty() ? 0 : 1;
       if (n.op == OP_DPMAP) kn.aux = (int32_t)n.consts[1];
+      if (n.op == OP_CONV) kn.aux = (int32_t)n.consts[0];
       if (n.op == OP_DALITZ || n.op == OP_TDDP) {
         const int R = (int)n.consts[6];
         kn.aux = (int32_t)R;
@@ -1222,6 +1349,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     // kernel family
     const NodeInfo& rootn = g->nodes[NN - 1];
     bool heavy = g->dz.node >= 0;
+    for (const NodeInfo& n : g->nodes) heavy = heavy || n.op == OP_CONV;  // the general interpreter only
     // mixture of single-column EXP/GAUSS leaves: static kernel with its own
     // accumulator layout [3 per child], combined on the host (MixInfo)
     bool mix = rootn.op == OP_ADD && (NN == 3 || NN == 4) && (int)rootn.child.size() == NN - 1 && P.n_cols == 1;

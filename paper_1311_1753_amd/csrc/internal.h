@@ -26,8 +26,9 @@ constexpr int kNumGroups = 9;        // (pair, spin) groups of Dalitz resonances
 
 enum Op : int16_t {
   OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7, OP_MAP = 8,
-  OP_DPMAP = 9
+  OP_DPMAP = 9, OP_CONV = 10
 };
+constexpr int kMaxConvGrid = 4096;  // CONV grid points
 
 // Node fields are 32-bit so that the kernels read them from the kernel
 // argument with scalar loads at wave-uniform node indices (16-bit fields at
@@ -70,6 +71,10 @@ struct KProgram {
 //          (zeros when hoisted); otherwise none
 //   DPMAP  0..n12-2 s12 cell boundaries, then n13-1 s13 boundaries (double,
 //          in the columns' offset frames); aux = n13
+//   CONV   0 first grid point (offset frame), 1 grid step, 2 d_lo, 3 d_hi,
+//          4 column reference, 5 shift c of the exponents, 6 (lnZ - c)_hi,
+//          7 (lnZ - c)_lo, then dlnZ/d(slot) for the model's and the
+//          resolution's slots (not hoisted; zeros when hoisted); aux = N
 //   DALITZ/TDDP: see the kDz* offsets below.
 // For the float path lnN is split into a float pair (hi + lo) so that the
 // rounding of the constant does not bias every event in the same direction.

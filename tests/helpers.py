@@ -80,6 +80,23 @@ def gen_data(name, n, seed):
             near = np.abs(x - b) < 1e-5
             x[near] = b + 1e-5
         return {"x": x}
+    if name in ("conv", "conv_poly"):
+        m = oracle_model(name)
+        th = m.theta(S.workload(name)["truth"])
+        grid = np.linspace(0.0, 10.0, 4001)
+        dens = lambda x: np.exp(m.logpdf(th, {"x": x}))
+        x = S.gen_accept_reject_1d(n, seed, dens, 1.3 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)
+        # events within 1e-5 of a point where the residual range starts or ends
+        # at a grid point move 2e-5 away: there the float-rounded offsets of
+        # the FP32-eval path could include or drop that grid term
+        sp = S.workload(name)["model"]
+        sp = sp if sp["op"] == "conv" else sp["children"][0]
+        h = 10.0 / sp["grid"]
+        for edge in (sp["d_lo"], sp["d_hi"]):
+            r = np.mod(x - edge - 0.5 * h, h)
+            near = np.minimum(r, h - r) < 1e-5
+            x[near] += 2e-5
+        return {"x": np.clip(x, 0.0, 10.0)}
     if name in ("shared", "shared_sum", "shared_2d"):
         # x from the 1-D density (the 2-D product factorises: x from the shared
         # product, y from its exponential by inverting the CDF)

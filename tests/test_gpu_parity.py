@@ -34,6 +34,8 @@ CASES = [
     ("shared_sum", 100_005, 27),
     ("shared_2d", 100_007, 28),
     ("c4s", 20_047, 29),
+    ("conv", 50_021, 30),
+    ("conv_poly", 50_023, 31),
 ]
 
 
@@ -247,6 +249,32 @@ def test_tddp_sigma_map_mixed_cells_match_oracle(P, stream, prec):
               f"{np.max(np.abs(gr - g_ref)[free] / gs[free]):.2e}", flush=True)
         assert abs(v - v_ref) <= TOL[prec] * s
         assert np.all(np.abs(gr - g_ref)[free] <= TOL[prec] * gs[free])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fit_convolution_matches_oracle_fit(P, stream, prec):
+    """Fit of the smeared exponential plus background with the resolution
+    fixed (an exponential smeared by a Gaussian is the same exponential away
+    from the box's edges, so the resolution is barely constrained by these
+    data; in practice it comes from a calibration)."""
+    from oracle import oracle as O
+    print(f"\n[case] fit conv (fixed resolution) prec={prec}", flush=True)
+    sp = get_spec("conv")
+    sp["params"] = [p[:5] + (True,) if p[0] in ("r_mu", "r_sigma") else p for p in sp["params"]]
+    sp["params"] = [(p[0], sp["truth"][p[0]]) + tuple(p[2:]) if p[0] in ("r_mu", "r_sigma") else p
+                    for p in sp["params"]]
+    data = data_for("conv", 100_019, 32)
+    om = O.Model(sp)
+    ref = om.fit(data)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec, stream)
+    r = P.fit(g, ds, stream=stream)
+    free = g.free_mask()
+    dev = np.abs(r["theta"] - ref["theta"])[free] / ref["errors"][free]
+    print(f"  status {r['status']} n_eval {r['n_eval']}; max |dtheta|/sigma {dev.max():.2e}", flush=True)
+    assert r["status"] == "OK"
+    assert dev.max() <= 1e-3
+    assert np.all(np.abs(r["errors"][free] / ref["errors"][free] - 1) < 1e-3)
 
 
 def test_numerical_gradient_fit_agrees(P, stream):

@@ -34,7 +34,7 @@ def test_library_exports_every_header_symbol():
 def test_graph_creation_for_every_workload():
     import paper_1311_1753_amd as P
     for name in ("c1", "c2", "c3", "c4", "c4x", "listing2", "mapped", "mapped_sum", "shared", "shared_sum",
-                 "shared_2d", "c4s"):
+                 "shared_2d", "c4s", "conv", "conv_poly"):
         g = P.Graph.from_spec(S.workload(name))
         assert g.n_par == len(S.workload(name)["params"])
 
@@ -80,6 +80,11 @@ def test_graph_validation_errors():
     dz["resonances"] = [dict(dz["resonances"][0], m0=0.2)] + dz["resonances"][1:]
     m["dalitz"] = dz
     _expect_graph_error(bad["obs"], bad["params"], m)
+    # CONV: a grid of one point, an empty residual range, a child that is not a leaf
+    cv = S.workload("conv_poly")
+    for bad in (dict(cv["model"], grid=1), dict(cv["model"], d_lo=1.0, d_hi=1.0),
+                dict(cv["model"], children=[cv["model"]["children"][0], dict(cv["model"], grid=16)])):
+        _expect_graph_error(cv["obs"], cv["params"], bad)
     # DPMAP: alone (not beside a Dalitz node), wrong child count, boundaries
     # outside the box, a child on another observable
     c4s = S.workload("c4s")

@@ -180,6 +180,9 @@ int pdf_graph_shape(const pdf_graph* g, int32_t* n_obs, int32_t* n_par);
  * Dalitz events inside the plot): otherwise HF_E_DOMAIN and nothing is
  * allocated.  Event order is preserved.  n_events may be 0.  Blocks until the
  * copy is done; the caller keeps ownership of the host columns. */
+/* (Graphs with a CONV node: the events are stored sorted by that node's
+ * observable, all columns permuted alike; the likelihood does not depend on
+ * the order, and dataset_read_column returns the stored order.) */
 int dataset_upload(const pdf_graph* g, const double* const* host_cols, int64_t n_events,
                    hf_precision prec, void* hip_stream, dataset** out);
 /* Borrows columns that already live in device memory (e.g. tensors of a

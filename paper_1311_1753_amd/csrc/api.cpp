@@ -7,6 +7,7 @@
 // the host, launches the tile kernel and the fixed-order reduction on the
 // caller's stream, and reads the reduced row from pinned, device-mapped host
 // memory written directly by the reduction kernel.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -314,6 +315,20 @@ static int upload(const pdf_graph* g, const double* const* host_cols, int64_t n,
       }
     }
 
+    // events of graphs with a CONV node are stored sorted by that node's
+    // observable (the likelihood is a sum over events; neighbouring events
+    // then share their grid ranges, and a wave skips the grid points none of
+    // its events reaches)
+    std::vector<int64_t> perm;
+    if (!metric && n > 1)
+      for (const NodeInfo& nd : g->nodes)
+        if (nd.op == OP_CONV) {
+          const double* key = host_cols[nd.obs[0]];
+          perm.resize(n);
+          for (int64_t i = 0; i < n; ++i) perm[i] = i;
+          std::stable_sort(perm.begin(), perm.end(), [key](int64_t a, int64_t b) { return key[a] < key[b]; });
+          break;
+        }
     // convert through the pinned staging buffer, one chunk at a time
     if (n > 0) {
       std::lock_guard<std::mutex> lk(g_stage_mu);
@@ -328,7 +343,15 @@ static int upload(const pdf_graph* g, const double* const* host_cols, int64_t n,
         const double ref = d->ref[c];
         for (int64_t b = 0; b < n; b += per) {
           const int64_t m = std::min(per, n - b);
-          if (es == 4) {
+          if (!perm.empty()) {
+            if (es == 4) {
+              float* s = (float*)g_stage;
+              for (int64_t i = 0; i < m; ++i) s[i] = (float)(x[perm[b + i]] - ref);
+            } else {
+              double* s = (double*)g_stage;
+              for (int64_t i = 0; i < m; ++i) s[i] = x[perm[b + i]];
+            }
+          } else if (es == 4) {
             float* s = (float*)g_stage;
             for (int64_t i = 0; i < m; ++i) s[i] = (float)(x[b + i] - ref);
           } else {

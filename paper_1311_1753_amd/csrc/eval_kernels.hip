@@ -748,17 +748,22 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         T S = T(0), gm[8], gr[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) gm[j] = gr[j] = T(0);
+        // (the term's work sits under the residual-range test: a wave whose
+        // events all miss grid point k skips it, which on datasets stored
+        // sorted by x leaves about the range's share of the grid)
         for (int k = 0; k < N; ++k) {
           const double t = t0 + k * hh, d = x - t;
-          T dm[8], dr[8];
-          const T lm = conv_leaf<T>(cs, cm, t, dm);
-          const T lr = conv_leaf<T>(cs, cr, d - ref, dr);
-          const T w = d >= dlo && d <= dhi ? Mth<T>::ex((lm + lr) - shift) : T(0);
-          S += w;
+          if (d >= dlo && d <= dhi) {
+            T dm[8], dr[8];
+            const T lm = conv_leaf<T>(cs, cm, t, dm);
+            const T lr = conv_leaf<T>(cs, cr, d - ref, dr);
+            const T w = Mth<T>::ex((lm + lr) - shift);
+            S += w;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            if (j < nm) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
-            if (j < nr) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
+            for (int j = 0; j < 8; ++j) {
+              if (j < nm) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
+              if (j < nr) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
+            }
           }
         }
         const T iS = Mth<T>::rcp(S);

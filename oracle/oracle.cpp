@@ -54,6 +54,11 @@
 //          P(x) = sum_k f_M(t_k) f_R(x - t_k) / Z over the N midpoints t_k of
 //          x's box, the residual x - t_k restricted to [d_lo, d_hi], and
 //          Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms)
+//   COMP   function composition f(g(x)) (section "Combining functions":
+//          CompositePdf): g a POLY leaf's value 1 + sum a_j (x - x0)^j, f an
+//          EXP / GAUSS / POLY leaf's unnormalised shape evaluated at g,
+//          P(x) = f(g(x)) / Z, Z = int_box f(g(x)) dx (numerical, composite
+//          Gauss-Legendre)
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -71,7 +76,7 @@ namespace {
 const double kPi = 3.14159265358979323846;
 
 enum Kind { K_EXP = 1, K_GAUSS = 2, K_POLY = 3, K_ADD = 4, K_PROD = 5, K_DALITZ = 6, K_TDDP = 7, K_MAP = 8,
-            K_DPMAP = 9, K_CONV = 10 };
+            K_DPMAP = 9, K_CONV = 10, K_COMP = 11 };
 
 // ---------------------------------------------------------------- sums
 struct Neumaier {
@@ -401,6 +406,36 @@ double leaf_shape(const Model& m, const Node& n, const double* th, double x, dou
   }
 }
 
+// d ln f / dx of a leaf's unnormalised shape at x.
+double leaf_shape_dx(const Node& n, const double* th, double x) {
+  switch (n.kind) {
+    case K_EXP: return th[n.par[0]];
+    case K_GAUSS: return -(x - th[n.par[0]]) / (th[n.par[1]] * th[n.par[1]]);
+    case K_POLY: {
+      double f = 1.0, df = 0.0;
+      for (size_t k = 1; k <= n.par.size(); ++k) {
+        f += th[n.par[k - 1]] * std::pow(x - n.x0, (double)k);
+        df += k * th[n.par[k - 1]] * std::pow(x - n.x0, (double)(k - 1));
+      }
+      return df / f;
+    }
+    default:
+      return NAN;
+  }
+}
+
+// f(g(x)) of a COMP node and d ln f(g(x)) / d theta into gr (dense).
+double comp_value(const Model& m, const Node& n, const double* th, double x, double* gr) {
+  const Node& C = m.nodes[n.child[0]];
+  const Node& F = m.nodes[n.child[1]];
+  std::vector<double> gc(m.n_par, 0.0);
+  const double gval = leaf_shape(m, C, th, x, gc.data());  // gc = d ln g / d theta
+  const double fv = leaf_shape(m, F, th, gval, gr);        // gr = d ln f / d theta (shell)
+  const double dfdg = leaf_shape_dx(F, th, gval);
+  for (int p = 0; p < m.n_par; ++p) gr[p] += dfdg * gval * gc[p];
+  return fv;
+}
+
 double node_eval(const Model& m, int id, const double* ev, const double* th, const std::vector<NodeNorm>& nn,
                  double* g);
 
@@ -565,6 +600,29 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
       for (int p = 0; p < m.n_par; ++p) r.dlnN[p] = dZ[p] / Z;
       break;
     }
+    case K_COMP: {
+      // Z = int_box f(g(x)) dx by 200 x 16-point Gauss-Legendre
+      struct GL16 { double x[16], w[16]; };
+      static const GL16 gl = [] { GL16 q; gauss_legendre(16, q.x, q.w); return q; }();
+      const double lo = m.lo[n.obs[0]], hi = m.hi[n.obs[0]];
+      const int nseg = 200;
+      const double h = (hi - lo) / nseg;
+      Neumaier Z;
+      std::vector<Neumaier> dZ(m.n_par);
+      std::vector<double> gr(m.n_par);
+      for (int k = 0; k < nseg; ++k)
+        for (int i = 0; i < 16; ++i) {
+          const double x = lo + h * (k + 0.5 * (gl.x[i] + 1.0));
+          std::fill(gr.begin(), gr.end(), 0.0);
+          const double f = 0.5 * h * gl.w[i] * comp_value(m, n, th, x, gr.data());
+          Z.add(f);
+          for (int p = 0; p < m.n_par; ++p) dZ[p].add(f * gr[p]);
+        }
+      const double z = Z.value();
+      r.lnN = std::log(z);
+      for (int p = 0; p < m.n_par; ++p) r.dlnN[p] = dZ[p].value() / z;
+      break;
+    }
     case K_CONV: {
       // Z = sum_k f_M(t_k) int f_R over the residuals that keep x in the box
       const Node& M = m.nodes[n.child[0]];
@@ -652,6 +710,12 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
       size_t sel = 0;
       while (sel < n.bounds.size() && x >= n.bounds[sel]) ++sel;
       lp = node_eval(m, n.child[sel], ev, th, nn, g) - nn[id].lnN;
+      break;
+    }
+    case K_COMP: {
+      const double f = comp_value(m, n, th, ev[n.obs[0]], g);
+      if (!(f > 0.0)) return -INFINITY;
+      lp = std::log(f) - nn[id].lnN;
       break;
     }
     case K_CONV: {
@@ -831,6 +895,11 @@ int om_dpmap(Model* m, int o12, int o13, int ou, int n12, int n13, const int* ch
 int om_conv(Model* m, int obs, int model, int resolution, int grid, double d_lo, double d_hi) {
   Node n; n.kind = K_CONV; n.obs = {obs}; n.child = {model, resolution}; n.grid = grid; n.d_lo = d_lo;
   n.d_hi = d_hi;
+  return push(m, n);
+}
+// COMP over observable obs: children core (POLY), shell.
+int om_comp(Model* m, int obs, int core, int shell) {
+  Node n; n.kind = K_COMP; n.obs = {obs}; n.child = {core, shell};
   return push(m, n);
 }
 int om_prod(Model* m, int n_child, const int* child) {

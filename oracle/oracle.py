@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KINDS = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7, "map": 8, "dpmap": 9, "conv": 10}
+KINDS = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7, "map": 8, "dpmap": 9, "conv": 10, "comp": 11}
 _CH = {"12": 12, "13": 13, "23": 23}
 
 
@@ -57,6 +57,7 @@ def lib():
         L.om_add.argtypes = [vp, ctypes.c_int, ip, ip]
         L.om_prod.argtypes = [vp, ctypes.c_int, ip]
         L.om_map.argtypes = [vp, ctypes.c_int, ctypes.c_int, ip, dp]
+        L.om_comp.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.om_conv.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double]
         L.om_dpmap.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp]
@@ -152,6 +153,10 @@ class Model:
             kk, kp = _ip(kids)
             b = np.ascontiguousarray(node["bounds"], dtype=np.float64)
             nid = L.om_map(self._h, self._o(node["obs"]), len(kids), kp, _dp(b))
+        elif op == "comp":
+            # children: core (POLY, its value is the argument), shell
+            kids = [self._add(c) for c in node["children"]]
+            nid = L.om_comp(self._h, self._o(node["obs"]), kids[0], kids[1])
         elif op == "conv":
             # children: model, resolution (one-observable leaves on obs)
             kids = [self._add(c) for c in node["children"]]

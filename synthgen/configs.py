@@ -20,7 +20,7 @@ import math
 
 __all__ = [
     "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "SHARED", "SHARED_SUM",
-    "SHARED_2D", "C4S", "CONV", "CONV_POLY", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
+    "SHARED_2D", "C4S", "CONV", "CONV_POLY", "COMP", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -310,6 +310,22 @@ CONV_POLY = {
     "seed": 27,
 }
 
+# ---------------------------------------------------------------- COMP
+# Function composition (CompositePdf): a Gaussian shell of a quadratic core,
+# P(x) ~ exp(-(g(x) - mu)^2 / (2 sigma^2)), g(x) = 1 + a1 (x - 5) + a2 (x - 5)^2.
+COMP = {
+    "name": "comp_gauss_of_quadratic",
+    "obs": [("x", 0.0, 10.0)],
+    "params": [("g_a1", 0.4, 0.02, 0.0, 0.0, False), ("g_a2", 0.04, 0.005, 0.0, 0.0, False),
+               ("s_mu", 2.2, 0.05, -5.0, 10.0, False), ("s_sigma", 1.0, 0.05, 0.05, 5.0, False)],
+    "truth": {"g_a1": 0.5, "g_a2": 0.05, "s_mu": 2.0, "s_sigma": 1.0},
+    "model": {"op": "comp", "obs": "x", "children": [
+        {"op": "poly", "obs": "x", "par": ["g_a1", "g_a2"], "x0": 5.0},
+        {"op": "gauss", "obs": "x", "par": ["s_mu", "s_sigma"]}]},
+    "n_events": 1_000_000,
+    "seed": 28,
+}
+
 # ---------------------------------------------------------------- C5
 # Stream of toy fits of the C1 model with uneven event counts.
 C5 = {
@@ -342,4 +358,4 @@ LISTING2 = {
 def workload(name):
     return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2, "mapped": MAPPED,
             "mapped_sum": MAPPED_SUM, "shared": SHARED, "shared_sum": SHARED_SUM, "shared_2d": SHARED_2D,
-            "c4s": C4S, "conv": CONV, "conv_poly": CONV_POLY}[name]
+            "c4s": C4S, "conv": CONV, "conv_poly": CONV_POLY, "comp": COMP}[name]

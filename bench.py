@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 5 times (reference for the HBM byte counters)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4x", "c4s", "mapped", "mapped_sum",
-                             "shared", "shared_sum", "conv", "conv_poly", "c1l", "c2l"],
+                             "shared", "shared_sum", "conv", "conv_poly", "comp", "c1l", "c2l"],
                     help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
                          "c3 Dalitz amplitude sum, c4 time-dependent Dalitz (c4x with x free: the "
                          "trigonometric terms; c4s times the sigma_t density that varies across "
@@ -72,7 +72,7 @@ def parse():
                          "added to an exponential, 1e7 events), shared / shared_sum a Gaussian times "
                          "an acceptance polynomial on the same observable (alone / added to an "
                          "exponential, 1e7 events), conv / conv_poly numerical convolutions "
-                         "(1e6 events), c1l / c2l the c1 / c2 "
+                         "(1e6 events), comp a Gaussian of a quadratic (1e6 events), c1l / c2l the c1 / c2 "
                          "models at 2^28 / 10^8 events (beyond the last-level cache): throughput only")
     return ap.parse_args()
 
@@ -219,7 +219,7 @@ def other_workload(args, P, S, torch, stream):
         data = S.gen_c1(n=n, seed=spec["seed"])
     elif base == "c2":
         data = S.gen_c2(n=n, seed=spec["seed"])
-    elif base in ("mapped", "mapped_sum", "shared", "shared_sum", "conv", "conv_poly"):
+    elif base in ("mapped", "mapped_sum", "shared", "shared_sum", "conv", "conv_poly", "comp"):
         # (conv_poly's density is zero below its first grid point)
         data = {"x": np.random.default_rng(spec["seed"]).uniform(0.1 if base == "conv_poly" else 0.0, 10.0, n)}
     else:

@@ -121,7 +121,13 @@ enum hf_op {
                         the model's t or the resolution's residual);
                         Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms, on the
                         host); obs = {x}; no par; consts = {N (2..4096), d_lo, d_hi}; the
-                        per-event sum runs over all N points (cost ~ N per event)            */
+                        per-event sum runs over all N points (cost ~ N per event)            */,
+  HF_OP_COMP = 11    /* function composition (section "Combining functions": CompositePdf):
+                        P(x) = f(g(x)) / Z with the core g(x) = 1 + sum_j a_j (x - x0)^j, a
+                        POLY leaf's value (degree <= 4), and f an EXP / GAUSS / POLY (degree
+                        <= 4) leaf's unnormalised shape (as for HF_OP_CONV) evaluated at g;
+                        Z = int_box f(g(x)) dx by 16-point Gauss-Legendre on 128 segments on
+                        the host; children = {core, shell} on x; obs = {x}; no par or consts */
 };
 
 /* DALITZ block of node constants:

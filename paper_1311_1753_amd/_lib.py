@@ -26,7 +26,7 @@ HF_FP32_EVAL = 1
 HF_METRIC_BNLL = 1
 HF_METRIC_CHI2 = 2
 
-OP = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7, "map": 8, "dpmap": 9, "conv": 10}
+OP = {"exp": 1, "gauss": 2, "poly": 3, "add": 4, "prod": 5, "dalitz": 6, "tddp": 7, "map": 8, "dpmap": 9, "conv": 10, "comp": 11}
 
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_GRAPH", -3: "E_SHAPE", -4: "E_OOM", -5: "E_HIP",
                 -6: "E_DOMAIN", -7: "E_NOT_CONVERGED", -8: "E_BUDGET", -9: "E_FULL"}

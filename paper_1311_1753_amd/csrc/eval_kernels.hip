@@ -776,6 +776,51 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         }
         resp[chm] = T(1);
         resp[chr] = T(1);
+      } else if (HEAVY && op == OP_COMP) {
+        // composition f(g(x)): the core's value g = 1 + sum a_j u^j
+        // (u = x - x0), the shell's shape at g; the children's slots receive
+        // d ln f / dg (x - x0)^j and the shell's own derivatives
+        const int chc = P.child[nd.child0], chf = P.child[nd.child0 + 1];
+        const KNode& cc = P.node[chc];
+        const KNode& cf = P.node[chf];
+        const int nc = cc.n_slot, nf = cf.n_slot;
+        const T u = (T)(xe[nd.col[0]] + cs.d[cc.c0]);
+        T uk[4], gv = T(1), w = T(1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          w *= u;
+          uk[j] = w;
+          if (j < nc) gv = Mth<T>::fma(cs.get<T>(cc.c0 + 1 + j), w, gv);
+        }
+        T df[8];
+        const double ref = cs.d[c0 + 2];
+        const T lf = conv_leaf<T>(cs, cf, (double)gv - ref, df);
+        T dfdg;
+        if (cf.op == OP_EXP) {
+          dfdg = cs.get<T>(cf.c0 + 1);
+        } else if (cf.op == OP_GAUSS) {
+          dfdg = -df[0];
+        } else {
+          const T v0 = (T)((double)gv - ref + cs.d[cf.c0]);
+          T pv = T(1), dp = T(0), vk = T(1);
+#pragma unroll
+          for (int j = 1; j <= 4; ++j)
+            if (j <= nf) {
+              dp = Mth<T>::fma(T(j) * cs.get<T>(cf.c0 + j), vk, dp);
+              vk *= v0;
+              pv = Mth<T>::fma(cs.get<T>(cf.c0 + j), vk, pv);
+            }
+          dfdg = dp * Mth<T>::rcp(pv);
+        }
+        v = (lf - cs.get<T>(c0)) - cs.get<T>(c0 + 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nc) dl[cc.slot0 + j] = dfdg * uk[j] - cs.get<T>(c0 + 3 + j);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nf) dl[cf.slot0 + j] = df[j] - cs.get<T>(c0 + 3 + nc + j);
+        resp[chc] = T(1);
+        resp[chf] = T(1);
       } else if (op == OP_DPMAP) {
         // the child of the event's cell on the s12 x s13 grid (row-major,
         // boundaries in the columns' offset frames) gives the value; the
@@ -829,7 +874,8 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
     for (int k = GRAD ? root : -1; k >= 0; --k) {
       const KNode& nd = P.node[k];
       const T a = adj[k];
-      if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP || nd.op == OP_CONV)
+      if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP || nd.op == OP_CONV ||
+          nd.op == OP_COMP)
         for (int j = 0; j < nd.n_child; ++j) {
           const int ch = P.child[nd.child0 + j];
           adj[ch] = a * resp[ch];

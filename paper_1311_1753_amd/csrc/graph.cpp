@@ -478,13 +478,8 @@ static double raw_integral(const HostLeaf& h, double lo, double u, double v, dou
   }
 }
 
-// Z = int_box prod_j P_j(x) dx over a group of one-observable leaves on one
-// observable, by composite 16-point Gauss-Legendre on segments no wider than
-// two of the narrowest Gaussian's widths and four decay lengths of the
-// steepest exponential (32 .. 4096 segments), and dZ/d(slot) / Z for the
-// leaves' slots in order.  False when Z is not positive.
-static bool shared_norm(const std::vector<HostLeaf>& lf, double lo, double hi, double& lnZ,
-                        std::vector<double>& dz) {
+// 16-point Gauss-Legendre nodes (first 16) and weights (next 16) on [-1, 1].
+static const double* gl16() {
   static const double* const gl = [] {
     // nodes (first 16) and weights (next 16) on [-1, 1] by Newton on P_16
     static double q[32];
@@ -508,6 +503,17 @@ static bool shared_norm(const std::vector<HostLeaf>& lf, double lo, double hi, d
     }
     return q;
   }();
+  return gl;
+}
+
+// Z = int_box prod_j P_j(x) dx over a group of one-observable leaves on one
+// observable, by composite 16-point Gauss-Legendre on segments no wider than
+// two of the narrowest Gaussian's widths and four decay lengths of the
+// steepest exponential (32 .. 4096 segments), and dZ/d(slot) / Z for the
+// leaves' slots in order.  False when Z is not positive.
+static bool shared_norm(const std::vector<HostLeaf>& lf, double lo, double hi, double& lnZ,
+                        std::vector<double>& dz) {
+  const double* const gl = gl16();
   const double L = hi - lo;
   double h = L / 32.0;
   for (const HostLeaf& f : lf) {
@@ -572,7 +578,7 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
   // of their own (and no domain check over the box)
   std::vector<char> conv_child(P.n_nodes, 0);
   for (int k = 0; k < P.n_nodes; ++k)
-    if (P.node[k].op == OP_CONV)
+    if (P.node[k].op == OP_CONV || P.node[k].op == OP_COMP)
       for (int c : g->nodes[k].child) conv_child[c] = 1;
   for (int k = 0; k < P.n_nodes; ++k) {
     const KNode& kn = P.node[k];
@@ -699,6 +705,77 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
             } else {
               setc(c0 + 2 + m, dslot[m]);
             }
+          }
+        }
+        if (hoist) {
+          sc.ht.lnN += lnZ;
+          set_ln(c0, c0 + 1, 0.0);
+        } else {
+          set_ln(c0, c0 + 1, lnZ);
+        }
+        break;
+      }
+      case OP_COMP: {
+        // Z = int_box f(g(x)) dx, composite 16-point Gauss-Legendre on 128
+        // segments, with d ln Z / d(slot) for the core's and the shell's slots
+        const int col = kn.col[0];
+        const ObsInfo& o = g->obs[g->obs_of_col[col]];
+        // (the core is a function, the shell is evaluated at its values: the
+        // box normalisations host_leaf checks do not apply)
+        bool ok = true, ok_c = true, ok_f = true;
+        HostLeaf C = host_leaf(g, g->nodes[nd.child[0]], th, rnd, fp32, ok_c);
+        HostLeaf F = host_leaf(g, g->nodes[nd.child[1]], th, rnd, fp32, ok_f);
+        if (F.op == OP_GAUSS && !(F.s > 0.0)) ok = false;
+        C.lnN = F.lnN = 0.0;
+        for (int j = 0; j < 8; ++j) C.dN[j] = F.dN[j] = 0.0;
+        const int nc = C.n_slot, nf = F.n_slot;
+        const double* gl = gl16();
+        const int nseg = 128;
+        const double hs = (o.hi - o.lo) / nseg;
+        double Z = 0.0;
+        std::vector<double> dZ(nc + nf, 0.0);
+        double dc[8], df[8];
+        for (int q = 0; q < nseg && ok; ++q)
+          for (int i = 0; i < 16; ++i) {
+            const double x = o.lo + hs * (q + 0.5 * (gl[i] + 1.0));
+            // core value and its slot derivatives (d g / d a_j = (x - x0)^j)
+            double gv = 1.0, uk = 1.0;
+            for (int j = 0; j < nc; ++j) {
+              uk *= x - C.x0;
+              dc[j] = uk;
+              gv += C.p[j] * uk;
+            }
+            double lf;
+            if (!F.eval(gv, lf, df)) { ok = false; break; }
+            // d ln f / dg of the shell's shape
+            double dfdg;
+            if (F.op == OP_EXP) dfdg = F.p[0];
+            else if (F.op == OP_GAUSS) dfdg = -(gv - F.p[0]) / (F.s * F.s);
+            else {
+              double pv = 1.0, dp = 0.0, w = 1.0;
+              for (int j = 1; j <= nf; ++j) {
+                dp += j * F.p[j - 1] * w;
+                w *= gv - F.x0;
+                pv += F.p[j - 1] * w;
+              }
+              dfdg = dp / pv;
+            }
+            const double wq = 0.5 * hs * gl[16 + i] * std::exp(lf);
+            Z += wq;
+            for (int j = 0; j < nc; ++j) dZ[j] += wq * dfdg * dc[j];
+            for (int j = 0; j < nf; ++j) dZ[nc + j] += wq * df[j];
+          }
+        if (!ok || !(Z > 0.0) || !std::isfinite(Z)) { sc.ok = false; Z = 1.0; }
+        const double lnZ = std::log(Z);
+        setc(c0 + 2, column_ref(g, col, prec));
+        for (int j = 0; j < nc + nf; ++j) {
+          const double dz = dZ[j] / Z;
+          const NodeInfo& cn = g->nodes[nd.child[j < nc ? 0 : 1]];
+          if (hoist) {
+            sc.ht.dlnN[cn.par[j < nc ? j : j - nc]] += dz;
+            setc(c0 + 3 + j, 0.0);
+          } else {
+            setc(c0 + 3 + j, dz);
           }
         }
         if (hoist) {
@@ -932,6 +1009,7 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
     }
     case OP_DPMAP: return (int)n.consts[0] + (int)n.consts[1] - 2;
     case OP_CONV: return 8 + node_slots(all[n.child[0]]) + node_slots(all[n.child[1]]);
+    case OP_COMP: return 3 + node_slots(all[n.child[0]]) + node_slots(all[n.child[1]]);
     case OP_EXP: return 5;
     case OP_GAUSS: return 6;
     case OP_POLY: return 2 * (int)n.par.size() + 3;
@@ -1058,6 +1136,21 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
             rc = need((cn.op == OP_EXP || cn.op == OP_GAUSS || cn.op == OP_POLY) && cn.obs.size() == 1 &&
                           cn.obs[0] == ni.obs[0],
                       "MAP children must be EXP / GAUSS / POLY leaves on the MAP's observable");
+          }
+          break;
+        }
+        case OP_COMP: {
+          // children = (core POLY, shell leaf) on obs
+          rc = need(n.n_child == 2 && n.n_par == 0 && n.n_obs == 1 && n.n_const == 0,
+                    "COMP takes a core and a shell, one observable, no parameters or constants");
+          if (!rc) rc = need(finite_box(ni.obs[0]), "COMP needs a finite observable box");
+          if (!rc) {
+            const NodeInfo& cc = in[ni.child[0]];
+            const NodeInfo& cf = in[ni.child[1]];
+            rc = need(cc.op == OP_POLY && cc.obs.size() == 1 && cc.obs[0] == ni.obs[0] && cc.par.size() <= 4 &&
+                          (cf.op == OP_EXP || cf.op == OP_GAUSS || cf.op == OP_POLY) && cf.obs.size() == 1 &&
+                          cf.obs[0] == ni.obs[0] && cf.par.size() <= 4,
+                      "COMP: a POLY core (degree <= 4) and an EXP / GAUSS / POLY shell, both on its observable");
           }
           break;
         }
@@ -1349,7 +1442,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     // kernel family
     const NodeInfo& rootn = g->nodes[NN - 1];
     bool heavy = g->dz.node >= 0;
-    for (const NodeInfo& n : g->nodes) heavy = heavy || n.op == OP_CONV;  // the general interpreter only
+    for (const NodeInfo& n : g->nodes) heavy = heavy || n.op == OP_CONV || n.op == OP_COMP;  // the general interpreter only
     // mixture of single-column EXP/GAUSS leaves: static kernel with its own
     // accumulator layout [3 per child], combined on the host (MixInfo)
     bool mix = rootn.op == OP_ADD && (NN == 3 || NN == 4) && (int)rootn.child.size() == NN - 1 && P.n_cols == 1;

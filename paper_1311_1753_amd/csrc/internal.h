@@ -26,7 +26,7 @@ constexpr int kNumGroups = 9;        // (pair, spin) groups of Dalitz resonances
 
 enum Op : int16_t {
   OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7, OP_MAP = 8,
-  OP_DPMAP = 9, OP_CONV = 10
+  OP_DPMAP = 9, OP_CONV = 10, OP_COMP = 11
 };
 constexpr int kMaxConvGrid = 4096;  // CONV grid points
 
@@ -75,6 +75,8 @@ struct KProgram {
 //          4 column reference, 5 shift c of the exponents, 6 (lnZ - c)_hi,
 //          7 (lnZ - c)_lo, then dlnZ/d(slot) for the model's and the
 //          resolution's slots (not hoisted; zeros when hoisted); aux = N
+//   COMP   0 lnZ_hi, 1 lnZ_lo, 2 column reference, then dlnZ/d(slot) for the
+//          core's and the shell's slots (zeros when hoisted)
 //   DALITZ/TDDP: see the kDz* offsets below.
 // For the float path lnN is split into a float pair (hi + lo) so that the
 // rounding of the constant does not bias every event in the same direction.

@@ -36,6 +36,7 @@ CASES = [
     ("c4s", 20_047, 29),
     ("conv", 50_021, 30),
     ("conv_poly", 50_023, 31),
+    ("comp", 50_027, 33),
 ]
 
 
@@ -264,6 +265,29 @@ def test_fit_convolution_matches_oracle_fit(P, stream, prec):
     sp["params"] = [(p[0], sp["truth"][p[0]]) + tuple(p[2:]) if p[0] in ("r_mu", "r_sigma") else p
                     for p in sp["params"]]
     data = data_for("conv", 100_019, 32)
+    om = O.Model(sp)
+    ref = om.fit(data)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, data, prec, stream)
+    r = P.fit(g, ds, stream=stream)
+    free = g.free_mask()
+    dev = np.abs(r["theta"] - ref["theta"])[free] / ref["errors"][free]
+    print(f"  status {r['status']} n_eval {r['n_eval']}; max |dtheta|/sigma {dev.max():.2e}", flush=True)
+    assert r["status"] == "OK"
+    assert dev.max() <= 1e-3
+    assert np.all(np.abs(r["errors"][free] / ref["errors"][free] - 1) < 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fit_composition_matches_oracle_fit(P, stream, prec):
+    """Fit of the Gaussian of a quadratic with the shell's width fixed (the
+    exponent depends on (1 - mu, a1, a2) / sigma only: one direction of the
+    four parameters is flat)."""
+    from oracle import oracle as O
+    print(f"\n[case] fit comp (fixed shell width) prec={prec}", flush=True)
+    sp = get_spec("comp")
+    sp["params"] = [p[:5] + (True,) if p[0] == "s_sigma" else p for p in sp["params"]]
+    data = data_for("comp", 100_003, 34)
     om = O.Model(sp)
     ref = om.fit(data)
     g = P.Graph.from_spec(sp)

@@ -34,7 +34,7 @@ def test_library_exports_every_header_symbol():
 def test_graph_creation_for_every_workload():
     import paper_1311_1753_amd as P
     for name in ("c1", "c2", "c3", "c4", "c4x", "listing2", "mapped", "mapped_sum", "shared", "shared_sum",
-                 "shared_2d", "c4s", "conv", "conv_poly"):
+                 "shared_2d", "c4s", "conv", "conv_poly", "comp"):
         g = P.Graph.from_spec(S.workload(name))
         assert g.n_par == len(S.workload(name)["params"])
 
@@ -85,6 +85,9 @@ def test_graph_validation_errors():
     for bad in (dict(cv["model"], grid=1), dict(cv["model"], d_lo=1.0, d_hi=1.0),
                 dict(cv["model"], children=[cv["model"]["children"][0], dict(cv["model"], grid=16)])):
         _expect_graph_error(cv["obs"], cv["params"], bad)
+    # COMP: a core that is not a polynomial
+    cp = S.workload("comp")
+    _expect_graph_error(cp["obs"], cp["params"], dict(cp["model"], children=cp["model"]["children"][::-1]))
     # DPMAP: alone (not beside a Dalitz node), wrong child count, boundaries
     # outside the box, a child on another observable
     c4s = S.workload("c4s")

@@ -125,3 +125,41 @@ def generate(spec, theta, n, seed, idx=None):
 
     node_(spec["model"], np.arange(n))
     return cols
+
+
+def generate_ar(spec, theta, n, seed, envelope, max_trials=10_000, logpdf=None):
+    """Accept-reject toys of any model whose observables have finite boxes.
+
+    Event i takes trials j = 0, 1, ...: with C observables (spec order), the
+    candidate's coordinate c is lo_c + u_m (hi_c - lo_c) with uniform number
+    m = j (C + 1) + c of the event, and the acceptance uniform is number
+    j (C + 1) + C; the first trial with u_acc * envelope < P(candidate) is
+    the event (P = 0 outside the Dalitz plot).  logpdf(theta, columns) is the
+    density (default: the oracle model of spec).  Returns the columns; raises
+    when an event exhausts max_trials or P exceeds the envelope."""
+    if logpdf is None:
+        from oracle import oracle as O
+        logpdf = O.Model(spec).logpdf
+    names = [o[0] for o in spec["obs"]]
+    lo = np.array([float(o[1]) for o in spec["obs"]])
+    hi = np.array([float(o[2]) for o in spec["obs"]])
+    if not (np.all(np.isfinite(lo)) and np.all(np.isfinite(hi))):
+        raise ValueError("accept-reject needs finite boxes")
+    C = len(names)
+    out = {k: np.empty(n) for k in names}
+    pending = np.arange(n, dtype=np.int64)
+    for j in range(max_trials):
+        if pending.size == 0:
+            return out
+        cand = {names[c]: lo[c] + uniforms(pending, seed, j * (C + 1) + c) * (hi[c] - lo[c]) for c in range(C)}
+        ua = uniforms(pending, seed, j * (C + 1) + C)
+        p = np.exp(logpdf(theta, cand))
+        if np.any(p > envelope):
+            raise ValueError("accept-reject envelope too low")
+        acc = ua * envelope < p
+        for k in names:
+            out[k][pending[acc]] = cand[k][acc]
+        pending = pending[~acc]
+    if pending.size:
+        raise ValueError("accept-reject: trials exhausted")
+    return out

@@ -92,3 +92,36 @@ def test_product_factors_are_independent_with_their_marginals():
 def test_unsupported_leaf_is_refused():
     with pytest.raises(ValueError):
         T.generate(S.workload("mapped"), np.zeros(len(S.workload("mapped")["params"])), 10, 1)
+
+
+def test_accept_reject_layout_and_distribution():
+    """A flat density under an envelope equal to it accepts every first
+    candidate (pins the candidate's uniform numbers); an exponential follows
+    its closed-form CDF; an envelope below the density is refused."""
+    sp = S.workload("c1")
+    x = T.generate_ar(sp, [0.0], 1000, 3, 0.1)["x"]
+    assert np.array_equal(x, 0.0 + T.uniforms(np.arange(1000), 3, 0) * 10.0)
+    x = T.generate_ar(sp, [-0.5], 40_000, 4, 0.6)["x"]
+    assert stats.kstest(x, lambda v: _cdf_exp(v, 0.0, 10.0, -0.5)).pvalue > 1e-3
+    with pytest.raises(ValueError):
+        T.generate_ar(sp, [-0.5], 1000, 4, 0.3)
+
+
+def test_accept_reject_dalitz_moments():
+    """Dalitz events: inside the plot, and the s12 and s13 means agree with
+    the density-weighted means over a fine grid within 4 standard errors."""
+    from oracle import oracle as O
+    sp = S.workload("c3")
+    m = O.Model(sp)
+    th = m.theta(sp["truth"])
+    lo, hi = S.dalitz_box()
+    G = 400
+    c = lo + (np.arange(G) + 0.5) * (hi - lo) / G
+    a, b = np.meshgrid(c, c, indexing="ij")
+    p = np.exp(m.logpdf(th, {"s12": a.ravel(), "s13": b.ravel()}))
+    d = T.generate_ar(sp, th, 20_000, 6, 1.5 * p.max())
+    assert all(O.inside(sp["model"]["dalitz"], u, v) for u, v in zip(d["s12"][:500], d["s13"][:500]))
+    for k, grid in (("s12", a.ravel()), ("s13", b.ravel())):
+        mean = np.sum(p * grid) / np.sum(p)
+        sd = np.sqrt(np.sum(p * (grid - mean) ** 2) / np.sum(p))
+        assert abs(d[k].mean() - mean) < 4 * sd / np.sqrt(d[k].size), k

@@ -237,6 +237,20 @@ int dataset_upload_binned(const pdf_graph* g, const double* const* centres, cons
  * n, seed) give the same events; event i does not depend on n. */
 int dataset_generate(const pdf_graph* g, const double* params, int64_t n_events, uint64_t seed,
                      hf_precision prec, void* hip_stream, dataset** out);
+/* Accept-reject toy generation on the device for any graph whose used
+ * observables all have finite boxes (DALITZ, MAP, CONV, COMP, ... included;
+ * not the time-dependent density): event i takes trials j = 0, 1, ...
+ * (at most max_trials); with C used observables (column order = observable
+ * index order), its uniforms j (C + 1) + c (numbered as for
+ * dataset_generate) place the candidate's column c at lo + u (hi - lo), and
+ * uniform j (C + 1) + C accepts the candidate when u * envelope < P(candidate)
+ * (double precision; P = 0 outside the Dalitz plot).  envelope must bound
+ * the normalised density over the box.  HF_E_DOMAIN when an event runs out
+ * of trials or a candidate's density exceeds the envelope (no dataset is
+ * returned), HF_E_GRAPH for an unbounded observable.  The first call on a
+ * Dalitz graph computes its normalisation grid. */
+int dataset_generate_ar(pdf_graph* g, const double* params, int64_t n_events, uint64_t seed, double envelope,
+                        int32_t max_trials, hf_precision prec, void* hip_stream, dataset** out);
 /* Copies observable obs of an unbinned dataset to the host as doubles (the
  * stored value, plus the column reference for HF_FP32_EVAL); host_out holds
  * n_events doubles.  Blocking on hip_stream. */

@@ -88,6 +88,8 @@ SIGNATURES = {
     "dataset_generate": (ctypes.c_int, [_VP, _DP, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, _VP,
                                         ctypes.POINTER(_VP)]),
     "dataset_read_column": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _DP]),
+    "dataset_generate_ar": (ctypes.c_int, [_VP, _DP, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double,
+                                           ctypes.c_int32, ctypes.c_int, _VP, ctypes.POINTER(_VP)]),
     "dataset_free": (None, [_VP]),
     "dataset_device_bytes": (ctypes.c_int64, [_VP]),
     # theta and grad are passed as raw addresses (numpy .ctypes.data)

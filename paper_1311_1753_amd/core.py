@@ -234,6 +234,25 @@ class Dataset:
         self.n = int(n)
         return self
 
+    @classmethod
+    def generate_ar(cls, graph, theta, n, seed, envelope, max_trials=10_000, precision="fp64", stream=None):
+        """Accept-reject toy dataset drawn on the device (dataset_generate_ar):
+        envelope bounds the normalised density over the box."""
+        self = cls.__new__(cls)
+        self.graph = graph
+        self.precision = _prec(precision)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if th.size != graph.n_par:
+            raise ValueError("theta needs one value per parameter")
+        h = ctypes.c_void_p()
+        check(lib().dataset_generate_ar(graph.handle, th.ctypes.data_as(_lib._DP), int(n),
+                                        int(seed) & 0xFFFFFFFFFFFFFFFF, float(envelope), int(max_trials),
+                                        self.precision, _stream_ptr(stream), ctypes.byref(h)))
+        self._keep = None
+        self._h = h
+        self.n = int(n)
+        return self
+
     def column(self, name, stream=None):
         """One observable's stored events as float64 (dataset_read_column)."""
         out = np.empty(self.n)

@@ -497,6 +497,83 @@ extern "C" int dataset_generate(const pdf_graph* g, const double* params, int64_
   }
 }
 
+extern "C" int dataset_generate_ar(pdf_graph* g, const double* params, int64_t n, uint64_t seed, double envelope,
+                                   int32_t max_trials, hf_precision prec, void* hip_stream, dataset** out) {
+  try {
+    if (!g || !params || !out) return fail(HF_E_INVALID, "dataset_generate_ar: NULL argument");
+    if (n < 0 || n > (int64_t(1) << 36)) return fail(HF_E_INVALID, "dataset_generate_ar: n_events out of range");
+    if (prec != HF_FP64 && prec != HF_FP32_EVAL) return fail(HF_E_INVALID, "dataset_generate_ar: bad precision");
+    if (!(envelope > 0.0) || !std::isfinite(envelope))
+      return fail(HF_E_INVALID, "dataset_generate_ar: envelope must be positive and finite");
+    if (max_trials < 1) return fail(HF_E_INVALID, "dataset_generate_ar: max_trials must be >= 1");
+    for (size_t p = 0; p < g->par.size(); ++p)
+      if (!std::isfinite(params[p])) return fail(HF_E_INVALID, "dataset_generate_ar: parameter not finite");
+    const int nc = (int)g->obs_of_col.size();
+    for (int c = 0; c < nc; ++c) {
+      const ObsInfo& o = g->obs[g->obs_of_col[c]];
+      if (!std::isfinite(o.lo) || !std::isfinite(o.hi))
+        return fail(HF_E_GRAPH, "dataset_generate_ar: every observable needs a finite box");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (int rc = ensure_grid(g, st)) return rc;
+    StagedCall sc;
+    stage(g, params, HF_FP64, sc, true);
+    if (!sc.ok) return fail(HF_E_DOMAIN, "dataset_generate_ar: parameters outside the density's domain");
+    std::unique_ptr<GenArArgs> a(new GenArArgs);
+    std::memset(a.get(), 0, sizeof(GenArArgs));
+    a->prog = sc.prog;
+    a->n = n;
+    a->key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a->key1 = (uint32_t)(seed >> 32);
+    a->max_trials = max_trials;
+    a->n_cols = nc;
+    a->fp32 = prec == HF_FP32_EVAL ? 1 : 0;
+    a->env = envelope;
+    a->ln_hoist = sc.ht.lnN;
+    if (g->dz.node >= 0) {
+      const NodeInfo& dn = g->nodes[g->dz.node];
+      a->dalitz = 1;
+      a->c12 = g->col_of_obs[dn.obs[0]];
+      a->c13 = g->col_of_obs[dn.obs[1]];
+      a->M = g->dz.M;
+      a->m1 = g->dz.m1;
+      a->m2 = g->dz.m2;
+      a->m3 = g->dz.m3;
+    }
+    std::unique_ptr<dataset> d;
+    if (int rc = make_dataset(g, n, prec, 0, 0.0, "dataset_generate_ar", d)) return rc;
+    for (int c = 0; c < nc; ++c) {
+      const ObsInfo& o = g->obs[g->obs_of_col[c]];
+      a->lo[c] = o.lo;
+      a->hi[c] = o.hi;
+      a->ref[c] = d->ref[c];
+      a->out[c] = const_cast<void*>(d->col[c]);
+    }
+    int32_t* flag = nullptr;
+    hipError_t e = hipMalloc(&flag, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int32_t), st);
+    a->fail = flag;
+    if (e == hipSuccess) e = launch_generate_ar(*a, st);
+    int32_t fl = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&fl, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (flag) hipFree(flag);
+    if (e != hipSuccess) {
+      hipFree(d->block);
+      return hip_fail(e, "dataset_generate_ar");
+    }
+    if (fl) {
+      hipFree(d->block);
+      return fail(HF_E_DOMAIN, (fl & 2) ? "dataset_generate_ar: the density exceeds the envelope"
+                                        : "dataset_generate_ar: an event ran out of trials");
+    }
+    *out = d.release();
+    return HF_OK;
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("dataset_generate_ar: ") + ex.what());
+  }
+}
+
 extern "C" int dataset_read_column(const dataset* d, int32_t obs, void* hip_stream, double* host_out) {
   try {
     if (!d || !host_out) return fail(HF_E_INVALID, "dataset_read_column: NULL argument");

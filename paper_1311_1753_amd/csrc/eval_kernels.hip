@@ -28,6 +28,7 @@
 #include "device_common.h"
 #include "internal.h"
 #include "kernels.h"
+#include "philox.h"
 
 namespace hf {
 
@@ -1200,6 +1201,77 @@ __device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const 
   row_chunks(n, n_rows, r, c0, c1);
   heavy_row<T, NCOL>(ev, P, cp, P.n_cols, n, c0, c1, acc);
   row_store_acc<NC>(acc, nc, out, n_rows);
+}
+
+// ------------------------------------------------------------------ accept-reject toys
+// Membership of the Dalitz plot (both orderings of the kinematic limits of
+// s13 at fixed s12), the rule the datasets are validated with.
+__device__ __forceinline__ bool dp_pair_in(double M, double m1, double sx, double sy, double mx, double my) {
+  const double lo = (m1 + mx) * (m1 + mx), hi = (M - my) * (M - my);
+  if (!(sx >= lo && sx <= hi)) return false;
+  const double rs = ::sqrt(sx);
+  const double E1 = (sx - mx * mx + m1 * m1) / (2.0 * rs);
+  const double Ey = (M * M - sx - my * my) / (2.0 * rs);
+  const double p1 = ::sqrt(fmax(E1 * E1 - m1 * m1, 0.0));
+  const double py = ::sqrt(fmax(Ey * Ey - my * my, 0.0));
+  const double e = E1 + Ey;
+  return sy >= e * e - (p1 + py) * (p1 + py) && sy <= e * e - (p1 - py) * (p1 - py);
+}
+
+// Event i takes trials j = 0, 1, ...: its uniforms j (C + 1) + c place the
+// candidate's column c in the box, number j (C + 1) + C decides acceptance
+// (u * envelope < P in double); the first accepted candidate is the event,
+// so the output does not depend on the launch shape.  An event that runs out
+// of trials, or a density above the envelope, sets a flag bit.
+__global__ __launch_bounds__(256) void k_generate_ar(const GenArArgs a) {
+  const CS cs{a.prog.c64, a.prog.c32};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+    EventStream rs{(uint32_t)((uint64_t)i & 0xFFFFFFFFu), (uint32_t)((uint64_t)i >> 32), a.key0, a.key1};
+    double x[kMaxCols];
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c) x[c] = 0.0;
+    bool done = false;
+    int flag = 0;
+    for (int j = 0; j < a.max_trials && !done; ++j) {
+#pragma unroll
+      for (int c = 0; c < kMaxCols; ++c)
+        if (c < a.n_cols) x[c] = __dadd_rn(a.lo[c], __dmul_rn(rs.next(), a.hi[c] - a.lo[c]));  // no fma: as written
+      const double ua = rs.next();
+      bool in = true;
+      if (a.dalitz) {
+        double s12 = 0.0, s13 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxCols; ++c) {
+          s12 = c == a.c12 ? x[c] : s12;
+          s13 = c == a.c13 ? x[c] : s13;
+        }
+        in = dp_pair_in(a.M, a.m1, s12, s13, a.m2, a.m3) && dp_pair_in(a.M, a.m1, s13, s12, a.m3, a.m2);
+      }
+      if (in) {
+        double dl[kMaxSlots];
+        const double p = ::exp(tree_eval<double, kMaxSlots, kMaxCols, true, false>(a.prog, cs, x, dl) - a.ln_hoist);
+        if (p > a.env) flag |= 2;
+        if (__dmul_rn(ua, a.env) < p) done = true;
+      }
+    }
+    if (!done) flag |= 1;
+    if (flag) atomicOr(a.fail, flag);
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c)
+      if (c < a.n_cols) {
+        if (a.fp32) ((float*)a.out[c])[i] = (float)(x[c] - a.ref[c]);
+        else ((double*)a.out[c])[i] = x[c];
+      }
+  }
+}
+
+hipError_t launch_generate_ar(const GenArArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  const int64_t blocks = (a.n + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
+  hipLaunchKernelGGL(k_generate_ar, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ reduction

@@ -71,6 +71,24 @@ struct GenArgs {
 };
 hipError_t launch_generate(const GenArgs& a, hipStream_t st);
 
+// Accept-reject toy generation for any graph whose observables have finite
+// boxes: candidates uniform over the columns' boxes, the density from the
+// tree interpreter in double (FP64 constants of `prog`).
+struct GenArArgs {
+  KProgram prog;
+  int64_t n;
+  uint32_t key0, key1;
+  int32_t max_trials, n_cols, fp32, dalitz;  // dalitz: test (s12, s13) = columns c12, c13
+  int32_t c12, c13;
+  double lo[kMaxCols], hi[kMaxCols], ref[kMaxCols];
+  double env, ln_hoist;        // envelope; normalisation applied on the host (subtracted here)
+  double M, m1, m2, m3;        // Dalitz kinematics
+  void* out[kMaxCols];
+  int32_t* fail;               // bit 0: trials exhausted; bit 1: density above the envelope
+};
+static_assert(sizeof(GenArArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+hipError_t launch_generate_ar(const GenArArgs& a, hipStream_t st);
+
 // Dalitz normalisation grid: M[w][p][q] for w in {I, Ibar, J} (n_mat of them),
 // complex, unscaled by the cell area.  `out_host` receives n_mat * na * na * 2
 // doubles.  Blocking.

@@ -151,3 +151,48 @@ def test_fit_of_generated_toy_recovers_truth(P, prec):
     up = P.Dataset(g, {"x": ds.column("x")}, prec)
     r2 = P.fit(g, up)
     assert abs(r2["theta"][0] - r["theta"][0]) <= 1e-6 * r["errors"][0]
+
+
+def _envelope(sp, th, grid=300):
+    """1.5 x the oracle's density maximum over a grid of the box."""
+    from oracle import oracle as O
+    m = O.Model(sp)
+    names = [o[0] for o in sp["obs"]]
+    axes = [np.linspace(o[1], o[2], grid) for o in sp["obs"]]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    p = np.exp(m.logpdf(th, {k: v.ravel() for k, v in zip(names, mesh)}))
+    return 1.5 * float(np.max(p[np.isfinite(p)]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,n", [("c3", 20_011), ("mapped", 30_001), ("comp", 30_003), ("conv_poly", 5_003)])
+def test_accept_reject_events_match_reference(P, name, n, prec):
+    """Candidates are the same doubles on both sides (lo + u (hi - lo)), and
+    the acceptance u * envelope < P is decided in double on both: the events
+    agree exactly, apart from decisions within rounding of a tie (none
+    expected at these sizes)."""
+    print(f"\n[case] toygen accept-reject {name} n={n} {prec}", flush=True)
+    sp = spec_of(name)
+    th = np.array([sp["truth"][p[0]] for p in sp["params"]])
+    env = _envelope(sp, th, grid=300 if len(sp["obs"]) == 2 else 4001)
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset.generate_ar(g, th, n, 99, env, precision=prec)
+    ref = T.generate_ar(sp, th, n, 99, env)
+    for k, xr in ref.items():
+        x = ds.column(k)
+        r = g.column_ref(k, prec)
+        expect = (xr - r).astype(np.float32).astype(np.float64) + r if prec == "fp32" else xr
+        bad = x != expect
+        print(f"  {k}: {int(bad.sum())} differing events", flush=True)
+        assert bad.sum() == 0
+
+
+def test_accept_reject_refuses_a_low_envelope(P):
+    sp = spec_of("c1")
+    g = P.Graph.from_spec(sp)
+    with pytest.raises(P.HipfitError) as ei:
+        P.Dataset.generate_ar(g, [-0.5], 1000, 1, 0.3)
+    assert ei.value.code == -6
+    with pytest.raises(P.HipfitError) as ei:
+        P.Dataset.generate_ar(g, [-0.5], 1000, 1, 1e6, max_trials=1)
+    assert ei.value.code == -6

@@ -648,7 +648,7 @@ __device__ __forceinline__ T conv_leaf(const CS& cs, const KNode& cn, double x, 
 // wave-uniform node / slot numbers.
 // Returns ln P of the root (without the normalisations of hoisted nodes)
 // and, with GRAD, its slot derivatives in dl[0 .. P.n_slots).
-template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const double* xe, T* dl) {
     // node capacity of this instantiation; float arrays get 16 entries so
     // that the compiler indexes them with register moves (8 floats become
@@ -679,7 +679,7 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           if (j < nd.aux) dl[s0 + j] = dp[j];
-      } else if (HEAVY && (op == OP_DALITZ || op == OP_TDDP)) {
+      } else if (HEAVY >= 2 && (op == OP_DALITZ || op == OP_TDDP)) {
         const int ns = nd.n_slot;
         const auto emit = [&](int j, const T (&d)[1]) {
           if (j < ns) dl[s0 + j] = d[0];
@@ -887,7 +887,7 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
     return lv[root];
 }
 
-template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 struct TreeEv {
   CS cs;
   template <class Acc>
@@ -907,7 +907,7 @@ struct TreeEv {
 // normalisations L are subtracted here.  Accumulators: [metric, sum over
 // bins of dmetric/dlnP x slot derivatives, sum of dmetric/dlnP] -- the last
 // carries the hoisted normalisations' derivatives on the host.
-template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 struct BinnedEv {
   CS cs;
   const double* w;
@@ -1184,7 +1184,7 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
   }
 }
 
-template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 __device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
                                          int n_rows, int r, double* __restrict__ out) {
   typedef typename Col<T>::S Sx;
@@ -1223,6 +1223,7 @@ __device__ __forceinline__ bool dp_pair_in(double M, double m1, double sx, doubl
 // (u * envelope < P in double); the first accepted candidate is the event,
 // so the output does not depend on the launch shape.  An event that runs out
 // of trials, or a density above the envelope, sets a flag bit.
+template <int H>
 __global__ __launch_bounds__(256) void k_generate_ar(const GenArArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1250,7 +1251,7 @@ __global__ __launch_bounds__(256) void k_generate_ar(const GenArArgs a) {
       }
       if (in) {
         double dl[kMaxSlots];
-        const double p = ::exp(tree_eval<double, kMaxSlots, kMaxCols, true, false>(a.prog, cs, x, dl) - a.ln_hoist);
+        const double p = ::exp(tree_eval<double, kMaxSlots, kMaxCols, H, false>(a.prog, cs, x, dl) - a.ln_hoist);
         if (p > a.env) flag |= 2;
         if (__dmul_rn(ua, a.env) < p) done = true;
       }
@@ -1270,7 +1271,8 @@ hipError_t launch_generate_ar(const GenArArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   const int64_t blocks = (a.n + 255) / 256;
   const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
-  hipLaunchKernelGGL(k_generate_ar, dim3(grid), dim3(256), 0, st, a);
+  if (a.dalitz) hipLaunchKernelGGL(k_generate_ar<2>, dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_generate_ar<1>, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1386,7 +1388,7 @@ void k_leaf(const EvalArgs a) {
     amp_leaf_row<T, OP, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
 }
 
-template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   tree_row<T, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
@@ -1399,7 +1401,7 @@ __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
 }
 
 // Binned datasets (any tree): the tree interpreter with the binned metric.
-template <typename T, int NS, int NCOL, bool HEAVY, bool GRAD>
+template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_binned(const EvalArgs a) {
   typedef typename Col<T>::S Sx;
   constexpr int NC = NS + 2;
@@ -1468,7 +1470,7 @@ __global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
   }
 }
 
-template <typename T, int NS, int NCOL, bool HEAVY>
+template <typename T, int NS, int NCOL, int HEAVY>
 __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
   const int total = a.hdr->total_rows, n_fits = a.hdr->n_fits;
   const FitRec* fits = (const FitRec*)(a.hdr + 1);
@@ -1494,13 +1496,14 @@ static const void* kernel_of(int kind) {
   switch (kind) {
     case KIND_EXP: return (const void*)&k_leaf<T, OP_EXP, GRAD>;
     case KIND_GAUSS: return (const void*)&k_leaf<T, OP_GAUSS, GRAD>;
-    case KIND_TREE_SMALL: return (const void*)&k_tree<T, 8, 2, false, GRAD>;
+    case KIND_TREE_SMALL: return (const void*)&k_tree<T, 8, 2, 0, GRAD>;
     case KIND_DALITZ: return (const void*)&k_leaf<T, OP_DALITZ, GRAD>;
     case KIND_TDDP: return (const void*)&k_leaf<T, OP_TDDP, GRAD>;
     case KIND_TDDPX: return (const void*)&k_leaf<T, OP_TDDP_X, GRAD>;
     case KIND_TDDPS: return (const void*)&k_leaf<T, OP_TDDP_S, GRAD>;
     case KIND_TDDPXS: return (const void*)&k_leaf<T, OP_TDDP_XS, GRAD>;
-    case KIND_TREE: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, true, GRAD>;
+    case KIND_TREE: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, 2, GRAD>;
+    case KIND_TREE_NOAMP: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, 1, GRAD>;
     default: return nullptr;  // mixtures: light, never below kRowsPerCU
   }
 }
@@ -1526,14 +1529,17 @@ static hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st, hipEve
   switch (kind) {
     case KIND_EXP: hipExtLaunchKernelGGL((k_leaf<T, OP_EXP, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_GAUSS: hipExtLaunchKernelGGL((k_leaf<T, OP_GAUSS, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
-    case KIND_TREE_SMALL: hipExtLaunchKernelGGL((k_tree<T, 8, 2, false, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TREE_SMALL: hipExtLaunchKernelGGL((k_tree<T, 8, 2, 0, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_DALITZ: hipExtLaunchKernelGGL((k_leaf<T, OP_DALITZ, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDP: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDPX: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_X, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDPS: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_S, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDPXS: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_XS, GRAD>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TREE:
-      hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+      hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, 2, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+      break;
+    case KIND_TREE_NOAMP:
+      hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, 1, GRAD>), grid, block, 0, st, e0, e1, 0, a);
       break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
@@ -1555,16 +1561,18 @@ hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStr
 }
 
 template <typename T, bool GRAD>
-static hipError_t launch_binned_t(bool heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t launch_binned_t(int heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid((unsigned)a.n_rows), block(kBlock);
-  if (heavy)
-    hipExtLaunchKernelGGL((k_binned<T, kMaxSlots, kMaxCols, true, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+  if (heavy >= 2)
+    hipExtLaunchKernelGGL((k_binned<T, kMaxSlots, kMaxCols, 2, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+  else if (heavy == 1)
+    hipExtLaunchKernelGGL((k_binned<T, kMaxSlots, kMaxCols, 1, GRAD>), grid, block, 0, st, e0, e1, 0, a);
   else
-    hipExtLaunchKernelGGL((k_binned<T, 8, 2, false, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((k_binned<T, 8, 2, 0, GRAD>), grid, block, 0, st, e0, e1, 0, a);
   return hipGetLastError();
 }
 
-hipError_t launch_binned(bool fp32, bool grad, bool heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0,
+hipError_t launch_binned(bool fp32, bool grad, int heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0,
                          hipEvent_t e1) {
   if (a.n_rows <= 0) return hipSuccess;
   if (fp32)
@@ -1578,13 +1586,14 @@ static hipError_t launch_b(int kind, const BatchArgs& a, int grid, hipStream_t s
   switch (kind) {
     case KIND_EXP: hipLaunchKernelGGL((k_leaf_batched<T, OP_EXP>), g, b, 0, st, a); break;
     case KIND_GAUSS: hipLaunchKernelGGL((k_leaf_batched<T, OP_GAUSS>), g, b, 0, st, a); break;
-    case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree_batched<T, 8, 2, false>), g, b, 0, st, a); break;
+    case KIND_TREE_SMALL: hipLaunchKernelGGL((k_tree_batched<T, 8, 2, 0>), g, b, 0, st, a); break;
     case KIND_DALITZ: hipLaunchKernelGGL((k_leaf_batched<T, OP_DALITZ>), g, b, 0, st, a); break;
     case KIND_TDDP: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP>), g, b, 0, st, a); break;
     case KIND_TDDPX: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_X>), g, b, 0, st, a); break;
     case KIND_TDDPS: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_S>), g, b, 0, st, a); break;
     case KIND_TDDPXS: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_XS>), g, b, 0, st, a); break;
-    case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, true>), g, b, 0, st, a); break;
+    case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, 2>), g, b, 0, st, a); break;
+    case KIND_TREE_NOAMP: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, 1>), g, b, 0, st, a); break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
     hipLaunchKernelGGL((k_mix_batched<T, K_, M_>), g, b, 0, st, a);                                 \

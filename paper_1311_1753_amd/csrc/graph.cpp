@@ -1476,7 +1476,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       // TDDP x sigma_t density of the event's Dalitz-plot cell: fused kernel
       g->kind = (int)g->nodes[0].par.size() == 2 * (int)g->nodes[0].consts[6] + 3 ? KIND_TDDPXS : KIND_TDDPS;
     else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2 && NN <= 8) g->kind = KIND_TREE_SMALL;
-    else g->kind = KIND_TREE;
+    else g->kind = g->dz.node >= 0 ? KIND_TREE : KIND_TREE_NOAMP;
     *out = g.release();
     return HF_OK;
   } catch (const std::exception& e) {

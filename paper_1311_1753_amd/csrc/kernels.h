@@ -17,6 +17,7 @@ enum KernelKind {
   KIND_TDDPX = 6,       // single TDDP leaf with x free (trigonometric terms)
   KIND_TDDPS = 7,       // PROD of a TDDP leaf (x = 0) and a DPMAP on its s12, s13, sigma_t
   KIND_TDDPXS = 12,     // the same with x free
+  KIND_TREE_NOAMP = 13, // any tree without DALITZ / TDDP nodes (the general interpreter minus the amplitude code)
   // root ADD of 2 (3) single-column EXP/GAUSS leaves: KIND_MIX2 (KIND_MIX3)
   // plus a mask with bit j set when child j is a GAUSS
   KIND_MIX2 = 8,
@@ -41,8 +42,9 @@ hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStr
                        hipEvent_t e1 = nullptr);
 hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Binned datasets: the tree interpreter with the binned metric; `heavy`
-// selects the general instantiation (32 slots, 8 columns, amplitude nodes).
-hipError_t launch_binned(bool fp32, bool grad, bool heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
+// selects the general instantiation (32 slots, 8 columns): 1 without, 2 with
+// the amplitude nodes.
+hipError_t launch_binned(bool fp32, bool grad, int heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);
 hipError_t launch_reduce(const FitRec* fits_dev, int n_fits, hipStream_t st);
 hipError_t launch_eval_batched(int kind, bool fp32, const KProgram& prog, const BatchHeader* hdr_dev, const double* c64,

@@ -178,7 +178,6 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
   if (d->n > 0) {
     if (int rc = ensure_result_buffer(d)) return rc;
     EvalArgs a;
-    std::memset(&a, 0, sizeof(a));
     a.prog = sc.prog;
     for (int c = 0; c < kMaxCols; ++c) a.col[c] = d->col[c];
     a.n_events = d->n;
@@ -188,9 +187,16 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     a.wcol = nullptr;
     a.kfac = 0.0;
     a.lnL = 0.0;
-    // the rows' sum: done by the evaluation kernel's last block (same order
-    // as the separate reduction kernel, which the batched path uses)
-    FitRec& fr = a.fr;
+    const bool prof = g_prof.on && (g_prof.calls++ % g_prof.every) == 0;
+    if (prof) {
+      hipError_t e = prof_harvest();
+      if (e != hipSuccess) return hip_fail(e, "profile events");
+    }
+    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
+                               prof ? g_prof.e[1] : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
+    FitRec fr;
+    std::memset(&fr, 0, sizeof(fr));
     fr.partials = d->partials;
     fr.n_rows = d->n_rows;
     fr.result = d->res_dev;
@@ -200,21 +206,8 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     dm->seq += 1;
     fr.flag = (int64_t*)(d->res_dev + kMaxSlots + 1);
     fr.seq = d->seq;
-    a.done = d->done;
-    const bool prof = g_prof.on && (g_prof.calls++ % g_prof.every) == 0;
-    if (prof) {
-      hipError_t e = prof_harvest();
-      if (e != hipSuccess) return hip_fail(e, "profile events");
-    }
-    hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
-                               prof ? g_prof.e[1] : nullptr);
-    if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
-    if (prof) {
-      // no separate reduction launch: its timing pair brackets nothing
-      e = hipEventRecord(g_prof.e[2], st);
-      if (e == hipSuccess) e = hipEventRecord(g_prof.e[3], st);
-      if (e != hipSuccess) return hip_fail(e, "profile events");
-    }
+    e = launch_reduce_one(fr, st, prof ? g_prof.e[2] : nullptr, prof ? g_prof.e[3] : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
     e = wait_result(d, st);
     if (e != hipSuccess) return hip_fail(e, "waiting for the reduction");
     if (prof) g_prof.pending = true;
@@ -257,19 +250,12 @@ static int make_dataset(const pdf_graph* g, int64_t n, hf_precision prec, int me
   const size_t col_bytes = align256((size_t)n * es);
   const size_t w_bytes = metric ? align256((size_t)n * sizeof(double)) : 0;
   const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * part_cols * sizeof(double));
-  const size_t total = col_bytes * nc + w_bytes + part_bytes + 256;
+  const size_t total = col_bytes * nc + w_bytes + part_bytes;
   void* blk = nullptr;
   hipError_t e = hipMalloc(&blk, total);
   if (e != hipSuccess) {
     d.reset();
     return fail(HF_E_OOM, std::string(who) + ": hipMalloc: " + hipGetErrorString(e));
-  }
-  d->done = (uint32_t*)((char*)blk + total - 256);
-  e = hipMemset(d->done, 0, 256);
-  if (e != hipSuccess) {
-    hipFree(blk);
-    d.reset();
-    return hip_fail(e, who);
   }
   d->block = blk;
   d->bytes = (int64_t)total;
@@ -646,14 +632,11 @@ extern "C" int dataset_wrap_device(const pdf_graph* g, void* const* dev_cols, in
     d->n_rows = rows_for(g->kind, prec, n);
     const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * (g->prog.n_slots + 1) * sizeof(double));
     void* blk = nullptr;
-    hipError_t e = hipMalloc(&blk, part_bytes + 256);
+    hipError_t e = hipMalloc(&blk, part_bytes);
     if (e != hipSuccess) return fail(HF_E_OOM, std::string("dataset_wrap_device: hipMalloc: ") + hipGetErrorString(e));
     d->block = blk;
     d->partials = (double*)blk;
-    d->bytes = (int64_t)(part_bytes + 256);
-    d->done = (uint32_t*)((char*)blk + part_bytes);
-    e = hipMemset(d->done, 0, 256);
-    if (e != hipSuccess) { hipFree(blk); return hip_fail(e, "dataset_wrap_device"); }
+    d->bytes = (int64_t)part_bytes;
     *out = d.release();
     return HF_OK;
   } catch (const std::exception& ex) {

@@ -1295,17 +1295,13 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = (a - (s - bp)) + (b - bp);
 }
 
-// WAVES: the waves of the calling block; the work is always cut into the
-// slices of kRedWaves waves, so that every block size sums in the same order
-// (bitwise equal results).
-template <int WAVES = kRedWaves>
 __device__ __forceinline__ void reduce_fit(const FitRec& fr) {
   const int nc = fr.n_slots + 1;
   const int R = fr.n_rows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int per_col = nc >= kRedWaves ? 1 : kRedWaves / nc;  // waves per column
   __shared__ double colsum[kMaxRedCols][kRedWaves][2];
-  for (int task = wave; task < nc * per_col; task += WAVES) {
+  for (int task = wave; task < nc * per_col; task += kRedWaves) {
     const int col = task / per_col, slice = task % per_col;
     const int r_begin = (int)((int64_t)R * slice / per_col);
     const int r_end = (int)((int64_t)R * (slice + 1) / per_col);
@@ -1364,24 +1360,6 @@ __device__ __forceinline__ void reduce_fit(const FitRec& fr) {
   }
 }
 
-// End of a single-dataset evaluation kernel with a `done` counter: every
-// block's row is stored; the block that finishes last (device-scope atomic
-// after a release fence) sums all rows as the separate reduction would,
-// writes the result and the host flag, and clears the counter for the next
-// call.  No block waits for another.
-__device__ __forceinline__ void last_block_reduce(const EvalArgs& a) {
-  if (a.done == nullptr) return;
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(a.done, 1u) == (uint32_t)(gridDim.x - 1) ? 1 : 0;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  reduce_fit<kBlock / 64>(a.fr);
-  if (threadIdx.x == 0) atomicExch(a.done, 0u);
-}
-
 __global__ __launch_bounds__(kRedBlock) void k_reduce(const FitRec* __restrict__ fits, int n_fits_max) {
   const FitRec& fr = fits[blockIdx.x];
   if (!fr.active) return;
@@ -1408,21 +1386,18 @@ void k_leaf(const EvalArgs a) {
     light_leaf_row<T, OP, GRAD>(a.prog.node[0], cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
   else
     amp_leaf_row<T, OP, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
-  last_block_reduce(a);
 }
 
 template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   tree_row<T, NS, NCOL, HEAVY, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
-  last_block_reduce(a);
 }
 
 template <typename T, int K, int MASK, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_mix(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   mix_row<T, K, MASK, GRAD>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, a.partials + blockIdx.x);
-  last_block_reduce(a);
 }
 
 // Binned datasets (any tree): the tree interpreter with the binned metric.

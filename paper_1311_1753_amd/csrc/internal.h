@@ -109,6 +109,24 @@ constexpr int dz_time_base(int R) { return dz_coef_base(R, true) + 2 * kMaxRes; 
 constexpr int dz_n_const(int R, bool tddp) { return dz_coef_base(R, tddp) + 2 * kMaxRes + (tddp ? kTdCount : 0); }
 
 // Arguments of one evaluation launch over one dataset.
+struct EvalArgs {
+  KProgram prog;
+  const void* col[kMaxCols];   // device columns (double or float)
+  int64_t n_events;
+  double* partials;            // column-major [n_slots + 1][n_rows]: sum(-ln P), slot sums
+  int32_t n_rows;              // one block per row
+  int32_t metric;              // 0: unbinned NLL; binned: 1 weighted NLL, 2 chi^2
+  const double* wcol;          // binned: bin weights (counts)
+  double kfac;                 // binned chi^2: expected count = kfac * P
+  double lnL;                  // binned: normalisations of hoisted nodes (ln P = kernel value - lnL)
+};
+
+// Header of a batched launch's device table, followed by the FitRec array.
+struct BatchHeader {
+  int32_t n_fits, total_rows, pad0, pad1;
+};
+
+// Per-fit record of a batched launch (device memory).
 struct FitRec {
   const void* col[kMaxCols];
   int64_t n_events;
@@ -121,28 +139,5 @@ struct FitRec {
   int64_t* flag;               // nullable: set to `seq` after the result is visible to the host
   int64_t seq;
 };
-
-struct EvalArgs {
-  KProgram prog;
-  const void* col[kMaxCols];   // device columns (double or float)
-  int64_t n_events;
-  double* partials;            // column-major [n_slots + 1][n_rows]: sum(-ln P), slot sums
-  int32_t n_rows;              // one block per row
-  int32_t metric;              // 0: unbinned NLL; binned: 1 weighted NLL, 2 chi^2
-  const double* wcol;          // binned: bin weights (counts)
-  double kfac;                 // binned chi^2: expected count = kfac * P
-  double lnL;                  // binned: normalisations of hoisted nodes (ln P = kernel value - lnL)
-  // nullable: blocks count themselves done here; the last one reduces the
-  // rows into `fr` (same order as the separate reduction) and resets it
-  uint32_t* done;
-  FitRec fr;
-};
-
-// Header of a batched launch's device table, followed by the FitRec array.
-struct BatchHeader {
-  int32_t n_fits, total_rows, pad0, pad1;
-};
-
-// Per-fit record of a batched launch (device memory).
 
 }  // namespace hf

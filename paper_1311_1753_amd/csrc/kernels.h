@@ -89,7 +89,6 @@ struct GenArArgs {
   int32_t* fail;               // bit 0: trials exhausted; bit 1: density above the envelope
 };
 static_assert(sizeof(GenArArgs) <= 4096, "kernel arguments are limited to 4 KiB");
-static_assert(sizeof(EvalArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 hipError_t launch_generate_ar(const GenArArgs& a, hipStream_t st);
 
 // Dalitz normalisation grid: M[w][p][q] for w in {I, Ibar, J} (n_mat of them),

@@ -93,7 +93,6 @@ struct dataset {
   const void* col[hf::kMaxCols] = {nullptr};
   double ref[hf::kMaxCols] = {0.0};           // per-column reference (float path)
   double* partials = nullptr;
-  uint32_t* done = nullptr;                   // device counter of finished rows (fused reduction)
   int32_t n_rows = 0;                         // one block per row (see rows_for)
   int64_t bytes = 0;
   double* res_host = nullptr;                 // pinned, device-mapped: result row, then the completion flag

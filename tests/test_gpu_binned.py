@@ -68,7 +68,7 @@ def histogram(name, seed):
         # only bins whose centre is inside the plot (their events are kept)
         return ({"s12": A.ravel()[inside], "s13": B.ravel()[inside]}, counts.ravel()[inside],
                 (e1[1] - e1[0]) * (e2[1] - e2[0]))
-    if name in ("mapped_sum", "shared_sum"):
+    if name in ("mapped_sum", "shared_sum", "comp", "conv"):
         from helpers import gen_data
         return hist1(gen_data(name, 100_000, seed)["x"], 0.0, 10.0, 100)
     raise ValueError(name)
@@ -90,7 +90,7 @@ def scales(om, th, cen, w, metric, vol):
 
 @pytest.mark.parametrize("metric", ["bnll", "chi2"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["c1", "c2", "poly", "listing2", "c3", "mapped_sum", "shared_sum"])
+@pytest.mark.parametrize("name", ["c1", "c2", "poly", "listing2", "c3", "mapped_sum", "shared_sum", "comp", "conv"])
 def test_binned_metric_matches_oracle(P, stream, name, prec, metric):
     print(f"\n[case] binned {name} {metric} {prec}", flush=True)
     sp = get_spec(name)

@@ -179,3 +179,20 @@ def test_toy_generation_refuses_unsampleable_graphs_and_bad_parameters():
         with pytest.raises(P.HipfitError) as ei:
             P.Dataset.generate(g, th, 10, 1)
         assert ei.value.code == -6, (th, ei.value)
+
+
+def test_accept_reject_generation_refuses_on_the_host():
+    """dataset_generate_ar: unbounded observables (the time-dependent
+    density's t), a non-positive envelope and zero trials are refused before
+    any device work."""
+    import paper_1311_1753_amd as P
+    sp = S.workload("c4")
+    g = P.Graph.from_spec(sp)
+    with pytest.raises(P.HipfitError) as ei:
+        P.Dataset.generate_ar(g, g.theta(sp["truth"]), 10, 1, 1.0)
+    assert ei.value.code == -2
+    g1 = P.Graph.from_spec(S.workload("c1"))
+    for env, trials in ((0.0, 10), (float("inf"), 10), (1.0, 0)):
+        with pytest.raises(P.HipfitError) as ei:
+            P.Dataset.generate_ar(g1, [-0.5], 10, 1, env, max_trials=trials)
+        assert ei.value.code == -1, (env, trials)

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
+#include "dp_inside.h"
 #include "internal.h"
 #include "kernels.h"
 #include "philox.h"
@@ -1204,20 +1205,6 @@ __device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const 
 }
 
 // ------------------------------------------------------------------ accept-reject toys
-// Membership of the Dalitz plot (both orderings of the kinematic limits of
-// s13 at fixed s12), the rule the datasets are validated with.
-__device__ __forceinline__ bool dp_pair_in(double M, double m1, double sx, double sy, double mx, double my) {
-  const double lo = (m1 + mx) * (m1 + mx), hi = (M - my) * (M - my);
-  if (!(sx >= lo && sx <= hi)) return false;
-  const double rs = ::sqrt(sx);
-  const double E1 = (sx - mx * mx + m1 * m1) / (2.0 * rs);
-  const double Ey = (M * M - sx - my * my) / (2.0 * rs);
-  const double p1 = ::sqrt(fmax(E1 * E1 - m1 * m1, 0.0));
-  const double py = ::sqrt(fmax(Ey * Ey - my * my, 0.0));
-  const double e = E1 + Ey;
-  return sy >= e * e - (p1 + py) * (p1 + py) && sy <= e * e - (p1 - py) * (p1 - py);
-}
-
 // Event i takes trials j = 0, 1, ...: its uniforms j (C + 1) + c place the
 // candidate's column c in the box, number j (C + 1) + C decides acceptance
 // (u * envelope < P in double); the first accepted candidate is the event,
@@ -1247,7 +1234,7 @@ __global__ __launch_bounds__(256) void k_generate_ar(const GenArArgs a) {
           s12 = c == a.c12 ? x[c] : s12;
           s13 = c == a.c13 ? x[c] : s13;
         }
-        in = dp_pair_in(a.M, a.m1, s12, s13, a.m2, a.m3) && dp_pair_in(a.M, a.m1, s13, s12, a.m3, a.m2);
+        in = dp_inside(a.M, a.m1, a.m2, a.m3, s12, s13);
       }
       if (in) {
         double dl[kMaxSlots];

@@ -19,6 +19,7 @@
 #include <set>
 #include <string>
 
+#include "dp_inside.h"
 #include "runtime.h"
 
 namespace hf {
@@ -112,18 +113,7 @@ void split(double x, float& hi, float& lo) {
 
 // ------------------------------------------------------------------ Dalitz helpers
 bool dalitz_inside(const DalitzInfo& dz, double s12, double s13) {
-  auto pair_in = [&](double s1x, double s1y, double mx, double my) {
-    const double lo = (dz.m1 + mx) * (dz.m1 + mx), hi = (dz.M - my) * (dz.M - my);
-    if (!(s1x >= lo && s1x <= hi)) return false;
-    const double rs = std::sqrt(s1x);
-    const double E1 = (s1x - mx * mx + dz.m1 * dz.m1) / (2.0 * rs);
-    const double Ey = (dz.M * dz.M - s1x - my * my) / (2.0 * rs);
-    const double p1 = std::sqrt(std::fmax(E1 * E1 - dz.m1 * dz.m1, 0.0));
-    const double py = std::sqrt(std::fmax(Ey * Ey - my * my, 0.0));
-    const double e = E1 + Ey;
-    return s1y >= e * e - (p1 + py) * (p1 + py) && s1y <= e * e - (p1 - py) * (p1 - py);
-  };
-  return pair_in(s12, s13, dz.m2, dz.m3) && pair_in(s13, s12, dz.m3, dz.m2);
+  return dp_inside(dz.M, dz.m1, dz.m2, dz.m3, s12, s13);
 }
 
 int ensure_grid(pdf_graph* g, hipStream_t st) {

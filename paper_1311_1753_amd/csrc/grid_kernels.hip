@@ -20,31 +20,13 @@
 #include <vector>
 
 #include "device_common.h"
+#include "dp_inside.h"
 #include "internal.h"
 #include "kernels.h"
 
 namespace hf {
 
 constexpr int kGridCells = 128;
-
-// Membership of (s_1x, s_1y) with x the partner of particle 1 and y the
-// bachelor: s_1x within [(m1+mx)^2, (M-my)^2] and s_1y within the limits at
-// that s_1x.  Evaluated without contractions so that the accepted cell set
-// does not depend on instruction selection.
-__device__ __forceinline__ bool in_pair(double M, double m1, double s1x, double s1y, double mx, double my) {
-#pragma clang fp contract(off)
-  const double lo = (m1 + mx) * (m1 + mx), hi = (M - my) * (M - my);
-  if (!(s1x >= lo && s1x <= hi)) return false;
-  const double rs = ::sqrt(s1x);
-  const double E1 = (s1x - mx * mx + m1 * m1) / (2.0 * rs);
-  const double Ey = (M * M - s1x - my * my) / (2.0 * rs);
-  const double p1 = ::sqrt(fmax(E1 * E1 - m1 * m1, 0.0));
-  const double py = ::sqrt(fmax(Ey * Ey - my * my, 0.0));
-  const double e = E1 + Ey;
-  const double smin = e * e - (p1 + py) * (p1 + py);
-  const double smax = e * e - (p1 - py) * (p1 - py);
-  return s1y >= smin && s1y <= smax;
-}
 
 struct GridArgs {
   KProgram prog;
@@ -69,8 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows(const GridArgs a) {
 #pragma clang fp contract(off)
       s12 = a.gs.lo12 + ((double)row + 0.5) * a.gs.h12;
       s13 = a.gs.lo13 + ((double)col + 0.5) * a.gs.h13;
-      in = in_pair(a.gs.M, a.gs.m1, s12, s13, a.gs.m2, a.gs.m3) &&
-           in_pair(a.gs.M, a.gs.m1, s13, s12, a.gs.m3, a.gs.m2);
+      in = dp_inside(a.gs.M, a.gs.m1, a.gs.m2, a.gs.m3, s12, s13);
     }
     AmpArr<double> a0, b0;
     if (in) {

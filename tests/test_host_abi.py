@@ -196,3 +196,42 @@ def test_accept_reject_generation_refuses_on_the_host():
         with pytest.raises(P.HipfitError) as ei:
             P.Dataset.generate_ar(g1, [-0.5], 10, 1, env, max_trials=trials)
         assert ei.value.code == -1, (env, trials)
+
+
+def test_dalitz_membership_on_the_boundary_matches_the_oracle(oracle_mod):
+    """Points placed on the kinematic boundary and a few ulps either side:
+    the library's membership rule (the one the upload validation, the
+    normalisation grid and the accept-reject generator share) and the
+    oracle's agree point by point, and both include exact boundary points
+    and reject points clearly outside."""
+    import paper_1311_1753_amd as P
+    g = P.Graph.from_spec(S.C3)
+    dz = S.C3["model"]["dalitz"]
+    M, m1, m2, m3 = dz["M"], dz["m1"], dz["m2"], dz["m3"]
+    rng = np.random.default_rng(31)
+    s12_all, s13_all = [], []
+    lo12, hi12 = (m1 + m2) ** 2, (M - m3) ** 2
+    for s12 in np.concatenate([rng.uniform(lo12, hi12, 300), [lo12, hi12]]):
+        # s13 limits at this s12 (textbook form, in double)
+        rs = np.sqrt(s12)
+        E1 = (s12 - m2 * m2 + m1 * m1) / (2 * rs)
+        E3 = (M * M - s12 - m3 * m3) / (2 * rs)
+        p1 = np.sqrt(max(E1 * E1 - m1 * m1, 0.0))
+        p3 = np.sqrt(max(E3 * E3 - m3 * m3, 0.0))
+        for edge in ((E1 + E3) ** 2 - (p1 + p3) ** 2, (E1 + E3) ** 2 - (p1 - p3) ** 2):
+            v = edge
+            for k in range(4):
+                v = np.nextafter(v, -np.inf)
+            for k in range(9):
+                s12_all.append(s12)
+                s13_all.append(v)
+                v = np.nextafter(v, np.inf)
+    s12_all, s13_all = np.array(s12_all), np.array(s13_all)
+    # and the mirrored points (the swapped ordering's boundary)
+    a = np.concatenate([s12_all, s13_all])
+    b = np.concatenate([s13_all, s12_all])
+    lib_in = g.dalitz_inside(a, b)
+    orc_in = np.array([oracle_mod.inside(dz, x, y) for x, y in zip(a, b)])
+    assert np.array_equal(lib_in.astype(bool), orc_in)
+    # both sides of the boundary occur among the probes
+    assert 0 < orc_in.sum() < orc_in.size

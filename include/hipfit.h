@@ -258,6 +258,12 @@ int dataset_read_column(const dataset* d, int32_t obs, void* hip_stream, double*
 void dataset_free(dataset* d);
 /* Device bytes held by a dataset (columns + workspace). */
 int64_t dataset_device_bytes(const dataset* d);
+/* Device bytes that dataset_upload / dataset_generate / dataset_generate_ar
+ * would allocate for an unbinned dataset of n_events events of graph g in
+ * precision prec (what dataset_device_bytes then reports), so that a caller
+ * can reserve device memory before it uploads.  HF_E_INVALID for NULL
+ * pointers, a negative or too large n_events or an unknown precision. */
+int dataset_bytes_needed(const pdf_graph* g, int64_t n_events, hf_precision prec, int64_t* bytes);
 
 /* ------------------------------------------------------------------ likelihood
  * params: n_par doubles (external values, fixed ones included).  Runs the
@@ -278,7 +284,9 @@ int nll_grad(const pdf_graph* g, const dataset* d, const double* params, void* h
  * params is n_fits x n_par row-major) in one launch; each result is bitwise
  * equal to what nll_grad returns for that fit alone.  nll[n_fits],
  * grad[n_fits x n_par]; per-fit domain errors give +INF for that fit only
- * (the call still returns HF_OK). */
+ * (the call still returns HF_OK).  A dataset may appear several times (for
+ * example one dataset at several parameter points): each repeat is
+ * evaluated by a following launch, as its partial sums have one workspace. */
 int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int32_t n_fits,
                      const double* params, void* hip_stream, double* nll, double* grad);
 

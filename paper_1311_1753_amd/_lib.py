@@ -92,6 +92,7 @@ SIGNATURES = {
                                            ctypes.c_int32, ctypes.c_int, _VP, ctypes.POINTER(_VP)]),
     "dataset_free": (None, [_VP]),
     "dataset_device_bytes": (ctypes.c_int64, [_VP]),
+    "dataset_bytes_needed": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     # theta and grad are passed as raw addresses (numpy .ctypes.data)
     "nll_eval": (ctypes.c_int, [_VP, _VP, _VP, _VP, _DP]),
     "nll_grad": (ctypes.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),

@@ -140,6 +140,13 @@ class Graph:
         check(lib().hf_column_ref(self.handle, self.obs_names.index(name), _prec(precision), ctypes.byref(r)))
         return r.value
 
+    def dataset_bytes(self, n_events, precision="fp32"):
+        """Device bytes a dataset of n_events events of this graph takes
+        (dataset_bytes_needed)."""
+        b = ctypes.c_int64()
+        check(lib().dataset_bytes_needed(self._h, int(n_events), _prec(precision), ctypes.byref(b)))
+        return b.value
+
     def dalitz_inside(self, s12, s13):
         a = np.ascontiguousarray(s12, dtype=np.float64)
         b = np.ascontiguousarray(s13, dtype=np.float64)

@@ -232,6 +232,26 @@ using namespace hf;
 // Allocates a dataset of n events for graph g: one device block holding the
 // columns (256-byte aligned, storage format of `prec`), the binned weights
 // (metric != 0) and the partial rows of the evaluation kernels.
+// Sizes of that block's parts.
+struct DatasetLayout {
+  int32_t n_rows;
+  size_t col_bytes, w_bytes, part_bytes, total;
+};
+static DatasetLayout dataset_layout(const pdf_graph* g, int64_t n, hf_precision prec, int metric) {
+  DatasetLayout L;
+  const int nc = (int)g->obs_of_col.size();
+  const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
+  // binned datasets run the tree interpreter: one event per chunk and
+  // thread, partial columns [metric, tree slots, sum of dmetric/dlnP]
+  L.n_rows = rows_for(metric ? (int)KIND_TREE : g->kind, prec, n);
+  const int part_cols = metric ? g->n_slots_tree + 2 : g->prog.n_slots + 1;
+  L.col_bytes = align256((size_t)n * es);
+  L.w_bytes = metric ? align256((size_t)n * sizeof(double)) : 0;
+  L.part_bytes = align256((size_t)std::max<int32_t>(L.n_rows, 1) * part_cols * sizeof(double));
+  L.total = L.col_bytes * nc + L.w_bytes + L.part_bytes;
+  return L;
+}
+
 static int make_dataset(const pdf_graph* g, int64_t n, hf_precision prec, int metric, double volume, const char* who,
                         std::unique_ptr<dataset>& d) {
   d.reset(new dataset);
@@ -240,17 +260,11 @@ static int make_dataset(const pdf_graph* g, int64_t n, hf_precision prec, int me
   d->prec = prec;
   d->n = n;
   d->n_cols = nc;
-  const size_t es = prec == HF_FP32_EVAL ? 4 : 8;
-  // binned datasets run the tree interpreter: one event per chunk and
-  // thread, partial columns [metric, tree slots, sum of dmetric/dlnP]
   d->metric = metric;
   d->volume = volume;
-  d->n_rows = rows_for(metric ? (int)KIND_TREE : g->kind, prec, n);
-  const int part_cols = metric ? g->n_slots_tree + 2 : g->prog.n_slots + 1;
-  const size_t col_bytes = align256((size_t)n * es);
-  const size_t w_bytes = metric ? align256((size_t)n * sizeof(double)) : 0;
-  const size_t part_bytes = align256((size_t)std::max<int32_t>(d->n_rows, 1) * part_cols * sizeof(double));
-  const size_t total = col_bytes * nc + w_bytes + part_bytes;
+  const DatasetLayout L = dataset_layout(g, n, prec, metric);
+  d->n_rows = L.n_rows;
+  const size_t col_bytes = L.col_bytes, w_bytes = L.w_bytes, total = L.total;
   void* blk = nullptr;
   hipError_t e = hipMalloc(&blk, total);
   if (e != hipSuccess) {
@@ -652,6 +666,14 @@ extern "C" void dataset_free(dataset* d) {
 }
 
 extern "C" int64_t dataset_device_bytes(const dataset* d) { return d ? d->bytes : 0; }
+
+extern "C" int dataset_bytes_needed(const pdf_graph* g, int64_t n_events, hf_precision prec, int64_t* bytes) {
+  if (!g || !bytes) return fail(HF_E_INVALID, "dataset_bytes_needed: NULL argument");
+  if (n_events < 0 || n_events > (int64_t(1) << 36)) return fail(HF_E_INVALID, "dataset_bytes_needed: n_events out of range");
+  if (prec != HF_FP64 && prec != HF_FP32_EVAL) return fail(HF_E_INVALID, "dataset_bytes_needed: bad precision");
+  *bytes = (int64_t)dataset_layout(g, n_events, prec, 0).total;
+  return HF_OK;
+}
 
 static int check_call(const pdf_graph* g, const dataset* d, const double* params) {
   if (!g || !d || !params) return fail(HF_E_INVALID, "NULL graph, dataset or params");

@@ -179,18 +179,33 @@ extern "C" int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int
       }
     }
     std::vector<double> rows((size_t)n_fits * (g->prog.n_slots + 1), 0.0);
-    if (!ds.empty()) {
+    // A dataset's partial rows serve one fit per launch: fits that repeat a
+    // dataset already in the launch go to a following launch (each result
+    // is still the one nll_grad gives alone).
+    while (!ds.empty()) {
+      std::vector<const dataset*> run_ds, rest_ds;
+      std::vector<const StagedCall*> run_sc, rest_sc;
+      std::vector<int> run_which, rest_which;
+      for (size_t k = 0; k < ds.size(); ++k) {
+        const bool seen = std::find(run_ds.begin(), run_ds.end(), ds[k]) != run_ds.end();
+        (seen ? rest_ds : run_ds).push_back(ds[k]);
+        (seen ? rest_sc : run_sc).push_back(scp[k]);
+        (seen ? rest_which : run_which).push_back(which[k]);
+      }
       BatchTables t;
-      int rc = t.alloc((int)ds.size(), g->n_const, g->prog.n_slots);
+      int rc = t.alloc((int)run_ds.size(), g->n_const, g->prog.n_slots);
       if (rc) { t.release(); return rc; }
-      fill_tables(g, t, ds, scp);
+      fill_tables(g, t, run_ds, run_sc);
       hipError_t e = enqueue_step(g, d[0]->prec == HF_FP32_EVAL, t, st);
-      if (e == hipSuccess) e = wait_fits(t, (int)ds.size(), st);
+      if (e == hipSuccess) e = wait_fits(t, (int)run_ds.size(), st);
       if (e != hipSuccess) { t.release(); return hip_fail(e, "nll_grad_batched"); }
-      for (size_t k = 0; k < ds.size(); ++k)
-        std::memcpy(&rows[(size_t)which[k] * (g->prog.n_slots + 1)], t.res_h + k * t.RS(),
+      for (size_t k = 0; k < run_ds.size(); ++k)
+        std::memcpy(&rows[(size_t)run_which[k] * (g->prog.n_slots + 1)], t.res_h + k * t.RS(),
                     (t.S + 1) * sizeof(double));
       t.release();
+      ds.swap(rest_ds);
+      scp.swap(rest_sc);
+      which.swap(rest_which);
     }
     for (int i = 0; i < n_fits; ++i) {
       if (!sc[i].ok) {

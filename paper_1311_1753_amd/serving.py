@@ -10,8 +10,12 @@ running fits may hold at most `hbm_budget_bytes`.
 event sample), are uploaded on a separate thread and stream, admitted in FIFO
 order as slots and budget free up, stepped together, and retired as they
 converge -- requests that arrive while others are on the GPU join the running
-batch at the next step boundary.  It records per-request latency (arrival to
-result on the host) and overall fits/s.
+batch at the next step boundary.  Device memory is reserved before an
+upload: a request's dataset is put on the device only when the datasets
+already there (running and waiting fits) leave room for it within the
+budget, so the datasets never hold more than `hbm_budget_bytes`; waiting
+requests stay host columns until then.  It records per-request latency
+(arrival to result on the host) and overall fits/s.
 """
 import collections
 import ctypes
@@ -86,6 +90,7 @@ class FitServer:
     def __init__(self, graph, precision="fp32", max_slots=256, hbm_budget_bytes=16 << 30, upload_stream=None):
         self.graph = graph
         self.precision = precision
+        self.budget = int(hbm_budget_bytes)
         self.engine = BatchEngine(graph, max_slots, hbm_budget_bytes)
         self.upload_stream = upload_stream
 
@@ -95,7 +100,10 @@ class FitServer:
 
         columns_of(req) -> event columns, uploaded from the host; or
         dataset_of(req, stream) -> Dataset made on the device (e.g. a toy
-        drawn with Dataset.generate), columns_of then unused.
+        drawn with Dataset.generate), columns_of then unused; either way
+        the event count (the columns' length) gives the device bytes
+        reserved before the dataset is made (req["n"] when the columns are
+        not given).
         theta0_of(req) -> start values.  realtime=False submits every request
         at t = 0 (closed loop).  Returns (results by id, summary)."""
         reqs = sorted(requests, key=lambda r: r["arrival_s"])
@@ -104,6 +112,25 @@ class FitServer:
         t0 = time.perf_counter()
         stop = threading.Event()
         errors = []
+        # device bytes of the datasets made and not yet freed (waiting and
+        # running fits), guarded by `room`
+        room = threading.Condition()
+        held = {"bytes": 0, "peak": 0}
+
+        def reserve(nbytes):
+            if nbytes > self.budget:
+                raise ValueError("a request's dataset (%d bytes) exceeds the whole budget (%d bytes)"
+                                 % (nbytes, self.budget))
+            with room:
+                while held["bytes"] + nbytes > self.budget and not stop.is_set():
+                    room.wait(timeout=0.5)
+                held["bytes"] += nbytes
+                held["peak"] = max(held["peak"], held["bytes"])
+
+        def release(nbytes):
+            with room:
+                held["bytes"] -= nbytes
+                room.notify_all()
 
         def uploader():
             try:
@@ -113,10 +140,24 @@ class FitServer:
                         time.sleep(wait)
                     if stop.is_set():
                         return
+                    cols = None
+                    if dataset_of is not None:
+                        n = int(r["n"])
+                    else:
+                        cols = columns_of(r)
+                        n = len(next(iter(cols.values())))
+                    need = self.graph.dataset_bytes(n, self.precision)
+                    reserve(need)
+                    if stop.is_set():
+                        release(need)
+                        return
                     if dataset_of is not None:
                         ds = dataset_of(r, self.upload_stream)
                     else:
-                        ds = Dataset(self.graph, columns_of(r), self.precision, self.upload_stream)
+                        ds = Dataset(self.graph, cols, self.precision, self.upload_stream)
+                    if ds.device_bytes != need:
+                        release(need)
+                        reserve(ds.device_bytes)
                     ready.put((r, ds))
             except Exception as e:  # surfaced by the main loop
                 errors.append(e)
@@ -160,7 +201,9 @@ class FitServer:
                     for res in eng.poll():
                         r, ds, t_adm = live.pop(res["tag"])
                         t_done = time.perf_counter() - t0
+                        nbytes = ds.device_bytes
                         ds.free()
+                        release(nbytes)
                         res.update({"arrival_s": arrivals[r["id"]], "admit_s": t_adm, "done_s": t_done,
                                     "latency_s": t_done - arrivals[r["id"]], "n_events": ds.n})
                         results[r["id"]] = res
@@ -168,6 +211,8 @@ class FitServer:
                     break
         finally:
             stop.set()
+            with room:
+                room.notify_all()
             th.join(timeout=60)
         lat = np.array([v["latency_s"] for v in results.values()])
         done = np.array([v["done_s"] for v in results.values()])
@@ -177,7 +222,8 @@ class FitServer:
                    "fits_per_s": len(results) / span if span > 0 else float("nan"),
                    "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else float("nan"),
                    "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else float("nan"),
-                   "statuses": dict(collections.Counter(v["status"] for v in results.values()))}
+                   "statuses": dict(collections.Counter(v["status"] for v in results.values())),
+                   "peak_dataset_bytes": held["peak"], "budget_bytes": self.budget}
         return results, summary
 
     def close(self):

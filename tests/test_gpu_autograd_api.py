@@ -30,6 +30,21 @@ def test_autograd_gradcheck(P):
     assert torch.autograd.gradcheck(f, (th,), eps=1e-7, atol=1e-4, rtol=1e-5)
 
 
+def test_autograd_with_theta_on_the_gpu(P):
+    """theta as a CUDA tensor: value and gradient come back on its device,
+    equal to the host-theta results."""
+    import torch
+    g = P.Graph.from_spec(get_spec("c2"))
+    ds = P.Dataset(g, S.gen_c2(n=20_000, seed=4), "fp64")
+    th = torch.tensor([0.31, 5.2801, 0.0031, -2.1], dtype=torch.float64, device="cuda", requires_grad=True)
+    v = P.autograd_nll(th, g, ds)
+    assert v.device == th.device
+    (2.0 * v).backward()
+    assert th.grad.device == th.device
+    ref_v, ref_g = P.nll_grad(g, ds, th.detach().cpu().numpy())
+    assert v.item() == ref_v and np.array_equal(th.grad.cpu().numpy(), 2.0 * ref_g)
+
+
 def test_listing1_flow_matches_oracle(P):
     """Variables -> UnbinnedDataSet.addEvent -> ExpPdf.setData -> FitManager.fit."""
     xvar = P.Variable("xvar", 0.0, 10.0)

@@ -105,11 +105,24 @@ def test_batched_equals_single_bitwise(P, stream, name, prec):
         d = data_for(name, n, 100 + i)
         dss.append(P.Dataset(g, d, prec, stream))
         ths.append(perturbed_theta(om, sp, seed=10 + i))
+    datas = [data_for(name, n, 100 + i) for i, n in enumerate(sizes)]
+    # the first dataset again at another parameter point: a repeated handle
+    dss.append(dss[0])
+    datas.append(datas[0])
+    ths.append(perturbed_theta(om, sp, seed=20))
     nll_b, grad_b = P.nll_grad_batched(g, dss, ths, stream)
-    for i in range(len(sizes)):
+    free = g.free_mask()
+    for i in range(len(dss)):
         v, gr = P.nll_grad(g, dss[i], ths[i], stream)
         assert v == nll_b[i], (i, v, nll_b[i])
         assert np.array_equal(gr, grad_b[i])
+        # and each batched result against the oracle on its own events
+        v_ref, g_ref = om.nll(ths[i], datas[i], grad=True)
+        s = nll_scale(om, ths[i], datas[i])
+        gs = grad_scale(om, ths[i], datas[i])
+        assert abs(nll_b[i] - v_ref) <= TOL[prec] * s, (i, nll_b[i], v_ref)
+        assert np.all(np.abs(grad_b[i] - g_ref)[free] <= TOL[prec] * gs[free]), i
+    assert nll_b[0] != nll_b[-1]
     # the same fit alone in a batch of one
     n1, g1 = P.nll_grad_batched(g, dss[1:2], ths[1:2], stream)
     assert n1[0] == nll_b[1] and np.array_equal(g1[0], grad_b[1])

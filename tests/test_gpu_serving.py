@@ -101,6 +101,26 @@ def test_fit_server_closed_and_open_loop(P):
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
 
 
+def test_fit_server_holds_datasets_within_budget(P):
+    """A budget of about three datasets and all requests arriving at once:
+    waiting requests stay on the host, the datasets on the device never
+    exceed the budget, and every fit still equals its engine fit."""
+    print("\n[case] fit server budget", flush=True)
+    g = P.Graph.from_spec(get_spec("c1"))
+    reqs = requests(12, seed=5)
+    ref = run_engine(P, g, reqs, "fp32")
+    big = max(g.dataset_bytes(r["n"], "fp32") for r in reqs)
+    budget = 3 * big
+    srv = P.FitServer(g, "fp32", max_slots=8, hbm_budget_bytes=budget)
+    res, summ = srv.run(reqs, cols, lambda r: [-2.0], realtime=False)
+    srv.close()
+    assert summ["n"] == len(reqs)
+    assert 0 < summ["peak_dataset_bytes"] <= budget
+    for r in reqs:
+        assert res[r["id"]]["status"] == "OK"
+        assert np.array_equal(res[r["id"]]["theta"], ref[r["id"]]["theta"])
+
+
 def test_fit_server_with_device_toys(P):
     """Requests whose toys are drawn on the device (Dataset.generate on the
     upload stream): every fit converges, and each equals the engine's fit of

@@ -235,3 +235,17 @@ def test_dalitz_membership_on_the_boundary_matches_the_oracle(oracle_mod):
     assert np.array_equal(lib_in.astype(bool), orc_in)
     # both sides of the boundary occur among the probes
     assert 0 < orc_in.sum() < orc_in.size
+
+
+def test_dataset_bytes_needed_argument_checks():
+    """The reservation query rejects bad arguments before any device query."""
+    import paper_1311_1753_amd as P
+    from paper_1311_1753_amd import _lib
+    L = _lib.lib()
+    g = P.Graph.from_spec(S.C1)
+    b = ctypes.c_int64(-7)
+    assert L.dataset_bytes_needed(None, 10, 0, ctypes.byref(b)) == -1
+    assert L.dataset_bytes_needed(g.handle, -1, 0, ctypes.byref(b)) == -1
+    assert L.dataset_bytes_needed(g.handle, 10, 5, ctypes.byref(b)) == -1
+    assert L.dataset_bytes_needed(g.handle, 10, 0, None) == -1
+    assert b.value == -7

@@ -381,7 +381,8 @@ double leaf_integral(const Model& m, const Node& n, const double* th, double u, 
 }
 
 // Unnormalised shape f of an EXP / GAUSS / POLY leaf at x (the forms of
-// leaf_integral) and d ln f / d theta added into g (dense); NaN when f <= 0.
+// leaf_integral) and d ln f / d theta added into g (dense); a POLY shape may
+// come out <= 0 (the caller decides what that means).
 double leaf_shape(const Model& m, const Node& n, const double* th, double x, double* g) {
   switch (n.kind) {
     case K_EXP: {
@@ -631,6 +632,7 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
       Neumaier Z;
       std::vector<Neumaier> dZ(m.n_par);
       std::vector<double> gm(m.n_par), dI(m.n_par);
+      bool undefined = false;
       for (int k = 0; k < n.grid; ++k) {
         const double t = lo + (k + 0.5) * h;
         const double u = std::max(lo - t, n.d_lo), v = std::min(hi - t, n.d_hi);
@@ -638,13 +640,19 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
         std::fill(gm.begin(), gm.end(), 0.0);
         std::fill(dI.begin(), dI.end(), 0.0);
         const double fm = leaf_shape(m, M, th, t, gm.data());
+        // a convolution of densities: a model shape that is not positive at
+        // a grid point that enters Z leaves the density undefined
+        if (!(fm > 0.0) || !std::isfinite(fm)) {
+          undefined = true;
+          break;
+        }
         const double I = leaf_integral(m, R, th, u, v, dI);
         Z.add(fm * I);
         for (int p = 0; p < m.n_par; ++p) dZ[p].add(fm * gm[p] * I + fm * dI[p]);
       }
       const double z = Z.value();
-      r.lnN = std::log(z);
-      for (int p = 0; p < m.n_par; ++p) r.dlnN[p] = dZ[p].value() / z;
+      r.lnN = undefined ? INFINITY : std::log(z);  // undefined: ln P = -inf at every event
+      for (int p = 0; p < m.n_par; ++p) r.dlnN[p] = undefined ? NAN : dZ[p].value() / z;
       break;
     }
     default:
@@ -730,7 +738,9 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
         const double t = lo + (k + 0.5) * h, d = x - t;
         if (d < n.d_lo || d > n.d_hi) continue;
         std::fill(gk.begin(), gk.end(), 0.0);
-        const double w = leaf_shape(m, M, th, t, gk.data()) * leaf_shape(m, R, th, d, gk.data());
+        const double fr = leaf_shape(m, R, th, d, gk.data());
+        if (!(fr > 0.0)) return -INFINITY;  // resolution shape not positive at a residual in use
+        const double w = leaf_shape(m, M, th, t, gk.data()) * fr;
         S.add(w);
         for (int p = 0; p < np; ++p) dS[p].add(w * gk[p]);
       }
@@ -1099,6 +1109,24 @@ void om_dalitz_amp2(Model* m, int id, const double* th, int64_t n, const double*
       for (int k = 0; k < d.n_amp(); ++k) A += c[k] * a[k];
       out[i] = std::norm(A);
     }
+  }
+}
+
+// sum_k |c_k A_k| (the constant term included) at the given theta for many
+// points, 0 outside: with |A| it gives the condition number of the
+// amplitude sum, the factor by which rounding in the terms can grow in A
+// (used to scale per-event tolerances).
+void om_dalitz_abs_terms(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
+                         double* out) {
+  const DalitzDef& d = *m->nodes[id].dz;
+  std::vector<cplx> a(d.n_amp()), c;
+  coeffs(d, th, c);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!inside(d, s12[i], s13[i])) { out[i] = 0.0; continue; }
+    amplitudes(d, s12[i], s13[i], a.data());
+    double t = 0.0;
+    for (int k = 0; k < d.n_amp(); ++k) t += std::abs(c[k] * a[k]);
+    out[i] = t;
   }
 }
 

@@ -26,11 +26,12 @@ _CH = {"12": 12, "13": 13, "23": 23}
 
 
 def build(force=True):
-    """Compile liboracle.so with g++ (plain -O2, no fast-math, OpenMP)."""
+    """Compile liboracle.so with g++ (plain -O2, no fast-math, no contraction into fused
+    multiply-adds: every expression is evaluated as written; OpenMP)."""
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["g++", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c++17",
+    subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c++17",
                            "-o", tmp, _SRC])
     os.replace(tmp, _LIB)
     return _LIB
@@ -79,6 +80,7 @@ def lib():
         L.om_dalitz_amp2.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp,
                                      ctypes.c_int, ctypes.c_int]
         L.om_dalitz_cross.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, ctypes.c_int]
+        L.om_dalitz_abs_terms.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp]
         L.om_dalitz_amp.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, dp]
         L.om_tddp_rate.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int]
         L.om_inside.restype = ctypes.c_int
@@ -288,6 +290,17 @@ class Model:
         out = np.zeros(2 * na * na)
         lib().om_dalitz_matrix(self._h, nid, which, _dp(out))
         return (out[0::2] + 1j * out[1::2]).reshape(na, na)
+
+    def dalitz_abs_terms(self, theta, s12, s13):
+        """sum_k |c_k A_k| (constant term included) per point, 0 outside the
+        plot: with |A| the condition number of the amplitude sum."""
+        nid, _ = self.dalitz_node()
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        a = np.ascontiguousarray(s12, dtype=np.float64)
+        b = np.ascontiguousarray(s13, dtype=np.float64)
+        out = np.empty(a.size)
+        lib().om_dalitz_abs_terms(self._h, nid, _dp(th), a.size, _dp(a), _dp(b), _dp(out))
+        return out
 
     def dalitz_amp2(self, theta, s12, s13, swapped=False, n_threads=None):
         nid, _ = self.dalitz_node()

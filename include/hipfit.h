@@ -121,7 +121,12 @@ enum hf_op {
                         the model's t or the resolution's residual);
                         Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms, on the
                         host); obs = {x}; no par; consts = {N (2..4096), d_lo, d_hi}; the
-                        per-event sum runs over all N points (cost ~ N per event)            */,
+                        per-event sum runs over all N points (cost ~ N per event); range
+                        tests take t_k = lo + (k + 1/2) h and x - t_k in double on the
+                        stored event value; a model shape <= 0 at a grid point whose
+                        residual window meets the box is a domain error of the parameters,
+                        a resolution shape <= 0 at a residual an event uses makes that
+                        event's density undefined (domain error)                            */,
   HF_OP_COMP = 11    /* function composition (section "Combining functions": CompositePdf):
                         P(x) = f(g(x)) / Z with the core g(x) = 1 + sum_j a_j (x - x0)^j, a
                         POLY leaf's value (degree <= 4), and f an EXP / GAUSS / POLY (degree
@@ -289,6 +294,23 @@ int nll_grad(const pdf_graph* g, const dataset* d, const double* params, void* h
  * evaluated by a following launch, as its partial sums have one workspace. */
 int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int32_t n_fits,
                      const double* params, void* hip_stream, double* nll, double* grad);
+/* Per-event terms of the likelihood (the metric's per-event values, paper
+ * section "GooFit code": the PDF evaluated at each event before the sum):
+ * lnp[i] = ln P(x_i; params) and, when dlnp is not NULL, dlnp[i * n_par + p]
+ * = d ln P(x_i) / d params[p] (0 for fixed parameters), for the n_events
+ * events of an unbinned dataset in its stored order.  They come from the
+ * evaluation kernels themselves, run so that each thread handles one event
+ * and writes its terms instead of adding them, followed by the same host
+ * assembly of normalisations as nll_grad; so nll_grad's NLL and gradient are
+ * sums of exactly these per-event values (up to the order of summation).
+ * Uses a temporary device buffer of at most 2^18 x (gradient slots + 1)
+ * doubles.  Blocking on hip_stream.  HF_E_INVALID for a binned dataset or a
+ * NULL lnp; HF_E_DOMAIN (all outputs still written, -INF where the density
+ * is <= 0, and at every event with NaN derivatives when the parameters are
+ * outside the density's domain) when the density is not positive and finite
+ * at some event. */
+int nll_terms(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream, double* lnp,
+              double* dlnp);
 
 /* ------------------------------------------------------------------ fit
  * Quasi-Newton (BFGS) minimisation with MINUIT-style sine transforms for

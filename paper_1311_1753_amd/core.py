@@ -352,6 +352,22 @@ def nll_grad(graph, ds, theta, stream=None, allow_domain=True):
     return out.value, g
 
 
+def nll_terms(graph, ds, theta, stream=None, grad=True, allow_domain=True):
+    """Per-event ln P_i and (grad) d ln P_i / d theta (n_events x n_par, 0 for
+    fixed parameters) from the evaluation kernels, in the dataset's stored
+    event order."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.size != graph.n_par:
+        raise ValueError("theta must have %d entries" % graph.n_par)
+    lp = np.empty(ds.n)
+    rows = np.empty((ds.n, graph.n_par)) if grad else None
+    rc = lib().nll_terms(graph.handle, ds.handle, th.ctypes.data, _stream_ptr(stream), lp.ctypes.data,
+                         rows.ctypes.data if grad else None)
+    if rc < 0:
+        check(rc, allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
+    return (lp, rows) if grad else lp
+
+
 def nll_grad_batched(graph, datasets, thetas, stream=None):
     """NLL and gradient of many fits (same graph) in one launch."""
     n = len(datasets)

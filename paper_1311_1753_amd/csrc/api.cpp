@@ -704,6 +704,79 @@ extern "C" int nll_grad(const pdf_graph* g, const dataset* d, const double* para
   }
 }
 
+// Per-event terms: the evaluation kernels instantiated with per-event output
+// (launch_terms), over slices of the dataset so that the device buffer stays
+// bounded; each event's terms are assembled like a one-event dataset.
+extern "C" int nll_terms(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream, double* lnp,
+                         double* dlnp) {
+  try {
+    if (int rc = check_call(g, d, params)) return rc;
+    if (!lnp) return fail(HF_E_INVALID, "nll_terms: NULL lnp");
+    if (d->metric != 0) return fail(HF_E_INVALID, "nll_terms: binned dataset (only unbinned datasets have terms)");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int np = (int)g->par.size();
+    if (int rc = ensure_grid(const_cast<pdf_graph*>(g), st)) return rc;
+    StagedCall sc;
+    stage(g, params, d->prec, sc, false);
+    if (!sc.ok) {  // the density is undefined at every event
+      for (int64_t i = 0; i < d->n; ++i) {
+        lnp[i] = -INFINITY;
+        if (dlnp)
+          for (int p = 0; p < np; ++p) dlnp[i * np + p] = NAN;
+      }
+      return fail(HF_E_DOMAIN, "nll_terms: parameters outside the density's domain");
+    }
+    if (d->n == 0) return HF_OK;
+    const int S = g->prog.n_slots, nc = 1 + S;
+    const int64_t kSlice = int64_t(1) << 18;  // events per terms launch
+    const int64_t slice_cap = std::min<int64_t>(kSlice, d->n);
+    const int64_t cap_rows = (slice_cap + kBlock - 1) / kBlock;
+    const size_t col_stride = (size_t)cap_rows * kBlock;
+    double* buf = nullptr;
+    hipError_t e = hipMalloc((void**)&buf, col_stride * nc * sizeof(double));
+    if (e != hipSuccess) return fail(HF_E_OOM, std::string("nll_terms: hipMalloc: ") + hipGetErrorString(e));
+    std::vector<double> host(col_stride * nc), sums(nc), gr(np);
+    const size_t es = d->prec == HF_FP32_EVAL ? 4 : 8;
+    bool bad = false;
+    int rc = HF_OK;
+    for (int64_t e0 = 0; e0 < d->n && rc == HF_OK; e0 += kSlice) {
+      const int64_t m = std::min<int64_t>(kSlice, d->n - e0);
+      EvalArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.prog = sc.prog;
+      for (int c = 0; c < kMaxCols; ++c)
+        a.col[c] = d->col[c] ? (const void*)((const char*)d->col[c] + (size_t)e0 * es) : nullptr;
+      a.n_events = m;
+      a.n_rows = (int32_t)((m + kBlock - 1) / kBlock);
+      a.partials = buf;
+      const size_t stride = (size_t)a.n_rows * kBlock;
+      e = launch_terms(g->kind, d->prec == HF_FP32_EVAL, a, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(host.data(), buf, stride * (dlnp ? nc : 1) * sizeof(double),
+                                              hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "nll_terms: terms launch");
+        break;
+      }
+      for (int64_t i = 0; i < m; ++i) {
+        for (int j = 0; j < (dlnp ? nc : 1); ++j) sums[j] = host[(size_t)j * stride + i];
+        double v = 0.0;
+        assemble(g, sc, sums.data(), 1, &v, dlnp ? gr.data() : nullptr);
+        lnp[e0 + i] = -v;
+        if (dlnp)
+          for (int p = 0; p < np; ++p) dlnp[(e0 + i) * np + p] = gr[p] == 0.0 ? 0.0 : -gr[p];
+        bad = bad || !std::isfinite(v);
+      }
+    }
+    hipFree(buf);
+    if (rc != HF_OK) return rc;
+    if (bad) return fail(HF_E_DOMAIN, "nll_terms: density <= 0 or not finite at some event");
+    return HF_OK;
+  } catch (const std::exception& ex) {
+    return fail(HF_E_INVALID, std::string("nll_terms: ") + ex.what());
+  }
+}
+
 extern "C" int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (g_prof.init) {

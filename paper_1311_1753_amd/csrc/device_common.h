@@ -10,6 +10,14 @@
 
 namespace hf {
 
+// Grid point t_k = lo + (k + 1/2) h of a numerical convolution, evaluated
+// as written (no fused multiply-add), so that the residual-range decisions
+// take the definition's double arithmetic.
+__device__ __forceinline__ double conv_grid_point(double lo, double h, int k) {
+#pragma clang fp contract(off)
+  return lo + ((double)k + 0.5) * h;
+}
+
 // ------------------------------------------------------------------ math
 template <typename T> struct Mth;
 template <> struct Mth<float> {

@@ -804,15 +804,25 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         double dm[8], dI[8];
         for (int k = 0; k < N; ++k) {
           const double t = o.lo + (k + 0.5) * h;
-          const double I = raw_integral(R, o.lo, std::max(o.lo - t, dlo), std::min(o.hi - t, dhi), dI);
-          if (I == 0.0 || !M.eval(t, l, dm)) continue;
+          const double u = std::max(o.lo - t, dlo), v = std::min(o.hi - t, dhi);
+          if (!(v > u)) continue;  // no residual of this grid point keeps x in the box
+          // a convolution of densities: the model's shape must be positive at
+          // every grid point that enters Z, else the density is undefined
+          if (!M.eval(t, l, dm)) {
+            ok = false;
+            continue;
+          }
+          const double I = raw_integral(R, o.lo, u, v, dI);
+          if (I == 0.0) continue;
           const double fm = std::exp(l);
           Z += fm * I;
           for (int j = 0; j < nm; ++j) dZ[j] += fm * dm[j] * I;
           for (int j = 0; j < nr; ++j) dZ[nm + j] += fm * dI[j];
         }
         if (!ok || !(Z > 0.0) || !std::isfinite(Z)) { sc.ok = false; Z = 1.0; }
-        P.c64[c0] = o.lo + 0.5 * h - ref;
+        // the kernel forms t_k = lo + (k + 1/2) h and x - t_k in double from
+        // the stored event's value, as here and in the definition
+        P.c64[c0] = o.lo;
         P.c32[c0] = (float)P.c64[c0];
         setc(c0 + 1, h);
         setc(c0 + 2, dlo);
@@ -839,29 +849,23 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         break;
       }
       case OP_DPMAP: {
-        // cell boundaries of s12 and s13 in their columns' offset frames
+        // the column references of s12 and s13 (the kernel adds them back
+        // to the stored values), then the cell boundaries
         const int n12 = (int)nd.consts[0], n13 = (int)nd.consts[1];
-        const double r12 = column_ref(g, kn.col[0], prec), r13 = column_ref(g, kn.col[1], prec);
-        for (int j = 0; j < n12 - 1; ++j) {
-          P.c64[c0 + j] = nd.consts[2 + j] - r12;
-          P.c32[c0 + j] = (float)P.c64[c0 + j];
-        }
-        for (int j = 0; j < n13 - 1; ++j) {
-          P.c64[c0 + n12 - 1 + j] = nd.consts[n12 + 1 + j] - r13;
-          P.c32[c0 + n12 - 1 + j] = (float)P.c64[c0 + n12 - 1 + j];
-        }
+        setc(c0, column_ref(g, kn.col[0], prec));
+        setc(c0 + 1, column_ref(g, kn.col[1], prec));
+        for (int j = 0; j < n12 - 1; ++j) setc(c0 + 2 + j, nd.consts[2 + j]);
+        for (int j = 0; j < n13 - 1; ++j) setc(c0 + 2 + n12 - 1 + j, nd.consts[n12 + 1 + j]);
         break;
       }
       case OP_MAP: {
-        // boundaries in the column's offset frame; Z = sum of the children's
-        // shares of their ranges (each child normalised over the box)
+        // boundaries, then the column reference (the kernel adds it back to
+        // the stored value); Z = sum of the children's shares of their
+        // ranges (each child normalised over the box)
         const int K = kn.n_child, col = kn.col[0];
         const ObsInfo& o = g->obs[g->obs_of_col[col]];
-        const double ref = column_ref(g, col, prec);
-        for (int j = 0; j < K - 1; ++j) {
-          P.c64[c0 + j] = nd.consts[j] - ref;
-          P.c32[c0 + j] = (float)P.c64[c0 + j];
-        }
+        for (int j = 0; j < K - 1; ++j) setc(c0 + j, nd.consts[j]);
+        setc(c0 + K - 1, column_ref(g, col, prec));
         double Z = 0.0;
         std::vector<std::vector<double>> dq(K);
         for (int j = 0; j < K; ++j) {
@@ -879,17 +883,17 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
             const double dz = dq[j][q] / Z;
             if (hoist) {
               sc.ht.dlnN[cn.par[q]] += dz;
-              setc(c0 + K + 1 + m, 0.0);
+              setc(c0 + K + 2 + m, 0.0);
             } else {
-              setc(c0 + K + 1 + m, dz);
+              setc(c0 + K + 2 + m, dz);
             }
           }
         }
         if (hoist) {
           sc.ht.lnN += lnZ;
-          set_ln(c0 + K - 1, c0 + K, 0.0);
+          set_ln(c0 + K, c0 + K + 1, 0.0);
         } else {
-          set_ln(c0 + K - 1, c0 + K, lnZ);
+          set_ln(c0 + K, c0 + K + 1, lnZ);
         }
         break;
       }
@@ -988,7 +992,7 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
     case OP_MAP: {
       int slots = 0;
       for (int c : n.child) slots += node_slots(all[c]);
-      return (int)n.child.size() + 1 + slots;
+      return (int)n.child.size() + 2 + slots;
     }
     case OP_PROD: {
       // with shared groups: lnZ_hi, lnZ_lo, then dlnZ/d(slot) of every child slot
@@ -997,7 +1001,7 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
       for (int c : n.child) slots += node_slots(all[c]);
       return 2 + slots;
     }
-    case OP_DPMAP: return (int)n.consts[0] + (int)n.consts[1] - 2;
+    case OP_DPMAP: return (int)n.consts[0] + (int)n.consts[1];
     case OP_CONV: return 8 + node_slots(all[n.child[0]]) + node_slots(all[n.child[1]]);
     case OP_COMP: return 3 + node_slots(all[n.child[0]]) + node_slots(all[n.child[1]]);
     case OP_EXP: return 5;

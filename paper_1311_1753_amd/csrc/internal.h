@@ -63,15 +63,17 @@ struct KProgram {
 //   GAUSS  0 loc = ref - mu (double), 1 1/sigma, 2 lnN_hi, 3 lnN_lo, 4 dlnN/dmu, 5 dlnN/dsigma
 //   POLY   0 loc = ref - x0 (double), 1..d a_k, d+1 lnN_hi, d+2 lnN_lo, d+3.. dlnN/da_k
 //   ADD    0..K-1 fractions (the last one 1 - sum of the others)
-//   MAP    0..K-2 inner range boundaries (double, in the column's offset frame),
-//          K-1 lnZ_hi, K lnZ_lo, then dlnZ/d(slot) for every slot of the
-//          children in child order (not hoisted; zeros when hoisted)
+//   MAP    0..K-2 inner range boundaries, K-1 column reference (added back
+//          to the stored value before the range test), K lnZ_hi, K+1 lnZ_lo,
+//          then dlnZ/d(slot) for every slot of the children in child order
+//          (not hoisted; zeros when hoisted)
 //   PROD   with leaves sharing an observable: 0 lnZ_hi, 1 lnZ_lo, then
 //          dlnZ/d(slot) for every slot of the children in child order
 //          (zeros when hoisted); otherwise none
-//   DPMAP  0..n12-2 s12 cell boundaries, then n13-1 s13 boundaries (double,
-//          in the columns' offset frames); aux = n13
-//   CONV   0 first grid point (offset frame), 1 grid step, 2 d_lo, 3 d_hi,
+//   DPMAP  0, 1 column references of s12 and s13, then n12-1 s12 cell
+//          boundaries and n13-1 s13 boundaries; aux = n13
+//   CONV   0 box lower end lo (grid t_k = lo + (k + 1/2) h), 1 grid step h,
+//          2 d_lo, 3 d_hi,
 //          4 column reference, 5 shift c of the exponents, 6 (lnZ - c)_hi,
 //          7 (lnZ - c)_lo, then dlnZ/d(slot) for the model's and the
 //          resolution's slots (not hoisted; zeros when hoisted); aux = N

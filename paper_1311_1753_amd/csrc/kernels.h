@@ -40,6 +40,9 @@ int resident_blocks_per_cu(int kind, bool fp32);
 // e0 / e1 (nullable): events that receive the dispatch's start / end time
 hipError_t launch_eval(int kind, bool fp32, bool grad, const EvalArgs& a, hipStream_t st, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
+// Terms launch of nll_terms: a.n_rows = the dataset's chunks (one per row);
+// a.partials receives [1 + accumulators][n_rows x 256] per-event terms.
+hipError_t launch_terms(int kind, bool fp32, const EvalArgs& a, hipStream_t st);
 hipError_t launch_reduce_one(const FitRec& fr, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Binned datasets: the tree interpreter with the binned metric; `heavy`
 // selects the general instantiation (32 slots, 8 columns): 1 without, 2 with

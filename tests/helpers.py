@@ -73,13 +73,7 @@ def gen_data(name, n, seed):
         th = m.theta(S.workload(name)["truth"])
         grid = np.linspace(0.0, 10.0, 4001)
         dens = lambda x: np.exp(m.logpdf(th, {"x": x}))
-        x = S.gen_accept_reject_1d(n, seed, dens, 1.2 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)
-        # events within 1e-5 of a range boundary move just above it: there the
-        # float-rounded offsets of the FP32-eval path could select the other range
-        for b in S.MAPPED["model"]["bounds"]:
-            near = np.abs(x - b) < 1e-5
-            x[near] = b + 1e-5
-        return {"x": x}
+        return {"x": S.gen_accept_reject_1d(n, seed, dens, 1.2 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)}
     if name == "comp":
         m = oracle_model(name)
         th = m.theta(S.workload(name)["truth"])
@@ -91,18 +85,7 @@ def gen_data(name, n, seed):
         th = m.theta(S.workload(name)["truth"])
         grid = np.linspace(0.0, 10.0, 4001)
         dens = lambda x: np.exp(m.logpdf(th, {"x": x}))
-        x = S.gen_accept_reject_1d(n, seed, dens, 1.3 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)
-        # events within 1e-5 of a point where the residual range starts or ends
-        # at a grid point move 2e-5 away: there the float-rounded offsets of
-        # the FP32-eval path could include or drop that grid term
-        sp = S.workload(name)["model"]
-        sp = sp if sp["op"] == "conv" else sp["children"][0]
-        h = 10.0 / sp["grid"]
-        for edge in (sp["d_lo"], sp["d_hi"]):
-            r = np.mod(x - edge - 0.5 * h, h)
-            near = np.minimum(r, h - r) < 1e-5
-            x[near] += 2e-5
-        return {"x": np.clip(x, 0.0, 10.0)}
+        return {"x": S.gen_accept_reject_1d(n, seed, dens, 1.3 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)}
     if name in ("shared", "shared_sum", "shared_2d"):
         # x from the 1-D density (the 2-D product factorises: x from the shared
         # product, y from its exponential by inverting the CDF)
@@ -141,6 +124,50 @@ def oracle_for(name):
     if name == "poly":
         return O.Model(POLY_SPEC)
     return oracle_model(name)
+
+
+def _nodes(m):
+    yield m
+    for c in m.get("children", []):
+        yield from _nodes(c)
+
+
+def column_refs(sp, prec):
+    """Per observable, the reference that the FP32-eval storage subtracts
+    (the documented storage format: the middle of a finite box; 0 for an
+    unbounded box and for the decay time and its uncertainty of a
+    time-dependent Dalitz node, which are stored as they are); 0 for FP64."""
+    if prec == "fp64":
+        return {o[0]: 0.0 for o in sp["obs"]}
+    raw = set()
+    for nd in _nodes(sp["model"]):
+        if nd["op"] == "tddp":
+            raw.update(nd["obs"][2:4])
+    out = {}
+    for name, lo, hi in sp["obs"]:
+        fin = math.isfinite(lo) and math.isfinite(hi)
+        out[name] = 0.5 * (lo + hi) if fin and name not in raw else 0.0
+    return out
+
+
+def stored_values(sp, data, prec):
+    """The events as the dataset holds them: FP64 as given; FP32-eval as the
+    float offset from the column reference, rounded once, plus the reference
+    (what the kernels evaluate, so the oracle is given the same events)."""
+    if prec == "fp64":
+        return {k: np.asarray(v, dtype=np.float64) for k, v in data.items()}
+    ref = column_refs(sp, prec)
+    return {k: ref[k] + (np.asarray(v, dtype=np.float64) - ref[k]).astype(np.float32).astype(np.float64)
+            for k, v in data.items()}
+
+
+def stored_order(sp, data):
+    """Event order of a dataset: graphs with a convolution node store their
+    events sorted by that node's observable (stable), others as given."""
+    for nd in _nodes(sp["model"]):
+        if nd["op"] == "conv":
+            return np.argsort(np.asarray(data[nd["obs"]]), kind="stable")
+    return np.arange(len(next(iter(data.values()))))
 
 
 def nll_scale(model, theta, data):

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synthgen as S
-from helpers import gen_data, get_spec, grad_scale, nll_scale, oracle_for, perturbed_theta
+from helpers import gen_data, get_spec, grad_scale, nll_scale, oracle_for, perturbed_theta, stored_values
 
 pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-12, "fp32": 1e-6}
@@ -74,10 +74,11 @@ def test_full_size_nll_grad(P, name, prec):
     g = P.Graph.from_spec(sp)
     ds = P.Dataset(g, data, prec)
     th = perturbed_theta(om, sp, rel=0.01, seed=3)
-    v_ref, g_ref = om.nll(th, data, grad=True)
+    sdata = stored_values(sp, data, prec)  # the events as stored (FP32-eval: float offsets)
+    v_ref, g_ref = om.nll(th, sdata, grad=True)
     v, gr = P.nll_grad(g, ds, th)
-    s = nll_scale(om, th, data)
-    gs = grad_scale(om, th, data)
+    s = nll_scale(om, th, sdata)
+    gs = grad_scale(om, th, sdata)
     free = g.free_mask()
     print(f"  n={ds.n} nll rel {abs(v - v_ref) / s:.2e} grad rel max {np.max(np.abs(gr - g_ref)[free] / gs[free]):.2e}",
           flush=True)

@@ -312,6 +312,27 @@ int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int32_t n_fits
 int nll_terms(const pdf_graph* g, const dataset* d, const double* params, void* hip_stream, double* lnp,
               double* dlnp);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): nll_grad over
+ * columns the caller already holds in device memory (dev_cols as for
+ * dataset_wrap_device, in the storage format of prec; NULL allowed for
+ * unused observables), with no dataset object and no allocation.  The
+ * evaluation kernels' partial rows and the result row live in a fixed
+ * 512 KiB device array of the library (one per GPU, kept until the process
+ * ends); the result comes back by a copy on hip_stream, and the call blocks
+ * until it is on the host.  Results are bitwise those of nll_grad on a
+ * dataset holding the same events.  Calls that overlap in time on one GPU
+ * share that array and race: serialise them.  HF_E_INVALID for NULL
+ * arguments, misaligned or missing used columns, more partial rows than the
+ * array holds (rows x (gradient slots + 1) > 65503 doubles; the default
+ * row count, 4 per compute unit, needs at most 33792), graphs with a CONV
+ * node (their events must be stored sorted) and Dalitz graphs whose
+ * normalisation grid has not been computed by an earlier nll_eval /
+ * nll_grad / fit; HF_E_DOMAIN as for nll_grad.  The columns are not
+ * validated. */
+int nll_grad_noalloc(const pdf_graph* g, void* const* dev_cols, int64_t n_events, hf_precision prec,
+                     const double* params, void* hip_stream, double* nll, double* grad);
+
 /* ------------------------------------------------------------------ fit
  * Quasi-Newton (BFGS) minimisation with MINUIT-style sine transforms for
  * bounded parameters, a bracketing line search, and a final Hessian from

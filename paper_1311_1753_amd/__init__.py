@@ -7,7 +7,8 @@ library; PyTorch is used only for device streams (and the autograd wrapper).
 """
 from ._lib import HipfitError, lib  # noqa: F401
 from .core import (FP32_EVAL, FP64, Dataset, Graph, fit, nll_eval, nll_grad,  # noqa: F401
-                   minimize, nll_grad_batched, nll_terms, profile, version)
+                   minimize, nll_grad_batched, nll_grad_noalloc, nll_terms, profile,
+                   version)
 from .serving import BatchEngine, FitServer, serve_one_at_a_time  # noqa: F401,E402
 
 

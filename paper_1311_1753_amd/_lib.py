@@ -97,6 +97,7 @@ SIGNATURES = {
     "nll_eval": (ctypes.c_int, [_VP, _VP, _VP, _VP, _DP]),
     "nll_grad": (ctypes.c_int, [_VP, _VP, _VP, _VP, _DP, _VP]),
     "nll_terms": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "nll_grad_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int, _VP, _VP, _DP, _VP]),
     "nll_grad_batched": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int32, _DP, _VP, _DP, _DP]),
     "fit": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(hf_fit_opts), _VP, _DP, _DP, _DP,
                            ctypes.POINTER(hf_fit_summary)]),

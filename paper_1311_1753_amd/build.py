@@ -18,7 +18,7 @@ OBJ = os.path.join(ROOT, "_build", "hipfit")
 LIB = os.path.join(HERE, "libhipfit.so")
 
 SOURCES = ["eval_kernels.hip", "terms_kernels.hip", "grid_kernels.hip", "gen_kernels.hip", "graph.cpp", "api.cpp",
-           "minimiser.cpp", "fit.cpp", "batch.cpp"]
+           "minimiser.cpp", "fit.cpp", "batch.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

@@ -368,6 +368,37 @@ def nll_terms(graph, ds, theta, stream=None, grad=True, allow_domain=True):
     return (lp, rows) if grad else lp
 
 
+def nll_grad_noalloc(graph, columns, theta, precision="fp64", stream=None, allow_domain=True):
+    """nll_grad over device tensors the caller holds (columns as for
+    Dataset.from_device) with no device allocation by the library: partial
+    sums in its fixed scratch array (nll_grad_noalloc).  Calls on one GPU
+    must not overlap."""
+    prec = _prec(precision)
+    want = "torch.float64" if prec == FP64 else "torch.float32"
+    ptrs = (ctypes.c_void_p * len(graph.obs_names))()
+    n = None
+    for i, name in enumerate(graph.obs_names):
+        t = columns.get(name)
+        if t is None:
+            continue
+        if str(t.dtype) != want or not t.is_cuda or not t.is_contiguous() or t.dim() != 1:
+            raise ValueError("column %r must be a contiguous 1-d CUDA tensor of %s" % (name, want))
+        if n is not None and t.numel() != n:
+            raise ValueError("columns differ in length")
+        n = t.numel()
+        ptrs[i] = t.data_ptr()
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.size != graph.n_par:
+        raise ValueError("theta must have %d entries" % graph.n_par)
+    out = ctypes.c_double()
+    g = np.empty(graph.n_par)
+    rc = lib().nll_grad_noalloc(graph.handle, ptrs, n or 0, prec, th.ctypes.data, _stream_ptr(stream),
+                                ctypes.byref(out), g.ctypes.data)
+    if rc < 0:
+        check(rc, allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
+    return out.value, g
+
+
 def nll_grad_batched(graph, datasets, thetas, stream=None):
     """NLL and gradient of many fits (same graph) in one launch."""
     n = len(datasets)

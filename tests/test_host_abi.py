@@ -249,3 +249,29 @@ def test_dataset_bytes_needed_argument_checks():
     assert L.dataset_bytes_needed(g.handle, 10, 5, ctypes.byref(b)) == -1
     assert L.dataset_bytes_needed(g.handle, 10, 0, None) == -1
     assert b.value == -7
+
+
+def test_noalloc_argument_checks():
+    """nll_grad_noalloc rejects bad arguments on the host, before any GPU
+    work: NULL outputs, a negative event count, an unknown precision, a
+    convolution graph (its events must be stored sorted) and a Dalitz graph
+    whose normalisation grid is not computed yet."""
+    import paper_1311_1753_amd as P
+    from paper_1311_1753_amd import _lib
+    L = _lib.lib()
+    g = P.Graph.from_spec(S.workload("c2"))
+    th = g.theta()
+    v = ctypes.c_double()
+    gr = np.zeros(g.n_par)
+    cols = (ctypes.c_void_p * 1)()
+    assert L.nll_grad_noalloc(g.handle, cols, 0, 0, th.ctypes.data, None, None, gr.ctypes.data) == -1
+    assert L.nll_grad_noalloc(g.handle, cols, -1, 0, th.ctypes.data, None, ctypes.byref(v), gr.ctypes.data) == -1
+    assert L.nll_grad_noalloc(g.handle, cols, 0, 7, th.ctypes.data, None, ctypes.byref(v), gr.ctypes.data) == -1
+    assert L.nll_grad_noalloc(g.handle, None, 5, 0, th.ctypes.data, None, ctypes.byref(v), gr.ctypes.data) == -1
+    assert L.nll_grad_noalloc(g.handle, cols, 5, 0, th.ctypes.data, None, ctypes.byref(v), gr.ctypes.data) == -1
+    for name, what in (("conv", "convolution"), ("c3", "grid")):
+        gc = P.Graph.from_spec(S.workload(name))
+        tc = gc.theta()
+        gg = np.zeros(gc.n_par)
+        rc = L.nll_grad_noalloc(gc.handle, cols, 0, 0, tc.ctypes.data, None, ctypes.byref(v), gg.ctypes.data)
+        assert rc == -1 and what in L.hf_last_error().decode(), L.hf_last_error()

@@ -103,6 +103,47 @@ def gen_data(name, n, seed):
     raise ValueError(name)
 
 
+_full_cache = {}
+
+
+def full_data(name):
+    """Events of a workload at its full size: the benchmark's 10^7-event
+    composite sample, the 10^6-event Dalitz sample (accept-reject on the
+    oracle's density), and for the time-dependent workloads 2x10^6 points
+    uniform over the plot with exponential decay times smeared by
+    sigma_t ~ U[0.02, 0.2] (shared by the x-free and sigma_t-map variants)."""
+    if name in _full_cache:
+        return _full_cache[name]
+    if name in ("c4x", "c4s"):  # the same observables as c4
+        return full_data("c4")
+    if name == "c2":
+        d = S.gen_c2()
+    elif name == "c3":
+        d = gen_data("c3", S.C3["n_events"], S.C3["seed"])
+    else:
+        om = oracle_for("c4")
+        n = S.C4["n_events"]
+        rng = np.random.default_rng(S.C4["seed"])
+        lo, hi = S.dalitz_box()
+        s12, s13 = [], []
+        got = 0
+        th = om.theta(S.C4["truth"])
+        while got < n:
+            a = lo + (hi - lo) * rng.random(1 << 22)
+            b = lo + (hi - lo) * rng.random(1 << 22)
+            keep = om.dalitz_amp2(np.zeros_like(th), a, b) > 0  # c = 0: |A|^2 = 1 inside
+            s12.append(a[keep])
+            s13.append(b[keep])
+            got += int(keep.sum())
+        s12 = np.concatenate(s12)[:n]
+        s13 = np.concatenate(s13)[:n]
+        st = rng.uniform(0.02, 0.2, n)
+        t = rng.exponential(0.41, n) + st * rng.standard_normal(n)
+        d = {"s12": s12, "s13": s13, "t": t, "sigma_t": st}
+    _full_cache[name] = d
+    return d
+
+
 POLY_SPEC = {
     "name": "poly3",
     "obs": [("x", -1.0, 3.0)],

@@ -13,8 +13,7 @@ Dalitz-plot cells reuse that sample."""
 import numpy as np
 import pytest
 
-import synthgen as S
-from helpers import gen_data, get_spec, grad_scale, nll_scale, oracle_for, perturbed_theta, stored_values
+from helpers import full_data, get_spec, grad_scale, nll_scale, oracle_for, perturbed_theta, stored_values
 
 pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-12, "fp32": 1e-6}
@@ -26,42 +25,6 @@ def P():
     assert torch.cuda.is_available()
     import paper_1311_1753_amd as P
     return P
-
-
-_cache = {}
-
-
-def full_data(name):
-    if name in _cache:
-        return _cache[name]
-    if name in ("c4x", "c4s"):  # the same observables as c4
-        return full_data("c4")
-    if name == "c2":
-        d = S.gen_c2()
-    elif name == "c3":
-        d = gen_data("c3", S.C3["n_events"], S.C3["seed"])
-    else:
-        om = oracle_for("c4")
-        n = S.C4["n_events"]
-        rng = np.random.default_rng(S.C4["seed"])
-        lo, hi = S.dalitz_box()
-        s12, s13 = [], []
-        got = 0
-        th = om.theta(S.C4["truth"])
-        while got < n:
-            a = lo + (hi - lo) * rng.random(1 << 22)
-            b = lo + (hi - lo) * rng.random(1 << 22)
-            keep = om.dalitz_amp2(np.zeros_like(th), a, b) > 0  # c = 0: |A|^2 = 1 inside
-            s12.append(a[keep])
-            s13.append(b[keep])
-            got += int(keep.sum())
-        s12 = np.concatenate(s12)[:n]
-        s13 = np.concatenate(s13)[:n]
-        st = rng.uniform(0.02, 0.2, n)
-        t = rng.exponential(0.41, n) + st * rng.standard_normal(n)
-        d = {"s12": s12, "s13": s13, "t": t, "sigma_t": st}
-    _cache[name] = d
-    return d
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])

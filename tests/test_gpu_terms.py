@@ -29,7 +29,7 @@ import numpy as np
 import pytest
 
 import synthgen as S
-from helpers import gen_data, get_spec, oracle_for, perturbed_theta, stored_order, stored_values
+from helpers import full_data, gen_data, get_spec, oracle_for, perturbed_theta, stored_order, stored_values
 
 pytestmark = pytest.mark.gpu
 
@@ -202,26 +202,35 @@ def test_terms_row_tails(P, n, prec):
     compare_terms(P, "c2", sp, om, g, data, prec, th)
 
 
-def test_terms_sampled_at_full_size(P):
-    """The 10^7-event benchmark workload: terms of every event from the
-    kernels, 20000 sampled events compared with the oracle one by one."""
-    print("\n[case] terms full-size c2 sampled", flush=True)
-    sp = get_spec("c2")
-    om = oracle_for("c2")
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c4x", "c4s"])
+def test_terms_sampled_at_full_size(P, name):
+    """The workloads at full size (10^7 composite events, 10^6 Dalitz
+    events, 2x10^6 time-dependent events): terms of every event from the
+    kernels, 20000 sampled events compared with the oracle one by one, and
+    the terms' sum against nll_grad over the whole dataset."""
+    print(f"\n[case] terms full-size {name} sampled", flush=True)
+    sp = get_spec(name)
+    om = oracle_for(name)
     g = P.Graph.from_spec(sp)
-    data = S.gen_c2()
+    data = full_data(name)
+    n = len(next(iter(data.values())))
     th = perturbed_theta(om, sp, rel=0.01, seed=3)
-    idx = np.sort(np.random.default_rng(8).choice(data["x"].size, 20_000, replace=False))
+    idx = np.sort(np.random.default_rng(8).choice(n, 20_000, replace=False))
+    free = g.free_mask()
     for prec in ("fp32", "fp64"):
         ds = P.Dataset(g, data, prec)
         lp, rows = P.nll_terms(g, ds, th)
         v, _ = P.nll_grad(g, ds, th)
         ds.free()
-        sd = {"x": stored_values(sp, data, prec)["x"][idx]}
+        sd = {k: v_[idx] for k, v_ in stored_values(sp, data, prec).items()}
         lp_ref, rows_ref = om.logpdf(th, sd, grad_rows=True)
-        el = np.abs(lp[idx] - lp_ref) / (1.0 + np.abs(lp_ref))
-        sc = np.abs(rows_ref) + np.abs(rows_ref).mean(axis=0)
-        eg = np.abs(rows[idx] - rows_ref) / sc
-        print(f"  {prec}: lnP err max {el.max():.2e}; grad err max {eg.max():.2e}", flush=True)
+        kappa = amp_condition(om, th, sd, name)
+        el = np.abs(lp[idx] - lp_ref) / ((1.0 + np.abs(lp_ref)) * kappa)
+        rr = rows_ref[:, free]
+        sc = np.abs(rr) + np.abs(rr).mean(axis=0)
+        eg = np.abs(rows[idx][:, free] - rr) / (np.maximum(sc, 1e-300) * kappa[:, None])
+        print(f"  {prec}: lnP err max {el.max():.2e}; grad err max {eg.max():.2e} (component "
+              f"{int(np.argmax(eg.max(axis=0)))})", flush=True)
         assert el.max() <= TOL_L[prec] and eg.max() <= TOL_G[prec]
         assert abs(v + lp.sum()) <= (1e-13 if prec == "fp64" else 1e-6) * np.abs(lp).sum()

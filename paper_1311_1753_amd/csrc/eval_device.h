@@ -673,6 +673,142 @@ __device__ __forceinline__ T conv_leaf(const CS& cs, const KNode& cn, double x, 
   return leaf_poly<T>(cs, cn.c0, cn.aux, true, x, d);
 }
 
+// Unnormalised shape of an EXP / GAUSS / POLY leaf (a CONV child) with its
+// constants read once into registers: ln f and d ln f / d(slot) at v (the
+// column's offset frame), the same arithmetic as leaf_exp / leaf_gauss /
+// leaf_poly with hoisted = true.
+template <typename T, int OP> struct Shape;
+template <typename T> struct Shape<T, OP_EXP> {
+  double loc;
+  T a;
+  __device__ __forceinline__ void load(const CS& cs, const KNode& n) {
+    loc = cs.d[n.c0];
+    a = cs.get<T>(n.c0 + 1);
+  }
+  __device__ __forceinline__ T eval(double v, T (&d)[4]) const {
+    const T u = (T)(v + loc);
+    d[0] = u;
+    return a * u;
+  }
+};
+template <typename T> struct Shape<T, OP_GAUSS> {
+  double loc;
+  T isg;
+  __device__ __forceinline__ void load(const CS& cs, const KNode& n) {
+    loc = cs.d[n.c0];
+    isg = cs.get<T>(n.c0 + 1);
+  }
+  __device__ __forceinline__ T eval(double v, T (&d)[4]) const {
+    const T z = (T)(v + loc) * isg;
+    d[0] = z * isg;
+    d[1] = z * z * isg;
+    return T(-0.5) * z * z;
+  }
+};
+template <typename T> struct Shape<T, OP_POLY> {  // degree <= 4
+  double loc;
+  T a[4];
+  int deg;
+  __device__ __forceinline__ void load(const CS& cs, const KNode& n) {
+    loc = cs.d[n.c0];
+    deg = n.aux;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = k < deg ? cs.get<T>(n.c0 + 1 + k) : T(0);
+  }
+  __device__ __forceinline__ T eval(double v, T (&d)[4]) const {
+    const T u = (T)(v + loc);
+    T p = T(0);
+#pragma unroll
+    for (int k = 3; k >= 0; --k)
+      if (k < deg) p = (p + a[k]) * u;
+    p += T(1);
+    const T ip = Mth<T>::rcp(p);
+    T uk = u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < deg) d[k] = uk * ip;
+      uk *= u;
+    }
+    return p > T(0) ? Mth<T>::ln(p) : T(-INFINITY);
+  }
+};
+
+// Any of the three shapes, the kind chosen at run time (a wave-uniform
+// branch per evaluation).
+template <typename T> struct ShapeAny {
+  double loc;
+  T a[4];
+  int op, deg;
+  __device__ __forceinline__ void load(const CS& cs, const KNode& n) {
+    op = n.op;
+    loc = cs.d[n.c0];
+    deg = op == OP_POLY ? n.aux : (op == OP_GAUSS ? 1 : 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = k < deg ? cs.get<T>(n.c0 + 1 + k) : T(0);
+  }
+  __device__ __forceinline__ T eval(double v, T (&d)[4]) const {
+    if (op == OP_EXP) {
+      const T u = (T)(v + loc);
+      d[0] = u;
+      return a[0] * u;
+    }
+    if (op == OP_GAUSS) {
+      const T isg = a[0];
+      const T z = (T)(v + loc) * isg;
+      d[0] = z * isg;
+      d[1] = z * z * isg;
+      return T(-0.5) * z * z;
+    }
+    const T u = (T)(v + loc);
+    T p = T(0);
+#pragma unroll
+    for (int k = 3; k >= 0; --k)
+      if (k < deg) p = (p + a[k]) * u;
+    p += T(1);
+    const T ip = Mth<T>::rcp(p);
+    T uk = u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < deg) d[k] = uk * ip;
+      uk *= u;
+    }
+    return p > T(0) ? Mth<T>::ln(p) : T(-INFINITY);
+  }
+};
+
+// The grid sum of a CONV node at x (the stored event's value): over
+// k in [k0, k1], the terms with the residual x - t_k in [d_lo, d_hi] add
+// w = exp(ln f_M(t_k) + ln f_R(x - t_k) - shift) to S and w d ln f / d(slot)
+// to the children's slot sums gm (model) and gr (resolution); undef is set
+// when the resolution's shape is not positive at a residual in use.
+template <typename T, int ROP>
+__device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const KNode& cr, double x, double lo,
+                                           double hh, double dlo, double dhi, double ref, T shift, int k0, int k1,
+                                           T& S, T (&gm)[8], T (&gr)[8], bool& undef) {
+  ShapeAny<T> M;
+  Shape<T, ROP> R;
+  M.load(cs, cm);
+  R.load(cs, cr);
+  constexpr int NM = 4;
+  constexpr int NR = ROP == OP_EXP ? 1 : (ROP == OP_GAUSS ? 2 : 4);
+  for (int k = k0; k <= k1; ++k) {
+    const double t = conv_grid_point(lo, hh, k), d = x - t;
+    if (d >= dlo && d <= dhi) {
+      T dm[4], dr[4];
+      const T lm = M.eval(t - ref, dm);
+      const T lr = R.eval(d - ref, dr);
+      undef = undef || !(lr > T(-INFINITY));
+      const T w = Mth<T>::ex((lm + lr) - shift);
+      S += w;
+#pragma unroll
+      for (int j = 0; j < NM; ++j)
+        if (j < cm.n_slot) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
+    }
+  }
+}
+
 // General trees (ADD / PROD over leaves).  Node log-values, adjoints and the
 // per-event slot derivatives live in small VGPR arrays indexed by
 // wave-uniform node / slot numbers.
@@ -781,25 +917,23 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         bool undef = false;  // the resolution's shape not positive at a residual in use
 #pragma unroll
         for (int j = 0; j < 8; ++j) gm[j] = gr[j] = T(0);
-        // (the term's work sits under the residual-range test: a wave whose
-        // events all miss grid point k skips it, which on datasets stored
-        // sorted by x leaves about the range's share of the grid)
-        for (int k = 0; k < N; ++k) {
-          const double t = conv_grid_point(lo, hh, k), d = x - t;
-          if (d >= dlo && d <= dhi) {
-            T dm[8], dr[8];
-            const T lm = conv_leaf<T>(cs, cm, t - ref, dm);
-            const T lr = conv_leaf<T>(cs, cr, d - ref, dr);
-            undef = undef || !(lr > T(-INFINITY));
-            const T w = Mth<T>::ex((lm + lr) - shift);
-            S += w;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              if (j < nm) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
-              if (j < nr) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
-            }
-          }
-        }
+        // Only the grid points whose residual can lie in [d_lo, d_hi] are
+        // visited: k in [(x - d_hi - lo)/h - 1/2, (x - d_lo - lo)/h - 1/2],
+        // widened by one point on each side so that rounding of these
+        // bounds cannot drop one; the range test (t_k and x - t_k in double,
+        // as the definition takes them) decides.  Datasets of graphs with a
+        // CONV node are stored sorted by x, so a wave's lanes run loops of
+        // nearly the same range.
+        int k0 = (int)__builtin_ceil((x - dhi - lo) / hh - 0.5) - 1;
+        int k1 = (int)__builtin_floor((x - dlo - lo) / hh - 0.5) + 1;
+        k0 = k0 < 0 ? 0 : k0;
+        k1 = k1 > N - 1 ? N - 1 : k1;
+        // the term loop is specialised on the resolution's kind; both
+        // children's constants are read once into registers
+#define HF_CONV_CASE(R_)                                                                                  \
+  if (cr.op == R_) conv_terms<T, R_>(cs, cm, cr, x, lo, hh, dlo, dhi, ref, shift, k0, k1, S, gm, gr, undef);
+        HF_CONV_CASE(OP_GAUSS) else HF_CONV_CASE(OP_EXP) else HF_CONV_CASE(OP_POLY)
+#undef HF_CONV_CASE
         const T iS = Mth<T>::rcp(S);
         v = S > T(0) && !undef ? Mth<T>::ln(S) : T(-INFINITY);
         v = (v - cs.get<T>(c0 + 6)) - cs.get<T>(c0 + 7);

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synthgen as S
-from helpers import get_spec
+from helpers import get_spec, oracle_for
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +62,10 @@ def test_alone_equals_in_the_mix(P, prec):
         ds = P.Dataset(g, cols(r), prec)
         single = P.fit(g, ds, [-2.0])
         assert abs(single["theta"][0] - m["theta"][0]) <= 1e-3 * single["errors"][0]
+        # and so does the oracle's fit of the same toy (from the same start)
+        ref = oracle_for("c1").fit(cols(r))
+        assert abs(m["theta"][0] - ref["theta"][0]) <= 1e-3 * ref["errors"][0], (m["theta"], ref["theta"])
+        assert abs(m["errors"][0] / ref["errors"][0] - 1.0) <= 2e-3
 
 
 def test_budget_admission_and_cancel(P):
@@ -99,6 +103,11 @@ def test_fit_server_closed_and_open_loop(P):
         assert res[r["id"]]["status"] == "OK"
         assert np.array_equal(res[r["id"]]["theta"], ref[r["id"]]["theta"])
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+    # served fits against the oracle's fits of the same toys
+    om = oracle_for("c1")
+    for r in reqs[::4]:
+        o = om.fit(cols(r))
+        assert abs(res[r["id"]]["theta"][0] - o["theta"][0]) <= 1e-3 * o["errors"][0]
 
 
 def test_fit_server_holds_datasets_within_budget(P):

@@ -50,7 +50,10 @@
 //          which that node is conditional).
 //   CONV   numerical convolution of a model M with a resolution R (section
 //          "Combining functions": ConvolutionPdf), both one-observable EXP /
-//          GAUSS / POLY leaves on x taken as unnormalised shapes f_M, f_R:
+//          GAUSS / POLY leaves on x taken as unnormalised shapes f_M, f_R,
+//          or ADDs of such leaves (mixtures of the leaves, each normalised
+//          over the child's domain: the box for the model, [d_lo, d_hi] for
+//          the resolution):
 //          P(x) = sum_k f_M(t_k) f_R(x - t_k) / Z over the N midpoints t_k of
 //          x's box, the residual x - t_k restricted to [d_lo, d_hi], and
 //          Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms)
@@ -407,6 +410,64 @@ double leaf_shape(const Model& m, const Node& n, const double* th, double x, dou
   }
 }
 
+// A CONV child as a function of v (section "Combining functions": the
+// children of a convolution may themselves be combinations): a leaf is its
+// unnormalised shape s(v); an ADD of leaves is the mixture
+// sum_j f_j s_j(v) / N_j of its components, each normalised over the
+// child's domain [dom_lo, dom_hi] (the observable's box for the model, the
+// residual range for the resolution), the last fraction 1 - sum of the
+// others.  Returns the value and adds d value / d theta into df (dense).
+double conv_child(const Model& m, const Node& n, const double* th, double v, double dom_lo, double dom_hi,
+                  double* df) {
+  const int np = m.n_par;
+  if (n.kind != K_ADD) {
+    std::vector<double> gl(np, 0.0);
+    const double f = leaf_shape(m, n, th, v, gl.data());
+    for (int p = 0; p < np; ++p) df[p] += f * gl[p];
+    return f;
+  }
+  const size_t K = n.child.size();
+  std::vector<double> q(K);
+  double flast = 1.0, val = 0.0;
+  for (size_t j = 0; j + 1 < K; ++j) flast -= th[n.par[j]];
+  for (size_t j = 0; j < K; ++j) {
+    const Node& c = m.nodes[n.child[j]];
+    std::vector<double> gl(np, 0.0), dN(np, 0.0);
+    const double sj = leaf_shape(m, c, th, v, gl.data());
+    const double Nj = leaf_integral(m, c, th, dom_lo, dom_hi, dN);
+    q[j] = sj / Nj;
+    const double fj = j + 1 < K ? th[n.par[j]] : flast;
+    val += fj * q[j];
+    for (int p = 0; p < np; ++p) df[p] += fj * q[j] * (gl[p] - dN[p] / Nj);
+  }
+  for (size_t j = 0; j + 1 < K; ++j) df[n.par[j]] += q[j] - q[K - 1];
+  return val;
+}
+
+// int_u^v of a CONV child (as conv_child) and its theta derivative (added
+// into dI, dense).
+double conv_child_integral(const Model& m, const Node& n, const double* th, double u, double v, double dom_lo,
+                           double dom_hi, std::vector<double>& dI) {
+  if (n.kind != K_ADD) return leaf_integral(m, n, th, u, v, dI);
+  const int np = m.n_par;
+  const size_t K = n.child.size();
+  std::vector<double> r(K);
+  double flast = 1.0, val = 0.0;
+  for (size_t j = 0; j + 1 < K; ++j) flast -= th[n.par[j]];
+  for (size_t j = 0; j < K; ++j) {
+    const Node& c = m.nodes[n.child[j]];
+    std::vector<double> dIj(np, 0.0), dN(np, 0.0);
+    const double Ij = leaf_integral(m, c, th, u, v, dIj);
+    const double Nj = leaf_integral(m, c, th, dom_lo, dom_hi, dN);
+    r[j] = Ij / Nj;
+    const double fj = j + 1 < K ? th[n.par[j]] : flast;
+    val += fj * r[j];
+    for (int p = 0; p < np; ++p) dI[p] += fj * (dIj[p] / Nj - Ij * dN[p] / (Nj * Nj));
+  }
+  for (size_t j = 0; j + 1 < K; ++j) dI[n.par[j]] += r[j] - r[K - 1];
+  return val;
+}
+
 // d ln f / dx of a leaf's unnormalised shape at x.
 double leaf_shape_dx(const Node& n, const double* th, double x) {
   switch (n.kind) {
@@ -631,24 +692,24 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
       const double lo = m.lo[n.obs[0]], hi = m.hi[n.obs[0]], h = (hi - lo) / n.grid;
       Neumaier Z;
       std::vector<Neumaier> dZ(m.n_par);
-      std::vector<double> gm(m.n_par), dI(m.n_par);
+      std::vector<double> dfm(m.n_par), dI(m.n_par);
       bool undefined = false;
       for (int k = 0; k < n.grid; ++k) {
         const double t = lo + (k + 0.5) * h;
         const double u = std::max(lo - t, n.d_lo), v = std::min(hi - t, n.d_hi);
         if (!(v > u)) continue;
-        std::fill(gm.begin(), gm.end(), 0.0);
+        std::fill(dfm.begin(), dfm.end(), 0.0);
         std::fill(dI.begin(), dI.end(), 0.0);
-        const double fm = leaf_shape(m, M, th, t, gm.data());
+        const double fm = conv_child(m, M, th, t, lo, hi, dfm.data());
         // a convolution of densities: a model shape that is not positive at
         // a grid point that enters Z leaves the density undefined
         if (!(fm > 0.0) || !std::isfinite(fm)) {
           undefined = true;
           break;
         }
-        const double I = leaf_integral(m, R, th, u, v, dI);
+        const double I = conv_child_integral(m, R, th, u, v, n.d_lo, n.d_hi, dI);
         Z.add(fm * I);
-        for (int p = 0; p < m.n_par; ++p) dZ[p].add(fm * gm[p] * I + fm * dI[p]);
+        for (int p = 0; p < m.n_par; ++p) dZ[p].add(dfm[p] * I + fm * dI[p]);
       }
       const double z = Z.value();
       r.lnN = undefined ? INFINITY : std::log(z);  // undefined: ln P = -inf at every event
@@ -733,16 +794,17 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
       const double x = ev[n.obs[0]], lo = m.lo[n.obs[0]], hi = m.hi[n.obs[0]], h = (hi - lo) / n.grid;
       Neumaier S;
       std::vector<Neumaier> dS(np);
-      std::vector<double> gk(np);
+      std::vector<double> dfm(np), dfr(np);
       for (int k = 0; k < n.grid; ++k) {
         const double t = lo + (k + 0.5) * h, d = x - t;
         if (d < n.d_lo || d > n.d_hi) continue;
-        std::fill(gk.begin(), gk.end(), 0.0);
-        const double fr = leaf_shape(m, R, th, d, gk.data());
+        std::fill(dfm.begin(), dfm.end(), 0.0);
+        std::fill(dfr.begin(), dfr.end(), 0.0);
+        const double fr = conv_child(m, R, th, d, n.d_lo, n.d_hi, dfr.data());
         if (!(fr > 0.0)) return -INFINITY;  // resolution shape not positive at a residual in use
-        const double w = leaf_shape(m, M, th, t, gk.data()) * fr;
-        S.add(w);
-        for (int p = 0; p < np; ++p) dS[p].add(w * gk[p]);
+        const double fm = conv_child(m, M, th, t, lo, hi, dfm.data());
+        S.add(fm * fr);
+        for (int p = 0; p < np; ++p) dS[p].add(dfm[p] * fr + fm * dfr[p]);
       }
       const double sv = S.value();
       if (!(sv > 0.0)) return -INFINITY;

@@ -20,7 +20,7 @@ import math
 
 __all__ = [
     "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "SHARED", "SHARED_SUM",
-    "SHARED_2D", "C4S", "CONV", "CONV_POLY", "COMP", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
+    "SHARED_2D", "C4S", "CONV", "CONV_POLY", "CONV_GMIX", "COMP", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -310,6 +310,30 @@ CONV_POLY = {
     "seed": 27,
 }
 
+# Nested composition: the exponential smeared by a resolution made of two
+# Gaussians (a core and a wider tail, each normalised over the residual
+# range), plus an exponential background -- the shape of the paper's binned
+# example, a lineshape convolved with a resolution of several Gaussians.
+CONV_GMIX = {
+    "name": "conv_exp_gaussmix_plus_exp",
+    "obs": [("x", 0.0, 10.0)],
+    "params": [("c_alpha", -0.3, 0.05, -5.0, 5.0, False), ("r_mu1", 0.0, 0.02, -1.0, 1.0, False),
+               ("r_sg1", 0.25, 0.02, 0.02, 2.0, False), ("r_mu2", 0.0, 0.02, -1.0, 1.0, False),
+               ("r_sg2", 0.7, 0.05, 0.02, 3.0, False), ("r_f", 0.6, 0.05, 0.0, 1.0, False),
+               ("c_f", 0.6, 0.05, 0.0, 1.0, False), ("b_beta", -0.05, 0.02, -5.0, 5.0, False)],
+    "truth": {"c_alpha": -0.4, "r_mu1": 0.02, "r_sg1": 0.2, "r_mu2": -0.1, "r_sg2": 0.8, "r_f": 0.7,
+              "c_f": 0.7, "b_beta": -0.1},
+    "model": {"op": "add", "par": ["c_f"], "children": [
+        {"op": "conv", "obs": "x", "grid": 400, "d_lo": -3.0, "d_hi": 3.0, "children": [
+            {"op": "exp", "obs": "x", "par": ["c_alpha"]},
+            {"op": "add", "par": ["r_f"], "children": [
+                {"op": "gauss", "obs": "x", "par": ["r_mu1", "r_sg1"]},
+                {"op": "gauss", "obs": "x", "par": ["r_mu2", "r_sg2"]}]}]},
+        {"op": "exp", "obs": "x", "par": ["b_beta"]}]},
+    "n_events": 1_000_000,
+    "seed": 34,
+}
+
 # ---------------------------------------------------------------- COMP
 # Function composition (CompositePdf): a Gaussian shell of a quadratic core,
 # P(x) ~ exp(-(g(x) - mu)^2 / (2 sigma^2)), g(x) = 1 + a1 (x - 5) + a2 (x - 5)^2.
@@ -358,4 +382,4 @@ LISTING2 = {
 def workload(name):
     return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2, "mapped": MAPPED,
             "mapped_sum": MAPPED_SUM, "shared": SHARED, "shared_sum": SHARED_SUM, "shared_2d": SHARED_2D,
-            "c4s": C4S, "conv": CONV, "conv_poly": CONV_POLY, "comp": COMP}[name]
+            "c4s": C4S, "conv": CONV, "conv_poly": CONV_POLY, "comp": COMP, "conv_gmix": CONV_GMIX}[name]

@@ -52,7 +52,8 @@ FP64_PEAK_TFLOPS = 78.6
 # (~40 flops + 1 T) and an x slot; c4s the event's sigma_t cell density and
 # its two slots (~12 flops + 0 T).  conv: per grid term in the residual
 # window (about 40 % of the 400 points) ~15 flops + 2 T; conv_poly: 10 % of
-# 256 points.
+# 256 points; conv_gmix: two Gaussian components per term (~25 flops + 2 T)
+# over about 60 % of 400 points.
 WORK = {
     "c1": {"bound": "hbm"}, "c2": {"bound": "hbm"}, "mapped": {"bound": "hbm"}, "mapped_sum": {"bound": "hbm"},
     "shared": {"bound": "hbm"}, "shared_sum": {"bound": "hbm"}, "c1l": {"bound": "hbm"}, "c2l": {"bound": "hbm"},
@@ -60,6 +61,7 @@ WORK = {
     "c3": {"bound": "alu", "flops": 330.0}, "c4": {"bound": "alu", "flops": 700.0},
     "c4x": {"bound": "alu", "flops": 740.0}, "c4s": {"bound": "alu", "flops": 712.0},
     "conv": {"bound": "alu", "flops": 160 * 15.0}, "conv_poly": {"bound": "alu", "flops": 26 * 15.0},
+    "conv_gmix": {"bound": "alu", "flops": 240 * 25.0},
 }
 
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE /
@@ -101,7 +103,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 5 times (reference for the HBM byte counters)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4x", "c4s", "mapped", "mapped_sum",
-                             "shared", "shared_sum", "conv", "conv_poly", "comp", "c1l", "c2l"],
+                             "shared", "shared_sum", "conv", "conv_poly", "conv_gmix", "comp", "c1l", "c2l"],
                     help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
                          "c3 Dalitz amplitude sum, c4 time-dependent Dalitz (c4x with x free: the "
                          "trigonometric terms; c4s times the sigma_t density that varies across "
@@ -354,7 +356,7 @@ def other_workload(args, P, S, torch, stream):
         data = S.gen_c1(n=n, seed=spec["seed"])
     elif base == "c2":
         data = S.gen_c2(n=n, seed=spec["seed"])
-    elif base in ("mapped", "mapped_sum", "shared", "shared_sum", "conv", "conv_poly", "comp"):
+    elif base in ("mapped", "mapped_sum", "shared", "shared_sum", "conv", "conv_poly", "conv_gmix", "comp"):
         # (conv_poly's density is zero below its first grid point)
         data = {"x": np.random.default_rng(spec["seed"]).uniform(0.1 if base == "conv_poly" else 0.0, 10.0, n)}
     else:

@@ -118,7 +118,9 @@ enum hf_op {
                         {model, resolution}, one-observable EXP / GAUSS / POLY (degree <= 4)
                         leaves on x taken as unnormalised shapes f (EXP e^{alpha (v - lo)},
                         GAUSS e^{-(v - mu)^2 / (2 sigma^2)}, POLY 1 + sum a_j (v - x0)^j, v
-                        the model's t or the resolution's residual);
+                        the model's t or the resolution's residual); the resolution may
+                        also be an ADD of 2 or 3 GAUSS leaves on x, a mixture whose
+                        components are each normalised over [d_lo, d_hi];
                         Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms, on the
                         host); obs = {x}; no par; consts = {N (2..4096), d_lo, d_hi}; the
                         per-event sum runs over all N points (cost ~ N per event); range

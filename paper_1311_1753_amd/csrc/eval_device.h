@@ -809,6 +809,63 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
   }
 }
 
+// The same grid sum with a resolution that is a mixture (ADD node cr) of
+// K <= 3 Gaussians, each normalised over the residual range (their staged
+// ln N and its derivatives): per term and component w_j = exp(ln f_M(t_k)
+// + ln g_j(x - t_k) - ln N_j - shift), S += sum f_j w_j; the resolution's
+// slot sums gr are ordered as its slots: each Gaussian's (mu, sigma), then
+// the K - 1 fractions (d/df_j: w_j - w_K).
+template <typename T>
+__device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P, const KNode& cm, const KNode& cr,
+                                                double x, double lo, double hh, double dlo, double dhi, double ref,
+                                                T shift, int k0, int k1, T& S, T (&gm)[8], T (&gr)[8]) {
+  ShapeAny<T> M;
+  M.load(cs, cm);
+  const int K = cr.n_child;
+  double loc[3];
+  T isg[3], lnh[3], lnl[3], dmu[3], dsg[3], f[3];
+  T last = T(1);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int c0 = cr.res_end[j < K ? j : 0];  // child j's constants
+    loc[j] = cs.d[c0];
+    isg[j] = cs.get<T>(c0 + 1);
+    lnh[j] = cs.get<T>(c0 + 2);
+    lnl[j] = cs.get<T>(c0 + 3);
+    dmu[j] = cs.get<T>(c0 + 4);
+    dsg[j] = cs.get<T>(c0 + 5);
+    f[j] = j < K ? cs.get<T>(cr.c0 + j) : T(0);  // the ADD's staged fractions, the last one included
+  }
+  (void)last;
+  for (int k = k0; k <= k1; ++k) {
+    const double t = conv_grid_point(lo, hh, k), d = x - t;
+    if (d >= dlo && d <= dhi) {
+      T dm[4];
+      const T lm = M.eval(t - ref, dm) - shift;
+      const double v = d - ref;
+      T w[3], sw = T(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (j < K) {
+          const T z = (T)(v + loc[j]) * isg[j];
+          w[j] = Mth<T>::ex(((lm - T(0.5) * z * z) - lnh[j]) - lnl[j]);
+          const T fw = f[j] * w[j];
+          sw += fw;
+          gr[2 * j] = Mth<T>::fma(fw, z * isg[j] - dmu[j], gr[2 * j]);
+          gr[2 * j + 1] = Mth<T>::fma(fw, z * z * isg[j] - dsg[j], gr[2 * j + 1]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (j + 1 < K) gr[2 * K + j] += w[j] - w[K - 1];
+      S += sw;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < cm.n_slot) gm[j] = Mth<T>::fma(sw, dm[j], gm[j]);
+    }
+  }
+}
+
 // General trees (ADD / PROD over leaves).  Node log-values, adjoints and the
 // per-event slot derivatives live in small VGPR arrays indexed by
 // wave-uniform node / slot numbers.
@@ -909,7 +966,11 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         const int chm = P.child[nd.child0], chr = P.child[nd.child0 + 1];
         const KNode& cm = P.node[chm];
         const KNode& cr = P.node[chr];
-        const int nm = cm.n_slot, nr = cr.n_slot;
+        // the resolution's slots: its own, or (a mixture of Gaussians) its
+        // Gaussians' and its fractions, contiguous and ending with its own
+        const bool mixr = cr.op == OP_ADD;
+        const int nm = cm.n_slot, nr = mixr ? 3 * cr.n_child - 1 : cr.n_slot;
+        const int r_first = cr.slot0 + cr.n_slot - nr;
         const double lo = cs.d[c0], hh = cs.d[c0 + 1], dlo = cs.d[c0 + 2], dhi = cs.d[c0 + 3], ref = cs.d[c0 + 4];
         const double x = xe[nd.col[0]] + ref;  // the stored event's value
         const T shift = cs.get<T>(c0 + 5);
@@ -932,7 +993,8 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         // children's constants are read once into registers
 #define HF_CONV_CASE(R_)                                                                                  \
   if (cr.op == R_) conv_terms<T, R_>(cs, cm, cr, x, lo, hh, dlo, dhi, ref, shift, k0, k1, S, gm, gr, undef);
-        HF_CONV_CASE(OP_GAUSS) else HF_CONV_CASE(OP_EXP) else HF_CONV_CASE(OP_POLY)
+        if (mixr) conv_terms_gmix<T>(cs, P, cm, cr, x, lo, hh, dlo, dhi, ref, shift, k0, k1, S, gm, gr);
+        else HF_CONV_CASE(OP_GAUSS) else HF_CONV_CASE(OP_EXP) else HF_CONV_CASE(OP_POLY)
 #undef HF_CONV_CASE
         const T iS = Mth<T>::rcp(S);
         v = S > T(0) && !undef ? Mth<T>::ln(S) : T(-INFINITY);
@@ -940,10 +1002,14 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           if (j < nm) dl[cm.slot0 + j] = gm[j] * iS - cs.get<T>(c0 + 8 + j);
-          if (j < nr) dl[cr.slot0 + j] = gr[j] * iS - cs.get<T>(c0 + 8 + nm + j);
+          if (j < nr) dl[r_first + j] = gr[j] * iS - cs.get<T>(c0 + 8 + nm + j);
         }
         resp[chm] = T(1);
         resp[chr] = T(1);
+        // a mixture's Gaussians carry the convolution's derivatives, scaled
+        // only by its adjoint in the reverse pass
+        if (mixr)
+          for (int j = 0; j < cr.n_child; ++j) resp[P.child[cr.child0 + j]] = T(1);
       } else if (HEAVY && op == OP_COMP) {
         // composition f(g(x)): the core's value g = 1 + sum a_j u^j
         // (u = x - x0), the shell's shape at g; the children's slots receive

@@ -280,6 +280,9 @@ int32_t rows_for(int kind, hf_precision prec, int64_t n) {
 // ------------------------------------------------------------------ staging
 namespace {
 
+int subtree_slots(const std::vector<NodeInfo>& all, int k);
+
+
 // One-observable leaf that a PROD may multiply with others on the same observable.
 bool is_leaf1(const NodeInfo& n) {
   return (n.op == OP_EXP || n.op == OP_GAUSS || n.op == OP_POLY) && n.obs.size() == 1;
@@ -570,6 +573,12 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
   for (int k = 0; k < P.n_nodes; ++k)
     if (P.node[k].op == OP_CONV || P.node[k].op == OP_COMP)
       for (int c : g->nodes[k].child) conv_child[c] = 1;
+  // the Gaussians of a CONV resolution mixture are normalised over the
+  // CONV's residual range (index of that CONV node, else -1)
+  std::vector<int> res_comp_of(P.n_nodes, -1);
+  for (int k = 0; k < P.n_nodes; ++k)
+    if (P.node[k].op == OP_CONV && g->nodes[g->nodes[k].child[1]].op == OP_ADD)
+      for (int c : g->nodes[g->nodes[k].child[1]].child) res_comp_of[c] = k;
   for (int k = 0; k < P.n_nodes; ++k) {
     const KNode& kn = P.node[k];
     const NodeInfo& nd = g->nodes[k];
@@ -614,7 +623,11 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         const double k1 = rnd(1.0 / th[nd.par[1]]);
         const double s = fp32 ? 1.0 / k1 : th[nd.par[1]];
         double lnN = 0, dmu = 0, ds = 0;
-        if (!gauss_norm(o.lo, o.hi, mu, s, lnN, dmu, ds) && !shape_only) sc.ok = false;
+        // over the box, or over the residual range for a component of a
+        // CONV resolution mixture
+        const int rk = res_comp_of[k];
+        const double nlo = rk >= 0 ? g->nodes[rk].consts[1] : o.lo, nhi = rk >= 0 ? g->nodes[rk].consts[2] : o.hi;
+        if (!(s > 0.0) || (!gauss_norm(nlo, nhi, mu, s, lnN, dmu, ds) && !shape_only)) sc.ok = false;
         P.c64[c0] = column_ref(g, col, prec) - mu;
         P.c32[c0] = 0.0f;
         setc(c0 + 1, k1);
@@ -786,18 +799,58 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         // resolution lives on the residual range)
         bool ok = true, ok_r = true;
         HostLeaf M = host_leaf(g, g->nodes[nd.child[0]], th, rnd, fp32, ok);
-        HostLeaf R = host_leaf(g, g->nodes[nd.child[1]], th, rnd, fp32, ok_r);
+        const NodeInfo& rn = g->nodes[nd.child[1]];
+        const bool mixr = rn.op == OP_ADD;  // resolution: a mixture of Gaussians
+        HostLeaf R = host_leaf(g, mixr ? g->nodes[rn.child[0]] : rn, th, rnd, fp32, ok_r);
         if (R.op == OP_GAUSS && !(R.s > 0.0)) ok = false;
         M.lnN = R.lnN = 0.0;  // shapes
         for (int j = 0; j < 8; ++j) M.dN[j] = R.dN[j] = 0.0;
-        const int nm = M.n_slot, nr = R.n_slot;
+        // mixture components (normalised over [d_lo, d_hi]) and fractions as
+        // the kernels see them (the ADD's staged constants)
+        const int KR = mixr ? (int)rn.child.size() : 0;
+        std::vector<HostLeaf> RC(KR);
+        std::vector<double> fr(KR), Nr(KR), dNr(2 * KR);
+        for (int j = 0; j < KR; ++j) {
+          bool okc = true;
+          RC[j] = host_leaf(g, g->nodes[rn.child[j]], th, rnd, fp32, okc);
+          if (!(RC[j].s > 0.0)) ok = false;
+          RC[j].lnN = 0.0;
+          RC[j].dN[0] = RC[j].dN[1] = 0.0;
+          double dn[8];
+          Nr[j] = raw_integral(RC[j], o.lo, dlo, dhi, dn);
+          dNr[2 * j] = dn[0];
+          dNr[2 * j + 1] = dn[1];
+          if (!(Nr[j] > 0.0)) { ok = false; Nr[j] = 1.0; }
+          fr[j] = P.c64[P.node[nd.child[1]].c0 + j];
+        }
+        const int nm = M.n_slot, nr = mixr ? 3 * KR - 1 : R.n_slot;
+        // the resolution's integral over [u, v] and its slot derivatives
+        // (mixture slots: each Gaussian's (mu, sigma), then the fractions)
+        auto res_integral = [&](double u, double v, double* dI) {
+          if (!mixr) return raw_integral(R, o.lo, u, v, dI);
+          double I = 0.0, rj[3];
+          for (int j = 0; j < KR; ++j) {
+            double di[8];
+            const double Ij = raw_integral(RC[j], o.lo, u, v, di);
+            rj[j] = Ij / Nr[j];
+            I += fr[j] * rj[j];
+            dI[2 * j] = fr[j] * (di[0] - rj[j] * dNr[2 * j]) / Nr[j];
+            dI[2 * j + 1] = fr[j] * (di[1] - rj[j] * dNr[2 * j + 1]) / Nr[j];
+          }
+          for (int j = 0; j + 1 < KR; ++j) dI[2 * KR + j] = rj[j] - rj[KR - 1];
+          return I;
+        };
         // exponent shift: the shapes' maxima over the grid and the residual range
         double cm = -INFINITY, cr = -INFINITY, l, d[8];
         for (int k = 0; k < N; ++k)
           if (M.eval(o.lo + (k + 0.5) * h, l, d)) cm = std::max(cm, l);
-        for (int k = 0; k <= 256; ++k)
-          if (R.eval(dlo + (dhi - dlo) * k / 256.0, l, d)) cr = std::max(cr, l);
-        if (R.op == OP_GAUSS && R.p[0] > dlo && R.p[0] < dhi) cr = std::max(cr, 0.0);
+        if (mixr) {
+          for (int j = 0; j < KR; ++j) cr = std::max(cr, -std::log(Nr[j]));  // a component's peak, 1 / N_j
+        } else {
+          for (int k = 0; k <= 256; ++k)
+            if (R.eval(dlo + (dhi - dlo) * k / 256.0, l, d)) cr = std::max(cr, l);
+          if (R.op == OP_GAUSS && R.p[0] > dlo && R.p[0] < dhi) cr = std::max(cr, 0.0);
+        }
         const double shift = std::isfinite(cm) && std::isfinite(cr) ? cm + cr : 0.0;
         double Z = 0.0;
         std::vector<double> dZ(nm + nr, 0.0);
@@ -812,7 +865,7 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
             ok = false;
             continue;
           }
-          const double I = raw_integral(R, o.lo, u, v, dI);
+          const double I = res_integral(u, v, dI);
           if (I == 0.0) continue;
           const double fm = std::exp(l);
           Z += fm * I;
@@ -830,11 +883,15 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
         setc(c0 + 4, ref);
         setc(c0 + 5, shift);
         const double lnZ = std::log(Z);
+        // the children's slots in order: the model's, then the resolution's
+        // subtree (its mixture's Gaussians, then its fractions)
+        const KNode& rk = P.node[nd.child[1]];
+        const int r_first = rk.slot0 + rk.n_slot - nr;
         for (int j = 0; j < nm + nr; ++j) {
           const double dz = dZ[j] / Z;
-          const NodeInfo& cn = g->nodes[nd.child[j < nm ? 0 : 1]];
+          const int slot = j < nm ? P.node[nd.child[0]].slot0 + j : r_first + (j - nm);
           if (hoist) {
-            sc.ht.dlnN[cn.par[j < nm ? j : j - nm]] += dz;
+            if (g->slot_par[slot] >= 0) sc.ht.dlnN[g->slot_par[slot]] += dz;
             setc(c0 + 8 + j, 0.0);
           } else {
             setc(c0 + 8 + j, dz);
@@ -987,6 +1044,14 @@ int node_slots(const NodeInfo& n) {
   }
 }
 
+// Slots of a node and everything below it (a CONV child: a leaf, or a
+// mixture of leaves).
+int subtree_slots(const std::vector<NodeInfo>& all, int k) {
+  int s = node_slots(all[k]);
+  for (int c : all[k].child) s += subtree_slots(all, c);
+  return s;
+}
+
 int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
   switch (n.op) {
     case OP_MAP: {
@@ -1002,7 +1067,7 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
       return 2 + slots;
     }
     case OP_DPMAP: return (int)n.consts[0] + (int)n.consts[1];
-    case OP_CONV: return 8 + node_slots(all[n.child[0]]) + node_slots(all[n.child[1]]);
+    case OP_CONV: return 8 + subtree_slots(all, n.child[0]) + subtree_slots(all, n.child[1]);
     case OP_COMP: return 3 + node_slots(all[n.child[0]]) + node_slots(all[n.child[1]]);
     case OP_EXP: return 5;
     case OP_GAUSS: return 6;
@@ -1157,12 +1222,25 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
             rc = need(ni.consts[0] >= 2 && ni.consts[0] <= kMaxConvGrid && ni.consts[0] == std::floor(ni.consts[0]) &&
                           std::isfinite(ni.consts[1]) && std::isfinite(ni.consts[2]) && ni.consts[1] < ni.consts[2],
                       "CONV: 2..4096 grid points and a residual range d_lo < d_hi");
-          for (int c : ni.child) {
-            if (rc) break;
-            const NodeInfo& cn = in[c];
+          for (int j = 0; j < (int)ni.child.size() && !rc; ++j) {
+            const NodeInfo& cn = in[ni.child[j]];
+            // the resolution may be a mixture of 2 or 3 Gaussians on the
+            // observable (each normalised over the residual range)
+            if (j == 1 && cn.op == OP_ADD) {
+              rc = need(cn.child.size() >= 2 && cn.child.size() <= 3,
+                        "a CONV resolution mixture takes 2 or 3 Gaussians");
+              for (int c : cn.child) {
+                if (rc) break;
+                const NodeInfo& gc = in[c];
+                rc = need(gc.op == OP_GAUSS && gc.obs.size() == 1 && gc.obs[0] == ni.obs[0],
+                          "a CONV resolution mixture takes Gaussians on the convolution's observable");
+              }
+              continue;
+            }
             rc = need((cn.op == OP_EXP || cn.op == OP_GAUSS || cn.op == OP_POLY) && cn.obs.size() == 1 &&
                           cn.obs[0] == ni.obs[0] && cn.par.size() <= 4,
-                      "CONV children must be EXP / GAUSS / POLY (degree <= 4) leaves on its observable");
+                      "CONV children must be EXP / GAUSS / POLY (degree <= 4) leaves on its observable (the "
+                      "resolution also a mixture of Gaussians)");
           }
           break;
         }
@@ -1349,6 +1427,10 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       if (n.op == OP_PROD) kn.aux = shared_groups(g->nodes, n).empty() ? 0 : 1;
       if (n.op == OP_DPMAP) kn.aux = (int32_t)n.consts[1];
       if (n.op == OP_CONV) kn.aux = (int32_t)n.consts[0];
+      // ADD: the first children's constant offsets (read with compile-time
+      // indices by the CONV resolution mixture, whose Gaussians they are)
+      if (n.op == OP_ADD)
+        for (int j = 0; j < (int)n.child.size() && j < kNumGroups; ++j) kn.res_end[j] = P.node[n.child[j]].c0;
       if (n.op == OP_DALITZ || n.op == OP_TDDP) {
         const int R = (int)n.consts[6];
         kn.aux = (int32_t)R;

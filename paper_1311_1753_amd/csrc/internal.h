@@ -47,6 +47,7 @@ struct KNode {
   // DALITZ/TDDP: the resonances are stored grouped by (pair, spin), group
   // g = 3 * pair + J (pairs 12, 13, 23 = 0, 1, 2); group g holds resonances
   // [res_end[g - 1], res_end[g]) with res_end[-1] = 0 and res_end[8] = R.
+  // ADD: res_end[j] is child j's first constant (c0).
   int32_t res_end[kNumGroups];
 };
 

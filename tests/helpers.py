@@ -80,7 +80,7 @@ def gen_data(name, n, seed):
         grid = np.linspace(0.0, 10.0, 4001)
         dens = lambda x: np.exp(m.logpdf(th, {"x": x}))
         return {"x": S.gen_accept_reject_1d(n, seed, dens, 1.2 * dens(grid).max(), 0.0, 10.0, batch=1 << 18)}
-    if name in ("conv", "conv_poly"):
+    if name in ("conv", "conv_poly", "conv_gmix"):
         m = oracle_model(name)
         th = m.theta(S.workload(name)["truth"])
         grid = np.linspace(0.0, 10.0, 4001)

@@ -37,6 +37,7 @@ CASES = [
     ("conv", 50_021, 30),
     ("conv_poly", 50_023, 31),
     ("comp", 50_027, 33),
+    ("conv_gmix", 50_029, 35),
 ]
 
 
@@ -278,19 +279,24 @@ def test_tddp_sigma_map_mixed_cells_match_oracle(P, stream, prec):
         assert np.all(np.abs(gr - g_ref)[free] <= TOL[prec] * gs[free])
 
 
+RES_PARAMS = {"conv": ("r_mu", "r_sigma"), "conv_gmix": ("r_mu1", "r_sg1", "r_mu2", "r_sg2", "r_f")}
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_fit_convolution_matches_oracle_fit(P, stream, prec):
+@pytest.mark.parametrize("name", ["conv", "conv_gmix"])
+def test_fit_convolution_matches_oracle_fit(P, stream, name, prec):
     """Fit of the smeared exponential plus background with the resolution
-    fixed (an exponential smeared by a Gaussian is the same exponential away
-    from the box's edges, so the resolution is barely constrained by these
-    data; in practice it comes from a calibration)."""
+    fixed (an exponential smeared by a Gaussian, or by a mixture of
+    Gaussians, is the same exponential away from the box's edges, so the
+    resolution is barely constrained by these data; in practice it comes
+    from a calibration)."""
     from oracle import oracle as O
-    print(f"\n[case] fit conv (fixed resolution) prec={prec}", flush=True)
-    sp = get_spec("conv")
-    sp["params"] = [p[:5] + (True,) if p[0] in ("r_mu", "r_sigma") else p for p in sp["params"]]
-    sp["params"] = [(p[0], sp["truth"][p[0]]) + tuple(p[2:]) if p[0] in ("r_mu", "r_sigma") else p
-                    for p in sp["params"]]
-    data = data_for("conv", 100_019, 32)
+    print(f"\n[case] fit {name} (fixed resolution) prec={prec}", flush=True)
+    sp = get_spec(name)
+    rp = RES_PARAMS[name]
+    sp["params"] = [p[:5] + (True,) if p[0] in rp else p for p in sp["params"]]
+    sp["params"] = [(p[0], sp["truth"][p[0]]) + tuple(p[2:]) if p[0] in rp else p for p in sp["params"]]
+    data = data_for(name, 100_019, 32)
     om = O.Model(sp)
     ref = om.fit(data)
     g = P.Graph.from_spec(sp)

@@ -37,7 +37,7 @@ TOL_L = {"fp64": 5e-14, "fp32": 4e-6}
 TOL_G = {"fp64": 5e-13, "fp32": 5e-5}
 
 NAMES = ["c1", "c2", "listing2", "poly", "c3", "c4", "c4x", "mapped", "mapped_sum", "shared", "shared_sum",
-         "shared_2d", "c4s", "conv", "conv_poly", "comp"]
+         "shared_2d", "c4s", "conv", "conv_poly", "comp", "conv_gmix"]
 AMP = {"c3", "c4", "c4x", "c4s"}
 
 
@@ -141,7 +141,7 @@ def _conv_edges(spc):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["mapped", "mapped_sum", "conv", "conv_poly", "c4s"])
+@pytest.mark.parametrize("name", ["mapped", "mapped_sum", "conv", "conv_poly", "conv_gmix", "c4s"])
 def test_terms_on_range_and_window_edges(P, name, prec):
     """Events on and next to the boundaries where a range, a cell or a
     residual-window decision changes, mixed into ordinary events."""
@@ -153,7 +153,7 @@ def test_terms_on_range_and_window_edges(P, name, prec):
     if name in ("mapped", "mapped_sum"):
         x = np.concatenate([base["x"], _map_edges()])
         data = {"x": x}
-    elif name in ("conv", "conv_poly"):
+    elif name in ("conv", "conv_poly", "conv_gmix"):
         spc = sp["model"] if sp["model"]["op"] == "conv" else sp["model"]["children"][0]
         data = {"x": np.concatenate([base["x"], _conv_edges(spc)])}
     else:

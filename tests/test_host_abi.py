@@ -34,7 +34,7 @@ def test_library_exports_every_header_symbol():
 def test_graph_creation_for_every_workload():
     import paper_1311_1753_amd as P
     for name in ("c1", "c2", "c3", "c4", "c4x", "listing2", "mapped", "mapped_sum", "shared", "shared_sum",
-                 "shared_2d", "c4s", "conv", "conv_poly", "comp"):
+                 "shared_2d", "c4s", "conv", "conv_poly", "comp", "conv_gmix"):
         g = P.Graph.from_spec(S.workload(name))
         assert g.n_par == len(S.workload(name)["params"])
 

@@ -420,19 +420,22 @@ double leaf_shape(const Model& m, const Node& n, const double* th, double x, dou
 double conv_child(const Model& m, const Node& n, const double* th, double v, double dom_lo, double dom_hi,
                   double* df) {
   const int np = m.n_par;
+  // per-call scratch (these run once per grid point and event)
+  thread_local std::vector<double> gl, dN, q;
+  gl.assign(np, 0.0);
   if (n.kind != K_ADD) {
-    std::vector<double> gl(np, 0.0);
     const double f = leaf_shape(m, n, th, v, gl.data());
     for (int p = 0; p < np; ++p) df[p] += f * gl[p];
     return f;
   }
   const size_t K = n.child.size();
-  std::vector<double> q(K);
+  q.assign(K, 0.0);
   double flast = 1.0, val = 0.0;
   for (size_t j = 0; j + 1 < K; ++j) flast -= th[n.par[j]];
   for (size_t j = 0; j < K; ++j) {
     const Node& c = m.nodes[n.child[j]];
-    std::vector<double> gl(np, 0.0), dN(np, 0.0);
+    gl.assign(np, 0.0);
+    dN.assign(np, 0.0);
     const double sj = leaf_shape(m, c, th, v, gl.data());
     const double Nj = leaf_integral(m, c, th, dom_lo, dom_hi, dN);
     q[j] = sj / Nj;
@@ -451,12 +454,14 @@ double conv_child_integral(const Model& m, const Node& n, const double* th, doub
   if (n.kind != K_ADD) return leaf_integral(m, n, th, u, v, dI);
   const int np = m.n_par;
   const size_t K = n.child.size();
-  std::vector<double> r(K);
+  thread_local std::vector<double> r, dIj, dN;
+  r.assign(K, 0.0);
   double flast = 1.0, val = 0.0;
   for (size_t j = 0; j + 1 < K; ++j) flast -= th[n.par[j]];
   for (size_t j = 0; j < K; ++j) {
     const Node& c = m.nodes[n.child[j]];
-    std::vector<double> dIj(np, 0.0), dN(np, 0.0);
+    dIj.assign(np, 0.0);
+    dN.assign(np, 0.0);
     const double Ij = leaf_integral(m, c, th, u, v, dIj);
     const double Nj = leaf_integral(m, c, th, dom_lo, dom_hi, dN);
     r[j] = Ij / Nj;

@@ -46,7 +46,7 @@ def test_composition_integrates_to_one(oracle_mod):
     sp = S.workload("comp")
     m = oracle_mod.Model(sp)
     th = m.theta(sp["truth"])
-    f = lambda v: math.exp(m.logpdf(th, {"x": np.array([v])})[0])
+    f = lambda v: math.exp(m.logpdf(th, {"x": np.array([v])}, n_threads=1)[0])
     assert abs(integrate.quad(f, 0.0, 10.0, epsabs=0, epsrel=1e-12, limit=400)[0] - 1.0) < 1e-11
 
 

@@ -65,7 +65,7 @@ def test_convolutions_integrate_to_one(oracle_mod, name):
     sp = S.workload(name)
     m = oracle_mod.Model(sp)
     th = m.theta(sp["truth"])
-    f = lambda v: math.exp(m.logpdf(th, {"x": np.array([v])})[0])
+    f = lambda v: math.exp(m.logpdf(th, {"x": np.array([v])}, n_threads=1)[0])
     # the integrand has kinks where the residual range starts or ends at a
     # grid point; quad over many pieces
     edges = np.linspace(0.0, 10.0, 81)
@@ -130,7 +130,7 @@ def test_mixture_resolution_workload_integrates_to_one_and_matches_fd(oracle_mod
     sp = S.workload("conv_gmix")
     m = oracle_mod.Model(sp)
     th = m.theta(sp["truth"])
-    f = lambda v: math.exp(m.logpdf(th, {"x": np.array([v])})[0])
+    f = lambda v: math.exp(m.logpdf(th, {"x": np.array([v])}, n_threads=1)[0])
     edges = np.linspace(0.0, 10.0, 81)
     tot = sum(integrate.quad(f, a, b, epsabs=0, epsrel=1e-11, limit=200)[0] for a, b in zip(edges[:-1], edges[1:]))
     assert abs(tot - 1.0) < 1e-8

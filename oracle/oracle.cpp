@@ -38,7 +38,12 @@
 //          the mixing parameter x the trigonometric terms enter too:
 //          P = [a_c C(t) + a_0 Cz(t) + a_s S(t) + b_s Sz(t)] / N_T, Cz / Sz the
 //          resolution-convolved e^{-t/tau} cos(x t/tau) / sin(x t/tau),
-//          b_s = -Im(conj(A) Abar)
+//          b_s = -Im(conj(A) Abar); the full model of the mixing fit adds
+//          complex q/p (Abar -> (q/p) Abar, the amplitude mixed in from the
+//          conjugate state) and resonance masses and widths as parameters,
+//          whose normalisation is then the grid sum of the time-integrated
+//          rate taken at the current parameters ("Results": the ~40-parameter
+//          time-dependent fit with 16 complex amplitudes)
 //   DPMAP  P(u | s12, s13) = P_c(u): the Dalitz box cut into an n12 x n13
 //          grid of rectangles (inner boundaries b12, b13; a boundary belongs
 //          to the cell above it), cell c = i12 n13 + i13 taking its own
@@ -186,7 +191,9 @@ double psi(double z) {
 }
 
 // ---------------------------------------------------------------- Dalitz kinematics
-struct Res { int ch; double m0, g0; int J; int p_re, p_im; };
+// p_m0 / p_g0: the parameters holding the mass and width when they float
+// (-1: fixed at m0 / g0)
+struct Res { int ch; double m0, g0; int J; int p_re, p_im; int p_m0 = -1, p_g0 = -1; };
 
 struct DalitzDef {
   double M, m1, m2, m3, r;
@@ -222,9 +229,17 @@ bool inside(const DalitzDef& d, double s12, double s13) {
   return inside_pair(d, s12, s13, d.m2, d.m3) && inside_pair(d, s13, s12, d.m3, d.m2);
 }
 
-// Amplitude of one resonance: B_J(q) * Z_J * BW(s_AB).  `parts`, when given,
-// receives {Gamma(s), B_J(q), Z_J, Re BW, Im BW}.
-cplx res_amp(const DalitzDef& d, const Res& R, double s12, double s13, double* parts = nullptr) {
+// Amplitude of one resonance, B_J(q) * Z_J * BW(s_AB), at mass m0 and
+// width g0.  `parts`, when given, receives {Gamma(s), B_J(q), Z_J, Re BW,
+// Im BW}; d_m0 / d_g0, when given, the derivatives of the amplitude in m0
+// and g0 (the floating-shape parameters of the full time-dependent fit,
+// section "Results"), written out from the same formulas:
+//   m0 Gamma(s) = W = g0 m0^2 q^{2J+1} P_J(z0) / (q0^{2J+1} sqrt(s) P_J(z)),
+//   BW = 1 / D, D = m0^2 - s - i W, B_J = sqrt(P_J(z0) / P_J(z)),
+// with z = r^2 q^2, z0 = r^2 q0^2, P_0 = 1, P_1 = 1 + z, P_2 = z^2 + 3z + 9
+// and q0^2 = lambda(m0^2, mA^2, mB^2) / (4 m0^2).
+cplx res_amp_mg(const DalitzDef& d, const Res& R, double m0, double g0, double s12, double s13, cplx* d_m0,
+                cplx* d_g0, double* parts = nullptr) {
   const double M2 = d.M * d.M;
   double s23 = M2 + d.m1 * d.m1 + d.m2 * d.m2 + d.m3 * d.m3 - s12 - s13;
   double sAB, sAC, sBC, mA, mB, mC;
@@ -232,15 +247,17 @@ cplx res_amp(const DalitzDef& d, const Res& R, double s12, double s13, double* p
   else if (R.ch == 12) { sAB = s12; sAC = s13; sBC = s23; mA = d.m1; mB = d.m2; mC = d.m3; }
   else { sAB = s13; sAC = s12; sBC = s23; mA = d.m1; mB = d.m3; mC = d.m2; }
   double mA2 = mA * mA, mB2 = mB * mB, mC2 = mC * mC;
-  double m02 = R.m0 * R.m0;
+  double m02 = m0 * m0;
+  double lam0 = kallen(m02, mA2, mB2);
   double q = std::sqrt(std::fmax(kallen(sAB, mA2, mB2), 0.0) / (4.0 * sAB));
-  double q0 = std::sqrt(std::fmax(kallen(m02, mA2, mB2), 0.0) / (4.0 * m02));
+  double q0 = std::sqrt(std::fmax(lam0, 0.0) / (4.0 * m02));
   double z = (q * d.r) * (q * d.r), z0 = (q0 * d.r) * (q0 * d.r);
-  double B2 = 1.0;
-  if (R.J == 1) B2 = (1.0 + z0) / (1.0 + z);
-  else if (R.J == 2) B2 = (z0 * z0 + 3.0 * z0 + 9.0) / (z * z + 3.0 * z + 9.0);
-  double width = R.g0 * std::pow(q / q0, 2 * R.J + 1) * (R.m0 / std::sqrt(sAB)) * B2;
-  cplx bw = 1.0 / cplx(m02 - sAB, -R.m0 * width);
+  double PJ = 1.0, PJ0 = 1.0, dPJ0 = 0.0;  // P_J(z), P_J(z0), P_J'(z0)
+  if (R.J == 1) { PJ = 1.0 + z; PJ0 = 1.0 + z0; dPJ0 = 1.0; }
+  else if (R.J == 2) { PJ = z * z + 3.0 * z + 9.0; PJ0 = z0 * z0 + 3.0 * z0 + 9.0; dPJ0 = 2.0 * z0 + 3.0; }
+  double B2 = PJ0 / PJ;
+  double width = g0 * std::pow(q / q0, 2 * R.J + 1) * (m0 / std::sqrt(sAB)) * B2;
+  cplx bw = 1.0 / cplx(m02 - sAB, -m0 * width);
   double Z = 1.0;
   if (R.J >= 1) {
     double z1 = sAC - sBC + (M2 - mC2) * (mB2 - mA2) / sAB;
@@ -252,13 +269,56 @@ cplx res_amp(const DalitzDef& d, const Res& R, double s12, double s13, double* p
     }
   }
   if (parts) { parts[0] = width; parts[1] = std::sqrt(B2); parts[2] = Z; parts[3] = bw.real(); parts[4] = bw.imag(); }
-  return std::sqrt(B2) * Z * bw;
+  const cplx A = std::sqrt(B2) * Z * bw;
+  if (d_m0 || d_g0) {
+    const double W = m0 * width;
+    const cplx bw2 = bw * bw;  // dBW = -BW^2 dD
+    // W is proportional to g0: dD/dg0 = -i W / g0
+    if (d_g0) *d_g0 = std::sqrt(B2) * Z * (-bw2) * cplx(0.0, -W / g0);
+    if (d_m0) {
+      // m0 enters through m0^2 in D and W, q0 in W and z0 in W and B_J
+      const double dq02 = ((2.0 * m02 - 2.0 * mA2 - 2.0 * mB2) / (4.0 * m02) - lam0 / (4.0 * m02 * m02)) * 2.0 * m0;
+      const double dlnP0 = dPJ0 / PJ0 * d.r * d.r * dq02;
+      const double dlnW = 2.0 / m0 - 0.5 * (2 * R.J + 1) * dq02 / (q0 * q0) + dlnP0;
+      const cplx dD(2.0 * m0, -W * dlnW);
+      *d_m0 = A * (0.5 * dlnP0) + std::sqrt(B2) * Z * (-bw2) * dD;
+    }
+  }
+  return A;
+}
+
+cplx res_amp(const DalitzDef& d, const Res& R, double s12, double s13, double* parts = nullptr) {
+  return res_amp_mg(d, R, R.m0, R.g0, s12, s13, nullptr, nullptr, parts);
 }
 
 // amps[0] = 1 (constant term), amps[k] = A_k.
 void amplitudes(const DalitzDef& d, double s12, double s13, cplx* amps) {
   amps[0] = cplx(1.0, 0.0);
   for (size_t k = 0; k < d.res.size(); ++k) amps[k + 1] = res_amp(d, d.res[k], s12, s13);
+}
+
+// The same at theta (floating masses and widths taken from it); dm / dg
+// (nullable) receive dA_k/dm0_k and dA_k/dg0_k at [k] (0 for the constant
+// term and for fixed shapes).
+void amplitudes_th(const DalitzDef& d, const double* th, double s12, double s13, cplx* amps, cplx* dm, cplx* dg) {
+  amps[0] = cplx(1.0, 0.0);
+  if (dm) dm[0] = 0.0;
+  if (dg) dg[0] = 0.0;
+  for (size_t k = 0; k < d.res.size(); ++k) {
+    const Res& R = d.res[k];
+    const bool fl = R.p_m0 >= 0;
+    const double m0 = fl ? th[R.p_m0] : R.m0, g0 = fl ? th[R.p_g0] : R.g0;
+    cplx a_m = 0.0, a_g = 0.0;
+    amps[k + 1] = res_amp_mg(d, R, m0, g0, s12, s13, fl && dm ? &a_m : nullptr, fl && dg ? &a_g : nullptr);
+    if (dm) dm[k + 1] = a_m;
+    if (dg) dg[k + 1] = a_g;
+  }
+}
+
+bool floating_shapes(const DalitzDef& d) {
+  for (const Res& R : d.res)
+    if (R.p_m0 >= 0) return true;
+  return false;
 }
 
 void build_grid(DalitzDef& d) {
@@ -311,10 +371,12 @@ struct Node {
   DalitzDef* dz = nullptr;  // DALITZ, TDDP
   int p_tau = -1, p_y = -1; // TDDP
   int p_x = -1;             // TDDP with the trigonometric terms (x free)
+  int p_qm = -1, p_qa = -1; // TDDP with complex q/p = |q/p| e^{i phi}: |q/p|, phi
 };
 
 struct Model {
   int n_obs = 0, n_par = 0, root = -1;
+  bool direct_norm = false;  // TDDP: the grid sum at theta even with fixed shapes (tests)
   std::vector<double> lo, hi;
   std::vector<Node> nodes;
   ~Model() { for (auto& n : nodes) delete n.dz; }
@@ -506,6 +568,51 @@ double comp_value(const Model& m, const Node& n, const double* th, double x, dou
 double node_eval(const Model& m, int id, const double* ev, const double* th, const std::vector<NodeNorm>& nn,
                  double* g);
 
+// threads of the grid sums inside a normalisation (the calling entry
+// point's thread count)
+int g_norm_threads = 1;
+int oracle_threads() { return g_norm_threads; }
+
+// q/p of a TDDP node (1 when it is not a parameter)
+cplx tddp_qp(const Node& n, const double* th) {
+  return n.p_qm >= 0 ? th[n.p_qm] * cplx(std::cos(th[n.p_qa]), std::sin(th[n.p_qa])) : cplx(1.0, 0.0);
+}
+
+// Derivatives of the time-dependent rate
+//   r = (|A|^2 + |Ab|^2)/2 C + (|A|^2 - |Ab|^2)/2 Cz - Re(conj(A) Ab) S - Im(conj(A) Ab) Sz
+// (Ab = (q/p) B0, B0 = sum_k c_k Abar_k) along the coefficient, q/p and
+// floating-shape parameters, added into out[p].  For a parameter moving A
+// by dA and Ab by dAb, dr = Re(conj(A) dA + conj(Ab) dAb) C
+// + Re(conj(A) dA - conj(Ab) dAb) Cz - Re(X') S - Im(X') Sz with
+// X' = conj(dA) Ab + conj(A) dAb.  (C, Cz, S, Sz) are the convolved time
+// factors of an event or their integrals over t for the normalisation.
+void tddp_tangents(const Node& n, const DalitzDef& d, const double* th, const std::vector<cplx>& c, cplx qp,
+                   cplx eph, cplx B0, const std::vector<cplx>& a, const std::vector<cplx>& ab,
+                   const std::vector<cplx>& dam, const std::vector<cplx>& dag, const std::vector<cplx>& dbm,
+                   const std::vector<cplx>& dbg, cplx A, cplx Ab, double C, double Cz, double S, double Sz,
+                   double* out) {
+  (void)th;
+  const auto dr = [&](cplx dA, cplx dAb) {
+    const double dnA = 2.0 * (std::conj(A) * dA).real(), dnB = 2.0 * (std::conj(Ab) * dAb).real();
+    const cplx dX = std::conj(dA) * Ab + std::conj(A) * dAb;
+    return 0.5 * (dnA + dnB) * C + 0.5 * (dnA - dnB) * Cz - dX.real() * S - dX.imag() * Sz;
+  };
+  const cplx I(0.0, 1.0);
+  for (size_t k = 0; k < d.res.size(); ++k) {
+    const Res& R = d.res[k];
+    out[R.p_re] += dr(a[k + 1], qp * ab[k + 1]);
+    out[R.p_im] += dr(I * a[k + 1], I * qp * ab[k + 1]);
+    if (R.p_m0 >= 0) {
+      out[R.p_m0] += dr(c[k + 1] * dam[k + 1], qp * c[k + 1] * dbm[k + 1]);
+      out[R.p_g0] += dr(c[k + 1] * dag[k + 1], qp * c[k + 1] * dbg[k + 1]);
+    }
+  }
+  if (n.p_qm >= 0) {
+    out[n.p_qm] += dr(0.0, eph * B0);  // d(q/p)/d|q/p| = e^{i phi}
+    out[n.p_qa] += dr(0.0, I * Ab);    // d(q/p)/dphi = i q/p
+  }
+}
+
 void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& out) {
   const Node& n = m.nodes[id];
   NodeNorm& r = out[id];
@@ -563,31 +670,98 @@ void node_norm(const Model& m, int id, const double* th, std::vector<NodeNorm>& 
     }
     case K_TDDP: {
       // N_T = int dDP int_R dt rate: the time integrals of E(t; G) over R
-      // are 1/G, so int C = tau/(1-y^2), int S = y tau/(1-y^2), int E = tau.
+      // are 1/G, so int C = tau/(1-y^2), int S = y tau/(1-y^2), and with x
+      // int Cz = tau/(1+x^2), int Sz = x tau/(1+x^2) (x = 0: int E = tau).
+      // The conjugate amplitude carries q/p: Abar' = (q/p) Abar.
       const DalitzDef& d = *n.dz;
       std::vector<cplx> c;
       coeffs(d, th, c);
       int na = d.n_amp();
-      // With x: int Cz = tau/(1+x^2), int Sz = x tau/(1+x^2).
       double tau = th[n.p_tau], y = th[n.p_y], x = n.p_x >= 0 ? th[n.p_x] : 0.0;
-      cplx QJ = quad_form(d.Jx, c, na);
-      double IAA = quad_form(d.I, c, na).real(), IBB = quad_form(d.Ib, c, na).real();
-      double RJ = QJ.real(), IJ = QJ.imag();
+      const cplx qp = tddp_qp(n, th), eph = n.p_qm >= 0 ? cplx(std::cos(th[n.p_qa]), std::sin(th[n.p_qa])) : cplx(1.0, 0.0);
+      const double aq = std::abs(qp);
+      const int np = m.n_par;
       double kc = tau / (1.0 - y * y), ks = y * tau / (1.0 - y * y);
       double opx = 1.0 + x * x, kz = tau / opx, kzs = x * tau / opx;
-      double N = 0.5 * (IAA + IBB) * kc + 0.5 * (IAA - IBB) * kz - RJ * ks - IJ * kzs;
-      r.lnN = std::log(N);
-      for (size_t k = 0; k < d.res.size(); ++k) {
-        cplx a1, a2, b1, b2, j1, j2;
-        quad_form_grad(d.I, c, na, (int)k + 1, a1, a2);
-        quad_form_grad(d.Ib, c, na, (int)k + 1, b1, b2);
-        quad_form_grad(d.Jx, c, na, (int)k + 1, j1, j2);
-        double dre = 0.5 * (a1.real() + b1.real()) * kc + 0.5 * (a1.real() - b1.real()) * kz - j1.real() * ks -
-                     j1.imag() * kzs;
-        double dim = 0.5 * (a2.real() + b2.real()) * kc + 0.5 * (a2.real() - b2.real()) * kz - j2.real() * ks -
-                     j2.imag() * kzs;
-        r.dlnN[d.res[k].p_re] += dre / N;
-        r.dlnN[d.res[k].p_im] += dim / N;
+      double IAA, IBB, RJ, IJ, N;
+      if (!floating_shapes(d) && !m.direct_norm) {
+        // grid matrices of the fixed shapes
+        cplx QJ0 = quad_form(d.Jx, c, na), QJ = qp * QJ0;
+        double IBB0 = quad_form(d.Ib, c, na).real();
+        IAA = quad_form(d.I, c, na).real();
+        IBB = aq * aq * IBB0;
+        RJ = QJ.real();
+        IJ = QJ.imag();
+        N = 0.5 * (IAA + IBB) * kc + 0.5 * (IAA - IBB) * kz - RJ * ks - IJ * kzs;
+        r.lnN = std::log(N);
+        for (size_t k = 0; k < d.res.size(); ++k) {
+          cplx a1, a2, b1, b2, j1, j2;
+          quad_form_grad(d.I, c, na, (int)k + 1, a1, a2);
+          quad_form_grad(d.Ib, c, na, (int)k + 1, b1, b2);
+          quad_form_grad(d.Jx, c, na, (int)k + 1, j1, j2);
+          b1 *= aq * aq; b2 *= aq * aq;
+          j1 *= qp; j2 *= qp;
+          double dre = 0.5 * (a1.real() + b1.real()) * kc + 0.5 * (a1.real() - b1.real()) * kz - j1.real() * ks -
+                       j1.imag() * kzs;
+          double dim = 0.5 * (a2.real() + b2.real()) * kc + 0.5 * (a2.real() - b2.real()) * kz - j2.real() * ks -
+                       j2.imag() * kzs;
+          r.dlnN[d.res[k].p_re] += dre / N;
+          r.dlnN[d.res[k].p_im] += dim / N;
+        }
+        if (n.p_qm >= 0) {
+          // dIBB/d|q/p| = 2 |q/p| IBB0, dQJ/d|q/p| = e^{i phi} QJ0, dQJ/dphi = i QJ
+          const cplx dq = eph * QJ0;
+          r.dlnN[n.p_qm] += (0.5 * 2.0 * aq * IBB0 * (kc - kz) - dq.real() * ks - dq.imag() * kzs) / N;
+          r.dlnN[n.p_qa] += (IJ * ks - RJ * kzs) / N;
+        }
+      } else {
+        // the grid sum at theta, cell by cell: the time-integrated rate and
+        // its derivatives (the same rule as the matrices: cell centres
+        // inside the plot, times the cell area)
+        const double lo12 = (d.m1 + d.m2) * (d.m1 + d.m2), hi12 = (d.M - d.m3) * (d.M - d.m3);
+        const double lo13 = (d.m1 + d.m3) * (d.m1 + d.m3), hi13 = (d.M - d.m2) * (d.M - d.m2);
+        const double h12 = (hi12 - lo12) / d.grid, h13 = (hi13 - lo13) / d.grid, area = h12 * h13;
+        const int G = d.grid;
+        // per grid row: sums of |A|^2, |Abar'|^2, Re and Im conj(A) Abar', then
+        // d(rate)/d theta_p for the coefficient, q/p and shape parameters
+        const int nw = 4 + np;
+        std::vector<double> rows((size_t)G * nw, 0.0);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(oracle_threads())
+#endif
+        for (int i = 0; i < G; ++i) {
+          std::vector<cplx> a(na), ab(na), dam(na), dag(na), dbm(na), dbg(na);
+          std::vector<Neumaier> acc(nw);
+          std::vector<double> gp(np);
+          const double s12 = lo12 + (i + 0.5) * h12;
+          for (int j = 0; j < G; ++j) {
+            const double s13 = lo13 + (j + 0.5) * h13;
+            if (!inside(d, s12, s13)) continue;
+            amplitudes_th(d, th, s12, s13, a.data(), dam.data(), dag.data());
+            amplitudes_th(d, th, s13, s12, ab.data(), dbm.data(), dbg.data());
+            cplx A = 0.0, B0 = 0.0;
+            for (int k = 0; k < na; ++k) { A += c[k] * a[k]; B0 += c[k] * ab[k]; }
+            const cplx Ab = qp * B0, X = std::conj(A) * Ab;
+            acc[0].add(std::norm(A));
+            acc[1].add(std::norm(Ab));
+            acc[2].add(X.real());
+            acc[3].add(X.imag());
+            std::fill(gp.begin(), gp.end(), 0.0);
+            tddp_tangents(n, d, th, c, qp, eph, B0, a, ab, dam, dag, dbm, dbg, A, Ab, kc, kz, ks, kzs, gp.data());
+            for (int p = 0; p < np; ++p) acc[4 + p].add(gp[p]);
+          }
+          for (int w = 0; w < nw; ++w) rows[(size_t)i * nw + w] = acc[w].value();
+        }
+        std::vector<Neumaier> tot(nw);
+        for (int i = 0; i < G; ++i)
+          for (int w = 0; w < nw; ++w) tot[w].add(rows[(size_t)i * nw + w]);
+        IAA = tot[0].value() * area;
+        IBB = tot[1].value() * area;
+        RJ = tot[2].value() * area;
+        IJ = tot[3].value() * area;
+        N = 0.5 * (IAA + IBB) * kc + 0.5 * (IAA - IBB) * kz - RJ * ks - IJ * kzs;
+        r.lnN = std::log(N);
+        for (int p = 0; p < np; ++p) r.dlnN[p] += tot[4 + p].value() * area / N;
       }
       double omy = 1.0 - y * y;
       double dN_dtau = 0.5 * (IAA + IBB) / omy + 0.5 * (IAA - IBB) / opx - RJ * y / omy - IJ * x / opx;
@@ -861,12 +1035,14 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
       double s12 = ev[n.obs[0]], s13 = ev[n.obs[1]], t = ev[n.obs[2]], st = ev[n.obs[3]];
       if (!inside(d, s12, s13) || !(st > 0.0)) return -INFINITY;
       const int na = d.n_amp();
-      std::vector<cplx> a(na), ab(na), c;
-      amplitudes(d, s12, s13, a.data());
-      amplitudes(d, s13, s12, ab.data());  // CP-conjugate amplitude: 2 <-> 3 swap
+      std::vector<cplx> a(na), ab(na), dam(na), dag(na), dbm(na), dbg(na), c;
+      amplitudes_th(d, th, s12, s13, a.data(), dam.data(), dag.data());
+      amplitudes_th(d, th, s13, s12, ab.data(), dbm.data(), dbg.data());  // CP conjugate: 2 <-> 3 swap
       coeffs(d, th, c);
-      cplx A = 0.0, Ab = 0.0;
-      for (int k = 0; k < na; ++k) { A += c[k] * a[k]; Ab += c[k] * ab[k]; }
+      const cplx qp = tddp_qp(n, th), eph = n.p_qm >= 0 ? cplx(std::cos(th[n.p_qa]), std::sin(th[n.p_qa])) : cplx(1.0, 0.0);
+      cplx A = 0.0, B0 = 0.0;
+      for (int k = 0; k < na; ++k) { A += c[k] * a[k]; B0 += c[k] * ab[k]; }
+      const cplx Ab = qp * B0;  // the conjugate amplitude with q/p
       double tau = th[n.p_tau], y = th[n.p_y];
       double Gm = (1.0 - y) / tau, Gp = (1.0 + y) / tau, G = 1.0 / tau;
       double Em = econv(t, Gm, st), Ep = econv(t, Gp, st);
@@ -889,16 +1065,11 @@ double node_eval(const Model& m, int id, const double* ev, const double* th,
       double R = ac * Ct + a0 * Cz + as * St + bs * Sz;
       if (!(R > 0.0)) return -INFINITY;
       lp = std::log(R) - nn[id].lnN;
-      for (size_t k = 0; k < d.res.size(); ++k) {
-        for (int part = 0; part < 2; ++part) {
-          cplx u = part == 0 ? cplx(1.0, 0.0) : cplx(0.0, 1.0);  // dc_k/dx
-          cplx dA = u * a[k + 1], dAb = u * ab[k + 1];
-          double dnA = 2.0 * (std::conj(A) * dA).real(), dnB = 2.0 * (std::conj(Ab) * dAb).real();
-          cplx dX = std::conj(dA) * Ab + std::conj(A) * dAb;
-          double dR = 0.5 * (dnA + dnB) * Ct + 0.5 * (dnA - dnB) * Cz - dX.real() * St - dX.imag() * Sz;
-          g[part == 0 ? d.res[k].p_re : d.res[k].p_im] += dR / R;
-        }
-      }
+      // coefficients, q/p and floating shapes: the rate's derivative along
+      // (dA, dAbar'), divided by the rate
+      std::vector<double> gr(np, 0.0);
+      tddp_tangents(n, d, th, c, qp, eph, B0, a, ab, dam, dag, dbm, dbg, A, Ab, Ct, Cz, St, Sz, gr.data());
+      for (int p = 0; p < np; ++p) g[p] += gr[p] / R;
       double dEm = econv_dG(t, Gm, st), dEp = econv_dG(t, Gp, st);
       // chain rule through Gm = (1-y)/tau, Gp = (1+y)/tau, G = 1/tau and the
       // oscillation frequency w = x/tau
@@ -1005,10 +1176,39 @@ int om_tddp(Model* m, int o12, int o13, int ot, int osig, const double* kin, int
   n.p_tau = p_tau; n.p_y = p_y; n.p_x = p_x;
   return push(m, n);
 }
+// The full time-dependent model: as om_tddp, plus complex q/p = |q/p| e^{i phi}
+// (p_qm, p_qa; -1: q/p = 1) and floating masses and widths (p_m0[k], p_g0[k]
+// >= 0: resonance k's m0 and Gamma0 are those parameters; m0[k], g0[k] are
+// then unused).  With floating shapes the normalisation is the grid sum
+// taken at every theta (no matrices).
+int om_tddp_full(Model* m, int o12, int o13, int ot, int osig, const double* kin, int grid, int n_res,
+                 const int* ch, const double* m0, const double* g0, const int* J, const int* p_re,
+                 const int* p_im, const int* p_m0, const int* p_g0, int p_tau, int p_y, int p_x, int p_qm,
+                 int p_qa) {
+  Node n; n.kind = K_TDDP; n.obs = {o12, o13, ot, osig};
+  DalitzDef* d = new DalitzDef;
+  d->M = kin[0]; d->m1 = kin[1]; d->m2 = kin[2]; d->m3 = kin[3]; d->r = kin[4];
+  d->grid = grid;
+  bool fl = false;
+  for (int k = 0; k < n_res; ++k) {
+    Res R{ch[k], m0[k], g0[k], J[k], p_re[k], p_im[k]};
+    R.p_m0 = p_m0[k];
+    R.p_g0 = p_g0[k];
+    fl = fl || R.p_m0 >= 0;
+    d->res.push_back(R);
+  }
+  if (!fl) build_grid(*d);
+  n.dz = d;
+  n.p_tau = p_tau; n.p_y = p_y; n.p_x = p_x; n.p_qm = p_qm; n.p_qa = p_qa;
+  return push(m, n);
+}
+// Tests: 1 makes every TDDP normalisation the grid sum at theta.
+void om_set_direct_norm(Model* m, int on) { m->direct_norm = on != 0; }
 
 // NLL = -sum ln P_root; grad (nullable) = dNLL/dtheta.  cols[o][i] is
 // observable o of event i.  Thread partials are combined in thread order.
 double om_nll(Model* m, const double* th, int64_t n, const double* const* cols, double* grad, int n_threads) {
+  g_norm_threads = n_threads > 0 ? n_threads : 1;
   std::vector<NodeNorm> nn(m->nodes.size());
   node_norm(*m, m->root, th, nn);
   const int np = m->n_par;
@@ -1058,6 +1258,7 @@ double om_nll(Model* m, const double* th, int64_t n, const double* const* cols, 
 // d metric / d theta.  Thread partials are combined in thread order.
 double om_binned(Model* m, const double* th, int64_t n, const double* const* cols, const double* w, int metric,
                  double K, double* grad, int n_threads) {
+  g_norm_threads = n_threads > 0 ? n_threads : 1;
   std::vector<NodeNorm> nn(m->nodes.size());
   node_norm(*m, m->root, th, nn);
   const int np = m->n_par;
@@ -1115,6 +1316,7 @@ double om_binned(Model* m, const double* th, int64_t n, const double* const* col
 // Per-event ln P_root (and optional per-event gradient rows, n x n_par).
 void om_logpdf(Model* m, const double* th, int64_t n, const double* const* cols, double* out, double* grad_rows,
                int n_threads) {
+  g_norm_threads = n_threads > 0 ? n_threads : 1;
   std::vector<NodeNorm> nn(m->nodes.size());
   node_norm(*m, m->root, th, nn);
   const int np = m->n_par;
@@ -1231,7 +1433,8 @@ void om_dalitz_amp(Model* m, int id, const double* th, int64_t n, const double* 
   }
 }
 
-// Unsmeared (sigma_t -> 0) decay rate of a TDDP node at (s12, s13, t >= 0):
+// Unsmeared (sigma_t -> 0) decay rate of a TDDP node at (s12, s13, t >= 0)
+// (Abar carrying q/p, floating shapes at theta):
 // e^{-t/tau}[a_c cosh(y t/tau) + a_0 cos(x t/tau) + a_s sinh(y t/tau)
 // + b_s sin(x t/tau)] with the same a_c, a_0, a_s, b_s.
 void om_tddp_rate(Model* m, int id, const double* th, int64_t n, const double* s12, const double* s13,
@@ -1246,15 +1449,17 @@ void om_tddp_rate(Model* m, int id, const double* th, int64_t n, const double* s
   {
     std::vector<cplx> a(d.n_amp()), ab(d.n_amp()), c;
     coeffs(d, th, c);
+    const cplx qp = tddp_qp(nd, th);
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
     for (int64_t i = 0; i < n; ++i) {
       if (!inside(d, s12[i], s13[i]) || t[i] < 0.0) { out[i] = 0.0; continue; }
-      amplitudes(d, s12[i], s13[i], a.data());
-      amplitudes(d, s13[i], s12[i], ab.data());
+      amplitudes_th(d, th, s12[i], s13[i], a.data(), nullptr, nullptr);
+      amplitudes_th(d, th, s13[i], s12[i], ab.data(), nullptr, nullptr);
       cplx A = 0.0, Ab = 0.0;
       for (int k = 0; k < d.n_amp(); ++k) { A += c[k] * a[k]; Ab += c[k] * ab[k]; }
+      Ab *= qp;
       double Em = std::exp(-(1.0 - y) * t[i] / tau), Ep = std::exp(-(1.0 + y) * t[i] / tau);
       double E0 = std::exp(-t[i] / tau);
       double ac = 0.5 * (std::norm(A) + std::norm(Ab)), a0 = 0.5 * (std::norm(A) - std::norm(Ab));
@@ -1269,6 +1474,17 @@ void om_tddp_rate(Model* m, int id, const double* th, int64_t n, const double* s
 int om_inside(const double* kin, double s12, double s13) {
   DalitzDef d; d.M = kin[0]; d.m1 = kin[1]; d.m2 = kin[2]; d.m3 = kin[3]; d.r = kin[4]; d.grid = 0;
   return inside(d, s12, s13) ? 1 : 0;
+}
+// One resonance amplitude and its derivatives in m0 and g0:
+// out = {Re A, Im A, Re dA/dm0, Im dA/dm0, Re dA/dg0, Im dA/dg0}.
+void om_res_amp_d(const double* kin, int ch, double m0, double g0, int J, double s12, double s13, double* out) {
+  DalitzDef d; d.M = kin[0]; d.m1 = kin[1]; d.m2 = kin[2]; d.m3 = kin[3]; d.r = kin[4]; d.grid = 0;
+  Res R{ch, m0, g0, J, 0, 0};
+  cplx dm, dg;
+  cplx a = res_amp_mg(d, R, m0, g0, s12, s13, &dm, &dg);
+  out[0] = a.real(); out[1] = a.imag();
+  out[2] = dm.real(); out[3] = dm.imag();
+  out[4] = dg.real(); out[5] = dg.imag();
 }
 // One resonance amplitude: out = {Re A, Im A, Gamma(s), B_J(q), Z_J, Re BW, Im BW}.
 void om_res_amp(const double* kin, int ch, double m0, double g0, int J, double s12, double s13, double* out) {

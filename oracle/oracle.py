@@ -67,6 +67,11 @@ def lib():
         L.om_tddp.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
                               ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, ip, ip,
                               ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.om_tddp_full.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
+                                   ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, ip, ip, ip, ip] + [ctypes.c_int] * 5
+        L.om_set_direct_norm.argtypes = [vp, ctypes.c_int]
+        L.om_res_amp_d.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_double, dp]
         L.om_nll.restype = ctypes.c_double
         L.om_nll.argtypes = [vp, dp, ctypes.c_int64, ctypes.POINTER(dp), dp, ctypes.c_int]
         L.om_binned.restype = ctypes.c_double
@@ -112,6 +117,39 @@ def n_threads_default():
         return len(os.sched_getaffinity(0))
     except AttributeError:
         return os.cpu_count() or 1
+
+
+def tddp_is_full(node):
+    """A TDDP node of the full model: complex q/p or floating resonance shapes."""
+    return bool(node.get("qp")) or any(r.get("float") for r in node["dalitz"]["resonances"])
+
+
+def tddp_layout(node):
+    """Positions in a full TDDP node's parameter list: 2R coefficients, tau,
+    y, x (when node["x"]), |q/p| and arg q/p (when node["qp"]), then m0 and
+    Gamma0 of every resonance with "float" set, in resonance order (-1:
+    absent)."""
+    res = node["dalitz"]["resonances"]
+    R = len(res)
+    k = 2 * R
+    lay = {"tau": k, "y": k + 1}
+    k += 2
+    lay["x"] = k if node.get("x") else -1
+    k += 1 if node.get("x") else 0
+    lay["qm"], lay["qa"] = (k, k + 1) if node.get("qp") else (-1, -1)
+    k += 2 if node.get("qp") else 0
+    lay["m0"], lay["g0"] = [], []
+    for r in res:
+        if r.get("float"):
+            lay["m0"].append(k)
+            lay["g0"].append(k + 1)
+            k += 2
+        else:
+            lay["m0"].append(-1)
+            lay["g0"].append(-1)
+    if len(node["par"]) != k:
+        raise ValueError("full TDDP node: %d parameters, expected %d" % (len(node["par"]), k))
+    return lay
 
 
 def kin_array(dz):
@@ -198,13 +236,21 @@ class Model:
             if op == "dalitz":
                 nid = L.om_dalitz(self._h, obs[0], obs[1], _dp(kin), int(dz["grid"]), len(res), chp,
                                   _dp(m0), _dp(g0), Jp, prep, pimp)
-            else:
+            elif not tddp_is_full(node):
                 # parameters: 2R coefficients, tau, y and optionally x
                 R = len(res)
                 p_x = self._p(names[2 * R + 2]) if len(names) == 2 * R + 3 else -1
                 nid = L.om_tddp(self._h, obs[0], obs[1], obs[2], obs[3], _dp(kin), int(dz["grid"]),
                                 R, chp, _dp(m0), _dp(g0), Jp, prep, pimp,
                                 self._p(names[2 * R]), self._p(names[2 * R + 1]), p_x)
+            else:
+                lay = tddp_layout(node)
+                idx = {k: (self._p(names[v]) if v >= 0 else -1) for k, v in lay.items() if not isinstance(v, list)}
+                pm, pmp = _ip([self._p(names[v]) if v >= 0 else -1 for v in lay["m0"]])
+                pg, pgp = _ip([self._p(names[v]) if v >= 0 else -1 for v in lay["g0"]])
+                nid = L.om_tddp_full(self._h, obs[0], obs[1], obs[2], obs[3], _dp(kin), int(dz["grid"]),
+                                     len(res), chp, _dp(m0), _dp(g0), Jp, prep, pimp, pmp, pgp,
+                                     idx["tau"], idx["y"], idx["x"], idx["qm"], idx["qa"])
         else:
             raise ValueError(op)
         self.node_ids.append((nid, node))
@@ -277,6 +323,10 @@ class Model:
         d = np.zeros(len(self.par_names))
         v = lib().om_node_lnnorm(self._h, node_id, _dp(th), _dp(d))
         return v, d
+
+    def set_direct_norm(self, on=True):
+        """Tests: every TDDP normalisation as the grid sum at theta."""
+        lib().om_set_direct_norm(self._h, int(bool(on)))
 
     def dalitz_node(self):
         for nid, node in self.node_ids:
@@ -439,6 +489,13 @@ def res_amp(dz, ch, m0, g0, J, s12, s13):
     lib().om_res_amp(_dp(k), _CH[ch], m0, g0, J, s12, s13, _dp(out))
     return {"A": out[0] + 1j * out[1], "width": out[2], "B": out[3], "Z": out[4],
             "BW": out[5] + 1j * out[6]}
+
+
+def res_amp_d(dz, ch, m0, g0, J, s12, s13):
+    """One resonance amplitude and its m0 and Gamma0 derivatives (complex)."""
+    out = np.zeros(6)
+    lib().om_res_amp_d(_dp(kin_array(dz)), _CH[ch], m0, g0, J, s12, s13, _dp(out))
+    return complex(out[0], out[1]), complex(out[2], out[3]), complex(out[4], out[5])
 
 
 def econv(t, G, s):

@@ -11,6 +11,9 @@ Everything here is plain data.  A model tree is a nested dict:
                    "dalitz": DALITZ_KINEMATICS}
   {"op": "tddp",   "obs": ["s12", "s13", "t", "sigma_t"],
                    "par": [re1, im1, ..., "tau", "y"], "dalitz": DALITZ_KINEMATICS}
+  full time-dependent model: "x": True / "qp": True on the tddp node and
+  "float": True on resonances; "par" then lists 2R coefficients, tau, y,
+  (x), (|q/p|, arg q/p), then (m0, Gamma0) of each floating resonance
 
 Observables are (name, lo, hi); parameters are (name, init, step, lo, hi,
 fixed) as in the two Variable constructors of the paper's first listing.
@@ -20,7 +23,7 @@ import math
 
 __all__ = [
     "C1", "C2", "C3", "C4", "C4X", "C5", "LISTING2", "MAPPED", "MAPPED_SUM", "SHARED", "SHARED_SUM",
-    "SHARED_2D", "C4S", "CONV", "CONV_POLY", "CONV_GMIX", "COMP", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
+    "SHARED_2D", "C4S", "C4F", "CONV", "CONV_POLY", "CONV_GMIX", "COMP", "RESONANCES_FULL", "SIGMA_T_CELLS", "SIGMA_T_BOUNDS", "DALITZ_KINEMATICS", "RESONANCES",
     "DALITZ_TRUTH", "dalitz_param_names", "dalitz_box", "workload",
 ]
 
@@ -180,6 +183,78 @@ C4X = {
     "n_events": 2_000_000,
     "seed": 6,
 }
+
+# ---------------------------------------------------------------- C4F
+# The full mixing model of the paper's time-dependent fit: 16 complex
+# amplitudes (the non-resonant term and 15 resonances), decay time with x
+# and y, complex q/p = |q/p| e^{i phi}, and the masses and widths of the
+# rho(770) and of the K*(892) in the 12 pair as parameters (their
+# normalisation is then re-computed on the grid at every evaluation):
+# 30 + 3 + 2 + 4 = 39 parameters.  Coefficients: magnitudes chosen for the
+# fit fractions (NR .058, then .093 .232 .006 .035 .023 .023 .012 .463 .012
+# .070 .012 .012 .006 .035 .012 on the 400 x 400 grid), phases (30, 0, 110,
+# -60, -20, 80, 150, 140, -40, 60, -100, 20, -150, 100, 45) degrees.
+RESONANCES_FULL = [
+    ("23", 0.500, 0.400, 0), ("23", 0.775, 0.149, 1), ("23", 0.783, 0.010, 1), ("23", 0.980, 0.060, 0),
+    ("23", 1.275, 0.185, 2), ("23", 1.370, 0.350, 0), ("23", 1.465, 0.400, 1),
+    ("12", 0.892, 0.050, 1), ("13", 0.892, 0.050, 1), ("12", 1.425, 0.270, 0), ("13", 1.425, 0.270, 0),
+    ("12", 1.430, 0.100, 2), ("13", 1.430, 0.100, 2), ("12", 1.717, 0.322, 1), ("13", 1.414, 0.232, 1),
+]
+FULL_TRUTH = [
+    (0.389105, 0.224650), (0.349743, 0.0), (-0.004659, 0.012801), (0.068723, -0.119032),
+    (0.350606, -0.127610), (0.105086, 0.595975), (-0.370700, 0.214024), (-0.376222, 0.315688),
+    (0.059486, -0.049915), (0.346499, 0.600155), (-0.049128, -0.278617), (0.296423, 0.107889),
+    (-0.193171, -0.111527), (-0.192947, 1.094255), (0.214472, 0.214472),
+]
+FULL_FLOATING = {1: ("rho_m0", "rho_g0", (0.70, 0.85), (0.10, 0.20)),
+                 7: ("kst_m0", "kst_g0", (0.85, 0.93), (0.03, 0.08))}
+
+
+def _full_model(grid=1000, n_events=1_000_000, seed=8):
+    import numpy as np
+    rng = np.random.default_rng(seed + 100)
+    R = len(RESONANCES_FULL)
+    res, shape_par, shape_names, truth = [], [], [], {}
+    for k, (ch, m0, g0, J) in enumerate(RESONANCES_FULL):
+        r = {"ch": ch, "m0": m0, "g0": g0, "J": J}
+        if k in FULL_FLOATING:
+            nm, ng, bm, bg = FULL_FLOATING[k]
+            r["float"] = True
+            shape_par += [(nm, m0 * (1.0 + 0.01 * rng.standard_normal()), 0.002, bm[0], bm[1], False),
+                          (ng, g0 * (1.0 + 0.05 * rng.standard_normal()), 0.002, bg[0], bg[1], False)]
+            shape_names += [nm, ng]
+            truth[nm], truth[ng] = m0, g0
+        res.append(r)
+    coef = []
+    for k, (re, im) in enumerate(FULL_TRUTH, start=1):
+        mag = math.hypot(re, im) * (1.0 + 0.1 * rng.standard_normal())
+        ph = math.atan2(im, re) + math.radians(10.0) * rng.standard_normal()
+        coef += [(f"re{k}", mag * math.cos(ph), 0.05, 0.0, 0.0, False),
+                 (f"im{k}", mag * math.sin(ph), 0.05, 0.0, 0.0, False)]
+        truth[f"re{k}"], truth[f"im{k}"] = re, im
+    params = coef + [("tau", 0.45, 0.01, 0.1, 2.0, False), ("y", 0.0, 0.005, -0.2, 0.2, False),
+                     ("x", 0.0, 0.005, -0.2, 0.2, False), ("qp_mag", 1.05, 0.02, 0.5, 1.5, False),
+                     ("qp_phase", 0.05, 0.02, -1.0, 1.0, False)] + shape_par
+    truth.update(tau=0.41, y=0.01, x=0.008, qp_mag=1.0, qp_phase=0.0)
+    box = dalitz_box()
+    return {
+        "name": "c4f_tddp_full_mixing",
+        "obs": [("s12", box[0], box[1]), ("s13", box[0], box[1]),
+                ("t", -math.inf, math.inf), ("sigma_t", 0.0, math.inf)],
+        "params": params,
+        "truth": truth,
+        "model": {
+            "op": "tddp", "obs": ["s12", "s13", "t", "sigma_t"], "x": True, "qp": True,
+            "par": dalitz_param_names(R) + ["tau", "y", "x", "qp_mag", "qp_phase"] + shape_names,
+            "dalitz": dict(DALITZ_KINEMATICS, grid=grid, resonances=res),
+        },
+        "sigma_t_range": (0.02, 0.2),
+        "n_events": n_events,
+        "seed": seed,
+    }
+
+
+C4F = _full_model()
 
 # ---------------------------------------------------------------- mapped densities
 # The MappedPdf form of section "Combining functions": a different leaf on
@@ -382,4 +457,4 @@ LISTING2 = {
 def workload(name):
     return {"c1": C1, "c2": C2, "c3": C3, "c4": C4, "c4x": C4X, "listing2": LISTING2, "mapped": MAPPED,
             "mapped_sum": MAPPED_SUM, "shared": SHARED, "shared_sum": SHARED_SUM, "shared_2d": SHARED_2D,
-            "c4s": C4S, "conv": CONV, "conv_poly": CONV_POLY, "comp": COMP, "conv_gmix": CONV_GMIX}[name]
+            "c4s": C4S, "c4f": C4F, "conv": CONV, "conv_poly": CONV_POLY, "comp": COMP, "conv_gmix": CONV_GMIX}[name]

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "hipfit")
 LIB = os.path.join(HERE, "libhipfit.so")
 
-SOURCES = ["eval_kernels.hip", "terms_kernels.hip", "grid_kernels.hip", "gen_kernels.hip", "graph.cpp", "api.cpp",
+SOURCES = ["eval_kernels.hip", "terms_kernels.hip", "full_kernels.hip", "grid_kernels.hip", "gen_kernels.hip", "graph.cpp", "api.cpp",
            "minimiser.cpp", "fit.cpp", "batch.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -43,12 +43,17 @@ def _prec(p):
     raise ValueError("precision must be 'fp64' or 'fp32'")
 
 
-def dalitz_consts(dz):
-    """Constant block of a DALITZ / TDDP node (see include/hipfit.h)."""
+def dalitz_consts(dz, node=None):
+    """Constant block of a DALITZ / TDDP node (see include/hipfit.h); the
+    full time-dependent form (node "qp" set, or resonances with "float")
+    appends the flags (1: x, 2: q/p) and the floating-shape flags."""
     res = dz["resonances"]
     c = [dz["M"], dz["m1"], dz["m2"], dz["m3"], dz["r"], float(dz["grid"]), float(len(res))]
     for r in res:
         c += [float(_CH[r["ch"]]), r["m0"], r["g0"], float(r["J"])]
+    if node is not None and node["op"] == "tddp" and (node.get("qp") or any(r.get("float") for r in res)):
+        c += [float((1 if node.get("x") else 0) | (2 if node.get("qp") else 0))]
+        c += [1.0 if r.get("float") else 0.0 for r in res]
     return c
 
 
@@ -80,7 +85,7 @@ class Graph:
             if op == "poly":
                 consts = [float(node.get("x0", 0.0))]
             elif op in ("dalitz", "tddp"):
-                consts = dalitz_consts(node["dalitz"])
+                consts = dalitz_consts(node["dalitz"], node)
             elif op == "map":
                 consts = [float(b) for b in node["bounds"]]
             elif op == "conv":

@@ -65,12 +65,21 @@ static hipError_t prof_harvest() {
   return hipSuccess;
 }
 
+// Layout of a dataset's mapped result row: the reduced sums of an
+// evaluation and their completion flag, then (the full time-dependent model
+// with floating shapes) the reduced grid sums of its normalisation and
+// their flag.
+constexpr int kResFlag = kMaxSlots + 1;
+constexpr int kNormRes = kMaxSlots + 2;
+constexpr int kNormFlag = kNormRes + kMaxSlots + 1;
+constexpr int kResultDoubles = kNormFlag + 1;
+
 // Waits for the reduction of one evaluation: spins on the flag that the
 // reduction kernel sets after its result is visible in mapped host memory,
 // asking the stream every 4096 spins (errors, or a finished stream without
 // the flag, end the wait).
-static hipError_t wait_result(const dataset* d, hipStream_t st) {
-  const volatile int64_t* flag = (const volatile int64_t*)(d->res_host + kMaxSlots + 1);
+static hipError_t wait_result(const dataset* d, hipStream_t st, int flag_at = kResFlag) {
+  const volatile int64_t* flag = (const volatile int64_t*)(d->res_host + flag_at);
   for (uint64_t spin = 1;; ++spin) {
     if (*flag == d->seq) {
       std::atomic_thread_fence(std::memory_order_acquire);
@@ -95,9 +104,9 @@ static int ensure_result_buffer(const dataset* dc) {
   dataset* d = const_cast<dataset*>(dc);
   if (d->res_host) return HF_OK;
   void* h = nullptr;
-  hipError_t e = hipHostMalloc(&h, (kMaxSlots + 2) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
+  hipError_t e = hipHostMalloc(&h, kResultDoubles * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
   if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(result row)");
-  std::memset(h, 0, (kMaxSlots + 2) * sizeof(double));  // flag 0: no evaluation finished yet
+  std::memset(h, 0, kResultDoubles * sizeof(double));  // flags 0: no evaluation finished yet
   void* dv = nullptr;
   e = hipHostGetDevicePointer(&dv, h, 0);
   if (e != hipSuccess) {
@@ -143,7 +152,7 @@ static int eval_binned(const pdf_graph* g, const dataset* d, const StagedCall& s
     fr.active = 1;
     dataset* dm = const_cast<dataset*>(d);
     dm->seq += 1;
-    fr.flag = (int64_t*)(d->res_dev + kMaxSlots + 1);
+    fr.flag = (int64_t*)(d->res_dev + kResFlag);
     fr.seq = d->seq;
     e = launch_reduce_one(fr, st);
     if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
@@ -158,6 +167,82 @@ static int eval_binned(const pdf_graph* g, const dataset* d, const StagedCall& s
     return fail(HF_E_DOMAIN, "density <= 0 or not finite at a bin with weight");
   }
   *value = v;
+  return HF_OK;
+}
+
+// The full time-dependent model with floating resonance shapes: the grid
+// kernel at this theta (constants of `sc`, column references 0) and its
+// reduction into the normalisation area of the dataset's result row, which
+// the reduction marks with the dataset's next sequence number (the caller's
+// evaluation then uses the same number for its own flag).
+static int launch_grid_norm(const pdf_graph* g, const dataset* d, const StagedCall& sc, bool want_grad,
+                            hipStream_t st) {
+  const DalitzInfo& dz = g->dz;
+  const KNode& kn = sc.prog.node[dz.node];
+  NormArgs na;
+  std::memset(&na, 0, sizeof(na));
+  na.prog = sc.prog;
+  for (int i : {kDzRef12, kDzRef13}) {
+    na.prog.c64[kn.c0 + i] = 0.0;
+    na.prog.c32[kn.c0 + i] = 0.0f;
+  }
+  na.gs = dz.gs;
+  na.partials = dz.norm_partials;
+  na.n_rows = dz.norm_rows;
+  hipError_t e = launch_full_norm(want_grad, na, st);
+  if (e != hipSuccess) return hip_fail(e, "launch of the normalisation grid kernel");
+  const int R = (int)dz.res.size();
+  FitRec fr;
+  std::memset(&fr, 0, sizeof(fr));
+  fr.partials = dz.norm_partials;
+  fr.n_rows = dz.norm_rows;
+  fr.result = d->res_dev + kNormRes;
+  fr.n_slots = want_grad ? 2 * R + 3 + (dz.hq ? 2 : 0) + 2 * (int)dz.fl.size() : 3;
+  fr.active = 1;
+  fr.flag = (int64_t*)(d->res_dev + kNormFlag);
+  fr.seq = d->seq + 1;
+  e = launch_reduce_one(fr, st);
+  if (e != hipSuccess) return hip_fail(e, "launch of the normalisation reduction");
+  return HF_OK;
+}
+
+// ln N and its derivatives from the grid sums (read after the reduction's
+// flag): N = area [sum |A|^2 (kc + kz)/2 + sum |Abar'|^2 (kc - kz)/2 +
+// sum a_s ks + sum b_s kzs], the coefficient, q/p and shape derivatives
+// summed by the kernel, those in tau, y and x from the four sums.
+static int grid_norm_terms(const pdf_graph* g, const dataset* d, const double* th, bool want_grad, StagedCall& sc) {
+  const DalitzInfo& dz = g->dz;
+  const double* v = d->res_host + kNormRes;
+  const int R = (int)dz.res.size();
+  const int nl = want_grad ? 1 + 2 * R : 1;  // |Abar'|^2 follows the LDS columns
+  const double area = dz.gs.h12 * dz.gs.h13;
+  const double IA = area * v[0], IB = area * v[nl], AS = area * v[nl + 1], BS = area * v[nl + 2];
+  const double kc = sc.tint[0], kz = sc.tint[1], ks = sc.tint[2], kzs = sc.tint[3];
+  const double N = 0.5 * (IA + IB) * kc + 0.5 * (IA - IB) * kz + AS * ks + BS * kzs;
+  if (!(N > 0.0) || !std::isfinite(N)) return fail(HF_E_DOMAIN, "normalisation <= 0 or not finite");
+  sc.ht.lnN += std::log(N);
+  if (!want_grad) return HF_OK;
+  const NodeInfo& nd = g->nodes[dz.node];
+  for (int j = 0; j < 2 * R; ++j) sc.ht.dlnN[nd.par[j]] += area * v[1 + j] / N;
+  int q = nl + 3;
+  if (dz.hq) {
+    sc.ht.dlnN[dz.p_qm] += area * v[q] / N;
+    sc.ht.dlnN[dz.p_qa] += area * v[q + 1] / N;
+    q += 2;
+  }
+  for (const FloatRes& f : dz.fl) {
+    sc.ht.dlnN[f.p_m0] += area * v[q] / N;
+    sc.ht.dlnN[f.p_g0] += area * v[q + 1] / N;
+    q += 2;
+  }
+  const double tau = th[dz.p_tau], y = th[dz.p_y], x = dz.p_x >= 0 ? th[dz.p_x] : 0.0;
+  const double X = -AS, Y = -BS, den = 1.0 - y * y, opx = 1.0 + x * x;
+  const double dtau = 0.5 * (IA + IB) / den + 0.5 * (IA - IB) / opx - X * y / den - Y * x / opx;
+  const double dy = 0.5 * (IA + IB) * tau * 2.0 * y / (den * den) - X * tau * (1.0 + y * y) / (den * den);
+  sc.ht.dlnN[dz.p_tau] += dtau / N;
+  sc.ht.dlnN[dz.p_y] += dy / N;
+  if (dz.p_x >= 0)
+    sc.ht.dlnN[dz.p_x] += (-0.5 * (IA - IB) * tau * 2.0 * x / (opx * opx) - Y * tau * (1.0 - x * x) / (opx * opx)) / N;
   return HF_OK;
 }
 
@@ -192,6 +277,8 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
       hipError_t e = prof_harvest();
       if (e != hipSuccess) return hip_fail(e, "profile events");
     }
+    if (sc.grid_norm)
+      if (int rc = launch_grid_norm(g, d, sc, want_grad, st)) return rc;
     hipError_t e = launch_eval(g->kind, d->prec == HF_FP32_EVAL, want_grad, a, st, prof ? g_prof.e[0] : nullptr,
                                prof ? g_prof.e[1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "launch of the likelihood kernel");
@@ -204,14 +291,20 @@ int eval_one(const pdf_graph* g, const dataset* d, const double* th, hipStream_t
     fr.active = 1;
     dataset* dm = const_cast<dataset*>(d);
     dm->seq += 1;
-    fr.flag = (int64_t*)(d->res_dev + kMaxSlots + 1);
+    fr.flag = (int64_t*)(d->res_dev + kResFlag);
     fr.seq = d->seq;
     e = launch_reduce_one(fr, st, prof ? g_prof.e[2] : nullptr, prof ? g_prof.e[3] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "launch of the reduction kernel");
     e = wait_result(d, st);
+    if (e == hipSuccess && sc.grid_norm) e = wait_result(d, st, kNormFlag);
     if (e != hipSuccess) return hip_fail(e, "waiting for the reduction");
     if (prof) g_prof.pending = true;
     for (int j = 0; j < (want_grad ? S + 1 : 1); ++j) sums[j] = d->res_host[j];
+    if (sc.grid_norm)
+      if (int rc = grid_norm_terms(g, d, th, want_grad, sc)) {
+        *nll = INFINITY;
+        return rc;
+      }
   }
   double v = 0.0;
   assemble(g, sc, d->n > 0 ? sums.data() : nullptr, d->n, &v, grad);
@@ -398,8 +491,9 @@ extern "C" int dataset_upload_binned(const pdf_graph* g, const double* const* ce
   if (!(bin_volume > 0.0) || !std::isfinite(bin_volume))
     return fail(HF_E_INVALID, "dataset_upload_binned: bin volume must be positive");
   if (!g) return fail(HF_E_INVALID, "dataset_upload_binned: NULL graph");
-  if (g->n_slots_tree + 2 > kMaxSlots + 1)
+  if (g->n_slots_tree + 2 > kMaxSlotsTree + 1)
     return fail(HF_E_GRAPH, "dataset_upload_binned: more than 31 gradient slots");
+  if (g->dz.full) return fail(HF_E_GRAPH, "dataset_upload_binned: the full time-dependent model is unbinned only");
   if (n_bins > 0 && !weights) return fail(HF_E_INVALID, "dataset_upload_binned: NULL weights");
   for (int64_t i = 0; i < n_bins; ++i)
     if (!(weights[i] >= 0.0) || !std::isfinite(weights[i]))
@@ -727,6 +821,14 @@ extern "C" int nll_terms(const pdf_graph* g, const dataset* d, const double* par
       return fail(HF_E_DOMAIN, "nll_terms: parameters outside the density's domain");
     }
     if (d->n == 0) return HF_OK;
+    if (sc.grid_norm) {
+      if (int rc = ensure_result_buffer(d)) return rc;
+      if (int rc = launch_grid_norm(g, d, sc, dlnp != nullptr, st)) return rc;
+      const_cast<dataset*>(d)->seq += 1;
+      hipError_t e = wait_result(d, st, kNormFlag);
+      if (e != hipSuccess) return hip_fail(e, "nll_terms: normalisation grid");
+      if (int rc = grid_norm_terms(g, d, params, dlnp != nullptr, sc)) return rc;
+    }
     const int S = g->prog.n_slots, nc = 1 + S;
     const int64_t kSlice = int64_t(1) << 18;  // events per terms launch
     const int64_t slice_cap = std::min<int64_t>(kSlice, d->n);

@@ -158,6 +158,8 @@ extern "C" int nll_grad_batched(const pdf_graph* g, const dataset* const* d, int
     if (!g || (n_fits > 0 && (!d || !params || !nll || !grad)) || n_fits < 0)
       return fail(HF_E_INVALID, "nll_grad_batched: bad argument");
     if (n_fits == 0) return HF_OK;
+    if (g->kind == KIND_TDDPF)
+      return fail(HF_E_INVALID, "nll_grad_batched: the full time-dependent model is evaluated one dataset at a time");
     const int np = (int)g->par.size();
     for (int i = 0; i < n_fits; ++i) {
       if (!d[i] || d[i]->g != g) return fail(HF_E_SHAPE, "nll_grad_batched: dataset of another graph");
@@ -290,6 +292,8 @@ extern "C" int batch_admit(batch_engine* b, const dataset* d, const double* para
     if (!b || !d || !params_init) return fail(HF_E_INVALID, "batch_admit: NULL argument");
     if (d->g != b->g) return fail(HF_E_SHAPE, "batch_admit: dataset of another graph");
     if (d->metric != 0) return fail(HF_E_INVALID, "batch_admit: binned datasets are fitted one at a time");
+    if (b->g->kind == KIND_TDDPF)
+      return fail(HF_E_INVALID, "batch_admit: the full time-dependent model is fitted one dataset at a time");
     if (opts && opts->grad_mode != 0) return fail(HF_E_INVALID, "batch_admit: only the analytic gradient is batched");
     if (b->prec_set && d->prec != b->prec) return fail(HF_E_INVALID, "batch_admit: precision differs from the engine's");
     if (d->bytes > b->budget) return fail(HF_E_INVALID, "batch_admit: dataset larger than the whole budget");

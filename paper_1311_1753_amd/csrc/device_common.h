@@ -94,12 +94,12 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // ------------------------------------------------------------------ Dalitz pieces
-// Per-event amplitudes: (re, im) pairs of the kMaxRes resonance places,
+// Per-event amplitudes: (re, im) pairs of the NR resonance places,
 // written at wave-uniform runtime indices.  Each event's array is a separate
 // plain array, picked by a compile-time event number, so that each is kept in
 // registers on its own (a two-dimensional array indexed by a runtime
 // resonance number would be placed in scratch memory).
-template <typename T> using AmpArr = T[2 * kMaxRes];
+template <typename T, int NR = kMaxRes> using AmpArr = T[2 * NR];
 template <int e, class A>
 __device__ __forceinline__ A& pick(A& x0, A& x1) {
   if constexpr (e == 0) return x0;
@@ -185,10 +185,10 @@ __device__ __forceinline__ Cx<T> res_amp(const CS& cs, int rb, const GroupQ<T>& 
 // and the conjugate amplitudes into b0, b1.  The bounds are wave-uniform, so
 // the writes are indexed register moves; each resonance's constants are read
 // once for the E events.
-template <typename T, int J, bool TD, int E>
+template <typename T, int J, bool TD, int E, int NR>
 __device__ __forceinline__ void res_group(const CS& cs, int rbase, T r2, int k0, int k1, const Chan<T> (&c)[E],
-                                          const Chan<T> (&cb)[E], AmpArr<T>& a0, AmpArr<T>& a1,
-                                          AmpArr<T>& b0, AmpArr<T>& b1) {
+                                          const Chan<T> (&cb)[E], AmpArr<T, NR>& a0, AmpArr<T, NR>& a1,
+                                          AmpArr<T, NR>& b0, AmpArr<T, NR>& b1) {
   if (k0 >= k1) return;
   GroupQ<T> gq[E], gb[E];
 #pragma unroll
@@ -220,10 +220,10 @@ __device__ __forceinline__ void res_group(const CS& cs, int rbase, T r2, int k0,
 // and vice versa.  The resonances are stored grouped by (pair, spin), so each
 // group is one loop with the pair and spin fixed at compile time.  Absent
 // resonance places (k >= R) get zero amplitudes.
-template <typename T, bool TD, int E>
+template <typename T, bool TD, int E, int NR = kMaxRes>
 __device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, const double (&s12)[E],
-                                            const double (&s13)[E], const double (&s23)[E], AmpArr<T>& a0,
-                                            AmpArr<T>& a1, AmpArr<T>& b0, AmpArr<T>& b1) {
+                                            const double (&s13)[E], const double (&s23)[E], AmpArr<T, NR>& a0,
+                                            AmpArr<T, NR>& a1, AmpArr<T, NR>& b0, AmpArr<T, NR>& b1) {
   const int R = nd.aux;
   const int chb = nd.c0 + dz_ch_base(R, TD), rbase = nd.c0 + dz_res_base(R, TD);
   // pair (A, B; C): 12 = (1, 2; 3), 13 = (1, 3; 2), 23 = (2, 3; 1)
@@ -253,16 +253,16 @@ __device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, const
   }
   const int32_t* g = nd.res_end;
   const T r2 = cs.get<T>(nd.c0 + kDzR2);
-  res_group<T, 0, TD, E>(cs, rbase, r2, 0, g[0], c12, b12, a0, a1, b0, b1);
-  res_group<T, 1, TD, E>(cs, rbase, r2, g[0], g[1], c12, b12, a0, a1, b0, b1);
-  res_group<T, 2, TD, E>(cs, rbase, r2, g[1], g[2], c12, b12, a0, a1, b0, b1);
-  res_group<T, 0, TD, E>(cs, rbase, r2, g[2], g[3], c13, b13, a0, a1, b0, b1);
-  res_group<T, 1, TD, E>(cs, rbase, r2, g[3], g[4], c13, b13, a0, a1, b0, b1);
-  res_group<T, 2, TD, E>(cs, rbase, r2, g[4], g[5], c13, b13, a0, a1, b0, b1);
-  res_group<T, 0, TD, E>(cs, rbase, r2, g[5], g[6], c23, b23, a0, a1, b0, b1);
-  res_group<T, 1, TD, E>(cs, rbase, r2, g[6], g[7], c23, b23, a0, a1, b0, b1);
-  res_group<T, 2, TD, E>(cs, rbase, r2, g[7], g[8], c23, b23, a0, a1, b0, b1);
-  for (int k = R; k < kMaxRes; ++k) {
+  res_group<T, 0, TD, E, NR>(cs, rbase, r2, 0, g[0], c12, b12, a0, a1, b0, b1);
+  res_group<T, 1, TD, E, NR>(cs, rbase, r2, g[0], g[1], c12, b12, a0, a1, b0, b1);
+  res_group<T, 2, TD, E, NR>(cs, rbase, r2, g[1], g[2], c12, b12, a0, a1, b0, b1);
+  res_group<T, 0, TD, E, NR>(cs, rbase, r2, g[2], g[3], c13, b13, a0, a1, b0, b1);
+  res_group<T, 1, TD, E, NR>(cs, rbase, r2, g[3], g[4], c13, b13, a0, a1, b0, b1);
+  res_group<T, 2, TD, E, NR>(cs, rbase, r2, g[4], g[5], c13, b13, a0, a1, b0, b1);
+  res_group<T, 0, TD, E, NR>(cs, rbase, r2, g[5], g[6], c23, b23, a0, a1, b0, b1);
+  res_group<T, 1, TD, E, NR>(cs, rbase, r2, g[6], g[7], c23, b23, a0, a1, b0, b1);
+  res_group<T, 2, TD, E, NR>(cs, rbase, r2, g[7], g[8], c23, b23, a0, a1, b0, b1);
+  for (int k = R; k < NR; ++k) {
     static_for<E>([&](auto ei) {
       constexpr int e = decltype(ei)::value;
       pick<e>(a0, a1)[2 * k] = pick<e>(a0, a1)[2 * k + 1] = T(0);

@@ -144,19 +144,64 @@ __device__ __forceinline__ void leaf_dalitz(const CS& cs, const KNode& nd, bool 
   }
 }
 
+// One resonance of the full model at one point, its pair and spin known
+// only at run time (wave-uniform): the amplitude A, 1 / (m0^2 - s - i m0
+// Gamma(s)) = D and the width factor g of m0 Gamma(s) = (Kw B0^2) g, from
+// which the mass and width derivatives follow (dA = A [D (-d(m0^2) + i g
+// d(Kw B0^2)) + d ln B0]).
+template <typename T>
+__device__ __forceinline__ void res_amp_rt(const CS& cs, const KNode& nd, int k, int pair, int J, double s12,
+                                           double s13, double s23, Cx<T>& A, Cx<T>& D, T& g) {
+  const int R = nd.aux;
+  const int cb = nd.c0 + dz_ch_base(R, true) + pair * kChStride;
+  const double sAB = pair == 0 ? s12 : (pair == 1 ? s13 : s23);
+  const double sAC = pair == 0 ? s13 : s12;
+  const double sBC = pair == 2 ? s13 : s23;
+  const Chan<T> c = chan_eval<T>(cs, cb, sAB, sAC, sBC);
+  const T r2 = cs.get<T>(nd.c0 + kDzR2);
+  const GroupQ<T> gq = J == 0 ? group_q<T, 0>(r2, c) : (J == 1 ? group_q<T, 1>(r2, c) : group_q<T, 2>(r2, c));
+  const int rb = nd.c0 + dz_res_base(R, true) + k * kResStride;
+  const T d = (T)(cs.d[rb + kResM02] - sAB);
+  const T mg = cs.get<T>(rb + kResKwB) * gq.g;
+  const T den = Mth<T>::rcp(Mth<T>::fma(d, d, mg * mg));
+  const T f = cs.get<T>(rb + kResSqB) * gq.zf * den;
+  A = {f * d, f * mg};
+  D = {d * den, mg * den};
+  g = gq.g;
+}
+
+// Tail receiver of the plain kernels (they emit every slot through emit).
+struct NoTail {
+  template <class J, class V> __device__ __forceinline__ void operator()(J, const V&) const {}
+};
+
 // TDDP: ln [a_c C + a_0 Cz + a_s S + b_s Sz] for E events at once, with
 // b_s = -Im(conj(A) Abar) and Cz + i Sz the resolution-convolved
 // e^{-t/tau} e^{i x t/tau} (without x: Cz = E(t; 1/tau), Sz = 0); slot
 // derivatives (coefficients, then tau, y and, with x, x) go to emit(slot,
-// values[E]), the coefficients' first over all kMaxRes places as for DALITZ,
+// values[E]), the coefficients' first over all NR places as for DALITZ,
 // then tau, y (, x) to slots 2R, 2R + 1 (, 2R + 2) after any zero emitted
 // there.
-template <typename T, int E, bool HX, class Emit>
+// FULL (the mixing fit's model, E = 1): Abar carries q/p, the trigonometric
+// terms are always formed (W = 0 without x), and the slots after the
+// coefficients go to tail(integral_constant<j>, values) with j = 0 tau,
+// 1 y, 2 x, 3 |q/p|, 4 arg q/p, 5 + 2f and 6 + 2f the mass and width of
+// floating resonance f (only those the node has are emitted).
+// NORM (full model, in double): one cell of the normalisation grid instead
+// of an event; the time factors are their integrals over the real line,
+// lv receives |A|^2 and tail 0, 1, 2 receive |Abar'|^2, a_s, b_s (their
+// sums give the normalisation and its tau, y, x derivatives); emit and the
+// q/p and shape tails receive derivatives of the time-integrated rate
+// itself (not divided by it).
+template <typename T, int E, bool HX, int NR = kMaxRes, bool FULL = false, bool NORM = false, class Emit,
+          class Tail = NoTail>
 __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool hoisted, const double (&x12)[E],
                                           const double (&x13)[E], const double (&xt)[E], const double (&xs)[E],
-                                          T (&lv)[E], const Emit& emit) {
+                                          T (&lv)[E], const Emit& emit, const Tail& tail = Tail{}) {
   const int c0 = nd.c0, R = nd.aux;
-  constexpr bool hx = HX;  // x free: trigonometric terms (the node has 2R + 3 slots)
+  constexpr bool hx = HX || FULL;  // trigonometric terms (x free: the plain node has 2R + 3 slots)
+  static_assert(!FULL || E == 1, "the full model takes one event per step");
+  static_assert(!NORM || FULL, "grid cells of the full model only");
   double s12[E], s13[E], s23[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -165,20 +210,32 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
     s23[e] = cs.d[c0 + kDzSsum] - s12[e] - s13[e];
   }
   static_assert(E == 1 || E == 2, "one or two events per step");
-  AmpArr<T> a0, a1, b0, b1;
-  dalitz_amps<T, true, E>(cs, nd, s12, s13, s23, a0, a1, b0, b1);
+  AmpArr<T, NR> a0, a1, b0, b1;
+  dalitz_amps<T, true, E, NR>(cs, nd, s12, s13, s23, a0, a1, b0, b1);
   const int cb = c0 + dz_coef_base(R, true);
-  const int tb = c0 + dz_time_base(R);
+  const int tb = c0 + dz_time_base(R, NR);
+  const int fb = c0 + dz_full_base(R);
+  // q/p multiplies the conjugate amplitudes (1 outside the full model)
+  Cx<T> qp = {T(1), T(0)};
+  if constexpr (FULL) {
+    qp = {cs.get<T>(fb + kFqRe), cs.get<T>(fb + kFqIm)};
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const Cx<T> w = cmul(qp, Cx<T>{b0[2 * k], b0[2 * k + 1]});
+      b0[2 * k] = w.re;
+      b0[2 * k + 1] = w.im;
+    }
+  }
   Cx<T> S[E], Sb[E];
-  T cc[E], cb_[E], St[E], Sz[E], iR[E], dtau[E], dy[E], dx[E];
+  T cc[E], cb_[E], St[E], Sz[E], iR[E], dtau[E], dy[E], dx[E], dqm[E], dqa[E], nBv[E], asv[E], bsv[E];
   static_for<E>([&](auto ei) {
     constexpr int e = decltype(ei)::value;
-    const AmpArr<T>& ae = pick<e>(a0, a1);
-    const AmpArr<T>& be = pick<e>(b0, b1);
+    const AmpArr<T, NR>& ae = pick<e>(a0, a1);
+    const AmpArr<T, NR>& be = pick<e>(b0, b1);
     S[e] = {T(1), T(0)};
-    Sb[e] = {T(1), T(0)};
+    Sb[e] = qp;
 #pragma unroll
-    for (int k = 0; k < kMaxRes; ++k) {
+    for (int k = 0; k < NR; ++k) {
       const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
       const Cx<T> t = cmul(c, Cx<T>{ae[2 * k], ae[2 * k + 1]});
       const Cx<T> u = cmul(c, Cx<T>{be[2 * k], be[2 * k + 1]});
@@ -189,6 +246,20 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
     const T nB = Sb[e].re * Sb[e].re + Sb[e].im * Sb[e].im;
     const T as = -(S[e].re * Sb[e].re + S[e].im * Sb[e].im);  // -Re(conj(A) Abar)
     const T bs = -(S[e].re * Sb[e].im - S[e].im * Sb[e].re);  // -Im(conj(A) Abar)
+    if constexpr (NORM) {
+      const double kc = cs.d[fb + kFkc], kz = cs.d[fb + kFkz];
+      cc[e] = (T)(kc + kz);
+      cb_[e] = (T)(kc - kz);
+      St[e] = (T)cs.d[fb + kFks];
+      Sz[e] = (T)cs.d[fb + kFkzs];
+      iR[e] = T(1);
+      lv[e] = nA;
+      nBv[e] = nB;
+      asv[e] = as;
+      bsv[e] = bs;
+      dqm[e] = (cb_[e] * nB + as * St[e] + bs * Sz[e]) * cs.get<T>(fb + kFiq);
+      dqa[e] = as * Sz[e] - bs * St[e];
+    } else {
     // Decay-time factors, formed in double: C - E(1/tau), S and the tau / y
     // derivative combinations are small differences of nearly equal terms
     // (|y| << 1), and rounding them in float would bias every event the
@@ -239,20 +310,27 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
     dtau[e] = rt * iR[e];
     dy[e] = (T(0.5) * (nA + nB) * yAB + as * yS) * iR[e];
     dx[e] = hx ? (T(0.5) * (nA - nB) * (T)Cz_x + bs * (T)Sz_x) * iR[e] : T(0);
+    if constexpr (FULL) {
+      // q/p = |q/p| e^{i phi} scales Abar: |Abar|^2 goes as |q/p|^2, a_s and
+      // b_s as |q/p|; the phase turns (a_s, b_s)
+      dqm[e] = (cb_[e] * nB + as * St[e] + bs * Sz[e]) * cs.get<T>(fb + kFiq) * iR[e];
+      dqa[e] = (as * Sz[e] - bs * St[e]) * iR[e];
+    }
     if (!hoisted) {
       dtau[e] -= cs.get<T>(c0 + kDzDln + 2 * R);
       dy[e] -= cs.get<T>(c0 + kDzDln + 2 * R + 1);
       dx[e] -= cs.get<T>(c0 + kDzDln + 2 * R + 2);
       lv[e] = (lv[e] - cs.get<T>(c0 + kDzLnHi)) - cs.get<T>(c0 + kDzLnLo);
     }
+    }
   });
 #pragma unroll
-  for (int k = 0; k < kMaxRes; ++k) {
+  for (int k = 0; k < NR; ++k) {
     T d_re[E], d_im[E];
     static_for<E>([&](auto ei) {
       constexpr int e = decltype(ei)::value;
-      const AmpArr<T>& ae = pick<e>(a0, a1);
-      const AmpArr<T>& be = pick<e>(b0, b1);
+      const AmpArr<T, NR>& ae = pick<e>(a0, a1);
+      const AmpArr<T, NR>& be = pick<e>(b0, b1);
       // re part: dA = A_k, dAb = Ab_k ; im part: dA = i A_k, dAb = i Ab_k
       const T ar = ae[2 * k], ai = ae[2 * k + 1], br = be[2 * k], bi = be[2 * k + 1];
       const T pA_re = S[e].re * ar + S[e].im * ai;    // Re(conj(S) A_k)
@@ -279,9 +357,62 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
     emit(2 * k, d_re);
     emit(2 * k + 1, d_im);
   }
-  emit(2 * R, dtau);
-  emit(2 * R + 1, dy);
-  if (hx) emit(2 * R + 2, dx);
+  if constexpr (!FULL) {
+    emit(2 * R, dtau);
+    emit(2 * R + 1, dy);
+    if (hx) emit(2 * R + 2, dx);
+  } else if constexpr (NORM) {
+    tail(std::integral_constant<int, 0>{}, nBv);
+    tail(std::integral_constant<int, 1>{}, asv);
+    tail(std::integral_constant<int, 2>{}, bsv);
+  } else {
+    tail(std::integral_constant<int, 0>{}, dtau);
+    tail(std::integral_constant<int, 1>{}, dy);
+    if (cs.d[fb + kFhx] != 0.0) tail(std::integral_constant<int, 2>{}, dx);
+  }
+  if constexpr (FULL) {
+    if (cs.d[fb + kFhq] != 0.0) {
+      tail(std::integral_constant<int, 3>{}, dqm);
+      tail(std::integral_constant<int, 4>{}, dqa);
+    }
+    // floating masses and widths: the rate moves along dA = c_k A_k F and
+    // dAbar' = (q/p) c_k Abar_k Fbar (F, Fbar the amplitudes' relative
+    // derivatives at the point and at the swapped point), so
+    // dR = Re(alpha c_k A_k F) + Re(beta (q/p) c_k Abar_k Fbar) with the
+    // adjoints alpha = d R / dA, beta = d R / dAbar' (as complex
+    // derivatives of a real function: dR = Re(alpha dA + beta dAbar'))
+    const int nf = (int)cs.d[fb + kFnf];
+    const Cx<T> cS = {S[0].re, -S[0].im}, cSb = {Sb[0].re, -Sb[0].im};
+    const Cx<T> al = {cc[0] * cS.re - St[0] * cSb.re + Sz[0] * cSb.im,
+                      cc[0] * cS.im - St[0] * cSb.im - Sz[0] * cSb.re};
+    const Cx<T> be = {cb_[0] * cSb.re - St[0] * cS.re - Sz[0] * cS.im,
+                      cb_[0] * cSb.im - St[0] * cS.im + Sz[0] * cS.re};
+    static_for<kMaxFloat>([&](auto fi) {
+      constexpr int f = decltype(fi)::value;
+      if (f < nf) {
+        const int lb = fb + kFlBase + f * kFlStride;
+        const int k = (int)cs.d[lb + kFlRes], pair = (int)cs.d[lb + kFlPair], J = (int)cs.d[lb + kFlJ];
+        Cx<T> A, D, Ab, Db;
+        T g, gb;
+        res_amp_rt<T>(cs, nd, k, pair, J, s12[0], s13[0], s23[0], A, D, g);
+        res_amp_rt<T>(cs, nd, k, pair, J, s13[0], s12[0], s23[0], Ab, Db, gb);
+        const Cx<T> ck = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
+        const Cx<T> w = cmul(al, cmul(ck, A));
+        const Cx<T> wb = cmul(be, cmul(qp, cmul(ck, Ab)));
+        const T dm2 = cs.get<T>(lb + kFlDm2), dkm = cs.get<T>(lb + kFlDkwM), dlb = cs.get<T>(lb + kFlDlbM),
+                dkg = cs.get<T>(lb + kFlDkwG);
+        // F_m = D (-dm2 + i g dkm) + dlb, F_g = D (i g dkg)
+        const Cx<T> Fm = {-D.re * dm2 - D.im * g * dkm + dlb, -D.im * dm2 + D.re * g * dkm};
+        const Cx<T> Fbm = {-Db.re * dm2 - Db.im * gb * dkm + dlb, -Db.im * dm2 + Db.re * gb * dkm};
+        const Cx<T> Fg = {-D.im * g * dkg, D.re * g * dkg};
+        const Cx<T> Fbg = {-Db.im * gb * dkg, Db.re * gb * dkg};
+        const T dm[1] = {(cmul(w, Fm).re + cmul(wb, Fbm).re) * iR[0]};
+        const T dg[1] = {(cmul(w, Fg).re + cmul(wb, Fbg).re) * iR[0]};
+        tail(std::integral_constant<int, 5 + 2 * f>{}, dm);
+        tail(std::integral_constant<int, 6 + 2 * f>{}, dg);
+      }
+    });
+  }
 }
 
 // ------------------------------------------------------------------ cross-lane sums
@@ -1275,6 +1406,7 @@ __device__ __forceinline__ int sig_cell(const SigLds& L, int n12, int n13, doubl
 // whose accumulators reuse the LDS of the first.
 constexpr int OP_TDDP_S = 17;    // x = 0
 constexpr int OP_TDDP_XS = 18;   // x free
+constexpr int OP_TDDP_F = 19;    // the full model (its own row function)
 template <int OP> struct AmpOp {
   static constexpr int base = OP == OP_TDDP_S ? OP_TDDP : (OP == OP_TDDP_XS ? OP_TDDP_X : OP);
   static constexpr bool sig = OP == OP_TDDP_S || OP == OP_TDDP_XS;
@@ -1426,6 +1558,103 @@ __device__ __forceinline__ void amp_leaf_row(const KProgram& P, const CS& cs, co
   }
 }
 
+// Output column (after the 2R coefficient slots) of tail entry j of a full
+// node (see leaf_tddp): tau, y, then x, |q/p|, arg q/p and the floating
+// shapes where present; -1 for an entry the node does not have.
+__device__ __forceinline__ int full_tail_col(const CS& cs, int fb, int j) {
+  const int hx = cs.d[fb + kFhx] != 0.0, hq = cs.d[fb + kFhq] != 0.0, nf = (int)cs.d[fb + kFnf];
+  if (j < 2) return j;
+  if (j == 2) return hx ? 2 : -1;
+  if (j < 5) return hq ? 2 + hx + (j - 3) : -1;
+  return j - 5 < 2 * nf ? 2 + hx + 2 * hq + (j - 5) : -1;
+}
+
+// Single TDDP leaf of the full model (up to kMaxResFull resonances, q/p,
+// floating shapes), one event per thread and step.  The NLL and the
+// coefficient slots accumulate per thread in LDS (1 + 2 kMaxResFull
+// columns), the tail slots (tau, y, x, q/p, shapes) per thread in
+// registers; the row store sums both in the same fixed order as the other
+// kernels (four waves, then the lanes).
+template <typename T, bool GRAD, bool TM = false>
+__device__ __forceinline__ void full_leaf_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
+                                              int n_rows, int r, double* __restrict__ out) {
+  typedef typename Col<T>::S Sx;
+  constexpr int NR = kMaxResFull;
+  constexpr int NC = 1 + 2 * NR;
+  const KNode& nd = P.node[0];
+  const int R = nd.aux;
+  const int fb = nd.c0 + dz_full_base(R);
+  const Sx* cp[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cp[c] = (const Sx*)cols[nd.col[c]];
+  __shared__ double accs[NC][kBlock];
+  const LdsAcc<NC> acc{accs};
+  acc.zero(GRAD ? NC : 1);
+  double tl[kFullTail];
+#pragma unroll
+  for (int j = 0; j < kFullTail; ++j) tl[j] = 0.0;
+  int64_t c0, c1;
+  row_chunks(n, n_rows, r, c0, c1);
+  const int64_t t = threadIdx.x;
+  Sx cur[4];
+  {
+    const int64_t i = c0 * kBlock + t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cur[c] = (c0 < c1 && i < n) ? cp[c][i] : Sx(0);
+  }
+#pragma unroll 1
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    const int64_t i = ch * kBlock + t;
+    double x[4][1];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c][0] = (double)cur[c];
+    if (ch + 1 < c1) {
+      const int64_t i1 = i + kBlock;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cur[c] = i1 < n ? cp[c][i1] : Sx(0);
+    }
+    if (i >= n) continue;
+    const auto emit = [&](int j, const T (&v)[1]) {
+      if (GRAD) acc.add(1 + j, (double)v[0]);
+    };
+    const auto tail = [&](auto j, const T (&v)[1]) {
+      constexpr int J = decltype(j)::value;
+      if (GRAD) tl[J] += (double)v[0];
+    };
+    T lv[1];
+    leaf_tddp<T, 1, true, NR, true>(cs, nd, true, x[0], x[1], x[2], x[3], lv, emit, tail);
+    acc.add(0, -(double)lv[0]);
+  }
+  const int n_lds = 1 + (GRAD ? 2 * R : 0);
+  const int64_t stride = out_stride<TM>(n_rows);
+  if constexpr (TM) thread_store_acc<NC>(acc, n_lds, out, stride);
+  else row_store_acc<NC>(acc, n_lds, out, n_rows);
+  if constexpr (GRAD) {
+    if constexpr (TM) {
+#pragma unroll
+      for (int j = 0; j < kFullTail; ++j) {
+        const int col = full_tail_col(cs, fb, j);
+        if (col >= 0) out[(int64_t)(1 + 2 * R + col) * stride + threadIdx.x] = tl[j];
+      }
+    } else {
+      __shared__ double red[kBlock / 64][kFullTail];
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+      for (int j = 0; j < kFullTail; ++j) {
+        const double v = wave_sum(tl[j]);
+        if (lane == 0) red[wave][j] = v;
+      }
+      __syncthreads();
+      const int j = threadIdx.x;
+      if (j < kFullTail) {
+        const int col = full_tail_col(cs, fb, j);
+        if (col >= 0) out[(int64_t)(1 + 2 * R + col) * n_rows] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <typename T, int NS, int NCOL, int HEAVY, bool GRAD, bool TM = false>
 __device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const void* const* cols, int64_t n,
                                          int n_rows, int r, double* __restrict__ out) {
@@ -1455,6 +1684,7 @@ template <> struct LeafWaves<float, OP_TDDP> { static constexpr int value = 3; }
 template <> struct LeafWaves<float, OP_TDDP_X> { static constexpr int value = 3; };
 template <> struct LeafWaves<float, OP_TDDP_S> { static constexpr int value = 3; };
 template <> struct LeafWaves<float, OP_TDDP_XS> { static constexpr int value = 3; };
+template <> struct LeafWaves<float, OP_TDDP_F> { static constexpr int value = 2; };
 
 // TM: terms launch (one chunk per row, per-event output, see thread_store);
 // the row's output then starts at its first event's place.
@@ -1470,6 +1700,8 @@ void k_leaf(const EvalArgs a) {
   if constexpr (OP == OP_EXP || OP == OP_GAUSS)
     light_leaf_row<T, OP, GRAD, TM>(a.prog.node[0], cs, a.col, a.n_events, a.n_rows, blockIdx.x,
                                     row_out<TM>(a.partials));
+  else if constexpr (OP == OP_TDDP_F)
+    full_leaf_row<T, GRAD, TM>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, row_out<TM>(a.partials));
   else
     amp_leaf_row<T, OP, GRAD, TM>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, row_out<TM>(a.partials));
 }
@@ -1501,11 +1733,12 @@ inline hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st, hipEve
     case KIND_TDDPX: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_X, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDPS: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_S, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a); break;
     case KIND_TDDPXS: hipExtLaunchKernelGGL((k_leaf<T, OP_TDDP_XS, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a); break;
+    case KIND_TDDPF: return launch_full_leaf(std::is_same<T, float>::value, GRAD, TM, a, st, e0, e1);
     case KIND_TREE:
-      hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, 2, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a);
+      hipExtLaunchKernelGGL((k_tree<T, kMaxSlotsTree, kMaxCols, 2, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a);
       break;
     case KIND_TREE_NOAMP:
-      hipExtLaunchKernelGGL((k_tree<T, kMaxSlots, kMaxCols, 1, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a);
+      hipExtLaunchKernelGGL((k_tree<T, kMaxSlotsTree, kMaxCols, 1, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a);
       break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \

@@ -44,8 +44,8 @@ __global__ __launch_bounds__(256) void k_generate_ar(const GenArArgs a) {
         in = dp_inside(a.M, a.m1, a.m2, a.m3, s12, s13);
       }
       if (in) {
-        double dl[kMaxSlots];
-        const double p = ::exp(tree_eval<double, kMaxSlots, kMaxCols, H, false>(a.prog, cs, x, dl) - a.ln_hoist);
+        double dl[kMaxSlotsTree];
+        const double p = ::exp(tree_eval<double, kMaxSlotsTree, kMaxCols, H, false>(a.prog, cs, x, dl) - a.ln_hoist);
         if (p > a.env) flag |= 2;
         if (__dmul_rn(ua, a.env) < p) done = true;
       }
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
 
 // ------------------------------------------------------------------ dispatch
 bool kind_light(int kind) {
-  if (kind >= KIND_MIX2) return true;
+  if ((kind >= KIND_MIX2 && kind < KIND_MIX2 + 4) || kind >= KIND_MIX3) return true;
   return kind == KIND_EXP || kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
 }
 
@@ -264,8 +264,9 @@ static const void* kernel_of(int kind) {
     case KIND_TDDPX: return (const void*)&k_leaf<T, OP_TDDP_X, GRAD>;
     case KIND_TDDPS: return (const void*)&k_leaf<T, OP_TDDP_S, GRAD>;
     case KIND_TDDPXS: return (const void*)&k_leaf<T, OP_TDDP_XS, GRAD>;
-    case KIND_TREE: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, 2, GRAD>;
-    case KIND_TREE_NOAMP: return (const void*)&k_tree<T, kMaxSlots, kMaxCols, 1, GRAD>;
+    case KIND_TREE: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, 2, GRAD>;
+    case KIND_TREE_NOAMP: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, 1, GRAD>;
+    case KIND_TDDPF: return full_leaf_kernel(std::is_same<T, float>::value, GRAD);
     default: return nullptr;  // mixtures: light, never below kRowsPerCU
   }
 }
@@ -296,9 +297,9 @@ template <typename T, bool GRAD>
 static hipError_t launch_binned_t(int heavy, const EvalArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid((unsigned)a.n_rows), block(kBlock);
   if (heavy >= 2)
-    hipExtLaunchKernelGGL((k_binned<T, kMaxSlots, kMaxCols, 2, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((k_binned<T, kMaxSlotsTree, kMaxCols, 2, GRAD>), grid, block, 0, st, e0, e1, 0, a);
   else if (heavy == 1)
-    hipExtLaunchKernelGGL((k_binned<T, kMaxSlots, kMaxCols, 1, GRAD>), grid, block, 0, st, e0, e1, 0, a);
+    hipExtLaunchKernelGGL((k_binned<T, kMaxSlotsTree, kMaxCols, 1, GRAD>), grid, block, 0, st, e0, e1, 0, a);
   else
     hipExtLaunchKernelGGL((k_binned<T, 8, 2, 0, GRAD>), grid, block, 0, st, e0, e1, 0, a);
   return hipGetLastError();
@@ -324,8 +325,8 @@ static hipError_t launch_b(int kind, const BatchArgs& a, int grid, hipStream_t s
     case KIND_TDDPX: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_X>), g, b, 0, st, a); break;
     case KIND_TDDPS: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_S>), g, b, 0, st, a); break;
     case KIND_TDDPXS: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_XS>), g, b, 0, st, a); break;
-    case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, 2>), g, b, 0, st, a); break;
-    case KIND_TREE_NOAMP: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlots, kMaxCols, 1>), g, b, 0, st, a); break;
+    case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlotsTree, kMaxCols, 2>), g, b, 0, st, a); break;
+    case KIND_TREE_NOAMP: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlotsTree, kMaxCols, 1>), g, b, 0, st, a); break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
     hipLaunchKernelGGL((k_mix_batched<T, K_, M_>), g, b, 0, st, a);                                 \

@@ -31,6 +31,35 @@ static void pair_masses(const DalitzInfo& dz, int c, double& mA, double& mB, dou
   else { mA = dz.m2; mB = dz.m3; mC = dz.m1; }
 }
 
+// A resonance's kernel constants (m0^2, Kw B0^2, B0: m0 Gamma(s) = Kw B0^2
+// q^{2J+1} / (P_J(z) sqrt(s)) and B_J = B0 / sqrt(P_J(z)), with B0^2 =
+// P_J(z0), z0 = r^2 q0^2, P_0 = 1, P_1 = 1 + z, P_2 = z^2 + 3z + 9,
+// Kw = m0^2 Gamma0 / q0^{2J+1}) at mass m0 and width g0, and their
+// derivatives: d(m0^2)/dm0, d(Kw B0^2)/dm0, d ln B0/dm0 and
+// d(Kw B0^2)/dGamma0 (the mass enters through q0 as well).
+struct ResConst { double m02, kwb, sqb, dm2, dkw_m, dlb_m, dkw_g; };
+static ResConst res_consts(const DalitzInfo& dz, int pair, int J, double m0, double g0) {
+  double mA, mB, mC;
+  pair_masses(dz, pair, mA, mB, mC);
+  const double m02 = m0 * m0, thrP = (mA + mB) * (mA + mB), thrM = (mA - mB) * (mA - mB);
+  const double q02 = (m02 - thrP) * (m02 - thrM) / (4.0 * m02);
+  // q0^2 = (u - P)(u - M) / (4u), u = m0^2: dq0^2/du = (2u - P - M) / (4u) - q0^2 / u
+  const double dq02 = ((2.0 * m02 - thrP - thrM) / (4.0 * m02) - q02 / m02) * 2.0 * m0;
+  const double r2 = dz.r * dz.r, z0 = r2 * q02, dz0 = r2 * dq02;
+  double bnum = 1.0, dbnum = 0.0;
+  if (J == 1) { bnum = 1.0 + z0; dbnum = 1.0; }
+  if (J == 2) { bnum = z0 * z0 + 3.0 * z0 + 9.0; dbnum = 2.0 * z0 + 3.0; }
+  ResConst c;
+  c.m02 = m02;
+  c.kwb = m02 * g0 / std::pow(std::sqrt(q02), 2 * J + 1) * bnum;
+  c.sqb = std::sqrt(bnum);
+  c.dm2 = 2.0 * m0;
+  c.dkw_m = c.kwb * (2.0 / m0 - 0.5 * (2 * J + 1) * dq02 / q02 + dbnum / bnum * dz0);
+  c.dlb_m = 0.5 * dbnum / bnum * dz0;
+  c.dkw_g = c.kwb / g0;
+  return c;
+}
+
 
 namespace {
 
@@ -121,6 +150,18 @@ int ensure_grid(pdf_graph* g, hipStream_t st) {
   if (dz.node < 0) return HF_OK;
   std::lock_guard<std::mutex> lk(g->grid_mu);
   if (dz.ready) return HF_OK;
+  if (dz.full && !dz.fl.empty()) {
+    // floating shapes: no matrices; the grid kernel runs with every
+    // evaluation and needs its rows of partials
+    const int64_t G = dz.gs.grid, chunks = (G * G + kBlock - 1) / kBlock;
+    const int R = (int)dz.res.size();
+    const int n_col = 1 + 2 * R + 3 + (dz.hq ? 2 : 0) + 2 * (int)dz.fl.size();
+    dz.norm_rows = (int32_t)std::min<int64_t>(chunks, 1024);
+    hipError_t e = hipMalloc(&dz.norm_partials, (size_t)n_col * dz.norm_rows * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(normalisation grid partials)");
+    dz.ready = true;
+    return HF_OK;
+  }
   const int na = (int)dz.res.size() + 1, n_mat = dz.tddp ? 3 : 1;
   std::vector<double> out((size_t)n_mat * na * na * 2);
   hipError_t e = dalitz_grid_matrices(dz.gs, g->prog, dz.node, dz.tddp, out.data(), st);
@@ -585,19 +626,23 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
     const int c0 = kn.c0;
     const bool hoist = kn.hoisted != 0;
     const bool shape_only = conv_child[k] != 0;
+    // n_max: entries of the node's dlnN block (-1: one per derivative; the
+    // full time-dependent node, always hoisted, has more derivatives than
+    // entries)
     auto norm_terms = [&](double lnN, const std::vector<std::pair<int, double>>& d, int i_hi, int i_lo,
-                          int i_d0) {
+                          int i_d0, int n_max = -1) {
+      const int nd_ = n_max < 0 ? (int)d.size() : std::min((int)d.size(), n_max);
       if (shape_only) {
         set_ln(i_hi, i_lo, 0.0);
-        for (size_t j = 0; j < d.size(); ++j) setc(i_d0 + (int)j, 0.0);
+        for (int j = 0; j < nd_; ++j) setc(i_d0 + j, 0.0);
       } else if (hoist) {
         sc.ht.lnN += lnN;
         for (auto& pd : d) sc.ht.dlnN[pd.first] += pd.second;
         set_ln(i_hi, i_lo, 0.0);
-        for (size_t j = 0; j < d.size(); ++j) setc(i_d0 + (int)j, 0.0);
+        for (int j = 0; j < nd_; ++j) setc(i_d0 + j, 0.0);
       } else {
         set_ln(i_hi, i_lo, lnN);
-        for (size_t j = 0; j < d.size(); ++j) setc(i_d0 + (int)j, d[j].second);
+        for (int j = 0; j < nd_; ++j) setc(i_d0 + j, d[j].second);
       }
     };
     switch (kn.op) {
@@ -980,37 +1025,105 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
             dv.push_back({nd.par[2 * j + 1], dim[j + 1] / N});
           }
         } else {
-          // parameters: 2R coefficients, tau, y and (optionally) x
-          const bool hx = (int)nd.par.size() == 2 * R + 3;
-          const double tau = th[nd.par[2 * R]], y = th[nd.par[2 * R + 1]], x = hx ? th[nd.par[2 * R + 2]] : 0.0;
+          // parameters: 2R coefficients, tau, y and (optionally) x; the full
+          // model adds q/p = |q/p| e^{i phi} and floating masses and widths
+          const bool hx = dz.p_x >= 0;
+          const double tau = th[dz.p_tau], y = th[dz.p_y], x = hx ? th[dz.p_x] : 0.0;
           if (!(tau > 0.0) || !(std::fabs(y) < 1.0)) sc.ok = false;
-          std::vector<double> aR, aI, bR, bI, jR, jI, kR, kI;
-          const double IA = herm_form(dz.I, c, aR, aI);
-          const double IB = herm_form(dz.Ib, c, bR, bI);
-          const double X = herm_form(dz.J, c, jR, jI);     // Re c^H J c
-          const double Y = herm_form_im(dz.J, c, kR, kI);  // Im c^H J c
+          double qr = 1.0, qi = 0.0, qm = 1.0, ph = 0.0;
+          if (dz.hq) {
+            qm = th[dz.p_qm];
+            ph = th[dz.p_qa];
+            if (!(qm > 0.0) || !std::isfinite(ph)) sc.ok = false;
+            qr = qm * std::cos(ph);
+            qi = qm * std::sin(ph);
+          }
           // time integrals over the real line: int C = tau/(1-y^2),
           // int S = y tau/(1-y^2), int Cz = tau/(1+x^2), int Sz = x tau/(1+x^2)
           const double den = 1.0 - y * y, opx = 1.0 + x * x;
           const double kc = tau / den, ks = y * tau / den, kz = tau / opx, kzs = x * tau / opx;
-          const double N = 0.5 * (IA + IB) * kc + 0.5 * (IA - IB) * kz - X * ks - Y * kzs;
-          if (!(N > 0.0)) sc.ok = false;
-          lnN = std::log(N);
-          for (int j = 1; j <= R; ++j) {
-            const double dr = 0.5 * (aR[j] + bR[j]) * kc + 0.5 * (aR[j] - bR[j]) * kz - jR[j] * ks - kR[j] * kzs;
-            const double di = 0.5 * (aI[j] + bI[j]) * kc + 0.5 * (aI[j] - bI[j]) * kz - jI[j] * ks - kI[j] * kzs;
-            dv.push_back({nd.par[2 * j - 2], dr / N});
-            dv.push_back({nd.par[2 * j - 1], di / N});
+          if (dz.full) {
+            const int fb = c0 + dz_full_base(R);
+            setc(fb + kFqRe, qr);
+            setc(fb + kFqIm, qi);
+            setc(fb + kFiq, qm > 0.0 ? 1.0 / qm : 0.0);
+            setc(fb + kFhx, hx ? 1.0 : 0.0);
+            setc(fb + kFhq, dz.hq ? 1.0 : 0.0);
+            setc(fb + kFnf, (double)dz.fl.size());
+            setc(fb + kFkc, kc);
+            setc(fb + kFkz, kz);
+            setc(fb + kFks, ks);
+            setc(fb + kFkzs, kzs);
+            // floating resonances: their constants and Jacobians at theta
+            for (size_t f = 0; f < dz.fl.size(); ++f) {
+              const FloatRes& fr = dz.fl[f];
+              const double m0 = th[fr.p_m0], g0 = th[fr.p_g0];
+              double mA, mB, mC;
+              pair_masses(dz, fr.pair, mA, mB, mC);
+              if (!(m0 > mA + mB) || !(g0 > 0.0) || !std::isfinite(m0) || !std::isfinite(g0)) {
+                sc.ok = false;
+                continue;
+              }
+              const ResConst rcn = res_consts(dz, fr.pair, fr.J, m0, g0);
+              const int rb = c0 + dz_res_base(R, true) + fr.place * kResStride;
+              setc(rb + kResM02, rcn.m02);
+              setc(rb + kResKwB, rcn.kwb);
+              setc(rb + kResSqB, rcn.sqb);
+              const int lb = fb + kFlBase + (int)f * kFlStride;
+              setc(lb + kFlRes, fr.place);
+              setc(lb + kFlPair, fr.pair);
+              setc(lb + kFlJ, fr.J);
+              setc(lb + kFlDm2, rcn.dm2);
+              setc(lb + kFlDkwM, rcn.dkw_m);
+              setc(lb + kFlDlbM, rcn.dlb_m);
+              setc(lb + kFlDkwG, rcn.dkw_g);
+            }
           }
-          const double dtau = 0.5 * (IA + IB) / den + 0.5 * (IA - IB) / opx - X * y / den - Y * x / opx;
-          const double dy = 0.5 * (IA + IB) * tau * 2.0 * y / (den * den) - X * tau * (1.0 + y * y) / (den * den);
-          dv.push_back({nd.par[2 * R], dtau / N});
-          dv.push_back({nd.par[2 * R + 1], dy / N});
-          if (hx) {
-            const double dx = -0.5 * (IA - IB) * tau * 2.0 * x / (opx * opx) - Y * tau * (1.0 - x * x) / (opx * opx);
-            dv.push_back({nd.par[2 * R + 2], dx / N});
+          if (dz.full && !dz.fl.empty()) {
+            // normalisation from the grid kernel at this theta (eval_one)
+            sc.grid_norm = true;
+            sc.tint[0] = kc;
+            sc.tint[1] = kz;
+            sc.tint[2] = ks;
+            sc.tint[3] = kzs;
+          } else {
+            std::vector<double> aR, aI, bR, bI, jR, jI, kR, kI;
+            const double IA = herm_form(dz.I, c, aR, aI);
+            const double IB0 = herm_form(dz.Ib, c, bR, bI);
+            const double X0 = herm_form(dz.J, c, jR, jI);     // Re c^H J c
+            const double Y0 = herm_form_im(dz.J, c, kR, kI);  // Im c^H J c
+            // with q/p: Ibar scales by |q/p|^2, the cross term c^H J c by q/p
+            const double IB = qm * qm * IB0, X = qr * X0 - qi * Y0, Y = qr * Y0 + qi * X0;
+            const double N = 0.5 * (IA + IB) * kc + 0.5 * (IA - IB) * kz - X * ks - Y * kzs;
+            if (!(N > 0.0)) sc.ok = false;
+            lnN = std::log(N);
+            for (int j = 1; j <= R; ++j) {
+              const double br = qm * qm * bR[j], bi = qm * qm * bI[j];
+              const double xr = qr * jR[j] - qi * kR[j], yr = qr * kR[j] + qi * jR[j];
+              const double xi = qr * jI[j] - qi * kI[j], yi = qr * kI[j] + qi * jI[j];
+              const double dr = 0.5 * (aR[j] + br) * kc + 0.5 * (aR[j] - br) * kz - xr * ks - yr * kzs;
+              const double di = 0.5 * (aI[j] + bi) * kc + 0.5 * (aI[j] - bi) * kz - xi * ks - yi * kzs;
+              dv.push_back({nd.par[2 * j - 2], dr / N});
+              dv.push_back({nd.par[2 * j - 1], di / N});
+            }
+            const double dtau = 0.5 * (IA + IB) / den + 0.5 * (IA - IB) / opx - X * y / den - Y * x / opx;
+            const double dy = 0.5 * (IA + IB) * tau * 2.0 * y / (den * den) - X * tau * (1.0 + y * y) / (den * den);
+            dv.push_back({dz.p_tau, dtau / N});
+            dv.push_back({dz.p_y, dy / N});
+            if (hx) {
+              const double dx = -0.5 * (IA - IB) * tau * 2.0 * x / (opx * opx) - Y * tau * (1.0 - x * x) / (opx * opx);
+              dv.push_back({dz.p_x, dx / N});
+            }
+            if (dz.hq) {
+              // d/d|q/p|: Ibar' = 2 |q/p| Ibar0, cross' = e^{i phi} c^H J c;
+              // d/dphi: cross' = i q/p c^H J c
+              const double er = std::cos(ph), ei = std::sin(ph);
+              const double dq = (0.5 * 2.0 * qm * IB0 * (kc - kz) - (er * X0 - ei * Y0) * ks - (er * Y0 + ei * X0) * kzs);
+              dv.push_back({dz.p_qm, dq / N});
+              dv.push_back({dz.p_qa, (Y * ks - X * kzs) / N});
+            }
           }
-          const int tb = c0 + dz_time_base(R);
+          const int tb = c0 + dz_time_base(R, dz.full ? kMaxResFull : kMaxRes);
           setc(tb + kTdGm, (1.0 - y) / tau);
           setc(tb + kTdGp, (1.0 + y) / tau);
           setc(tb + kTdG, 1.0 / tau);
@@ -1023,7 +1136,7 @@ void stage(const pdf_graph* g, const double* th, hf_precision prec, StagedCall& 
           setc(tb + kTdDWTau, -x / (tau * tau));
           setc(tb + kTdDWX, hx ? 1.0 / tau : 0.0);
         }
-        norm_terms(lnN, dv, c0 + kDzLnHi, c0 + kDzLnLo, c0 + kDzDln);
+        norm_terms(lnN, dv, c0 + kDzLnHi, c0 + kDzLnLo, c0 + kDzDln, dz_n_dln(R, td));
         break;
       }
     }
@@ -1042,6 +1155,15 @@ int node_slots(const NodeInfo& n) {
     case OP_PROD: return 0;
     default: return (int)n.par.size();
   }
+}
+
+// A TDDP node of the full time-dependent model (the full constant form, or
+// more resonances than the plain kernels hold): evaluated by the full
+// kernel, as the root only.
+bool tddp_full(const NodeInfo& n) {
+  if (n.op != OP_TDDP) return false;
+  const int R = (int)n.consts[6];
+  return R > kMaxRes || (int)n.consts.size() == 8 + 5 * R;
 }
 
 // Slots of a node and everything below it (a CONV child: a leaf, or a
@@ -1074,7 +1196,7 @@ int node_consts(const std::vector<NodeInfo>& all, const NodeInfo& n) {
     case OP_POLY: return 2 * (int)n.par.size() + 3;
     case OP_ADD: return (int)n.child.size() + 1;
     case OP_DALITZ: return dz_n_const((int)n.consts[6], false);
-    default: return dz_n_const((int)n.consts[6], true);
+    default: return tddp_full(n) ? dz_n_const_full((int)n.consts[6]) : dz_n_const((int)n.consts[6], true);
   }
 }
 
@@ -1099,6 +1221,24 @@ void group_resonances(NodeInfo& n, int R) {
     for (int i = 0; i < 4; ++i) n.consts[7 + 4 * j + i] = c[7 + 4 * idx[j] + i];
     n.par[2 * j] = p[2 * idx[j]];
     n.par[2 * j + 1] = p[2 * idx[j] + 1];
+  }
+  if ((int)c.size() == 8 + 5 * R) {
+    // full form: the floating-shape flags move with their resonances, and so
+    // do the (m0, Gamma0) parameter pairs at the end of the list (given in
+    // resonance order)
+    const int fl = (int)c[7 + 4 * R];
+    const int tail0 = 2 * R + 2 + (fl & 1) + 2 * ((fl >> 1) & 1);
+    std::vector<int> pair_of(R, -1);
+    for (int j = 0, f = 0; j < R; ++j)
+      if (c[8 + 4 * R + j] == 1) pair_of[j] = f++;
+    for (int j = 0, f = 0; j < R; ++j) {
+      n.consts[8 + 4 * R + j] = c[8 + 4 * R + idx[j]];
+      if (pair_of[idx[j]] >= 0) {
+        n.par[tail0 + 2 * f] = p[tail0 + 2 * pair_of[idx[j]]];
+        n.par[tail0 + 2 * f + 1] = p[tail0 + 2 * pair_of[idx[j]] + 1];
+        ++f;
+      }
+    }
   }
 }
 
@@ -1280,10 +1420,34 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
           rc = need(n.n_child == 0 && n.n_const >= 7, "Dalitz node needs the constant block");
           if (rc) break;
           const int R = (int)ni.consts[6];
-          rc = need(R >= 1 && R <= kMaxRes && n.n_const == 7 + 4 * R, "Dalitz: 1..8 resonances, 7 + 4R constants");
-          if (!rc)
+          const int rmax = td ? kMaxResFull : kMaxRes;
+          // the full time-dependent form adds a block of 1 + R constants:
+          // flags (1: x, 2: q/p), then 1 for each resonance whose mass and
+          // width are parameters
+          const bool ext = td && R >= 1 && n.n_const == 8 + 5 * R;
+          rc = need(R >= 1 && R <= rmax && (n.n_const == 7 + 4 * R || ext),
+                    td ? "time-dependent Dalitz: 1..16 resonances, 7 + 4R (full form 8 + 5R) constants"
+                       : "Dalitz: 1..8 resonances, 7 + 4R constants");
+          if (!rc && ext) {
+            const double fl = ni.consts[7 + 4 * R];
+            rc = need(fl == 0 || fl == 1 || fl == 2 || fl == 3, "time-dependent Dalitz: flags must be 0..3");
+            int nf = 0;
+            for (int j = 0; j < R && !rc; ++j) {
+              const double v = ni.consts[8 + 4 * R + j];
+              rc = need(v == 0 || v == 1, "time-dependent Dalitz: floating-shape flags must be 0 or 1");
+              nf += v == 1;
+            }
+            if (!rc) rc = need(nf <= kMaxFloat, "time-dependent Dalitz: at most 4 resonances with floating shapes");
+            if (!rc) {
+              const int hx = ((int)fl & 1) != 0, hq = ((int)fl & 2) != 0;
+              rc = need(n.n_par == 2 * R + 2 + hx + 2 * hq + 2 * nf,
+                        "time-dependent Dalitz (full form): 2R + tau, y (+ x) (+ |q/p|, arg q/p) + 2 per "
+                        "floating resonance parameters");
+            }
+          } else if (!rc) {
             rc = need(td ? (n.n_par == 2 * R + 2 || n.n_par == 2 * R + 3) : n.n_par == 2 * R,
                       "Dalitz: 2R parameters; time-dependent: 2R + tau, y (+ x)");
+          }
           if (!rc) rc = need(n.n_obs == (td ? 4 : 2), "Dalitz: observables (s12, s13[, t, sigma_t])");
           if (!rc) rc = need(finite_box(ni.obs[0]) && finite_box(ni.obs[1]), "Dalitz: s12, s13 need finite boxes");
           if (rc) break;
@@ -1443,7 +1607,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       else for (int j = 0; j < kn.n_slot; ++j) g->slot_par.push_back(n.par[j]);
       slot += kn.n_slot;
       cst += node_consts(g->nodes, n);
-      if (slot > kMaxSlots) return fail(HF_E_GRAPH, "more than 32 gradient slots");
+      if (slot > kMaxSlots) return fail(HF_E_GRAPH, "more than 48 gradient slots");
       if (cst > kMaxConst) return fail(HF_E_GRAPH, "constant table overflow (too many resonances or nodes)");
     }
     P.n_slots = slot;
@@ -1460,6 +1624,32 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       const int R = (int)n.consts[6];
       for (int j = 0; j < R; ++j)
         dz.res.push_back({(int)n.consts[7 + 4 * j], n.consts[8 + 4 * j], n.consts[9 + 4 * j], (int)n.consts[10 + 4 * j]});
+      if (dz.tddp) {
+        dz.p_tau = n.par[2 * R];
+        dz.p_y = n.par[2 * R + 1];
+      }
+      if (tddp_full(n)) {
+        if (NN != 1) return fail(HF_E_GRAPH, "the full time-dependent Dalitz node must be the graph's only node");
+        dz.full = true;
+        const bool ext = (int)n.consts.size() == 8 + 5 * R;
+        const int flags = ext ? (int)n.consts[7 + 4 * R] : ((int)n.par.size() == 2 * R + 3 ? 1 : 0);
+        dz.hx = (flags & 1) != 0;
+        dz.hq = (flags & 2) != 0;
+        int q = 2 * R + 2;
+        if (dz.hx) dz.p_x = n.par[q++];
+        if (dz.hq) {
+          dz.p_qm = n.par[q++];
+          dz.p_qa = n.par[q++];
+        }
+        for (int j = 0; ext && j < R; ++j)
+          if (n.consts[8 + 4 * R + j] == 1) {
+            const int ch = (int)n.consts[7 + 4 * j];
+            dz.fl.push_back({j, ch == 12 ? 0 : (ch == 13 ? 1 : 2), (int)n.consts[10 + 4 * j], n.par[q], n.par[q + 1]});
+            q += 2;
+          }
+      } else if (dz.tddp && (int)n.par.size() == 2 * R + 3) {
+        dz.p_x = n.par[2 * R + 2];
+      }
       const double lo12 = (dz.m1 + dz.m2) * (dz.m1 + dz.m2), hi12 = (dz.M - dz.m3) * (dz.M - dz.m3);
       const double lo13 = (dz.m1 + dz.m3) * (dz.m1 + dz.m3), hi13 = (dz.M - dz.m2) * (dz.M - dz.m2);
       dz.gs = GridSpec{lo12, (hi12 - lo12) / dz.grid, lo13, (hi13 - lo13) / dz.grid, dz.M, dz.m1, dz.m2, dz.m3, dz.grid};
@@ -1486,20 +1676,11 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       for (int j = 0; j < R; ++j) {
         const ResInfo& r = dz.res[j];
         const int c = r.ch == 12 ? 0 : (r.ch == 13 ? 1 : 2);
-        double mA, mB, mC;
-        pair_masses(dz, c, mA, mB, mC);
         const int rb = rbase + j * kResStride;
-        const double m02 = r.m0 * r.m0;
-        const double thrP = (mA + mB) * (mA + mB), thrM = (mA - mB) * (mA - mB);
-        const double q02 = (m02 - thrP) * (m02 - thrM) / (4.0 * m02);
-        const double q0 = std::sqrt(q02);
-        const double z0 = dz.r * dz.r * q02;
-        double bnum = 1.0;
-        if (r.J == 1) bnum = 1.0 + z0;
-        if (r.J == 2) bnum = z0 * z0 + 3.0 * z0 + 9.0;
-        setc(rb + kResM02, m02);
-        setc(rb + kResKwB, m02 * r.g0 / std::pow(q0, 2 * r.J + 1) * bnum);
-        setc(rb + kResSqB, std::sqrt(bnum));
+        const ResConst rcn = res_consts(dz, c, r.J, r.m0, r.g0);
+        setc(rb + kResM02, rcn.m02);
+        setc(rb + kResKwB, rcn.kwb);
+        setc(rb + kResSqB, rcn.sqb);
       }
     }
     // the generic slot layout (the tree interpreter's, used by binned datasets)
@@ -1544,6 +1725,7 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     if (NN == 1 && rootn.op == OP_EXP) g->kind = KIND_EXP;
     else if (NN == 1 && rootn.op == OP_GAUSS) g->kind = KIND_GAUSS;
     else if (NN == 1 && rootn.op == OP_DALITZ) g->kind = KIND_DALITZ;
+    else if (NN == 1 && rootn.op == OP_TDDP && g->dz.full) g->kind = KIND_TDDPF;
     else if (NN == 1 && rootn.op == OP_TDDP)
       g->kind = (int)rootn.par.size() == 2 * (int)rootn.consts[6] + 3 ? KIND_TDDPX : KIND_TDDP;
     else if (NN >= 5 && rootn.op == OP_PROD && rootn.child.size() == 2 && P.node[0].op == OP_TDDP &&
@@ -1553,6 +1735,8 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       g->kind = (int)g->nodes[0].par.size() == 2 * (int)g->nodes[0].consts[6] + 3 ? KIND_TDDPXS : KIND_TDDPS;
     else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2 && NN <= 8) g->kind = KIND_TREE_SMALL;
     else g->kind = g->dz.node >= 0 ? KIND_TREE : KIND_TREE_NOAMP;
+    if ((g->kind == KIND_TREE || g->kind == KIND_TREE_NOAMP) && P.n_slots > kMaxSlotsTree)
+      return fail(HF_E_GRAPH, "more than 32 gradient slots in a tree of several nodes");
     *out = g.release();
     return HF_OK;
   } catch (const std::exception& e) {

@@ -12,8 +12,9 @@
 // only on the resonance shapes, so it is computed once per graph.
 //
 // Pass 1: a block takes 128 cells of one grid row, evaluates their
-// amplitudes into LDS, and n_mat * na^2 threads each sum one matrix element
-// over those cells.  Pass 2: one block per matrix element sums the row
+// amplitudes into LDS, and its threads each sum matrix elements (n_mat *
+// na^2 of them, so more than one per thread beyond 15 resonances) over
+// those cells.  Pass 2: one block per matrix element sums the row
 // partials in a fixed order.  Both passes are deterministic.
 #include <hip/hip_runtime.h>
 
@@ -35,12 +36,13 @@ struct GridArgs {
   double2* part;     // [row * n_chunks + chunk][n_mat * na * na]
 };
 
+template <int NR>
 __global__ __launch_bounds__(kBlock) void k_grid_rows(const GridArgs a) {
   const int na = a.R + 1;
   const int n_mat = a.tddp ? 3 : 1;
   const int row = blockIdx.x / a.n_chunks, chunk = blockIdx.x % a.n_chunks;
-  __shared__ double2 sa[kGridCells][kMaxRes + 1];
-  __shared__ double2 sb[kGridCells][kMaxRes + 1];
+  __shared__ double2 sa[kGridCells][NR + 1];
+  __shared__ double2 sb[kGridCells][NR + 1];
   const CS cs{a.prog.c64, a.prog.c32};
   const int t = threadIdx.x;
   if (t < kGridCells) {
@@ -53,11 +55,11 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows(const GridArgs a) {
       s13 = a.gs.lo13 + ((double)col + 0.5) * a.gs.h13;
       in = dp_inside(a.gs.M, a.gs.m1, a.gs.m2, a.gs.m3, s12, s13);
     }
-    AmpArr<double> a0, b0;
+    AmpArr<double, NR> a0, b0;
     if (in) {
       const double p12[1] = {s12}, p13[1] = {s13}, p23[1] = {cs.d[a.c0 + kDzSsum] - s12 - s13};
-      if (a.tddp) dalitz_amps<double, true, 1>(cs, a.prog.node[a.node], p12, p13, p23, a0, a0, b0, b0);
-      else dalitz_amps<double, false, 1>(cs, a.prog.node[a.node], p12, p13, p23, a0, a0, b0, b0);
+      if (a.tddp) dalitz_amps<double, true, 1, NR>(cs, a.prog.node[a.node], p12, p13, p23, a0, a0, b0, b0);
+      else dalitz_amps<double, false, 1, NR>(cs, a.prog.node[a.node], p12, p13, p23, a0, a0, b0, b0);
     }
     sa[t][0] = make_double2(in ? 1.0 : 0.0, 0.0);
     sb[t][0] = sa[t][0];
@@ -68,8 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows(const GridArgs a) {
   }
   __syncthreads();
   const int n_el = n_mat * na * na;
-  if (t < n_el) {
-    const int w = t / (na * na), pq = t % (na * na), p = pq / na, q = pq % na;
+  for (int el = t; el < n_el; el += kBlock) {
+    const int w = el / (na * na), pq = el % (na * na), p = pq / na, q = pq % na;
     double re = 0.0, im = 0.0;
     for (int c = 0; c < kGridCells; ++c) {
       const double2 x = (w == 1) ? sb[c][p] : sa[c][p];
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_rows(const GridArgs a) {
       re += x.x * y.x + x.y * y.y;
       im += x.x * y.y - x.y * y.x;
     }
-    a.part[(int64_t)blockIdx.x * n_el + t] = make_double2(re, im);
+    a.part[(int64_t)blockIdx.x * n_el + el] = make_double2(re, im);
   }
 }
 
@@ -135,7 +137,8 @@ hipError_t dalitz_grid_matrices(const GridSpec& gs, const KProgram& prog, int no
   e = hipMalloc(&out, (size_t)n_el * sizeof(double2));
   if (e != hipSuccess) { hipFree(part); return e; }
   a.part = part;
-  hipLaunchKernelGGL(k_grid_rows, dim3(n_rows), dim3(kBlock), 0, st, a);
+  if (R > kMaxRes) hipLaunchKernelGGL(k_grid_rows<kMaxResFull>, dim3(n_rows), dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL(k_grid_rows<kMaxRes>, dim3(n_rows), dim3(kBlock), 0, st, a);
   e = hipGetLastError();
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_grid_sum, dim3(n_el), dim3(kBlock), 0, st, part, n_rows, n_el, out);

@@ -18,9 +18,12 @@ namespace hf {
 constexpr int kBlock = 256;          // threads per block (4 wave64)
 constexpr int kMaxNodes = 16;
 constexpr int kMaxCols = 8;
-constexpr int kMaxSlots = 32;
-constexpr int kMaxConst = 176;
-constexpr int kMaxRes = 8;
+constexpr int kMaxSlots = 48;       // gradient slots of a graph
+constexpr int kMaxSlotsTree = 32;   // ... evaluated by the tree interpreter
+constexpr int kMaxConst = 192;
+constexpr int kMaxRes = 8;          // resonances of DALITZ / TDDP nodes in the plain kernels
+constexpr int kMaxResFull = 16;     // ... of the full time-dependent kernel (the mixing fit)
+constexpr int kMaxFloat = 4;        // resonances with floating mass and width
 constexpr int kMaxPar = 64;
 constexpr int kNumGroups = 9;        // (pair, spin) groups of Dalitz resonances
 
@@ -105,11 +108,30 @@ constexpr int kTdGm = 0, kTdGp = 1, kTdG = 2, kTdDGmTau = 3, kTdDGpTau = 4, kTdD
 constexpr int dz_n_dln(int R, bool tddp) { return 2 * R + (tddp ? 3 : 0); }
 constexpr int dz_ch_base(int R, bool tddp) { return kDzDln + dz_n_dln(R, tddp); }
 constexpr int dz_res_base(int R, bool tddp) { return dz_ch_base(R, tddp) + kNumCh * kChStride; }
-// the coefficient block always has room for kMaxRes coefficients; those of
-// absent resonances stay zero, so the kernels sum over all kMaxRes
+// the coefficient block always has room for NR coefficients (NR = kMaxRes,
+// or kMaxResFull for the full model); those of absent resonances stay zero,
+// so the kernels sum over all NR places
 constexpr int dz_coef_base(int R, bool tddp) { return dz_res_base(R, tddp) + R * kResStride; }
-constexpr int dz_time_base(int R) { return dz_coef_base(R, true) + 2 * kMaxRes; }
+constexpr int dz_time_base(int R, int NR = kMaxRes) { return dz_coef_base(R, true) + 2 * NR; }
 constexpr int dz_n_const(int R, bool tddp) { return dz_coef_base(R, tddp) + 2 * kMaxRes + (tddp ? kTdCount : 0); }
+
+// Full time-dependent model (the mixing fit: up to kMaxResFull resonances,
+// complex q/p, floating masses and widths), after the time constants:
+//   kFqRe, kFqIm   q/p (1, 0 without q/p);  kFiq  1 / |q/p|
+//   kFhx, kFhq     1.0 when x (q/p) is a parameter;  kFnf  floating resonances
+//   kFkc..kFkzs    time integrals of C, Cz, S, Sz over the real line
+//   then per floating resonance f (stride kFlStride): its place, pair
+//   (0, 1, 2 for 12, 13, 23) and spin, d(m0^2)/dm0, d(Kw B0^2)/dm0,
+//   d ln B0/dm0 and d(Kw B0^2)/dGamma0
+constexpr int kFqRe = 0, kFqIm = 1, kFiq = 2, kFhx = 3, kFhq = 4, kFnf = 5, kFkc = 6, kFkz = 7, kFks = 8,
+              kFkzs = 9, kFlBase = 10;
+constexpr int kFlRes = 0, kFlPair = 1, kFlJ = 2, kFlDm2 = 3, kFlDkwM = 4, kFlDlbM = 5, kFlDkwG = 6, kFlStride = 7;
+constexpr int dz_full_base(int R) { return dz_time_base(R, kMaxResFull) + kTdCount; }
+constexpr int dz_n_const_full(int R) { return dz_full_base(R) + kFlBase + kFlStride * kMaxFloat; }
+// slots of a full node: 2R coefficients, tau, y, (x), (|q/p|, arg q/p), then
+// (m0, Gamma0) per floating resonance; at most this many after the
+// coefficients
+constexpr int kFullTail = 5 + 2 * kMaxFloat;
 
 // Arguments of one evaluation launch over one dataset.
 struct EvalArgs {

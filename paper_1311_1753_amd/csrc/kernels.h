@@ -18,6 +18,7 @@ enum KernelKind {
   KIND_TDDPS = 7,       // PROD of a TDDP leaf (x = 0) and a DPMAP on its s12, s13, sigma_t
   KIND_TDDPXS = 12,     // the same with x free
   KIND_TREE_NOAMP = 13, // any tree without DALITZ / TDDP nodes (the general interpreter minus the amplitude code)
+  KIND_TDDPF = 14,      // single TDDP leaf of the full model (up to 16 resonances, q/p, floating shapes)
   // root ADD of 2 (3) single-column EXP/GAUSS leaves: KIND_MIX2 (KIND_MIX3)
   // plus a mask with bit j set when child j is a GAUSS
   KIND_MIX2 = 8,
@@ -104,5 +105,22 @@ struct GridSpec {
 };
 hipError_t dalitz_grid_matrices(const GridSpec& gs, const KProgram& prog, int node, bool tddp, double* out_host,
                                 hipStream_t st);
+
+// The full time-dependent model: its likelihood kernels (tm: terms launch)
+// and, with floating resonance shapes, the grid normalisation at the
+// current parameters (see full_kernels.hip): partials receive
+// [|A|^2, 2R coefficient derivatives, |Abar'|^2, a_s, b_s, (|q/p|, arg q/p),
+// (m0, Gamma0 per floating resonance)] per row, before the cell area.
+struct NormArgs {
+  KProgram prog;      // the evaluation's constants, column references 0
+  GridSpec gs;
+  double* partials;   // [column][row]
+  int32_t n_rows;
+};
+static_assert(sizeof(NormArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+hipError_t launch_full_leaf(bool fp32, bool grad, bool tm, const EvalArgs& a, hipStream_t st, hipEvent_t e0,
+                            hipEvent_t e1);
+const void* full_leaf_kernel(bool fp32, bool grad);
+hipError_t launch_full_norm(bool grad, const NormArgs& a, hipStream_t st);
 
 }  // namespace hf

@@ -75,6 +75,9 @@ extern "C" int nll_grad_noalloc(const pdf_graph* g, void* const* dev_cols, int64
       if (g->prog.node[k].op == OP_CONV)
         return fail(HF_E_INVALID, "nll_grad_noalloc: graphs with a convolution need their events sorted "
                                   "(use dataset_upload)");
+    if (g->dz.full && !g->dz.fl.empty())
+      return fail(HF_E_INVALID, "nll_grad_noalloc: floating resonance shapes re-compute the normalisation grid "
+                                "with every evaluation (use nll_grad on an uploaded dataset)");
     if (g->dz.node >= 0 && !g->dz.ready)
       return fail(HF_E_INVALID, "nll_grad_noalloc: the Dalitz normalisation grid is not computed yet (it is, "
                                 "once, by the first nll_eval / nll_grad / fit on a dataset of this graph)");

@@ -28,6 +28,10 @@ struct NodeInfo {
 
 // Resonance description (Dalitz nodes).
 struct ResInfo { int ch; double m0, g0; int J; };
+// A resonance of the full time-dependent model whose mass and width are
+// parameters: its place in the grouped order, pair (0, 1, 2 for 12, 13,
+// 23), spin and the two parameter indices.
+struct FloatRes { int place, pair, J, p_m0, p_g0; };
 
 struct DalitzInfo {
   int node = -1;          // index of the DALITZ / TDDP node
@@ -39,6 +43,15 @@ struct DalitzInfo {
   bool ready = false;     // matrices computed
   // I, Ibar, J (na x na complex, area included), row-major
   std::vector<double> I, Ib, J;
+  // full time-dependent model (KIND_TDDPF): x and q/p present, their
+  // parameters, the floating resonances; with floating shapes the
+  // normalisation is the grid kernel's sum at every evaluation, over
+  // norm_rows rows of partials (device, allocated with the first call)
+  bool full = false, hx = false, hq = false;
+  int p_tau = -1, p_y = -1, p_x = -1, p_qm = -1, p_qa = -1;
+  std::vector<FloatRes> fl;
+  double* norm_partials = nullptr;
+  int32_t norm_rows = 0;
 };
 
 // Host-side terms added after the device reduction (normalisations of the
@@ -62,6 +75,8 @@ struct StagedCall {
   KProgram prog;                    // structure + constants for this call
   HostTerms ht;
   bool ok = true;                   // false: parameters outside the density's domain
+  bool grid_norm = false;           // the full model's normalisation comes from the grid kernel
+  double tint[4] = {0, 0, 0, 0};    // ... with these time integrals kc, kz, ks, kzs
 };
 
 }  // namespace hf
@@ -82,6 +97,9 @@ struct pdf_graph {
   hf::DalitzInfo dz;
   hf::MixInfo mix;
   std::mutex grid_mu;
+  ~pdf_graph() {
+    if (dz.norm_partials) (void)hipFree(dz.norm_partials);
+  }
 };
 
 struct dataset {

@@ -226,6 +226,58 @@ static void graphs() {
     stage_both(g);
     pdf_graph_destroy(g);
 
+    // the full form: x and q/p (flags 3), the second resonance's mass and
+    // width as parameters (given after |q/p|, arg q/p), with and without
+    // floating shapes; a bad flag and a wrong parameter count are errors
+    Spec f = t;
+    f.consts.clear();
+    f.op.clear();
+    f.child.clear();
+    f.pars.clear();
+    f.obsi.clear();
+    f.par.push_back(P("qm", 0.9, 0.01, 0.5, 1.5));
+    f.par.push_back(P("qa", 0.2, 0.01, -1.0, 1.0));
+    f.par.push_back(P("m0", 0.89, 0.002, 0.8, 0.95));
+    f.par.push_back(P("g0", 0.05, 0.002, 0.03, 0.08));
+    std::vector<double> fc = dalitz_consts(true);
+    fc.push_back(3);
+    fc.insert(fc.end(), {0, 1, 0});
+    f.add(HF_OP_TDDP, {}, {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12}, {0, 1, 2, 3}, fc);
+    CHECK(f.create(&g) == HF_OK);
+    CHECK(g->dz.full && g->dz.hq && g->dz.hx && g->dz.fl.size() == 1);
+    stage_both(g);
+    {
+      // floating shapes: staging leaves the normalisation to the grid kernel
+      using namespace hf;
+      std::vector<double> th(g->par.size());
+      for (size_t p = 0; p < th.size(); ++p) th[p] = g->par[p].init;
+      StagedCall sc;
+      stage(g, th.data(), HF_FP32_EVAL, sc, false);
+      CHECK(sc.ok && sc.grid_norm);
+      th[11] = 0.2;  // mass below the K pi threshold
+      stage(g, th.data(), HF_FP64, sc, false);
+      CHECK(!sc.ok);
+    }
+    pdf_graph_destroy(g);
+    f.op.clear();
+    f.child.clear();
+    f.pars.clear();
+    f.obsi.clear();
+    f.consts.clear();
+    fc[fc.size() - 2] = 0;  // no floating shape: the q/p matrices path
+    f.add(HF_OP_TDDP, {}, {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10}, {0, 1, 2, 3}, fc);
+    CHECK(f.create(&g) == HF_OK);
+    stage_both(g);
+    pdf_graph_destroy(g);
+    f.op.clear();
+    f.child.clear();
+    f.pars.clear();
+    f.obsi.clear();
+    f.consts.clear();
+    fc[fc.size() - 4] = 7;  // flags 0..3 only
+    f.add(HF_OP_TDDP, {}, {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10}, {0, 1, 2, 3}, fc);
+    CHECK(f.create(&g) == HF_E_GRAPH);
+
     Spec u = s;
     u.op.clear();
     u.child.clear();

@@ -9,7 +9,8 @@
 namespace hf {
 
 bool kind_light(int kind) {
-  return kind >= KIND_MIX2 || kind == KIND_EXP || kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
+  return (kind >= KIND_MIX2 && kind < KIND_MIX2 + 4) || kind >= KIND_MIX3 || kind == KIND_EXP ||
+         kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
 }
 int resident_blocks_per_cu(int, bool) { return 0; }
 hipError_t launch_eval(int, bool, bool, const EvalArgs&, hipStream_t, hipEvent_t, hipEvent_t) {
@@ -26,6 +27,11 @@ hipError_t launch_eval_batched(int, bool, const KProgram&, const BatchHeader*, c
   return hipErrorNotSupported;
 }
 hipError_t launch_generate(const GenArgs&, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_full_leaf(bool, bool, bool, const EvalArgs&, hipStream_t, hipEvent_t, hipEvent_t) {
+  return hipErrorNotSupported;
+}
+const void* full_leaf_kernel(bool, bool) { return nullptr; }
+hipError_t launch_full_norm(bool, const NormArgs&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_generate_ar(const GenArArgs&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t dalitz_grid_matrices(const GridSpec&, const KProgram&, int, bool, double*, hipStream_t) {
   return hipErrorNotSupported;

@@ -53,7 +53,13 @@ FP64_PEAK_TFLOPS = 78.6
 # its two slots (~12 flops + 0 T).  conv: per grid term in the residual
 # window (about 40 % of the 400 points) ~15 flops + 2 T; conv_poly: 10 % of
 # 256 points; conv_gmix: two Gaussian components per term (~25 flops + 2 T)
-# over about 60 % of 400 points.
+# over about 60 % of 400 points.  c4f (the full mixing model: 15
+# resonances, q/p, two floating shapes): amplitudes and swapped amplitudes
+# (2 x (45 + 15 x 15)), coefficient sums (2 x 15 x 8), time factors and rate
+# (~100 + 4 T), a 39-slot adjoint (~30 x 20) and the floating-shape
+# derivatives (2 x 2 x ~80): ~1800 flops + 40 T per event; its grid
+# normalisation (the same evaluation without the time factors at every
+# cell inside the plot) runs once per evaluation beside it.
 WORK = {
     "c1": {"bound": "hbm"}, "c2": {"bound": "hbm"}, "mapped": {"bound": "hbm"}, "mapped_sum": {"bound": "hbm"},
     "shared": {"bound": "hbm"}, "shared_sum": {"bound": "hbm"}, "c1l": {"bound": "hbm"}, "c2l": {"bound": "hbm"},
@@ -61,7 +67,7 @@ WORK = {
     "c3": {"bound": "alu", "flops": 330.0}, "c4": {"bound": "alu", "flops": 700.0},
     "c4x": {"bound": "alu", "flops": 740.0}, "c4s": {"bound": "alu", "flops": 712.0},
     "conv": {"bound": "alu", "flops": 160 * 15.0}, "conv_poly": {"bound": "alu", "flops": 26 * 15.0},
-    "conv_gmix": {"bound": "alu", "flops": 240 * 25.0},
+    "conv_gmix": {"bound": "alu", "flops": 240 * 25.0}, "c4f": {"bound": "alu", "flops": 1800.0},
 }
 
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE /
@@ -102,12 +108,13 @@ def parse():
                     help="skip the oracle's fit timings on the C1-C4 workloads (part of the CPU leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB device buffer 5 times (reference for the HBM byte counters)")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4x", "c4s", "mapped", "mapped_sum",
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4x", "c4s", "c4f", "mapped", "mapped_sum",
                              "shared", "shared_sum", "conv", "conv_poly", "conv_gmix", "comp", "c1l", "c2l"],
                     help="c2 (default): composite Gauss+exp, the metric's workload; c1 exponential, "
                          "c3 Dalitz amplitude sum, c4 time-dependent Dalitz (c4x with x free: the "
                          "trigonometric terms; c4s times the sigma_t density that varies across "
-                         "the plot), mapped / mapped_sum the piecewise density (alone / "
+                         "the plot; c4f the full mixing model: 16 amplitudes, q/p, floating "
+                         "resonance shapes), mapped / mapped_sum the piecewise density (alone / "
                          "added to an exponential, 1e7 events), shared / shared_sum a Gaussian times "
                          "an acceptance polynomial on the same observable (alone / added to an "
                          "exponential, 1e7 events), conv / conv_poly numerical convolutions "
@@ -361,7 +368,7 @@ def other_workload(args, P, S, torch, stream):
         data = {"x": np.random.default_rng(spec["seed"]).uniform(0.1 if base == "conv_poly" else 0.0, 10.0, n)}
     else:
         data = S.gen_flat_box(n, spec["seed"], g.dalitz_inside)
-        if args.workload in ("c4", "c4x", "c4s"):
+        if args.workload in ("c4", "c4x", "c4s", "c4f"):
             rng = np.random.default_rng(spec["seed"] + 100)
             st = rng.uniform(0.02, 0.2, n)
             data["sigma_t"] = st

@@ -94,7 +94,21 @@ enum hf_op {
                         (section "Results": hyperbolic and trigonometric terms); t is
                         normalised over the real line; obs = {s12, s13, t, sigma_t};
                         par = {Re c_1, Im c_1, ..., tau, y} (x = 0: Cz = E(t; 1/tau), Sz = 0)
-                        or {..., tau, y, x}; consts = DALITZ block                          */,
+                        or {..., tau, y, x}; consts = DALITZ block.
+                        Full form (the mixing fit of section "Results": up to 16 resonances,
+                        complex q/p, floating resonance shapes): the DALITZ block followed by
+                        flags (1: x is a parameter, 2: q/p is) and R floating-shape flags
+                        (1: resonance k's mass and width are parameters); par = {2R
+                        coefficients, tau, y, (x), (|q/p|, arg q/p), then (m0, Gamma0) of each
+                        floating resonance in resonance order}; at most 4 floating.  q/p
+                        multiplies the conjugate amplitude: Abar -> (q/p) Abar in every term
+                        above and in N_T.  With floating shapes N_T is re-computed on the grid
+                        at every evaluation (grid kernel, FP64) instead of from the cached
+                        grid matrices.  A full-form node (or a TDDP node with more than 8
+                        resonances) must be the graph's only node; binned datasets,
+                        nll_grad_batched, the batch engine and nll_grad_noalloc with floating
+                        shapes reject it (HF_E_GRAPH / HF_E_INVALID).  Domain: |q/p| > 0,
+                        m0 above the pair's threshold, Gamma0 > 0 (else HF_E_DOMAIN)    */,
   HF_OP_MAP = 8      /* piecewise density (section "Combining functions": MappedPdf):
                         P(x) = P_j(x) / Z for x in the j-th of the K ranges [lo, b_1),
                         [b_1, b_2), ..., [b_{K-1}, hi] of observable x's box; children = K >= 2
@@ -142,7 +156,8 @@ enum hf_op {
  * M: parent mass; m1..m3: daughter masses (GeV); r: Blatt-Weisskopf radius
  * (1/GeV); G: normalisation grid size (G x G midpoint cells over the box
  * [(m1+m2)^2, (M-m3)^2] x [(m1+m3)^2, (M-m2)^2], a cell counting when its
- * centre is inside the plot in both orderings); R <= 8 resonances; channel
+ * centre is inside the plot in both orderings); R <= 8 resonances (16 for a
+ * TDDP node; the full form appends 1 + R constants, see HF_OP_TDDP); channel
  * 12, 13 or 23 (pair of daughters); J in {0, 1, 2}.  Amplitude of a
  * resonance: B_J(q) Z_J BW(s_AB) with the mass-dependent width
  * Gamma(s) = Gamma0 (q/q0)^{2J+1} (m0/sqrt s) B_J^2, Blatt-Weisskopf ratios

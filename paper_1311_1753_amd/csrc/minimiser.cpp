@@ -222,27 +222,31 @@ void Minimiser::begin_line() {
   phase_ = LINE;
 }
 
+// Step of the final Hessian's central differences for parameter j with error
+// scale s: a tenth of it (the NLL is close to quadratic over that range, and
+// the step is large against rounding noise in the gradient), above the
+// parameter's rounding in the evaluation (relative precision eps: kept below
+// 1e-4 of the step) and at most a quarter of the distance to a bound.
+double Minimiser::hess_step(int j, double s) const {
+  if (!(s > 0.0) || !std::isfinite(s)) s = ps_[j].step;
+  double h = 0.1 * s;
+  h = std::max(h, 1e-12 * (std::fabs(x_best[j]) + 1.0));
+  const double eps = o_.param_eps > 0.0 ? o_.param_eps : (o_.param_eps < 0.0 ? 0.0 : ps_[j].eps);
+  h = std::max(h, 1e4 * eps * std::fabs(x_best[j]));
+  if (bounded(ps_[j])) h = std::min(h, 0.25 * std::min(x_best[j] - ps_[j].lo, ps_[j].hi - x_best[j]));
+  return h;
+}
+
 void Minimiser::begin_final() {
   if (!o_.want_errors) {
     finish(status == RUNNING ? CONVERGED : status);
     return;
   }
+  // first pass: steps from the variable metric's (marginal) errors
   hstep_.assign(nf_, 0.0);
-  for (int k = 0; k < nf_; ++k) {
-    const int j = free_[k];
-    double s = sigma_ext(j);
-    if (!(s > 0.0) || !std::isfinite(s)) s = ps_[j].step;
-    // a tenth of the error: the NLL is close to quadratic over that range, and
-    // the step is large against rounding noise in the gradient
-    double h = 0.1 * s;
-    h = std::max(h, 1e-12 * (std::fabs(x_best[j]) + 1.0));
-    // when the evaluation rounds the parameter (relative precision eps),
-    // keep that rounding below 1e-4 of the step
-    const double eps = o_.param_eps > 0.0 ? o_.param_eps : (o_.param_eps < 0.0 ? 0.0 : ps_[j].eps);
-    h = std::max(h, 1e4 * eps * std::fabs(x_best[j]));
-    if (bounded(ps_[j])) h = std::min(h, 0.25 * std::min(x_best[j] - ps_[j].lo, ps_[j].hi - x_best[j]));
-    hstep_[k] = h;
-  }
+  for (int k = 0; k < nf_; ++k) hstep_[k] = hess_step(free_[k], sigma_ext(free_[k]));
+  h_refined_ = false;
+  H1_.clear();
   Hcols_.assign((size_t)nf_ * nf_, 0.0);
   k_ = 0;
   phase_ = FINAL_H;
@@ -388,6 +392,39 @@ void Minimiser::tell(double f, const std::vector<double>& g) {
       Hext_.assign((size_t)nf_ * nf_, 0.0);
       for (int i = 0; i < nf_; ++i)
         for (int j = 0; j < nf_; ++j) Hext_[i * nf_ + j] = 0.5 * (Hcols_[i * nf_ + j] + Hcols_[j * nf_ + i]);
+      if (!h_refined_) {
+        // second pass where a parameter's conditional error sqrt(2 up / H_jj)
+        // is much smaller than its marginal one (strongly correlated
+        // parameters): the first steps were long against the range over
+        // which the NLL is quadratic along that parameter alone
+        h_refined_ = true;
+        bool again = false;
+        std::vector<double> hn(nf_);
+        for (int k = 0; k < nf_; ++k) {
+          const double hkk = Hext_[k * nf_ + k];
+          hn[k] = hkk > 0.0 && std::isfinite(hkk) ? hess_step(free_[k], std::sqrt(2.0 * o_.up / hkk)) : hstep_[k];
+          again = again || hn[k] < 0.5 * hstep_[k];
+        }
+        if (again) {
+          H1_ = Hext_;
+          hstep_ = hn;
+          k_ = 0;
+          return;
+        }
+      } else if (!H1_.empty()) {
+        // the shorter steps cost more rounding noise in the gradient; they
+        // are kept only where they change an error by more than 1 % (the
+        // NLL is not quadratic over the first steps), else the first
+        // pass's Hessian stands
+        std::vector<double> C1, C2;
+        if (spd_inverse(H1_, nf_, C1) && spd_inverse(Hext_, nf_, C2)) {
+          double dmax = 0.0;
+          for (int a = 0; a < nf_; ++a)
+            dmax = std::max(dmax, std::fabs(std::sqrt(C2[a * nf_ + a] / C1[a * nf_ + a]) - 1.0));
+          if (!(dmax > 1e-2)) Hext_ = H1_;
+        }
+        H1_.clear();
+      }
       std::vector<double> C;
       if (!spd_inverse(Hext_, nf_, C)) {
         Hext_.clear();

@@ -68,6 +68,9 @@ class Minimiser {
   int n_back_ = 0, n_ext_ = 0, n_fail_ = 0;
   int k_ = 0;                        // column counter for Hessians
   std::vector<double> hstep_, Hcols_, gplus_;
+  bool h_refined_ = false;  // the final Hessian's second pass (conditional-error steps) was taken
+  std::vector<double> H1_;  // the first pass's Hessian while the second runs
+  double hess_step(int j, double s) const;
   std::vector<double> x_pend_;       // point handed out by ask()
   int polish_ = 0;
   double edm_polish_ = 0.0;          // EDM before the last Newton polish

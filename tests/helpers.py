@@ -12,14 +12,29 @@ import numpy as np
 import synthgen as S
 
 
+def full_fit_spec():
+    """The full time-dependent model (15 resonances and the non-resonant
+    term, x, y, complex q/p, two floating shapes) at a test size: a 200 x 200
+    normalisation grid, mixing parameters y = 0.1, x = 0.08 so that q/p is
+    constrained by 5 x 10^4 events, starts at y = 0.09, x = 0.07."""
+    sp = S.configs._full_model(grid=200, n_events=50_000, seed=9)
+    sp["name"] = "c4f_fit"
+    sp["truth"] = dict(sp["truth"], y=0.1, x=0.08)
+    start = {"y": 0.09, "x": 0.07}
+    sp["params"] = [(p[0], start.get(p[0], p[1])) + tuple(p[2:]) for p in sp["params"]]
+    return sp
+
+
 def spec(name):
+    if name == "c4f_fit":
+        return full_fit_spec()
     return copy.deepcopy(S.workload(name))
 
 
 @functools.lru_cache(maxsize=None)
 def _oracle_model(name):
     from oracle import oracle as O
-    return O.Model(S.workload(name))
+    return O.Model(spec(name))
 
 
 def oracle_model(name):
@@ -50,9 +65,9 @@ def gen_data(name, n, seed):
         cells = (S.SIGMA_T_BOUNDS[0], S.SIGMA_T_BOUNDS[1], S.SIGMA_T_CELLS)
         return S.gen_accept_reject_tddp(n, seed, lambda x, yy, t: m.tddp_rate(th, x, yy, t), env, th[-2], th[-1],
                                         batch=1 << 18, sigma_t_cells=cells)
-    if name in ("c3", "c4", "c4x"):
+    if name in ("c3", "c4", "c4x", "c4f_fit"):
         m = oracle_model(name)
-        th = m.theta(S.workload(name)["truth"])
+        th = m.theta(spec(name)["truth"])
         lo, hi = S.dalitz_box()
         G = 200
         c = lo + (np.arange(G) + 0.5) * (hi - lo) / G
@@ -65,7 +80,7 @@ def gen_data(name, n, seed):
         b2 = m.dalitz_amp2(th, a.ravel(), b.ravel(), swapped=True)
         # the rate over e^{-(1-|y|) t/tau} is at most (1 + 1/sqrt2)(|A|^2 + |Abar|^2)
         env = (1.3 if name == "c4" else 1.8) * (a2 + b2).max()
-        tau, y = (th[-2], th[-1]) if name == "c4" else (th[-3], th[-2])
+        tau, y = th[m.par_names.index("tau")], th[m.par_names.index("y")]
         return S.gen_accept_reject_tddp(n, seed, lambda x, yy, t: m.tddp_rate(th, x, yy, t), env, tau, y,
                                         batch=1 << 18)
     if name in ("mapped", "mapped_sum"):

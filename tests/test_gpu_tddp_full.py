@@ -180,3 +180,37 @@ def test_full_model_repeatable_and_domain(P):
         v, gr = P.nll_grad(g, ds, bad)
         assert v == np.inf
     ds.free()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_model_fit_matches_oracle_fit(P, prec):
+    """The 39-parameter fit on the GPU (the project's minimiser, analytic
+    gradient) against the oracle's fit of the same 5 x 10^4 events from the
+    same start (tests/golden/tddp_full_fit.json, written by
+    make_tddp_full_fit.py from the oracle alone): parameters within 1e-3
+    sigma, errors within 2e-3 relative."""
+    import json
+    import os
+    from helpers import gen_data, get_spec, oracle_for
+    print(f"\n[case] full tddp fit {prec}", flush=True)
+    ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "tddp_full_fit.json")))["fit"]
+    sp = get_spec(ref["name"])
+    om = oracle_for(ref["name"])
+    assert np.allclose(om.theta(), ref["start"], rtol=0, atol=0)
+    assert [p[0] for p in sp["params"]] == ref["par_names"]
+    g = P.Graph.from_spec(sp)
+    ds = P.Dataset(g, gen_data(ref["name"], ref["n_events"], ref["seed"]), prec)
+    r = P.fit(g, ds)
+    free = g.free_mask()
+    th_ref, err_ref = np.array(ref["theta"]), np.array(ref["errors"])
+    dev = np.abs(r["theta"] - th_ref)[free] / err_ref[free]
+    rel_err = np.abs(r["errors"][free] / err_ref[free] - 1.0)
+    print(f"  status {r['status']} n_eval {r['n_eval']} nll {r['nll']:.10f} (oracle {ref['nll']:.10f}) "
+          f"max |dtheta|/sigma {dev.max():.2e} ({sp['params'][int(np.argmax(dev))][0]}) "
+          f"max error ratio - 1 {rel_err.max():.2e}", flush=True)
+    assert r["status"] == "OK"
+    assert dev.max() <= 1e-3, "different minimum" if dev.max() > 1.0 else dev.max()
+    assert rel_err.max() <= 2e-3
+    ds.free()

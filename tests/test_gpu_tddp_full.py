@@ -10,7 +10,11 @@ Per-event bounds as for the other amplitude workloads (see test_gpu_terms:
 |d ln P_i| <= TOL_L (1 + |ln P_i|) k_i, the gradient relative to
 |dlnP_ij| + mean_i |dlnP_ij|, k_i the condition number of the event's
 amplitude sums); summed results within 1e-12 (FP64) and 1e-6 (FP32) of
-the sum of |ln P_i| and of each gradient component's sum of magnitudes.
+the sum of |ln P_i| and of each gradient component's scale: the sum over
+events of its per-event scale (below) times k_i, plus n |d ln N / d theta_j|
+(the per-event bounds summed; each event's derivative is its own term minus
+the normalisation's, and the summed gradient carries the normalisation's
+rounding n times, whatever the events' terms cancel).
 
 The |q/p| and arg q/p derivatives, (|Abar'|^2 (C - Cz) + a_s S + b_s Sz) /
 (|q/p| R) and (a_s Sz - b_s S) / R, hold the difference C - Cz of two decay
@@ -61,20 +65,22 @@ def points(sp, n, seed):
     resolution, sigma_t ~ U[0.02, 0.2] (the shapes of the time-dependent
     workloads' full-size samples)."""
     from oracle import oracle as O
-    dz = sp["model"]["dalitz"]
+    om = O.Model(full_spec(True, grid=10))  # membership only: |A|^2 = 1 inside at c = 0
+    zero = np.zeros(len(om.par_names))
     lo, hi = S.dalitz_box()
     rng = np.random.default_rng(seed)
     a, b = [], []
-    while len(a) < n:
-        u = rng.uniform(lo, hi, 4 * n)
-        v = rng.uniform(lo, hi, 4 * n)
-        for x, y in zip(u, v):
-            if O.inside(dz, x, y):
-                a.append(x)
-                b.append(y)
+    got = 0
+    while got < n:
+        u = rng.uniform(lo, hi, 4 * n + 64)
+        v = rng.uniform(lo, hi, 4 * n + 64)
+        keep = om.dalitz_amp2(zero, u, v) > 0
+        a.append(u[keep])
+        b.append(v[keep])
+        got += int(keep.sum())
     st = rng.uniform(0.02, 0.2, n)
     t = rng.exponential(0.41, n) + st * rng.standard_normal(n)
-    return {"s12": np.array(a[:n]), "s13": np.array(b[:n]), "t": t, "sigma_t": st}
+    return {"s12": np.concatenate(a)[:n], "s13": np.concatenate(b)[:n], "t": t, "sigma_t": st}
 
 
 def theta_off(om, sp, seed=3):
@@ -96,7 +102,7 @@ def qp_scale(om, th, d):
     i = om.par_names.index
     ab2 = om.dalitz_amp2(th, d["s13"], d["s12"])
     tau = th[i("tau")]
-    E = np.array([om_econv(t, 1.0 / tau, s) for t, s in zip(d["t"], d["sigma_t"])])
+    E = np.fromiter((om_econv(t, 1.0 / tau, s) for t, s in zip(d["t"], d["sigma_t"])), float, len(d["t"]))
     lnN = om.node_lnnorm(om.root, th)[0]
     R = np.exp(om.logpdf(th, d) + lnN)
     return th[i("qp_mag")] ** 2 * ab2 * E / R
@@ -149,9 +155,7 @@ def test_full_model_terms_and_sums(P, floating, prec):
         vr, grr = om.nll(th, sd, grad=True)
         tol = 1e-12 if prec == "fp64" else 1e-6
         assert abs(v - vr) <= tol * np.abs(lp_ref).sum(), (v, vr)
-        gl1 = np.abs(rows_ref).sum(axis=0) + 1e-300
-        for name in ("qp_mag", "qp_phase"):  # the same term magnitude as per event
-            gl1[om.par_names.index(name)] += q.sum()
+        gl1 = (kappa[:, None] * sc_all).sum(axis=0) + 1e-300 + len(lp_ref) * np.abs(om.node_lnnorm(om.root, th)[1])
         err = np.abs(gr - grr)[free] / gl1[free]
         print(f"  sums: NLL err {abs(v - vr) / np.abs(lp_ref).sum():.2e}, grad err max {err.max():.2e}", flush=True)
         assert np.all(err <= tol), (float(err.max()), om.par_names[int(np.argmax(err))])
@@ -213,4 +217,39 @@ def test_full_model_fit_matches_oracle_fit(P, prec):
     assert r["status"] == "OK"
     assert dev.max() <= 1e-3, "different minimum" if dev.max() > 1.0 else dev.max()
     assert rel_err.max() <= 2e-3
+    ds.free()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_model_full_size(P, prec):
+    """The benchmark's full model (normalisation grid 1000 x 1000, 10^6
+    events uniform over the plot with exponential decay times, as the
+    benchmark times it) at a parameter point off the truth: summed NLL and
+    gradient against the oracle's, with the bounds of the small-size test."""
+    from oracle import oracle as O
+    print(f"\n[case] full tddp full size {prec}", flush=True)
+    sp = S.configs._full_model()
+    om = O.Model(sp)
+    g = P.Graph.from_spec(sp)
+    data = points(sp, sp["n_events"], sp["seed"])
+    th = theta_off(om, sp)
+    ds = P.Dataset(g, data, prec)
+    v, gr = P.nll_grad(g, ds, th)
+    sd = stored_values(sp, data, prec)
+    lp_ref, rows_ref = om.logpdf(th, sd, grad_rows=True)
+    vr, grr = -lp_ref.sum(), -rows_ref.sum(axis=0)
+    q = qp_scale(om, th, sd)
+    kappa = condition(om, th, sd)
+    sc_all = np.abs(rows_ref) + np.abs(rows_ref).mean(axis=0)
+    for name in ("qp_mag", "qp_phase"):
+        sc_all[:, om.par_names.index(name)] += q
+    gl1 = (kappa[:, None] * sc_all).sum(axis=0) + 1e-300 + len(lp_ref) * np.abs(om.node_lnnorm(om.root, th)[1])
+    free = g.free_mask()
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    err = np.abs(gr - grr)[free] / gl1[free]
+    print(f"  n={ds.n} NLL err {abs(v - vr) / np.abs(lp_ref).sum():.2e}, grad err max {err.max():.2e} "
+          f"({om.par_names[int(np.argmax(np.abs(gr - grr) / gl1))]})", flush=True)
+    assert abs(v - vr) <= tol * np.abs(lp_ref).sum()
+    assert np.all(err <= tol)
     ds.free()

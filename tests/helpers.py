@@ -238,6 +238,37 @@ def grad_scale(model, theta, data):
     return np.abs(rows).sum(axis=0)
 
 
+AMP_WORKLOADS = {"c3", "c4", "c4x", "c4s"}
+
+
+def amp_condition(om, th, sdata, name):
+    """(1 + sum_k |c_k A_k|) / |A| per event, from the oracle's amplitudes
+    (time-dependent: the larger of A's and Abar's): the factor by which the
+    rounding of the terms of the amplitude sum can grow in A."""
+    s12, s13 = sdata["s12"], sdata["s13"]
+    ks = []
+    for sw in (False, True) if name != "c3" else (False,):
+        a, b = (s13, s12) if sw else (s12, s13)
+        amp2 = om.dalitz_amp2(th, a, b)
+        ks.append(om.dalitz_abs_terms(th, a, b) / np.sqrt(np.maximum(amp2, 1e-300)))
+    return np.maximum.reduce(ks)
+
+
+def sum_grad_scale(name, om, th, sdata):
+    """Scale of each summed gradient component: sum_i |d ln P_i / d theta_j|,
+    and for the amplitude workloads the per-event bounds summed, sum_i k_i
+    (|d_ij| + mean_i |d_ij|) with k_i the amplitude condition number, plus
+    n |d ln N / d theta_j| of the amplitude node (its rounding enters once
+    per event whatever the events' terms cancel)."""
+    _, rows = om.logpdf(th, sdata, grad_rows=True)
+    if name not in AMP_WORKLOADS:
+        return np.abs(rows).sum(axis=0)
+    k = amp_condition(om, th, sdata, name)
+    sc = (k[:, None] * (np.abs(rows) + np.abs(rows).mean(axis=0))).sum(axis=0)
+    nid, _ = om.dalitz_node()
+    return sc + rows.shape[0] * np.abs(om.node_lnnorm(nid, th)[1])
+
+
 def perturbed_theta(model, spec_, rel=0.5, seed=0):
     """Truth moved by rel x (parameter step) x N(0, 1), kept inside the bounds."""
     rng = np.random.default_rng(seed)

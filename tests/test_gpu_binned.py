@@ -62,9 +62,8 @@ def histogram(name, seed):
         counts, e1, e2 = np.histogram2d(d["s12"], d["s13"], bins=nb, range=[[lo, hi], [lo, hi]])
         c1, c2 = 0.5 * (e1[1:] + e1[:-1]), 0.5 * (e2[1:] + e2[:-1])
         A, B = np.meshgrid(c1, c2, indexing="ij")
-        import paper_1311_1753_amd as P
-        g = P.Graph.from_spec(S.workload("c3"))
-        inside = g.dalitz_inside(A.ravel(), B.ravel()).astype(bool)
+        om = oracle_for("c3")  # membership by the oracle's rule (c = 0: |A|^2 = 1 inside)
+        inside = om.dalitz_amp2(np.zeros(len(om.par_names)), A.ravel(), B.ravel()) > 0
         # only bins whose centre is inside the plot (their events are kept)
         return ({"s12": A.ravel()[inside], "s13": B.ravel()[inside]}, counts.ravel()[inside],
                 (e1[1] - e1[0]) * (e2[1] - e2[0]))

@@ -187,6 +187,8 @@ static int launch_grid_norm(const pdf_graph* g, const dataset* d, const StagedCa
     na.prog.c32[kn.c0 + i] = 0.0f;
   }
   na.gs = dz.gs;
+  na.cells = dz.norm_cells;
+  na.n_cells = dz.n_norm_cells;
   na.partials = dz.norm_partials;
   na.n_rows = dz.norm_rows;
   hipError_t e = launch_full_norm(want_grad, na, st);

@@ -8,13 +8,14 @@
 // Normalisation: N = sum over the G x G midpoint cells inside the plot of
 // the time-integrated rate, |A|^2 (kc + kz)/2 + |Abar'|^2 (kc - kz)/2
 // + a_s ks + b_s kzs, times the cell area (kc, kz, ks, kzs the integrals of
-// C, Cz, S, Sz over the real line).  One thread per cell, rows of
-// consecutive cells as a dataset's rows of events; per row the sums of
+// C, Cz, S, Sz over the real line).  One thread per cell of the list of
+// cells inside the plot (made once per graph on the host with the same
+// membership rule), rows of consecutive list entries as a dataset's rows of
+// events; per row the sums of
 // |A|^2, |Abar'|^2, a_s, b_s and the derivatives of the rate in the
 // coefficient, q/p and shape slots, reduced by the same fixed-order
 // reduction as the likelihood.  The tau, y and x derivatives follow on the
 // host from the four sums.
-#include "dp_inside.h"
 #include "eval_device.h"
 
 namespace hf {
@@ -39,8 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_full_norm(const NormArgs a) {
   const KNode& nd = a.prog.node[0];
   const int R = nd.aux;
   const int fb = nd.c0 + dz_full_base(R);
-  const int G = a.gs.grid;
-  const int64_t n_cells = (int64_t)G * G;
+  const int64_t n_cells = a.n_cells;
   __shared__ double accs[NC][kBlock];
   const LdsAcc<NC> acc{accs};
   acc.zero(GRAD ? NC : 1);
@@ -51,16 +51,16 @@ __global__ __launch_bounds__(kBlock) void k_full_norm(const NormArgs a) {
   row_chunks(n_cells, a.n_rows, blockIdx.x, c0, c1);
 #pragma unroll 1
   for (int64_t ch = c0; ch < c1; ++ch) {
-    const int64_t cell = ch * kBlock + threadIdx.x;
-    if (cell >= n_cells) continue;
-    const int i = (int)(cell / G), j = (int)(cell % G);
+    const int64_t c = ch * kBlock + threadIdx.x;
+    if (c >= n_cells) continue;
+    const uint32_t cell = a.cells[c];
+    const int i = (int)(cell >> 16), j = (int)(cell & 0xffffu);
     double s12, s13;
     {
 #pragma clang fp contract(off)
       s12 = a.gs.lo12 + ((double)i + 0.5) * a.gs.h12;
       s13 = a.gs.lo13 + ((double)j + 0.5) * a.gs.h13;
     }
-    if (!dp_inside(a.gs.M, a.gs.m1, a.gs.m2, a.gs.m3, s12, s13)) continue;
     const double x12[1] = {s12}, x13[1] = {s13}, xz[1] = {0.0}, xs[1] = {1.0};
     const auto emit = [&](int k, const double (&v)[1]) {
       if (GRAD) acc.add(1 + k, v[0]);

@@ -152,13 +152,28 @@ int ensure_grid(pdf_graph* g, hipStream_t st) {
   if (dz.ready) return HF_OK;
   if (dz.full && !dz.fl.empty()) {
     // floating shapes: no matrices; the grid kernel runs with every
-    // evaluation and needs its rows of partials
-    const int64_t G = dz.gs.grid, chunks = (G * G + kBlock - 1) / kBlock;
+    // evaluation over the list of the cells inside the plot (so that no
+    // lane of a wave idles on a cell outside) and needs its rows of partials
+    const int G = dz.gs.grid;
+    std::vector<uint32_t> cells;
+    for (int i = 0; i < G; ++i) {
+      const double s12 = dz.gs.lo12 + ((double)i + 0.5) * dz.gs.h12;
+      for (int j = 0; j < G; ++j) {
+        const double s13 = dz.gs.lo13 + ((double)j + 0.5) * dz.gs.h13;
+        if (dalitz_inside(dz, s12, s13)) cells.push_back(((uint32_t)i << 16) | (uint32_t)j);
+      }
+    }
+    const int64_t chunks = ((int64_t)cells.size() + kBlock - 1) / kBlock;
     const int R = (int)dz.res.size();
     const int n_col = 1 + 2 * R + 3 + (dz.hq ? 2 : 0) + 2 * (int)dz.fl.size();
-    dz.norm_rows = (int32_t)std::min<int64_t>(chunks, 1024);
+    dz.norm_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(chunks, 1024));
     hipError_t e = hipMalloc(&dz.norm_partials, (size_t)n_col * dz.norm_rows * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(normalisation grid partials)");
+    e = hipMalloc(&dz.norm_cells, std::max<size_t>(cells.size(), 1) * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(normalisation grid cells)");
+    e = hipMemcpy(dz.norm_cells, cells.data(), cells.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "copy of the normalisation grid cells");
+    dz.n_norm_cells = (int64_t)cells.size();
     dz.ready = true;
     return HF_OK;
   }

@@ -114,7 +114,9 @@ hipError_t dalitz_grid_matrices(const GridSpec& gs, const KProgram& prog, int no
 struct NormArgs {
   KProgram prog;      // the evaluation's constants, column references 0
   GridSpec gs;
-  double* partials;   // [column][row]
+  const uint32_t* cells;  // the cells inside the plot, (i << 16) | j
+  int64_t n_cells;
+  double* partials;       // [column][row]
   int32_t n_rows;
 };
 static_assert(sizeof(NormArgs) <= 4096, "kernel arguments are limited to 4 KiB");

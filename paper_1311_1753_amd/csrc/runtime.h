@@ -52,6 +52,8 @@ struct DalitzInfo {
   std::vector<FloatRes> fl;
   double* norm_partials = nullptr;
   int32_t norm_rows = 0;
+  uint32_t* norm_cells = nullptr;  // the grid cells inside the plot, (i << 16) | j (device)
+  int64_t n_norm_cells = 0;
 };
 
 // Host-side terms added after the device reduction (normalisations of the
@@ -99,6 +101,7 @@ struct pdf_graph {
   std::mutex grid_mu;
   ~pdf_graph() {
     if (dz.norm_partials) (void)hipFree(dz.norm_partials);
+    if (dz.norm_cells) (void)hipFree(dz.norm_cells);
   }
 };
 

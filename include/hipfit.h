@@ -437,8 +437,11 @@ int hf_dalitz_inside(const pdf_graph* g, int32_t node, int64_t n, const double* 
  * number of timed calls so far (all complete when read).  Not for concurrent
  * use from several threads. */
 int hf_profile(int32_t enable, double* eval_ms, double* reduce_ms, int64_t* n_launch);
-/* Last error message of the calling thread ("" if none). */
+/* Last error message of the calling thread ("" if none); valid until the
+ * thread's next call into the library.  last_error_message is the same
+ * function under the boundary's plain name. */
 const char* hf_last_error(void);
+const char* last_error_message(void);
 /* Library version string. */
 const char* hf_version(void);
 

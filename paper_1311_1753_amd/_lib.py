@@ -114,6 +114,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_uint8)]),
     "hf_profile": (ctypes.c_int, [ctypes.c_int32, _DP, _DP, ctypes.POINTER(ctypes.c_int64)]),
     "hf_last_error": (ctypes.c_char_p, []),
+    "last_error_message": (ctypes.c_char_p, []),
     "hf_version": (ctypes.c_char_p, []),
 }
 

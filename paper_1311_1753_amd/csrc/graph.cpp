@@ -1778,4 +1778,5 @@ extern "C" int hf_dalitz_inside(const pdf_graph* g, int32_t node, int64_t n, con
 }
 
 extern "C" const char* hf_last_error(void) { return hf::last_error(); }
+extern "C" const char* last_error_message(void) { return hf::last_error(); }
 extern "C" const char* hf_version(void) { return "hipfit 0.1 (gfx950)"; }

@@ -134,6 +134,7 @@ def test_graph_create_raw_abi_errors():
     assert L.pdf_graph_create(obs, 1, par, 1, nodes, 2, 0, ctypes.byref(h)) == -2
     assert L.pdf_graph_create(obs, 1, par, 1, nodes, 2, 5, ctypes.byref(h)) == -2
     assert b"root" in L.hf_last_error()
+    assert L.last_error_message() == L.hf_last_error()
     # a valid single EXP node through the raw ABI
     assert L.pdf_graph_create(obs, 1, par, 1, ctypes.byref(nodes[1]), 1, 0, ctypes.byref(h)) == 0
     n_obs, n_par = ctypes.c_int32(), ctypes.c_int32()

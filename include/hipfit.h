@@ -421,6 +421,12 @@ int batch_poll(batch_engine* b, int32_t max, int64_t* tags, int32_t* status, dou
                double* errors, double* nll, int32_t* n_eval);
 /* Cancels an active fit by tag (its slot and budget are freed at once). */
 int batch_cancel(batch_engine* b, int64_t tag);
+/* Failure injection for tests of the engine's per-fit isolation, from the
+ * host only: with HIPFIT_FAULT="tag:eval:domain" set when batch_create runs,
+ * the fit with that tag receives NLL = +inf at its eval-th evaluation (as
+ * from a density <= 0: its line search backs off); with "tag:eval:abort" the
+ * fit ends there with status HF_E_HIP.  Other fits are unaffected.  A
+ * malformed value makes batch_create fail with HF_E_INVALID. */
 
 /* ------------------------------------------------------------------ misc
  * Dalitz-plot membership (the same rule as the normalisation grid) of n

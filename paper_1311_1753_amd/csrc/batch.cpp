@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -234,7 +235,19 @@ struct batch_engine {
     StagedCall sc;
     int64_t bytes = 0;
     int n_eval = 0;
+    int status_override = 0;  // nonzero: the fit ended by an injected failure
   };
+  // Failure injection from the host (HIPFIT_FAULT="tag:eval:kind" at
+  // batch_create): when the fit with that tag receives its eval-th
+  // evaluation, "domain" replaces the result by NLL = +inf (as a density <= 0
+  // would: the fit's line search backs off), "abort" ends that fit with
+  // status HF_E_HIP.  The kernels are untouched; the other fits must not
+  // notice (their results stay bitwise the same).
+  struct Fault {
+    int64_t tag = -1;
+    int eval = -1;
+    int kind = 0;  // 1 domain, 2 abort
+  } fault;
   const pdf_graph* g = nullptr;
   int max_slots = 0;
   int64_t budget = 0, in_use = 0;
@@ -262,6 +275,17 @@ extern "C" int batch_create(const pdf_graph* g, int32_t max_slots, int64_t hbm_b
     b->slots.resize(max_slots);
     const char* ng = std::getenv("HIPFIT_NO_GRAPH");
     b->use_graph = !(ng && ng[0] == '1');
+    if (const char* fe = std::getenv("HIPFIT_FAULT")) {
+      long long tag = -1;
+      int ev = -1;
+      char kind[16] = {0};
+      if (std::sscanf(fe, "%lld:%d:%15s", &tag, &ev, kind) != 3 || ev < 0 ||
+          (std::strcmp(kind, "domain") != 0 && std::strcmp(kind, "abort") != 0))
+        return fail(HF_E_INVALID, "batch_create: HIPFIT_FAULT must be tag:eval:domain or tag:eval:abort");
+      b->fault.tag = tag;
+      b->fault.eval = ev;
+      b->fault.kind = std::strcmp(kind, "domain") == 0 ? 1 : 2;
+    }
     hipError_t e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "batch_create: stream");
     if (int rc = b->t.alloc(max_slots, g->n_const, g->prog.n_slots)) {
@@ -313,6 +337,7 @@ extern "C" int batch_admit(batch_engine* b, const dataset* d, const double* para
     s.tag = tag;
     s.bytes = d->bytes;
     s.n_eval = 0;
+    s.status_override = 0;
     s.m.start(min_params(b->g, d->prec), params_init, min_options(opts, d->prec));
     b->in_use += d->bytes;
     b->prec = d->prec;
@@ -327,6 +352,20 @@ extern "C" int batch_admit(batch_engine* b, const dataset* d, const double* para
 static void retire_running(batch_engine* b, batch_engine::Slot& s) {
   s.running = false;
   b->in_use -= s.bytes;
+}
+
+// The injected failure, if this evaluation of this fit is the chosen one:
+// true when the fit was ended ("abort"); f replaced by +inf ("domain").
+static bool inject_fault(batch_engine* b, batch_engine::Slot& s, double& f) {
+  if (s.tag != b->fault.tag || s.n_eval != b->fault.eval) return false;
+  if (b->fault.kind == 1) {
+    f = INFINITY;
+    for (double& v : s.g) v = 0.0;  // as the host answers a point outside the domain
+    return false;
+  }
+  s.status_override = HF_E_HIP;
+  retire_running(b, s);
+  return true;
 }
 
 extern "C" int batch_step(batch_engine* b, int32_t* n_active_out, int32_t* n_done_out) {
@@ -350,6 +389,7 @@ extern "C" int batch_step(batch_engine* b, int32_t* n_active_out, int32_t* n_don
         double f = INFINITY;
         if (s.sc.ok) finish_fit(g, s.d, s.sc, nullptr, &f, s.g.data());
         ++s.n_eval;
+        if (inject_fault(b, s, f)) break;
         s.m.tell(f, s.g);
       }
       if (!s.running) continue;
@@ -384,6 +424,7 @@ extern "C" int batch_step(batch_engine* b, int32_t* n_active_out, int32_t* n_don
         double f;
         finish_fit(g, s.d, s.sc, b->t.res_h + k * b->t.RS(), &f, s.g.data());
         ++s.n_eval;
+        if (inject_fault(b, s, f)) continue;
         s.m.tell(f, s.g);
         if (s.m.done()) retire_running(b, s);
       }
@@ -410,7 +451,7 @@ extern "C" int batch_poll(batch_engine* b, int32_t max, int64_t* tags, int32_t* 
     if (k >= max) break;
     if (!s.used || s.running) continue;
     if (tags) tags[k] = s.tag;
-    if (status) status[k] = status_code(s.m.status);
+    if (status) status[k] = s.status_override ? s.status_override : status_code(s.m.status);
     if (params) std::memcpy(params + (size_t)k * np, s.m.x_best.data(), np * sizeof(double));
     if (errors) std::memcpy(errors + (size_t)k * np, s.m.err.data(), np * sizeof(double));
     if (nll) nll[k] = s.m.f_best;

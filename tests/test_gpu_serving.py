@@ -159,3 +159,34 @@ def test_fit_server_with_device_toys(P):
         assert res[r["id"]]["status"] == "OK"
         assert np.array_equal(res[r["id"]]["theta"], ref[r["id"]]["theta"])
         assert abs(res[r["id"]]["theta"][0] - r["alpha"]) < 5 * res[r["id"]]["errors"][0]
+
+
+@pytest.mark.parametrize("kind", ["domain", "abort"])
+def test_injected_failure_stays_in_its_fit(P, kind, monkeypatch):
+    """A failure injected from the host into one fit's evaluation
+    (HIPFIT_FAULT: an NLL of +inf at its 4th evaluation, or the fit ended
+    there) changes only that fit: every other fit's result is bitwise the
+    one of the run without the failure."""
+    print(f"\n[case] injected failure {kind}", flush=True)
+    g = P.Graph.from_spec(get_spec("c1"))
+    reqs = requests(6, seed=11)
+    clean = run_engine(P, g, reqs, "fp32")
+    monkeypatch.setenv("HIPFIT_FAULT", f"2:4:{kind}")
+    hit = run_engine(P, g, reqs, "fp32")
+    monkeypatch.delenv("HIPFIT_FAULT")
+    for r in reqs:
+        a, b = clean[r["id"]], hit[r["id"]]
+        if r["id"] == 2:
+            if kind == "abort":
+                assert b["status"] == "E_HIP" and b["n_eval"] == 4
+            else:
+                # the line search backs off from the +inf point and the fit
+                # still converges, after more evaluations
+                assert b["status"] == "OK" and b["n_eval"] > a["n_eval"]
+                assert np.all(np.abs(b["theta"] - a["theta"]) <= 1e-3 * np.abs(a["errors"])), (b, a)
+            continue
+        assert a["status"] == b["status"] == "OK"
+        assert np.array_equal(a["theta"], b["theta"]) and a["nll"] == b["nll"] and a["n_eval"] == b["n_eval"]
+    with pytest.raises(P.HipfitError):
+        monkeypatch.setenv("HIPFIT_FAULT", "bad")
+        P.BatchEngine(g, max_slots=4, hbm_budget_bytes=1 << 30)

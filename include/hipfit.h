@@ -192,7 +192,8 @@ typedef struct batch_engine batch_engine;
  * used twice, root not the last reachable node, PROD children sharing an
  * observable, ADD children over different observables, wrong par/obs/const
  * counts for the op, lo >= hi, an unbounded box for an EXP/GAUSS/POLY/DALITZ
- * observable, more than 16 nodes, 32 gradient slots or 8 observables.  The
+ * observable, more than 16 nodes, 48 gradient slots (32 in a graph of several
+ * nodes) or 8 observables, a constant table beyond 192 entries.  The
  * arrays are copied; no GPU work is done here. */
 int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param* par, int32_t n_par,
                      const hf_node* nodes, int32_t n_nodes, int32_t root, pdf_graph** out);

@@ -253,3 +253,48 @@ def test_full_model_full_size(P, prec):
     assert abs(v - vr) <= tol * np.abs(lp_ref).sum()
     assert np.all(err <= tol)
     ds.free()
+
+
+@pytest.mark.parametrize("floating", [True, False])
+def test_full_model_nll_only_empty_and_noalloc(P, floating):
+    """The NLL-only evaluation (the grid kernel without derivatives) against
+    the oracle in both precisions; an empty dataset gives NLL 0 and a zero
+    gradient; the allocation-free entry point gives nll_grad's bits with
+    fixed shapes and refuses floating ones (their grid kernel needs its own
+    partial rows)."""
+    import torch
+    from oracle import oracle as O
+    print(f"\n[case] full tddp nll-only/empty/noalloc floating={floating}", flush=True)
+    sp = full_spec(floating)
+    om = O.Model(sp)
+    g = P.Graph.from_spec(sp)
+    data = points(sp, 4001, 21)
+    th = theta_off(om, sp)
+    for prec in ("fp64", "fp32"):
+        ds = P.Dataset(g, data, prec)
+        v = P.nll_eval(g, ds, th)
+        sd = stored_values(sp, data, prec)
+        lp_ref = om.logpdf(th, sd)
+        tol = 1e-12 if prec == "fp64" else 1e-6
+        assert abs(v + lp_ref.sum()) <= tol * np.abs(lp_ref).sum(), (prec, v, -lp_ref.sum())
+        v2, gr2 = P.nll_grad(g, ds, th)
+        assert abs(v2 - v) <= tol * np.abs(lp_ref).sum()
+        cols = {}
+        for name, x in data.items():
+            x = np.asarray(x, dtype=np.float64)
+            if prec == "fp64":
+                cols[name] = torch.tensor(x, dtype=torch.float64, device="cuda")
+            else:
+                ref = g.column_ref(name, "fp32")
+                cols[name] = torch.tensor((x - ref).astype(np.float32), dtype=torch.float32, device="cuda")
+        if floating:
+            with pytest.raises(P.HipfitError):
+                P.nll_grad_noalloc(g, cols, th, precision=prec)
+        else:
+            v3, gr3 = P.nll_grad_noalloc(g, cols, th, precision=prec)
+            assert v3 == v2 and np.array_equal(gr3, gr2)
+        ds.free()
+    empty = P.Dataset(g, {k: v[:0] for k, v in data.items()}, "fp64")
+    v, gr = P.nll_grad(g, empty, th)
+    assert v == 0.0 and not np.any(gr)
+    empty.free()

@@ -907,6 +907,31 @@ template <typename T> struct ShapeAny {
   }
 };
 
+// Visits the grid points k0..k1 of an event's residual window: the first and
+// last two take the definition's range test (t_k = lo + (k + 1/2) h and
+// x - t_k in double, as written), those between lie inside by the window's
+// construction (it is widened by a whole grid step on each side beyond
+// rounding) and go untested, their model and resolution arguments
+// t_k - ref and x - t_k - ref formed with one fused multiply-add each.
+// body(k, t_k - ref, x - t_k - ref) adds a term.
+template <class Body>
+__device__ __forceinline__ void conv_window(double x, double lo, double hh, double dlo, double dhi, double ref,
+                                            int k0, int k1, const Body& body) {
+  const auto tested = [&](int k) {
+    const double t = conv_grid_point(lo, hh, k), d = x - t;
+    if (d >= dlo && d <= dhi) body(k, t - ref, d - ref);
+  };
+  const int ka = k0 + 2 < k1 + 1 ? k0 + 2 : k1 + 1;  // first untested point
+  const int kb = k1 - 2 >= ka ? k1 - 2 : ka - 1;     // last untested point
+  for (int k = k0; k < ka; ++k) tested(k);
+  const double cM = (lo - ref) + 0.5 * hh, cR = ((x - ref) - lo) - 0.5 * hh;
+  for (int k = ka; k <= kb; ++k) {
+    const double dk = (double)k;
+    body(k, __builtin_fma(dk, hh, cM), __builtin_fma(-dk, hh, cR));
+  }
+  for (int k = kb + 1; k <= k1; ++k) tested(k);
+}
+
 // The grid sum of a CONV node at x (the stored event's value): over
 // k in [k0, k1], the terms with the residual x - t_k in [d_lo, d_hi] add
 // w = exp(ln f_M(t_k) + ln f_R(x - t_k) - shift) to S and w d ln f / d(slot)
@@ -922,22 +947,19 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
   R.load(cs, cr);
   constexpr int NM = 4;
   constexpr int NR = ROP == OP_EXP ? 1 : (ROP == OP_GAUSS ? 2 : 4);
-  for (int k = k0; k <= k1; ++k) {
-    const double t = conv_grid_point(lo, hh, k), d = x - t;
-    if (d >= dlo && d <= dhi) {
-      T dm[4], dr[4];
-      const T lm = M.eval(t - ref, dm);
-      const T lr = R.eval(d - ref, dr);
-      undef = undef || !(lr > T(-INFINITY));
-      const T w = Mth<T>::ex((lm + lr) - shift);
-      S += w;
+  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int, double vm, double vr) {
+    T dm[4], dr[4];
+    const T lm = M.eval(vm, dm);
+    const T lr = R.eval(vr, dr);
+    undef = undef || !(lr > T(-INFINITY));
+    const T w = Mth<T>::ex((lm + lr) - shift);
+    S += w;
 #pragma unroll
-      for (int j = 0; j < NM; ++j)
-        if (j < cm.n_slot) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
+    for (int j = 0; j < NM; ++j)
+      if (j < cm.n_slot) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
 #pragma unroll
-      for (int j = 0; j < NR; ++j) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
-    }
-  }
+    for (int j = 0; j < NR; ++j) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
+  });
 }
 
 // The same grid sum with a resolution that is a mixture (ADD node cr) of
@@ -968,33 +990,29 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
     f[j] = j < K ? cs.get<T>(cr.c0 + j) : T(0);  // the ADD's staged fractions, the last one included
   }
   (void)last;
-  for (int k = k0; k <= k1; ++k) {
-    const double t = conv_grid_point(lo, hh, k), d = x - t;
-    if (d >= dlo && d <= dhi) {
-      T dm[4];
-      const T lm = M.eval(t - ref, dm) - shift;
-      const double v = d - ref;
-      T w[3], sw = T(0);
+  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int, double vm, double v) {
+    T dm[4];
+    const T lm = M.eval(vm, dm) - shift;
+    T w[3], sw = T(0);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        if (j < K) {
-          const T z = (T)(v + loc[j]) * isg[j];
-          w[j] = Mth<T>::ex(((lm - T(0.5) * z * z) - lnh[j]) - lnl[j]);
-          const T fw = f[j] * w[j];
-          sw += fw;
-          gr[2 * j] = Mth<T>::fma(fw, z * isg[j] - dmu[j], gr[2 * j]);
-          gr[2 * j + 1] = Mth<T>::fma(fw, z * z * isg[j] - dsg[j], gr[2 * j + 1]);
-        }
+    for (int j = 0; j < 3; ++j) {
+      if (j < K) {
+        const T z = (T)(v + loc[j]) * isg[j];
+        w[j] = Mth<T>::ex(((lm - T(0.5) * z * z) - lnh[j]) - lnl[j]);
+        const T fw = f[j] * w[j];
+        sw += fw;
+        gr[2 * j] = Mth<T>::fma(fw, z * isg[j] - dmu[j], gr[2 * j]);
+        gr[2 * j + 1] = Mth<T>::fma(fw, z * z * isg[j] - dsg[j], gr[2 * j + 1]);
       }
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        if (j + 1 < K) gr[2 * K + j] += w[j] - w[K - 1];
-      S += sw;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (j < cm.n_slot) gm[j] = Mth<T>::fma(sw, dm[j], gm[j]);
     }
-  }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (j + 1 < K) gr[2 * K + j] += w[j] - w[K - 1];
+    S += sw;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < cm.n_slot) gm[j] = Mth<T>::fma(sw, dm[j], gm[j]);
+  });
 }
 
 // General trees (ADD / PROD over leaves).  Node log-values, adjoints and the

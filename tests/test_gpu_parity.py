@@ -289,7 +289,12 @@ def test_fit_convolution_matches_oracle_fit(P, stream, name, prec):
     fixed (an exponential smeared by a Gaussian, or by a mixture of
     Gaussians, is the same exponential away from the box's edges, so the
     resolution is barely constrained by these data; in practice it comes
-    from a calibration)."""
+    from a calibration).  Errors within 1e-3 (FP64) and 3e-3 (FP32-eval) of
+    the oracle's: both are central differences of the gradient over a tenth
+    of an error, and the two sides' steps differ (the NLL's departure from a
+    quadratic over them moves the FP64 errors by up to 5e-4 here); in the
+    FP32-eval path the gradient also carries float rounding, about 1e-3 of
+    the Hessian at those steps for 10^5 events."""
     from oracle import oracle as O
     print(f"\n[case] fit {name} (fixed resolution) prec={prec}", flush=True)
     sp = get_spec(name)
@@ -304,10 +309,12 @@ def test_fit_convolution_matches_oracle_fit(P, stream, name, prec):
     r = P.fit(g, ds, stream=stream)
     free = g.free_mask()
     dev = np.abs(r["theta"] - ref["theta"])[free] / ref["errors"][free]
-    print(f"  status {r['status']} n_eval {r['n_eval']}; max |dtheta|/sigma {dev.max():.2e}", flush=True)
+    er = np.abs(r["errors"][free] / ref["errors"][free] - 1)
+    print(f"  status {r['status']} n_eval {r['n_eval']}; max |dtheta|/sigma {dev.max():.2e}; "
+          f"errors ratio - 1 {er}", flush=True)
     assert r["status"] == "OK"
     assert dev.max() <= 1e-3
-    assert np.all(np.abs(r["errors"][free] / ref["errors"][free] - 1) < 1e-3)
+    assert np.all(er < (1e-3 if prec == "fp64" else 3e-3))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -178,6 +178,16 @@ static int eval_binned(const pdf_graph* g, const dataset* d, const StagedCall& s
 static int launch_grid_norm(const pdf_graph* g, const dataset* d, const StagedCall& sc, bool want_grad,
                             hipStream_t st) {
   const DalitzInfo& dz = g->dz;
+  if (!d->norm_partials) {
+    // the dataset's own rows, so that evaluations of different datasets of
+    // one graph may overlap
+    dataset* dm = const_cast<dataset*>(d);
+    hipError_t e = hipMalloc(&dm->norm_partials, (size_t)dz.norm_cols * dz.norm_rows * sizeof(double));
+    if (e != hipSuccess) {
+      dm->norm_partials = nullptr;
+      return hip_fail(e, "hipMalloc(normalisation grid partials)");
+    }
+  }
   const KNode& kn = sc.prog.node[dz.node];
   NormArgs na;
   std::memset(&na, 0, sizeof(na));
@@ -189,14 +199,14 @@ static int launch_grid_norm(const pdf_graph* g, const dataset* d, const StagedCa
   na.gs = dz.gs;
   na.cells = dz.norm_cells;
   na.n_cells = dz.n_norm_cells;
-  na.partials = dz.norm_partials;
+  na.partials = d->norm_partials;
   na.n_rows = dz.norm_rows;
   hipError_t e = launch_full_norm(want_grad, na, st);
   if (e != hipSuccess) return hip_fail(e, "launch of the normalisation grid kernel");
   const int R = (int)dz.res.size();
   FitRec fr;
   std::memset(&fr, 0, sizeof(fr));
-  fr.partials = dz.norm_partials;
+  fr.partials = d->norm_partials;
   fr.n_rows = dz.norm_rows;
   fr.result = d->res_dev + kNormRes;
   fr.n_slots = want_grad ? 2 * R + 3 + (dz.hq ? 2 : 0) + 2 * (int)dz.fl.size() : 3;
@@ -758,6 +768,7 @@ extern "C" void dataset_free(dataset* d) {
   if (!d) return;
   if (d->block) hipFree(d->block);
   if (d->res_host) hipHostFree(d->res_host);
+  if (d->norm_partials) hipFree(d->norm_partials);
   delete d;
 }
 

@@ -167,9 +167,8 @@ int ensure_grid(pdf_graph* g, hipStream_t st) {
     const int R = (int)dz.res.size();
     const int n_col = 1 + 2 * R + 3 + (dz.hq ? 2 : 0) + 2 * (int)dz.fl.size();
     dz.norm_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(chunks, 1024));
-    hipError_t e = hipMalloc(&dz.norm_partials, (size_t)n_col * dz.norm_rows * sizeof(double));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(normalisation grid partials)");
-    e = hipMalloc(&dz.norm_cells, std::max<size_t>(cells.size(), 1) * sizeof(uint32_t));
+    dz.norm_cols = n_col;
+    hipError_t e = hipMalloc(&dz.norm_cells, std::max<size_t>(cells.size(), 1) * sizeof(uint32_t));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(normalisation grid cells)");
     e = hipMemcpy(dz.norm_cells, cells.data(), cells.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "copy of the normalisation grid cells");

@@ -45,13 +45,14 @@ struct DalitzInfo {
   std::vector<double> I, Ib, J;
   // full time-dependent model (KIND_TDDPF): x and q/p present, their
   // parameters, the floating resonances; with floating shapes the
-  // normalisation is the grid kernel's sum at every evaluation, over
-  // norm_rows rows of partials (device, allocated with the first call)
+  // normalisation is the grid kernel's sum at every evaluation over the
+  // cells inside the plot (device list, made with the first call), into
+  // norm_rows rows of partials that each dataset holds (dataset::norm_partials)
   bool full = false, hx = false, hq = false;
   int p_tau = -1, p_y = -1, p_x = -1, p_qm = -1, p_qa = -1;
   std::vector<FloatRes> fl;
-  double* norm_partials = nullptr;
   int32_t norm_rows = 0;
+  int32_t norm_cols = 0;
   uint32_t* norm_cells = nullptr;  // the grid cells inside the plot, (i << 16) | j (device)
   int64_t n_norm_cells = 0;
 };
@@ -100,7 +101,6 @@ struct pdf_graph {
   hf::MixInfo mix;
   std::mutex grid_mu;
   ~pdf_graph() {
-    if (dz.norm_partials) (void)hipFree(dz.norm_partials);
     if (dz.norm_cells) (void)hipFree(dz.norm_cells);
   }
 };
@@ -117,6 +117,7 @@ struct dataset {
   int32_t n_rows = 0;                         // one block per row (see rows_for)
   int64_t bytes = 0;
   double* res_host = nullptr;                 // pinned, device-mapped: result row, then the completion flag
+  double* norm_partials = nullptr;            // full model with floating shapes: the grid kernel's rows (device)
   double* res_dev = nullptr;
   int64_t seq = 0;                            // completion flag value of the last evaluation
   int metric = 0;                             // 0: unbinned; 1 binned NLL; 2 chi^2 (HF_METRIC_*)

@@ -271,6 +271,50 @@ __device__ __forceinline__ void dalitz_amps(const CS& cs, const KNode& nd, const
   }
 }
 
+// The conjugate-pair amplitudes of one event one resonance at a time, with
+// no per-event arrays: f(k, A_k, Abar_k) for every resonance k in place
+// order (Abar_k = A_k(s13, s12), the same pair quantities as dalitz_amps).
+// The double kernels of the full model take this form: sixteen places of
+// double amplitudes do not fit the registers, and arrays indexed at run
+// time would go to scratch memory.
+template <typename T, int J, class F>
+__device__ __forceinline__ void res_group_stream(const CS& cs, int rbase, T r2, int k0, int k1, const Chan<T>& c,
+                                                 const Chan<T>& cb, const F& f) {
+  if (k0 >= k1) return;
+  const GroupQ<T> gq = group_q<T, J>(r2, c), gb = group_q<T, J>(r2, cb);
+  for (int k = k0; k < k1; ++k) {
+    const int rb = rbase + k * kResStride;
+    f(k, res_amp<T>(cs, rb, gq, c.sABd), res_amp<T>(cs, rb, gb, cb.sABd));
+  }
+}
+
+template <typename T, class F>
+__device__ __forceinline__ void dalitz_stream(const CS& cs, const KNode& nd, double s12, double s13, double s23,
+                                              const F& f) {
+  const int R = nd.aux;
+  const int chb = nd.c0 + dz_ch_base(R, true), rbase = nd.c0 + dz_res_base(R, true);
+  const Chan<T> c12 = chan_eval<T>(cs, chb, s12, s13, s23);
+  const Chan<T> c13 = chan_eval<T>(cs, chb + kChStride, s13, s12, s23);
+  const Chan<T> c23 = chan_eval<T>(cs, chb + 2 * kChStride, s23, s12, s13);
+  bool sym = true;
+#pragma unroll
+  for (int i = 0; i < kChStride; ++i) sym = sym && cs.d[chb + i] == cs.d[chb + kChStride + i];
+  const Chan<T> b12 = sym ? c13 : chan_eval<T>(cs, chb, s13, s12, s23);
+  const Chan<T> b13 = sym ? c12 : chan_eval<T>(cs, chb + kChStride, s12, s13, s23);
+  const Chan<T> b23 = chan_swap_ac_bc<T>(cs, chb + 2 * kChStride, c23, s12, s13);
+  const int32_t* g = nd.res_end;
+  const T r2 = cs.get<T>(nd.c0 + kDzR2);
+  res_group_stream<T, 0>(cs, rbase, r2, 0, g[0], c12, b12, f);
+  res_group_stream<T, 1>(cs, rbase, r2, g[0], g[1], c12, b12, f);
+  res_group_stream<T, 2>(cs, rbase, r2, g[1], g[2], c12, b12, f);
+  res_group_stream<T, 0>(cs, rbase, r2, g[2], g[3], c13, b13, f);
+  res_group_stream<T, 1>(cs, rbase, r2, g[3], g[4], c13, b13, f);
+  res_group_stream<T, 2>(cs, rbase, r2, g[4], g[5], c13, b13, f);
+  res_group_stream<T, 0>(cs, rbase, r2, g[5], g[6], c23, b23, f);
+  res_group_stream<T, 1>(cs, rbase, r2, g[6], g[7], c23, b23, f);
+  res_group_stream<T, 2>(cs, rbase, r2, g[7], g[8], c23, b23, f);
+}
+
 // Gaussian-resolution convolution of e^{-G t}, written without branches:
 //   w = (G s^2 - t)/(sqrt2 s), g = e^{-t^2/(2 s^2)}
 //   w > 0 : E = g erfcx(w) / 2

@@ -202,6 +202,9 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
   constexpr bool hx = HX || FULL;  // trigonometric terms (x free: the plain node has 2R + 3 slots)
   static_assert(!FULL || E == 1, "the full model takes one event per step");
   static_assert(!NORM || FULL, "grid cells of the full model only");
+  // the full model in double takes its amplitudes one at a time, twice
+  // (sums, then derivatives), instead of holding them in arrays
+  constexpr bool STREAM = FULL && std::is_same<T, double>::value;
   double s12[E], s13[E], s23[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -211,7 +214,7 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
   }
   static_assert(E == 1 || E == 2, "one or two events per step");
   AmpArr<T, NR> a0, a1, b0, b1;
-  dalitz_amps<T, true, E, NR>(cs, nd, s12, s13, s23, a0, a1, b0, b1);
+  if constexpr (!STREAM) dalitz_amps<T, true, E, NR>(cs, nd, s12, s13, s23, a0, a1, b0, b1);
   const int cb = c0 + dz_coef_base(R, true);
   const int tb = c0 + dz_time_base(R, NR);
   const int fb = c0 + dz_full_base(R);
@@ -219,11 +222,13 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
   Cx<T> qp = {T(1), T(0)};
   if constexpr (FULL) {
     qp = {cs.get<T>(fb + kFqRe), cs.get<T>(fb + kFqIm)};
+    if constexpr (!STREAM) {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const Cx<T> w = cmul(qp, Cx<T>{b0[2 * k], b0[2 * k + 1]});
-      b0[2 * k] = w.re;
-      b0[2 * k + 1] = w.im;
+      for (int k = 0; k < NR; ++k) {
+        const Cx<T> w = cmul(qp, Cx<T>{b0[2 * k], b0[2 * k + 1]});
+        b0[2 * k] = w.re;
+        b0[2 * k + 1] = w.im;
+      }
     }
   }
   Cx<T> S[E], Sb[E];
@@ -234,13 +239,23 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
     const AmpArr<T, NR>& be = pick<e>(b0, b1);
     S[e] = {T(1), T(0)};
     Sb[e] = qp;
+    if constexpr (STREAM) {
+      dalitz_stream<T>(cs, nd, s12[e], s13[e], s23[e], [&](int k, Cx<T> A, Cx<T> Ab) {
+        const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
+        const Cx<T> t = cmul(c, A);
+        const Cx<T> u = cmul(c, cmul(qp, Ab));
+        S[e].re += t.re; S[e].im += t.im;
+        Sb[e].re += u.re; Sb[e].im += u.im;
+      });
+    } else {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
-      const Cx<T> t = cmul(c, Cx<T>{ae[2 * k], ae[2 * k + 1]});
-      const Cx<T> u = cmul(c, Cx<T>{be[2 * k], be[2 * k + 1]});
-      S[e].re += t.re; S[e].im += t.im;
-      Sb[e].re += u.re; Sb[e].im += u.im;
+      for (int k = 0; k < NR; ++k) {
+        const Cx<T> c = {cs.get<T>(cb + 2 * k), cs.get<T>(cb + 2 * k + 1)};
+        const Cx<T> t = cmul(c, Cx<T>{ae[2 * k], ae[2 * k + 1]});
+        const Cx<T> u = cmul(c, Cx<T>{be[2 * k], be[2 * k + 1]});
+        S[e].re += t.re; S[e].im += t.im;
+        Sb[e].re += u.re; Sb[e].im += u.im;
+      }
     }
     const T nA = S[e].re * S[e].re + S[e].im * S[e].im;
     const T nB = Sb[e].re * Sb[e].re + Sb[e].im * Sb[e].im;
@@ -324,38 +339,52 @@ __device__ __forceinline__ void leaf_tddp(const CS& cs, const KNode& nd, bool ho
     }
     }
   });
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    T d_re[E], d_im[E];
-    static_for<E>([&](auto ei) {
-      constexpr int e = decltype(ei)::value;
-      const AmpArr<T, NR>& ae = pick<e>(a0, a1);
-      const AmpArr<T, NR>& be = pick<e>(b0, b1);
-      // re part: dA = A_k, dAb = Ab_k ; im part: dA = i A_k, dAb = i Ab_k
-      const T ar = ae[2 * k], ai = ae[2 * k + 1], br = be[2 * k], bi = be[2 * k + 1];
-      const T pA_re = S[e].re * ar + S[e].im * ai;    // Re(conj(S) A_k)
-      const T pA_im = S[e].re * ai - S[e].im * ar;    // Im(conj(S) A_k)
-      const T pB_re = Sb[e].re * br + Sb[e].im * bi;
-      const T pB_im = Sb[e].re * bi - Sb[e].im * br;
-      const T x1_re = ar * Sb[e].re + ai * Sb[e].im;  // Re(conj(A_k) Sb)
-      const T x1_im = ar * Sb[e].im - ai * Sb[e].re;  // Im(conj(A_k) Sb)
-      const T x2_re = S[e].re * br + S[e].im * bi;    // Re(conj(S) Ab_k)
-      const T x2_im = S[e].re * bi - S[e].im * br;    // Im(conj(S) Ab_k)
-      T dR_re = cc[e] * pA_re + cb_[e] * pB_re - (x1_re + x2_re) * St[e];
-      T dR_im = -cc[e] * pA_im - cb_[e] * pB_im - (x1_im - x2_im) * St[e];
-      if (hx) {
-        dR_re -= (x1_im + x2_im) * Sz[e];
-        dR_im += (x1_re - x2_re) * Sz[e];
-      }
-      d_re[e] = dR_re * iR[e];
-      d_im[e] = dR_im * iR[e];
-      if (!hoisted && k < R) {
-        d_re[e] -= cs.get<T>(c0 + kDzDln + 2 * k);
-        d_im[e] -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
-      }
+  // coefficient k's two slot derivatives at event e from A_k = (ar, ai) and
+  // the conjugate-side amplitude (br, bi) (with q/p): re part dA = A_k,
+  // dAb = Ab_k; im part dA = i A_k, dAb = i Ab_k
+  const auto coef_d = [&](int e, int k, T ar, T ai, T br, T bi, T& dre, T& dim) {
+    const T pA_re = S[e].re * ar + S[e].im * ai;    // Re(conj(S) A_k)
+    const T pA_im = S[e].re * ai - S[e].im * ar;    // Im(conj(S) A_k)
+    const T pB_re = Sb[e].re * br + Sb[e].im * bi;
+    const T pB_im = Sb[e].re * bi - Sb[e].im * br;
+    const T x1_re = ar * Sb[e].re + ai * Sb[e].im;  // Re(conj(A_k) Sb)
+    const T x1_im = ar * Sb[e].im - ai * Sb[e].re;  // Im(conj(A_k) Sb)
+    const T x2_re = S[e].re * br + S[e].im * bi;    // Re(conj(S) Ab_k)
+    const T x2_im = S[e].re * bi - S[e].im * br;    // Im(conj(S) Ab_k)
+    T dR_re = cc[e] * pA_re + cb_[e] * pB_re - (x1_re + x2_re) * St[e];
+    T dR_im = -cc[e] * pA_im - cb_[e] * pB_im - (x1_im - x2_im) * St[e];
+    if (hx) {
+      dR_re -= (x1_im + x2_im) * Sz[e];
+      dR_im += (x1_re - x2_re) * Sz[e];
+    }
+    dre = dR_re * iR[e];
+    dim = dR_im * iR[e];
+    if (!hoisted && k < R) {
+      dre -= cs.get<T>(c0 + kDzDln + 2 * k);
+      dim -= cs.get<T>(c0 + kDzDln + 2 * k + 1);
+    }
+  };
+  if constexpr (STREAM) {
+    dalitz_stream<T>(cs, nd, s12[0], s13[0], s23[0], [&](int k, Cx<T> A, Cx<T> Ab) {
+      const Cx<T> B = cmul(qp, Ab);
+      T d_re[E], d_im[E];
+      coef_d(0, k, A.re, A.im, B.re, B.im, d_re[0], d_im[0]);
+      emit(2 * k, d_re);
+      emit(2 * k + 1, d_im);
     });
-    emit(2 * k, d_re);
-    emit(2 * k + 1, d_im);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      T d_re[E], d_im[E];
+      static_for<E>([&](auto ei) {
+        constexpr int e = decltype(ei)::value;
+        const AmpArr<T, NR>& ae = pick<e>(a0, a1);
+        const AmpArr<T, NR>& be = pick<e>(b0, b1);
+        coef_d(e, k, ae[2 * k], ae[2 * k + 1], be[2 * k], be[2 * k + 1], d_re[e], d_im[e]);
+      });
+      emit(2 * k, d_re);
+      emit(2 * k + 1, d_im);
+    }
   }
   if constexpr (!FULL) {
     emit(2 * R, dtau);

@@ -961,31 +961,79 @@ __device__ __forceinline__ void conv_window(double x, double lo, double hh, doub
   for (int k = kb + 1; k <= k1; ++k) tested(k);
 }
 
+// The model child of one CONV node at every grid point, staged in LDS once
+// per row: ln f_M(t_k) and d ln f_M / d(slot j) (zero beyond the model's
+// slots), t_k = lo + (k + 1/2) h in the offset frame.  The model does not
+// depend on the event, so the term loop then reads it instead of evaluating
+// it per term.  Grids of at most kConvTab points qualify (the table fits
+// beside the row's LDS accumulators without costing a resident block).
+constexpr int kHeavyConvTab = 3;  // the tree interpreter's staged-CONV instantiation
+template <typename T> struct ConvTab {
+  T v[5][kConvTab];
+};
+
+template <typename T>
+__device__ __forceinline__ ConvTab<T>& conv_tab_lds() {
+  __shared__ ConvTab<T> t;
+  return t;
+}
+
+// Stages the first CONV node with at most kConvTab grid points; returns its
+// index, or -1 when there is none (every lane of the block takes part).
+template <typename T>
+__device__ __forceinline__ int conv_stage(const KProgram& P, const CS& cs, ConvTab<T>& tab) {
+  int node = -1;
+  for (int k = 0; k < P.n_nodes; ++k)
+    if (node < 0 && P.node[k].op == OP_CONV && P.node[k].aux <= kConvTab) node = k;
+  if (node < 0) return -1;
+  const KNode& nd = P.node[node];
+  ShapeAny<T> M;
+  M.load(cs, P.node[P.child[nd.child0]]);
+  const double lo = cs.d[nd.c0], hh = cs.d[nd.c0 + 1], ref = cs.d[nd.c0 + 4];
+  __syncthreads();  // a previous row of this block may still read the table
+  for (int k = threadIdx.x; k < nd.aux; k += kBlock) {
+    T d[4] = {T(0), T(0), T(0), T(0)};
+    const T l = M.eval(conv_grid_point(lo, hh, k) - ref, d);
+    tab.v[0][k] = l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tab.v[1 + j][k] = d[j];
+  }
+  __syncthreads();
+  return node;
+}
+
 // The grid sum of a CONV node at x (the stored event's value): over
 // k in [k0, k1], the terms with the residual x - t_k in [d_lo, d_hi] add
 // w = exp(ln f_M(t_k) + ln f_R(x - t_k) - shift) to S and w d ln f / d(slot)
 // to the children's slot sums gm (model) and gr (resolution); undef is set
 // when the resolution's shape is not positive at a residual in use.
-template <typename T, int ROP>
+// With TAB the model's values come from the staged table.
+template <typename T, int ROP, bool TAB>
 __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const KNode& cr, double x, double lo,
                                            double hh, double dlo, double dhi, double ref, T shift, int k0, int k1,
-                                           T& S, T (&gm)[8], T (&gr)[8], bool& undef) {
+                                           T& S, T (&gm)[8], T (&gr)[8], bool& undef, const ConvTab<T>* tab) {
   ShapeAny<T> M;
   Shape<T, ROP> R;
-  M.load(cs, cm);
+  if (!TAB) M.load(cs, cm);
   R.load(cs, cr);
   constexpr int NM = 4;
   constexpr int NR = ROP == OP_EXP ? 1 : (ROP == OP_GAUSS ? 2 : 4);
-  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int, double vm, double vr) {
-    T dm[4], dr[4];
-    const T lm = M.eval(vm, dm);
+  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double vm, double vr) {
+    T dm[4], dr[4], lm;
+    if constexpr (TAB) {
+      lm = tab->v[0][k];
+#pragma unroll
+      for (int j = 0; j < NM; ++j) dm[j] = tab->v[1 + j][k];
+    } else {
+      lm = M.eval(vm, dm);
+    }
     const T lr = R.eval(vr, dr);
     undef = undef || !(lr > T(-INFINITY));
     const T w = Mth<T>::ex((lm + lr) - shift);
     S += w;
 #pragma unroll
     for (int j = 0; j < NM; ++j)
-      if (j < cm.n_slot) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
+      if (TAB || j < cm.n_slot) gm[j] = Mth<T>::fma(w, dm[j], gm[j]);
 #pragma unroll
     for (int j = 0; j < NR; ++j) gr[j] = Mth<T>::fma(w, dr[j], gr[j]);
   });
@@ -997,12 +1045,13 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
 // + ln g_j(x - t_k) - ln N_j - shift), S += sum f_j w_j; the resolution's
 // slot sums gr are ordered as its slots: each Gaussian's (mu, sigma), then
 // the K - 1 fractions (d/df_j: w_j - w_K).
-template <typename T>
+template <typename T, bool TAB>
 __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P, const KNode& cm, const KNode& cr,
                                                 double x, double lo, double hh, double dlo, double dhi, double ref,
-                                                T shift, int k0, int k1, T& S, T (&gm)[8], T (&gr)[8]) {
+                                                T shift, int k0, int k1, T& S, T (&gm)[8], T (&gr)[8],
+                                                const ConvTab<T>* tab) {
   ShapeAny<T> M;
-  M.load(cs, cm);
+  if (!TAB) M.load(cs, cm);
   const int K = cr.n_child;
   double loc[3];
   T isg[3], lnh[3], lnl[3], dmu[3], dsg[3], f[3];
@@ -1019,9 +1068,15 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
     f[j] = j < K ? cs.get<T>(cr.c0 + j) : T(0);  // the ADD's staged fractions, the last one included
   }
   (void)last;
-  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int, double vm, double v) {
-    T dm[4];
-    const T lm = M.eval(vm, dm) - shift;
+  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double vm, double v) {
+    T dm[4], lm;
+    if constexpr (TAB) {
+      lm = tab->v[0][k] - shift;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dm[j] = tab->v[1 + j][k];
+    } else {
+      lm = M.eval(vm, dm) - shift;
+    }
     T w[3], sw = T(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -1040,7 +1095,7 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
     S += sw;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (j < cm.n_slot) gm[j] = Mth<T>::fma(sw, dm[j], gm[j]);
+      if (TAB || j < cm.n_slot) gm[j] = Mth<T>::fma(sw, dm[j], gm[j]);
   });
 }
 
@@ -1049,8 +1104,12 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
 // wave-uniform node / slot numbers.
 // Returns ln P of the root (without the normalisations of hoisted nodes)
 // and, with GRAD, its slot derivatives in dl[0 .. P.n_slots).
+// HEAVY: 0 light nodes only; 1 adds CONV and COMP; 2 also DALITZ / TDDP;
+// kHeavyConvTab as 1 with the CONV node's model read from the row's LDS
+// table tab (node tab_node, staged by conv_stage).
 template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
-__device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const double* xe, T* dl) {
+__device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const double* xe, T* dl,
+                                       const ConvTab<T>* tab = nullptr, int tab_node = -1) {
     // node capacity of this instantiation; float arrays get 16 entries so
     // that the compiler indexes them with register moves (8 floats become
     // chains of compares and selects, one per entry and access; 8 doubles
@@ -1080,7 +1139,7 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           if (j < nd.aux) dl[s0 + j] = dp[j];
-      } else if (HEAVY >= 2 && (op == OP_DALITZ || op == OP_TDDP)) {
+      } else if (HEAVY == 2 && (op == OP_DALITZ || op == OP_TDDP)) {
         const int ns = nd.n_slot;
         const auto emit = [&](int j, const T (&d)[1]) {
           if (j < ns) dl[s0 + j] = d[0];
@@ -1167,12 +1226,17 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         int k1 = (int)__builtin_floor((x - dlo - lo) / hh - 0.5) + 1;
         k0 = k0 < 0 ? 0 : k0;
         k1 = k1 > N - 1 ? N - 1 : k1;
-        // the term loop is specialised on the resolution's kind; both
-        // children's constants are read once into registers
-#define HF_CONV_CASE(R_)                                                                                  \
-  if (cr.op == R_) conv_terms<T, R_>(cs, cm, cr, x, lo, hh, dlo, dhi, ref, shift, k0, k1, S, gm, gr, undef);
-        if (mixr) conv_terms_gmix<T>(cs, P, cm, cr, x, lo, hh, dlo, dhi, ref, shift, k0, k1, S, gm, gr);
-        else HF_CONV_CASE(OP_GAUSS) else HF_CONV_CASE(OP_EXP) else HF_CONV_CASE(OP_POLY)
+        // the term loop is specialised on the resolution's kind; the
+        // children's constants are read once into registers.  The staged
+        // instantiation (HEAVY == kHeavyConvTab, chosen on the host for
+        // graphs whose one CONV node qualifies) reads the model from the
+        // row's LDS table and has no per-term model code: carrying both
+        // loops makes the interpreter copy its kernel argument to scratch
+#define HF_CONV_CASE(R_, TAB_)                                                                            \
+  if (cr.op == R_) conv_terms<T, R_, TAB_>(cs, cm, cr, x, lo, hh, dlo, dhi, ref, shift, k0, k1, S, gm, gr, undef, tab);
+        constexpr bool TAB = HEAVY == kHeavyConvTab;
+        if (mixr) conv_terms_gmix<T, TAB>(cs, P, cm, cr, x, lo, hh, dlo, dhi, ref, shift, k0, k1, S, gm, gr, tab);
+        else HF_CONV_CASE(OP_GAUSS, TAB) else HF_CONV_CASE(OP_EXP, TAB) else HF_CONV_CASE(OP_POLY, TAB)
 #undef HF_CONV_CASE
         const T iS = Mth<T>::rcp(S);
         v = S > T(0) && !undef ? Mth<T>::ln(S) : T(-INFINITY);
@@ -1302,11 +1366,13 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
 template <typename T, int NS, int NCOL, int HEAVY, bool GRAD>
 struct TreeEv {
   CS cs;
+  const ConvTab<T>* tab;  // staged CONV model (HEAVY rows), else null
+  int tab_node;
   template <class Acc>
   __device__ __forceinline__ void operator()(const KProgram& P, const double* xe, int64_t, const Acc& acc) const {
     const int n_slots = GRAD ? P.n_slots : 0;
     T dl[sizeof(T) == 4 && NS < 16 ? 16 : NS];  // indexed with register moves (see tree_eval)
-    const T lr = tree_eval<T, NS, NCOL, HEAVY, GRAD>(P, cs, xe, dl);
+    const T lr = tree_eval<T, NS, NCOL, HEAVY, GRAD>(P, cs, xe, dl, tab, tab_node);
     acc.add(0, -(double)lr);
 #pragma unroll
     for (int j = 0; j < NS; ++j)
@@ -1707,7 +1773,13 @@ __device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const 
                                          int n_rows, int r, double* __restrict__ out) {
   typedef typename Col<T>::S Sx;
   constexpr int NC = 1 + NS;
-  const TreeEv<T, NS, NCOL, HEAVY, GRAD> ev{cs};
+  ConvTab<T>* tab = nullptr;
+  int tab_node = -1;
+  if constexpr (HEAVY == kHeavyConvTab) {
+    tab = &conv_tab_lds<T>();
+    tab_node = conv_stage<T>(P, cs, *tab);
+  }
+  const TreeEv<T, NS, NCOL, HEAVY, GRAD> ev{cs, tab, tab_node};
   const Sx* cp[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) cp[c] = (const Sx*)cols[c];
@@ -1786,6 +1858,9 @@ inline hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st, hipEve
       break;
     case KIND_TREE_NOAMP:
       hipExtLaunchKernelGGL((k_tree<T, kMaxSlotsTree, kMaxCols, 1, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a);
+      break;
+    case KIND_TREE_CONV:
+      hipExtLaunchKernelGGL((k_tree<T, kMaxSlotsTree, kMaxCols, kHeavyConvTab, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a);
       break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \

@@ -266,6 +266,7 @@ static const void* kernel_of(int kind) {
     case KIND_TDDPXS: return (const void*)&k_leaf<T, OP_TDDP_XS, GRAD>;
     case KIND_TREE: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, 2, GRAD>;
     case KIND_TREE_NOAMP: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, 1, GRAD>;
+    case KIND_TREE_CONV: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, kHeavyConvTab, GRAD>;
     case KIND_TDDPF: return full_leaf_kernel(std::is_same<T, float>::value, GRAD);
     default: return nullptr;  // mixtures: light, never below kRowsPerCU
   }
@@ -327,6 +328,9 @@ static hipError_t launch_b(int kind, const BatchArgs& a, int grid, hipStream_t s
     case KIND_TDDPXS: hipLaunchKernelGGL((k_leaf_batched<T, OP_TDDP_XS>), g, b, 0, st, a); break;
     case KIND_TREE: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlotsTree, kMaxCols, 2>), g, b, 0, st, a); break;
     case KIND_TREE_NOAMP: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlotsTree, kMaxCols, 1>), g, b, 0, st, a); break;
+    case KIND_TREE_CONV:
+      hipLaunchKernelGGL((k_tree_batched<T, kMaxSlotsTree, kMaxCols, kHeavyConvTab>), g, b, 0, st, a);
+      break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \
     hipLaunchKernelGGL((k_mix_batched<T, K_, M_>), g, b, 0, st, a);                                 \

@@ -1749,7 +1749,20 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
       g->kind = (int)g->nodes[0].par.size() == 2 * (int)g->nodes[0].consts[6] + 3 ? KIND_TDDPXS : KIND_TDDPS;
     else if (!heavy && P.n_slots <= 8 && P.n_cols <= 2 && NN <= 8) g->kind = KIND_TREE_SMALL;
     else g->kind = g->dz.node >= 0 ? KIND_TREE : KIND_TREE_NOAMP;
-    if ((g->kind == KIND_TREE || g->kind == KIND_TREE_NOAMP) && P.n_slots > kMaxSlotsTree)
+    if (g->kind == KIND_TREE_NOAMP) {
+      // one CONV node with a grid small enough for the row's LDS table: the
+      // interpreter that reads the model's grid values from that table
+      int n_conv = 0;
+      bool fits = true;
+      for (int k = 0; k < P.n_nodes; ++k)
+        if (P.node[k].op == OP_CONV) {
+          ++n_conv;
+          fits = fits && P.node[k].aux <= kConvTab;
+        }
+      if (n_conv == 1 && fits) g->kind = KIND_TREE_CONV;
+    }
+    if ((g->kind == KIND_TREE || g->kind == KIND_TREE_NOAMP || g->kind == KIND_TREE_CONV) &&
+        P.n_slots > kMaxSlotsTree)
       return fail(HF_E_GRAPH, "more than 32 gradient slots in a tree of several nodes");
     *out = g.release();
     return HF_OK;

@@ -26,6 +26,7 @@ constexpr int kMaxResFull = 16;     // ... of the full time-dependent kernel (th
 constexpr int kMaxFloat = 4;        // resonances with floating mass and width
 constexpr int kMaxPar = 64;
 constexpr int kNumGroups = 9;        // (pair, spin) groups of Dalitz resonances
+constexpr int kConvTab = 512;        // grid points of a CONV model that a row stages in LDS
 
 enum Op : int16_t {
   OP_EXP = 1, OP_GAUSS = 2, OP_POLY = 3, OP_ADD = 4, OP_PROD = 5, OP_DALITZ = 6, OP_TDDP = 7, OP_MAP = 8,

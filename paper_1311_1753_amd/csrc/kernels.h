@@ -19,6 +19,7 @@ enum KernelKind {
   KIND_TDDPXS = 12,     // the same with x free
   KIND_TREE_NOAMP = 13, // any tree without DALITZ / TDDP nodes (the general interpreter minus the amplitude code)
   KIND_TDDPF = 14,      // single TDDP leaf of the full model (up to 16 resonances, q/p, floating shapes)
+  KIND_TREE_CONV = 15,  // KIND_TREE_NOAMP with one CONV node of at most kConvTab grid points (model staged in LDS)
   // root ADD of 2 (3) single-column EXP/GAUSS leaves: KIND_MIX2 (KIND_MIX3)
   // plus a mask with bit j set when child j is a GAUSS
   KIND_MIX2 = 8,

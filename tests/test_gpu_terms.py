@@ -25,6 +25,8 @@ float terms.  So TOL_L = 5e-14 / 4e-6 and TOL_G = 5e-13 / 5e-5; the largest
 values seen over every workload were 6.2e-15 / 6.8e-7 (ln P) and 5.0e-14 /
 1.2e-5 (gradient).
 """
+import copy
+
 import numpy as np
 import pytest
 
@@ -234,3 +236,36 @@ def test_terms_sampled_at_full_size(P, name):
               f"{int(np.argmax(eg.max(axis=0)))})", flush=True)
         assert el.max() <= TOL_L[prec] and eg.max() <= TOL_G[prec]
         assert abs(v + lp.sum()) <= (1e-13 if prec == "fp64" else 1e-6) * np.abs(lp).sum()
+
+
+def _conv_variant(grid, second):
+    """The CONV workload with another grid size, or (second) with its
+    background replaced by a second convolution (the background exponential
+    smeared by the same Gaussian on a 300-point grid)."""
+    sp = copy.deepcopy(S.configs.CONV)
+    sp["name"] = f"conv_grid{grid}" + ("_two" if second else "")
+    sp["model"]["children"][0]["grid"] = grid
+    if second:
+        sp["model"]["children"][1] = {"op": "conv", "obs": "x", "grid": 300, "d_lo": -2.0, "d_hi": 2.0, "children": [
+            {"op": "exp", "obs": "x", "par": ["b_beta"]},
+            {"op": "gauss", "obs": "x", "par": ["r_mu", "r_sigma"]}]}
+    return sp
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid,second", [(512, False), (513, False), (400, True)])
+def test_terms_conv_staged_and_direct_model(P, grid, second, prec):
+    """A row stages the model of a graph's one CONV node in LDS when its grid
+    has at most 512 points; a larger grid, or a second CONV node, takes the
+    interpreter that evaluates the model per term.  Both at the limit and
+    either side of it, per event against the oracle (edge events included)."""
+    from oracle import oracle as O
+    print(f"\n[case] terms conv grid={grid} second={second} {prec}", flush=True)
+    sp = _conv_variant(grid, second)
+    om = O.Model(sp)
+    g = P.Graph.from_spec(sp)
+    rng = np.random.default_rng(grid + 7 * second)
+    x = np.concatenate([rng.uniform(0.0, 10.0, 6_007), _conv_edges(sp["model"]["children"][0])])
+    data = {"x": x}
+    for th in (om.theta(sp["truth"]), perturbed_theta(om, sp, seed=79)):
+        compare_terms(P, sp["name"], sp, om, g, data, prec, th)

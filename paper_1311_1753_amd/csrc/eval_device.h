@@ -962,8 +962,9 @@ __device__ __forceinline__ void conv_window(double x, double lo, double hh, doub
 }
 
 // The model child of one CONV node at every grid point, staged in LDS once
-// per row: ln f_M(t_k) and d ln f_M / d(slot j) (zero beyond the model's
-// slots), t_k = lo + (k + 1/2) h in the offset frame.  The model does not
+// per row: ln f_M(t_k) - c (c the node's exponent shift) and
+// d ln f_M / d(slot j) (zero beyond the model's slots), t_k = lo + (k + 1/2) h
+// in the offset frame.  The model does not
 // depend on the event, so the term loop then reads it instead of evaluating
 // it per term.  Grids of at most kConvTab points qualify (the table fits
 // beside the row's LDS accumulators without costing a resident block).
@@ -990,11 +991,12 @@ __device__ __forceinline__ int conv_stage(const KProgram& P, const CS& cs, ConvT
   ShapeAny<T> M;
   M.load(cs, P.node[P.child[nd.child0]]);
   const double lo = cs.d[nd.c0], hh = cs.d[nd.c0 + 1], ref = cs.d[nd.c0 + 4];
+  const T shift = cs.get<T>(nd.c0 + 5);
   __syncthreads();  // a previous row of this block may still read the table
   for (int k = threadIdx.x; k < nd.aux; k += kBlock) {
     T d[4] = {T(0), T(0), T(0), T(0)};
     const T l = M.eval(conv_grid_point(lo, hh, k) - ref, d);
-    tab.v[0][k] = l;
+    tab.v[0][k] = l - shift;
 #pragma unroll
     for (int j = 0; j < 4; ++j) tab.v[1 + j][k] = d[j];
   }
@@ -1018,10 +1020,37 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
   R.load(cs, cr);
   constexpr int NM = 4;
   constexpr int NR = ROP == OP_EXP ? 1 : (ROP == OP_GAUSS ? 2 : 4);
+  if constexpr (TAB && ROP == OP_GAUSS) {
+    // Gaussian resolution, u = x - t_k + (ref - mu): ln f_R = c u^2 with
+    // c = -1/(2 sigma^2), d/dmu = u / sigma^2, d/dsigma = u^2 / sigma^3, so
+    // the term adds w, w u and w u^2 and the sums are scaled once per event;
+    // the loop is specialised on the model's slot count
+    const T isg = R.isg, c = T(-0.5) * isg * isg;
+    T su = T(0), su2 = T(0);
+    const auto run = [&](auto nms) __attribute__((always_inline)) {
+      constexpr int NMS = decltype(nms)::value;
+      conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double vr) {
+        const T u = (T)(vr + R.loc);
+        const T u2 = u * u;
+        const T w = Mth<T>::ex(Mth<T>::fma(c, u2, tab->v[0][k]));
+        S += w;
+        su = Mth<T>::fma(w, u, su);
+        su2 = Mth<T>::fma(w, u2, su2);
+#pragma unroll
+        for (int j = 0; j < NMS; ++j) gm[j] = Mth<T>::fma(w, tab->v[1 + j][k], gm[j]);
+      });
+    };
+    if (cm.n_slot == 1) run(std::integral_constant<int, 1>{});
+    else if (cm.n_slot == 2) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 4>{});
+    gr[0] = su * (isg * isg);
+    gr[1] = su2 * (isg * isg * isg);
+    return;
+  }
   conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double vm, double vr) {
     T dm[4], dr[4], lm;
     if constexpr (TAB) {
-      lm = tab->v[0][k];
+      lm = tab->v[0][k];  // shift already subtracted
 #pragma unroll
       for (int j = 0; j < NM; ++j) dm[j] = tab->v[1 + j][k];
     } else {
@@ -1029,7 +1058,7 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
     }
     const T lr = R.eval(vr, dr);
     undef = undef || !(lr > T(-INFINITY));
-    const T w = Mth<T>::ex((lm + lr) - shift);
+    const T w = Mth<T>::ex(TAB ? lm + lr : (lm + lr) - shift);
     S += w;
 #pragma unroll
     for (int j = 0; j < NM; ++j)
@@ -1068,15 +1097,48 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
     f[j] = j < K ? cs.get<T>(cr.c0 + j) : T(0);  // the ADD's staged fractions, the last one included
   }
   (void)last;
-  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double vm, double v) {
-    T dm[4], lm;
-    if constexpr (TAB) {
-      lm = tab->v[0][k] - shift;
+  if constexpr (TAB) {
+    // per component the sums of w_j z_j and w_j z_j^2 (kept in gr[2j] and
+    // gr[2j + 1]) and of w_j (the first K - 1 in gr[2K + j], the last in
+    // wl); the slot sums f_j (w_j (z_j / sigma_j - dlnN_j/dmu_j)) and
+    // f_j (w_j (z_j^2 / sigma_j - dlnN_j/dsigma_j)) and the fractions'
+    // w_j - w_K follow once per event
+    T wl = T(0);
+    conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double v) {
+      const T lm = tab->v[0][k];  // shift already subtracted
+      T sw = T(0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dm[j] = tab->v[1 + j][k];
-    } else {
-      lm = M.eval(vm, dm) - shift;
-    }
+      for (int j = 0; j < 3; ++j) {
+        if (j < K) {
+          const T z = (T)(v + loc[j]) * isg[j];
+          const T z2 = z * z;
+          const T w = Mth<T>::ex(((lm - T(0.5) * z2) - lnh[j]) - lnl[j]);
+          sw = Mth<T>::fma(f[j], w, sw);
+          gr[2 * j] = Mth<T>::fma(w, z, gr[2 * j]);
+          gr[2 * j + 1] = Mth<T>::fma(w, z2, gr[2 * j + 1]);
+          if (j + 1 < K) gr[2 * K + j] += w;
+          else wl += w;
+        }
+      }
+      S += sw;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gm[j] = Mth<T>::fma(sw, tab->v[1 + j][k], gm[j]);
+    });
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j < K) {
+        const T wj = j + 1 < K ? gr[2 * K + j] : wl;
+        gr[2 * j] = f[j] * (isg[j] * gr[2 * j] - dmu[j] * wj);
+        gr[2 * j + 1] = f[j] * (isg[j] * gr[2 * j + 1] - dsg[j] * wj);
+      }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (j + 1 < K) gr[2 * K + j] -= wl;
+    return;
+  }
+  conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double vm, double v) {
+    T dm[4];
+    const T lm = M.eval(vm, dm) - shift;
     T w[3], sw = T(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -1095,7 +1157,7 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
     S += sw;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (TAB || j < cm.n_slot) gm[j] = Mth<T>::fma(sw, dm[j], gm[j]);
+      if (j < cm.n_slot) gm[j] = Mth<T>::fma(sw, dm[j], gm[j]);
   });
 }
 

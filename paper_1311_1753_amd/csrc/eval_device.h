@@ -943,7 +943,9 @@ template <typename T> struct ShapeAny {
 // rounding) and go untested, their model and resolution arguments
 // t_k - ref and x - t_k - ref formed with one fused multiply-add each.
 // body(k, t_k - ref, x - t_k - ref) adds a term.
-template <class Body>
+// PAIRS: the untested points are visited two per loop step (then the odd
+// one), so that two independent terms are in flight.
+template <bool PAIRS = false, class Body>
 __device__ __forceinline__ void conv_window(double x, double lo, double hh, double dlo, double dhi, double ref,
                                             int k0, int k1, const Body& body) {
   const auto tested = [&](int k) {
@@ -954,10 +956,17 @@ __device__ __forceinline__ void conv_window(double x, double lo, double hh, doub
   const int kb = k1 - 2 >= ka ? k1 - 2 : ka - 1;     // last untested point
   for (int k = k0; k < ka; ++k) tested(k);
   const double cM = (lo - ref) + 0.5 * hh, cR = ((x - ref) - lo) - 0.5 * hh;
-  for (int k = ka; k <= kb; ++k) {
+  const auto untested = [&](int k) {
     const double dk = (double)k;
     body(k, __builtin_fma(dk, hh, cM), __builtin_fma(-dk, hh, cR));
-  }
+  };
+  int k = ka;
+  if constexpr (PAIRS)
+    for (; k < kb; k += 2) {
+      untested(k);
+      untested(k + 1);
+    }
+  for (; k <= kb; ++k) untested(k);
   for (int k = kb + 1; k <= k1; ++k) tested(k);
 }
 
@@ -1029,7 +1038,7 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
     T su = T(0), su2 = T(0);
     const auto run = [&](auto nms) __attribute__((always_inline)) {
       constexpr int NMS = decltype(nms)::value;
-      conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double vr) {
+      conv_window<true>(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double vr) {
         const T u = (T)(vr + R.loc);
         const T u2 = u * u;
         const T w = Mth<T>::ex(Mth<T>::fma(c, u2, tab->v[0][k]));
@@ -1104,7 +1113,7 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
     // f_j (w_j (z_j^2 / sigma_j - dlnN_j/dsigma_j)) and the fractions'
     // w_j - w_K follow once per event
     T wl = T(0);
-    conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double v) {
+    conv_window<true>(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double v) {
       const T lm = tab->v[0][k];  // shift already subtracted
       T sw = T(0);
 #pragma unroll

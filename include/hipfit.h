@@ -137,7 +137,10 @@ enum hf_op {
                         components are each normalised over [d_lo, d_hi];
                         Z = sum_k f_M(t_k) int_box f_R(x - t_k) dx (closed forms, on the
                         host); obs = {x}; no par; consts = {N (2..4096), d_lo, d_hi}; the
-                        per-event sum runs over all N points (cost ~ N per event); range
+                        per-event sum visits only the points whose residual can lie in
+                        [d_lo, d_hi] (cost ~ N (d_hi - d_lo) / box width per event), and a
+                        graph whose one CONV node has N <= 512 reads the model's values at
+                        the grid points from a table each block builds once; range
                         tests take t_k = lo + (k + 1/2) h and x - t_k in double on the
                         stored event value; a model shape <= 0 at a grid point whose
                         residual window meets the box is a domain error of the parameters,

@@ -1030,7 +1030,8 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
   constexpr int NM = 4;
   constexpr int NR = ROP == OP_EXP ? 1 : (ROP == OP_GAUSS ? 2 : 4);
   if constexpr (TAB && ROP == OP_GAUSS) {
-    // Gaussian resolution, u = x - t_k + (ref - mu): ln f_R = c u^2 with
+    // Gaussian resolution, u = x - t_k - mu (the residual less the mean, from
+    // the offset-frame residual and the staged ref - mu): ln f_R = c u^2 with
     // c = -1/(2 sigma^2), d/dmu = u / sigma^2, d/dsigma = u^2 / sigma^3, so
     // the term adds w, w u and w u^2 and the sums are scaled once per event;
     // the loop is specialised on the model's slot count

@@ -97,7 +97,7 @@ def test_nll_and_gradient_match_oracle(P, stream, name, n, seed, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4s"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4s", "mapped", "comp", "conv", "conv_gmix"])
 def test_batched_equals_single_bitwise(P, stream, name, prec):
     print(f"\n[case] batched {name} {prec}", flush=True)
     sp = get_spec(name)

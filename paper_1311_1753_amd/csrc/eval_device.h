@@ -1452,6 +1452,245 @@ struct TreeEv {
   }
 };
 
+// Light trees (EXP, GAUSS, POLY leaves under ADD, PROD, MAP and DPMAP; at
+// most 8 nodes, 8 slots and 2 columns) for E events per walk of the node
+// list: each node's fields are read and its kind decided once for the E
+// events, which take the same arithmetic as in tree_eval.  Values, adjoints
+// and slot derivatives are [node or slot][event] arrays, so that one index
+// serves the E events.
+template <typename T, int E, bool GRAD>
+__device__ __forceinline__ void tree_eval_light(const KProgram& P, const CS& cs, const double (&xe)[E][2],
+                                                T (&dl)[8][E], T (&out)[E]) {
+  constexpr int NN = 8;
+  const int n_nodes = P.n_nodes;
+  T lv[NN][E], adj[NN][E], resp[NN][E];
+  for (int k = 0; k < n_nodes; ++k) {
+    const KNode& nd = P.node[k];
+    const int op = nd.op;
+    const int c0 = nd.c0, s0 = nd.slot0;
+    const bool h = nd.hoisted != 0;
+    T v[E];
+    if (op == OP_EXP) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        T d1[1];
+        v[e] = leaf_exp<T>(cs, c0, h, (nd.col[0] ? xe[e][1] : xe[e][0]), d1);
+        dl[s0][e] = d1[0];
+      }
+    } else if (op == OP_GAUSS) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        T d2[2];
+        v[e] = leaf_gauss<T>(cs, c0, h, (nd.col[0] ? xe[e][1] : xe[e][0]), d2);
+        dl[s0][e] = d2[0];
+        dl[s0 + 1][e] = d2[1];
+      }
+    } else if (op == OP_POLY) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        T dp[8];
+        v[e] = leaf_poly<T>(cs, c0, nd.aux, h, (nd.col[0] ? xe[e][1] : xe[e][0]), dp);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < nd.aux) dl[s0 + j][e] = dp[j];
+      }
+    } else if (op == OP_PROD) {
+      const bool sub = nd.aux != 0 && !h;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = T(0);
+      int m = 0;
+      for (int j = 0; j < nd.n_child; ++j) {
+        const int ch = P.child[nd.child0 + j];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          v[e] += lv[ch][e];
+          resp[ch][e] = T(1);
+        }
+        const KNode& cn = P.node[ch];
+        if (sub)
+          for (int q = 0; q < cn.n_slot; ++q, ++m) {
+            const T dz = cs.get<T>(c0 + 2 + m);
+#pragma unroll
+            for (int e = 0; e < E; ++e) dl[cn.slot0 + q][e] -= dz;
+          }
+      }
+      if (sub)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = (v[e] - cs.get<T>(c0)) - cs.get<T>(c0 + 1);
+    } else if (op == OP_MAP) {
+      const int K = nd.n_child;
+      int sel[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double x = (nd.col[0] ? xe[e][1] : xe[e][0]) + cs.d[c0 + K - 1];
+        sel[e] = 0;
+        for (int j = 0; j < K - 1; ++j) sel[e] += x >= cs.d[c0 + j] ? 1 : 0;
+        v[e] = T(0);
+      }
+      int m = 0;
+      for (int j = 0; j < K; ++j) {
+        const int ch = P.child[nd.child0 + j];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          v[e] = sel[e] == j ? lv[ch][e] : v[e];
+          resp[ch][e] = T(1);
+        }
+        const KNode& cn = P.node[ch];
+        for (int q = 0; q < cn.n_slot; ++q, ++m) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            T d = sel[e] == j ? dl[cn.slot0 + q][e] : T(0);
+            if (!h) d -= cs.get<T>(c0 + K + 2 + m);
+            dl[cn.slot0 + q][e] = d;
+          }
+        }
+      }
+      if (!h)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = (v[e] - cs.get<T>(c0 + K)) - cs.get<T>(c0 + K + 1);
+    } else if (op == OP_DPMAP) {
+      const int K = nd.n_child, n13 = nd.aux, n12 = K / n13;
+      int sel[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double a = (nd.col[0] ? xe[e][1] : xe[e][0]) + cs.d[c0], b = (nd.col[1] ? xe[e][1] : xe[e][0]) + cs.d[c0 + 1];
+        int i12 = 0, i13 = 0;
+        for (int j = 0; j < n12 - 1; ++j) i12 += a >= cs.d[c0 + 2 + j] ? 1 : 0;
+        for (int j = 0; j < n13 - 1; ++j) i13 += b >= cs.d[c0 + 2 + n12 - 1 + j] ? 1 : 0;
+        sel[e] = i12 * n13 + i13;
+        v[e] = T(0);
+      }
+      for (int j = 0; j < K; ++j) {
+        const int ch = P.child[nd.child0 + j];
+        const KNode& cn = P.node[ch];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const bool on = sel[e] == j;
+          v[e] = on ? lv[ch][e] : v[e];
+          resp[ch][e] = T(1);
+          for (int q = 0; q < cn.n_slot; ++q) dl[cn.slot0 + q][e] = on ? dl[cn.slot0 + q][e] : T(0);
+        }
+      }
+    } else {  // OP_ADD: log-sum-exp with the largest child as pivot
+      const int K = nd.n_child;
+      T mx[E], sm[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        mx[e] = T(-INFINITY);
+        sm[e] = T(0);
+      }
+      for (int j = 0; j < K; ++j) {
+        const int ch = P.child[nd.child0 + j];
+#pragma unroll
+        for (int e = 0; e < E; ++e) mx[e] = lv[ch][e] > mx[e] ? lv[ch][e] : mx[e];
+      }
+      for (int j = 0; j < K; ++j) {
+        const int ch = P.child[nd.child0 + j];
+        const T fj = cs.get<T>(c0 + j);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const T w = mx[e] > T(-INFINITY) ? Mth<T>::ex(lv[ch][e] - mx[e]) : T(0);
+          resp[ch][e] = w;  // e_j for now
+          sm[e] += fj * w;
+        }
+      }
+      T is[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        is[e] = Mth<T>::rcp(sm[e]);
+        v[e] = mx[e] > T(-INFINITY) && sm[e] > T(0) ? mx[e] + Mth<T>::ln(sm[e]) : T(-INFINITY);
+        if (!h) v[e] -= cs.get<T>(c0 + K);
+      }
+      const int chK = P.child[nd.child0 + K - 1];
+      T eK[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) eK[e] = resp[chK][e];
+      for (int j = 0; j < K; ++j) {
+        const int ch = P.child[nd.child0 + j];
+        const T fj = cs.get<T>(c0 + j);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const T ej = resp[ch][e];
+          if (j < K - 1) dl[s0 + j][e] = (ej - eK[e]) * is[e];
+          resp[ch][e] = fj * ej * is[e];  // responsibility of child j
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) lv[k][e] = v[e];
+  }
+  const int root = n_nodes - 1;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    adj[root][e] = T(1);
+    out[e] = lv[root][e];
+  }
+  for (int k = GRAD ? root : -1; k >= 0; --k) {
+    const KNode& nd = P.node[k];
+    if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP)
+      for (int j = 0; j < nd.n_child; ++j) {
+        const int ch = P.child[nd.child0 + j];
+#pragma unroll
+        for (int e = 0; e < E; ++e) adj[ch][e] = adj[k][e] * resp[ch][e];
+      }
+    if (k != root)
+      for (int j = 0; j < nd.n_slot; ++j)
+#pragma unroll
+        for (int e = 0; e < E; ++e) dl[nd.slot0 + j][e] = dl[nd.slot0 + j][e] * adj[k][e];
+  }
+}
+
+// Row loop of the light-tree kernels: E consecutive chunks per step (a
+// thread's E events, the next step's loads in flight); an event past the
+// row's end takes the step's first event's values and is not added.
+template <typename T, int E, bool GRAD, class Acc>
+__device__ __forceinline__ void light_tree_row(const KProgram& P, const CS& cs, const typename Col<T>::S* const* cp,
+                                               int ncols, int64_t n, int64_t c0, int64_t c1, const Acc& acc) {
+  typedef typename Col<T>::S Sx;
+  const int64_t t = threadIdx.x;
+  const int n_slots = GRAD ? P.n_slots : 0;
+  Sx cur[E][2];
+  const auto load = [&](int64_t ch, Sx (&dst)[E][2]) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t i = (ch + e) * kBlock + t;
+      const bool ok = ch + e < c1 && i < n;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) dst[e][c] = (c < ncols && ok) ? cp[c][i] : Sx(0);
+    }
+  };
+  if (c0 < c1) load(c0, cur);
+#pragma unroll 1
+  for (int64_t ch = c0; ch < c1; ch += E) {
+    bool ok[E];
+    double xe[E][2];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      ok[e] = ch + e < c1 && (ch + e) * kBlock + t < n;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) xe[e][c] = (double)(ok[e] ? cur[e][c] : cur[0][c]);
+    }
+    if (ch + E < c1) load(ch + E, cur);
+    if (!ok[0]) continue;
+    T dl[8][E], lr[E];
+    tree_eval_light<T, E, GRAD>(P, cs, xe, dl, lr);
+    double nl = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (ok[e]) nl -= (double)lr[e];
+    acc.add(0, nl);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < n_slots) {
+        double g = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (ok[e]) g += (double)dl[j][e];
+        acc.add(1 + j, g);
+      }
+  }
+}
+
 // Binned metrics over bin centres with weights w (metric 1: -w ln P; metric
 // 2: (w - K P)^2 / max(w, 1)).  ln P is the full log-density: the hoisted
 // normalisations L are subtracted here.  Accumulators: [metric, sum over
@@ -1861,7 +2100,8 @@ __device__ __forceinline__ void tree_row(const KProgram& P, const CS& cs, const 
   acc.zero(nc);
   int64_t c0, c1;
   row_chunks(n, n_rows, r, c0, c1);
-  heavy_row<T, NCOL>(ev, P, cp, P.n_cols, n, c0, c1, acc);
+  if constexpr (HEAVY == 0 && !TM) light_tree_row<T, 2, GRAD>(P, cs, cp, P.n_cols, n, c0, c1, acc);
+  else heavy_row<T, NCOL>(ev, P, cp, P.n_cols, n, c0, c1, acc);
   if constexpr (TM) thread_store_acc<NC>(acc, nc, out, out_stride<TM>(n_rows));
   else row_store_acc<NC>(acc, nc, out, n_rows);
 }

@@ -140,7 +140,7 @@ static int eval_binned(const pdf_graph* g, const dataset* d, const StagedCall& s
     a.lnL = sc.ht.lnN;
     bool heavy = g->dz.node >= 0 || S > 8 || g->prog.n_cols > 2 || g->prog.n_nodes > 8;
     for (int k = 0; k < g->prog.n_nodes; ++k)
-      heavy = heavy || g->prog.node[k].op == OP_CONV || g->prog.node[k].op == OP_COMP;
+      heavy = heavy || g->prog.node[k].op == OP_CONV;
     hipError_t e = launch_binned(d->prec == HF_FP32_EVAL, want_grad, heavy ? (g->dz.node >= 0 ? 2 : 1) : 0, a, st);
     if (e != hipSuccess) return hip_fail(e, "launch of the binned kernel");
     FitRec fr;

@@ -1324,7 +1324,7 @@ __device__ __forceinline__ T tree_eval(const KProgram& P, const CS& cs, const do
         // only by its adjoint in the reverse pass
         if (mixr)
           for (int j = 0; j < cr.n_child; ++j) resp[P.child[cr.child0 + j]] = T(1);
-      } else if (HEAVY && op == OP_COMP) {
+      } else if (op == OP_COMP) {
         // composition f(g(x)): the core's value g = 1 + sum a_j u^j
         // (u = x - x0), the shell's shape at g; the children's slots receive
         // d ln f / dg (x - x0)^j and the shell's own derivatives
@@ -1452,8 +1452,8 @@ struct TreeEv {
   }
 };
 
-// Light trees (EXP, GAUSS, POLY leaves under ADD, PROD, MAP and DPMAP; at
-// most 8 nodes, 8 slots and 2 columns) for E events per walk of the node
+// Light trees (EXP, GAUSS, POLY leaves under ADD, PROD, MAP, DPMAP and COMP;
+// at most 8 nodes, 8 slots and 2 columns) for E events per walk of the node
 // list: each node's fields are read and its kind decided once for the E
 // events, which take the same arithmetic as in tree_eval.  Values, adjoints
 // and slot derivatives are [node or slot][event] arrays, so that one index
@@ -1548,6 +1548,52 @@ __device__ __forceinline__ void tree_eval_light(const KProgram& P, const CS& cs,
       if (!h)
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = (v[e] - cs.get<T>(c0 + K)) - cs.get<T>(c0 + K + 1);
+    } else if (op == OP_COMP) {
+      // composition f(g(x)), as in tree_eval
+      const int chc = P.child[nd.child0], chf = P.child[nd.child0 + 1];
+      const KNode& cc = P.node[chc];
+      const KNode& cf = P.node[chf];
+      const int nc = cc.n_slot, nf = cf.n_slot;
+      const double ref = cs.d[c0 + 2];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const T u = (T)((nd.col[0] ? xe[e][1] : xe[e][0]) + cs.d[cc.c0]);
+        T uk[4], gv = T(1), w = T(1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          w *= u;
+          uk[j] = w;
+          if (j < nc) gv = Mth<T>::fma(cs.get<T>(cc.c0 + 1 + j), w, gv);
+        }
+        T df[8];
+        const T lf = conv_leaf<T>(cs, cf, (double)gv - ref, df);
+        T dfdg;
+        if (cf.op == OP_EXP) {
+          dfdg = cs.get<T>(cf.c0 + 1);
+        } else if (cf.op == OP_GAUSS) {
+          dfdg = -df[0];
+        } else {
+          const T v0 = (T)((double)gv - ref + cs.d[cf.c0]);
+          T pv = T(1), dp = T(0), vk = T(1);
+#pragma unroll
+          for (int j = 1; j <= 4; ++j)
+            if (j <= nf) {
+              dp = Mth<T>::fma(T(j) * cs.get<T>(cf.c0 + j), vk, dp);
+              vk *= v0;
+              pv = Mth<T>::fma(cs.get<T>(cf.c0 + j), vk, pv);
+            }
+          dfdg = dp * Mth<T>::rcp(pv);
+        }
+        v[e] = (lf - cs.get<T>(c0)) - cs.get<T>(c0 + 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nc) dl[cc.slot0 + j][e] = dfdg * uk[j] - cs.get<T>(c0 + 3 + j);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nf) dl[cf.slot0 + j][e] = df[j] - cs.get<T>(c0 + 3 + nc + j);
+        resp[chc][e] = T(1);
+        resp[chf][e] = T(1);
+      }
     } else if (op == OP_DPMAP) {
       const int K = nd.n_child, n13 = nd.aux, n12 = K / n13;
       int sel[E];
@@ -1627,7 +1673,7 @@ __device__ __forceinline__ void tree_eval_light(const KProgram& P, const CS& cs,
   }
   for (int k = GRAD ? root : -1; k >= 0; --k) {
     const KNode& nd = P.node[k];
-    if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP)
+    if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP || nd.op == OP_COMP)
       for (int j = 0; j < nd.n_child; ++j) {
         const int ch = P.child[nd.child0 + j];
 #pragma unroll
@@ -2137,8 +2183,14 @@ void k_leaf(const EvalArgs a) {
     amp_leaf_row<T, OP, GRAD, TM>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, row_out<TM>(a.partials));
 }
 
+// Waves per SIMD the tree kernels must leave room for: 2 for the double
+// light-tree kernel (two events per walk fit in 256 registers).
+template <typename T, int HEAVY> struct TreeWaves { static constexpr int value = 1; };
+template <> struct TreeWaves<double, 0> { static constexpr int value = 2; };
+
 template <typename T, int NS, int NCOL, int HEAVY, bool GRAD, bool TM = false>
-__global__ __launch_bounds__(kBlock) void k_tree(const EvalArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TreeWaves<T, HEAVY>::value)))
+void k_tree(const EvalArgs a) {
   const CS cs{a.prog.c64, a.prog.c32};
   tree_row<T, NS, NCOL, HEAVY, GRAD, TM>(a.prog, cs, a.col, a.n_events, a.n_rows, blockIdx.x, row_out<TM>(a.partials));
 }

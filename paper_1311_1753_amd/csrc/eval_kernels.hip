@@ -233,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_mix_batched(const BatchArgs a) {
 }
 
 template <typename T, int NS, int NCOL, int HEAVY>
-__global__ __launch_bounds__(kBlock) void k_tree_batched(const BatchArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TreeWaves<T, HEAVY>::value)))
+void k_tree_batched(const BatchArgs a) {
   const int total = a.hdr->total_rows, n_fits = a.hdr->n_fits;
   const FitRec* fits = (const FitRec*)(a.hdr + 1);
   for (int gr = blockIdx.x; gr < total; gr += gridDim.x) {

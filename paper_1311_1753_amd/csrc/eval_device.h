@@ -1452,8 +1452,9 @@ struct TreeEv {
   }
 };
 
-// Light trees (EXP, GAUSS, POLY leaves under ADD, PROD, MAP, DPMAP and COMP;
-// at most 8 nodes, 8 slots and 2 columns) for E events per walk of the node
+// Light trees (EXP, GAUSS, POLY leaves under ADD, PROD, MAP and COMP; at most
+// 8 nodes, 8 slots and 2 columns; a DPMAP only ever sits beside a DALITZ /
+// TDDP node, so never here) for E events per walk of the node
 // list: each node's fields are read and its kind decided once for the E
 // events, which take the same arithmetic as in tree_eval.  Values, adjoints
 // and slot derivatives are [node or slot][event] arrays, so that one index
@@ -1594,29 +1595,6 @@ __device__ __forceinline__ void tree_eval_light(const KProgram& P, const CS& cs,
         resp[chc][e] = T(1);
         resp[chf][e] = T(1);
       }
-    } else if (op == OP_DPMAP) {
-      const int K = nd.n_child, n13 = nd.aux, n12 = K / n13;
-      int sel[E];
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const double a = (nd.col[0] ? xe[e][1] : xe[e][0]) + cs.d[c0], b = (nd.col[1] ? xe[e][1] : xe[e][0]) + cs.d[c0 + 1];
-        int i12 = 0, i13 = 0;
-        for (int j = 0; j < n12 - 1; ++j) i12 += a >= cs.d[c0 + 2 + j] ? 1 : 0;
-        for (int j = 0; j < n13 - 1; ++j) i13 += b >= cs.d[c0 + 2 + n12 - 1 + j] ? 1 : 0;
-        sel[e] = i12 * n13 + i13;
-        v[e] = T(0);
-      }
-      for (int j = 0; j < K; ++j) {
-        const int ch = P.child[nd.child0 + j];
-        const KNode& cn = P.node[ch];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const bool on = sel[e] == j;
-          v[e] = on ? lv[ch][e] : v[e];
-          resp[ch][e] = T(1);
-          for (int q = 0; q < cn.n_slot; ++q) dl[cn.slot0 + q][e] = on ? dl[cn.slot0 + q][e] : T(0);
-        }
-      }
     } else {  // OP_ADD: log-sum-exp with the largest child as pivot
       const int K = nd.n_child;
       T mx[E], sm[E];
@@ -1673,7 +1651,7 @@ __device__ __forceinline__ void tree_eval_light(const KProgram& P, const CS& cs,
   }
   for (int k = GRAD ? root : -1; k >= 0; --k) {
     const KNode& nd = P.node[k];
-    if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_DPMAP || nd.op == OP_COMP)
+    if (nd.op == OP_ADD || nd.op == OP_PROD || nd.op == OP_MAP || nd.op == OP_COMP)
       for (int j = 0; j < nd.n_child; ++j) {
         const int ch = P.child[nd.child0 + j];
 #pragma unroll

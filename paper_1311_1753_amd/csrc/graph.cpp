@@ -1713,7 +1713,9 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
     // kernel family
     const NodeInfo& rootn = g->nodes[NN - 1];
     bool heavy = g->dz.node >= 0;
-    for (const NodeInfo& n : g->nodes) heavy = heavy || n.op == OP_CONV;  // the general interpreter only
+    // the general interpreter only (a DPMAP also implies a DALITZ / TDDP node;
+    // the light-tree kernels have no DPMAP code)
+    for (const NodeInfo& n : g->nodes) heavy = heavy || n.op == OP_CONV || n.op == OP_DPMAP;
     // mixture of single-column EXP/GAUSS leaves: static kernel with its own
     // accumulator layout [3 per child], combined on the host (MixInfo)
     bool mix = rootn.op == OP_ADD && (NN == 3 || NN == 4) && (int)rootn.child.size() == NN - 1 && P.n_cols == 1;

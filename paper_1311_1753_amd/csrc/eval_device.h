@@ -978,6 +978,14 @@ __device__ __forceinline__ void conv_window(double x, double lo, double hh, doub
 // it per term.  Grids of at most kConvTab points qualify (the table fits
 // beside the row's LDS accumulators without costing a resident block).
 constexpr int kHeavyConvTab = 3;  // the tree interpreter's staged-CONV instantiation
+// Array sizes of the staged-CONV interpreter for small trees: 8 slots and 2
+// columns in float (157 instead of 245 registers: three waves per SIMD);
+// the double kernel keeps the general sizes (its small form needs more
+// than 256 registers)
+template <typename T> struct ConvSmall {
+  static constexpr int NS = sizeof(T) == 4 ? 8 : kMaxSlotsTree;
+  static constexpr int NCOL = sizeof(T) == 4 ? 2 : kMaxCols;
+};
 template <typename T> struct ConvTab {
   T v[5][kConvTab];
 };
@@ -2203,6 +2211,10 @@ inline hipError_t launch_any(int kind, const EvalArgs& a, hipStream_t st, hipEve
       break;
     case KIND_TREE_CONV:
       hipExtLaunchKernelGGL((k_tree<T, kMaxSlotsTree, kMaxCols, kHeavyConvTab, GRAD, TM>), grid, block, 0, st, e0, e1, 0, a);
+      break;
+    case KIND_TREE_CONV_SMALL:
+      hipExtLaunchKernelGGL((k_tree<T, ConvSmall<T>::NS, ConvSmall<T>::NCOL, kHeavyConvTab, GRAD, TM>), grid, block, 0,
+                            st, e0, e1, 0, a);
       break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \

@@ -248,7 +248,7 @@ void k_tree_batched(const BatchArgs a) {
 
 // ------------------------------------------------------------------ dispatch
 bool kind_light(int kind) {
-  if ((kind >= KIND_MIX2 && kind < KIND_MIX2 + 4) || kind >= KIND_MIX3) return true;
+  if ((kind >= KIND_MIX2 && kind < KIND_MIX2 + 4) || (kind >= KIND_MIX3 && kind < KIND_MIX3 + 8)) return true;
   return kind == KIND_EXP || kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
 }
 
@@ -268,6 +268,7 @@ static const void* kernel_of(int kind) {
     case KIND_TREE: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, 2, GRAD>;
     case KIND_TREE_NOAMP: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, 1, GRAD>;
     case KIND_TREE_CONV: return (const void*)&k_tree<T, kMaxSlotsTree, kMaxCols, kHeavyConvTab, GRAD>;
+    case KIND_TREE_CONV_SMALL: return (const void*)&k_tree<T, ConvSmall<T>::NS, ConvSmall<T>::NCOL, kHeavyConvTab, GRAD>;
     case KIND_TDDPF: return full_leaf_kernel(std::is_same<T, float>::value, GRAD);
     default: return nullptr;  // mixtures: light, never below kRowsPerCU
   }
@@ -331,6 +332,9 @@ static hipError_t launch_b(int kind, const BatchArgs& a, int grid, hipStream_t s
     case KIND_TREE_NOAMP: hipLaunchKernelGGL((k_tree_batched<T, kMaxSlotsTree, kMaxCols, 1>), g, b, 0, st, a); break;
     case KIND_TREE_CONV:
       hipLaunchKernelGGL((k_tree_batched<T, kMaxSlotsTree, kMaxCols, kHeavyConvTab>), g, b, 0, st, a);
+      break;
+    case KIND_TREE_CONV_SMALL:
+      hipLaunchKernelGGL((k_tree_batched<T, ConvSmall<T>::NS, ConvSmall<T>::NCOL, kHeavyConvTab>), g, b, 0, st, a);
       break;
 #define HF_MIX(K_, M_)                                                                              \
   case (K_ == 2 ? KIND_MIX2 : KIND_MIX3) + M_:                                                      \

@@ -299,7 +299,7 @@ void assemble_binned(const pdf_graph* g, const StagedCall& sc, const double* sum
 int32_t rows_for(int kind, hf_precision prec, int64_t n) {
   if (n <= 0) return 0;
   static std::atomic<int> cus[64];
-  static std::atomic<int> resident[64][2][KIND_MIX3 + 8];
+  static std::atomic<int> resident[64][2][KIND_COUNT];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   if (cus[dev].load() <= 0) {
@@ -316,7 +316,7 @@ int32_t rows_for(int kind, hf_precision prec, int64_t n) {
   }();
   int per_cu = per_cu_env ? per_cu_env : kRowsPerCU;
   const bool fp32 = prec == HF_FP32_EVAL;
-  if (!per_cu_env && kind >= 0 && kind < KIND_MIX3 + 8) {
+  if (!per_cu_env && kind >= 0 && kind < KIND_COUNT) {
     std::atomic<int>& r = resident[dev][fp32 ? 1 : 0][kind];
     if (r.load() == 0) {
       const int nb = resident_blocks_per_cu(kind, fp32);
@@ -1761,7 +1761,8 @@ extern "C" int pdf_graph_create(const hf_obs* obs, int32_t n_obs, const hf_param
           ++n_conv;
           fits = fits && P.node[k].aux <= kConvTab;
         }
-      if (n_conv == 1 && fits) g->kind = KIND_TREE_CONV;
+      if (n_conv == 1 && fits)
+        g->kind = P.n_slots <= 8 && P.n_cols <= 2 && NN <= 8 ? KIND_TREE_CONV_SMALL : KIND_TREE_CONV;
     }
     if ((g->kind == KIND_TREE || g->kind == KIND_TREE_NOAMP || g->kind == KIND_TREE_CONV) &&
         P.n_slots > kMaxSlotsTree)

@@ -23,7 +23,11 @@ enum KernelKind {
   // root ADD of 2 (3) single-column EXP/GAUSS leaves: KIND_MIX2 (KIND_MIX3)
   // plus a mask with bit j set when child j is a GAUSS
   KIND_MIX2 = 8,
-  KIND_MIX3 = 16
+  KIND_MIX3 = 16,
+  // KIND_TREE_CONV within the light trees' sizes (at most 8 nodes, 8 slots,
+  // 2 columns): the staged-model interpreter with arrays of that size
+  KIND_TREE_CONV_SMALL = 24,
+  KIND_COUNT = 25
 };
 
 // Rows (blocks) per dataset: at most kRowsPerCU per compute unit (fewer when

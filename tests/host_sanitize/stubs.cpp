@@ -9,7 +9,7 @@
 namespace hf {
 
 bool kind_light(int kind) {
-  return (kind >= KIND_MIX2 && kind < KIND_MIX2 + 4) || kind >= KIND_MIX3 || kind == KIND_EXP ||
+  return (kind >= KIND_MIX2 && kind < KIND_MIX2 + 4) || (kind >= KIND_MIX3 && kind < KIND_MIX3 + 8) || kind == KIND_EXP ||
          kind == KIND_GAUSS || kind == KIND_TREE_SMALL;
 }
 int resident_blocks_per_cu(int, bool) { return 0; }

@@ -269,3 +269,35 @@ def test_terms_conv_staged_and_direct_model(P, grid, second, prec):
     data = {"x": x}
     for th in (om.theta(sp["truth"]), perturbed_theta(om, sp, seed=79)):
         compare_terms(P, sp["name"], sp, om, g, data, prec, th)
+
+
+def _conv_gmix_times_exp_y():
+    """The two-Gaussian-resolution convolution workload times an exponential
+    in a second observable: 9 slots, more than the small staged-CONV kernel
+    takes, so the general staged-CONV interpreter evaluates it."""
+    base = S.configs.CONV_GMIX
+    return {
+        "name": "conv_gmix_times_exp_y",
+        "obs": list(base["obs"]) + [("y", 0.0, 5.0)],
+        "params": list(base["params"]) + [("y_alpha", -0.4, 0.05, -5.0, 5.0, False)],
+        "truth": dict(base["truth"], y_alpha=-0.5),
+        "model": {"op": "prod", "children": [copy.deepcopy(base["model"]),
+                                             {"op": "exp", "obs": "y", "par": ["y_alpha"]}]},
+    }
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_terms_conv_staged_general_interpreter(P, prec):
+    """A CONV graph beyond the small kernel's 8 slots (the general staged-CONV
+    interpreter), per event against the oracle, window-edge events included."""
+    from oracle import oracle as O
+    print(f"\n[case] terms conv_gmix x exp(y) {prec}", flush=True)
+    sp = _conv_gmix_times_exp_y()
+    om = O.Model(sp)
+    g = P.Graph.from_spec(sp)
+    assert g.n_par == 9
+    rng = np.random.default_rng(97)
+    x = np.concatenate([rng.uniform(0.0, 10.0, 6_011), _conv_edges(sp["model"]["children"][0]["children"][0])])
+    data = {"x": x, "y": rng.uniform(0.0, 5.0, x.size)}
+    for th in (om.theta(sp["truth"]), perturbed_theta(om, sp, seed=81)):
+        compare_terms(P, sp["name"], sp, om, g, data, prec, th)

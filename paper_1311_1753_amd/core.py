@@ -12,6 +12,7 @@ with observables [(name, lo, hi)] and parameters
 [(name, init, step, lo, hi, fixed)].
 """
 import ctypes
+import threading
 
 import numpy as np
 
@@ -331,13 +332,37 @@ def _dp(a):
     return a.ctypes.data_as(_lib._DP)
 
 
+# Per-thread argument buffers of the evaluation calls, by parameter count:
+# theta in, gradient and NLL out, with their addresses taken once (a call
+# then costs one copy in and one copy out instead of fresh arrays and
+# address look-ups).
+_tls = threading.local()
+
+
+def _io(n):
+    bufs = getattr(_tls, "bufs", None)
+    if bufs is None:
+        bufs = _tls.bufs = {}
+    b = bufs.get(n)
+    if b is None:
+        th, g, out = np.empty(n), np.empty(n), ctypes.c_double()
+        b = bufs[n] = (th, th.ctypes.data, g, g.ctypes.data, out, ctypes.byref(out))
+    return b
+
+
+def _theta_in(buf, theta, n):
+    a = theta if isinstance(theta, np.ndarray) else np.asarray(theta, dtype=np.float64)
+    if a.size != n:
+        raise ValueError("theta must have %d entries" % n)
+    buf[:] = a.reshape(n)
+
+
 def nll_eval(graph, ds, theta, stream=None, allow_domain=True):
     """NLL at theta (+inf outside the density's domain when allow_domain)."""
-    th = np.ascontiguousarray(theta, dtype=np.float64)
-    if th.size != graph.n_par:
-        raise ValueError("theta must have %d entries" % graph.n_par)
-    out = ctypes.c_double()
-    rc = lib().nll_eval(graph.handle, ds.handle, th.ctypes.data, _stream_ptr(stream), ctypes.byref(out))
+    n = graph.n_par
+    th, thp, _, _, out, outp = _io(n)
+    _theta_in(th, theta, n)
+    rc = lib().nll_eval(graph.handle, ds.handle, thp, _stream_ptr(stream), outp)
     if rc < 0:
         check(rc, allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
     return out.value
@@ -345,16 +370,13 @@ def nll_eval(graph, ds, theta, stream=None, allow_domain=True):
 
 def nll_grad(graph, ds, theta, stream=None, allow_domain=True):
     """(NLL, dNLL/dtheta) at theta from the per-event adjoint kernels."""
-    th = np.ascontiguousarray(theta, dtype=np.float64)
-    if th.size != graph.n_par:
-        raise ValueError("theta must have %d entries" % graph.n_par)
-    out = ctypes.c_double()
-    g = np.empty(graph.n_par)
-    rc = lib().nll_grad(graph.handle, ds.handle, th.ctypes.data, _stream_ptr(stream), ctypes.byref(out),
-                        g.ctypes.data)
+    n = graph.n_par
+    th, thp, g, gp, out, outp = _io(n)
+    _theta_in(th, theta, n)
+    rc = lib().nll_grad(graph.handle, ds.handle, thp, _stream_ptr(stream), outp, gp)
     if rc < 0:
         check(rc, allow=(_lib.HF_E_DOMAIN,) if allow_domain else ())
-    return out.value, g
+    return out.value, g.copy()
 
 
 def nll_terms(graph, ds, theta, stream=None, grad=True, allow_domain=True):

@@ -979,12 +979,11 @@ __device__ __forceinline__ void conv_window(double x, double lo, double hh, doub
 // beside the row's LDS accumulators without costing a resident block).
 constexpr int kHeavyConvTab = 3;  // the tree interpreter's staged-CONV instantiation
 // Array sizes of the staged-CONV interpreter for small trees: 8 slots and 2
-// columns in float (157 instead of 245 registers: three waves per SIMD);
-// the double kernel keeps the general sizes (its small form needs more
-// than 256 registers)
+// columns (float: 157 instead of 245 registers, three waves per SIMD;
+// double: held to 256 registers, two waves per SIMD instead of one)
 template <typename T> struct ConvSmall {
-  static constexpr int NS = sizeof(T) == 4 ? 8 : kMaxSlotsTree;
-  static constexpr int NCOL = sizeof(T) == 4 ? 2 : kMaxCols;
+  static constexpr int NS = 8;
+  static constexpr int NCOL = 2;
 };
 template <typename T> struct ConvTab {
   T v[5][kConvTab];
@@ -2173,6 +2172,7 @@ void k_leaf(const EvalArgs a) {
 // light-tree kernel (two events per walk fit in 256 registers).
 template <typename T, int HEAVY> struct TreeWaves { static constexpr int value = 1; };
 template <> struct TreeWaves<double, 0> { static constexpr int value = 2; };
+template <> struct TreeWaves<double, 3> { static constexpr int value = 2; };
 
 template <typename T, int NS, int NCOL, int HEAVY, bool GRAD, bool TM = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TreeWaves<T, HEAVY>::value)))

@@ -1121,26 +1121,30 @@ __device__ __forceinline__ void conv_terms_gmix(const CS& cs, const KProgram& P,
     // f_j (w_j (z_j^2 / sigma_j - dlnN_j/dsigma_j)) and the fractions'
     // w_j - w_K follow once per event
     T wl = T(0);
-    conv_window<true>(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double v) {
-      const T lm = tab->v[0][k];  // shift already subtracted
-      T sw = T(0);
+    // the term loop specialised on the component count (2 or 3)
+    const auto run = [&](auto kc) __attribute__((always_inline)) {
+      constexpr int KC = decltype(kc)::value;
+      conv_window<true>(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double v) {
+        const T lm = tab->v[0][k];  // shift already subtracted
+        T sw = T(0);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        if (j < K) {
+        for (int j = 0; j < KC; ++j) {
           const T z = (T)(v + loc[j]) * isg[j];
           const T z2 = z * z;
           const T w = Mth<T>::ex(((lm - T(0.5) * z2) - lnh[j]) - lnl[j]);
           sw = Mth<T>::fma(f[j], w, sw);
           gr[2 * j] = Mth<T>::fma(w, z, gr[2 * j]);
           gr[2 * j + 1] = Mth<T>::fma(w, z2, gr[2 * j + 1]);
-          if (j + 1 < K) gr[2 * K + j] += w;
+          if (j + 1 < KC) gr[2 * KC + j] += w;
           else wl += w;
         }
-      }
-      S += sw;
+        S += sw;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) gm[j] = Mth<T>::fma(sw, tab->v[1 + j][k], gm[j]);
-    });
+        for (int j = 0; j < 4; ++j) gm[j] = Mth<T>::fma(sw, tab->v[1 + j][k], gm[j]);
+      });
+    };
+    if (K == 2) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 3>{});
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       if (j < K) {

@@ -301,3 +301,42 @@ def test_terms_conv_staged_general_interpreter(P, prec):
     data = {"x": x, "y": rng.uniform(0.0, 5.0, x.size)}
     for th in (om.theta(sp["truth"]), perturbed_theta(om, sp, seed=81)):
         compare_terms(P, sp["name"], sp, om, g, data, prec, th)
+
+
+def _conv_three_gauss_resolution():
+    """An exponential smeared by a resolution of three Gaussians (core, wider
+    and tail), each normalised over the residual range: 9 slots, the general
+    staged-CONV interpreter's loop for three components."""
+    return {
+        "name": "conv_exp_three_gauss",
+        "obs": [("x", 0.0, 10.0)],
+        "params": [("c_alpha", -0.3, 0.05, -5.0, 5.0, False),
+                   ("r_mu1", 0.0, 0.02, -1.0, 1.0, False), ("r_sg1", 0.2, 0.02, 0.02, 2.0, False),
+                   ("r_mu2", 0.0, 0.02, -1.0, 1.0, False), ("r_sg2", 0.5, 0.05, 0.02, 3.0, False),
+                   ("r_mu3", 0.0, 0.02, -1.0, 1.0, False), ("r_sg3", 1.0, 0.05, 0.02, 3.0, False),
+                   ("r_f1", 0.6, 0.05, 0.0, 1.0, False), ("r_f2", 0.3, 0.05, 0.0, 1.0, False)],
+        "truth": {"c_alpha": -0.4, "r_mu1": 0.02, "r_sg1": 0.2, "r_mu2": -0.05, "r_sg2": 0.5,
+                  "r_mu3": 0.1, "r_sg3": 1.1, "r_f1": 0.6, "r_f2": 0.3},
+        "model": {"op": "conv", "obs": "x", "grid": 400, "d_lo": -3.0, "d_hi": 3.0, "children": [
+            {"op": "exp", "obs": "x", "par": ["c_alpha"]},
+            {"op": "add", "par": ["r_f1", "r_f2"], "children": [
+                {"op": "gauss", "obs": "x", "par": ["r_mu1", "r_sg1"]},
+                {"op": "gauss", "obs": "x", "par": ["r_mu2", "r_sg2"]},
+                {"op": "gauss", "obs": "x", "par": ["r_mu3", "r_sg3"]}]}]},
+    }
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_terms_conv_three_gaussian_resolution(P, prec):
+    """A three-Gaussian resolution mixture, per event against the oracle,
+    window-edge events included."""
+    from oracle import oracle as O
+    print(f"\n[case] terms conv three-Gaussian resolution {prec}", flush=True)
+    sp = _conv_three_gauss_resolution()
+    om = O.Model(sp)
+    g = P.Graph.from_spec(sp)
+    rng = np.random.default_rng(113)
+    x = np.concatenate([rng.uniform(0.0, 10.0, 6_007), _conv_edges(sp["model"])])
+    data = {"x": x}
+    for th in (om.theta(sp["truth"]), perturbed_theta(om, sp, seed=83)):
+        compare_terms(P, sp["name"], sp, om, g, data, prec, th)

@@ -1064,6 +1064,26 @@ __device__ __forceinline__ void conv_terms(const CS& cs, const KNode& cm, const 
     gr[1] = su2 * (isg * isg * isg);
     return;
   }
+  if constexpr (TAB && ROP == OP_EXP) {
+    // one-sided exponential resolution: ln f_R = a u and d/da = u, the loop
+    // specialised on the model's slot count, two points per step
+    const auto run = [&](auto nms) __attribute__((always_inline)) {
+      constexpr int NMS = decltype(nms)::value;
+      conv_window<true>(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double, double vr) {
+        T dr[4];
+        const T lr = R.eval(vr, dr);
+        const T w = Mth<T>::ex(tab->v[0][k] + lr);
+        S += w;
+        gr[0] = Mth<T>::fma(w, dr[0], gr[0]);
+#pragma unroll
+        for (int j = 0; j < NMS; ++j) gm[j] = Mth<T>::fma(w, tab->v[1 + j][k], gm[j]);
+      });
+    };
+    if (cm.n_slot == 1) run(std::integral_constant<int, 1>{});
+    else if (cm.n_slot == 2) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 4>{});
+    return;
+  }
   conv_window(x, lo, hh, dlo, dhi, ref, k0, k1, [&](int k, double vm, double vr) {
     T dm[4], dr[4], lm;
     if constexpr (TAB) {
